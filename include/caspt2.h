@@ -1,0 +1,192 @@
+/*
+ * caspt2.h -- C ABI of the MI355X (gfx950) library for the hot path of fully
+ * internally contracted (X)MS-CASPT2: the amplitude equation (Eq. 10), the
+ * effective Hamiltonian (Eqs. 15-17) and the lambda equation (Eq. 20) of
+ * Vlaisavljevich & Shiozaki, "Nuclear energy gradients for internally
+ * contracted complete active space second-order perturbation theory:
+ * multistate extensions" (Sec. II.A-II.C).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Orbitals: closed 0..nc-1 | active nc..nc+na-1 | virtual nc+na..nmo-1.
+ * All floating point is IEEE binary64, row major.
+ *
+ * Reference states (Sec. II.A, Eqs. 1-2): ci[N][I], N < nst, over the
+ * determinants of na active orbitals with n_alpha = ceil(nelec/2) and
+ * n_beta = floor(nelec/2) electrons.  A string is a bit mask over the active
+ * orbitals; strings with a given count are enumerated in increasing integer
+ * value; I = ia * n_beta_strings + ib; |I> = alpha creators (ascending
+ * orbital) left of beta creators (ascending orbital) on the vacuum.  The CI
+ * vectors must be eigenvectors of the active Hamiltonian with energies eref
+ * (only eref enters H^ref, Eq. 6).
+ *
+ * Fock operator (Eqs. 11-12): f is symmetric; its closed-closed and
+ * virtual-virtual blocks must be diagonal (semicanonical orbitals); the
+ * active block and the closed-active, active-virtual and closed-virtual
+ * blocks are general.  Normal ordering with respect to the closed vacuum is
+ * taken as {E_ij}_C = E_ij - 2 delta_ij.
+ *
+ * Hamiltonian: hcore = h^c, the one-electron operator dressed by the closed
+ * orbitals, h^c_xy = h_xy + sum_i [2 (xy|ii) - (xi|iy)]; dfB[Q][p][q] with
+ * (pq|rs) = sum_Q B^Q_pq B^Q_rs.  The core energy constant is not included
+ * in any energy returned.
+ *
+ * Internally contracted space (Eqs. 7-9): E_Omega |N~> for the nine operator
+ * types of Eq. 8 in product form E_pq E_rs, from every reference state
+ * (MS-MR) or from |L~> only (SS-SR).  They are grouped in eight blocks by the
+ * number of closed holes and virtual particles; E_ai,rs and E_ar,si share
+ * the caav block.
+ *
+ * Packed amplitude layout (per state L).  Entries in this order:
+ *   ccvv+, ccvv-, cavv+, cavv-, aavv+, aavv-, ccav+, ccav-, ccaa+, ccaa-,
+ *   aaav, caaa, caav.
+ * Block operators and external slots (storage order):
+ *   ccvv  E_ai E_bj   (i, j, a, b)   swaps (i,j) and (a,b)
+ *   cavv  E_ar E_bi   (i, a, b)      swap  (a,b)
+ *   aavv  E_ar E_bs   (a, b)         swap  (a,b)
+ *   ccav  E_ai E_rj   (i, j, a)      swap  (i,j)
+ *   ccaa  E_ri E_sj   (i, j)         swap  (i,j)
+ *   aaav  E_ar E_st   (a)
+ *   caaa  E_ri E_st   (i)
+ *   caav  E_ai E_rs (type 0), E_ar E_si (type 1)   (i, a)
+ * Each entry is a row-major matrix [rows][nalpha].  Rows are canonical orbit
+ * representatives: for every swap (k,l) the index in slot k is >= the index
+ * in slot l (strictly > for a '-' entry); slots vary lexicographically, so a
+ * swapped pair is stored as the pair index k(k+1)/2 + l ('+') or
+ * k(k-1)/2 + l ('-').  ccvv '-' means the character (-,-) over its two swaps.
+ * Columns alpha = (state M, operator type, active tuple) with the active
+ * tuple (r, s, t) row-major, state M slowest; in SS-SR the state is absent.
+ * A packed row relates to the coefficients x[e] of the individual functions
+ * E_Omega(e)|M~> by x[e] = sum_chi chi(pi_e) t_chi / sqrt(|orbit|), pi_e
+ * being the swaps that map the representative to e.
+ *
+ * Status codes: every entry point returns int; 0 is success.
+ * Ownership: the caller owns every buffer it passes; caspt2_create copies
+ * the inputs it needs; the handle owns all device memory and
+ * caspt2_destroy frees it.  Pointers marked "device" must be HIP device
+ * memory of the handle's device; pointers marked "host" are host memory.
+ * Threading: one host thread at a time per handle; distinct handles are
+ * independent.  All work is issued on the stream given at creation and is
+ * complete when an entry point returns.
+ */
+#ifndef CASPT2_H
+#define CASPT2_H
+
+#include <stdint.h>
+
+#if defined(__GNUC__)
+#define CASPT2_API __attribute__((visibility("default")))
+#else
+#define CASPT2_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  CASPT2_OK = 0,
+  CASPT2_E_ARG = -1,         /* bad dimension, non-finite or non-symmetric input, bad pointer */
+  CASPT2_E_NOMEM = -2,       /* device allocation failed */
+  CASPT2_E_DEVICE = -3,      /* a HIP call failed (caspt2_last_error() has the text) */
+  CASPT2_E_NOCONV = -4,      /* maxiter reached; best iterate kept, info filled */
+  CASPT2_E_INDEFINITE = -5,  /* a denominator <= 0, or p^T A p <= 0 in PCG */
+  CASPT2_E_NOTIMPL = -6,     /* feature not available in this build */
+  CASPT2_E_STATE = -7        /* call out of order (e.g. heff before amplitudes) */
+};
+
+enum { CASPT2_MSMR = 0, CASPT2_SSSR = 1 };  /* Sec. II.B, Eqs. 7 and 9 */
+enum { CASPT2_FP64 = 0 };
+
+typedef struct {
+  int32_t nclosed, nact, nvirt, naux, nstates, nelec;
+  int32_t scheme;      /* CASPT2_MSMR or CASPT2_SSSR */
+  int32_t xms;         /* 1: XMS rotation (Eqs. 3-5); 0: U = 1, MS-CASPT2 */
+  int32_t precision;   /* CASPT2_FP64 */
+  int32_t reserved;
+  double shift;        /* real vertical shift E_s (Sec. II.B) */
+  double ovl_thresh;   /* overlap eigenvalue truncation, 1e-9 in the paper */
+} caspt2_dims;
+
+typedef struct {      /* all [row-major], read only, copied at create */
+  const double* fock;   /* [nmo][nmo] f (Eq. 11) */
+  const double* hcore;  /* [nmo][nmo] h^c */
+  const double* dfB;    /* [naux][nmo][nmo] B^Q_pq, symmetric in p,q */
+  const double* ci;     /* [nst][ndet] reference CI vectors (not XMS rotated) */
+  const double* eref;   /* [nst] active-space CAS-CI energies */
+} caspt2_inputs;
+
+typedef struct {
+  int32_t iters;        /* PCG iterations */
+  int32_t flags;        /* bit 0: converged */
+  double resnorm;       /* final 2-norm of the residual in the orthonormal basis */
+  double e0;            /* E_L^(0) (Eq. 14) */
+  double min_denom;     /* smallest preconditioner denominator */
+  double emin_kept;     /* smallest kept overlap eigenvalue (all blocks) */
+  double emax_dropped;  /* largest dropped overlap eigenvalue (-1 if none) */
+} caspt2_info;
+
+typedef struct caspt2_handle caspt2_handle;
+
+/* Set up one problem (Sec. II.A-II.B): copies inputs to the device, applies
+ * the XMS rotation (dims.xms), builds the density-fitted integral classes,
+ * the sources <M~|E_Omega^+ H|N~> for every N, the overlap and Fock metrics
+ * of every block and their orthonormal kept bases (eigenvalues >= thresh).
+ * inputs_on_device: 0 if the inputs are host pointers, 1 if device.
+ * stream: a hipStream_t (NULL = default stream).
+ * Errors: E_ARG (dims <= 0 where forbidden, nst > ndet, non-finite inputs,
+ * |f - f^T| > 1e-12, non-diagonal closed or virtual Fock block), E_NOMEM,
+ * E_DEVICE, E_INDEFINITE (a denominator <= 0 for some state). */
+CASPT2_API int caspt2_create(const caspt2_dims* dims, const caspt2_inputs* inputs, int inputs_on_device,
+                  void* stream, caspt2_handle** out);
+CASPT2_API int caspt2_destroy(caspt2_handle* h);
+
+/* Packed vector length per state L (number of doubles). */
+CASPT2_API int64_t caspt2_vector_length(const caspt2_handle* h);
+/* Layout entry k (0..12, order above): offset (doubles), rows, nalpha.
+ * Returns E_ARG for k out of range. */
+CASPT2_API int caspt2_layout(const caspt2_handle* h, int32_t k, int64_t* offset, int64_t* rows,
+                  int64_t* nalpha);
+
+/* Residual of the amplitude equation (Eq. 10) for state L:
+ * sigma = sum_N <M~|E_Omega^+ (f - E_L^(0) + E_s) T_LN|N~> (+ <M~|E_Omega^+ H|L~>)
+ * in the packed non-orthogonal layout.  x, sigma: device, length
+ * caspt2_vector_length; they must not overlap. */
+CASPT2_API int caspt2_residual(caspt2_handle* h, int32_t L, int32_t with_source, const double* x,
+                    double* sigma);
+/* Residuals for every state at once: x and sigma are [nst][length] device. */
+CASPT2_API int caspt2_residual_all(caspt2_handle* h, int32_t with_source, const double* x, double* sigma);
+
+/* Solve Eq. 10 for every state by preconditioned conjugate gradients in the
+ * orthonormal kept basis (preconditioner: external orbital energies +
+ * E_s - E_L + eigenvalues of the block Fock metric).  Stops when the
+ * residual 2-norm <= tol.  info: host array [nst] or NULL.
+ * Returns E_NOCONV if any state hit maxiter, E_INDEFINITE as documented. */
+CASPT2_API int caspt2_solve_amplitudes(caspt2_handle* h, double tol, int32_t maxiter, caspt2_info* info);
+/* Copy T_L (packed, device) after caspt2_solve_amplitudes; E_STATE before. */
+CASPT2_API int caspt2_get_amplitudes(caspt2_handle* h, int32_t L, double* T);
+
+/* XMS rotation computed at create (Eqs. 3-5): U [nst][nst] (column M is the
+ * rotated state |M~>, ascending E~, largest-magnitude entry of each column
+ * positive; identity when dims.xms = 0) and E_L^(0) [nst] (Eq. 14). host. */
+CASPT2_API int xms_rotate(const caspt2_handle* h, double* U, double* e0);
+
+/* Effective Hamiltonian (Eq. 15), its eigenvalues E^MS ascending (Eq. 17)
+ * and eigenvectors R (Eq. 16, columns, largest-magnitude entry positive).
+ * host outputs, [nst][nst], [nst], [nst][nst].  E_STATE before amplitudes. */
+CASPT2_API int xms_heff(caspt2_handle* h, double* heff, double* e_ms, double* R);
+
+/* Solve the lambda equation (Eq. 20) for target state P with the same
+ * operator and solver as the amplitudes.  E_STATE before xms_heff. */
+CASPT2_API int caspt2_solve_lambda(caspt2_handle* h, int32_t target, double tol, int32_t maxiter,
+                        caspt2_info* info);
+CASPT2_API int caspt2_get_lambda(caspt2_handle* h, int32_t L, double* lambda);
+
+/* Human-readable text for a status code; last HIP error text. */
+CASPT2_API const char* caspt2_strerror(int code);
+CASPT2_API const char* caspt2_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

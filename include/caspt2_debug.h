@@ -1,0 +1,36 @@
+/*
+ * caspt2_debug.h -- inspection entry points of the caspt2 library, for tests.
+ * They expose intermediates of the set-up so that each can be compared with
+ * an independent evaluation; none is needed to use the library.
+ */
+#ifndef CASPT2_DEBUG_H
+#define CASPT2_DEBUG_H
+#include "caspt2.h"
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* C = A * op(B) with the library's FP64 MFMA GEMM.  A [M][K]; B [N][K] when
+ * b_is_nk, else [K][N]; C [M][N]; all device, row major. */
+CASPT2_API int caspt2_debug_gemm(int32_t b_is_nk, int64_t M, int64_t N, int64_t K, const double* A,
+                                 const double* B, double* C);
+
+/* Copy an intermediate of layout entry k of function set `set` (0 for MS-MR,
+ * L for SS-SR) into host memory `out`: which = 0 overlap metric S [na][na],
+ * 1 Fock metric F [na][na], 2 row energies [rows], 3 kept count (one
+ * double), 4 X [na][nkeep], 5 mu [nkeep]; na = nalpha of the entry. */
+CASPT2_API int caspt2_debug_entry(const caspt2_handle* h, int32_t set, int32_t k, int32_t which,
+                                  double* out);
+
+/* Source <M~|E_Omega^+ H|N~> for ket N in the function set `set` (packed,
+ * device out). */
+CASPT2_API int caspt2_debug_source(const caspt2_handle* h, int32_t set, int32_t N, double* out);
+
+/* Symmetric eigendecomposition with the library's Jacobi solver: A [n][n]
+ * device (overwritten), w host [n] (unsorted), V device [n][n] (columns). */
+CASPT2_API int caspt2_debug_eigh(int32_t n, double* A, double* w, double* V);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

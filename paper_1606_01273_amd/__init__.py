@@ -1,0 +1,130 @@
+"""MI355X-native hot path of internally contracted (X)MS-CASPT2.
+
+Python front end over the C ABI in include/caspt2.h.  PyTorch provides device
+memory and streams only; every arithmetic step runs in the HIP library.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import (E_ARG, E_DEVICE, E_INDEFINITE, E_NOCONV, E_NOMEM, E_NOTIMPL, E_STATE, ENTRY_NAMES,
+                   MSMR, OK, SSSR, Caspt2Error)
+
+__all__ = ["Caspt2", "Caspt2Error", "lib", "MSMR", "SSSR", "ENTRY_NAMES"]
+
+_LIB = None
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        _LIB = _lib.load()
+    return _LIB
+
+
+def _ptr(t) -> int:
+    return int(t.data_ptr())
+
+
+def _check(rc: int, where: str, allow=(OK,)):
+    if rc not in allow:
+        L = lib()
+        raise Caspt2Error(rc, where, f"{L.caspt2_strerror(rc).decode()}: {L.caspt2_last_error().decode()}")
+    return rc
+
+
+class Caspt2:
+    """One problem on the current HIP device (device memory held by the
+    library handle).  Host numpy inputs are copied at creation."""
+
+    def __init__(self, nclosed, nact, nvirt, naux, nstates, nelec, fock, hcore, dfB, ci, eref,
+                 shift=0.0, scheme=MSMR, xms=True, thresh=1e-9, stream=None):
+        import torch
+        L = lib()
+        self.nst = nstates
+        d = _lib.Dims(nclosed, nact, nvirt, naux, nstates, nelec, scheme, 1 if xms else 0, 0, 0,
+                      float(shift), float(thresh))
+        arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (fock, hcore, dfB, ci, eref)]
+        inp = _lib.Inputs(*[a.ctypes.data for a in arrs])
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self._stream = stream
+        h = ctypes.c_void_p()
+        _check(L.caspt2_create(ctypes.byref(d), ctypes.byref(inp), 0, ctypes.c_void_p(stream.cuda_stream),
+                               ctypes.byref(h)), "caspt2_create")
+        self._h = h
+        self.length = int(L.caspt2_vector_length(h))
+
+    @classmethod
+    def from_problem(cls, prob, scheme=MSMR, xms=True, thresh=1e-9, **kw):
+        return cls(prob.nc, prob.na, prob.nv, prob.naux, prob.nst, prob.nelec, prob.fock, prob.hcore,
+                   prob.B, prob.ci, prob.eref, shift=prob.shift, scheme=scheme, xms=xms,
+                   thresh=thresh, **kw)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().caspt2_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def layout(self):
+        out = []
+        for k in range(len(ENTRY_NAMES)):
+            o, r, a = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+            _check(lib().caspt2_layout(self._h, k, ctypes.byref(o), ctypes.byref(r), ctypes.byref(a)),
+                   "caspt2_layout")
+            out.append((ENTRY_NAMES[k], o.value, r.value, a.value))
+        return out
+
+    def residual(self, L, x, sigma, with_source=True):
+        _check(lib().caspt2_residual(self._h, L, 1 if with_source else 0, _ptr(x), _ptr(sigma)),
+               "caspt2_residual")
+
+    def residual_all(self, x, sigma, with_source=True):
+        _check(lib().caspt2_residual_all(self._h, 1 if with_source else 0, _ptr(x), _ptr(sigma)),
+               "caspt2_residual_all")
+
+    def solve_amplitudes(self, tol=1e-10, maxiter=200):
+        info = (_lib.Info * self.nst)()
+        rc = _check(lib().caspt2_solve_amplitudes(self._h, tol, maxiter, info),
+                    "caspt2_solve_amplitudes", allow=(OK, E_NOCONV))
+        return rc, [i.as_dict() for i in info]
+
+    def amplitudes(self, L):
+        import torch
+        t = torch.empty(self.length, dtype=torch.float64, device="cuda")
+        _check(lib().caspt2_get_amplitudes(self._h, L, _ptr(t)), "caspt2_get_amplitudes")
+        return t
+
+    def xms_rotate(self):
+        U = np.zeros((self.nst, self.nst))
+        e0 = np.zeros(self.nst)
+        _check(lib().xms_rotate(self._h, U.ctypes.data_as(_lib._D), e0.ctypes.data_as(_lib._D)), "xms_rotate")
+        return U, e0
+
+    def heff(self):
+        n = self.nst
+        H, w, R = np.zeros((n, n)), np.zeros(n), np.zeros((n, n))
+        _check(lib().xms_heff(self._h, H.ctypes.data_as(_lib._D), w.ctypes.data_as(_lib._D),
+                              R.ctypes.data_as(_lib._D)), "xms_heff")
+        return H, w, R
+
+    def solve_lambda(self, target=0, tol=1e-10, maxiter=200):
+        info = (_lib.Info * self.nst)()
+        rc = _check(lib().caspt2_solve_lambda(self._h, target, tol, maxiter, info),
+                    "caspt2_solve_lambda", allow=(OK, E_NOCONV))
+        return rc, [i.as_dict() for i in info]
+
+    def lam(self, L):
+        import torch
+        t = torch.empty(self.length, dtype=torch.float64, device="cuda")
+        _check(lib().caspt2_get_lambda(self._h, L, _ptr(t)), "caspt2_get_lambda")
+        return t

@@ -1,0 +1,1273 @@
+// C ABI of the (X)MS-CASPT2 hot path on MI355X: set-up (XMS rotation, DF
+// integral classes, sources, metrics, orthonormal bases), the residual of
+// the amplitude equation, PCG, the effective Hamiltonian and lambda.
+// Every floating-point step on problem data runs in kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/caspt2.h"
+#include "engine.hpp"
+#include "kernels.hpp"
+
+using namespace caspt2;
+
+static thread_local std::string g_last_error;
+
+namespace {
+
+struct DevError : std::runtime_error {
+  int code;
+  DevError(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIPCHECK(expr)                                                                   \
+  do {                                                                                   \
+    hipError_t _e = (expr);                                                              \
+    if (_e != hipSuccess)                                                                \
+      throw DevError(_e == hipErrorOutOfMemory ? CASPT2_E_NOMEM : CASPT2_E_DEVICE,       \
+                     std::string(#expr) + ": " + hipGetErrorString(_e));                 \
+  } while (0)
+
+// owning device buffer
+struct DBuf {
+  double* p = nullptr;
+  int64_t n = 0;
+  DBuf() = default;
+  explicit DBuf(int64_t n_) { alloc(n_); }
+  void alloc(int64_t n_) {
+    release();
+    n = n_;
+    if (n > 0) HIPCHECK(hipMalloc(&p, (size_t)n * sizeof(double)));
+  }
+  void zero(hipStream_t s) {
+    if (n > 0) HIPCHECK(hipMemsetAsync(p, 0, (size_t)n * sizeof(double), s));
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  ~DBuf() { release(); }
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  DBuf(DBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DBuf& operator=(DBuf&& o) noexcept {
+    release();
+    p = o.p;
+    n = o.n;
+    o.p = nullptr;
+    o.n = 0;
+    return *this;
+  }
+};
+
+struct IBuf {
+  int32_t* p = nullptr;
+  void alloc(int64_t n) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    if (n > 0) HIPCHECK(hipMalloc(&p, (size_t)n * sizeof(int32_t)));
+  }
+  ~IBuf() { if (p) (void)hipFree(p); }
+};
+
+int64_t ipow(int64_t b, int e) {
+  int64_t r = 1;
+  for (int k = 0; k < e; ++k) r *= b;
+  return r;
+}
+
+// one packed layout entry of one state's function set
+struct Entry {
+  int block;
+  std::vector<int> chi;
+  int64_t nrow = 0, nalpha = 0, offset = 0;
+  int64_t nkeep = 0, ooff = 0;   // orthogonal-basis columns and offset
+  DBuf S, F, X, mu, eps;          // S,F [nalpha^2]; X [nalpha][nkeep]; mu [nkeep]; eps [nrow]
+  double emin_kept = INFINITY, emax_dropped = -1.0;
+};
+
+struct Gather {
+  IBuf src;
+  DBuf sign;
+  Sector to;
+  int64_t dim_to;
+};
+
+}  // namespace
+
+struct caspt2_handle {
+  caspt2_dims d;
+  hipStream_t s = nullptr;
+  int nc, na, nv, nmo, nst, naux;
+  Sector sec0;
+  std::unique_ptr<ActiveSpace> as;
+  int64_t ndet = 0;
+  DBuf fock, hcore, B, ci_raw, ci;   // ci: rotated [nst][dim]
+  std::vector<double> h_fock, h_eps, U, e0, fref, href, eref;
+  // layout per function set (one for MS-MR, nst for SS-SR)
+  std::vector<std::vector<Entry>> sets;
+  int64_t length = 0, olength = 0;
+  // sources: src[set][N] packed
+  std::vector<std::vector<DBuf>> src;
+  // integrals
+  std::map<std::string, DBuf> eri;
+  // gather tables
+  std::map<std::tuple<char, int, int, int>, std::unique_ptr<Gather>> gathers;
+  // applied-string cache
+  std::map<std::string, std::pair<DBuf, Sector>> vcache;
+  DBuf red_partial, red_out;
+  // solutions
+  std::vector<DBuf> T, Tt, lam, lamt;  // packed and orthogonal
+  std::vector<caspt2_info> tinfo, linfo;
+  bool have_T = false, have_heff = false, have_lam = false;
+  std::vector<double> heff, ems, R;
+  DBuf jws;
+};
+
+namespace {
+
+using H = caspt2_handle;
+
+const Gather& gather(H& h, char kind, int spin, Sector from) {
+  auto key = std::make_tuple(kind, spin, from.na_el, from.nb_el);
+  auto it = h.gathers.find(key);
+  if (it != h.gathers.end()) return *it->second;
+  auto g = std::make_unique<Gather>();
+  std::vector<int32_t> src;
+  std::vector<double> sign;
+  h.as->gather_table(kind, spin, from, src, sign);
+  g->to = h.as->target(kind, spin, from);
+  g->dim_to = h.as->valid(g->to) ? h.as->dim(g->to) : 0;
+  g->src.alloc((int64_t)src.size());
+  g->sign.alloc((int64_t)sign.size());
+  if (!src.empty()) {
+    HIPCHECK(hipMemcpyAsync(g->src.p, src.data(), src.size() * sizeof(int32_t),
+                            hipMemcpyHostToDevice, h.s));
+    HIPCHECK(hipMemcpyAsync(g->sign.p, sign.data(), sign.size() * sizeof(double),
+                            hipMemcpyHostToDevice, h.s));
+  }
+  HIPCHECK(hipStreamSynchronize(h.s));
+  auto& ref = *g;
+  h.gathers[key] = std::move(g);
+  return ref;
+}
+
+std::string skey(const ActString& a) {
+  std::string k;
+  for (const auto& o : a) {
+    k += o.kind;
+    k += char('0' + o.spin);
+  }
+  return k;
+}
+
+// Apply an active string (rightmost first) to the reference CI vectors.
+// Result [labels in string order][nst][dim]; returns sector, or invalid.
+const std::pair<DBuf, Sector>* apply_string(H& h, const ActString& ops) {
+  const std::string key = skey(ops);
+  auto it = h.vcache.find(key);
+  if (it != h.vcache.end()) return &it->second;
+  Sector sec = h.sec0;
+  int64_t lead = h.nst;
+  DBuf cur(lead * h.ndet);
+  HIPCHECK(hipMemcpyAsync(cur.p, h.ci.p, (size_t)lead * h.ndet * sizeof(double),
+                          hipMemcpyDeviceToDevice, h.s));
+  int64_t dim = h.ndet;
+  for (auto o = ops.rbegin(); o != ops.rend(); ++o) {
+    const Gather& g = gather(h, o->kind, o->spin, sec);
+    if (g.dim_to == 0 || !h.as->valid(g.to)) return nullptr;
+    DBuf nxt((int64_t)h.na * lead * g.dim_to);
+    HIPCHECK(launch_gather_apply(cur.p, lead, dim, g.src.p, g.sign.p, h.na, g.dim_to, nxt.p, h.s));
+    cur = std::move(nxt);
+    lead *= h.na;
+    dim = g.dim_to;
+    sec = g.to;
+  }
+  auto& slot = h.vcache[key];
+  slot.first = std::move(cur);
+  slot.second = sec;
+  return &slot;
+}
+
+// sum_sigma-free one-body operator sum_xy f_xy a+_{x s} a_{y s} applied to
+// vectors V [lead][dim] in sector sec (same sector out).
+void apply_onebody(H& h, const double* fact, int spin, const double* V, int64_t lead, Sector sec,
+                   double* out) {
+  const Gather& ga = gather(h, 'a', spin, sec);
+  if (ga.dim_to == 0 || !h.as->valid(ga.to)) {
+    HIPCHECK(vec_fill(lead * h.as->dim(sec), 0.0, out, h.s));
+    return;
+  }
+  const int64_t dim = h.as->dim(sec);
+  DBuf Z((int64_t)h.na * lead * ga.dim_to), Z2((int64_t)h.na * lead * ga.dim_to);
+  HIPCHECK(launch_gather_apply(V, lead, dim, ga.src.p, ga.sign.p, h.na, ga.dim_to, Z.p, h.s));
+  // Z2[x] = sum_y f[x][y] Z[y]
+  HIPCHECK(gemm_f64(false, h.na, lead * ga.dim_to, h.na, 1.0, fact, h.na, 0, Z.p,
+                    lead * ga.dim_to, 0, 0.0, Z2.p, lead * ga.dim_to, 0, 1, h.s));
+  // out = sum_x a+_x Z2[x]: gather each x into a temp and accumulate
+  const Gather& gc = gather(h, 'c', spin, ga.to);
+  DBuf tmp((int64_t)h.na * lead * dim);
+  HIPCHECK(vec_fill(lead * dim, 0.0, out, h.s));
+  for (int x = 0; x < h.na; ++x) {
+    // only the x-th slab of the creation table applied to Z2[x]
+    HIPCHECK(launch_gather_apply(Z2.p + (int64_t)x * lead * ga.dim_to, lead, ga.dim_to,
+                                 gc.src.p + (int64_t)x * dim, gc.sign.p + (int64_t)x * dim, 1, dim,
+                                 tmp.p, h.s));
+    HIPCHECK(vec_axpy(lead * dim, 1.0, tmp.p, out, h.s));
+  }
+}
+
+struct TypeInfo {
+  int nlab;       // active labels of the function
+  int64_t ntup;   // na^nlab
+};
+
+// Accumulate sum_entries coeff * <bra(M)| mid ket |N> into G with layout
+// [mid labels][alpha_b = (M, tb, tuple_b)][alpha_k = (N, tk, tuple_k)].
+// For sources (ket_block < 0) alpha_k = N.  fock_mid: the mid string is the
+// one-body operator contracted with fact (mid labels absent from G).
+void accumulate_gram(H& h, const WickEntry& w, int tb, int ntypes_b, int64_t ntup_b, int tk,
+                     int ntypes_k, int64_t ntup_k, bool source, const double* fact, DBuf& G,
+                     int64_t nmid_lab) {
+  const int nst = h.nst;
+  const auto* U = apply_string(h, w.bra);
+  if (!U) return;
+  ActString wk = w.ket;
+  int64_t nmid = 1;
+  const bool fock_mid = fact != nullptr;
+  if (!fock_mid) {
+    wk = w.mid;
+    wk.insert(wk.end(), w.ket.begin(), w.ket.end());
+    nmid = ipow(h.na, (int)w.mid.size());
+  }
+  const auto* Wp = apply_string(h, wk);
+  if (!Wp) return;
+  Sector wsec = Wp->second;
+  const int64_t nWlead = Wp->first.n / h.as->dim(wsec);
+  const double* Wdata = Wp->first.p;
+  DBuf Wf;
+  if (fock_mid) {
+    if (!(wsec == U->second)) return;
+    Wf.alloc(Wp->first.n);
+    apply_onebody(h, fact, w.mid[0].spin, Wp->first.p, nWlead, wsec, Wf.p);
+    Wdata = Wf.p;
+  }
+  if (!(wsec == U->second)) return;
+  const int64_t dim = h.as->dim(wsec);
+  const int64_t nUlead = U->first.n / dim;
+  DBuf Gr(nUlead * nWlead);
+  HIPCHECK(gemm_f64(true, nUlead, nWlead, dim, 1.0, U->first.p, dim, 0, Wdata, dim, 0, 0.0, Gr.p,
+                    nWlead, 0, 1, h.s));
+  // Gram axes: [bra labels][M][mid labels][ket labels][N]
+  const int nbl = (int)w.bra.size(), nml = fock_mid ? 0 : (int)w.mid.size(),
+            nkl = (int)w.ket.size();
+  const int64_t na_b_all = (int64_t)nst * ntypes_b * ntup_b;
+  const int64_t na_k_all = source ? nst : (int64_t)nst * ntypes_k * ntup_k;
+  std::vector<int64_t> dims, strides;
+  for (int k = 0; k < nbl; ++k) {
+    dims.push_back(h.na);
+    strides.push_back(ipow(h.na, nbl - 1 - k) * na_k_all);
+  }
+  dims.push_back(nst);
+  strides.push_back((int64_t)ntypes_b * ntup_b * na_k_all);
+  for (int k = 0; k < nml; ++k) {
+    dims.push_back(h.na);
+    strides.push_back(ipow(h.na, nml - 1 - k) * na_b_all * na_k_all);
+  }
+  for (int k = 0; k < nkl; ++k) {
+    dims.push_back(h.na);
+    strides.push_back(ipow(h.na, nkl - 1 - k));
+  }
+  dims.push_back(nst);
+  strides.push_back(source ? 1 : (int64_t)ntypes_k * ntup_k);
+  const int64_t base = (int64_t)tb * ntup_b * na_k_all + (source ? 0 : (int64_t)tk * ntup_k);
+  (void)nmid_lab;
+  HIPCHECK(permute_axpy((int)dims.size(), dims.data(), strides.data(), w.coeff, Gr.p, G.p + base,
+                        h.s));
+}
+
+// characters of a pairing: which swaps of the block are applied
+double perm_sign(const Block& b, const Pairing& P, const std::vector<int>& chi) {
+  double sg = 1.0;
+  for (size_t s = 0; s < b.swaps.size(); ++s) {
+    const std::string lk = b.ext[b.swaps[s].first].first + "_b";
+    const std::string ll = b.ext[b.swaps[s].second].first + "_k";
+    for (const auto& pr : P.pairs)
+      if ((pr.first == lk && pr.second == ll) || (pr.first == ll && pr.second == lk)) sg *= chi[s];
+  }
+  return sg;
+}
+
+int64_t orbit_rows(const H& h, const Block& b, const std::vector<int>& chi) {
+  int64_t rows = 1;
+  for (size_t k = 0; k < b.ext.size(); ++k) {
+    int sw = -1;
+    for (size_t s = 0; s < b.swaps.size(); ++s)
+      if (b.swaps[s].first == (int)k) sw = (int)s;
+    const int64_t dim = b.ext[k].second == CLO ? h.nc : h.nv;
+    if (sw >= 0) {
+      rows *= chi[sw] < 0 ? dim * (dim - 1) / 2 : dim * (dim + 1) / 2;
+      ++k;
+    } else {
+      rows *= dim;
+    }
+  }
+  return rows;
+}
+
+TermDesc base_desc(const H& h, const Block& b, const Entry& e) {
+  TermDesc d{};
+  d.block = e.block;
+  d.nslot = (int)b.ext.size();
+  for (int k = 0; k < d.nslot; ++k) d.slot_dim[k] = b.ext[k].second == CLO ? h.nc : h.nv;
+  d.nswap = (int)b.swaps.size();
+  for (int s = 0; s < d.nswap; ++s) {
+    d.swap_k[s] = b.swaps[s].first;
+    d.swap_l[s] = b.swaps[s].second;
+    d.chi[s] = e.chi[s];
+    d.strict[s] = e.chi[s] < 0 ? 1 : 0;
+  }
+  d.nrow = e.nrow;
+  d.nalpha = e.nalpha;
+  d.ldo = e.nalpha;
+  d.na = h.na;
+  return d;
+}
+
+void host_sync(H& h) { HIPCHECK(hipStreamSynchronize(h.s)); }
+
+double dev_scalar(H& h, const double* p) {
+  double v;
+  HIPCHECK(hipMemcpyAsync(&v, p, sizeof(double), hipMemcpyDeviceToHost, h.s));
+  host_sync(h);
+  return v;
+}
+
+// symmetric eigendecomposition of an n x n device matrix: values (host,
+// unsorted as on the diagonal) and vectors (device, columns)
+void eigh_dev(H& h, const double* A, int64_t n, std::vector<double>& w, DBuf& Vec) {
+  DBuf Aw(n * n);
+  HIPCHECK(hipMemcpyAsync(Aw.p, A, (size_t)(n * n) * sizeof(double), hipMemcpyDeviceToDevice, h.s));
+  Vec.alloc(n * n);
+  if (h.jws.n < 4 * n + 16) h.jws.alloc(4 * n + 16);
+  int sweeps = 0;
+  HIPCHECK(jacobi_eigh((int)n, Aw.p, Vec.p, h.jws.p, 60, 1e-15, h.s, &sweeps));
+  std::vector<double> full(n * n);
+  HIPCHECK(hipMemcpyAsync(full.data(), Aw.p, (size_t)(n * n) * sizeof(double),
+                          hipMemcpyDeviceToHost, h.s));
+  host_sync(h);
+  w.resize(n);
+  for (int64_t i = 0; i < n; ++i) w[i] = full[i * n + i];
+}
+
+// X = Q[:, keep] / sqrt(w); then rotate to diagonalise X^T F X (Sec. II.B)
+void orthonormal_basis(H& h, Entry& e) {
+  const int64_t n = e.nalpha;
+  std::vector<double> w;
+  DBuf Q;
+  eigh_dev(h, e.S.p, n, w, Q);
+  std::vector<int64_t> keep;
+  for (int64_t i = 0; i < n; ++i) {
+    if (w[i] >= h.d.ovl_thresh) {
+      keep.push_back(i);
+      e.emin_kept = std::min(e.emin_kept, w[i]);
+    } else {
+      e.emax_dropped = std::max(e.emax_dropped, w[i]);
+    }
+  }
+  const int64_t nk = (int64_t)keep.size();
+  e.nkeep = nk;
+  if (nk == 0) {
+    e.X.alloc(0);
+    e.mu.alloc(0);
+    return;
+  }
+  // X0[:, k] = Q[:, keep[k]] / sqrt(w[keep[k]])
+  DBuf X0(n * nk), sc(nk);
+  IBuf ki;
+  ki.alloc(nk);
+  {
+    std::vector<int32_t> kk(nk);
+    std::vector<double> sv(nk);
+    for (int64_t k = 0; k < nk; ++k) {
+      kk[k] = (int32_t)keep[k];
+      sv[k] = 1.0 / std::sqrt(w[keep[k]]);
+    }
+    HIPCHECK(hipMemcpyAsync(ki.p, kk.data(), nk * sizeof(int32_t), hipMemcpyHostToDevice, h.s));
+    HIPCHECK(hipMemcpyAsync(sc.p, sv.data(), nk * sizeof(double), hipMemcpyHostToDevice, h.s));
+    HIPCHECK(select_scale_cols(n, n, Q.p, ki.p, sc.p, nk, X0.p, h.s));
+    host_sync(h);
+  }
+  // Fo = X0^T F X0 : FX = F X0 [n][nk]; Fo = X0^T FX
+  DBuf FX(n * nk), X0t(nk * n), Fo(nk * nk);
+  HIPCHECK(gemm_f64(false, n, nk, n, 1.0, e.F.p, n, 0, X0.p, nk, 0, 0.0, FX.p, nk, 0, 1, h.s));
+  {
+    const int64_t dims[2] = {n, nk};
+    const int64_t str[2] = {1, n};
+    X0t.zero(h.s);
+    HIPCHECK(permute_axpy(2, dims, str, 1.0, X0.p, X0t.p, h.s));
+  }
+  HIPCHECK(gemm_f64(false, nk, nk, n, 1.0, X0t.p, n, 0, FX.p, nk, 0, 0.0, Fo.p, nk, 0, 1, h.s));
+  std::vector<double> mu;
+  DBuf Z;
+  eigh_dev(h, Fo.p, nk, mu, Z);
+  e.X.alloc(n * nk);
+  HIPCHECK(gemm_f64(false, n, nk, nk, 1.0, X0.p, nk, 0, Z.p, nk, 0, 0.0, e.X.p, nk, 0, 1, h.s));
+  e.mu.alloc(nk);
+  HIPCHECK(hipMemcpyAsync(e.mu.p, mu.data(), nk * sizeof(double), hipMemcpyHostToDevice, h.s));
+  host_sync(h);
+}
+
+// DF integral class (sp sq | sr ss) as a contiguous [np][nq][nr][ns] tensor
+const double* eri_block(H& h, char sp, char sq, char sr, char ss) {
+  std::string key{sp, sq, sr, ss};
+  auto it = h.eri.find(key);
+  if (it != h.eri.end()) return it->second.p;
+  auto off = [&](char c) { return c == CLO ? 0 : c == ACT ? h.nc : h.nc + h.na; };
+  auto dim = [&](char c) { return c == CLO ? h.nc : c == ACT ? h.na : h.nv; };
+  const int np = dim(sp), nq = dim(sq), nr = dim(sr), ns = dim(ss);
+  DBuf A((int64_t)np * nq * h.naux), Bt((int64_t)nr * ns * h.naux);
+  HIPCHECK(df_pack(h.B.p, h.naux, h.nmo, off(sp), np, off(sq), nq, A.p, h.s));
+  HIPCHECK(df_pack(h.B.p, h.naux, h.nmo, off(sr), nr, off(ss), ns, Bt.p, h.s));
+  DBuf out((int64_t)np * nq * nr * ns);
+  HIPCHECK(gemm_f64(true, (int64_t)np * nq, (int64_t)nr * ns, h.naux, 1.0, A.p, h.naux, 0, Bt.p,
+                    h.naux, 0, 0.0, out.p, (int64_t)nr * ns, 0, 1, h.s));
+  auto& slot = h.eri[key];
+  slot = std::move(out);
+  return slot.p;
+}
+
+// row energies: sum of virtual minus closed diagonal Fock elements
+void row_energies(H& h, const Block& b, Entry& e) {
+  // sum over slots of +eps (virtual) / -eps (closed) on the representative
+  e.eps.alloc(e.nrow);
+  e.eps.zero(h.s);
+  DBuf epsd((int64_t)h.nmo), one(1);
+  HIPCHECK(hipMemcpyAsync(epsd.p, h.h_eps.data(), h.nmo * sizeof(double), hipMemcpyHostToDevice,
+                          h.s));
+  HIPCHECK(vec_fill(1, 1.0, one.p, h.s));
+  for (size_t k = 0; k < b.ext.size(); ++k) {
+    const bool vir = b.ext[k].second == VIR;
+    TermDesc d = base_desc(h, b, e);
+    d.nalpha = 1;
+    d.ldo = 1;
+    d.ncax = 1;
+    d.c_slot[0] = (int)k;
+    d.c_stride[0] = 1;
+    d.nopact = 0;
+    d.gcols = 1;
+    d.gcol = 0;
+    d.galpha = 1;
+    d.goff = 0;
+    d.mode_avg = 1;
+    d.scale = vir ? 1.0 : -1.0;
+    HIPCHECK(term_source(d, epsd.p + (vir ? h.nc + h.na : 0), one.p, e.eps.p, h.s));
+  }
+  host_sync(h);
+}
+
+}  // namespace
+
+namespace {
+
+std::string pair_key(const Pairing& P) {
+  std::vector<std::string> v;
+  for (const auto& p : P.pairs) v.push_back(std::min(p.first, p.second) + "=" + std::max(p.first, p.second));
+  std::sort(v.begin(), v.end());
+  std::string k;
+  for (auto& s : v) k += s + ";";
+  return k;
+}
+
+struct PairAcc {
+  Pairing P;   // pairs only
+  DBuf G;
+};
+
+// copy the (L, L) state block of an all-states alpha x alpha matrix
+void state_block(H& h, const double* G, int64_t nall, int64_t n, int L, double c, double* out) {
+  DBuf tmp(n * n);
+  HIPCHECK(hipMemcpy2DAsync(tmp.p, (size_t)n * sizeof(double), G + (int64_t)L * n * nall + (int64_t)L * n,
+                            (size_t)nall * sizeof(double), (size_t)n * sizeof(double), (size_t)n,
+                            hipMemcpyDeviceToDevice, h.s));
+  HIPCHECK(vec_axpy(n * n, c, tmp.p, out, h.s));
+}
+
+void setup_blocks(H& h) {
+  const bool ss = h.d.scheme == CASPT2_SSSR;
+  const int nst = h.nst;
+  const int nsets = ss ? nst : 1;
+  h.sets.clear();
+  h.sets.resize(nsets);
+  // active block of f on the device, contiguous [na][na]
+  DBuf fact((int64_t)h.na * h.na);
+  {
+    std::vector<double> fa((size_t)h.na * h.na);
+    for (int r = 0; r < h.na; ++r)
+      for (int s = 0; s < h.na; ++s) fa[r * h.na + s] = h.h_fock[(h.nc + r) * h.nmo + h.nc + s];
+    if (!fa.empty())
+      HIPCHECK(hipMemcpyAsync(fact.p, fa.data(), fa.size() * sizeof(double), hipMemcpyHostToDevice,
+                              h.s));
+  }
+  const auto& BL = blocks();
+  for (int bi = 0; bi < NBLOCK; ++bi) {
+    const Block& b = BL[bi];
+    const int ntypes = (int)b.types.size();
+    const int64_t ntup = ipow(h.na, (int)b.act.size());
+    const int64_t nall = (int64_t)nst * ntypes * ntup;
+    const int64_t nset = (ss ? 1 : nst) * ntypes * ntup;
+    // metric and Fock-metric accumulators per pairing
+    std::map<std::string, PairAcc> met, fk;
+    const OpString fop = E("x_o", ACT, "y_o", ACT, "so");
+    for (int tb = 0; tb < ntypes; ++tb)
+      for (int tk = 0; tk < ntypes; ++tk) {
+        const OpString bra = suffixed(b.types[tb], "_b"), ket = suffixed(b.types[tk], "_k");
+        for (int which = 0; which < 2; ++which) {
+          auto pairings = matrix_element(bra, which == 0 ? OpString{} : fop, ket);
+          auto& acc = which == 0 ? met : fk;
+          for (auto& P : pairings) {
+            const std::string key = pair_key(P);
+            auto it = acc.find(key);
+            if (it == acc.end()) {
+              PairAcc pa;
+              pa.P.pairs = P.pairs;
+              pa.G.alloc(nall * nall);
+              pa.G.zero(h.s);
+              it = acc.emplace(key, std::move(pa)).first;
+            }
+            for (const auto& w : P.entries)
+              accumulate_gram(h, w, tb, ntypes, ntup, tk, ntypes, ntup, false,
+                              which == 0 ? nullptr : fact.p, it->second.G, 0);
+          }
+        }
+      }
+    for (int set = 0; set < nsets; ++set) {
+      for (const auto& chi : characters(b)) {
+        Entry e;
+        e.block = bi;
+        e.chi = chi;
+        e.nrow = orbit_rows(h, b, chi);
+        e.nalpha = nset;
+        e.S.alloc(nset * nset);
+        e.F.alloc(nset * nset);
+        e.S.zero(h.s);
+        e.F.zero(h.s);
+        for (int which = 0; which < 2; ++which) {
+          auto& acc = which == 0 ? met : fk;
+          DBuf& dst = which == 0 ? e.S : e.F;
+          for (auto& kv : acc) {
+            const double sg = perm_sign(b, kv.second.P, chi);
+            if (nset == 0) continue;
+            if (ss)
+              state_block(h, kv.second.G.p, nall, nset, set, sg, dst.p);
+            else
+              HIPCHECK(vec_axpy(nset * nset, sg, kv.second.G.p, dst.p, h.s));
+          }
+        }
+        if (e.nrow > 0 && e.nalpha > 0) {
+          row_energies(h, b, e);
+          orthonormal_basis(h, e);
+        }
+        h.sets[set].push_back(std::move(e));
+      }
+    }
+    h.vcache.clear();
+    host_sync(h);
+  }
+  // offsets
+  for (auto& set : h.sets) {
+    int64_t off = 0, ooff = 0;
+    for (auto& e : set) {
+      e.offset = off;
+      e.ooff = ooff;
+      off += e.nrow * e.nalpha;
+      ooff += e.nrow * e.nkeep;
+    }
+    h.length = off;
+    h.olength = std::max(h.olength, ooff);
+  }
+}
+
+// sources <M~| E_Omega^+ H |N~> for every N, packed, per function set
+void setup_sources(H& h) {
+  const bool ss = h.d.scheme == CASPT2_SSSR;
+  const int nst = h.nst;
+  const int nsets = ss ? nst : 1;
+  h.src.clear();
+  h.src.resize(nsets);
+  for (int set = 0; set < nsets; ++set)
+    for (int N = 0; N < nst; ++N) {
+      h.src[set].emplace_back(h.length);
+      h.src[set].back().zero(h.s);
+    }
+  struct Comp {
+    OpString ops;
+    std::vector<std::string> labels;
+    std::vector<char> spaces;
+    double scale;
+  };
+  std::vector<Comp> comps;
+  for (char sp : {ACT, VIR})
+    for (char sq : {ACT, CLO}) {
+      if (sp == ACT && sq == ACT) continue;
+      comps.push_back({E("p_o", sp, "q_o", sq, "so"), {"p_o", "q_o"}, {sp, sq}, 1.0});
+    }
+  for (char sp : {ACT, VIR})
+    for (char sq : {ACT, CLO})
+      for (char sr : {ACT, VIR})
+        for (char ss2 : {ACT, CLO}) {
+          if (sp == ACT && sq == ACT && sr == ACT && ss2 == ACT) continue;
+          OpString ops = {Op{'c', "p_o", sp, "so"}, Op{'c', "r_o", sr, "to"},
+                          Op{'a', "s_o", ss2, "to"}, Op{'a', "q_o", sq, "so"}};
+          comps.push_back({ops, {"p_o", "q_o", "r_o", "s_o"}, {sp, sq, sr, ss2}, 0.5});
+        }
+  auto dim = [&](char c) { return c == CLO ? h.nc : c == ACT ? h.na : h.nv; };
+  auto off = [&](char c) { return c == CLO ? 0 : c == ACT ? h.nc : h.nc + h.na; };
+  const auto& BL = blocks();
+  for (int bi = 0; bi < NBLOCK; ++bi) {
+    const Block& b = BL[bi];
+    const int ntypes = (int)b.types.size();
+    const int64_t ntup = ipow(h.na, (int)b.act.size());
+    const int64_t nall = (int64_t)nst * ntypes * ntup;
+    const int64_t nset = (ss ? 1 : nst) * ntypes * ntup;
+    if (nset == 0) continue;
+    for (const auto& c : comps) {
+      bool empty = false;
+      for (char sp : c.spaces)
+        if (dim(sp) == 0) empty = true;
+      if (empty) continue;
+      std::map<std::string, PairAcc> acc;
+      int nopact = 0;
+      for (const auto& o : c.ops)
+        if (o.space == ACT) ++nopact;
+      const int64_t ny = ipow(h.na, nopact);
+      for (int tb = 0; tb < ntypes; ++tb) {
+        auto pairings = matrix_element(suffixed(b.types[tb], "_b"), c.ops, OpString{});
+        for (auto& P : pairings) {
+          const std::string key = pair_key(P);
+          auto it = acc.find(key);
+          if (it == acc.end()) {
+            PairAcc pa;
+            pa.P.pairs = P.pairs;
+            pa.G.alloc(ny * nall * nst);
+            pa.G.zero(h.s);
+            it = acc.emplace(key, std::move(pa)).first;
+          }
+          for (const auto& w : P.entries)
+            accumulate_gram(h, w, tb, ntypes, ntup, 0, 1, 1, true, nullptr, it->second.G, nopact);
+        }
+      }
+      if (acc.empty()) continue;
+      // coefficient tensor
+      const double* C = nullptr;
+      int64_t cstr[4] = {0, 0, 0, 0};
+      if (c.labels.size() == 2) {
+        C = h.hcore.p + (int64_t)off(c.spaces[0]) * h.nmo + off(c.spaces[1]);
+        cstr[0] = h.nmo;
+        cstr[1] = 1;
+      } else {
+        C = eri_block(h, c.spaces[0], c.spaces[1], c.spaces[2], c.spaces[3]);
+        cstr[3] = 1;
+        cstr[2] = dim(c.spaces[3]);
+        cstr[1] = cstr[2] * dim(c.spaces[2]);
+        cstr[0] = cstr[1] * dim(c.spaces[1]);
+      }
+      for (auto& kv : acc) {
+        for (int set = 0; set < nsets; ++set)
+          for (auto& e : h.sets[set]) {
+            if (e.block != bi || e.nrow == 0) continue;
+            TermDesc d = base_desc(h, b, e);
+            d.ncax = (int)c.labels.size();
+            // active labels index G in operator-string order
+            std::vector<std::string> mid_order;
+            for (const auto& o : c.ops)
+              if (o.space == ACT) mid_order.push_back(o.label);
+            for (int a = 0; a < d.ncax; ++a) {
+              d.c_stride[a] = cstr[a];
+              if (c.spaces[a] == ACT) {
+                const int pos = (int)(std::find(mid_order.begin(), mid_order.end(), c.labels[a]) -
+                                      mid_order.begin());
+                d.c_slot[a] = -1 - pos;
+              } else {
+                int slot = -1;
+                for (const auto& pr : kv.second.P.pairs) {
+                  std::string other;
+                  if (pr.first == c.labels[a]) other = pr.second;
+                  if (pr.second == c.labels[a]) other = pr.first;
+                  if (!other.empty())
+                    for (size_t k = 0; k < b.ext.size(); ++k)
+                      if (b.ext[k].first + "_b" == other) slot = (int)k;
+                }
+                if (slot < 0) throw DevError(CASPT2_E_DEVICE, "source pairing without bra slot");
+                d.c_slot[a] = slot;
+              }
+            }
+            d.nopact = nopact;
+            d.gcols = nst;
+            d.galpha = nall;
+            d.goff = ss ? (int64_t)set * nset : 0;
+            d.mode_avg = 0;
+            d.scale = c.scale;
+            for (int N = 0; N < nst; ++N) {
+              d.gcol = N;
+              HIPCHECK(term_source(d, C, kv.second.G.p, h.src[set][N].p + e.offset, h.s));
+            }
+          }
+      }
+      host_sync(h);
+    }
+    h.vcache.clear();
+  }
+  host_sync(h);
+}
+
+// ---------------------------------------------------------------------------
+// residual and solver
+// ---------------------------------------------------------------------------
+int set_of(const H& h, int L) { return h.d.scheme == CASPT2_SSSR ? L : 0; }
+
+void residual(H& h, int L, const double* x, double* sig, bool with_source) {
+  const int set = set_of(h, L);
+  const double dshift = h.d.shift - h.e0[L];
+  for (auto& e : h.sets[set]) {
+    if (e.nrow == 0 || e.nalpha == 0) continue;
+    const double* V = with_source ? h.src[set][L].p + e.offset : nullptr;
+    if (e.nalpha <= 64)
+      HIPCHECK(residual_small_f64(e.nrow, e.nalpha, x + e.offset, e.S.p, e.F.p, e.eps.p, dshift, V,
+                                  sig + e.offset, h.s));
+    else
+      HIPCHECK(residual_gemm_f64(e.nrow, e.nalpha, e.nalpha, x + e.offset, e.nalpha, e.S.p, e.F.p,
+                                 e.eps.p, dshift, V, e.nalpha, sig + e.offset, e.nalpha, h.s));
+  }
+}
+
+void to_orth(H& h, int set, const double* v, double* o) {
+  for (auto& e : h.sets[set]) {
+    if (e.nrow == 0 || e.nkeep == 0) continue;
+    HIPCHECK(gemm_f64(false, e.nrow, e.nkeep, e.nalpha, 1.0, v + e.offset, e.nalpha, 0, e.X.p,
+                      e.nkeep, 0, 0.0, o + e.ooff, e.nkeep, 0, 1, h.s));
+  }
+}
+
+void from_orth(H& h, int set, const double* o, double* v) {
+  for (auto& e : h.sets[set]) {
+    if (e.nrow == 0 || e.nalpha == 0) continue;
+    if (e.nkeep == 0) {
+      HIPCHECK(vec_fill(e.nrow * e.nalpha, 0.0, v + e.offset, h.s));
+      continue;
+    }
+    HIPCHECK(gemm_f64(true, e.nrow, e.nalpha, e.nkeep, 1.0, o + e.ooff, e.nkeep, 0, e.X.p, e.nkeep,
+                      0, 0.0, v + e.offset, e.nalpha, 0, 1, h.s));
+  }
+}
+
+int64_t olen(const H& h, int set) {
+  int64_t n = 0;
+  for (auto& e : h.sets[set]) n += e.nrow * e.nkeep;
+  return n;
+}
+
+double ddot(H& h, int64_t n, const double* x, const double* y) {
+  HIPCHECK(vec_dot(n, x, y, h.red_partial.p, h.red_out.p, h.s));
+  return dev_scalar(h, h.red_out.p);
+}
+
+// denominators D[row][k] = eps[row] + E_s - E_L + mu[k]
+void build_denoms(H& h, int L, DBuf& D, double* dmin) {
+  const int set = set_of(h, L);
+  const int64_t n = olen(h, set);
+  D.alloc(n);
+  DBuf ones_mu, tmp;
+  double mn = INFINITY;
+  for (auto& e : h.sets[set]) {
+    if (e.nrow == 0 || e.nkeep == 0) continue;
+    // D = eps (x) 1 + 1 (x) mu + shift via two rank-1 GEMMs
+    DBuf one_r(e.nrow), one_k(e.nkeep);
+    HIPCHECK(vec_fill(e.nrow, 1.0, one_r.p, h.s));
+    HIPCHECK(vec_fill(e.nkeep, 1.0, one_k.p, h.s));
+    double* Dp = D.p + e.ooff;
+    HIPCHECK(gemm_f64(false, e.nrow, e.nkeep, 1, 1.0, e.eps.p, 1, 0, one_k.p, e.nkeep, 0, 0.0, Dp,
+                      e.nkeep, 0, 1, h.s));
+    HIPCHECK(gemm_f64(false, e.nrow, e.nkeep, 1, 1.0, one_r.p, 1, 0, e.mu.p, e.nkeep, 0, 1.0, Dp,
+                      e.nkeep, 0, 1, h.s));
+    HIPCHECK(vec_fill(1, h.d.shift - h.e0[L], one_r.p, h.s));
+    DBuf shiftv(e.nrow * e.nkeep);
+    HIPCHECK(vec_fill(e.nrow * e.nkeep, h.d.shift - h.e0[L], shiftv.p, h.s));
+    HIPCHECK(vec_axpy(e.nrow * e.nkeep, 1.0, shiftv.p, Dp, h.s));
+    HIPCHECK(vec_min(e.nrow * e.nkeep, Dp, h.red_partial.p, h.red_out.p, h.s));
+    mn = std::min(mn, dev_scalar(h, h.red_out.p));
+  }
+  *dmin = mn;
+}
+
+int pcg(H& h, int L, const double* b_orth, double tol, int maxiter, DBuf& t, caspt2_info& info) {
+  const int set = set_of(h, L);
+  const int64_t n = olen(h, set);
+  DBuf D;
+  double dmin;
+  build_denoms(h, L, D, &dmin);
+  info.min_denom = dmin;
+  info.e0 = h.e0[L];
+  info.emin_kept = INFINITY;
+  info.emax_dropped = -1.0;
+  for (auto& e : h.sets[set]) {
+    info.emin_kept = std::min(info.emin_kept, e.emin_kept);
+    info.emax_dropped = std::max(info.emax_dropped, e.emax_dropped);
+  }
+  if (!(dmin > 0.0)) return CASPT2_E_INDEFINITE;
+  t.alloc(n);
+  t.zero(h.s);
+  DBuf r(n), z(n), p(n), Ap(n), x(h.length), sg(h.length);
+  HIPCHECK(vec_scale_copy(n, -1.0, b_orth, r.p, h.s));
+  HIPCHECK(vec_div(n, r.p, D.p, z.p, h.s));
+  HIPCHECK(hipMemcpyAsync(p.p, z.p, n * sizeof(double), hipMemcpyDeviceToDevice, h.s));
+  double rz = ddot(h, n, r.p, z.p);
+  double rn = std::sqrt(ddot(h, n, r.p, r.p));
+  int it = 0;
+  while (rn > tol && it < maxiter) {
+    from_orth(h, set, p.p, x.p);
+    residual(h, L, x.p, sg.p, false);
+    to_orth(h, set, sg.p, Ap.p);
+    const double pAp = ddot(h, n, p.p, Ap.p);
+    if (!(pAp > 0.0)) {
+      info.iters = it;
+      info.resnorm = rn;
+      return CASPT2_E_INDEFINITE;
+    }
+    const double alpha = rz / pAp;
+    HIPCHECK(vec_axpy(n, alpha, p.p, t.p, h.s));
+    HIPCHECK(vec_axpy(n, -alpha, Ap.p, r.p, h.s));
+    rn = std::sqrt(ddot(h, n, r.p, r.p));
+    HIPCHECK(vec_div(n, r.p, D.p, z.p, h.s));
+    const double rz2 = ddot(h, n, r.p, z.p);
+    HIPCHECK(vec_xpay(n, z.p, rz2 / rz, p.p, h.s));
+    rz = rz2;
+    ++it;
+  }
+  info.iters = it;
+  info.resnorm = rn;
+  info.flags = rn <= tol ? 1 : 0;
+  return rn <= tol ? CASPT2_OK : CASPT2_E_NOCONV;
+}
+
+void validate(const caspt2_dims* d, const std::vector<double>& f, const std::vector<double>& hc,
+              int nmo, int nc, int na) {
+  auto bad = [](const char* m) { throw DevError(CASPT2_E_ARG, m); };
+  for (double v : f)
+    if (!std::isfinite(v)) bad("non-finite fock");
+  for (double v : hc)
+    if (!std::isfinite(v)) bad("non-finite hcore");
+  for (int i = 0; i < nmo; ++i)
+    for (int j = 0; j < nmo; ++j) {
+      if (std::fabs(f[i * nmo + j] - f[j * nmo + i]) > 1e-12) bad("fock not symmetric");
+      if (std::fabs(hc[i * nmo + j] - hc[j * nmo + i]) > 1e-12) bad("hcore not symmetric");
+    }
+  (void)d;
+  (void)na;
+  (void)nc;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+#define ABI_GUARD(...)                                                       \
+  try {                                                                      \
+    __VA_ARGS__                                                              \
+  } catch (const DevError& ex) {                                             \
+    g_last_error = ex.what();                                                \
+    return ex.code;                                                          \
+  } catch (const std::exception& ex) {                                       \
+    g_last_error = ex.what();                                                \
+    return CASPT2_E_DEVICE;                                                  \
+  }
+
+extern "C" {
+
+const char* caspt2_last_error(void) { return g_last_error.c_str(); }
+
+const char* caspt2_strerror(int code) {
+  switch (code) {
+    case CASPT2_OK: return "ok";
+    case CASPT2_E_ARG: return "invalid argument";
+    case CASPT2_E_NOMEM: return "device out of memory";
+    case CASPT2_E_DEVICE: return "HIP device error";
+    case CASPT2_E_NOCONV: return "not converged";
+    case CASPT2_E_INDEFINITE: return "operator not positive definite";
+    case CASPT2_E_NOTIMPL: return "not implemented";
+    case CASPT2_E_STATE: return "call out of order";
+    default: return "unknown status";
+  }
+}
+
+int caspt2_create(const caspt2_dims* dims, const caspt2_inputs* in, int on_device, void* stream,
+                  caspt2_handle** out) {
+  if (!dims || !in || !out) return CASPT2_E_ARG;
+  *out = nullptr;
+  std::unique_ptr<caspt2_handle> hp(new caspt2_handle());
+  H& h = *hp;
+  ABI_GUARD({
+    h.d = *dims;
+    h.s = (hipStream_t)stream;
+    h.nc = dims->nclosed;
+    h.na = dims->nact;
+    h.nv = dims->nvirt;
+    h.naux = dims->naux;
+    h.nst = dims->nstates;
+    h.nmo = h.nc + h.na + h.nv;
+    if (h.nc < 0 || h.na < 0 || h.nv < 0 || h.naux <= 0 || h.nst <= 0 || h.nst > 16 ||
+        h.nmo <= 0 || dims->nelec < 0 || dims->nelec > 2 * h.na ||
+        (dims->scheme != CASPT2_MSMR && dims->scheme != CASPT2_SSSR) ||
+        dims->precision != CASPT2_FP64 || !(dims->ovl_thresh > 0.0) || !std::isfinite(dims->shift))
+      throw DevError(CASPT2_E_ARG, "bad dimensions");
+    if (!in->fock || !in->hcore || !in->dfB || !in->ci || !in->eref)
+      throw DevError(CASPT2_E_ARG, "null input");
+    h.as = std::make_unique<ActiveSpace>(h.na);
+    h.sec0 = Sector{(dims->nelec + 1) / 2, dims->nelec / 2};
+    h.ndet = h.as->dim(h.sec0);
+    if (h.nst > h.ndet) throw DevError(CASPT2_E_ARG, "more states than determinants");
+    const int64_t n2 = (int64_t)h.nmo * h.nmo;
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToHost : hipMemcpyHostToHost;
+    h.h_fock.resize(n2);
+    std::vector<double> hc(n2);
+    h.eref.resize(h.nst);
+    HIPCHECK(hipMemcpy(h.h_fock.data(), in->fock, n2 * sizeof(double), kind));
+    HIPCHECK(hipMemcpy(hc.data(), in->hcore, n2 * sizeof(double), kind));
+    HIPCHECK(hipMemcpy(h.eref.data(), in->eref, h.nst * sizeof(double), kind));
+    validate(dims, h.h_fock, hc, h.nmo, h.nc, h.na);
+    for (double v : h.eref)
+      if (!std::isfinite(v)) throw DevError(CASPT2_E_ARG, "non-finite eref");
+    // closed-closed and virtual-virtual blocks must be diagonal
+    bool offblock = false;
+    for (int i = 0; i < h.nmo; ++i)
+      for (int j = 0; j < h.nmo; ++j) {
+        if (i == j) continue;
+        auto cls = [&](int p) { return p < h.nc ? 0 : p < h.nc + h.na ? 1 : 2; };
+        const double v = h.h_fock[i * h.nmo + j];
+        if (cls(i) == cls(j) && cls(i) != 1 && std::fabs(v) > 1e-12)
+          throw DevError(CASPT2_E_NOTIMPL, "non-diagonal closed or virtual Fock block");
+        if (cls(i) != cls(j) && v != 0.0) offblock = true;
+      }
+    if (offblock)
+      throw DevError(CASPT2_E_NOTIMPL, "Fock couplings between orbital classes not built yet");
+    h.h_eps.resize(h.nmo);
+    for (int i = 0; i < h.nmo; ++i) h.h_eps[i] = h.h_fock[i * h.nmo + i];
+    // device copies
+    const hipMemcpyKind k2 = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    h.fock.alloc(n2);
+    h.hcore.alloc(n2);
+    h.B.alloc((int64_t)h.naux * n2);
+    h.ci_raw.alloc((int64_t)h.nst * h.ndet);
+    h.ci.alloc((int64_t)h.nst * h.ndet);
+    HIPCHECK(hipMemcpyAsync(h.fock.p, h.h_fock.data(), n2 * sizeof(double), hipMemcpyHostToDevice, h.s));
+    HIPCHECK(hipMemcpyAsync(h.hcore.p, hc.data(), n2 * sizeof(double), hipMemcpyHostToDevice, h.s));
+    HIPCHECK(hipMemcpyAsync(h.B.p, in->dfB, (size_t)h.naux * n2 * sizeof(double), k2, h.s));
+    HIPCHECK(hipMemcpyAsync(h.ci_raw.p, in->ci, (size_t)h.nst * h.ndet * sizeof(double), k2, h.s));
+    h.red_partial.alloc(1024);
+    h.red_out.alloc(4);
+    // ---- XMS (Eqs. 3-5): F^ref_MN = <M| f_act |N> -------------------------
+    const int nst = h.nst;
+    DBuf fact((int64_t)h.na * h.na), W((int64_t)nst * h.ndet), W2((int64_t)nst * h.ndet), Fr(nst * nst);
+    {
+      std::vector<double> fa((size_t)h.na * h.na);
+      for (int r = 0; r < h.na; ++r)
+        for (int s2 = 0; s2 < h.na; ++s2) fa[r * h.na + s2] = h.h_fock[(h.nc + r) * h.nmo + h.nc + s2];
+      if (!fa.empty())
+        HIPCHECK(hipMemcpyAsync(fact.p, fa.data(), fa.size() * sizeof(double), hipMemcpyHostToDevice, h.s));
+    }
+    if (h.na > 0) {
+      apply_onebody(h, fact.p, 0, h.ci_raw.p, nst, h.sec0, W.p);
+      apply_onebody(h, fact.p, 1, h.ci_raw.p, nst, h.sec0, W2.p);
+      HIPCHECK(vec_axpy((int64_t)nst * h.ndet, 1.0, W2.p, W.p, h.s));
+      HIPCHECK(gemm_f64(true, nst, nst, h.ndet, 1.0, h.ci_raw.p, h.ndet, 0, W.p, h.ndet, 0, 0.0,
+                        Fr.p, nst, 0, 1, h.s));
+    } else {
+      Fr.zero(h.s);
+    }
+    h.fref.resize(nst * nst);
+    HIPCHECK(hipMemcpyAsync(h.fref.data(), Fr.p, nst * nst * sizeof(double), hipMemcpyDeviceToHost, h.s));
+    host_sync(h);
+    DBuf wv(nst), Ud(nst * nst);
+    h.U.assign(nst * nst, 0.0);
+    h.e0.assign(nst, 0.0);
+    if (dims->xms) {
+      HIPCHECK(small_eigh(nst, Fr.p, wv.p, Ud.p, h.s));
+      HIPCHECK(hipMemcpyAsync(h.U.data(), Ud.p, nst * nst * sizeof(double), hipMemcpyDeviceToHost, h.s));
+      HIPCHECK(hipMemcpyAsync(h.e0.data(), wv.p, nst * sizeof(double), hipMemcpyDeviceToHost, h.s));
+      host_sync(h);
+    } else {
+      for (int k = 0; k < nst; ++k) {
+        h.U[k * nst + k] = 1.0;
+        h.e0[k] = h.fref[k * nst + k];
+      }
+      HIPCHECK(hipMemcpyAsync(Ud.p, h.U.data(), nst * nst * sizeof(double), hipMemcpyHostToDevice, h.s));
+    }
+    // rotated CI: ci[M] = sum_N U[N][M] ci_raw[N]  ->  C = U^T ci_raw
+    {
+      DBuf Ut(nst * nst);
+      const int64_t dims2[2] = {nst, nst};
+      const int64_t str2[2] = {1, nst};
+      Ut.zero(h.s);
+      HIPCHECK(permute_axpy(2, dims2, str2, 1.0, Ud.p, Ut.p, h.s));
+      HIPCHECK(gemm_f64(false, nst, h.ndet, nst, 1.0, Ut.p, nst, 0, h.ci_raw.p, h.ndet, 0, 0.0,
+                        h.ci.p, h.ndet, 0, 1, h.s));
+      // H^ref = U^T diag(eref) U
+      DBuf Er(nst * nst), T1(nst * nst), Hr(nst * nst);
+      std::vector<double> ed(nst * nst, 0.0);
+      for (int k = 0; k < nst; ++k) ed[k * nst + k] = h.eref[k];
+      HIPCHECK(hipMemcpyAsync(Er.p, ed.data(), nst * nst * sizeof(double), hipMemcpyHostToDevice, h.s));
+      HIPCHECK(gemm_f64(false, nst, nst, nst, 1.0, Er.p, nst, 0, Ud.p, nst, 0, 0.0, T1.p, nst, 0, 1, h.s));
+      HIPCHECK(gemm_f64(false, nst, nst, nst, 1.0, Ut.p, nst, 0, T1.p, nst, 0, 0.0, Hr.p, nst, 0, 1, h.s));
+      h.href.resize(nst * nst);
+      HIPCHECK(hipMemcpyAsync(h.href.data(), Hr.p, nst * nst * sizeof(double), hipMemcpyDeviceToHost, h.s));
+      host_sync(h);
+    }
+    h.vcache.clear();
+    // ---- blocks, orthonormal bases, sources ------------------------------
+    setup_blocks(h);
+    setup_sources(h);
+    h.eri.clear();
+    host_sync(h);
+    *out = hp.release();
+    return CASPT2_OK;
+  })
+}
+
+int caspt2_destroy(caspt2_handle* h) {
+  delete h;
+  return CASPT2_OK;
+}
+
+int64_t caspt2_vector_length(const caspt2_handle* h) { return h ? h->length : -1; }
+
+int caspt2_layout(const caspt2_handle* h, int32_t k, int64_t* offset, int64_t* rows, int64_t* nalpha) {
+  if (!h || k < 0 || k >= (int32_t)h->sets[0].size()) return CASPT2_E_ARG;
+  const auto& e = h->sets[0][k];
+  if (offset) *offset = e.offset;
+  if (rows) *rows = e.nrow;
+  if (nalpha) *nalpha = e.nalpha;
+  return CASPT2_OK;
+}
+
+int caspt2_residual(caspt2_handle* h, int32_t L, int32_t with_source, const double* x, double* sigma) {
+  if (!h || L < 0 || L >= h->nst || !x || !sigma) return CASPT2_E_ARG;
+  ABI_GUARD({
+    residual(*h, L, x, sigma, with_source != 0);
+    host_sync(*h);
+    return CASPT2_OK;
+  })
+}
+
+int caspt2_residual_all(caspt2_handle* h, int32_t with_source, const double* x, double* sigma) {
+  if (!h || !x || !sigma) return CASPT2_E_ARG;
+  ABI_GUARD({
+    for (int L = 0; L < h->nst; ++L)
+      residual(*h, L, x + (int64_t)L * h->length, sigma + (int64_t)L * h->length, with_source != 0);
+    host_sync(*h);
+    return CASPT2_OK;
+  })
+}
+
+int caspt2_solve_amplitudes(caspt2_handle* h, double tol, int32_t maxiter, caspt2_info* info) {
+  if (!h || !(tol > 0.0) || maxiter < 0) return CASPT2_E_ARG;
+  ABI_GUARD({
+    H& hh = *h;
+    hh.T.clear();
+    hh.Tt.clear();
+    hh.tinfo.assign(hh.nst, caspt2_info{});
+    int status = CASPT2_OK;
+    for (int L = 0; L < hh.nst; ++L) {
+      const int set = set_of(hh, L);
+      DBuf b(olen(hh, set)), t;
+      to_orth(hh, set, hh.src[set][L].p, b.p);
+      const int rc = pcg(hh, L, b.p, tol, maxiter, t, hh.tinfo[L]);
+      if (rc == CASPT2_E_INDEFINITE) return rc;
+      if (rc != CASPT2_OK) status = rc;
+      DBuf T(hh.length);
+      from_orth(hh, set, t.p, T.p);
+      hh.T.push_back(std::move(T));
+      hh.Tt.push_back(std::move(t));
+    }
+    host_sync(hh);
+    hh.have_T = true;
+    hh.have_heff = hh.have_lam = false;
+    if (info)
+      for (int L = 0; L < hh.nst; ++L) info[L] = hh.tinfo[L];
+    return status;
+  })
+}
+
+int caspt2_get_amplitudes(caspt2_handle* h, int32_t L, double* T) {
+  if (!h || L < 0 || L >= h->nst || !T) return CASPT2_E_ARG;
+  if (!h->have_T) return CASPT2_E_STATE;
+  ABI_GUARD({
+    HIPCHECK(hipMemcpyAsync(T, h->T[L].p, h->length * sizeof(double), hipMemcpyDeviceToDevice, h->s));
+    host_sync(*h);
+    return CASPT2_OK;
+  })
+}
+
+int xms_rotate(const caspt2_handle* h, double* U, double* e0) {
+  if (!h) return CASPT2_E_ARG;
+  if (U) std::memcpy(U, h->U.data(), h->nst * h->nst * sizeof(double));
+  if (e0) std::memcpy(e0, h->e0.data(), h->nst * sizeof(double));
+  return CASPT2_OK;
+}
+
+int xms_heff(caspt2_handle* h, double* heff, double* e_ms, double* R) {
+  if (!h) return CASPT2_E_ARG;
+  if (!h->have_T) return CASPT2_E_STATE;
+  ABI_GUARD({
+    H& hh = *h;
+    const int nst = hh.nst;
+    std::vector<double> Hm(hh.href);
+    for (int L = 0; L < nst; ++L) {
+      for (int Lp = 0; Lp < nst; ++Lp) {
+        const double a = ddot(hh, hh.length, hh.T[L].p, hh.src[set_of(hh, L)][Lp].p);
+        const double b = ddot(hh, hh.length, hh.T[Lp].p, hh.src[set_of(hh, Lp)][L].p);
+        Hm[L * nst + Lp] += 0.5 * (a + b);
+      }
+      const int64_t n = olen(hh, set_of(hh, L));
+      Hm[L * nst + L] -= hh.d.shift * ddot(hh, n, hh.Tt[L].p, hh.Tt[L].p);
+    }
+    DBuf Hd(nst * nst), wv(nst), Rd(nst * nst);
+    HIPCHECK(hipMemcpyAsync(Hd.p, Hm.data(), nst * nst * sizeof(double), hipMemcpyHostToDevice, hh.s));
+    HIPCHECK(small_eigh(nst, Hd.p, wv.p, Rd.p, hh.s));
+    hh.heff = Hm;
+    hh.ems.resize(nst);
+    hh.R.resize(nst * nst);
+    HIPCHECK(hipMemcpyAsync(hh.ems.data(), wv.p, nst * sizeof(double), hipMemcpyDeviceToHost, hh.s));
+    HIPCHECK(hipMemcpyAsync(hh.R.data(), Rd.p, nst * nst * sizeof(double), hipMemcpyDeviceToHost, hh.s));
+    host_sync(hh);
+    if (heff) std::memcpy(heff, Hm.data(), nst * nst * sizeof(double));
+    if (e_ms) std::memcpy(e_ms, hh.ems.data(), nst * sizeof(double));
+    if (R) std::memcpy(R, hh.R.data(), nst * nst * sizeof(double));
+    hh.have_heff = true;
+    return CASPT2_OK;
+  })
+}
+
+int caspt2_solve_lambda(caspt2_handle* h, int32_t P, double tol, int32_t maxiter, caspt2_info* info) {
+  if (!h || P < 0 || P >= h->nst || !(tol > 0.0) || maxiter < 0) return CASPT2_E_ARG;
+  if (!h->have_heff) return CASPT2_E_STATE;
+  ABI_GUARD({
+    H& hh = *h;
+    const int nst = hh.nst;
+    hh.lam.clear();
+    hh.lamt.clear();
+    hh.linfo.assign(nst, caspt2_info{});
+    int status = CASPT2_OK;
+    for (int L = 0; L < nst; ++L) {
+      const int set = set_of(hh, L);
+      const int64_t n = olen(hh, set);
+      // b = R_LP sum_N R_NP X^T V^(N) - 2 E_s R_LP^2 t_L   (Eq. 20; X^T S X = 1)
+      DBuf b(n), tmp(n), t;
+      b.zero(hh.s);
+      for (int N = 0; N < nst; ++N) {
+        to_orth(hh, set, hh.src[set][N].p, tmp.p);
+        HIPCHECK(vec_axpy(n, hh.R[L * nst + P] * hh.R[N * nst + P], tmp.p, b.p, hh.s));
+      }
+      HIPCHECK(vec_axpy(n, -2.0 * hh.d.shift * hh.R[L * nst + P] * hh.R[L * nst + P], hh.Tt[L].p,
+                        b.p, hh.s));
+      const int rc = pcg(hh, L, b.p, tol, maxiter, t, hh.linfo[L]);
+      if (rc == CASPT2_E_INDEFINITE) return rc;
+      if (rc != CASPT2_OK) status = rc;
+      DBuf lam(hh.length);
+      from_orth(hh, set, t.p, lam.p);
+      hh.lam.push_back(std::move(lam));
+      hh.lamt.push_back(std::move(t));
+    }
+    host_sync(hh);
+    hh.have_lam = true;
+    if (info)
+      for (int L = 0; L < nst; ++L) info[L] = hh.linfo[L];
+    return status;
+  })
+}
+
+int caspt2_get_lambda(caspt2_handle* h, int32_t L, double* lambda) {
+  if (!h || L < 0 || L >= h->nst || !lambda) return CASPT2_E_ARG;
+  if (!h->have_lam) return CASPT2_E_STATE;
+  ABI_GUARD({
+    HIPCHECK(hipMemcpyAsync(lambda, h->lam[L].p, h->length * sizeof(double), hipMemcpyDeviceToDevice,
+                            h->s));
+    host_sync(*h);
+    return CASPT2_OK;
+  })
+}
+
+}  // extern "C"
+
+#include "../../include/caspt2_debug.h"
+
+extern "C" {
+
+int caspt2_debug_gemm(int32_t b_is_nk, int64_t M, int64_t N, int64_t K, const double* A,
+                      const double* B, double* C) {
+  ABI_GUARD({
+    HIPCHECK(gemm_f64(b_is_nk != 0, M, N, K, 1.0, A, K, 0, B, b_is_nk ? K : N, 0, 0.0, C, N, 0, 1,
+                      nullptr));
+    HIPCHECK(hipStreamSynchronize(nullptr));
+    return CASPT2_OK;
+  })
+}
+
+int caspt2_debug_entry(const caspt2_handle* h, int32_t set, int32_t k, int32_t which, double* out) {
+  if (!h || set < 0 || set >= (int32_t)h->sets.size() || k < 0 ||
+      k >= (int32_t)h->sets[set].size() || !out)
+    return CASPT2_E_ARG;
+  ABI_GUARD({
+    const auto& e = h->sets[set][k];
+    const double* src = nullptr;
+    int64_t n = 0;
+    switch (which) {
+      case 0: src = e.S.p; n = e.S.n; break;
+      case 1: src = e.F.p; n = e.F.n; break;
+      case 2: src = e.eps.p; n = e.eps.n; break;
+      case 3: out[0] = (double)e.nkeep; return CASPT2_OK;
+      case 4: src = e.X.p; n = e.X.n; break;
+      case 5: src = e.mu.p; n = e.mu.n; break;
+      default: return CASPT2_E_ARG;
+    }
+    if (n > 0) HIPCHECK(hipMemcpy(out, src, n * sizeof(double), hipMemcpyDeviceToHost));
+    return CASPT2_OK;
+  })
+}
+
+int caspt2_debug_source(const caspt2_handle* h, int32_t set, int32_t N, double* out) {
+  if (!h || set < 0 || set >= (int32_t)h->src.size() || N < 0 || N >= h->nst || !out)
+    return CASPT2_E_ARG;
+  ABI_GUARD({
+    HIPCHECK(hipMemcpy(out, h->src[set][N].p, h->length * sizeof(double), hipMemcpyDeviceToDevice));
+    return CASPT2_OK;
+  })
+}
+
+int caspt2_debug_eigh(int32_t n, double* A, double* w, double* V) {
+  if (n <= 0 || !A || !w || !V) return CASPT2_E_ARG;
+  ABI_GUARD({
+    double* ws = nullptr;
+    HIPCHECK(hipMalloc(&ws, (4 * (size_t)n + 16) * sizeof(double)));
+    int sweeps = 0;
+    hipError_t e = jacobi_eigh(n, A, V, ws, 60, 1e-15, nullptr, &sweeps);
+    std::vector<double> full((size_t)n * n);
+    if (e == hipSuccess) e = hipMemcpy(full.data(), A, full.size() * sizeof(double), hipMemcpyDeviceToHost);
+    (void)hipFree(ws);
+    HIPCHECK(e);
+    for (int i = 0; i < n; ++i) w[i] = full[(size_t)i * n + i];
+    return CASPT2_OK;
+  })
+}
+
+}  // extern "C"

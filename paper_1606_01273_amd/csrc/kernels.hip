@@ -1,0 +1,747 @@
+// HIP kernels for gfx950 (CDNA4): operator application on CI vectors, FP64
+// MFMA GEMMs, packed-term contractions, Jacobi eigensolver, vector ops.
+#include "kernels.hpp"
+
+#include <cmath>
+#include <vector>
+
+namespace caspt2 {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+static inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+// ---------------------------------------------------------------------------
+// operator application: Y[r][lead][t] = sign[r][t] * X[lead][src[r][t]]
+// ---------------------------------------------------------------------------
+__global__ void k_gather_apply(const double* __restrict__ X, int64_t nlead, int64_t dim_from,
+                               const int32_t* __restrict__ src, const double* __restrict__ sign,
+                               int na, int64_t dim_to, double* __restrict__ Y) {
+  const int64_t total = (int64_t)na * nlead * dim_to;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t t = g % dim_to;
+    const int64_t rl = g / dim_to;
+    const int64_t lead = rl % nlead;
+    const int64_t r = rl / nlead;
+    const int32_t s = src[r * dim_to + t];
+    Y[g] = s >= 0 ? sign[r * dim_to + t] * X[lead * dim_from + s] : 0.0;
+  }
+}
+
+hipError_t launch_gather_apply(const double* X, int64_t nlead, int64_t dim_from,
+                               const int32_t* src, const double* sign, int na, int64_t dim_to,
+                               double* Y, hipStream_t s) {
+  const int64_t total = (int64_t)na * nlead * dim_to;
+  if (total == 0) return hipSuccess;
+  unsigned grid = cdiv(total, 256);
+  if (grid > 65536) grid = 65536;
+  hipLaunchKernelGGL(k_gather_apply, dim3(grid), dim3(256), 0, s, X, nlead, dim_from, src, sign,
+                     na, dim_to, Y);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// FP64 GEMM on MFMA (v_mfma_f64_16x16x4f64)
+//   block tile 64x64, 4 waves of 32x32, K step 16 through LDS.
+//   Operand layout of the 16x16x4 instruction (per lane l):
+//     A[i][k]: i = l % 16, k = l / 16;  B[k][j]: j = l % 16, k = l / 16;
+//     D[i][j]: j = l % 16, i = l / 16 + 4 * v, v = 0..3 (checked on gfx950).
+// ---------------------------------------------------------------------------
+constexpr int BM = 64, BN = 64, BK = 16, LDP = BK + 1;
+
+template <bool B_NK, bool DUAL>
+__global__ __launch_bounds__(256) void k_gemm_f64(int64_t M, int64_t N, int64_t K, double alpha,
+                                                  const double* __restrict__ A, int64_t lda,
+                                                  int64_t sA, const double* __restrict__ B,
+                                                  int64_t ldb, int64_t sB,
+                                                  const double* __restrict__ B2, double beta,
+                                                  double* __restrict__ C, int64_t ldc, int64_t sC,
+                                                  const double* __restrict__ dvec, double dshift,
+                                                  const double* __restrict__ V, int64_t ldv) {
+  __shared__ double As[BM][LDP];
+  __shared__ double Bs[BN][LDP];
+  __shared__ double B2s[DUAL ? BN : 1][LDP];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int64_t bz = blockIdx.z;
+  A += bz * sA;
+  B += bz * sB;
+  C += bz * sC;
+  const int64_t m0 = (int64_t)blockIdx.y * BM;
+  const int64_t n0 = (int64_t)blockIdx.x * BN;
+  d4 acc[2][2], acc2[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+      acc[i][j] = d4{0, 0, 0, 0};
+      acc2[i][j] = d4{0, 0, 0, 0};
+    }
+  for (int64_t k0 = 0; k0 < K; k0 += BK) {
+    // A tile: 64 rows x 16 k, 4 per thread
+    {
+      const int r = tid >> 2, c = (tid & 3) * 4;
+      const int64_t gm = m0 + r;
+      for (int u = 0; u < 4; ++u) {
+        const int64_t gk = k0 + c + u;
+        As[r][c + u] = (gm < M && gk < K) ? A[gm * lda + gk] : 0.0;
+      }
+    }
+    if (B_NK) {
+      const int r = tid >> 2, c = (tid & 3) * 4;
+      const int64_t gn = n0 + r;
+      for (int u = 0; u < 4; ++u) {
+        const int64_t gk = k0 + c + u;
+        Bs[r][c + u] = (gn < N && gk < K) ? B[gn * ldb + gk] : 0.0;
+      }
+    } else {
+      // B is [K][N]: thread loads k = tid/16, n = (tid%16)*4 .. +3
+      const int kk = tid >> 4, c = (tid & 15) * 4;
+      const int64_t gk = k0 + kk;
+      for (int u = 0; u < 4; ++u) {
+        const int64_t gn = n0 + c + u;
+        Bs[c + u][kk] = (gn < N && gk < K) ? B[gk * ldb + gn] : 0.0;
+        if (DUAL) B2s[c + u][kk] = (gn < N && gk < K) ? B2[gk * ldb + gn] : 0.0;
+      }
+    }
+    __syncthreads();
+    for (int kk = 0; kk < BK; kk += 4) {
+      double a[2], b[2], b2[2];
+      for (int i = 0; i < 2; ++i) a[i] = As[wm * 32 + i * 16 + (lane & 15)][kk + (lane >> 4)];
+      for (int j = 0; j < 2; ++j) {
+        b[j] = Bs[wn * 32 + j * 16 + (lane & 15)][kk + (lane >> 4)];
+        if (DUAL) b2[j] = B2s[wn * 32 + j * 16 + (lane & 15)][kk + (lane >> 4)];
+      }
+      for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+          if (DUAL) acc2[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b2[j], acc2[i][j], 0, 0, 0);
+        }
+    }
+    __syncthreads();
+  }
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      for (int v = 0; v < 4; ++v) {
+        const int64_t gm = m0 + wm * 32 + i * 16 + (lane >> 4) + 4 * v;
+        const int64_t gn = n0 + wn * 32 + j * 16 + (lane & 15);
+        if (gm < M && gn < N) {
+          if (DUAL) {
+            double r = dvec[gm] + dshift;
+            double val = r * acc[i][j][v] + acc2[i][j][v];
+            if (V) val += V[gm * ldv + gn];
+            C[gm * ldc + gn] = val;
+          } else {
+            double val = alpha * acc[i][j][v];
+            if (beta != 0.0) val += beta * C[gm * ldc + gn];
+            C[gm * ldc + gn] = val;
+          }
+        }
+      }
+}
+
+hipError_t gemm_f64(bool b_is_nk, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
+                    int64_t lda, int64_t sA, const double* B, int64_t ldb, int64_t sB, double beta,
+                    double* C, int64_t ldc, int64_t sC, int batch, hipStream_t s) {
+  if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+  dim3 grid(cdiv(N, BN), cdiv(M, BM), batch);
+  if (b_is_nk)
+    hipLaunchKernelGGL((k_gemm_f64<true, false>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda,
+                       sA, B, ldb, sB, (const double*)nullptr, beta, C, ldc, sC,
+                       (const double*)nullptr, 0.0, (const double*)nullptr, (int64_t)0);
+  else
+    hipLaunchKernelGGL((k_gemm_f64<false, false>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda,
+                       sA, B, ldb, sB, (const double*)nullptr, beta, C, ldc, sC,
+                       (const double*)nullptr, 0.0, (const double*)nullptr, (int64_t)0);
+  return hipGetLastError();
+}
+
+hipError_t residual_gemm_f64(int64_t M, int64_t N, int64_t K, const double* X, int64_t ldx,
+                             const double* S, const double* F, const double* d, double dshift,
+                             const double* V, int64_t ldv, double* C, int64_t ldc, hipStream_t s) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  dim3 grid(cdiv(N, BN), cdiv(M, BM), 1);
+  hipLaunchKernelGGL((k_gemm_f64<false, true>), grid, dim3(256), 0, s, M, N, K, 1.0, X, ldx,
+                     (int64_t)0, S, N, (int64_t)0, F, 0.0, C, ldc, (int64_t)0, d, dshift, V, ldv);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// streaming residual for small alpha dimension (K = N <= 64):
+//   C[m][n] = V[m][n] + (d[m] + dshift) * sum_k X[m][k] S[k][n] + sum_k X[m][k] F[k][n]
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_residual_small(int64_t M, int N, const double* __restrict__ X,
+                                                        const double* __restrict__ S,
+                                                        const double* __restrict__ F,
+                                                        const double* __restrict__ d, double dshift,
+                                                        const double* __restrict__ V,
+                                                        double* __restrict__ C) {
+  __shared__ double Ss[64 * 64];
+  __shared__ double Fs[64 * 64];
+  for (int i = threadIdx.x; i < N * N; i += blockDim.x) {
+    Ss[i] = S[i];
+    Fs[i] = F[i];
+  }
+  __syncthreads();
+  const int64_t total = M * N;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t m = g / N;
+    const int n = (int)(g % N);
+    const double* x = X + m * N;
+    double as = 0.0, af = 0.0;
+    for (int k = 0; k < N; ++k) {
+      const double xv = x[k];
+      as += xv * Ss[k * N + n];
+      af += xv * Fs[k * N + n];
+    }
+    double val = (d[m] + dshift) * as + af;
+    if (V) val += V[g];
+    C[g] = val;
+  }
+}
+
+hipError_t residual_small_f64(int64_t M, int64_t N, const double* X, const double* S,
+                              const double* F, const double* d, double dshift, const double* V,
+                              double* C, hipStream_t s) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  if (N > 64) return hipErrorInvalidValue;
+  unsigned grid = cdiv(M * N, 256);
+  if (grid > 65536) grid = 65536;
+  hipLaunchKernelGGL(k_residual_small, dim3(grid), dim3(256), 0, s, M, (int)N, X, S, F, d, dshift,
+                     V, C);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// permuted accumulate and leading contraction
+// ---------------------------------------------------------------------------
+struct PermArgs {
+  int nd;
+  int64_t dims[10];
+  int64_t dstride[10];
+};
+
+__global__ void k_permute_axpy(PermArgs p, int64_t total, double c, const double* __restrict__ src,
+                               double* __restrict__ dst) {
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    int64_t rem = g, off = 0;
+    for (int k = p.nd - 1; k >= 0; --k) {
+      const int64_t ik = rem % p.dims[k];
+      rem /= p.dims[k];
+      off += ik * p.dstride[k];
+    }
+    dst[off] += c * src[g];
+  }
+}
+
+hipError_t permute_axpy(int nd, const int64_t* dims, const int64_t* dstride, double c,
+                        const double* src, double* dst, hipStream_t s) {
+  PermArgs p;
+  p.nd = nd;
+  int64_t total = 1;
+  for (int k = 0; k < nd; ++k) {
+    p.dims[k] = dims[k];
+    p.dstride[k] = dstride[k];
+    total *= dims[k];
+  }
+  if (total == 0) return hipSuccess;
+  unsigned grid = cdiv(total, 256);
+  if (grid > 65536) grid = 65536;
+  hipLaunchKernelGGL(k_permute_axpy, dim3(grid), dim3(256), 0, s, p, total, c, src, dst);
+  return hipGetLastError();
+}
+
+__global__ void k_contract_lead(int64_t ni, int64_t nj, const double* __restrict__ c,
+                                const double* __restrict__ G, double* __restrict__ y) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < nj;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int64_t i = 0; i < ni; ++i) acc += c[i] * G[i * nj + j];
+    y[j] += acc;
+  }
+}
+
+hipError_t contract_lead(int64_t ni, int64_t nj, const double* c, const double* G, double* y,
+                         hipStream_t s) {
+  if (nj == 0) return hipSuccess;
+  unsigned grid = cdiv(nj, 256);
+  if (grid > 65536) grid = 65536;
+  hipLaunchKernelGGL(k_contract_lead, dim3(grid), dim3(256), 0, s, ni, nj, c, G, y);
+  return hipGetLastError();
+}
+
+__global__ void k_df_pack(const double* __restrict__ B, int naux, int nmo, int p0, int np, int q0,
+                          int nq, double* __restrict__ Bt) {
+  const int64_t total = (int64_t)np * nq * naux;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t Q = g % naux;
+    const int64_t pq = g / naux;
+    const int64_t p = pq / nq, q = pq % nq;
+    Bt[g] = B[(Q * nmo + p0 + p) * nmo + q0 + q];
+  }
+}
+
+hipError_t df_pack(const double* B, int naux, int nmo, int p0, int np, int q0, int nq, double* Bt,
+                   hipStream_t s) {
+  const int64_t total = (int64_t)np * nq * naux;
+  if (total == 0) return hipSuccess;
+  unsigned grid = cdiv(total, 256);
+  if (grid > 65536) grid = 65536;
+  hipLaunchKernelGGL(k_df_pack, dim3(grid), dim3(256), 0, s, B, naux, nmo, p0, np, q0, nq, Bt);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// packed term contraction
+//   out[row][alpha] += scale * sum_{images e of the orbit} w chi(pi_e)
+//                      * sum_{y} C[idx(e, y)] * G[(y * nalpha + alpha) * gcols + gcol]
+// ---------------------------------------------------------------------------
+__device__ inline void decode_orbit(const TermDesc& d, int64_t row, int e[4]) {
+  // units from the last slot backwards; a swap pair (k, k+1) is one unit
+  int k = d.nslot - 1;
+  int64_t rem = row;
+  while (k >= 0) {
+    int sw = -1;
+    for (int s = 0; s < d.nswap; ++s)
+      if (d.swap_l[s] == k && d.swap_k[s] == k - 1) sw = s;
+    if (sw >= 0) {
+      const int64_t dim = d.slot_dim[k];
+      const int64_t cnt = d.strict[sw] ? dim * (dim - 1) / 2 : dim * (dim + 1) / 2;
+      const int64_t p = rem % cnt;
+      rem /= cnt;
+      int64_t hi;
+      if (d.strict[sw]) {
+        hi = (int64_t)floor((sqrt(8.0 * (double)p + 1.0) + 1.0) * 0.5);
+        while (hi * (hi - 1) / 2 > p) --hi;
+        while ((hi + 1) * hi / 2 <= p) ++hi;
+        e[k - 1] = (int)hi;
+        e[k] = (int)(p - hi * (hi - 1) / 2);
+      } else {
+        hi = (int64_t)floor((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
+        while (hi * (hi + 1) / 2 > p) --hi;
+        while ((hi + 1) * (hi + 2) / 2 <= p) ++hi;
+        e[k - 1] = (int)hi;
+        e[k] = (int)(p - hi * (hi + 1) / 2);
+      }
+      k -= 2;
+    } else {
+      const int64_t dim = d.slot_dim[k];
+      e[k] = (int)(rem % dim);
+      rem /= dim;
+      k -= 1;
+    }
+  }
+}
+
+__global__ void k_term_source(TermDesc d, const double* __restrict__ C, const double* __restrict__ G,
+                              double* __restrict__ out) {
+  const int64_t total = d.nrow * d.nalpha;
+  int64_t ny = 1;
+  for (int k = 0; k < d.nopact; ++k) ny *= d.na;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t row = g / d.nalpha;
+    const int64_t al = g % d.nalpha;
+    int e0[4] = {0, 0, 0, 0};
+    decode_orbit(d, row, e0);
+    int ndistinct = 0;
+    for (int s = 0; s < d.nswap; ++s)
+      if (e0[d.swap_k[s]] != e0[d.swap_l[s]]) ++ndistinct;
+    const double w = d.mode_avg ? 1.0 : 1.0 / sqrt((double)(1 << ndistinct));
+    double acc = 0.0;
+    const int nbits = d.mode_avg ? 1 : (1 << d.nswap);
+    for (int bits = 0; bits < nbits; ++bits) {
+      int e[4] = {e0[0], e0[1], e0[2], e0[3]};
+      double sg = 1.0;
+      bool dup = false;
+      for (int s = 0; s < d.nswap; ++s)
+        if ((bits >> s) & 1) {
+          if (e0[d.swap_k[s]] == e0[d.swap_l[s]]) dup = true;
+          const int t = e[d.swap_k[s]];
+          e[d.swap_k[s]] = e[d.swap_l[s]];
+          e[d.swap_l[s]] = t;
+          sg *= d.chi[s];
+        }
+      if (dup) continue;
+      double val = 0.0;
+      for (int64_t y = 0; y < ny; ++y) {
+        int yi[3] = {0, 0, 0};
+        int64_t yr = y;
+        for (int k = d.nopact - 1; k >= 0; --k) {
+          yi[k] = (int)(yr % d.na);
+          yr /= d.na;
+        }
+        int64_t off = 0;
+        for (int a = 0; a < d.ncax; ++a) {
+          const int src = d.c_slot[a];
+          const int v = src >= 0 ? e[src] : yi[-1 - src];
+          off += (int64_t)v * d.c_stride[a];
+        }
+        val += C[off] * G[(y * d.galpha + d.goff + al) * d.gcols + d.gcol];
+      }
+      acc += sg * val;
+    }
+    out[row * d.ldo + al] += d.scale * w * acc;
+  }
+}
+
+hipError_t term_source(const TermDesc& d, const double* C, const double* G, double* out,
+                       hipStream_t s) {
+  const int64_t total = d.nrow * d.nalpha;
+  if (total == 0) return hipSuccess;
+  unsigned grid = cdiv(total, 256);
+  if (grid > 65536) grid = 65536;
+  hipLaunchKernelGGL(k_term_source, dim3(grid), dim3(256), 0, s, d, C, G, out);
+  return hipGetLastError();
+}
+
+__global__ void k_select_scale_cols(int64_t n, int64_t ncq, const double* __restrict__ Q,
+                                    const int32_t* __restrict__ idx, const double* __restrict__ sc,
+                                    int64_t nk, double* __restrict__ X0) {
+  const int64_t total = n * nk;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = g / nk, k = g % nk;
+    X0[g] = Q[i * ncq + idx[k]] * sc[k];
+  }
+}
+
+hipError_t select_scale_cols(int64_t n, int64_t ncq, const double* Q, const int32_t* idx,
+                             const double* scale, int64_t nk, double* X0, hipStream_t s) {
+  const int64_t total = n * nk;
+  if (total == 0) return hipSuccess;
+  unsigned grid = cdiv(total, 256);
+  if (grid > 65536) grid = 65536;
+  hipLaunchKernelGGL(k_select_scale_cols, dim3(grid), dim3(256), 0, s, n, ncq, Q, idx, scale, nk, X0);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Jacobi eigensolver: parallel cyclic (round-robin) two-sided rotations
+// ---------------------------------------------------------------------------
+__device__ inline int rr_player(int pos, int step, int m) {
+  if (pos == 0) return 0;
+  return 1 + ((pos - 1 + step) % (m - 1));
+}
+
+__global__ void k_jac_params(int n, int m, int step, const double* __restrict__ A,
+                             double* __restrict__ cs, int* __restrict__ pq) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= m / 2) return;
+  int p = rr_player(k, step, m), q = rr_player(m - 1 - k, step, m);
+  if (p > q) {
+    const int t = p;
+    p = q;
+    q = t;
+  }
+  double c = 1.0, s = 0.0;
+  if (q < n) {
+    const double apq = A[(int64_t)p * n + q];
+    if (apq != 0.0) {
+      const double app = A[(int64_t)p * n + p], aqq = A[(int64_t)q * n + q];
+      const double tau = (aqq - app) / (2.0 * apq);
+      const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+      c = 1.0 / sqrt(1.0 + t * t);
+      s = t * c;
+    }
+  }
+  cs[2 * k] = c;
+  cs[2 * k + 1] = s;
+  pq[2 * k] = p;
+  pq[2 * k + 1] = q;
+}
+
+// one thread per (pair a, pair b): rotate the 2x2 block; extra threads rotate V
+__global__ void k_jac_apply(int n, int m, double* __restrict__ A, double* __restrict__ V,
+                            const double* __restrict__ cs, const int* __restrict__ pq) {
+  const int64_t h = m / 2;
+  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g < h * h) {
+    const int a = (int)(g / h), b = (int)(g % h);
+    const int pa = pq[2 * a], qa = pq[2 * a + 1], pb = pq[2 * b], qb = pq[2 * b + 1];
+    const double ca = cs[2 * a], sa = cs[2 * a + 1], cb = cs[2 * b], sb = cs[2 * b + 1];
+    const bool ipa = pa < n, iqa = qa < n, ipb = pb < n, iqb = qb < n;
+    const double m00 = (ipa && ipb) ? A[(int64_t)pa * n + pb] : 0.0;
+    const double m01 = (ipa && iqb) ? A[(int64_t)pa * n + qb] : 0.0;
+    const double m10 = (iqa && ipb) ? A[(int64_t)qa * n + pb] : 0.0;
+    const double m11 = (iqa && iqb) ? A[(int64_t)qa * n + qb] : 0.0;
+    // rows: J_a^T
+    const double r00 = ca * m00 - sa * m10, r01 = ca * m01 - sa * m11;
+    const double r10 = sa * m00 + ca * m10, r11 = sa * m01 + ca * m11;
+    // cols: J_b
+    const double o00 = cb * r00 - sb * r01, o01 = sb * r00 + cb * r01;
+    const double o10 = cb * r10 - sb * r11, o11 = sb * r10 + cb * r11;
+    if (ipa && ipb) A[(int64_t)pa * n + pb] = o00;
+    if (ipa && iqb) A[(int64_t)pa * n + qb] = o01;
+    if (iqa && ipb) A[(int64_t)qa * n + pb] = o10;
+    if (iqa && iqb) A[(int64_t)qa * n + qb] = o11;
+  } else if (g < h * h + (int64_t)n * h) {
+    const int64_t gg = g - h * h;
+    const int i = (int)(gg / h), a = (int)(gg % h);
+    const int pa = pq[2 * a], qa = pq[2 * a + 1];
+    if (qa >= n) return;
+    const double ca = cs[2 * a], sa = cs[2 * a + 1];
+    const double vp = V[(int64_t)i * n + pa], vq = V[(int64_t)i * n + qa];
+    V[(int64_t)i * n + pa] = ca * vp - sa * vq;
+    V[(int64_t)i * n + qa] = sa * vp + ca * vq;
+  }
+}
+
+__global__ void k_eye(int n, double* V) {
+  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g < (int64_t)n * n) V[g] = (g / n == g % n) ? 1.0 : 0.0;
+}
+
+// off-diagonal and total squared norms, one block
+__global__ void k_jac_norms(int n, const double* __restrict__ A, double* __restrict__ out) {
+  __shared__ double so[256], st[256];
+  double off = 0.0, tot = 0.0;
+  for (int64_t g = threadIdx.x; g < (int64_t)n * n; g += blockDim.x) {
+    const double v = A[g];
+    tot += v * v;
+    if (g / n != g % n) off += v * v;
+  }
+  so[threadIdx.x] = off;
+  st[threadIdx.x] = tot;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      so[threadIdx.x] += so[threadIdx.x + w];
+      st[threadIdx.x] += st[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = so[0];
+    out[1] = st[0];
+  }
+}
+
+hipError_t jacobi_eigh(int n, double* A, double* V, double* ws, int max_sweeps, double tol,
+                       hipStream_t s, int* sweeps_done) {
+  if (n <= 0) return hipSuccess;
+  const int m = n + (n & 1);
+  double* cs = ws;
+  double* norms = ws + 2 * m;
+  int* pq = reinterpret_cast<int*>(ws + 2 * m + 4);
+  hipLaunchKernelGGL(k_eye, dim3(cdiv((int64_t)n * n, 256)), dim3(256), 0, s, n, V);
+  int sw = 0;
+  double hn[2];
+  for (; sw < max_sweeps; ++sw) {
+    hipLaunchKernelGGL(k_jac_norms, dim3(1), dim3(256), 0, s, n, A, norms);
+    hipError_t e = hipMemcpyAsync(hn, norms, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return e;
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    if (hn[0] <= tol * tol * hn[1] || hn[1] == 0.0 || m < 2) break;
+    for (int step = 0; step < m - 1; ++step) {
+      hipLaunchKernelGGL(k_jac_params, dim3(cdiv(m / 2, 128)), dim3(128), 0, s, n, m, step, A, cs,
+                         pq);
+      const int64_t work = (int64_t)(m / 2) * (m / 2) + (int64_t)n * (m / 2);
+      hipLaunchKernelGGL(k_jac_apply, dim3(cdiv(work, 256)), dim3(256), 0, s, n, m, A, V, cs, pq);
+    }
+  }
+  if (sweeps_done) *sweeps_done = sw;
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// vectors
+// ---------------------------------------------------------------------------
+__global__ void k_dot_partial(int64_t n, const double* __restrict__ x, const double* __restrict__ y,
+                              double* __restrict__ partial) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n;
+       g += (int64_t)gridDim.x * blockDim.x)
+    acc += x[g] * y[g];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+__global__ void k_sum_final(int np, const double* __restrict__ partial, double* __restrict__ out) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) acc += partial[i];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+hipError_t vec_dot(int64_t n, const double* x, const double* y, double* partial, double* out,
+                   hipStream_t s) {
+  // fixed grid so the summation order is the same on every call
+  const int nb = 1024;
+  hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(256), 0, s, n, x, y, partial);
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, s, nb, partial, out);
+  return hipGetLastError();
+}
+
+__global__ void k_min_partial(int64_t n, const double* __restrict__ x, double* __restrict__ partial) {
+  __shared__ double sh[256];
+  double acc = INFINITY;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n;
+       g += (int64_t)gridDim.x * blockDim.x)
+    acc = fmin(acc, x[g]);
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] = fmin(sh[threadIdx.x], sh[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+__global__ void k_min_final(int np, const double* __restrict__ partial, double* __restrict__ out) {
+  __shared__ double sh[256];
+  double acc = INFINITY;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) acc = fmin(acc, partial[i]);
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] = fmin(sh[threadIdx.x], sh[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+hipError_t vec_min(int64_t n, const double* x, double* partial, double* out, hipStream_t s) {
+  const int nb = 1024;
+  hipLaunchKernelGGL(k_min_partial, dim3(nb), dim3(256), 0, s, n, x, partial);
+  hipLaunchKernelGGL(k_min_final, dim3(1), dim3(256), 0, s, nb, partial, out);
+  return hipGetLastError();
+}
+
+#define CASPT2_ELEMENTWISE(NAME, EXPR)                                                        \
+  __global__ void k_##NAME(int64_t n, double a, const double* __restrict__ x,                \
+                           const double* __restrict__ d, double* __restrict__ y) {           \
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n;                 \
+         g += (int64_t)gridDim.x * blockDim.x) {                                             \
+      EXPR;                                                                                  \
+    }                                                                                        \
+  }
+
+CASPT2_ELEMENTWISE(axpy, y[g] += a * x[g])
+CASPT2_ELEMENTWISE(xpay, y[g] = x[g] + a * y[g])
+CASPT2_ELEMENTWISE(div, y[g] = x[g] / d[g])
+CASPT2_ELEMENTWISE(scale_copy, y[g] = a * x[g])
+CASPT2_ELEMENTWISE(fill, y[g] = a)
+
+static inline unsigned egrid(int64_t n) {
+  unsigned g = cdiv(n, 256);
+  return g > 65536 ? 65536 : (g == 0 ? 1 : g);
+}
+
+hipError_t vec_axpy(int64_t n, double a, const double* x, double* y, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_axpy, dim3(egrid(n)), dim3(256), 0, s, n, a, x, (const double*)nullptr, y);
+  return hipGetLastError();
+}
+hipError_t vec_xpay(int64_t n, const double* x, double a, double* y, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_xpay, dim3(egrid(n)), dim3(256), 0, s, n, a, x, (const double*)nullptr, y);
+  return hipGetLastError();
+}
+hipError_t vec_div(int64_t n, const double* x, const double* d, double* y, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_div, dim3(egrid(n)), dim3(256), 0, s, n, 0.0, x, d, y);
+  return hipGetLastError();
+}
+hipError_t vec_scale_copy(int64_t n, double a, const double* x, double* y, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scale_copy, dim3(egrid(n)), dim3(256), 0, s, n, a, x, (const double*)nullptr,
+                     y);
+  return hipGetLastError();
+}
+hipError_t vec_fill(int64_t n, double v, double* y, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill, dim3(egrid(n)), dim3(256), 0, s, n, v, (const double*)nullptr,
+                     (const double*)nullptr, y);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// small symmetric eigenproblem (n <= 16) on a single thread: cyclic Jacobi,
+// ascending values, eigenvector columns with largest-magnitude entry positive
+// ---------------------------------------------------------------------------
+__global__ void k_small_eigh(int n, const double* __restrict__ Ain, double* __restrict__ w,
+                             double* __restrict__ R) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double A[16][16], Vm[16][16];
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      A[i][j] = 0.5 * (Ain[i * n + j] + Ain[j * n + i]);
+      Vm[i][j] = i == j ? 1.0 : 0.0;
+    }
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        tot += A[i][j] * A[i][j];
+        if (i != j) off += A[i][j] * A[i][j];
+      }
+    if (off <= 1e-34 * tot || off == 0.0) break;
+    for (int p = 0; p < n - 1; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = A[p][q];
+        if (apq == 0.0) continue;
+        const double tau = (A[q][q] - A[p][p]) / (2.0 * apq);
+        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+        const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
+        for (int k = 0; k < n; ++k) {
+          const double akp = A[k][p], akq = A[k][q];
+          A[k][p] = c * akp - s * akq;
+          A[k][q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double apk = A[p][k], aqk = A[q][k];
+          A[p][k] = c * apk - s * aqk;
+          A[q][k] = s * apk + c * aqk;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double vkp = Vm[k][p], vkq = Vm[k][q];
+          Vm[k][p] = c * vkp - s * vkq;
+          Vm[k][q] = s * vkp + c * vkq;
+        }
+      }
+  }
+  int order[16];
+  for (int i = 0; i < n; ++i) order[i] = i;
+  for (int i = 0; i < n; ++i)
+    for (int j = i + 1; j < n; ++j)
+      if (A[order[j]][order[j]] < A[order[i]][order[i]]) {
+        const int t = order[i];
+        order[i] = order[j];
+        order[j] = t;
+      }
+  for (int c = 0; c < n; ++c) {
+    const int k = order[c];
+    w[c] = A[k][k];
+    int imax = 0;
+    for (int i = 1; i < n; ++i)
+      if (fabs(Vm[i][k]) > fabs(Vm[imax][k])) imax = i;
+    const double sg = Vm[imax][k] < 0.0 ? -1.0 : 1.0;
+    for (int i = 0; i < n; ++i) R[i * n + c] = sg * Vm[i][k];
+  }
+}
+
+hipError_t small_eigh(int n, const double* A, double* w, double* R, hipStream_t s) {
+  if (n <= 0 || n > 16) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_small_eigh, dim3(1), dim3(64), 0, s, n, A, w, R);
+  return hipGetLastError();
+}
+
+}  // namespace caspt2

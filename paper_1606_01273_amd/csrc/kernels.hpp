@@ -1,0 +1,97 @@
+// Launchers of the HIP kernels (gfx950).  All take a stream and return
+// hipError_t from the launch.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace caspt2 {
+
+// Y[r][lead][t] = sign[r][t] * X[lead][src[r][t]] (0 where src < 0)
+hipError_t launch_gather_apply(const double* X, int64_t nlead, int64_t dim_from,
+                               const int32_t* src, const double* sign, int na, int64_t dim_to,
+                               double* Y, hipStream_t s);
+
+// C = alpha * A * op(B) + beta * C, FP64 on MFMA.
+//   A: [M][K] row major, lda;  B: NT -> [N][K] (ldb), NN -> [K][N] (ldb)
+//   C: [M][N] row major, ldc.  batch with element strides sA, sB, sC.
+hipError_t gemm_f64(bool b_is_nk, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
+                    int64_t lda, int64_t sA, const double* B, int64_t ldb, int64_t sB, double beta,
+                    double* C, int64_t ldc, int64_t sC, int batch, hipStream_t s);
+
+// Residual of one packed entry on MFMA:
+//   C[m][n] = V[m][n] + d[m] * (X S)[m][n] + (X F)[m][n]   (V may be null)
+// X [M][K], S and F [K][N] row major (symmetric in use), d [M].
+hipError_t residual_gemm_f64(int64_t M, int64_t N, int64_t K, const double* X, int64_t ldx,
+                             const double* S, const double* F, const double* d, double dshift,
+                             const double* V, int64_t ldv, double* C, int64_t ldc, hipStream_t s);
+// Same for small K = N (<= 64): streaming kernel with S, F staged in LDS.
+hipError_t residual_small_f64(int64_t M, int64_t N, const double* X, const double* S,
+                              const double* F, const double* d, double dshift, const double* V,
+                              double* C, hipStream_t s);
+
+// dst[sum_k idx_k * dstride_k] += c * src[flat], src dims dims[0..nd)
+hipError_t permute_axpy(int nd, const int64_t* dims, const int64_t* dstride, double c,
+                        const double* src, double* dst, hipStream_t s);
+
+// y[j] += sum_i c[i] * G[i][j], i < ni, j < nj   (c on device)
+hipError_t contract_lead(int64_t ni, int64_t nj, const double* c, const double* G, double* y,
+                         hipStream_t s);
+
+// B [Q][nmo][nmo] -> Bt [p-range x q-range][Q] for a block of orbitals
+hipError_t df_pack(const double* B, int naux, int nmo, int p0, int np, int q0, int nq, double* Bt,
+                   hipStream_t s);
+
+// Packed term contraction (sources and couplings); see kernels.hip.
+struct TermDesc {
+  int block;            // output block id
+  int nslot;            // number of external slots of the output block
+  int slot_dim[4];      // dimension of each slot (nc or nv)
+  int swap_k[2], swap_l[2], nswap;
+  int chi[2];           // character of this output entry
+  int strict[2];        // 1 where chi = -1 (strict pair)
+  int64_t nrow, nalpha;
+  int64_t ldo;          // row stride of the output (== nalpha)
+  // coefficient tensor: up to 4 axes; axis a takes its index from
+  // slot c_slot[a] (>= 0) or from active label -1-c_slot[a]
+  int ncax;
+  int c_slot[4];
+  int64_t c_stride[4];
+  // active labels summed: nopact (0..3), each of range na
+  int nopact, na;
+  // G layout: [opact (na^nopact)][nalpha][gcols], ket column gcol
+  int64_t gcols;
+  int gcol;
+  int64_t galpha;       // alpha extent of G (>= nalpha) and offset of column 0
+  int64_t goff;
+  int mode_avg;         // 1: evaluate on the representative only, weight 1
+  double scale;
+};
+hipError_t term_source(const TermDesc& d, const double* C, const double* G, double* out,
+                       hipStream_t s);
+
+// X0[i][k] = Q[i][idx[k]] * scale[k]  (Q is n x ncq, X0 is n x nk)
+hipError_t select_scale_cols(int64_t n, int64_t ncq, const double* Q, const int32_t* idx,
+                             const double* scale, int64_t nk, double* X0, hipStream_t s);
+
+// Jacobi eigensolver of a symmetric n x n matrix A (destroyed; diagonal ->
+// eigenvalues, unsorted); V receives eigenvectors (columns).  ws: device
+// workspace of >= 4*n doubles + 2*n ints. sweeps: max sweeps.
+hipError_t jacobi_eigh(int n, double* A, double* V, double* ws, int max_sweeps, double tol,
+                       hipStream_t s, int* sweeps_done);
+
+// vector kernels
+hipError_t vec_dot(int64_t n, const double* x, const double* y, double* partial, double* out,
+                   hipStream_t s);  // out on device (1 double); partial >= 1024 doubles
+hipError_t vec_axpy(int64_t n, double a, const double* x, double* y, hipStream_t s);  // y += a x
+hipError_t vec_xpay(int64_t n, const double* x, double a, double* y, hipStream_t s);  // y = x + a y
+hipError_t vec_div(int64_t n, const double* x, const double* d, double* y, hipStream_t s);  // y = x/d
+hipError_t vec_scale_copy(int64_t n, double a, const double* x, double* y, hipStream_t s);  // y = a x
+hipError_t vec_fill(int64_t n, double v, double* y, hipStream_t s);
+hipError_t vec_min(int64_t n, const double* x, double* partial, double* out, hipStream_t s);
+
+// small dense symmetric eigenproblem on one thread (n <= 16): A -> values w
+// ascending, vectors R (columns, largest-magnitude entry positive)
+hipError_t small_eigh(int n, const double* A, double* w, double* R, hipStream_t s);
+
+}  // namespace caspt2
