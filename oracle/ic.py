@@ -330,19 +330,46 @@ def _apply_string(space: ActiveSpace, ops_spins, base: np.ndarray, sector):
     return arr, labels, sec
 
 
-def active_gram(space, ci, sector, bra_act, mid_act, ket_act, ket_base=None):
+def _apply_onebody(space: ActiveSpace, C: np.ndarray, spin: int, vec: np.ndarray, sector):
+    """sum_xy C[x, y] a+_{x spin} a_{y spin} applied to vec (same sector)."""
+    Z, sec1 = [], None
+    for y in range(space.na):
+        v, sec1 = space.apply("a", y, spin, vec, sector)
+        Z.append(v)
+    if sec1 is None or min(sec1) < 0:
+        return np.zeros_like(vec)
+    Zc = np.tensordot(C, np.stack(Z, axis=0), axes=([1], [0]))
+    out = np.zeros_like(vec)
+    for x in range(space.na):
+        w, _ = space.apply("c", x, spin, Zc[x], sec1)
+        out += w
+    return out
+
+
+def active_gram(space, ci, sector, bra_act, mid_act, ket_act, ket_base=None, mid_coef=None):
     """G[mid labels..., bra labels..., M, ket labels..., N] =
     <M| (bra string)^+ (mid string) (ket string) |N>.  Labels are returned
-    with the axis order.  ket_base replaces ci on the ket side (sources)."""
+    with the axis order.  ket_base replaces ci on the ket side (sources).
+    With mid_coef, the mid string must be a+_x a_y of one spin and is summed
+    with the coefficients mid_coef[x, y] before the inner product (no mid
+    axes in G)."""
     kb = ci if ket_base is None else ket_base
     U, ul, us = _apply_string(space, bra_act, ci, sector)
-    W, wl, ws = _apply_string(space, list(mid_act) + list(ket_act), kb, sector)
+    if mid_coef is not None:
+        W, wl, ws = _apply_string(space, list(ket_act), kb, sector)
+        if W is not None:
+            (ox, sx), (oy, sy) = mid_act
+            assert ox.kind == "c" and oy.kind == "a" and sx == sy
+            W = _apply_onebody(space, mid_coef, sx, W, ws)
+        nm = 0
+    else:
+        W, wl, ws = _apply_string(space, list(mid_act) + list(ket_act), kb, sector)
+        nm = len(mid_act)
     if U is None or W is None or us != ws:
         return None, None
     nu = len(ul)
     nw = len(wl)
     # mid labels come first in wl (they were applied last), ket labels after
-    nm = len(mid_act)
     G = np.tensordot(U, W, axes=([nu + 1, nu + 2], [nw + 1, nw + 2]))
     # G axes: [ul..., M, wl..., N]; reorder to [mid..., ul..., M, ket..., N]
     ax_ul = list(range(nu))
@@ -546,12 +573,12 @@ class Caspt2Oracle:
         return xall
 
     # -- operator terms ------------------------------------------------------
-    def _gram(self, key, bra_act, mid_act, ket_act, ket_base=None):
+    def _gram(self, key, bra_act, mid_act, ket_act, ket_base=None, mid_coef=None):
         G, labels = active_gram(self.space, self.ci, self.sector, bra_act, mid_act, ket_act,
-                                ket_base=ket_base)
+                                ket_base=ket_base, mid_coef=mid_coef)
         return G, labels
 
-    def _block_pair_terms(self, bb: Block, op_ops, kb: Block | None):
+    def _block_pair_terms(self, bb: Block, op_ops, kb: Block | None, mid_coef=None):
         """Collect, per pairing, the summed active tensor for <bra| op |ket>.
 
         Returns list of (classes, op_labels, G[opact..., alpha_bra, alpha_ket]).
@@ -572,14 +599,14 @@ class Caspt2Oracle:
                 for classes, entries in terms.items():
                     acc = out.get(classes)
                     for (coef, bra_act, mid_act, ket_act) in entries:
-                        G, labels = self._gram(None, bra_act, mid_act, ket_act)
+                        G, labels = self._gram(None, bra_act, mid_act, ket_act, mid_coef=mid_coef)
                         if G is None:
                             continue
                         mid_l, bra_l, ket_l = labels
                         # reorder label axes to block storage order
                         bra_order = [lbl + "_b" for lbl in bb.act]
                         ket_order = [] if kb is None else [lbl + "_k" for lbl in kb.act]
-                        mid_order = [o.label for o in op_ops if o.space == ACT]
+                        mid_order = [] if mid_coef is not None else [o.label for o in op_ops if o.space == ACT]
                         nm, nb_, nk = len(mid_l), len(bra_l), len(ket_l)
                         perm = ([mid_l.index(x) for x in mid_order]
                                 + [nm + bra_l.index(x) for x in bra_order]
@@ -668,11 +695,19 @@ class Caspt2Oracle:
         x_str = "".join(cl[lab + "_k"] for (lab, _) in kb.ext) + "Z"
         return f"{c_str},{g_str},{x_str}->{out}"
 
-    def _plan(self, key, bb, kb, op_ops, coef, clabels):
+    def _plan(self, key, bb, kb, op_ops, coef, clabels, precontract=False):
+        """Einsum plans of <bra| op |ket> per pairing.  With precontract the
+        op is a one-body operator on active orbitals whose coefficients are
+        summed into the ket vectors first; the plan then takes C = 1."""
         if key not in self._plans:
-            terms = self._block_pair_terms(bb, op_ops, kb)
-            self._plans[key] = [(self._spec(bb, kb, op_ops, clabels, classes), G, classes)
-                                for classes, G in terms]
+            if precontract:
+                terms = self._block_pair_terms(bb, op_ops, kb, mid_coef=coef)
+                self._plans[key] = [(self._spec(bb, kb, [], [], classes), G, classes)
+                                    for classes, G in terms]
+            else:
+                terms = self._block_pair_terms(bb, op_ops, kb)
+                self._plans[key] = [(self._spec(bb, kb, op_ops, clabels, classes), G, classes)
+                                    for classes, G in terms]
         return [(s, coef, G, c) for (s, G, c) in self._plans[key]]
 
     def _alpha_slice(self, b: Block, L: int):
@@ -704,9 +739,11 @@ class Caspt2Oracle:
                         out[bb.name] += shiftL * np.einsum(s2, Gr, x, optimize=True)
                 for ci_, (ops, C, clabels) in enumerate(self.fock_components()):
                     key = ("F", ci_, bb.name, kb.name)
-                    for spec, _, G, _ in self._plan(key, bb, kb, ops, C, clabels):
+                    pre = all(o.space == ACT for o in ops)
+                    for spec, _, G, _ in self._plan(key, bb, kb, ops, C, clabels, precontract=pre):
                         Gr = self._restrict(G, bb, kb, L)
-                        out[bb.name] += np.einsum(spec, C, Gr, x, optimize=True)
+                        Cx = np.float64(1.0) if pre else C
+                        out[bb.name] += np.einsum(spec, Cx, Gr, x, optimize=True)
         return out
 
     def sources(self) -> dict:
@@ -772,9 +809,9 @@ class Caspt2Oracle:
         F = np.zeros((n, n))
         fa = self.f[self.sl[ACT], self.sl[ACT]]
         ops = E("x_o", ACT, "y_o", ACT, "so")
-        for spec, _, G, classes in self._plan(("FA", b.name), b, b, ops, fa, ["x_o", "y_o"]):
-            F += self._perm_sign(b, classes, chi) * np.einsum(
-                "xy,xyAB->AB", fa, self._restrict(G, b, b, L))
+        for spec, _, G, classes in self._plan(("FA", b.name), b, b, ops, fa, ["x_o", "y_o"],
+                                              precontract=True):
+            F += self._perm_sign(b, classes, chi) * self._restrict(G, b, b, L)
         return F
 
     def ortho(self, L: int = 0):
