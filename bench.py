@@ -1,0 +1,183 @@
+"""Benchmark: residual evaluations of the (X)MS-CASPT2 amplitude equation on
+one MI355X.
+
+One step = sigma_L = A_L x + V^(L) for every state L over all eight excitation
+blocks (Eq. 10), on device-resident synthetic inputs.  Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--workload full|mid|small]
+
+The roofline object reports the dominant residual kernel (HIP events inside
+the library, on the stream it launches on); the cpu_baseline object times
+the CPU oracle on a bounded sample of the same workload in a child process
+(its set-up overlaps the GPU set-up; its timed part runs after the GPU timed
+region).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import multiprocessing as mp
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# (nc, na, nv, naux, nst, seed, shift) and a short name
+WORKLOADS = {
+    "full": ((30, 8, 400, 1500, 4, 2, 0.2), "XMS-CASPT2 MS-MR 30c/8a(8e)/400v naux 1500, 4 states, shift 0.2"),
+    "mid": ((10, 6, 120, 400, 3, 1, 0.2), "XMS-CASPT2 MS-MR 10c/6a(6e)/120v naux 400, 3 states, shift 0.2"),
+    "small": ((4, 4, 20, 60, 1, 0, 0.0), "CASPT2 4c/4a(4e)/20v naux 60, 1 state, no shift"),
+}
+HBM_PEAK_GBS = 8000.0
+
+
+def _cpu_worker(conn, dims, reading, sample_nv, min_seconds):
+    """Child process: oracle residual on a sample with fewer virtuals."""
+    try:
+        import numpy as np
+        from threadpoolctl import threadpool_info
+        from synth.gen import make_problem
+        from oracle.ic import Caspt2Oracle
+        nc, na, nv, naux, nst, seed, shift = dims
+        p = make_problem(nc, na, sample_nv, naux, nst, seed, reading=reading, shift=shift)
+        o = Caspt2Oracle(p, "MSMR")
+        x = np.random.default_rng(0).standard_normal(o.length)
+        o.residual(0, x)                      # builds the plans (set-up, untimed)
+        conn.send(("ready", o.length))
+        conn.recv()                           # wait until the GPU timed region is over
+        n, t0 = 0, time.perf_counter()
+        while True:
+            for L in range(nst):
+                o.residual(L, x)
+            n += 1
+            if time.perf_counter() - t0 >= min_seconds:
+                break
+        dt = (time.perf_counter() - t0) / n
+        threads = max((i.get("num_threads", 1) for i in threadpool_info()), default=1)
+        conn.send(("done", dt, o.length, threads))
+    except Exception as ex:  # report instead of hanging the parent
+        conn.send(("error", repr(ex)))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="full")
+    ap.add_argument("--reading", default="A")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-nv", type=int, default=24)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--solve", action="store_true", help="also time the amplitude and lambda solves")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only (the method's per-state equations "
+              "shard by state and batch instance; see DESIGN.md); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    dims, wname = WORKLOADS[args.workload]
+    nc, na, nv, naux, nst, seed, shift = dims
+
+    child = None
+    if not args.no_cpu_baseline:
+        ctx = mp.get_context("spawn")
+        parent_conn, child_conn = ctx.Pipe()
+        child = ctx.Process(target=_cpu_worker,
+                            args=(child_conn, dims, args.reading, args.cpu_sample_nv, args.cpu_seconds),
+                            daemon=True)
+        child.start()
+
+    import numpy as np
+    import torch
+    from synth.gen import make_problem
+    from paper_1606_01273_amd import ENTRY_NAMES, Caspt2
+
+    t0 = time.perf_counter()
+    prob = make_problem(nc, na, nv, naux, nst, seed, reading=args.reading, shift=shift)
+    t_gen = time.perf_counter() - t0
+    print(f"[bench] generated inputs in {t_gen:.1f} s", file=sys.stderr, flush=True)
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    g = Caspt2.from_problem(prob)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    print(f"[bench] library set-up {t_setup:.1f} s, vector length {g.length}", file=sys.stderr, flush=True)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(0)
+    x = torch.randn((nst, g.length), dtype=torch.float64, device="cuda", generator=gen)
+    sig = torch.empty_like(x)
+    for _ in range(args.warmup):
+        g.residual_all(x, sig)
+    torch.cuda.synchronize()
+    g.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.residual_all(x, sig)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = {ENTRY_NAMES[k]: g.profile_entry(k) for k in range(len(ENTRY_NAMES))}
+    g.profile(False)
+    print(f"[bench] {args.steps} steps in {elapsed:.3f} s", file=sys.stderr, flush=True)
+
+    # dominant kernel by total time
+    tot = {k: v[0] * v[1] for k, v in prof.items()}
+    dom = max(tot, key=tot.get)
+    avg_ms, launches, bytes_pl = prof[dom]
+    achieved = bytes_pl / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_residual_rows (ccvv +/-)" if dom.startswith("ccvv") else dom,
+                "entry": dom, "avg_ms": round(avg_ms, 4), "launches": launches,
+                "bytes_per_launch": bytes_pl}
+    per_entry = {k: {"avg_ms": round(v[0], 4), "launches": v[1], "GBs": round(v[2] / (v[0] * 1e-3) / 1e9, 1)
+                     if v[0] > 0 else None} for k, v in prof.items()}
+
+    solve = None
+    if args.solve:
+        t0 = time.perf_counter()
+        rc, info = g.solve_amplitudes(tol=1e-10, maxiter=200)
+        H, w, R = g.heff()
+        rc2, linfo = g.solve_lambda(0, tol=1e-10, maxiter=200)
+        torch.cuda.synchronize()
+        solve = {"seconds": round(time.perf_counter() - t0, 3), "status": [rc, rc2],
+                 "amp_iters": [i["iters"] for i in info], "lambda_iters": [i["iters"] for i in linfo],
+                 "e_ms": [float(v) for v in w]}
+
+    cpu = None
+    if child is not None:
+        msg = parent_conn.recv()
+        if msg[0] == "ready":
+            parent_conn.send("go")
+            msg = parent_conn.recv()
+        if msg[0] == "done":
+            dt, slen, threads = msg[1], msg[2], msg[3]
+            # scale the sample's time per evaluation by the vector-length ratio
+            scaled_dt = dt * (g.length / slen)
+            cpu = {"value": 1.0 / scaled_dt, "unit": "evals/s", "cores": int(threads), "kind": "oracle",
+                   "sample": f"CPU oracle residual for all {nst} states with {args.cpu_sample_nv} virtuals "
+                             f"(other sizes as the workload), {dt:.3f} s per evaluation, scaled by vector "
+                             f"length {slen} -> {g.length}"}
+        else:
+            cpu = {"value": None, "unit": "evals/s", "cores": None, "kind": "oracle", "sample": str(msg)}
+        child.join(timeout=30)
+
+    value = args.steps / elapsed
+    out = {"metric": "residual evals/s", "value": round(value, 3), "unit": "evals/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic (seeded generator: DF factors, orbital energies, CAS-CI)",
+           "config": {"workload": wname, "reading": args.reading, "scheme": "MS-MR", "vector_length": g.length,
+                      "setup_s": round(t_setup, 2)},
+           "roofline": roofline, "cpu_baseline": cpu, "per_entry": per_entry}
+    if solve is not None:
+        out["solve"] = solve
+    print(json.dumps(out))
+    g.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -182,6 +182,16 @@ CASPT2_API int caspt2_solve_lambda(caspt2_handle* h, int32_t target, double tol,
                         caspt2_info* info);
 CASPT2_API int caspt2_get_lambda(caspt2_handle* h, int32_t L, double* lambda);
 
+/* Measurement support: enable (1) or disable (0) HIP-event timing of every
+ * residual kernel launch (clears what was recorded), and read, per packed
+ * layout entry k (0..12; the '+' entry also covers its '-' partner when both
+ * run in one launch), the average launch duration in ms, the number of
+ * launches and the algorithmic bytes per launch (read x, read the source when
+ * it is added, write sigma; 8 bytes per double). */
+CASPT2_API int caspt2_profile(caspt2_handle* h, int32_t enable);
+CASPT2_API int caspt2_profile_entry(caspt2_handle* h, int32_t k, double* avg_ms, int64_t* launches,
+                                    double* bytes_per_launch);
+
 /* Human-readable text for a status code; last HIP error text. */
 CASPT2_API const char* caspt2_strerror(int code);
 CASPT2_API const char* caspt2_last_error(void);

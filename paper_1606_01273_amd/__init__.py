@@ -84,6 +84,15 @@ class Caspt2:
             out.append((ENTRY_NAMES[k], o.value, r.value, a.value))
         return out
 
+    def profile(self, enable=True):
+        _check(lib().caspt2_profile(self._h, 1 if enable else 0), "caspt2_profile")
+
+    def profile_entry(self, k):
+        ms, n, b = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+        _check(lib().caspt2_profile_entry(self._h, k, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b)),
+               "caspt2_profile_entry")
+        return ms.value, n.value, b.value
+
     def residual(self, L, x, sigma, with_source=True):
         _check(lib().caspt2_residual(self._h, L, 1 if with_source else 0, _ptr(x), _ptr(sigma)),
                "caspt2_residual")

@@ -61,6 +61,8 @@ SIGNATURES = {
                                            ctypes.POINTER(Info)]),
     "caspt2_get_lambda": (ctypes.c_int, [_P, ctypes.c_int32, _P]),
     "caspt2_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "caspt2_profile": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "caspt2_profile_entry": (ctypes.c_int, [_P, ctypes.c_int32, _D, ctypes.POINTER(ctypes.c_int64), _D]),
     "caspt2_debug_gemm": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
                                          _P, _P, _P]),
     "caspt2_debug_entry": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _D]),

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
+#include <cstdlib>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -96,6 +98,12 @@ struct Entry {
   double emin_kept = INFINITY, emax_dropped = -1.0;
 };
 
+struct ProfEventRec {
+  int entry;
+  double bytes;
+  hipEvent_t a, b;
+};
+
 struct Gather {
   IBuf src;
   DBuf sign;
@@ -132,6 +140,10 @@ struct caspt2_handle {
   bool have_T = false, have_heff = false, have_lam = false;
   std::vector<double> heff, ems, R;
   DBuf jws;
+  bool prof_on = false;
+  bool verbose = false;
+  double t_start = 0.0;
+  std::vector<ProfEventRec> prof_events;
 };
 
 namespace {
@@ -345,6 +357,18 @@ TermDesc base_desc(const H& h, const Block& b, const Entry& e) {
 }
 
 void host_sync(H& h) { HIPCHECK(hipStreamSynchronize(h.s)); }
+
+double wall() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// progress of the set-up on stderr when CASPT2_VERBOSE is set
+void progress(H& h, const std::string& what) {
+  if (!h.verbose) return;
+  host_sync(h);
+  std::fprintf(stderr, "[caspt2] %8.2f s  %s\n", wall() - h.t_start, what.c_str());
+  std::fflush(stderr);
+}
 
 double dev_scalar(H& h, const double* p) {
   double v;
@@ -583,6 +607,7 @@ void setup_blocks(H& h) {
     }
     h.vcache.clear();
     host_sync(h);
+    progress(h, "metrics and orthonormal bases of block " + b.name);
   }
   // offsets
   for (auto& set : h.sets) {
@@ -727,6 +752,7 @@ void setup_sources(H& h) {
       host_sync(h);
     }
     h.vcache.clear();
+    progress(h, "sources of block " + b.name);
   }
   host_sync(h);
 }
@@ -736,18 +762,54 @@ void setup_sources(H& h) {
 // ---------------------------------------------------------------------------
 int set_of(const H& h, int L) { return h.d.scheme == CASPT2_SSSR ? L : 0; }
 
+// Profiling: HIP events around every entry's residual launch (entry index
+// of the packed layout) with the algorithmic bytes of the launch (read x,
+// read the source if added, write sigma), accumulated until read.
+void prof_begin(H& h, hipEvent_t* a) {
+  if (!h.prof_on) return;
+  HIPCHECK(hipEventCreate(a));
+  HIPCHECK(hipEventRecord(*a, h.s));
+}
+
+void prof_end(H& h, int entry, double bytes, hipEvent_t a) {
+  if (!h.prof_on) return;
+  hipEvent_t b;
+  HIPCHECK(hipEventCreate(&b));
+  HIPCHECK(hipEventRecord(b, h.s));
+  h.prof_events.push_back({entry, bytes, a, b});
+}
+
 void residual(H& h, int L, const double* x, double* sig, bool with_source) {
   const int set = set_of(h, L);
   const double dshift = h.d.shift - h.e0[L];
-  for (auto& e : h.sets[set]) {
+  auto& es = h.sets[set];
+  for (size_t k = 0; k < es.size(); ++k) {
+    auto& e = es[k];
     if (e.nrow == 0 || e.nalpha == 0) continue;
     const double* V = with_source ? h.src[set][L].p + e.offset : nullptr;
-    if (e.nalpha <= 64)
+    hipEvent_t ev = nullptr;
+    // '+' and '-' entries of a block with nalpha <= 4 share one streaming launch
+    if (e.nalpha <= 4 && k + 1 < es.size() && es[k + 1].block == e.block && es[k + 1].nalpha == e.nalpha) {
+      auto& e2 = es[k + 1];
+      prof_begin(h, &ev);
+      HIPCHECK(residual_rows_f64((int)e.nalpha, e.nrow, e2.nrow, x + e.offset, e.S.p, e.F.p,
+                                 e2.nrow ? e2.S.p : nullptr, e2.nrow ? e2.F.p : nullptr, e.eps.p,
+                                 e2.nrow ? e2.eps.p : nullptr, dshift, V, sig + e.offset, h.s));
+      prof_end(h, (int)k, (with_source ? 3.0 : 2.0) * 8.0 * (double)(e.nrow + e2.nrow) * e.nalpha, ev);
+      ++k;
+      continue;
+    }
+    prof_begin(h, &ev);
+    if (e.nalpha <= 4)
+      HIPCHECK(residual_rows_f64((int)e.nalpha, e.nrow, 0, x + e.offset, e.S.p, e.F.p, nullptr,
+                                 nullptr, e.eps.p, nullptr, dshift, V, sig + e.offset, h.s));
+    else if (e.nalpha <= 64)
       HIPCHECK(residual_small_f64(e.nrow, e.nalpha, x + e.offset, e.S.p, e.F.p, e.eps.p, dshift, V,
                                   sig + e.offset, h.s));
     else
       HIPCHECK(residual_gemm_f64(e.nrow, e.nalpha, e.nalpha, x + e.offset, e.nalpha, e.S.p, e.F.p,
                                  e.eps.p, dshift, V, e.nalpha, sig + e.offset, e.nalpha, h.s));
+    prof_end(h, (int)k, (with_source ? 3.0 : 2.0) * 8.0 * (double)e.nrow * e.nalpha, ev);
   }
 }
 
@@ -920,6 +982,8 @@ int caspt2_create(const caspt2_dims* dims, const caspt2_inputs* in, int on_devic
   ABI_GUARD({
     h.d = *dims;
     h.s = (hipStream_t)stream;
+    h.verbose = std::getenv("CASPT2_VERBOSE") != nullptr;
+    h.t_start = wall();
     h.nc = dims->nclosed;
     h.na = dims->nact;
     h.nv = dims->nvirt;
@@ -1034,6 +1098,7 @@ int caspt2_create(const caspt2_dims* dims, const caspt2_inputs* in, int on_devic
       host_sync(h);
     }
     h.vcache.clear();
+    progress(h, "XMS rotation");
     // ---- blocks, orthonormal bases, sources ------------------------------
     setup_blocks(h);
     setup_sources(h);
@@ -1045,8 +1110,49 @@ int caspt2_create(const caspt2_dims* dims, const caspt2_inputs* in, int on_devic
 }
 
 int caspt2_destroy(caspt2_handle* h) {
+  if (h)
+    for (auto& r : h->prof_events) {
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
   delete h;
   return CASPT2_OK;
+}
+
+int caspt2_profile(caspt2_handle* h, int32_t enable) {
+  if (!h) return CASPT2_E_ARG;
+  ABI_GUARD({
+    HIPCHECK(hipStreamSynchronize(h->s));
+    for (auto& r : h->prof_events) {
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+    h->prof_events.clear();
+    h->prof_on = enable != 0;
+    return CASPT2_OK;
+  })
+}
+
+int caspt2_profile_entry(caspt2_handle* h, int32_t k, double* avg_ms, int64_t* launches,
+                         double* bytes_per_launch) {
+  if (!h || k < 0 || k >= (int32_t)h->sets[0].size()) return CASPT2_E_ARG;
+  ABI_GUARD({
+    HIPCHECK(hipStreamSynchronize(h->s));
+    double tot = 0.0, bytes = 0.0;
+    int64_t n = 0;
+    for (auto& r : h->prof_events) {
+      if (r.entry != k) continue;
+      float ms = 0.f;
+      HIPCHECK(hipEventElapsedTime(&ms, r.a, r.b));
+      tot += ms;
+      bytes += r.bytes;
+      ++n;
+    }
+    if (avg_ms) *avg_ms = n ? tot / n : 0.0;
+    if (launches) *launches = n;
+    if (bytes_per_launch) *bytes_per_launch = n ? bytes / n : 0.0;
+    return CASPT2_OK;
+  })
 }
 
 int64_t caspt2_vector_length(const caspt2_handle* h) { return h ? h->length : -1; }

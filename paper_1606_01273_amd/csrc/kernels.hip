@@ -215,6 +215,83 @@ hipError_t residual_small_f64(int64_t M, int64_t N, const double* X, const doubl
 }
 
 // ---------------------------------------------------------------------------
+// ccvv streaming residual: rows of NST doubles, two consecutive entries (the
+// '+' and '-' characters) in one launch.  Row m of entry c:
+//   C[m][n] = V[m][n] + (d[m] + dshift) sum_k X[m][k] S_c[k][n] + sum_k X[m][k] F_c[k][n]
+// S_c, F_c are NST x NST (kept in registers); one thread per row.
+// ---------------------------------------------------------------------------
+template <int NST>
+__global__ __launch_bounds__(256) void k_residual_rows(int64_t M0, int64_t M1,
+                                                       const double* __restrict__ X,
+                                                       const double* __restrict__ S0,
+                                                       const double* __restrict__ F0,
+                                                       const double* __restrict__ S1,
+                                                       const double* __restrict__ F1,
+                                                       const double* __restrict__ d0,
+                                                       const double* __restrict__ d1, double dshift,
+                                                       const double* __restrict__ V,
+                                                       double* __restrict__ C) {
+  double s0[NST * NST], f0[NST * NST], s1[NST * NST], f1[NST * NST];
+#pragma unroll
+  for (int i = 0; i < NST * NST; ++i) {
+    s0[i] = S0[i];
+    f0[i] = F0[i];
+    s1[i] = S1 ? S1[i] : 0.0;
+    f1[i] = F1 ? F1[i] : 0.0;
+  }
+  const int64_t total = M0 + M1;
+  for (int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; m < total;
+       m += (int64_t)gridDim.x * blockDim.x) {
+    const bool second = m >= M0;
+    const double r = (second ? d1[m - M0] : d0[m]) + dshift;
+    double x[NST], out[NST];
+#pragma unroll
+    for (int k = 0; k < NST; ++k) x[k] = X[m * NST + k];
+#pragma unroll
+    for (int n = 0; n < NST; ++n) {
+      double as = 0.0, af = 0.0;
+#pragma unroll
+      for (int k = 0; k < NST; ++k) {
+        as += x[k] * (second ? s1[k * NST + n] : s0[k * NST + n]);
+        af += x[k] * (second ? f1[k * NST + n] : f0[k * NST + n]);
+      }
+      out[n] = r * as + af;
+    }
+    if (V) {
+#pragma unroll
+      for (int n = 0; n < NST; ++n) out[n] += V[m * NST + n];
+    }
+#pragma unroll
+    for (int n = 0; n < NST; ++n) C[m * NST + n] = out[n];
+  }
+}
+
+hipError_t residual_rows_f64(int nst, int64_t M0, int64_t M1, const double* X, const double* S0,
+                             const double* F0, const double* S1, const double* F1, const double* d0,
+                             const double* d1, double dshift, const double* V, double* C,
+                             hipStream_t s) {
+  const int64_t total = M0 + M1;
+  if (total <= 0) return hipSuccess;
+  unsigned grid = cdiv(total, 256);
+  if (grid > 8192) grid = 8192;
+  switch (nst) {
+#define CASPT2_ROWS(NS)                                                                        \
+  case NS:                                                                                     \
+    hipLaunchKernelGGL(k_residual_rows<NS>, dim3(grid), dim3(256), 0, s, M0, M1, X, S0, F0, S1, \
+                       F1, d0, d1, dshift, V, C);                                              \
+    break;
+    CASPT2_ROWS(1)
+    CASPT2_ROWS(2)
+    CASPT2_ROWS(3)
+    CASPT2_ROWS(4)
+#undef CASPT2_ROWS
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // permuted accumulate and leading contraction
 // ---------------------------------------------------------------------------
 struct PermArgs {

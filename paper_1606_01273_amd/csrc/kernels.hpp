@@ -30,6 +30,14 @@ hipError_t residual_small_f64(int64_t M, int64_t N, const double* X, const doubl
                               const double* F, const double* d, double dshift, const double* V,
                               double* C, hipStream_t s);
 
+// Streaming residual of two consecutive packed entries with nalpha = nst
+// (<= 4), e.g. ccvv '+' and '-': rows [0, M0) use (S0, F0, d0), rows
+// [M0, M0+M1) use (S1, F1, d1).  X, V, C are [M0+M1][nst].
+hipError_t residual_rows_f64(int nst, int64_t M0, int64_t M1, const double* X, const double* S0,
+                             const double* F0, const double* S1, const double* F1, const double* d0,
+                             const double* d1, double dshift, const double* V, double* C,
+                             hipStream_t s);
+
 // dst[sum_k idx_k * dstride_k] += c * src[flat], src dims dims[0..nd)
 hipError_t permute_axpy(int nd, const int64_t* dims, const int64_t* dstride, double c,
                         const double* src, double* dst, hipStream_t s);
