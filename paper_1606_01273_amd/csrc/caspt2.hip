@@ -98,6 +98,14 @@ struct Entry {
   double emin_kept = INFINITY, emax_dropped = -1.0;
 };
 
+struct CoupleTerm {
+  bool up;
+  int bra, ket;          // block ids
+  CoupleDesc d;          // ket_src, fx/fy, nsum, sum_dim, ny, f_stride filled
+  int64_t f_off;         // offset of the Fock block origin in f
+  DBuf G;                // up: [ny * nalpha_b][nalpha_k]; down: [nalpha_b][ny * nalpha_k]
+};
+
 struct ProfEventRec {
   int entry;
   double bytes;
@@ -140,6 +148,8 @@ struct caspt2_handle {
   bool have_T = false, have_heff = false, have_lam = false;
   std::vector<double> heff, ems, R;
   DBuf jws;
+  std::vector<std::vector<struct CoupleTerm>> couple;  // per function set
+  DBuf cscratch;                                       // W / Y of the couplings
   bool prof_on = false;
   bool verbose = false;
   double t_start = 0.0;
@@ -758,6 +768,243 @@ void setup_sources(H& h) {
 }
 
 // ---------------------------------------------------------------------------
+// Fock couplings between blocks (closed-active, active-virtual and
+// closed-virtual blocks of f): one term per Wick pairing
+// ---------------------------------------------------------------------------
+PackInfo pack_info(const H& h, int set, int block, const double* base, const std::vector<int64_t>* offs,
+                   int64_t rowlen) {
+  const Block& b = blocks()[block];
+  PackInfo p{};
+  p.nslot = (int)b.ext.size();
+  for (int k = 0; k < p.nslot; ++k) p.slot_dim[k] = b.ext[k].second == CLO ? h.nc : h.nv;
+  p.nswap = (int)b.swaps.size();
+  for (int s2 = 0; s2 < p.nswap; ++s2) {
+    p.swap_k[s2] = b.swaps[s2].first;
+    p.swap_l[s2] = b.swaps[s2].second;
+  }
+  int ent = 0;
+  for (size_t k = 0; k < h.sets[set].size(); ++k) {
+    const auto& e = h.sets[set][k];
+    if (e.block != block) continue;
+    for (int s2 = 0; s2 < p.nswap; ++s2) p.chi[ent][s2] = e.chi[s2];
+    p.offset[ent] = offs ? (*offs)[ent] : e.offset;
+    ++ent;
+  }
+  p.nent = ent;
+  p.rowlen = rowlen;
+  (void)base;
+  return p;
+}
+
+void setup_couplings(H& h) {
+  const bool ss = h.d.scheme == CASPT2_SSSR;
+  const int nst = h.nst;
+  const int nsets = ss ? nst : 1;
+  h.couple.clear();
+  h.couple.resize(nsets);
+  auto off = [&](char c) { return c == CLO ? 0 : c == ACT ? h.nc : h.nc + h.na; };
+  auto dim = [&](char c) { return c == CLO ? h.nc : c == ACT ? h.na : h.nv; };
+  // Fock blocks between orbital classes that are present
+  std::vector<std::pair<char, char>> comps;
+  for (auto pr : std::vector<std::pair<char, char>>{{ACT, CLO}, {CLO, ACT}, {VIR, ACT}, {ACT, VIR},
+                                                    {VIR, CLO}, {CLO, VIR}}) {
+    bool nz = false;
+    for (int x = 0; x < dim(pr.first) && !nz; ++x)
+      for (int y = 0; y < dim(pr.second); ++y)
+        if (h.h_fock[(off(pr.first) + x) * h.nmo + off(pr.second) + y] != 0.0) {
+          nz = true;
+          break;
+        }
+    if (nz) comps.push_back(pr);
+  }
+  if (comps.empty()) return;
+  const auto& BL = blocks();
+  int64_t scratch = 0;
+  for (int bb = 0; bb < NBLOCK; ++bb)
+    for (int kb = 0; kb < NBLOCK; ++kb) {
+      if (bb == kb) continue;
+      const Block& B1 = BL[bb];
+      const Block& B2 = BL[kb];
+      const int nty_b = (int)B1.types.size(), nty_k = (int)B2.types.size();
+      const int64_t ntup_b = ipow(h.na, (int)B1.act.size()), ntup_k = ipow(h.na, (int)B2.act.size());
+      const int64_t nall_b = (int64_t)nst * nty_b * ntup_b, nall_k = (int64_t)nst * nty_k * ntup_k;
+      const int64_t nset_b = (ss ? 1 : nst) * nty_b * ntup_b, nset_k = (ss ? 1 : nst) * nty_k * ntup_k;
+      if (nset_b == 0 || nset_k == 0) continue;
+      for (auto comp : comps) {
+        const OpString op = E("x_o", comp.first, "y_o", comp.second, "so");
+        const int ny = (comp.first == ACT || comp.second == ACT) ? h.na : 1;
+        std::map<std::string, PairAcc> acc;
+        for (int tb = 0; tb < nty_b; ++tb)
+          for (int tk = 0; tk < nty_k; ++tk) {
+            auto pairings = matrix_element(suffixed(B1.types[tb], "_b"), op, suffixed(B2.types[tk], "_k"));
+            for (auto& P : pairings) {
+              const std::string key = pair_key(P);
+              auto it = acc.find(key);
+              if (it == acc.end()) {
+                PairAcc pa;
+                pa.P.pairs = P.pairs;
+                pa.G.alloc((int64_t)ny * nall_b * nall_k);
+                pa.G.zero(h.s);
+                it = acc.emplace(key, std::move(pa)).first;
+              }
+              for (const auto& w : P.entries)
+                accumulate_gram(h, w, tb, nty_b, ntup_b, tk, nty_k, ntup_k, false, nullptr,
+                                it->second.G, 0);
+            }
+          }
+        h.vcache.clear();
+        for (auto& kv : acc) {
+          const auto& pairs = kv.second.P.pairs;
+          auto partner = [&](const std::string& lab) {
+            for (const auto& pr : pairs) {
+              if (pr.first == lab) return pr.second;
+              if (pr.second == lab) return pr.first;
+            }
+            return std::string();
+          };
+          auto bra_slot = [&](const std::string& lab) {
+            for (size_t k = 0; k < B1.ext.size(); ++k)
+              if (B1.ext[k].first + "_b" == lab) return (int)k;
+            return -1;
+          };
+          auto ket_slot = [&](const std::string& lab) {
+            for (size_t k = 0; k < B2.ext.size(); ++k)
+              if (B2.ext[k].first + "_k" == lab) return (int)k;
+            return -1;
+          };
+          // direction: the operator's external labels pair with the bra (up)
+          // or with the ket (down)
+          bool up = true;
+          for (const char* lab : {"x_o", "y_o"}) {
+            const char sp = std::string(lab) == "x_o" ? comp.first : comp.second;
+            if (sp == ACT) continue;
+            if (ket_slot(partner(lab)) >= 0) up = false;
+          }
+          for (int set = 0; set < nsets; ++set) {
+            CoupleTerm t;
+            t.up = up;
+            t.bra = bb;
+            t.ket = kb;
+            t.d = CoupleDesc{};
+            t.d.ny = ny;
+            t.d.f_stride = h.nmo;
+            t.f_off = (int64_t)off(comp.first) * h.nmo + off(comp.second);
+            int nsum = 0;
+            std::map<std::string, int> sum_of;   // ket label -> summed index
+            if (up) {
+              for (size_t l = 0; l < B2.ext.size(); ++l)
+                t.d.ket_src[l] = bra_slot(partner(B2.ext[l].first + "_k"));
+            } else {
+              for (size_t l = 0; l < B2.ext.size(); ++l) {
+                const std::string kl = B2.ext[l].first + "_k";
+                const int bs = bra_slot(partner(kl));
+                if (bs >= 0) {
+                  t.d.ket_src[l] = bs;
+                } else {
+                  sum_of[kl] = nsum;
+                  t.d.sum_dim[nsum] = B2.ext[l].second == CLO ? h.nc : h.nv;
+                  t.d.ket_src[l] = -1 - nsum;
+                  ++nsum;
+                }
+              }
+            }
+            t.d.nsum = nsum;
+            for (int which = 0; which < 2; ++which) {
+              const std::string lab = which == 0 ? "x_o" : "y_o";
+              const char sp = which == 0 ? comp.first : comp.second;
+              int src;
+              if (sp == ACT) src = -10;
+              else if (up) src = bra_slot(partner(lab));
+              else src = -1 - sum_of.at(partner(lab));
+              (which == 0 ? t.d.fx_src : t.d.fy_src) = src;
+            }
+            // active tensor of this function set, [y][alpha_b][alpha_k]
+            DBuf Gs((int64_t)ny * nset_b * nset_k);
+            if (ss) {
+              for (int y = 0; y < ny; ++y)
+                HIPCHECK(hipMemcpy2DAsync(Gs.p + (int64_t)y * nset_b * nset_k, (size_t)nset_k * sizeof(double),
+                                          kv.second.G.p + (int64_t)y * nall_b * nall_k +
+                                              (int64_t)set * nset_b * nall_k + (int64_t)set * nset_k,
+                                          (size_t)nall_k * sizeof(double), (size_t)nset_k * sizeof(double),
+                                          (size_t)nset_b, hipMemcpyDeviceToDevice, h.s));
+            } else {
+              HIPCHECK(hipMemcpyAsync(Gs.p, kv.second.G.p, Gs.n * sizeof(double), hipMemcpyDeviceToDevice, h.s));
+            }
+            if (up) {
+              t.G = std::move(Gs);                     // [(y, alpha_b)][alpha_k]
+              int64_t rows_k = 0;
+              for (auto& e : h.sets[set])
+                if (e.block == kb) rows_k += e.nrow;
+              scratch = std::max(scratch, rows_k * ny * nset_b);
+            } else {
+              t.G.alloc((int64_t)nset_b * ny * nset_k);   // [alpha_b][(y, alpha_k)]
+              t.G.zero(h.s);
+              const int64_t dims3[3] = {ny, nset_b, nset_k};
+              const int64_t str3[3] = {nset_k, (int64_t)ny * nset_k, 1};
+              HIPCHECK(permute_axpy(3, dims3, str3, 1.0, Gs.p, t.G.p, h.s));
+              int64_t rows_b = 0;
+              for (auto& e : h.sets[set])
+                if (e.block == bb) rows_b = std::max(rows_b, e.nrow);
+              scratch = std::max(scratch, rows_b * ny * nset_k);
+            }
+            h.couple[set].push_back(std::move(t));
+          }
+        }
+        host_sync(h);
+      }
+      progress(h, "couplings " + B1.name + " <- " + B2.name);
+    }
+  h.cscratch.alloc(scratch);
+}
+
+void apply_couplings(H& h, int set, const double* x, double* sig) {
+  for (auto& t : h.couple[set]) {
+    const double* f = h.fock.p + t.f_off;
+    if (t.up) {
+      // stage 1: W_e'[rows][(y, alpha_b)] = x_e'[rows][alpha_k] G^T, per ket entry
+      std::vector<int64_t> offs;
+      int64_t off = 0, nab = 0;
+      for (auto& e : h.sets[set])
+        if (e.block == t.bra) nab = e.nalpha;
+      const int64_t width = (int64_t)t.d.ny * nab;
+      for (auto& e : h.sets[set]) {
+        if (e.block != t.ket) continue;
+        offs.push_back(off);
+        HIPCHECK(gemm_f64(true, e.nrow, width, e.nalpha, 1.0, x + e.offset, e.nalpha, 0, t.G.p,
+                          e.nalpha, 0, 0.0, h.cscratch.p + off, width, 0, 1, h.s));
+        off += e.nrow * width;
+      }
+      CoupleDesc d = t.d;
+      d.in = pack_info(h, set, t.ket, nullptr, &offs, width);
+      d.ncol = nab;
+      for (auto& e : h.sets[set]) {
+        if (e.block != t.bra || e.nrow == 0) continue;
+        d.out = base_desc(h, blocks()[t.bra], e);
+        d.out.scale = 1.0;
+        HIPCHECK(couple_up(d, f, h.cscratch.p, sig + e.offset, h.s));
+      }
+    } else {
+      int64_t nak = 0;
+      for (auto& e : h.sets[set])
+        if (e.block == t.ket) nak = e.nalpha;
+      CoupleDesc d = t.d;
+      d.in = pack_info(h, set, t.ket, nullptr, nullptr, nak);
+      d.ncol = nak;
+      const int64_t width = (int64_t)t.d.ny * nak;
+      for (auto& e : h.sets[set]) {
+        if (e.block != t.bra || e.nrow == 0) continue;
+        d.out = base_desc(h, blocks()[t.bra], e);
+        d.out.scale = 1.0;
+        // stage 1: Y[rows_b][(y, alpha_k)] = sum_z f x_all ; stage 2: sigma += Y G^T
+        HIPCHECK(couple_down(d, f, x, h.cscratch.p, h.s));
+        HIPCHECK(gemm_f64(true, e.nrow, e.nalpha, width, 1.0, h.cscratch.p, width, 0, t.G.p, width, 0,
+                          1.0, sig + e.offset, e.nalpha, 0, 1, h.s));
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // residual and solver
 // ---------------------------------------------------------------------------
 int set_of(const H& h, int L) { return h.d.scheme == CASPT2_SSSR ? L : 0; }
@@ -811,6 +1058,7 @@ void residual(H& h, int L, const double* x, double* sig, bool with_source) {
                                  e.eps.p, dshift, V, e.nalpha, sig + e.offset, e.nalpha, h.s));
     prof_end(h, (int)k, (with_source ? 3.0 : 2.0) * 8.0 * (double)e.nrow * e.nalpha, ev);
   }
+  if (!h.couple.empty() && !h.couple[set].empty()) apply_couplings(h, set, x, sig);
 }
 
 void to_orth(H& h, int set, const double* v, double* o) {
@@ -1023,8 +1271,7 @@ int caspt2_create(const caspt2_dims* dims, const caspt2_inputs* in, int on_devic
           throw DevError(CASPT2_E_NOTIMPL, "non-diagonal closed or virtual Fock block");
         if (cls(i) != cls(j) && v != 0.0) offblock = true;
       }
-    if (offblock)
-      throw DevError(CASPT2_E_NOTIMPL, "Fock couplings between orbital classes not built yet");
+    (void)offblock;
     h.h_eps.resize(h.nmo);
     for (int i = 0; i < h.nmo; ++i) h.h_eps[i] = h.h_fock[i * h.nmo + i];
     // device copies
@@ -1102,6 +1349,7 @@ int caspt2_create(const caspt2_dims* dims, const caspt2_inputs* in, int on_devic
     // ---- blocks, orthonormal bases, sources ------------------------------
     setup_blocks(h);
     setup_sources(h);
+    setup_couplings(h);
     h.eri.clear();
     host_sync(h);
     *out = hp.release();

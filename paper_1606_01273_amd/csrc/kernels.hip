@@ -476,6 +476,174 @@ hipError_t term_source(const TermDesc& d, const double* C, const double* G, doub
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// coupling kernels
+// ---------------------------------------------------------------------------
+__device__ inline int64_t pair_rank(int hi, int lo, bool strict) {
+  return strict ? (int64_t)hi * (hi - 1) / 2 + lo : (int64_t)hi * (hi + 1) / 2 + lo;
+}
+
+// value of the all-orderings amplitude x[e][col] from the packed rows:
+// x[e] = sum_chi chi(pi_e) t_chi[orbit(e)] / sqrt(|orbit|)
+__device__ double gather_all(const PackInfo& p, const double* __restrict__ base, const int e[4],
+                             int64_t col) {
+  int c[4] = {e[0], e[1], e[2], e[3]};
+  int swapped[2] = {0, 0}, equal[2] = {0, 0}, ndist = 0;
+  for (int s = 0; s < p.nswap; ++s) {
+    const int k = p.swap_k[s], l = p.swap_l[s];
+    if (c[k] < c[l]) {
+      const int t = c[k];
+      c[k] = c[l];
+      c[l] = t;
+      swapped[s] = 1;
+    }
+    if (c[k] == c[l]) equal[s] = 1;
+    else ++ndist;
+  }
+  const double w = 1.0 / sqrt((double)(1 << ndist));
+  double acc = 0.0;
+  for (int ent = 0; ent < p.nent; ++ent) {
+    bool ok = true;
+    double sg = 1.0;
+    for (int s = 0; s < p.nswap; ++s) {
+      if (equal[s] && p.chi[ent][s] < 0) ok = false;
+      if (swapped[s]) sg *= p.chi[ent][s];
+    }
+    if (!ok) continue;
+    int64_t row = 0;
+    for (int k = 0; k < p.nslot; ++k) {
+      int sw = -1;
+      for (int s = 0; s < p.nswap; ++s)
+        if (p.swap_k[s] == k) sw = s;
+      const int64_t d = p.slot_dim[k];
+      if (sw >= 0) {
+        const bool strict = p.chi[ent][sw] < 0;
+        const int64_t cnt = strict ? d * (d - 1) / 2 : d * (d + 1) / 2;
+        row = row * cnt + pair_rank(c[k], c[k + 1], strict);
+        ++k;
+      } else {
+        row = row * d + c[k];
+      }
+    }
+    acc += sg * base[p.offset[ent] + row * p.rowlen + col];
+  }
+  return w * acc;
+}
+
+__device__ inline int src_value(int src, const int e[4], const int z[2], int y) {
+  return src >= 0 ? e[src] : (src == -10 ? y : z[-1 - src]);
+}
+
+__global__ void k_couple_up(CoupleDesc d, const double* __restrict__ f, const double* __restrict__ W,
+                            double* __restrict__ out) {
+  const TermDesc& o = d.out;
+  const int64_t total = o.nrow * d.ncol;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t row = g / d.ncol;
+    const int64_t a = g % d.ncol;
+    int e0[4] = {0, 0, 0, 0};
+    decode_orbit(o, row, e0);
+    int ndistinct = 0;
+    for (int s = 0; s < o.nswap; ++s)
+      if (e0[o.swap_k[s]] != e0[o.swap_l[s]]) ++ndistinct;
+    const double w = 1.0 / sqrt((double)(1 << ndistinct));
+    const int z[2] = {0, 0};
+    double acc = 0.0;
+    for (int bits = 0; bits < (1 << o.nswap); ++bits) {
+      int e[4] = {e0[0], e0[1], e0[2], e0[3]};
+      double sg = 1.0;
+      bool dup = false;
+      for (int s = 0; s < o.nswap; ++s)
+        if ((bits >> s) & 1) {
+          if (e0[o.swap_k[s]] == e0[o.swap_l[s]]) dup = true;
+          const int t = e[o.swap_k[s]];
+          e[o.swap_k[s]] = e[o.swap_l[s]];
+          e[o.swap_l[s]] = t;
+          sg *= o.chi[s];
+        }
+      if (dup) continue;
+      int ek[4] = {0, 0, 0, 0};
+      for (int l = 0; l < d.in.nslot; ++l) ek[l] = src_value(d.ket_src[l], e, z, 0);
+      double val = 0.0;
+      for (int y = 0; y < d.ny; ++y) {
+        const int fx = src_value(d.fx_src, e, z, y), fy = src_value(d.fy_src, e, z, y);
+        val += f[(int64_t)fx * d.f_stride + fy] * gather_all(d.in, W, ek, (int64_t)y * d.ncol + a);
+      }
+      acc += sg * val;
+    }
+    out[row * o.ldo + a] += o.scale * w * acc;
+  }
+}
+
+__global__ void k_couple_down(CoupleDesc d, const double* __restrict__ f, const double* __restrict__ X,
+                              double* __restrict__ Y) {
+  const TermDesc& o = d.out;
+  const int64_t width = (int64_t)d.ny * d.ncol;
+  const int64_t total = o.nrow * width;
+  const int n0 = d.nsum > 0 ? d.sum_dim[0] : 1;
+  const int n1 = d.nsum > 1 ? d.sum_dim[1] : 1;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t row = g / width;
+    const int64_t rem = g % width;
+    const int y = (int)(rem / d.ncol);
+    const int64_t a = rem % d.ncol;
+    int e0[4] = {0, 0, 0, 0};
+    decode_orbit(o, row, e0);
+    int ndistinct = 0;
+    for (int s = 0; s < o.nswap; ++s)
+      if (e0[o.swap_k[s]] != e0[o.swap_l[s]]) ++ndistinct;
+    const double w = 1.0 / sqrt((double)(1 << ndistinct));
+    double acc = 0.0;
+    for (int bits = 0; bits < (1 << o.nswap); ++bits) {
+      int e[4] = {e0[0], e0[1], e0[2], e0[3]};
+      double sg = 1.0;
+      bool dup = false;
+      for (int s = 0; s < o.nswap; ++s)
+        if ((bits >> s) & 1) {
+          if (e0[o.swap_k[s]] == e0[o.swap_l[s]]) dup = true;
+          const int t = e[o.swap_k[s]];
+          e[o.swap_k[s]] = e[o.swap_l[s]];
+          e[o.swap_l[s]] = t;
+          sg *= o.chi[s];
+        }
+      if (dup) continue;
+      double val = 0.0;
+      for (int z0 = 0; z0 < n0; ++z0)
+        for (int z1 = 0; z1 < n1; ++z1) {
+          const int z[2] = {z0, z1};
+          int ek[4] = {0, 0, 0, 0};
+          for (int l = 0; l < d.in.nslot; ++l) ek[l] = src_value(d.ket_src[l], e, z, y);
+          const int fx = src_value(d.fx_src, e, z, y), fy = src_value(d.fy_src, e, z, y);
+          val += f[(int64_t)fx * d.f_stride + fy] * gather_all(d.in, X, ek, a);
+        }
+      acc += sg * val;
+    }
+    Y[row * width + rem] = o.scale * w * acc;
+  }
+}
+
+hipError_t couple_up(const CoupleDesc& d, const double* f, const double* W, double* out,
+                     hipStream_t s) {
+  const int64_t total = d.out.nrow * d.ncol;
+  if (total == 0) return hipSuccess;
+  unsigned grid = cdiv(total, 256);
+  if (grid > 65536) grid = 65536;
+  hipLaunchKernelGGL(k_couple_up, dim3(grid), dim3(256), 0, s, d, f, W, out);
+  return hipGetLastError();
+}
+
+hipError_t couple_down(const CoupleDesc& d, const double* f, const double* X, double* Y,
+                       hipStream_t s) {
+  const int64_t total = d.out.nrow * d.ny * d.ncol;
+  if (total == 0) return hipSuccess;
+  unsigned grid = cdiv(total, 256);
+  if (grid > 65536) grid = 65536;
+  hipLaunchKernelGGL(k_couple_down, dim3(grid), dim3(256), 0, s, d, f, X, Y);
+  return hipGetLastError();
+}
+
 __global__ void k_select_scale_cols(int64_t n, int64_t ncq, const double* __restrict__ Q,
                                     const int32_t* __restrict__ idx, const double* __restrict__ sc,
                                     int64_t nk, double* __restrict__ X0) {

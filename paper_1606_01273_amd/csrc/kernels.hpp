@@ -78,6 +78,40 @@ struct TermDesc {
 hipError_t term_source(const TermDesc& d, const double* C, const double* G, double* out,
                        hipStream_t s);
 
+// Packed representation of one block (for gathering all-orderings values):
+// entries (characters) with their offsets relative to a base pointer.
+struct PackInfo {
+  int nslot;
+  int slot_dim[4];
+  int nswap;
+  int swap_k[2], swap_l[2];
+  int nent;               // character entries present (1 or 2)
+  int chi[2][2];          // chi[entry][swap]
+  int64_t offset[2];      // entry offsets (doubles) from the base pointer
+  int64_t rowlen;         // doubles per packed row
+};
+
+// Coupling kernels (Fock couplings between blocks).  Index sources: a value
+// >= 0 is a bra slot, -1 - s is summed external label s, -10 is the
+// operator's active label y.
+struct CoupleDesc {
+  TermDesc out;           // bra entry: decode, images, characters (scale used)
+  PackInfo in;            // ket block (W for up, x for down)
+  int ket_src[4];         // source of each ket slot
+  int fx_src, fy_src;     // sources of the two Fock indices
+  int64_t f_stride;       // row stride of f (nmo); f points at the block origin
+  int nsum;               // summed external labels (down): 0..2
+  int sum_dim[2];
+  int ny;                 // 1 or na (operator active label)
+  int64_t ncol;           // alpha columns of the bra (up) or of the ket (down)
+};
+// up, stage 2: out[row][a] += scale * sum_img w chi sum_y f(.) W_all(e_k, y*ncol + a)
+hipError_t couple_up(const CoupleDesc& d, const double* f, const double* W, double* out,
+                     hipStream_t s);
+// down, stage 1: Y[row][y*ncol + a'] = sum_img w chi sum_z f(.) X_all(e_k, a')
+hipError_t couple_down(const CoupleDesc& d, const double* f, const double* X, double* Y,
+                       hipStream_t s);
+
 // X0[i][k] = Q[i][idx[k]] * scale[k]  (Q is n x ncq, X0 is n x nk)
 hipError_t select_scale_cols(int64_t n, int64_t ncq, const double* Q, const int32_t* idx,
                              const double* scale, int64_t nk, double* X0, hipStream_t s);

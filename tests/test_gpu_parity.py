@@ -79,6 +79,13 @@ CASES = [
     ((5, 4, 30, 70, 2), 8, "A", "MSMR", True, 0.2),
     ((3, 4, 10, 40, 2), 7, "A", "SSSR", True, 0.2),
     ((3, 3, 9, 30, 3), 7, "A", "MSMR", False, 0.1),
+    # Fock couplings between orbital classes (closed-active, active-virtual,
+    # closed-virtual blocks of f)
+    ((2, 3, 3, 16, 3), 7, "B", "MSMR", True, 0.15),
+    ((4, 4, 20, 60, 1), 7, "B", "MSMR", True, 0.0),
+    ((5, 4, 30, 70, 2), 8, "B", "MSMR", True, 0.2),
+    ((3, 4, 10, 40, 2), 7, "B", "SSSR", True, 0.2),
+    ((3, 3, 9, 30, 3), 7, "B", "MSMR", False, 0.1),
 ]
 
 
