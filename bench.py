@@ -34,6 +34,26 @@ WORKLOADS = {
 HBM_PEAK_GBS = 8000.0
 
 
+def _pmc_traffic(entry, workload, reading):
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 PMC summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of
+    known size), or None when no summary matches this kernel source."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    src = os.path.join(ROOT, "paper_1606_01273_amd", "csrc", "kernels.hip")
+    with open(src, "rb") as fh:
+        digest = hashlib.sha256(fh.read()).hexdigest()
+    key = f"{workload}/{reading}/{entry}"
+    r = rec.get(key)
+    if not r or r.get("kernels_sha256") != digest:
+        return None
+    return r.get("bytes_per_launch")
+
+
 def _cpu_worker(conn, dims, reading, sample_nv, min_seconds):
     """Child process: oracle residual on a sample with fewer virtuals."""
     try:
@@ -73,6 +93,8 @@ def main():
     ap.add_argument("--cpu-sample-nv", type=int, default=24)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--solve", action="store_true", help="also time the amplitude and lambda solves")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the timed region, run a plain 1 GiB device copy (calibrates PMC byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (the method's per-state equations "
@@ -120,21 +142,31 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     prof = {ENTRY_NAMES[k]: g.profile_entry(k) for k in range(len(ENTRY_NAMES))}
+    coupl = g.profile_entry(len(ENTRY_NAMES))
     g.profile(False)
     print(f"[bench] {args.steps} steps in {elapsed:.3f} s", file=sys.stderr, flush=True)
+
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # dominant kernel by total time
     tot = {k: v[0] * v[1] for k, v in prof.items()}
     dom = max(tot, key=tot.get)
     avg_ms, launches, bytes_pl = prof[dom]
     achieved = bytes_pl / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    traffic = _pmc_traffic(dom, args.workload, args.reading)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "k_residual_rows (ccvv +/-)" if dom.startswith("ccvv") else dom,
                 "entry": dom, "avg_ms": round(avg_ms, 4), "launches": launches,
                 "bytes_per_launch": bytes_pl}
     per_entry = {k: {"avg_ms": round(v[0], 4), "launches": v[1], "GBs": round(v[2] / (v[0] * 1e-3) / 1e9, 1)
                      if v[0] > 0 else None} for k, v in prof.items()}
+    per_entry["couplings"] = {"avg_ms": round(coupl[0], 4), "launches": coupl[1]}
 
     solve = None
     if args.solve:

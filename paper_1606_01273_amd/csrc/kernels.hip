@@ -202,11 +202,87 @@ __global__ __launch_bounds__(256) void k_residual_small(int64_t M, int N, const 
   }
 }
 
+// Streaming residual on MFMA for 16 < K = N <= 64: S and F (zero padded to
+// K16 = ceil16(K)) live in LDS for the whole launch; each wave stages 16 rows
+// of X in LDS with coalesced loads and accumulates X S and X F with
+// v_mfma_f64_16x16x4f64; epilogue (d[m] + dshift) XS + XF + V.
+template <int K16>
+__global__ __launch_bounds__(256) void k_residual_mfma(int64_t M, int K, const double* __restrict__ X,
+                                                       const double* __restrict__ S,
+                                                       const double* __restrict__ F,
+                                                       const double* __restrict__ d, double dshift,
+                                                       const double* __restrict__ V,
+                                                       double* __restrict__ C) {
+  __shared__ double Ss[K16][K16 + 1];
+  __shared__ double Fs[K16][K16 + 1];
+  __shared__ double Xs[4][16][K16 + 1];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int i = tid; i < K16 * K16; i += 256) {
+    const int r = i / K16, c = i % K16;
+    const bool in = r < K && c < K;
+    Ss[r][c] = in ? S[r * K + c] : 0.0;
+    Fs[r][c] = in ? F[r * K + c] : 0.0;
+  }
+  __syncthreads();
+  const int64_t ntiles = (M + 15) / 16;
+  for (int64_t tile = (int64_t)blockIdx.x * 4 + w; tile < ntiles; tile += (int64_t)gridDim.x * 4) {
+    const int64_t m0 = tile * 16;
+    // stage 16 rows (contiguous 16*K doubles) of X
+    const int64_t base = m0 * K;
+    const int64_t limit = M * (int64_t)K;
+    for (int i = lane; i < 16 * K16; i += 64) {
+      const int r = i / K16, c = i % K16;
+      const int64_t gi = base + (int64_t)r * K + c;
+      Xs[w][r][c] = (c < K && gi < limit) ? X[gi] : 0.0;
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int ct = 0; ct < K16 / 16; ++ct) {
+      d4 as = {0, 0, 0, 0}, af = {0, 0, 0, 0};
+#pragma unroll
+      for (int k0 = 0; k0 < K16; k0 += 4) {
+        const double a = Xs[w][lane & 15][k0 + (lane >> 4)];
+        const double bs = Ss[k0 + (lane >> 4)][ct * 16 + (lane & 15)];
+        const double bf = Fs[k0 + (lane >> 4)][ct * 16 + (lane & 15)];
+        as = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bs, as, 0, 0, 0);
+        af = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bf, af, 0, 0, 0);
+      }
+      const int col = ct * 16 + (lane & 15);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = m0 + (lane >> 4) + 4 * v;
+        if (row < M && col < K) {
+          double val = (d[row] + dshift) * as[v] + af[v];
+          if (V) val += V[row * K + col];
+          C[row * K + col] = val;
+        }
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
 hipError_t residual_small_f64(int64_t M, int64_t N, const double* X, const double* S,
                               const double* F, const double* d, double dshift, const double* V,
                               double* C, hipStream_t s) {
   if (M <= 0 || N <= 0) return hipSuccess;
   if (N > 64) return hipErrorInvalidValue;
+  if (N > 16) {
+    const int64_t ntiles = (M + 15) / 16;
+    unsigned grid = cdiv(ntiles, 4);
+    if (grid > 16384) grid = 16384;
+    if (N <= 32)
+      hipLaunchKernelGGL(k_residual_mfma<32>, dim3(grid), dim3(256), 0, s, M, (int)N, X, S, F, d,
+                         dshift, V, C);
+    else if (N <= 48)
+      hipLaunchKernelGGL(k_residual_mfma<48>, dim3(grid), dim3(256), 0, s, M, (int)N, X, S, F, d,
+                         dshift, V, C);
+    else
+      hipLaunchKernelGGL(k_residual_mfma<64>, dim3(grid), dim3(256), 0, s, M, (int)N, X, S, F, d,
+                         dshift, V, C);
+    return hipGetLastError();
+  }
   unsigned grid = cdiv(M * N, 256);
   if (grid > 65536) grid = 65536;
   hipLaunchKernelGGL(k_residual_small, dim3(grid), dim3(256), 0, s, M, (int)N, X, S, F, d, dshift,
@@ -534,113 +610,242 @@ __device__ inline int src_value(int src, const int e[4], const int z[2], int y) 
   return src >= 0 ? e[src] : (src == -10 ? y : z[-1 - src]);
 }
 
-__global__ void k_couple_up(CoupleDesc d, const double* __restrict__ f, const double* __restrict__ W,
-                            double* __restrict__ out) {
-  const TermDesc& o = d.out;
-  const int64_t total = o.nrow * d.ncol;
-  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
-       g += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t row = g / d.ncol;
-    const int64_t a = g % d.ncol;
-    int e0[4] = {0, 0, 0, 0};
-    decode_orbit(o, row, e0);
-    int ndistinct = 0;
-    for (int s = 0; s < o.nswap; ++s)
-      if (e0[o.swap_k[s]] != e0[o.swap_l[s]]) ++ndistinct;
-    const double w = 1.0 / sqrt((double)(1 << ndistinct));
-    const int z[2] = {0, 0};
-    double acc = 0.0;
-    for (int bits = 0; bits < (1 << o.nswap); ++bits) {
-      int e[4] = {e0[0], e0[1], e0[2], e0[3]};
-      double sg = 1.0;
-      bool dup = false;
-      for (int s = 0; s < o.nswap; ++s)
-        if ((bits >> s) & 1) {
-          if (e0[o.swap_k[s]] == e0[o.swap_l[s]]) dup = true;
-          const int t = e[o.swap_k[s]];
-          e[o.swap_k[s]] = e[o.swap_l[s]];
-          e[o.swap_l[s]] = t;
-          sg *= o.chi[s];
-        }
-      if (dup) continue;
-      int ek[4] = {0, 0, 0, 0};
-      for (int l = 0; l < d.in.nslot; ++l) ek[l] = src_value(d.ket_src[l], e, z, 0);
-      double val = 0.0;
-      for (int y = 0; y < d.ny; ++y) {
-        const int fx = src_value(d.fx_src, e, z, y), fy = src_value(d.fy_src, e, z, y);
-        val += f[(int64_t)fx * d.f_stride + fy] * gather_all(d.in, W, ek, (int64_t)y * d.ncol + a);
-      }
-      acc += sg * val;
-    }
-    out[row * o.ldo + a] += o.scale * w * acc;
+__device__ inline void decode_all(const AllDesc& a, int64_t row, int e[4]) {
+  for (int k = a.nslot - 1; k >= 0; --k) {
+    e[k] = (int)(row % a.slot_dim[k]);
+    row /= a.slot_dim[k];
   }
 }
 
-__global__ void k_couple_down(CoupleDesc d, const double* __restrict__ f, const double* __restrict__ X,
-                              double* __restrict__ Y) {
-  const TermDesc& o = d.out;
-  const int64_t width = (int64_t)d.ny * d.ncol;
-  const int64_t total = o.nrow * width;
-  const int n0 = d.nsum > 0 ? d.sum_dim[0] : 1;
-  const int n1 = d.nsum > 1 ? d.sum_dim[1] : 1;
+__device__ inline int64_t encode_all(const AllDesc& a, const int e[4]) {
+  int64_t row = 0;
+  for (int k = 0; k < a.nslot; ++k) row = row * a.slot_dim[k] + e[k];
+  return row;
+}
+
+__global__ void k_unpack_all(PackInfo p, AllDesc a, int64_t nrows, const double* __restrict__ packed,
+                             double* __restrict__ out) {
+  const int64_t total = nrows * p.rowlen;
   for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
        g += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t row = g / width;
-    const int64_t rem = g % width;
-    const int y = (int)(rem / d.ncol);
-    const int64_t a = rem % d.ncol;
-    int e0[4] = {0, 0, 0, 0};
-    decode_orbit(o, row, e0);
-    int ndistinct = 0;
-    for (int s = 0; s < o.nswap; ++s)
-      if (e0[o.swap_k[s]] != e0[o.swap_l[s]]) ++ndistinct;
-    const double w = 1.0 / sqrt((double)(1 << ndistinct));
-    double acc = 0.0;
-    for (int bits = 0; bits < (1 << o.nswap); ++bits) {
-      int e[4] = {e0[0], e0[1], e0[2], e0[3]};
-      double sg = 1.0;
-      bool dup = false;
-      for (int s = 0; s < o.nswap; ++s)
-        if ((bits >> s) & 1) {
-          if (e0[o.swap_k[s]] == e0[o.swap_l[s]]) dup = true;
-          const int t = e[o.swap_k[s]];
-          e[o.swap_k[s]] = e[o.swap_l[s]];
-          e[o.swap_l[s]] = t;
-          sg *= o.chi[s];
-        }
-      if (dup) continue;
-      double val = 0.0;
-      for (int z0 = 0; z0 < n0; ++z0)
-        for (int z1 = 0; z1 < n1; ++z1) {
-          const int z[2] = {z0, z1};
-          int ek[4] = {0, 0, 0, 0};
-          for (int l = 0; l < d.in.nslot; ++l) ek[l] = src_value(d.ket_src[l], e, z, y);
-          const int fx = src_value(d.fx_src, e, z, y), fy = src_value(d.fy_src, e, z, y);
-          val += f[(int64_t)fx * d.f_stride + fy] * gather_all(d.in, X, ek, a);
-        }
-      acc += sg * val;
-    }
-    Y[row * width + rem] = o.scale * w * acc;
+    const int64_t row = g / p.rowlen, c = g % p.rowlen;
+    int e[4] = {0, 0, 0, 0};
+    decode_all(a, row, e);
+    out[g] = gather_all(p, packed, e, c);
   }
 }
 
-hipError_t couple_up(const CoupleDesc& d, const double* f, const double* W, double* out,
-                     hipStream_t s) {
-  const int64_t total = d.out.nrow * d.ncol;
+hipError_t unpack_all(const PackInfo& p, const AllDesc& a, const double* packed, double* out_all,
+                      hipStream_t s) {
+  int64_t nrows = 1;
+  for (int k = 0; k < a.nslot; ++k) nrows *= a.slot_dim[k];
+  const int64_t total = nrows * p.rowlen;
   if (total == 0) return hipSuccess;
   unsigned grid = cdiv(total, 256);
   if (grid > 65536) grid = 65536;
-  hipLaunchKernelGGL(k_couple_up, dim3(grid), dim3(256), 0, s, d, f, W, out);
+  hipLaunchKernelGGL(k_unpack_all, dim3(grid), dim3(256), 0, s, p, a, nrows, packed, out_all);
   return hipGetLastError();
 }
 
-hipError_t couple_down(const CoupleDesc& d, const double* f, const double* X, double* Y,
-                       hipStream_t s) {
-  const int64_t total = d.out.nrow * d.ny * d.ncol;
+__global__ void k_pack_acc(TermDesc d, AllDesc a, const double* __restrict__ in,
+                           double* __restrict__ out) {
+  const int64_t total = d.nrow * d.nalpha;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t row = g / d.nalpha, c = g % d.nalpha;
+    int e0[4] = {0, 0, 0, 0};
+    decode_orbit(d, row, e0);
+    int ndistinct = 0;
+    for (int s = 0; s < d.nswap; ++s)
+      if (e0[d.swap_k[s]] != e0[d.swap_l[s]]) ++ndistinct;
+    const double w = 1.0 / sqrt((double)(1 << ndistinct));
+    double acc = 0.0;
+    for (int bits = 0; bits < (1 << d.nswap); ++bits) {
+      int e[4] = {e0[0], e0[1], e0[2], e0[3]};
+      double sg = 1.0;
+      bool dup = false;
+      for (int s = 0; s < d.nswap; ++s)
+        if ((bits >> s) & 1) {
+          if (e0[d.swap_k[s]] == e0[d.swap_l[s]]) dup = true;
+          const int t = e[d.swap_k[s]];
+          e[d.swap_k[s]] = e[d.swap_l[s]];
+          e[d.swap_l[s]] = t;
+          sg *= d.chi[s];
+        }
+      if (dup) continue;
+      acc += sg * in[encode_all(a, e) * d.nalpha + c];
+    }
+    out[row * d.ldo + c] += w * acc;
+  }
+}
+
+hipError_t pack_acc(const TermDesc& d, const AllDesc& a, const double* in_all, double* packed,
+                    hipStream_t s) {
+  const int64_t total = d.nrow * d.nalpha;
   if (total == 0) return hipSuccess;
   unsigned grid = cdiv(total, 256);
   if (grid > 65536) grid = 65536;
-  hipLaunchKernelGGL(k_couple_down, dim3(grid), dim3(256), 0, s, d, f, X, Y);
+  hipLaunchKernelGGL(k_pack_acc, dim3(grid), dim3(256), 0, s, d, a, in_all, packed);
+  return hipGetLastError();
+}
+
+// expand: one thread per (ket row, alpha column); the bra slots that are not
+// fed from the ket (the Fock index slots) are looped inside the thread, so
+// every W row is read once.
+__global__ void k_couple_expand(CoupleDesc d, const double* __restrict__ f,
+                                const double* __restrict__ W, double* __restrict__ out) {
+  int64_t nrows_k = 1;
+  for (int k = 0; k < d.ket.nslot; ++k) nrows_k *= d.ket.slot_dim[k];
+  const int64_t total = nrows_k * d.ncol;
+  const int64_t wlen = (int64_t)d.ny * d.ncol;
+  // bra slots not fed from the ket
+  int free_slot[2] = {-1, -1}, nfree = 0;
+  for (int k = 0; k < d.bra.nslot; ++k) {
+    bool fed = false;
+    for (int l = 0; l < d.ket.nslot; ++l)
+      if (d.ket_src[l] == k) fed = true;
+    if (!fed && nfree < 2) free_slot[nfree++] = k;
+  }
+  const int n0 = nfree > 0 ? d.bra.slot_dim[free_slot[0]] : 1;
+  const int n1 = nfree > 1 ? d.bra.slot_dim[free_slot[1]] : 1;
+  const int z[2] = {0, 0};
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t rk = g / d.ncol, a = g % d.ncol;
+    int ek[4] = {0, 0, 0, 0}, e[4] = {0, 0, 0, 0};
+    decode_all(d.ket, rk, ek);
+    for (int l = 0; l < d.ket.nslot; ++l) e[d.ket_src[l]] = ek[l];
+    double wreg[8];
+    const double* w = W + rk * wlen + a;
+    for (int y = 0; y < d.ny; ++y) wreg[y] = w[(int64_t)y * d.ncol];
+    for (int z0 = 0; z0 < n0; ++z0) {
+      if (nfree > 0) e[free_slot[0]] = z0;
+      for (int z1 = 0; z1 < n1; ++z1) {
+        if (nfree > 1) e[free_slot[1]] = z1;
+        double acc = 0.0;
+        for (int y = 0; y < d.ny; ++y)
+          acc += f[(int64_t)src_value(d.fx_src, e, z, y) * d.f_stride + src_value(d.fy_src, e, z, y)] *
+                 wreg[y];
+        out[encode_all(d.bra, e) * d.ncol + a] += acc;
+      }
+    }
+  }
+}
+
+// expand, output-parallel form (for kets with few rows): one thread per
+// (bra row, alpha column); W rows are small and stay in cache.
+__global__ void k_couple_expand_out(CoupleDesc d, const double* __restrict__ f,
+                                    const double* __restrict__ W, double* __restrict__ out) {
+  int64_t nrows = 1;
+  for (int k = 0; k < d.bra.nslot; ++k) nrows *= d.bra.slot_dim[k];
+  const int64_t total = nrows * d.ncol;
+  const int64_t wlen = (int64_t)d.ny * d.ncol;
+  const int z[2] = {0, 0};
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t row = g / d.ncol, a = g % d.ncol;
+    int e[4] = {0, 0, 0, 0}, ek[4] = {0, 0, 0, 0};
+    decode_all(d.bra, row, e);
+    for (int l = 0; l < d.ket.nslot; ++l) ek[l] = e[d.ket_src[l]];
+    const double* w = W + encode_all(d.ket, ek) * wlen + a;
+    double acc = 0.0;
+    for (int y = 0; y < d.ny; ++y)
+      acc += f[(int64_t)src_value(d.fx_src, e, z, y) * d.f_stride + src_value(d.fy_src, e, z, y)] *
+             w[(int64_t)y * d.ncol];
+    out[g] += acc;
+  }
+}
+
+hipError_t couple_expand(const CoupleDesc& d, const double* f, const double* W, double* out_all,
+                         hipStream_t s) {
+  if (d.ny > 8) return hipErrorInvalidValue;
+  int64_t nrows_k = 1, nrows_b = 1;
+  for (int k = 0; k < d.ket.nslot; ++k) nrows_k *= d.ket.slot_dim[k];
+  for (int k = 0; k < d.bra.nslot; ++k) nrows_b *= d.bra.slot_dim[k];
+  if (nrows_b * d.ncol == 0) return hipSuccess;
+  if (nrows_k * d.ncol >= (int64_t)1 << 20) {
+    unsigned grid = cdiv(nrows_k * d.ncol, 256);
+    if (grid > 65536) grid = 65536;
+    hipLaunchKernelGGL(k_couple_expand, dim3(grid), dim3(256), 0, s, d, f, W, out_all);
+  } else {
+    unsigned grid = cdiv(nrows_b * d.ncol, 256);
+    if (grid > 65536) grid = 65536;
+    hipLaunchKernelGGL(k_couple_expand_out, dim3(grid), dim3(256), 0, s, d, f, W, out_all);
+  }
+  return hipGetLastError();
+}
+
+// reduce: a workgroup handles R bra rows; thread = (row, alpha column, z part);
+// partial sums over the summed external labels are combined through LDS.
+__global__ __launch_bounds__(256) void k_couple_reduce(CoupleDesc d, int P, int CT,
+                                                       const double* __restrict__ f,
+                                                       const double* __restrict__ X,
+                                                       double* __restrict__ Y) {
+  __shared__ double part[256 * 8];
+  int64_t nrows = 1;
+  for (int k = 0; k < d.bra.nslot; ++k) nrows *= d.bra.slot_dim[k];
+  const int per_row = CT * P;
+  const int R = 256 / per_row;
+  const int n0 = d.nsum > 0 ? d.sum_dim[0] : 1;
+  const int n1 = d.nsum > 1 ? d.sum_dim[1] : 1;
+  const int nz = n0 * n1;
+  const int t = threadIdx.x;
+  // lanes: column fastest, then row, then z part (coalesced row reads)
+  const int zp = t / (R * CT);
+  const int rr = t % (R * CT);
+  const int r = rr / CT;
+  const int64_t a = (int64_t)blockIdx.y * CT + rr % CT;
+  const bool acol = a < d.ncol;
+  const int64_t width = (int64_t)d.ny * d.ncol;
+  for (int64_t row0 = (int64_t)blockIdx.x * R; row0 < nrows; row0 += (int64_t)gridDim.x * R) {
+    const int64_t row = row0 + r;
+    const bool live = zp < P && row < nrows && acol;
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (live) {
+      int e[4] = {0, 0, 0, 0};
+      decode_all(d.bra, row, e);
+      for (int zz = zp; zz < nz; zz += P) {
+        const int zv[2] = {zz / n1, zz % n1};
+        int ek[4] = {0, 0, 0, 0};
+        for (int l = 0; l < d.ket.nslot; ++l) ek[l] = src_value(d.ket_src[l], e, zv, 0);
+        const double xv = X[encode_all(d.ket, ek) * d.ncol + a];
+        for (int y = 0; y < d.ny; ++y)
+          acc[y] += f[(int64_t)src_value(d.fx_src, e, zv, y) * d.f_stride + src_value(d.fy_src, e, zv, y)] * xv;
+      }
+    }
+    for (int y = 0; y < 8; ++y) part[y * 256 + t] = acc[y];
+    __syncthreads();
+    if (live && zp == 0) {
+      for (int y = 0; y < d.ny; ++y) {
+        double sum = 0.0;
+        for (int q = 0; q < P; ++q) sum += part[y * 256 + t + q * R * CT];
+        Y[row * width + (int64_t)y * d.ncol + a] = sum;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t couple_reduce(const CoupleDesc& d, const double* f, const double* X, double* Y,
+                         hipStream_t s) {
+  if (d.ny > 8) return hipErrorInvalidValue;
+  int64_t nrows = 1;
+  for (int k = 0; k < d.bra.nslot; ++k) nrows *= d.bra.slot_dim[k];
+  if (nrows * d.ncol == 0) return hipSuccess;
+  const int n0 = d.nsum > 0 ? d.sum_dim[0] : 1;
+  const int n1 = d.nsum > 1 ? d.sum_dim[1] : 1;
+  const int nz = n0 * n1;
+  const int CT = (int)(d.ncol < 256 ? d.ncol : 256);
+  // rows per block: fill a wave with (row, column) pairs first
+  int Rw = 1;
+  while (Rw * 2 * CT <= 64) Rw *= 2;
+  int P = 1;
+  while (P * 2 <= nz && P * 2 * Rw * CT <= 256) P *= 2;
+  const int R = 256 / (CT * P);
+  unsigned gx = cdiv(nrows, R);
+  if (gx > 65536) gx = 65536;
+  const unsigned gy = cdiv(d.ncol, CT);
+  hipLaunchKernelGGL(k_couple_reduce, dim3(gx, gy), dim3(256), 0, s, d, P, CT, f, X, Y);
   return hipGetLastError();
 }
 
@@ -766,23 +971,140 @@ __global__ void k_jac_norms(int n, const double* __restrict__ A, double* __restr
   }
 }
 
+// Whole cyclic-Jacobi solve in one workgroup (n <= 512): the same
+// round-robin rotations as the multi-launch path, with barriers instead of
+// launches; stops when the off-diagonal norm falls below tol * |A|_F, stops
+// decreasing, or after max_sweeps.
+__global__ __launch_bounds__(1024) void k_jacobi_small(int n, double* __restrict__ A,
+                                                       double* __restrict__ V, double tol,
+                                                       int max_sweeps, int* __restrict__ sweeps) {
+  __shared__ double cs[512];
+  __shared__ int pq[512];
+  __shared__ double red[2][1024];
+  __shared__ int stop;
+  const int t = threadIdx.x, nt = blockDim.x;
+  const int m = n + (n & 1);
+  const int h = m / 2;
+  for (int64_t g = t; g < (int64_t)n * n; g += nt) V[g] = (g / n == g % n) ? 1.0 : 0.0;
+  double prev_off = INFINITY;
+  int sw = 0;
+  __syncthreads();
+  for (; sw < max_sweeps; ++sw) {
+    double off = 0.0, tot = 0.0;
+    for (int64_t g = t; g < (int64_t)n * n; g += nt) {
+      const double v = A[g];
+      tot += v * v;
+      if (g / n != g % n) off += v * v;
+    }
+    red[0][t] = off;
+    red[1][t] = tot;
+    __syncthreads();
+    for (int w = nt / 2; w > 0; w >>= 1) {
+      if (t < w) {
+        red[0][t] += red[0][t + w];
+        red[1][t] += red[1][t + w];
+      }
+      __syncthreads();
+    }
+    if (t == 0) {
+      const double o = red[0][0], tt = red[1][0];
+      // converged, or no longer decreasing (round-off floor)
+      stop = (o <= tol * tol * tt || tt == 0.0 || m < 2 || (sw > 2 && !(o < prev_off))) ? 1 : 0;
+    }
+    prev_off = red[0][0];
+    __syncthreads();
+    if (stop) break;
+    for (int step = 0; step < m - 1; ++step) {
+      for (int k = t; k < h; k += nt) {
+        int p = rr_player(k, step, m), q = rr_player(m - 1 - k, step, m);
+        if (p > q) {
+          const int tmp = p;
+          p = q;
+          q = tmp;
+        }
+        double c = 1.0, s = 0.0;
+        if (q < n) {
+          const double apq = A[(int64_t)p * n + q];
+          if (apq != 0.0) {
+            const double app = A[(int64_t)p * n + p], aqq = A[(int64_t)q * n + q];
+            const double tau = (aqq - app) / (2.0 * apq);
+            const double tt2 = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + tt2 * tt2);
+            s = tt2 * c;
+          }
+        }
+        cs[2 * k] = c;
+        cs[2 * k + 1] = s;
+        pq[2 * k] = p;
+        pq[2 * k + 1] = q;
+      }
+      __syncthreads();
+      const int64_t work = (int64_t)h * h + (int64_t)n * h;
+      for (int64_t g = t; g < work; g += nt) {
+        if (g < (int64_t)h * h) {
+          const int a = (int)(g / h), b = (int)(g % h);
+          const int pa = pq[2 * a], qa = pq[2 * a + 1], pb = pq[2 * b], qb = pq[2 * b + 1];
+          const double ca = cs[2 * a], sa = cs[2 * a + 1], cb = cs[2 * b], sb = cs[2 * b + 1];
+          const bool ipa = pa < n, iqa = qa < n, ipb = pb < n, iqb = qb < n;
+          const double m00 = (ipa && ipb) ? A[(int64_t)pa * n + pb] : 0.0;
+          const double m01 = (ipa && iqb) ? A[(int64_t)pa * n + qb] : 0.0;
+          const double m10 = (iqa && ipb) ? A[(int64_t)qa * n + pb] : 0.0;
+          const double m11 = (iqa && iqb) ? A[(int64_t)qa * n + qb] : 0.0;
+          const double r00 = ca * m00 - sa * m10, r01 = ca * m01 - sa * m11;
+          const double r10 = sa * m00 + ca * m10, r11 = sa * m01 + ca * m11;
+          if (ipa && ipb) A[(int64_t)pa * n + pb] = cb * r00 - sb * r01;
+          if (ipa && iqb) A[(int64_t)pa * n + qb] = sb * r00 + cb * r01;
+          if (iqa && ipb) A[(int64_t)qa * n + pb] = cb * r10 - sb * r11;
+          if (iqa && iqb) A[(int64_t)qa * n + qb] = sb * r10 + cb * r11;
+        } else {
+          const int64_t gg = g - (int64_t)h * h;
+          const int i = (int)(gg / h), a = (int)(gg % h);
+          const int pa = pq[2 * a], qa = pq[2 * a + 1];
+          if (qa < n) {
+            const double ca = cs[2 * a], sa = cs[2 * a + 1];
+            const double vp = V[(int64_t)i * n + pa], vq = V[(int64_t)i * n + qa];
+            V[(int64_t)i * n + pa] = ca * vp - sa * vq;
+            V[(int64_t)i * n + qa] = sa * vp + ca * vq;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (t == 0 && sweeps) *sweeps = sw;
+}
+
 hipError_t jacobi_eigh(int n, double* A, double* V, double* ws, int max_sweeps, double tol,
                        hipStream_t s, int* sweeps_done) {
   if (n <= 0) return hipSuccess;
+  // the attainable off-diagonal norm grows with n (round-off of the rotations)
+  tol = fmax(tol, 4e-16 * (double)n);
+  if (n <= 512) {
+    int* dsw = reinterpret_cast<int*>(ws + 2 * n + 8);
+    hipLaunchKernelGGL(k_jacobi_small, dim3(1), dim3(1024), 0, s, n, A, V, tol, max_sweeps, dsw);
+    if (sweeps_done) {
+      hipError_t e = hipMemcpyAsync(sweeps_done, dsw, sizeof(int), hipMemcpyDeviceToHost, s);
+      if (e != hipSuccess) return e;
+      e = hipStreamSynchronize(s);
+      if (e != hipSuccess) return e;
+    }
+    return hipGetLastError();
+  }
   const int m = n + (n & 1);
   double* cs = ws;
   double* norms = ws + 2 * m;
   int* pq = reinterpret_cast<int*>(ws + 2 * m + 4);
   hipLaunchKernelGGL(k_eye, dim3(cdiv((int64_t)n * n, 256)), dim3(256), 0, s, n, V);
   int sw = 0;
-  double hn[2];
+  double hn[2], prev = INFINITY;
   for (; sw < max_sweeps; ++sw) {
     hipLaunchKernelGGL(k_jac_norms, dim3(1), dim3(256), 0, s, n, A, norms);
     hipError_t e = hipMemcpyAsync(hn, norms, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
     if (e != hipSuccess) return e;
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return e;
-    if (hn[0] <= tol * tol * hn[1] || hn[1] == 0.0 || m < 2) break;
+    if (hn[0] <= tol * tol * hn[1] || hn[1] == 0.0 || m < 2 || (sw > 2 && !(hn[0] < prev))) break;
+    prev = hn[0];
     for (int step = 0; step < m - 1; ++step) {
       hipLaunchKernelGGL(k_jac_params, dim3(cdiv(m / 2, 128)), dim3(128), 0, s, n, m, step, A, cs,
                          pq);

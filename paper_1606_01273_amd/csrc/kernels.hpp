@@ -91,26 +91,42 @@ struct PackInfo {
   int64_t rowlen;         // doubles per packed row
 };
 
-// Coupling kernels (Fock couplings between blocks).  Index sources: a value
-// >= 0 is a bra slot, -1 - s is summed external label s, -10 is the
-// operator's active label y.
-struct CoupleDesc {
-  TermDesc out;           // bra entry: decode, images, characters (scale used)
-  PackInfo in;            // ket block (W for up, x for down)
-  int ket_src[4];         // source of each ket slot
-  int fx_src, fy_src;     // sources of the two Fock indices
-  int64_t f_stride;       // row stride of f (nmo); f points at the block origin
-  int nsum;               // summed external labels (down): 0..2
-  int sum_dim[2];
-  int ny;                 // 1 or na (operator active label)
-  int64_t ncol;           // alpha columns of the bra (up) or of the ket (down)
+// All-orderings tensors of a block: rows are the external index tuples in
+// row-major slot order (dims slot_dim), rowlen doubles per row.
+struct AllDesc {
+  int nslot;
+  int slot_dim[4];
 };
-// up, stage 2: out[row][a] += scale * sum_img w chi sum_y f(.) W_all(e_k, y*ncol + a)
-hipError_t couple_up(const CoupleDesc& d, const double* f, const double* W, double* out,
-                     hipStream_t s);
-// down, stage 1: Y[row][y*ncol + a'] = sum_img w chi sum_z f(.) X_all(e_k, a')
-hipError_t couple_down(const CoupleDesc& d, const double* f, const double* X, double* Y,
-                       hipStream_t s);
+
+// out_all[e][c] = x_all[e][c] for every tuple e (unpack packed rows)
+hipError_t unpack_all(const PackInfo& p, const AllDesc& a, const double* packed, double* out_all,
+                      hipStream_t s);
+// packed[row][c] += sum_{images e of the orbit} w chi(pi_e) in_all[e][c] for
+// one packed entry described by d (decode, images, character; d.ldo = row
+// stride, d.nalpha = columns)
+hipError_t pack_acc(const TermDesc& d, const AllDesc& a, const double* in_all, double* packed,
+                    hipStream_t s);
+
+// Index sources of the coupling kernels: a value >= 0 is a bra slot, -1 - s
+// is summed external label s, -10 is the operator's active label y.
+struct CoupleDesc {
+  AllDesc bra, ket;
+  int ket_src[4];
+  int fx_src, fy_src;
+  int64_t f_stride;       // row stride of f; f points at the block origin
+  int nsum;
+  int sum_dim[2];
+  int ny;                 // 1 or na
+  int64_t ncol;           // alpha columns (bra for expand, ket for reduce)
+};
+// expand (bra has more external slots):
+//   out_all[e_b][a] += sum_y f(.) W_all[e_k(e_b)][y * ncol + a]
+hipError_t couple_expand(const CoupleDesc& d, const double* f, const double* W, double* out_all,
+                         hipStream_t s);
+// reduce (bra has fewer external slots):
+//   Y_all[e_b][y * ncol + a] = sum_z f(.) X_all[e_k(e_b, z)][a]
+hipError_t couple_reduce(const CoupleDesc& d, const double* f, const double* X, double* Y,
+                         hipStream_t s);
 
 // X0[i][k] = Q[i][idx[k]] * scale[k]  (Q is n x ncq, X0 is n x nk)
 hipError_t select_scale_cols(int64_t n, int64_t ncq, const double* Q, const int32_t* idx,

@@ -58,7 +58,7 @@ def test_debug_gemm_matches_numpy(dev):
 def test_debug_eigh_matches_numpy(dev):
     from paper_1606_01273_amd import lib
     rng = np.random.default_rng(1)
-    for n in (1, 2, 3, 7, 64, 101):
+    for n in (1, 2, 3, 7, 64, 101, 512, 600):
         G = rng.standard_normal((n, n))
         S = G @ G.T / n
         ta = torch.tensor(S, device=dev)
