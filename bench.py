@@ -97,8 +97,8 @@ def main():
                     help="after the timed region, run a plain 1 GiB device copy (calibrates PMC byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only (the method's per-state equations "
-              "shard by state and batch instance; see DESIGN.md); use --gpus 1", file=sys.stderr)
+        print("bench.py: one GPU only; the per-state equations would shard by state and by batch "
+              "instance across GPUs, which is not implemented here; use --gpus 1", file=sys.stderr)
         sys.exit(2)
     dims, wname = WORKLOADS[args.workload]
     nc, na, nv, naux, nst, seed, shift = dims

@@ -187,7 +187,8 @@ CASPT2_API int caspt2_get_lambda(caspt2_handle* h, int32_t L, double* lambda);
  * layout entry k (0..12; the '+' entry also covers its '-' partner when both
  * run in one launch), the average launch duration in ms, the number of
  * launches and the algorithmic bytes per launch (read x, read the source when
- * it is added, write sigma; 8 bytes per double). */
+ * it is added, write sigma; 8 bytes per double).  k = 13 reports the Fock
+ * couplings between blocks of one residual, timed together (bytes 0). */
 CASPT2_API int caspt2_profile(caspt2_handle* h, int32_t enable);
 CASPT2_API int caspt2_profile_entry(caspt2_handle* h, int32_t k, double* avg_ms, int64_t* launches,
                                     double* bytes_per_launch);

@@ -1,6 +1,7 @@
 // HIP kernels for gfx950 (CDNA4): operator application on CI vectors, FP64
 // MFMA GEMMs, packed-term contractions, Jacobi eigensolver, vector ops.
 #include "kernels.hpp"
+#include "device_common.hpp"
 
 #include <cmath>
 #include <vector>
@@ -453,42 +454,6 @@ hipError_t df_pack(const double* B, int naux, int nmo, int p0, int np, int q0, i
 //   out[row][alpha] += scale * sum_{images e of the orbit} w chi(pi_e)
 //                      * sum_{y} C[idx(e, y)] * G[(y * nalpha + alpha) * gcols + gcol]
 // ---------------------------------------------------------------------------
-__device__ inline void decode_orbit(const TermDesc& d, int64_t row, int e[4]) {
-  // units from the last slot backwards; a swap pair (k, k+1) is one unit
-  int k = d.nslot - 1;
-  int64_t rem = row;
-  while (k >= 0) {
-    int sw = -1;
-    for (int s = 0; s < d.nswap; ++s)
-      if (d.swap_l[s] == k && d.swap_k[s] == k - 1) sw = s;
-    if (sw >= 0) {
-      const int64_t dim = d.slot_dim[k];
-      const int64_t cnt = d.strict[sw] ? dim * (dim - 1) / 2 : dim * (dim + 1) / 2;
-      const int64_t p = rem % cnt;
-      rem /= cnt;
-      int64_t hi;
-      if (d.strict[sw]) {
-        hi = (int64_t)floor((sqrt(8.0 * (double)p + 1.0) + 1.0) * 0.5);
-        while (hi * (hi - 1) / 2 > p) --hi;
-        while ((hi + 1) * hi / 2 <= p) ++hi;
-        e[k - 1] = (int)hi;
-        e[k] = (int)(p - hi * (hi - 1) / 2);
-      } else {
-        hi = (int64_t)floor((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
-        while (hi * (hi + 1) / 2 > p) --hi;
-        while ((hi + 1) * (hi + 2) / 2 <= p) ++hi;
-        e[k - 1] = (int)hi;
-        e[k] = (int)(p - hi * (hi + 1) / 2);
-      }
-      k -= 2;
-    } else {
-      const int64_t dim = d.slot_dim[k];
-      e[k] = (int)(rem % dim);
-      rem /= dim;
-      k -= 1;
-    }
-  }
-}
 
 __global__ void k_term_source(TermDesc d, const double* __restrict__ C, const double* __restrict__ G,
                               double* __restrict__ out) {
@@ -549,303 +514,6 @@ hipError_t term_source(const TermDesc& d, const double* C, const double* G, doub
   unsigned grid = cdiv(total, 256);
   if (grid > 65536) grid = 65536;
   hipLaunchKernelGGL(k_term_source, dim3(grid), dim3(256), 0, s, d, C, G, out);
-  return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// coupling kernels
-// ---------------------------------------------------------------------------
-__device__ inline int64_t pair_rank(int hi, int lo, bool strict) {
-  return strict ? (int64_t)hi * (hi - 1) / 2 + lo : (int64_t)hi * (hi + 1) / 2 + lo;
-}
-
-// value of the all-orderings amplitude x[e][col] from the packed rows:
-// x[e] = sum_chi chi(pi_e) t_chi[orbit(e)] / sqrt(|orbit|)
-__device__ double gather_all(const PackInfo& p, const double* __restrict__ base, const int e[4],
-                             int64_t col) {
-  int c[4] = {e[0], e[1], e[2], e[3]};
-  int swapped[2] = {0, 0}, equal[2] = {0, 0}, ndist = 0;
-  for (int s = 0; s < p.nswap; ++s) {
-    const int k = p.swap_k[s], l = p.swap_l[s];
-    if (c[k] < c[l]) {
-      const int t = c[k];
-      c[k] = c[l];
-      c[l] = t;
-      swapped[s] = 1;
-    }
-    if (c[k] == c[l]) equal[s] = 1;
-    else ++ndist;
-  }
-  const double w = 1.0 / sqrt((double)(1 << ndist));
-  double acc = 0.0;
-  for (int ent = 0; ent < p.nent; ++ent) {
-    bool ok = true;
-    double sg = 1.0;
-    for (int s = 0; s < p.nswap; ++s) {
-      if (equal[s] && p.chi[ent][s] < 0) ok = false;
-      if (swapped[s]) sg *= p.chi[ent][s];
-    }
-    if (!ok) continue;
-    int64_t row = 0;
-    for (int k = 0; k < p.nslot; ++k) {
-      int sw = -1;
-      for (int s = 0; s < p.nswap; ++s)
-        if (p.swap_k[s] == k) sw = s;
-      const int64_t d = p.slot_dim[k];
-      if (sw >= 0) {
-        const bool strict = p.chi[ent][sw] < 0;
-        const int64_t cnt = strict ? d * (d - 1) / 2 : d * (d + 1) / 2;
-        row = row * cnt + pair_rank(c[k], c[k + 1], strict);
-        ++k;
-      } else {
-        row = row * d + c[k];
-      }
-    }
-    acc += sg * base[p.offset[ent] + row * p.rowlen + col];
-  }
-  return w * acc;
-}
-
-__device__ inline int src_value(int src, const int e[4], const int z[2], int y) {
-  return src >= 0 ? e[src] : (src == -10 ? y : z[-1 - src]);
-}
-
-__device__ inline void decode_all(const AllDesc& a, int64_t row, int e[4]) {
-  for (int k = a.nslot - 1; k >= 0; --k) {
-    e[k] = (int)(row % a.slot_dim[k]);
-    row /= a.slot_dim[k];
-  }
-}
-
-__device__ inline int64_t encode_all(const AllDesc& a, const int e[4]) {
-  int64_t row = 0;
-  for (int k = 0; k < a.nslot; ++k) row = row * a.slot_dim[k] + e[k];
-  return row;
-}
-
-__global__ void k_unpack_all(PackInfo p, AllDesc a, int64_t nrows, const double* __restrict__ packed,
-                             double* __restrict__ out) {
-  const int64_t total = nrows * p.rowlen;
-  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
-       g += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t row = g / p.rowlen, c = g % p.rowlen;
-    int e[4] = {0, 0, 0, 0};
-    decode_all(a, row, e);
-    out[g] = gather_all(p, packed, e, c);
-  }
-}
-
-hipError_t unpack_all(const PackInfo& p, const AllDesc& a, const double* packed, double* out_all,
-                      hipStream_t s) {
-  int64_t nrows = 1;
-  for (int k = 0; k < a.nslot; ++k) nrows *= a.slot_dim[k];
-  const int64_t total = nrows * p.rowlen;
-  if (total == 0) return hipSuccess;
-  unsigned grid = cdiv(total, 256);
-  if (grid > 65536) grid = 65536;
-  hipLaunchKernelGGL(k_unpack_all, dim3(grid), dim3(256), 0, s, p, a, nrows, packed, out_all);
-  return hipGetLastError();
-}
-
-__global__ void k_pack_acc(TermDesc d, AllDesc a, const double* __restrict__ in,
-                           double* __restrict__ out) {
-  const int64_t total = d.nrow * d.nalpha;
-  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
-       g += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t row = g / d.nalpha, c = g % d.nalpha;
-    int e0[4] = {0, 0, 0, 0};
-    decode_orbit(d, row, e0);
-    int ndistinct = 0;
-    for (int s = 0; s < d.nswap; ++s)
-      if (e0[d.swap_k[s]] != e0[d.swap_l[s]]) ++ndistinct;
-    const double w = 1.0 / sqrt((double)(1 << ndistinct));
-    double acc = 0.0;
-    for (int bits = 0; bits < (1 << d.nswap); ++bits) {
-      int e[4] = {e0[0], e0[1], e0[2], e0[3]};
-      double sg = 1.0;
-      bool dup = false;
-      for (int s = 0; s < d.nswap; ++s)
-        if ((bits >> s) & 1) {
-          if (e0[d.swap_k[s]] == e0[d.swap_l[s]]) dup = true;
-          const int t = e[d.swap_k[s]];
-          e[d.swap_k[s]] = e[d.swap_l[s]];
-          e[d.swap_l[s]] = t;
-          sg *= d.chi[s];
-        }
-      if (dup) continue;
-      acc += sg * in[encode_all(a, e) * d.nalpha + c];
-    }
-    out[row * d.ldo + c] += w * acc;
-  }
-}
-
-hipError_t pack_acc(const TermDesc& d, const AllDesc& a, const double* in_all, double* packed,
-                    hipStream_t s) {
-  const int64_t total = d.nrow * d.nalpha;
-  if (total == 0) return hipSuccess;
-  unsigned grid = cdiv(total, 256);
-  if (grid > 65536) grid = 65536;
-  hipLaunchKernelGGL(k_pack_acc, dim3(grid), dim3(256), 0, s, d, a, in_all, packed);
-  return hipGetLastError();
-}
-
-// expand: one thread per (ket row, alpha column); the bra slots that are not
-// fed from the ket (the Fock index slots) are looped inside the thread, so
-// every W row is read once.
-__global__ void k_couple_expand(CoupleDesc d, const double* __restrict__ f,
-                                const double* __restrict__ W, double* __restrict__ out) {
-  int64_t nrows_k = 1;
-  for (int k = 0; k < d.ket.nslot; ++k) nrows_k *= d.ket.slot_dim[k];
-  const int64_t total = nrows_k * d.ncol;
-  const int64_t wlen = (int64_t)d.ny * d.ncol;
-  // bra slots not fed from the ket
-  int free_slot[2] = {-1, -1}, nfree = 0;
-  for (int k = 0; k < d.bra.nslot; ++k) {
-    bool fed = false;
-    for (int l = 0; l < d.ket.nslot; ++l)
-      if (d.ket_src[l] == k) fed = true;
-    if (!fed && nfree < 2) free_slot[nfree++] = k;
-  }
-  const int n0 = nfree > 0 ? d.bra.slot_dim[free_slot[0]] : 1;
-  const int n1 = nfree > 1 ? d.bra.slot_dim[free_slot[1]] : 1;
-  const int z[2] = {0, 0};
-  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
-       g += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t rk = g / d.ncol, a = g % d.ncol;
-    int ek[4] = {0, 0, 0, 0}, e[4] = {0, 0, 0, 0};
-    decode_all(d.ket, rk, ek);
-    for (int l = 0; l < d.ket.nslot; ++l) e[d.ket_src[l]] = ek[l];
-    double wreg[8];
-    const double* w = W + rk * wlen + a;
-    for (int y = 0; y < d.ny; ++y) wreg[y] = w[(int64_t)y * d.ncol];
-    for (int z0 = 0; z0 < n0; ++z0) {
-      if (nfree > 0) e[free_slot[0]] = z0;
-      for (int z1 = 0; z1 < n1; ++z1) {
-        if (nfree > 1) e[free_slot[1]] = z1;
-        double acc = 0.0;
-        for (int y = 0; y < d.ny; ++y)
-          acc += f[(int64_t)src_value(d.fx_src, e, z, y) * d.f_stride + src_value(d.fy_src, e, z, y)] *
-                 wreg[y];
-        out[encode_all(d.bra, e) * d.ncol + a] += acc;
-      }
-    }
-  }
-}
-
-// expand, output-parallel form (for kets with few rows): one thread per
-// (bra row, alpha column); W rows are small and stay in cache.
-__global__ void k_couple_expand_out(CoupleDesc d, const double* __restrict__ f,
-                                    const double* __restrict__ W, double* __restrict__ out) {
-  int64_t nrows = 1;
-  for (int k = 0; k < d.bra.nslot; ++k) nrows *= d.bra.slot_dim[k];
-  const int64_t total = nrows * d.ncol;
-  const int64_t wlen = (int64_t)d.ny * d.ncol;
-  const int z[2] = {0, 0};
-  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
-       g += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t row = g / d.ncol, a = g % d.ncol;
-    int e[4] = {0, 0, 0, 0}, ek[4] = {0, 0, 0, 0};
-    decode_all(d.bra, row, e);
-    for (int l = 0; l < d.ket.nslot; ++l) ek[l] = e[d.ket_src[l]];
-    const double* w = W + encode_all(d.ket, ek) * wlen + a;
-    double acc = 0.0;
-    for (int y = 0; y < d.ny; ++y)
-      acc += f[(int64_t)src_value(d.fx_src, e, z, y) * d.f_stride + src_value(d.fy_src, e, z, y)] *
-             w[(int64_t)y * d.ncol];
-    out[g] += acc;
-  }
-}
-
-hipError_t couple_expand(const CoupleDesc& d, const double* f, const double* W, double* out_all,
-                         hipStream_t s) {
-  if (d.ny > 8) return hipErrorInvalidValue;
-  int64_t nrows_k = 1, nrows_b = 1;
-  for (int k = 0; k < d.ket.nslot; ++k) nrows_k *= d.ket.slot_dim[k];
-  for (int k = 0; k < d.bra.nslot; ++k) nrows_b *= d.bra.slot_dim[k];
-  if (nrows_b * d.ncol == 0) return hipSuccess;
-  if (nrows_k * d.ncol >= (int64_t)1 << 20) {
-    unsigned grid = cdiv(nrows_k * d.ncol, 256);
-    if (grid > 65536) grid = 65536;
-    hipLaunchKernelGGL(k_couple_expand, dim3(grid), dim3(256), 0, s, d, f, W, out_all);
-  } else {
-    unsigned grid = cdiv(nrows_b * d.ncol, 256);
-    if (grid > 65536) grid = 65536;
-    hipLaunchKernelGGL(k_couple_expand_out, dim3(grid), dim3(256), 0, s, d, f, W, out_all);
-  }
-  return hipGetLastError();
-}
-
-// reduce: a workgroup handles R bra rows; thread = (row, alpha column, z part);
-// partial sums over the summed external labels are combined through LDS.
-__global__ __launch_bounds__(256) void k_couple_reduce(CoupleDesc d, int P, int CT,
-                                                       const double* __restrict__ f,
-                                                       const double* __restrict__ X,
-                                                       double* __restrict__ Y) {
-  __shared__ double part[256 * 8];
-  int64_t nrows = 1;
-  for (int k = 0; k < d.bra.nslot; ++k) nrows *= d.bra.slot_dim[k];
-  const int per_row = CT * P;
-  const int R = 256 / per_row;
-  const int n0 = d.nsum > 0 ? d.sum_dim[0] : 1;
-  const int n1 = d.nsum > 1 ? d.sum_dim[1] : 1;
-  const int nz = n0 * n1;
-  const int t = threadIdx.x;
-  // lanes: column fastest, then row, then z part (coalesced row reads)
-  const int zp = t / (R * CT);
-  const int rr = t % (R * CT);
-  const int r = rr / CT;
-  const int64_t a = (int64_t)blockIdx.y * CT + rr % CT;
-  const bool acol = a < d.ncol;
-  const int64_t width = (int64_t)d.ny * d.ncol;
-  for (int64_t row0 = (int64_t)blockIdx.x * R; row0 < nrows; row0 += (int64_t)gridDim.x * R) {
-    const int64_t row = row0 + r;
-    const bool live = zp < P && row < nrows && acol;
-    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    if (live) {
-      int e[4] = {0, 0, 0, 0};
-      decode_all(d.bra, row, e);
-      for (int zz = zp; zz < nz; zz += P) {
-        const int zv[2] = {zz / n1, zz % n1};
-        int ek[4] = {0, 0, 0, 0};
-        for (int l = 0; l < d.ket.nslot; ++l) ek[l] = src_value(d.ket_src[l], e, zv, 0);
-        const double xv = X[encode_all(d.ket, ek) * d.ncol + a];
-        for (int y = 0; y < d.ny; ++y)
-          acc[y] += f[(int64_t)src_value(d.fx_src, e, zv, y) * d.f_stride + src_value(d.fy_src, e, zv, y)] * xv;
-      }
-    }
-    for (int y = 0; y < 8; ++y) part[y * 256 + t] = acc[y];
-    __syncthreads();
-    if (live && zp == 0) {
-      for (int y = 0; y < d.ny; ++y) {
-        double sum = 0.0;
-        for (int q = 0; q < P; ++q) sum += part[y * 256 + t + q * R * CT];
-        Y[row * width + (int64_t)y * d.ncol + a] = sum;
-      }
-    }
-    __syncthreads();
-  }
-}
-
-hipError_t couple_reduce(const CoupleDesc& d, const double* f, const double* X, double* Y,
-                         hipStream_t s) {
-  if (d.ny > 8) return hipErrorInvalidValue;
-  int64_t nrows = 1;
-  for (int k = 0; k < d.bra.nslot; ++k) nrows *= d.bra.slot_dim[k];
-  if (nrows * d.ncol == 0) return hipSuccess;
-  const int n0 = d.nsum > 0 ? d.sum_dim[0] : 1;
-  const int n1 = d.nsum > 1 ? d.sum_dim[1] : 1;
-  const int nz = n0 * n1;
-  const int CT = (int)(d.ncol < 256 ? d.ncol : 256);
-  // rows per block: fill a wave with (row, column) pairs first
-  int Rw = 1;
-  while (Rw * 2 * CT <= 64) Rw *= 2;
-  int P = 1;
-  while (P * 2 <= nz && P * 2 * Rw * CT <= 256) P *= 2;
-  const int R = 256 / (CT * P);
-  unsigned gx = cdiv(nrows, R);
-  if (gx > 65536) gx = 65536;
-  const unsigned gy = cdiv(d.ncol, CT);
-  hipLaunchKernelGGL(k_couple_reduce, dim3(gx, gy), dim3(256), 0, s, d, P, CT, f, X, Y);
   return hipGetLastError();
 }
 

@@ -99,12 +99,14 @@ struct AllDesc {
 };
 
 // out_all[e][c] = x_all[e][c] for every tuple e (unpack packed rows)
-hipError_t unpack_all(const PackInfo& p, const AllDesc& a, const double* packed, double* out_all,
+template <typename T>
+hipError_t unpack_all(const PackInfo& p, const AllDesc& a, const T* packed, T* out_all,
                       hipStream_t s);
 // packed[row][c] += sum_{images e of the orbit} w chi(pi_e) in_all[e][c] for
 // one packed entry described by d (decode, images, character; d.ldo = row
 // stride, d.nalpha = columns)
-hipError_t pack_acc(const TermDesc& d, const AllDesc& a, const double* in_all, double* packed,
+template <typename T>
+hipError_t pack_acc(const TermDesc& d, const AllDesc& a, const T* in_all, T* packed,
                     hipStream_t s);
 
 // Index sources of the coupling kernels: a value >= 0 is a bra slot, -1 - s
@@ -121,11 +123,13 @@ struct CoupleDesc {
 };
 // expand (bra has more external slots):
 //   out_all[e_b][a] += sum_y f(.) W_all[e_k(e_b)][y * ncol + a]
-hipError_t couple_expand(const CoupleDesc& d, const double* f, const double* W, double* out_all,
+template <typename T>
+hipError_t couple_expand(const CoupleDesc& d, const double* f, const T* W, T* out_all,
                          hipStream_t s);
 // reduce (bra has fewer external slots):
 //   Y_all[e_b][y * ncol + a] = sum_z f(.) X_all[e_k(e_b, z)][a]
-hipError_t couple_reduce(const CoupleDesc& d, const double* f, const double* X, double* Y,
+template <typename T>
+hipError_t couple_reduce(const CoupleDesc& d, const double* f, const T* X, T* Y,
                          hipStream_t s);
 
 // X0[i][k] = Q[i][idx[k]] * scale[k]  (Q is n x ncq, X0 is n x nk)
