@@ -92,7 +92,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-nv", type=int, default=24)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--solve", action="store_true", help="also time the amplitude and lambda solves")
+    ap.add_argument("--solve", action="store_true",
+                    help="also time the amplitude, H_eff and lambda solves in FP64 and in mixed precision")
+    ap.add_argument("--solve-tol", type=float, default=1e-10)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed region, run a plain 1 GiB device copy (calibrates PMC byte counters)")
     args = ap.parse_args()
@@ -170,14 +172,38 @@ def main():
 
     solve = None
     if args.solve:
-        t0 = time.perf_counter()
-        rc, info = g.solve_amplitudes(tol=1e-10, maxiter=200)
-        H, w, R = g.heff()
-        rc2, linfo = g.solve_lambda(0, tol=1e-10, maxiter=200)
-        torch.cuda.synchronize()
-        solve = {"seconds": round(time.perf_counter() - t0, 3), "status": [rc, rc2],
-                 "amp_iters": [i["iters"] for i in info], "lambda_iters": [i["iters"] for i in linfo],
-                 "e_ms": [float(v) for v in w]}
+        # amplitude + H_eff + lambda solves in FP64 and in mixed precision
+        # (FP64 refinement around FP32 PCG), same inputs, same tolerance
+        from paper_1606_01273_amd import MIXED
+        solve = {"tol": args.solve_tol}
+        ref = None
+        for name in ("fp64", "mixed"):
+            gg = g if name == "fp64" else Caspt2.from_problem(prob, precision=MIXED)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rc, info = gg.solve_amplitudes(tol=args.solve_tol, maxiter=400)
+            H, w, R = gg.heff()
+            rc2, linfo = gg.solve_lambda(0, tol=args.solve_tol, maxiter=400)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            lam = [gg.lam(L) for L in range(nst)]
+            rec = {"seconds": round(dt, 3), "status": [rc, rc2], "amp_iters": [i["iters"] for i in info],
+                   "lambda_iters": [i["iters"] for i in linfo], "e_ms": [float(v) for v in w],
+                   "lambda_norm": [float(torch.linalg.vector_norm(v)) for v in lam]}
+            if name == "mixed":
+                rec["refinements"] = [i["refinements"] for i in info] + [i["refinements"] for i in linfo]
+                rec["max_abs_dE_ms_vs_fp64"] = float(np.abs(np.asarray(w) - ref[0]).max())
+                scale = max(float(torch.linalg.vector_norm(v)) for v in ref[1])
+                rec["max_rel_dlambda_vs_fp64"] = max(float(torch.linalg.vector_norm(a - b)) / scale
+                                                     for a, b in zip(lam, ref[1]))
+                rec["speedup_vs_fp64"] = round(solve["fp64"]["seconds"] / dt, 3)
+                del lam
+                gg.close()
+            else:
+                ref = (np.asarray(w).copy(), lam)
+            solve[name] = rec
+            print(f"[bench] {name} solves in {dt:.2f} s", file=sys.stderr, flush=True)
+        ref = None
 
     cpu = None
     if child is not None:

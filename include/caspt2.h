@@ -96,13 +96,20 @@ enum {
 };
 
 enum { CASPT2_MSMR = 0, CASPT2_SSSR = 1 };  /* Sec. II.B, Eqs. 7 and 9 */
-enum { CASPT2_FP64 = 0 };
+/* Arithmetic of the solves.  FP64: every step in FP64.  MIXED: the
+ * set-up (XMS, integrals, sources, metrics, bases, denominators), the
+ * effective Hamiltonian and the refinement residual stay FP64; each PCG
+ * (amplitudes, lambda) runs as FP64 iterative refinement around an inner
+ * PCG whose operator, basis transforms, couplings and vectors are FP32 (dot
+ * products accumulated in FP64).  The refined solution meets the same FP64
+ * residual tolerance.  caspt2_residual is FP64 in both modes. */
+enum { CASPT2_FP64 = 0, CASPT2_MIXED = 1 };
 
 typedef struct {
   int32_t nclosed, nact, nvirt, naux, nstates, nelec;
   int32_t scheme;      /* CASPT2_MSMR or CASPT2_SSSR */
   int32_t xms;         /* 1: XMS rotation (Eqs. 3-5); 0: U = 1, MS-CASPT2 */
-  int32_t precision;   /* CASPT2_FP64 */
+  int32_t precision;   /* CASPT2_FP64 or CASPT2_MIXED */
   int32_t reserved;
   double shift;        /* real vertical shift E_s (Sec. II.B) */
   double ovl_thresh;   /* overlap eigenvalue truncation, 1e-9 in the paper */
@@ -117,13 +124,16 @@ typedef struct {      /* all [row-major], read only, copied at create */
 } caspt2_inputs;
 
 typedef struct {
-  int32_t iters;        /* PCG iterations */
+  int32_t iters;        /* PCG iterations (FP32 inner iterations in MIXED) */
   int32_t flags;        /* bit 0: converged */
   double resnorm;       /* final 2-norm of the residual in the orthonormal basis */
   double e0;            /* E_L^(0) (Eq. 14) */
   double min_denom;     /* smallest preconditioner denominator */
   double emin_kept;     /* smallest kept overlap eigenvalue (all blocks) */
   double emax_dropped;  /* largest dropped overlap eigenvalue (-1 if none) */
+  int32_t refinements;  /* MIXED: FP64 refinement steps (iters counts the FP32
+                           inner iterations of all of them); 0 in FP64 */
+  int32_t reserved;
 } caspt2_info;
 
 typedef struct caspt2_handle caspt2_handle;

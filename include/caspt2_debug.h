@@ -15,6 +15,10 @@ extern "C" {
 CASPT2_API int caspt2_debug_gemm(int32_t b_is_nk, int64_t M, int64_t N, int64_t K, const double* A,
                                  const double* B, double* C);
 
+/* C = A * op(B) with the library's FP32 GEMM (same layout, float data). */
+CASPT2_API int caspt2_debug_gemm_f32(int32_t b_is_nk, int64_t M, int64_t N, int64_t K, const float* A,
+                                     const float* B, float* C);
+
 /* Copy an intermediate of layout entry k of function set `set` (0 for MS-MR,
  * L for SS-SR) into host memory `out`: which = 0 overlap metric S [na][na],
  * 1 Fock metric F [na][na], 2 row energies [rows], 3 kept count (one

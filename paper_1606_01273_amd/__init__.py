@@ -11,9 +11,9 @@ import numpy as np
 
 from . import _lib
 from ._lib import (E_ARG, E_DEVICE, E_INDEFINITE, E_NOCONV, E_NOMEM, E_NOTIMPL, E_STATE, ENTRY_NAMES,
-                   MSMR, OK, SSSR, Caspt2Error)
+                   FP64, MIXED, MSMR, OK, SSSR, Caspt2Error)
 
-__all__ = ["Caspt2", "Caspt2Error", "lib", "MSMR", "SSSR", "ENTRY_NAMES"]
+__all__ = ["Caspt2", "Caspt2Error", "lib", "MSMR", "SSSR", "FP64", "MIXED", "ENTRY_NAMES"]
 
 _LIB = None
 
@@ -41,11 +41,11 @@ class Caspt2:
     library handle).  Host numpy inputs are copied at creation."""
 
     def __init__(self, nclosed, nact, nvirt, naux, nstates, nelec, fock, hcore, dfB, ci, eref,
-                 shift=0.0, scheme=MSMR, xms=True, thresh=1e-9, stream=None):
+                 shift=0.0, scheme=MSMR, xms=True, thresh=1e-9, precision=FP64, stream=None):
         import torch
         L = lib()
         self.nst = nstates
-        d = _lib.Dims(nclosed, nact, nvirt, naux, nstates, nelec, scheme, 1 if xms else 0, 0, 0,
+        d = _lib.Dims(nclosed, nact, nvirt, naux, nstates, nelec, scheme, 1 if xms else 0, int(precision), 0,
                       float(shift), float(thresh))
         arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (fock, hcore, dfB, ci, eref)]
         inp = _lib.Inputs(*[a.ctypes.data for a in arrs])

@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libcaspt2.so")
 
 OK, E_ARG, E_NOMEM, E_DEVICE, E_NOCONV, E_INDEFINITE, E_NOTIMPL, E_STATE = 0, -1, -2, -3, -4, -5, -6, -7
 MSMR, SSSR = 0, 1
+FP64, MIXED = 0, 1
 ENTRY_NAMES = ["ccvv+", "ccvv-", "cavv+", "cavv-", "aavv+", "aavv-", "ccav+", "ccav-",
                "ccaa+", "ccaa-", "aaav", "caaa", "caav"]
 
@@ -35,7 +36,8 @@ class Inputs(ctypes.Structure):
 class Info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("flags", ctypes.c_int32), ("resnorm", ctypes.c_double),
                 ("e0", ctypes.c_double), ("min_denom", ctypes.c_double),
-                ("emin_kept", ctypes.c_double), ("emax_dropped", ctypes.c_double)]
+                ("emin_kept", ctypes.c_double), ("emax_dropped", ctypes.c_double),
+                ("refinements", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -65,6 +67,8 @@ SIGNATURES = {
     "caspt2_profile_entry": (ctypes.c_int, [_P, ctypes.c_int32, _D, ctypes.POINTER(ctypes.c_int64), _D]),
     "caspt2_debug_gemm": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
                                          _P, _P, _P]),
+    "caspt2_debug_gemm_f32": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                             _P, _P, _P]),
     "caspt2_debug_entry": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _D]),
     "caspt2_debug_source": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P]),
     "caspt2_debug_eigh": (ctypes.c_int, [ctypes.c_int32, _P, _D, _P]),

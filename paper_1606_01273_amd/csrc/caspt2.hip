@@ -40,29 +40,30 @@ struct DevError : std::runtime_error {
   } while (0)
 
 // owning device buffer
-struct DBuf {
-  double* p = nullptr;
+template <typename T>
+struct DevBuf {
+  T* p = nullptr;
   int64_t n = 0;
-  DBuf() = default;
-  explicit DBuf(int64_t n_) { alloc(n_); }
+  DevBuf() = default;
+  explicit DevBuf(int64_t n_) { alloc(n_); }
   void alloc(int64_t n_) {
     release();
     n = n_;
-    if (n > 0) HIPCHECK(hipMalloc(&p, (size_t)n * sizeof(double)));
+    if (n > 0) HIPCHECK(hipMalloc(&p, (size_t)n * sizeof(T)));
   }
   void zero(hipStream_t s) {
-    if (n > 0) HIPCHECK(hipMemsetAsync(p, 0, (size_t)n * sizeof(double), s));
+    if (n > 0) HIPCHECK(hipMemsetAsync(p, 0, (size_t)n * sizeof(T), s));
   }
   void release() {
     if (p) (void)hipFree(p);
     p = nullptr;
     n = 0;
   }
-  ~DBuf() { release(); }
-  DBuf(const DBuf&) = delete;
-  DBuf& operator=(const DBuf&) = delete;
-  DBuf(DBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
-  DBuf& operator=(DBuf&& o) noexcept {
+  ~DevBuf() { release(); }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
     release();
     p = o.p;
     n = o.n;
@@ -71,6 +72,8 @@ struct DBuf {
     return *this;
   }
 };
+using DBuf = DevBuf<double>;
+using FBuf = DevBuf<float>;
 
 struct IBuf {
   int32_t* p = nullptr;
@@ -95,6 +98,7 @@ struct Entry {
   int64_t nrow = 0, nalpha = 0, offset = 0;
   int64_t nkeep = 0, ooff = 0;   // orthogonal-basis columns and offset
   DBuf S, F, X, mu, eps;          // S,F [nalpha^2]; X [nalpha][nkeep]; mu [nkeep]; eps [nrow]
+  FBuf S32, F32, X32, eps32;      // FP32 copies for the inner solver (mixed precision)
   double emin_kept = INFINITY, emax_dropped = -1.0;
 };
 
@@ -104,7 +108,59 @@ struct CoupleTerm {
   CoupleDesc d;          // ket_src, fx/fy, nsum, sum_dim, ny, f_stride filled
   int64_t f_off;         // offset of the Fock block origin in f
   DBuf G;                // up: [ny * nalpha_b][nalpha_k]; down: [nalpha_b][ny * nalpha_k]
+  FBuf G32;              // FP32 copy (mixed precision)
 };
+
+// element-type selection of the per-entry and per-term operands
+template <typename T>
+struct Sel;
+template <>
+struct Sel<double> {
+  static const double* S(const Entry& e) { return e.S.p; }
+  static const double* F(const Entry& e) { return e.F.p; }
+  static const double* X(const Entry& e) { return e.X.p; }
+  static const double* eps(const Entry& e) { return e.eps.p; }
+  static const double* G(const CoupleTerm& t) { return t.G.p; }
+};
+template <>
+struct Sel<float> {
+  static const float* S(const Entry& e) { return e.S32.p; }
+  static const float* F(const Entry& e) { return e.F32.p; }
+  static const float* X(const Entry& e) { return e.X32.p; }
+  static const float* eps(const Entry& e) { return e.eps32.p; }
+  static const float* G(const CoupleTerm& t) { return t.G32.p; }
+};
+
+inline hipError_t gemm_t(bool nk, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
+                         int64_t lda, const double* B, int64_t ldb, double beta, double* C,
+                         int64_t ldc, hipStream_t s) {
+  return gemm_f64(nk, M, N, K, alpha, A, lda, 0, B, ldb, 0, beta, C, ldc, 0, 1, s);
+}
+inline hipError_t gemm_t(bool nk, int64_t M, int64_t N, int64_t K, double alpha, const float* A,
+                         int64_t lda, const float* B, int64_t ldb, double beta, float* C,
+                         int64_t ldc, hipStream_t s) {
+  return gemm_f32(nk, M, N, K, (float)alpha, A, lda, 0, B, ldb, 0, (float)beta, C, ldc, 0, 1, s);
+}
+inline hipError_t residual_small_t(int64_t M, int64_t N, const double* X, const double* S,
+                                   const double* F, const double* d, double dshift,
+                                   const double* V, double* C, hipStream_t s) {
+  return residual_small_f64(M, N, X, S, F, d, dshift, V, C, s);
+}
+inline hipError_t residual_small_t(int64_t M, int64_t N, const float* X, const float* S,
+                                   const float* F, const float* d, double dshift, const float* V,
+                                   float* C, hipStream_t s) {
+  return residual_small_f32(M, N, X, S, F, d, (float)dshift, V, C, s);
+}
+inline hipError_t residual_gemm_t(int64_t M, int64_t N, const double* X, const double* S,
+                                  const double* F, const double* d, double dshift,
+                                  const double* V, double* C, hipStream_t s) {
+  return residual_gemm_f64(M, N, N, X, N, S, F, d, dshift, V, N, C, N, s);
+}
+inline hipError_t residual_gemm_t(int64_t M, int64_t N, const float* X, const float* S,
+                                  const float* F, const float* d, double dshift, const float* V,
+                                  float* C, hipStream_t s) {
+  return residual_gemm_f32(M, N, N, X, N, S, F, d, (float)dshift, V, N, C, N, s);
+}
 
 struct ProfEventRec {
   int entry;
@@ -985,16 +1041,22 @@ void setup_couplings(H& h) {
 // sigma += (Fock couplings between blocks) x, through all-orderings tensors:
 // unpack the blocks, run every term (GEMM over the compound active index and
 // an index-mapped expand or reduce with the Fock block), pack once per block.
-void apply_couplings(H& h, int set, const double* x, double* sig) {
+// (T = float in the inner solver of the mixed-precision mode: the
+// all-orderings buffers, sized for doubles, then hold floats.)
+template <typename T>
+void apply_couplings(H& h, int set, const T* x, T* sig) {
   auto nalpha_of = [&](int block) {
     for (auto& e : h.sets[set])
       if (e.block == block) return e.nalpha;
     return (int64_t)0;
   };
+  auto xall = [&](int b) { return reinterpret_cast<T*>(h.xall[b].p); };
+  auto sall = [&](int b) { return reinterpret_cast<T*>(h.sall[b].p); };
+  T* scratch = reinterpret_cast<T*>(h.cscratch.p);
   for (int b = 0; b < NBLOCK; ++b) {
     if (!h.xall[b].p) continue;
     const int64_t na_b = nalpha_of(b);
-    HIPCHECK(unpack_all(pack_info(h, set, b, nullptr, nullptr, na_b), all_desc(h, b), x, h.xall[b].p, h.s));
+    HIPCHECK(unpack_all(pack_info(h, set, b, nullptr, nullptr, na_b), all_desc(h, b), x, xall(b), h.s));
     h.sall[b].zero(h.s);
   }
   const bool diag = h.verbose_level >= 2;   // per-term timing on stderr
@@ -1012,14 +1074,14 @@ void apply_couplings(H& h, int set, const double* x, double* sig) {
     }
     if (t.up) {
       const int64_t width = (int64_t)t.d.ny * nab;
-      HIPCHECK(gemm_f64(true, all_rows(h, t.ket), width, nak, 1.0, h.xall[t.ket].p, nak, 0, t.G.p, nak, 0,
-                        0.0, h.cscratch.p, width, 0, 1, h.s));
-      HIPCHECK(couple_expand(t.d, f, h.cscratch.p, h.sall[t.bra].p, h.s));
+      HIPCHECK(gemm_t(true, all_rows(h, t.ket), width, nak, 1.0, xall(t.ket), nak, Sel<T>::G(t), nak, 0.0,
+                      scratch, width, h.s));
+      HIPCHECK(couple_expand(t.d, f, (const T*)scratch, sall(t.bra), h.s));
     } else {
       const int64_t width = (int64_t)t.d.ny * nak;
-      HIPCHECK(couple_reduce(t.d, f, h.xall[t.ket].p, h.cscratch.p, h.s));
-      HIPCHECK(gemm_f64(true, all_rows(h, t.bra), nab, width, 1.0, h.cscratch.p, width, 0, t.G.p, width,
-                        0, 1.0, h.sall[t.bra].p, nab, 0, 1, h.s));
+      HIPCHECK(couple_reduce(t.d, f, (const T*)xall(t.ket), scratch, h.s));
+      HIPCHECK(gemm_t(true, all_rows(h, t.bra), nab, width, 1.0, scratch, width, Sel<T>::G(t), width, 1.0,
+                      sall(t.bra), nab, h.s));
     }
   }
   if (diag) {
@@ -1031,7 +1093,7 @@ void apply_couplings(H& h, int set, const double* x, double* sig) {
     for (auto& e : h.sets[set]) {
       if (e.block != b || e.nrow == 0) continue;
       TermDesc d = base_desc(h, blocks()[b], e);
-      HIPCHECK(pack_acc(d, all_desc(h, b), h.sall[b].p, sig + e.offset, h.s));
+      HIPCHECK(pack_acc(d, all_desc(h, b), (const T*)sall(b), sig + e.offset, h.s));
     }
   }
 }
@@ -1058,63 +1120,85 @@ void prof_end(H& h, int entry, double bytes, hipEvent_t a) {
   h.prof_events.push_back({entry, bytes, a, b});
 }
 
-void residual(H& h, int L, const double* x, double* sig, bool with_source) {
+// sigma_L = A_L x (+ V^(L)) in the packed layout (Eq. 10).  T = double is
+// the FP64 operator; T = float the FP32 operator of the mixed-precision
+// inner solver (FP32 copies of S, F, eps and of the coupling matrices).
+template <typename T>
+void residual(H& h, int L, const T* x, T* sig, bool with_source) {
   const int set = set_of(h, L);
   const double dshift = h.d.shift - h.e0[L];
+  const double esz = (double)sizeof(T);
   auto& es = h.sets[set];
   for (size_t k = 0; k < es.size(); ++k) {
     auto& e = es[k];
     if (e.nrow == 0 || e.nalpha == 0) continue;
-    const double* V = with_source ? h.src[set][L].p + e.offset : nullptr;
+    const T* V = nullptr;
+    if (with_source) {
+      if (sizeof(T) != sizeof(double)) throw DevError(CASPT2_E_ARG, "source only in FP64");
+      V = reinterpret_cast<const T*>(h.src[set][L].p) + e.offset;
+    }
     hipEvent_t ev = nullptr;
     // '+' and '-' entries of a block with nalpha <= 4 share one streaming launch
     if (e.nalpha <= 4 && k + 1 < es.size() && es[k + 1].block == e.block && es[k + 1].nalpha == e.nalpha) {
       auto& e2 = es[k + 1];
       prof_begin(h, &ev);
-      HIPCHECK(residual_rows_f64((int)e.nalpha, e.nrow, e2.nrow, x + e.offset, e.S.p, e.F.p,
-                                 e2.nrow ? e2.S.p : nullptr, e2.nrow ? e2.F.p : nullptr, e.eps.p,
-                                 e2.nrow ? e2.eps.p : nullptr, dshift, V, sig + e.offset, h.s));
-      prof_end(h, (int)k, (with_source ? 3.0 : 2.0) * 8.0 * (double)(e.nrow + e2.nrow) * e.nalpha, ev);
+      HIPCHECK(residual_rows<T>((int)e.nalpha, e.nrow, e2.nrow, x + e.offset, Sel<T>::S(e), Sel<T>::F(e),
+                                e2.nrow ? Sel<T>::S(e2) : nullptr, e2.nrow ? Sel<T>::F(e2) : nullptr,
+                                Sel<T>::eps(e), e2.nrow ? Sel<T>::eps(e2) : nullptr, (T)dshift, V,
+                                sig + e.offset, h.s));
+      prof_end(h, (int)k, (with_source ? 3.0 : 2.0) * esz * (double)(e.nrow + e2.nrow) * e.nalpha, ev);
       ++k;
       continue;
     }
     prof_begin(h, &ev);
     if (e.nalpha <= 4)
-      HIPCHECK(residual_rows_f64((int)e.nalpha, e.nrow, 0, x + e.offset, e.S.p, e.F.p, nullptr,
-                                 nullptr, e.eps.p, nullptr, dshift, V, sig + e.offset, h.s));
+      HIPCHECK(residual_rows<T>((int)e.nalpha, e.nrow, 0, x + e.offset, Sel<T>::S(e), Sel<T>::F(e), nullptr,
+                                nullptr, Sel<T>::eps(e), nullptr, (T)dshift, V, sig + e.offset, h.s));
     else if (e.nalpha <= 64)
-      HIPCHECK(residual_small_f64(e.nrow, e.nalpha, x + e.offset, e.S.p, e.F.p, e.eps.p, dshift, V,
-                                  sig + e.offset, h.s));
+      HIPCHECK(residual_small_t(e.nrow, e.nalpha, x + e.offset, Sel<T>::S(e), Sel<T>::F(e), Sel<T>::eps(e),
+                                dshift, V, sig + e.offset, h.s));
     else
-      HIPCHECK(residual_gemm_f64(e.nrow, e.nalpha, e.nalpha, x + e.offset, e.nalpha, e.S.p, e.F.p,
-                                 e.eps.p, dshift, V, e.nalpha, sig + e.offset, e.nalpha, h.s));
-    prof_end(h, (int)k, (with_source ? 3.0 : 2.0) * 8.0 * (double)e.nrow * e.nalpha, ev);
+      HIPCHECK(residual_gemm_t(e.nrow, e.nalpha, x + e.offset, Sel<T>::S(e), Sel<T>::F(e), Sel<T>::eps(e),
+                               dshift, V, sig + e.offset, h.s));
+    prof_end(h, (int)k, (with_source ? 3.0 : 2.0) * esz * (double)e.nrow * e.nalpha, ev);
   }
   if (!h.couple.empty() && !h.couple[set].empty()) {
     hipEvent_t ev = nullptr;
     prof_begin(h, &ev);
-    apply_couplings(h, set, x, sig);
+    apply_couplings<T>(h, set, x, sig);
     prof_end(h, (int)es.size(), 0.0, ev);   // pseudo entry: all couplings
   }
 }
 
-void to_orth(H& h, int set, const double* v, double* o) {
+// packed -> orthonormal kept basis of every entry: o = v X (Sec. II.B)
+template <typename T>
+void to_orth(H& h, int set, const T* v, T* o) {
   for (auto& e : h.sets[set]) {
     if (e.nrow == 0 || e.nkeep == 0) continue;
-    HIPCHECK(gemm_f64(false, e.nrow, e.nkeep, e.nalpha, 1.0, v + e.offset, e.nalpha, 0, e.X.p,
-                      e.nkeep, 0, 0.0, o + e.ooff, e.nkeep, 0, 1, h.s));
+    if (e.nalpha <= 8)
+      HIPCHECK(transform_rows<T>(e.nrow, (int)e.nalpha, (int)e.nkeep, v + e.offset, Sel<T>::X(e),
+                                 (int)e.nkeep, 1, o + e.ooff, h.s));
+    else
+      HIPCHECK(gemm_t(false, e.nrow, e.nkeep, e.nalpha, 1.0, v + e.offset, e.nalpha, Sel<T>::X(e), e.nkeep,
+                      0.0, o + e.ooff, e.nkeep, h.s));
   }
 }
 
-void from_orth(H& h, int set, const double* o, double* v) {
+// orthonormal -> packed: v = o X^T
+template <typename T>
+void from_orth(H& h, int set, const T* o, T* v) {
   for (auto& e : h.sets[set]) {
     if (e.nrow == 0 || e.nalpha == 0) continue;
     if (e.nkeep == 0) {
       HIPCHECK(vec_fill(e.nrow * e.nalpha, 0.0, v + e.offset, h.s));
       continue;
     }
-    HIPCHECK(gemm_f64(true, e.nrow, e.nalpha, e.nkeep, 1.0, o + e.ooff, e.nkeep, 0, e.X.p, e.nkeep,
-                      0, 0.0, v + e.offset, e.nalpha, 0, 1, h.s));
+    if (e.nalpha <= 8)
+      HIPCHECK(transform_rows<T>(e.nrow, (int)e.nkeep, (int)e.nalpha, o + e.ooff, Sel<T>::X(e), 1,
+                                 (int)e.nkeep, v + e.offset, h.s));
+    else
+      HIPCHECK(gemm_t(true, e.nrow, e.nalpha, e.nkeep, 1.0, o + e.ooff, e.nkeep, Sel<T>::X(e), e.nkeep, 0.0,
+                      v + e.offset, e.nalpha, h.s));
   }
 }
 
@@ -1124,7 +1208,8 @@ int64_t olen(const H& h, int set) {
   return n;
 }
 
-double ddot(H& h, int64_t n, const double* x, const double* y) {
+template <typename T>
+double ddot(H& h, int64_t n, const T* x, const T* y) {
   HIPCHECK(vec_dot(n, x, y, h.red_partial.p, h.red_out.p, h.s));
   return dev_scalar(h, h.red_out.p);
 }
@@ -1207,6 +1292,117 @@ int pcg(H& h, int L, const double* b_orth, double tol, int maxiter, DBuf& t, cas
   return rn <= tol ? CASPT2_OK : CASPT2_E_NOCONV;
 }
 
+// Mixed precision: FP64 iterative refinement around an FP32 PCG.  The outer
+// loop keeps t and the true residual r = -b - A t in FP64 (FP64 operator);
+// each inner solve runs PCG on A d = r / |r| entirely in FP32 (operator,
+// transforms, couplings, vectors; dot products accumulated in FP64) until
+// its residual drops by inner_tol, then t += |r| d.  The converged t meets
+// the same FP64 residual tolerance as pcg(); the inputs (sources, metrics,
+// bases, denominators) are the FP64 ones, rounded once for the inner solve.
+int pcg_mixed(H& h, int L, const double* b_orth, double tol, int maxiter, DBuf& t, caspt2_info& info) {
+  const int set = set_of(h, L);
+  const int64_t n = olen(h, set);
+  DBuf D;
+  double dmin;
+  build_denoms(h, L, D, &dmin);
+  info.min_denom = dmin;
+  info.e0 = h.e0[L];
+  info.emin_kept = INFINITY;
+  info.emax_dropped = -1.0;
+  for (auto& e : h.sets[set]) {
+    info.emin_kept = std::min(info.emin_kept, e.emin_kept);
+    info.emax_dropped = std::max(info.emax_dropped, e.emax_dropped);
+  }
+  if (!(dmin > 0.0)) return CASPT2_E_INDEFINITE;
+  const double inner_tol = 1e-5;   // relative reduction per inner solve
+  const int inner_cap = 200;       // FP32 iterations per inner solve
+  t.alloc(n);
+  t.zero(h.s);
+  FBuf D32(n), r32(n), z32(n), p32(n), q32(n), d32(n), x32(h.length), s32(h.length);
+  DBuf r(n), Ap(n), x(h.length), sg(h.length);
+  HIPCHECK(vec_scale_copy(n, 1.0, D.p, D32.p, h.s));
+  HIPCHECK(vec_scale_copy(n, -1.0, b_orth, r.p, h.s));
+  double rn = std::sqrt(ddot(h, n, r.p, r.p));
+  int inner = 0, outer = 0;
+  while (rn > tol && inner < maxiter) {
+    HIPCHECK(vec_scale_copy(n, 1.0 / rn, r.p, r32.p, h.s));
+    HIPCHECK(vec_fill(n, 0.0, d32.p, h.s));
+    HIPCHECK(vec_div(n, r32.p, D32.p, z32.p, h.s));
+    HIPCHECK(hipMemcpyAsync(p32.p, z32.p, n * sizeof(float), hipMemcpyDeviceToDevice, h.s));
+    double rz = ddot(h, n, r32.p, z32.p);
+    double rin = std::sqrt(ddot(h, n, r32.p, r32.p));
+    const double goal = std::max(inner_tol, 0.5 * tol / rn);
+    int k = 0;
+    while (rin > goal && inner < maxiter && k < inner_cap) {
+      from_orth(h, set, (const float*)p32.p, x32.p);
+      residual(h, L, (const float*)x32.p, s32.p, false);
+      to_orth(h, set, (const float*)s32.p, q32.p);
+      const double pAp = ddot(h, n, p32.p, q32.p);
+      if (!(pAp > 0.0)) {
+        info.iters = inner;
+        info.refinements = outer;
+        info.resnorm = rn;
+        return CASPT2_E_INDEFINITE;
+      }
+      const double alpha = rz / pAp;
+      HIPCHECK(vec_axpy(n, alpha, p32.p, d32.p, h.s));
+      HIPCHECK(vec_axpy(n, -alpha, q32.p, r32.p, h.s));
+      rin = std::sqrt(ddot(h, n, r32.p, r32.p));
+      HIPCHECK(vec_div(n, r32.p, D32.p, z32.p, h.s));
+      const double rz2 = ddot(h, n, r32.p, z32.p);
+      HIPCHECK(vec_xpay(n, z32.p, rz2 / rz, p32.p, h.s));
+      rz = rz2;
+      ++inner;
+      ++k;
+    }
+    HIPCHECK(vec_axpy(n, rn, d32.p, t.p, h.s));   // t += |r| d (FP32 d widened)
+    // true residual in FP64
+    from_orth(h, set, (const double*)t.p, x.p);
+    residual(h, L, (const double*)x.p, sg.p, false);
+    to_orth(h, set, (const double*)sg.p, Ap.p);
+    HIPCHECK(vec_scale_copy(n, -1.0, b_orth, r.p, h.s));
+    HIPCHECK(vec_axpy(n, -1.0, Ap.p, r.p, h.s));
+    const double rn_new = std::sqrt(ddot(h, n, r.p, r.p));
+    ++outer;
+    if (!(rn_new < rn)) {   // refinement no longer reduces the FP64 residual
+      rn = rn_new;
+      break;
+    }
+    rn = rn_new;
+  }
+  info.iters = inner;
+  info.refinements = outer;
+  info.resnorm = rn;
+  info.flags = rn <= tol ? 1 : 0;
+  return rn <= tol ? CASPT2_OK : CASPT2_E_NOCONV;
+}
+
+// FP32 copies of the operands of the inner solver (mixed precision)
+void setup_mixed(H& h) {
+  for (auto& es : h.sets)
+    for (auto& e : es) {
+      auto cast = [&](const DBuf& src, FBuf& dst) {
+        dst.alloc(src.n);
+        HIPCHECK(vec_scale_copy(src.n, 1.0, src.p, dst.p, h.s));
+      };
+      cast(e.S, e.S32);
+      cast(e.F, e.F32);
+      cast(e.X, e.X32);
+      cast(e.eps, e.eps32);
+    }
+  for (auto& cs : h.couple)
+    for (auto& t : cs) {
+      t.G32.alloc(t.G.n);
+      HIPCHECK(vec_scale_copy(t.G.n, 1.0, t.G.p, t.G32.p, h.s));
+    }
+}
+
+int solve_pcg(H& h, int L, const double* b_orth, double tol, int maxiter, DBuf& t, caspt2_info& info) {
+  info.refinements = 0;
+  if (h.d.precision == CASPT2_MIXED) return pcg_mixed(h, L, b_orth, tol, maxiter, t, info);
+  return pcg(h, L, b_orth, tol, maxiter, t, info);
+}
+
 void validate(const caspt2_dims* d, const std::vector<double>& f, const std::vector<double>& hc,
               int nmo, int nc, int na) {
   auto bad = [](const char* m) { throw DevError(CASPT2_E_ARG, m); };
@@ -1279,7 +1475,7 @@ int caspt2_create(const caspt2_dims* dims, const caspt2_inputs* in, int on_devic
     if (h.nc < 0 || h.na < 0 || h.nv < 0 || h.naux <= 0 || h.nst <= 0 || h.nst > 16 ||
         h.nmo <= 0 || dims->nelec < 0 || dims->nelec > 2 * h.na ||
         (dims->scheme != CASPT2_MSMR && dims->scheme != CASPT2_SSSR) ||
-        dims->precision != CASPT2_FP64 || !(dims->ovl_thresh > 0.0) || !std::isfinite(dims->shift))
+        (dims->precision != CASPT2_FP64 && dims->precision != CASPT2_MIXED) || !(dims->ovl_thresh > 0.0) || !std::isfinite(dims->shift))
       throw DevError(CASPT2_E_ARG, "bad dimensions");
     if (!in->fock || !in->hcore || !in->dfB || !in->ci || !in->eref)
       throw DevError(CASPT2_E_ARG, "null input");
@@ -1388,6 +1584,7 @@ int caspt2_create(const caspt2_dims* dims, const caspt2_inputs* in, int on_devic
     setup_blocks(h);
     setup_sources(h);
     setup_couplings(h);
+    if (dims->precision == CASPT2_MIXED) setup_mixed(h);
     h.eri.clear();
     host_sync(h);
     *out = hp.release();
@@ -1483,7 +1680,7 @@ int caspt2_solve_amplitudes(caspt2_handle* h, double tol, int32_t maxiter, caspt
       const int set = set_of(hh, L);
       DBuf b(olen(hh, set)), t;
       to_orth(hh, set, hh.src[set][L].p, b.p);
-      const int rc = pcg(hh, L, b.p, tol, maxiter, t, hh.tinfo[L]);
+      const int rc = solve_pcg(hh, L, b.p, tol, maxiter, t, hh.tinfo[L]);
       if (rc == CASPT2_E_INDEFINITE) return rc;
       if (rc != CASPT2_OK) status = rc;
       DBuf T(hh.length);
@@ -1572,7 +1769,7 @@ int caspt2_solve_lambda(caspt2_handle* h, int32_t P, double tol, int32_t maxiter
       }
       HIPCHECK(vec_axpy(n, -2.0 * hh.d.shift * hh.R[L * nst + P] * hh.R[L * nst + P], hh.Tt[L].p,
                         b.p, hh.s));
-      const int rc = pcg(hh, L, b.p, tol, maxiter, t, hh.linfo[L]);
+      const int rc = solve_pcg(hh, L, b.p, tol, maxiter, t, hh.linfo[L]);
       if (rc == CASPT2_E_INDEFINITE) return rc;
       if (rc != CASPT2_OK) status = rc;
       DBuf lam(hh.length);
@@ -1609,6 +1806,16 @@ int caspt2_debug_gemm(int32_t b_is_nk, int64_t M, int64_t N, int64_t K, const do
                       const double* B, double* C) {
   ABI_GUARD({
     HIPCHECK(gemm_f64(b_is_nk != 0, M, N, K, 1.0, A, K, 0, B, b_is_nk ? K : N, 0, 0.0, C, N, 0, 1,
+                      nullptr));
+    HIPCHECK(hipStreamSynchronize(nullptr));
+    return CASPT2_OK;
+  })
+}
+
+int caspt2_debug_gemm_f32(int32_t b_is_nk, int64_t M, int64_t N, int64_t K, const float* A,
+                          const float* B, float* C) {
+  ABI_GUARD({
+    HIPCHECK(gemm_f32(b_is_nk != 0, M, N, K, 1.f, A, K, 0, B, b_is_nk ? K : N, 0, 0.f, C, N, 0, 1,
                       nullptr));
     HIPCHECK(hipStreamSynchronize(nullptr));
     return CASPT2_OK;

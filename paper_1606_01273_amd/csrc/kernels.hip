@@ -12,6 +12,17 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 
 static inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
+// grid of tiles: the dimension with more tiles on x; false when neither
+// orientation fits the 65535 limit of grid y and z
+static inline bool tile_grid(int64_t M, int64_t N, int batch, int tm, int tn, dim3* grid, int* m_on_x) {
+  const int64_t tmn = (M + tm - 1) / tm, tnn = (N + tn - 1) / tn;
+  *m_on_x = tmn >= tnn ? 1 : 0;
+  const int64_t gx = *m_on_x ? tmn : tnn, gy = *m_on_x ? tnn : tmn;
+  if (gy > 65535 || batch > 65535 || gx > 0x7fffffff) return false;
+  *grid = dim3((unsigned)gx, (unsigned)gy, (unsigned)batch);
+  return true;
+}
+
 // ---------------------------------------------------------------------------
 // operator application: Y[r][lead][t] = sign[r][t] * X[lead][src[r][t]]
 // ---------------------------------------------------------------------------
@@ -59,7 +70,8 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int64_t M, int64_t N, int64_t 
                                                   const double* __restrict__ B2, double beta,
                                                   double* __restrict__ C, int64_t ldc, int64_t sC,
                                                   const double* __restrict__ dvec, double dshift,
-                                                  const double* __restrict__ V, int64_t ldv) {
+                                                  const double* __restrict__ V, int64_t ldv,
+                                                  int m_on_x) {
   __shared__ double As[BM][LDP];
   __shared__ double Bs[BN][LDP];
   __shared__ double B2s[DUAL ? BN : 1][LDP];
@@ -71,8 +83,9 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int64_t M, int64_t N, int64_t 
   A += bz * sA;
   B += bz * sB;
   C += bz * sC;
-  const int64_t m0 = (int64_t)blockIdx.y * BM;
-  const int64_t n0 = (int64_t)blockIdx.x * BN;
+  // the longer tile dimension runs on grid x (y and z are limited to 65535)
+  const int64_t m0 = (int64_t)(m_on_x ? blockIdx.x : blockIdx.y) * BM;
+  const int64_t n0 = (int64_t)(m_on_x ? blockIdx.y : blockIdx.x) * BN;
   d4 acc[2][2], acc2[2][2];
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j) {
@@ -146,15 +159,17 @@ hipError_t gemm_f64(bool b_is_nk, int64_t M, int64_t N, int64_t K, double alpha,
                     int64_t lda, int64_t sA, const double* B, int64_t ldb, int64_t sB, double beta,
                     double* C, int64_t ldc, int64_t sC, int batch, hipStream_t s) {
   if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
-  dim3 grid(cdiv(N, BN), cdiv(M, BM), batch);
+  dim3 grid;
+  int mx;
+  if (!tile_grid(M, N, batch, BM, BN, &grid, &mx)) return hipErrorInvalidValue;
   if (b_is_nk)
     hipLaunchKernelGGL((k_gemm_f64<true, false>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda,
                        sA, B, ldb, sB, (const double*)nullptr, beta, C, ldc, sC,
-                       (const double*)nullptr, 0.0, (const double*)nullptr, (int64_t)0);
+                       (const double*)nullptr, 0.0, (const double*)nullptr, (int64_t)0, mx);
   else
     hipLaunchKernelGGL((k_gemm_f64<false, false>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda,
                        sA, B, ldb, sB, (const double*)nullptr, beta, C, ldc, sC,
-                       (const double*)nullptr, 0.0, (const double*)nullptr, (int64_t)0);
+                       (const double*)nullptr, 0.0, (const double*)nullptr, (int64_t)0, mx);
   return hipGetLastError();
 }
 
@@ -162,9 +177,11 @@ hipError_t residual_gemm_f64(int64_t M, int64_t N, int64_t K, const double* X, i
                              const double* S, const double* F, const double* d, double dshift,
                              const double* V, int64_t ldv, double* C, int64_t ldc, hipStream_t s) {
   if (M <= 0 || N <= 0) return hipSuccess;
-  dim3 grid(cdiv(N, BN), cdiv(M, BM), 1);
+  dim3 grid;
+  int mx;
+  if (!tile_grid(M, N, 1, BM, BN, &grid, &mx)) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_gemm_f64<false, true>), grid, dim3(256), 0, s, M, N, K, 1.0, X, ldx,
-                     (int64_t)0, S, N, (int64_t)0, F, 0.0, C, ldc, (int64_t)0, d, dshift, V, ldv);
+                     (int64_t)0, S, N, (int64_t)0, F, 0.0, C, ldc, (int64_t)0, d, dshift, V, ldv, mx);
   return hipGetLastError();
 }
 
@@ -172,14 +189,15 @@ hipError_t residual_gemm_f64(int64_t M, int64_t N, int64_t K, const double* X, i
 // streaming residual for small alpha dimension (K = N <= 64):
 //   C[m][n] = V[m][n] + (d[m] + dshift) * sum_k X[m][k] S[k][n] + sum_k X[m][k] F[k][n]
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_residual_small(int64_t M, int N, const double* __restrict__ X,
-                                                        const double* __restrict__ S,
-                                                        const double* __restrict__ F,
-                                                        const double* __restrict__ d, double dshift,
-                                                        const double* __restrict__ V,
-                                                        double* __restrict__ C) {
-  __shared__ double Ss[64 * 64];
-  __shared__ double Fs[64 * 64];
+template <typename T>
+__global__ __launch_bounds__(256) void k_residual_small(int64_t M, int N, const T* __restrict__ X,
+                                                        const T* __restrict__ S,
+                                                        const T* __restrict__ F,
+                                                        const T* __restrict__ d, T dshift,
+                                                        const T* __restrict__ V,
+                                                        T* __restrict__ C) {
+  __shared__ T Ss[64 * 64];
+  __shared__ T Fs[64 * 64];
   for (int i = threadIdx.x; i < N * N; i += blockDim.x) {
     Ss[i] = S[i];
     Fs[i] = F[i];
@@ -190,14 +208,14 @@ __global__ __launch_bounds__(256) void k_residual_small(int64_t M, int N, const 
        g += (int64_t)gridDim.x * blockDim.x) {
     const int64_t m = g / N;
     const int n = (int)(g % N);
-    const double* x = X + m * N;
-    double as = 0.0, af = 0.0;
+    const T* x = X + m * N;
+    T as = 0, af = 0;
     for (int k = 0; k < N; ++k) {
-      const double xv = x[k];
+      const T xv = x[k];
       as += xv * Ss[k * N + n];
       af += xv * Fs[k * N + n];
     }
-    double val = (d[m] + dshift) * as + af;
+    T val = (d[m] + dshift) * as + af;
     if (V) val += V[g];
     C[g] = val;
   }
@@ -286,8 +304,20 @@ hipError_t residual_small_f64(int64_t M, int64_t N, const double* X, const doubl
   }
   unsigned grid = cdiv(M * N, 256);
   if (grid > 65536) grid = 65536;
-  hipLaunchKernelGGL(k_residual_small, dim3(grid), dim3(256), 0, s, M, (int)N, X, S, F, d, dshift,
-                     V, C);
+  hipLaunchKernelGGL(k_residual_small<double>, dim3(grid), dim3(256), 0, s, M, (int)N, X, S, F, d,
+                     dshift, V, C);
+  return hipGetLastError();
+}
+
+hipError_t residual_small_f32(int64_t M, int64_t N, const float* X, const float* S, const float* F,
+                              const float* d, float dshift, const float* V, float* C,
+                              hipStream_t s) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  if (N > 64) return hipErrorInvalidValue;
+  unsigned grid = cdiv(M * N, 256);
+  if (grid > 65536) grid = 65536;
+  hipLaunchKernelGGL(k_residual_small<float>, dim3(grid), dim3(256), 0, s, M, (int)N, X, S, F, d,
+                     dshift, V, C);
   return hipGetLastError();
 }
 
@@ -297,36 +327,36 @@ hipError_t residual_small_f64(int64_t M, int64_t N, const double* X, const doubl
 //   C[m][n] = V[m][n] + (d[m] + dshift) sum_k X[m][k] S_c[k][n] + sum_k X[m][k] F_c[k][n]
 // S_c, F_c are NST x NST (kept in registers); one thread per row.
 // ---------------------------------------------------------------------------
-template <int NST>
+template <typename T, int NST>
 __global__ __launch_bounds__(256) void k_residual_rows(int64_t M0, int64_t M1,
-                                                       const double* __restrict__ X,
-                                                       const double* __restrict__ S0,
-                                                       const double* __restrict__ F0,
-                                                       const double* __restrict__ S1,
-                                                       const double* __restrict__ F1,
-                                                       const double* __restrict__ d0,
-                                                       const double* __restrict__ d1, double dshift,
-                                                       const double* __restrict__ V,
-                                                       double* __restrict__ C) {
-  double s0[NST * NST], f0[NST * NST], s1[NST * NST], f1[NST * NST];
+                                                       const T* __restrict__ X,
+                                                       const T* __restrict__ S0,
+                                                       const T* __restrict__ F0,
+                                                       const T* __restrict__ S1,
+                                                       const T* __restrict__ F1,
+                                                       const T* __restrict__ d0,
+                                                       const T* __restrict__ d1, T dshift,
+                                                       const T* __restrict__ V,
+                                                       T* __restrict__ C) {
+  T s0[NST * NST], f0[NST * NST], s1[NST * NST], f1[NST * NST];
 #pragma unroll
   for (int i = 0; i < NST * NST; ++i) {
     s0[i] = S0[i];
     f0[i] = F0[i];
-    s1[i] = S1 ? S1[i] : 0.0;
-    f1[i] = F1 ? F1[i] : 0.0;
+    s1[i] = S1 ? S1[i] : T(0);
+    f1[i] = F1 ? F1[i] : T(0);
   }
   const int64_t total = M0 + M1;
   for (int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; m < total;
        m += (int64_t)gridDim.x * blockDim.x) {
     const bool second = m >= M0;
-    const double r = (second ? d1[m - M0] : d0[m]) + dshift;
-    double x[NST], out[NST];
+    const T r = (second ? d1[m - M0] : d0[m]) + dshift;
+    T x[NST], out[NST];
 #pragma unroll
     for (int k = 0; k < NST; ++k) x[k] = X[m * NST + k];
 #pragma unroll
     for (int n = 0; n < NST; ++n) {
-      double as = 0.0, af = 0.0;
+      T as = 0, af = 0;
 #pragma unroll
       for (int k = 0; k < NST; ++k) {
         as += x[k] * (second ? s1[k * NST + n] : s0[k * NST + n]);
@@ -343,10 +373,10 @@ __global__ __launch_bounds__(256) void k_residual_rows(int64_t M0, int64_t M1,
   }
 }
 
-hipError_t residual_rows_f64(int nst, int64_t M0, int64_t M1, const double* X, const double* S0,
-                             const double* F0, const double* S1, const double* F1, const double* d0,
-                             const double* d1, double dshift, const double* V, double* C,
-                             hipStream_t s) {
+template <typename T>
+hipError_t residual_rows(int nst, int64_t M0, int64_t M1, const T* X, const T* S0, const T* F0,
+                         const T* S1, const T* F1, const T* d0, const T* d1, T dshift, const T* V,
+                         T* C, hipStream_t s) {
   const int64_t total = M0 + M1;
   if (total <= 0) return hipSuccess;
   unsigned grid = cdiv(total, 256);
@@ -354,7 +384,7 @@ hipError_t residual_rows_f64(int nst, int64_t M0, int64_t M1, const double* X, c
   switch (nst) {
 #define CASPT2_ROWS(NS)                                                                        \
   case NS:                                                                                     \
-    hipLaunchKernelGGL(k_residual_rows<NS>, dim3(grid), dim3(256), 0, s, M0, M1, X, S0, F0, S1, \
+    hipLaunchKernelGGL((k_residual_rows<T, NS>), dim3(grid), dim3(256), 0, s, M0, M1, X, S0, F0, S1, \
                        F1, d0, d1, dshift, V, C);                                              \
     break;
     CASPT2_ROWS(1)
@@ -371,6 +401,61 @@ hipError_t residual_rows_f64(int nst, int64_t M0, int64_t M1, const double* X, c
 // ---------------------------------------------------------------------------
 // permuted accumulate and leading contraction
 // ---------------------------------------------------------------------------
+template hipError_t residual_rows<double>(int, int64_t, int64_t, const double*, const double*,
+                                          const double*, const double*, const double*,
+                                          const double*, const double*, double, const double*,
+                                          double*, hipStream_t);
+template hipError_t residual_rows<float>(int, int64_t, int64_t, const float*, const float*,
+                                         const float*, const float*, const float*, const float*,
+                                         const float*, float, const float*, float*, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// row transform for narrow rows (nin, nout <= 8), one thread per row:
+//   out[m][j] = sum_i in[m][i] W[i * ws_in + j * ws_out]
+// (the basis transforms of the entries with few active columns, streaming)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_transform_rows(int64_t M, int nin, int nout,
+                                                        const T* __restrict__ in,
+                                                        const T* __restrict__ W, int ws_in,
+                                                        int ws_out, T* __restrict__ out) {
+  T w[8][8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) w[i][j] = (i < nin && j < nout) ? W[i * ws_in + j * ws_out] : T(0);
+  for (int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; m < M;
+       m += (int64_t)gridDim.x * blockDim.x) {
+    T x[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) x[i] = i < nin ? in[m * nin + i] : T(0);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      if (j >= nout) break;
+      T acc = 0;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) acc += x[i] * w[i][j];
+      out[m * nout + j] = acc;
+    }
+  }
+}
+
+template <typename T>
+hipError_t transform_rows(int64_t M, int nin, int nout, const T* in, const T* W, int ws_in,
+                          int ws_out, T* out, hipStream_t s) {
+  if (M <= 0 || nout <= 0) return hipSuccess;
+  if (nin < 0 || nin > 8 || nout > 8) return hipErrorInvalidValue;
+  unsigned grid = cdiv(M, 256);
+  if (grid > 8192) grid = 8192;
+  hipLaunchKernelGGL(k_transform_rows<T>, dim3(grid), dim3(256), 0, s, M, nin, nout, in, W, ws_in,
+                     ws_out, out);
+  return hipGetLastError();
+}
+template hipError_t transform_rows<double>(int64_t, int, int, const double*, const double*, int,
+                                           int, double*, hipStream_t);
+template hipError_t transform_rows<float>(int64_t, int, int, const float*, const float*, int, int,
+                                          float*, hipStream_t);
+
 struct PermArgs {
   int nd;
   int64_t dims[10];
@@ -787,13 +872,14 @@ hipError_t jacobi_eigh(int n, double* A, double* V, double* ws, int max_sweeps, 
 // ---------------------------------------------------------------------------
 // vectors
 // ---------------------------------------------------------------------------
-__global__ void k_dot_partial(int64_t n, const double* __restrict__ x, const double* __restrict__ y,
+template <typename T>
+__global__ void k_dot_partial(int64_t n, const T* __restrict__ x, const T* __restrict__ y,
                               double* __restrict__ partial) {
   __shared__ double sh[256];
   double acc = 0.0;
   for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n;
        g += (int64_t)gridDim.x * blockDim.x)
-    acc += x[g] * y[g];
+    acc += (double)x[g] * (double)y[g];
   sh[threadIdx.x] = acc;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
@@ -816,14 +902,19 @@ __global__ void k_sum_final(int np, const double* __restrict__ partial, double* 
   if (threadIdx.x == 0) out[0] = sh[0];
 }
 
-hipError_t vec_dot(int64_t n, const double* x, const double* y, double* partial, double* out,
-                   hipStream_t s) {
-  // fixed grid so the summation order is the same on every call
+// FP64 accumulation for either element type; fixed grid so the summation
+// order is the same on every call
+template <typename T>
+hipError_t vec_dot(int64_t n, const T* x, const T* y, double* partial, double* out, hipStream_t s) {
   const int nb = 1024;
-  hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(256), 0, s, n, x, y, partial);
+  hipLaunchKernelGGL(k_dot_partial<T>, dim3(nb), dim3(256), 0, s, n, x, y, partial);
   hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, s, nb, partial, out);
   return hipGetLastError();
 }
+template hipError_t vec_dot<double>(int64_t, const double*, const double*, double*, double*,
+                                    hipStream_t);
+template hipError_t vec_dot<float>(int64_t, const float*, const float*, double*, double*,
+                                   hipStream_t);
 
 __global__ void k_min_partial(int64_t n, const double* __restrict__ x, double* __restrict__ partial) {
   __shared__ double sh[256];
@@ -860,53 +951,74 @@ hipError_t vec_min(int64_t n, const double* x, double* partial, double* out, hip
   return hipGetLastError();
 }
 
+// element-wise kernels; X is the input element type, Y the output one
 #define CASPT2_ELEMENTWISE(NAME, EXPR)                                                        \
-  __global__ void k_##NAME(int64_t n, double a, const double* __restrict__ x,                \
-                           const double* __restrict__ d, double* __restrict__ y) {           \
+  template <typename X, typename Y>                                                          \
+  __global__ void k_##NAME(int64_t n, double a, const X* __restrict__ x,                     \
+                           const Y* __restrict__ d, Y* __restrict__ y) {                     \
     for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n;                 \
          g += (int64_t)gridDim.x * blockDim.x) {                                             \
       EXPR;                                                                                  \
     }                                                                                        \
   }
 
-CASPT2_ELEMENTWISE(axpy, y[g] += a * x[g])
-CASPT2_ELEMENTWISE(xpay, y[g] = x[g] + a * y[g])
+CASPT2_ELEMENTWISE(axpy, y[g] += (Y)(a * x[g]))
+CASPT2_ELEMENTWISE(xpay, y[g] = x[g] + (Y)a * y[g])
 CASPT2_ELEMENTWISE(div, y[g] = x[g] / d[g])
-CASPT2_ELEMENTWISE(scale_copy, y[g] = a * x[g])
-CASPT2_ELEMENTWISE(fill, y[g] = a)
+CASPT2_ELEMENTWISE(scale_copy, y[g] = (Y)(a * x[g]))
+CASPT2_ELEMENTWISE(fill, y[g] = (Y)a)
 
 static inline unsigned egrid(int64_t n) {
   unsigned g = cdiv(n, 256);
   return g > 65536 ? 65536 : (g == 0 ? 1 : g);
 }
 
-hipError_t vec_axpy(int64_t n, double a, const double* x, double* y, hipStream_t s) {
+template <typename X, typename Y>
+hipError_t vec_axpy(int64_t n, double a, const X* x, Y* y, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_axpy, dim3(egrid(n)), dim3(256), 0, s, n, a, x, (const double*)nullptr, y);
+  hipLaunchKernelGGL((k_axpy<X, Y>), dim3(egrid(n)), dim3(256), 0, s, n, a, x, (const Y*)nullptr, y);
   return hipGetLastError();
 }
-hipError_t vec_xpay(int64_t n, const double* x, double a, double* y, hipStream_t s) {
+template <typename T>
+hipError_t vec_xpay(int64_t n, const T* x, double a, T* y, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_xpay, dim3(egrid(n)), dim3(256), 0, s, n, a, x, (const double*)nullptr, y);
+  hipLaunchKernelGGL((k_xpay<T, T>), dim3(egrid(n)), dim3(256), 0, s, n, a, x, (const T*)nullptr, y);
   return hipGetLastError();
 }
-hipError_t vec_div(int64_t n, const double* x, const double* d, double* y, hipStream_t s) {
+template <typename T>
+hipError_t vec_div(int64_t n, const T* x, const T* d, T* y, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_div, dim3(egrid(n)), dim3(256), 0, s, n, 0.0, x, d, y);
+  hipLaunchKernelGGL((k_div<T, T>), dim3(egrid(n)), dim3(256), 0, s, n, 0.0, x, d, y);
   return hipGetLastError();
 }
-hipError_t vec_scale_copy(int64_t n, double a, const double* x, double* y, hipStream_t s) {
+template <typename X, typename Y>
+hipError_t vec_scale_copy(int64_t n, double a, const X* x, Y* y, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_scale_copy, dim3(egrid(n)), dim3(256), 0, s, n, a, x, (const double*)nullptr,
+  hipLaunchKernelGGL((k_scale_copy<X, Y>), dim3(egrid(n)), dim3(256), 0, s, n, a, x, (const Y*)nullptr,
                      y);
   return hipGetLastError();
 }
-hipError_t vec_fill(int64_t n, double v, double* y, hipStream_t s) {
+template <typename T>
+hipError_t vec_fill(int64_t n, double v, T* y, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fill, dim3(egrid(n)), dim3(256), 0, s, n, v, (const double*)nullptr,
-                     (const double*)nullptr, y);
+  hipLaunchKernelGGL((k_fill<T, T>), dim3(egrid(n)), dim3(256), 0, s, n, v, (const T*)nullptr,
+                     (const T*)nullptr, y);
   return hipGetLastError();
 }
+template hipError_t vec_axpy<double, double>(int64_t, double, const double*, double*, hipStream_t);
+template hipError_t vec_axpy<float, float>(int64_t, double, const float*, float*, hipStream_t);
+template hipError_t vec_axpy<float, double>(int64_t, double, const float*, double*, hipStream_t);
+template hipError_t vec_xpay<double>(int64_t, const double*, double, double*, hipStream_t);
+template hipError_t vec_xpay<float>(int64_t, const float*, double, float*, hipStream_t);
+template hipError_t vec_div<double>(int64_t, const double*, const double*, double*, hipStream_t);
+template hipError_t vec_div<float>(int64_t, const float*, const float*, float*, hipStream_t);
+template hipError_t vec_scale_copy<double, double>(int64_t, double, const double*, double*,
+                                                   hipStream_t);
+template hipError_t vec_scale_copy<double, float>(int64_t, double, const double*, float*,
+                                                  hipStream_t);
+template hipError_t vec_scale_copy<float, float>(int64_t, double, const float*, float*, hipStream_t);
+template hipError_t vec_fill<double>(int64_t, double, double*, hipStream_t);
+template hipError_t vec_fill<float>(int64_t, double, float*, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // small symmetric eigenproblem (n <= 16) on a single thread: cyclic Jacobi,

@@ -30,13 +30,34 @@ hipError_t residual_small_f64(int64_t M, int64_t N, const double* X, const doubl
                               const double* F, const double* d, double dshift, const double* V,
                               double* C, hipStream_t s);
 
+// FP32 form of residual_small_f64 for K = N <= 64 (SIMT, S and F in LDS).
+hipError_t residual_small_f32(int64_t M, int64_t N, const float* X, const float* S, const float* F,
+                              const float* d, float dshift, const float* V, float* C,
+                              hipStream_t s);
+
 // Streaming residual of two consecutive packed entries with nalpha = nst
 // (<= 4), e.g. ccvv '+' and '-': rows [0, M0) use (S0, F0, d0), rows
-// [M0, M0+M1) use (S1, F1, d1).  X, V, C are [M0+M1][nst].
-hipError_t residual_rows_f64(int nst, int64_t M0, int64_t M1, const double* X, const double* S0,
-                             const double* F0, const double* S1, const double* F1, const double* d0,
-                             const double* d1, double dshift, const double* V, double* C,
-                             hipStream_t s);
+// [M0, M0+M1) use (S1, F1, d1).  X, V, C are [M0+M1][nst].  T: double, float.
+template <typename T>
+hipError_t residual_rows(int nst, int64_t M0, int64_t M1, const T* X, const T* S0, const T* F0,
+                         const T* S1, const T* F1, const T* d0, const T* d1, T dshift, const T* V,
+                         T* C, hipStream_t s);
+
+// C = alpha * A * op(B) + beta * C in FP32 (SIMT FMA, 64 x 64 tiles); same
+// operand conventions as gemm_f64.
+hipError_t gemm_f32(bool b_is_nk, int64_t M, int64_t N, int64_t K, float alpha, const float* A,
+                    int64_t lda, int64_t sA, const float* B, int64_t ldb, int64_t sB, float beta,
+                    float* C, int64_t ldc, int64_t sC, int batch, hipStream_t s);
+// FP32 form of residual_gemm_f64.
+hipError_t residual_gemm_f32(int64_t M, int64_t N, int64_t K, const float* X, int64_t ldx,
+                             const float* S, const float* F, const float* d, float dshift,
+                             const float* V, int64_t ldv, float* C, int64_t ldc, hipStream_t s);
+
+// out[m][j] = sum_i in[m][i] W[i * ws_in + j * ws_out] for rows of nin <= 8
+// inputs and nout <= 8 outputs (in [M][nin], out [M][nout]).  T: double, float.
+template <typename T>
+hipError_t transform_rows(int64_t M, int nin, int nout, const T* in, const T* W, int ws_in,
+                          int ws_out, T* out, hipStream_t s);
 
 // dst[sum_k idx_k * dstride_k] += c * src[flat], src dims dims[0..nd)
 hipError_t permute_axpy(int nd, const int64_t* dims, const int64_t* dstride, double c,
@@ -142,14 +163,19 @@ hipError_t select_scale_cols(int64_t n, int64_t ncq, const double* Q, const int3
 hipError_t jacobi_eigh(int n, double* A, double* V, double* ws, int max_sweeps, double tol,
                        hipStream_t s, int* sweeps_done);
 
-// vector kernels
-hipError_t vec_dot(int64_t n, const double* x, const double* y, double* partial, double* out,
-                   hipStream_t s);  // out on device (1 double); partial >= 1024 doubles
-hipError_t vec_axpy(int64_t n, double a, const double* x, double* y, hipStream_t s);  // y += a x
-hipError_t vec_xpay(int64_t n, const double* x, double a, double* y, hipStream_t s);  // y = x + a y
-hipError_t vec_div(int64_t n, const double* x, const double* d, double* y, hipStream_t s);  // y = x/d
-hipError_t vec_scale_copy(int64_t n, double a, const double* x, double* y, hipStream_t s);  // y = a x
-hipError_t vec_fill(int64_t n, double v, double* y, hipStream_t s);
+// vector kernels (element types as instantiated in kernels.hip)
+template <typename T>  // FP64 accumulation; out on device (1 double); partial >= 1024 doubles
+hipError_t vec_dot(int64_t n, const T* x, const T* y, double* partial, double* out, hipStream_t s);
+template <typename X, typename Y>  // y += a x
+hipError_t vec_axpy(int64_t n, double a, const X* x, Y* y, hipStream_t s);
+template <typename T>  // y = x + a y
+hipError_t vec_xpay(int64_t n, const T* x, double a, T* y, hipStream_t s);
+template <typename T>  // y = x / d
+hipError_t vec_div(int64_t n, const T* x, const T* d, T* y, hipStream_t s);
+template <typename X, typename Y>  // y = a x (converting)
+hipError_t vec_scale_copy(int64_t n, double a, const X* x, Y* y, hipStream_t s);
+template <typename T>
+hipError_t vec_fill(int64_t n, double v, T* y, hipStream_t s);
 hipError_t vec_min(int64_t n, const double* x, double* partial, double* out, hipStream_t s);
 
 // small dense symmetric eigenproblem on one thread (n <= 16): A -> values w
