@@ -192,6 +192,24 @@ CASPT2_API int caspt2_solve_lambda(caspt2_handle* h, int32_t target, double tol,
                         caspt2_info* info);
 CASPT2_API int caspt2_get_lambda(caspt2_handle* h, int32_t L, double* lambda);
 
+/* Batched solves over many independent problems (each a handle created with
+ * CASPT2_FP64; the problems may differ in every dimension and state count).
+ * All amplitude systems (every state of every problem) advance in one
+ * grouped PCG with device-resident scalars and one captured HIP graph per
+ * system for the operator application; as soon as the amplitudes of a
+ * problem converge, its H_eff (Eqs. 15-17) is formed and its lambda systems
+ * (Eq. 20, target state targets[i]) join the running group, so amplitude and
+ * lambda solves of different problems interleave.  Results are stored in
+ * each handle as after caspt2_solve_amplitudes, xms_heff and
+ * caspt2_solve_lambda (read them with the per-handle getters).
+ * handles [n] (distinct), targets [n] host; amp_info and lambda_info host
+ * arrays of sum_i nstates_i entries (problem-major) or NULL.  Returns the
+ * first failure over the problems (E_INDEFINITE takes precedence, then
+ * E_NOCONV); a problem whose amplitude solve fails gets no lambda.
+ * E_NOTIMPL if a handle is not FP64. */
+CASPT2_API int caspt2_batch_solve(caspt2_handle* const* handles, int32_t n, const int32_t* targets, double tol,
+                                  int32_t maxiter, caspt2_info* amp_info, caspt2_info* lambda_info);
+
 /* Measurement support: enable (1) or disable (0) HIP-event timing of every
  * residual kernel launch (clears what was recorded), and read, per packed
  * layout entry k (0..12; the '+' entry also covers its '-' partner when both

@@ -13,7 +13,7 @@ from . import _lib
 from ._lib import (E_ARG, E_DEVICE, E_INDEFINITE, E_NOCONV, E_NOMEM, E_NOTIMPL, E_STATE, ENTRY_NAMES,
                    FP64, MIXED, MSMR, OK, SSSR, Caspt2Error)
 
-__all__ = ["Caspt2", "Caspt2Error", "lib", "MSMR", "SSSR", "FP64", "MIXED", "ENTRY_NAMES"]
+__all__ = ["Caspt2", "Caspt2Error", "batch_solve", "lib", "MSMR", "SSSR", "FP64", "MIXED", "ENTRY_NAMES"]
 
 _LIB = None
 
@@ -137,3 +137,24 @@ class Caspt2:
         t = torch.empty(self.length, dtype=torch.float64, device="cuda")
         _check(lib().caspt2_get_lambda(self._h, L, _ptr(t)), "caspt2_get_lambda")
         return t
+
+
+def batch_solve(problems, targets=None, tol=1e-10, maxiter=200):
+    """caspt2_batch_solve over a list of FP64 Caspt2 objects (distinct).
+    Returns (status, amplitude infos, lambda infos), one list per problem;
+    results are read afterwards from each object (amplitudes, heff, lam)."""
+    n = len(problems)
+    if targets is None:
+        targets = [0] * n
+    hs = (ctypes.c_void_p * n)(*[p._h.value for p in problems])
+    tg = (ctypes.c_int32 * n)(*targets)
+    tot = sum(p.nst for p in problems)
+    ai, li = (_lib.Info * tot)(), (_lib.Info * tot)()
+    rc = _check(lib().caspt2_batch_solve(hs, n, tg, tol, maxiter, ai, li), "caspt2_batch_solve",
+                allow=(OK, E_NOCONV, E_INDEFINITE))
+    out_a, out_l, k = [], [], 0
+    for p in problems:
+        out_a.append([ai[k + L].as_dict() for L in range(p.nst)])
+        out_l.append([li[k + L].as_dict() for L in range(p.nst)])
+        k += p.nst
+    return rc, out_a, out_l

@@ -62,6 +62,9 @@ SIGNATURES = {
     "caspt2_solve_lambda": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
                                            ctypes.POINTER(Info)]),
     "caspt2_get_lambda": (ctypes.c_int, [_P, ctypes.c_int32, _P]),
+    "caspt2_batch_solve": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                          ctypes.c_double, ctypes.c_int32, ctypes.POINTER(Info),
+                                          ctypes.POINTER(Info)]),
     "caspt2_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "caspt2_profile": (ctypes.c_int, [_P, ctypes.c_int32]),
     "caspt2_profile_entry": (ctypes.c_int, [_P, ctypes.c_int32, _D, ctypes.POINTER(ctypes.c_int64), _D]),

@@ -206,7 +206,9 @@ struct caspt2_handle {
   DBuf jws;
   std::vector<std::vector<struct CoupleTerm>> couple;  // per function set
   DBuf cscratch;                                       // W / Y of the couplings
+  DBuf wx, wsg;                                        // operator work vectors of the grouped solver
   DBuf xall[NBLOCK], sall[NBLOCK];                      // all-orderings x and sigma per block
+  bool direct[NBLOCK] = {};                            // ket read from packed rows (no all-orderings x)
   bool prof_on = false;
   bool verbose = false;
   int verbose_level = 0;
@@ -1027,13 +1029,73 @@ void setup_couplings(H& h) {
       }
       progress(h, "couplings " + B1.name + " <- " + B2.name);
     }
+  // merge terms that act identically (same blocks, index maps, Fock block
+  // and shapes): their active tensors add.  A ccvv ket is symmetric under the
+  // joint exchange (i, a) <-> (j, b) of its slots, so its slot map is first
+  // brought to a canonical form.
+  for (int set = 0; set < nsets; ++set) {
+    auto& cs = h.couple[set];
+    std::vector<CoupleTerm> merged;
+    std::map<std::vector<int64_t>, size_t> seen;
+    for (auto& t : cs) {
+      int* ks = t.d.ket_src;
+      if (!t.up && t.ket == CCVV && t.d.ket.nslot == 4) {
+        const int alt[4] = {ks[1], ks[0], ks[3], ks[2]};
+        if (std::lexicographical_compare(alt, alt + 4, ks, ks + 4)) std::copy(alt, alt + 4, ks);
+      }
+      // an up term into the ccvv bra and its image under the joint exchange
+      // of the bra slots give the same packed contribution (the exchange has
+      // character +1 in both ccvv entries): map bra slots k -> pi(k)
+      if (t.up && t.bra == CCVV && t.d.bra.nslot == 4) {
+        auto pi = [](int v) { return v >= 0 && v < 4 ? (v ^ 1) : v; };
+        int alt[6];
+        for (int l = 0; l < 4; ++l) alt[l] = l < t.d.ket.nslot ? pi(ks[l]) : ks[l];
+        alt[4] = pi(t.d.fx_src);
+        alt[5] = pi(t.d.fy_src);
+        const int cur[6] = {ks[0], ks[1], ks[2], ks[3], t.d.fx_src, t.d.fy_src};
+        if (std::lexicographical_compare(alt, alt + 6, cur, cur + 6)) {
+          std::copy(alt, alt + 4, ks);
+          t.d.fx_src = alt[4];
+          t.d.fy_src = alt[5];
+        }
+      }
+      const std::vector<int64_t> key = {t.up, t.bra, t.ket, ks[0], ks[1], ks[2], ks[3], t.d.fx_src, t.d.fy_src,
+                                        t.f_off, t.d.nsum, t.d.sum_dim[0], t.d.sum_dim[1], t.d.ny, t.d.ncol,
+                                        t.G.n};
+      auto it = seen.find(key);
+      if (it == seen.end()) {
+        seen.emplace(key, merged.size());
+        merged.push_back(std::move(t));
+      } else {
+        HIPCHECK(vec_axpy(t.G.n, 1.0, t.G.p, merged[it->second].G.p, h.s));
+      }
+    }
+    host_sync(h);
+    if (h.verbose)
+      std::fprintf(stderr, "[caspt2] coupling terms of set %d: %zu merged into %zu\n", set, cs.size(),
+                   merged.size());
+    cs = std::move(merged);
+  }
+  // ccvv, the largest block, is read from its packed rows by the reduce of
+  // the down terms (it is never the ket of an up term): no all-orderings copy
+  // of x for it
+  if (used[CCVV]) h.direct[CCVV] = true;
+  scratch = 0;
+  for (auto& cs : h.couple)
+    for (auto& t : cs) {
+      if (t.up && h.direct[t.ket]) throw DevError(CASPT2_E_NOTIMPL, "up coupling from a packed ket");
+      if (t.up)
+        scratch = std::max(scratch, all_rows(h, t.ket) * t.d.ny * t.d.ncol);
+      else
+        scratch = std::max(scratch, all_rows(h, t.bra) * t.d.ny * t.d.ncol);
+    }
   h.cscratch.alloc(scratch);
   // all-orderings copies of the blocks taking part (one function set at a time)
   const int64_t nset_of = ss ? 1 : nst;
   for (int b = 0; b < NBLOCK; ++b) {
     if (!used[b]) continue;
     const int64_t na_b = nset_of * (int64_t)BL[b].types.size() * ipow(h.na, (int)BL[b].act.size());
-    h.xall[b].alloc(all_rows(h, b) * na_b);
+    if (!h.direct[b]) h.xall[b].alloc(all_rows(h, b) * na_b);
     h.sall[b].alloc(all_rows(h, b) * na_b);
   }
 }
@@ -1053,22 +1115,29 @@ void apply_couplings(H& h, int set, const T* x, T* sig) {
   auto xall = [&](int b) { return reinterpret_cast<T*>(h.xall[b].p); };
   auto sall = [&](int b) { return reinterpret_cast<T*>(h.sall[b].p); };
   T* scratch = reinterpret_cast<T*>(h.cscratch.p);
-  for (int b = 0; b < NBLOCK; ++b) {
-    if (!h.xall[b].p) continue;
-    const int64_t na_b = nalpha_of(b);
-    HIPCHECK(unpack_all(pack_info(h, set, b, nullptr, nullptr, na_b), all_desc(h, b), x, xall(b), h.s));
-    h.sall[b].zero(h.s);
-  }
-  const bool diag = h.verbose_level >= 2;   // per-term timing on stderr
+  const bool diag = h.verbose_level >= 2;   // per-stage timing on stderr
   double t_prev = diag ? (host_sync(h), wall()) : 0.0;
+  auto stage = [&](const char* what) {
+    if (!diag) return;
+    host_sync(h);
+    const double now = wall();
+    std::fprintf(stderr, "[caspt2] coupling %s %.3f ms\n", what, 1e3 * (now - t_prev));
+    t_prev = now;
+  };
+  for (int b = 0; b < NBLOCK; ++b) {
+    if (!h.sall[b].p) continue;
+    const int64_t na_b = nalpha_of(b);
+    if (h.xall[b].p)
+      HIPCHECK(unpack_all(pack_info(h, set, b, nullptr, nullptr, na_b), all_desc(h, b), x, xall(b), h.s));
+    // fill kernel, not a memset: this sequence is recorded into HIP graphs
+    HIPCHECK(vec_fill(h.sall[b].n, 0.0, h.sall[b].p, h.s));
+  }
+  stage("unpack");
   for (auto& t : h.couple[set]) {
     const double* f = h.fock.p + t.f_off;
     const int64_t nab = nalpha_of(t.bra), nak = nalpha_of(t.ket);
     if (diag) {
-      host_sync(h);
-      const double now = wall();
-      std::fprintf(stderr, "[caspt2] coupling stage %.3f ms\n", 1e3 * (now - t_prev));
-      t_prev = now;
+      stage("stage");
       std::fprintf(stderr, "[caspt2] term %s %s <- %s ny %d nsum %d: ", t.up ? "up" : "down",
                    blocks()[t.bra].name.c_str(), blocks()[t.ket].name.c_str(), t.d.ny, t.d.nsum);
     }
@@ -1079,15 +1148,15 @@ void apply_couplings(H& h, int set, const T* x, T* sig) {
       HIPCHECK(couple_expand(t.d, f, (const T*)scratch, sall(t.bra), h.s));
     } else {
       const int64_t width = (int64_t)t.d.ny * nak;
-      HIPCHECK(couple_reduce(t.d, f, (const T*)xall(t.ket), scratch, h.s));
+      if (h.direct[t.ket])
+        HIPCHECK(couple_reduce_packed(t.d, pack_info(h, set, t.ket, nullptr, nullptr, nak), f, x, scratch, h.s));
+      else
+        HIPCHECK(couple_reduce(t.d, f, (const T*)xall(t.ket), scratch, h.s));
       HIPCHECK(gemm_t(true, all_rows(h, t.bra), nab, width, 1.0, scratch, width, Sel<T>::G(t), width, 1.0,
                       sall(t.bra), nab, h.s));
     }
   }
-  if (diag) {
-    host_sync(h);
-    std::fprintf(stderr, "[caspt2] last term %.3f ms\n", 1e3 * (wall() - t_prev));
-  }
+  stage("last term");
   for (int b = 0; b < NBLOCK; ++b) {
     if (!h.sall[b].p) continue;
     for (auto& e : h.sets[set]) {
@@ -1096,6 +1165,7 @@ void apply_couplings(H& h, int set, const T* x, T* sig) {
       HIPCHECK(pack_acc(d, all_desc(h, b), (const T*)sall(b), sig + e.offset, h.s));
     }
   }
+  stage("pack");
 }
 
 // ---------------------------------------------------------------------------
@@ -1242,56 +1312,6 @@ void build_denoms(H& h, int L, DBuf& D, double* dmin) {
   *dmin = mn;
 }
 
-int pcg(H& h, int L, const double* b_orth, double tol, int maxiter, DBuf& t, caspt2_info& info) {
-  const int set = set_of(h, L);
-  const int64_t n = olen(h, set);
-  DBuf D;
-  double dmin;
-  build_denoms(h, L, D, &dmin);
-  info.min_denom = dmin;
-  info.e0 = h.e0[L];
-  info.emin_kept = INFINITY;
-  info.emax_dropped = -1.0;
-  for (auto& e : h.sets[set]) {
-    info.emin_kept = std::min(info.emin_kept, e.emin_kept);
-    info.emax_dropped = std::max(info.emax_dropped, e.emax_dropped);
-  }
-  if (!(dmin > 0.0)) return CASPT2_E_INDEFINITE;
-  t.alloc(n);
-  t.zero(h.s);
-  DBuf r(n), z(n), p(n), Ap(n), x(h.length), sg(h.length);
-  HIPCHECK(vec_scale_copy(n, -1.0, b_orth, r.p, h.s));
-  HIPCHECK(vec_div(n, r.p, D.p, z.p, h.s));
-  HIPCHECK(hipMemcpyAsync(p.p, z.p, n * sizeof(double), hipMemcpyDeviceToDevice, h.s));
-  double rz = ddot(h, n, r.p, z.p);
-  double rn = std::sqrt(ddot(h, n, r.p, r.p));
-  int it = 0;
-  while (rn > tol && it < maxiter) {
-    from_orth(h, set, p.p, x.p);
-    residual(h, L, x.p, sg.p, false);
-    to_orth(h, set, sg.p, Ap.p);
-    const double pAp = ddot(h, n, p.p, Ap.p);
-    if (!(pAp > 0.0)) {
-      info.iters = it;
-      info.resnorm = rn;
-      return CASPT2_E_INDEFINITE;
-    }
-    const double alpha = rz / pAp;
-    HIPCHECK(vec_axpy(n, alpha, p.p, t.p, h.s));
-    HIPCHECK(vec_axpy(n, -alpha, Ap.p, r.p, h.s));
-    rn = std::sqrt(ddot(h, n, r.p, r.p));
-    HIPCHECK(vec_div(n, r.p, D.p, z.p, h.s));
-    const double rz2 = ddot(h, n, r.p, z.p);
-    HIPCHECK(vec_xpay(n, z.p, rz2 / rz, p.p, h.s));
-    rz = rz2;
-    ++it;
-  }
-  info.iters = it;
-  info.resnorm = rn;
-  info.flags = rn <= tol ? 1 : 0;
-  return rn <= tol ? CASPT2_OK : CASPT2_E_NOCONV;
-}
-
 // Mixed precision: FP64 iterative refinement around an FP32 PCG.  The outer
 // loop keeps t and the true residual r = -b - A t in FP64 (FP64 operator);
 // each inner solve runs PCG on A d = r / |r| entirely in FP32 (operator,
@@ -1397,10 +1417,372 @@ void setup_mixed(H& h) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Grouped FP64 PCG.  Every linear system of a solve (all states of one
+// problem, or all amplitude and lambda systems of a batch of problems)
+// advances in lockstep.  Per system, the operator application q = A p
+// (from_orth, residual, to_orth) is one captured HIP graph; the recurrence
+// runs in the grouped kernels with device-resident scalars; the host reads
+// the scalars every few iterations only (then retires finished systems and
+// may add new ones).
+// ---------------------------------------------------------------------------
+struct PcgSystem {
+  H* h = nullptr;
+  int L = 0, set = 0, kind = 0;   // kind 0: amplitudes, 1: lambda
+  int64_t n = 0;
+  DBuf t, r, p, q, D;
+  hipGraphExec_t graph = nullptr;
+  int id = -1;
+  int status = PCG_IDLE;
+  caspt2_info info{};
+  PcgSystem() = default;
+  PcgSystem(const PcgSystem&) = delete;
+  PcgSystem& operator=(const PcgSystem&) = delete;
+  ~PcgSystem() {
+    if (graph) (void)hipGraphExecDestroy(graph);
+  }
+};
+
+void ensure_work(H& h) {
+  if (h.wx.n != h.length) {
+    h.wx.alloc(h.length);
+    h.wsg.alloc(h.length);
+  }
+}
+
+// capture q = A p of one system into a graph recorded on stream s (the
+// handle's own launches are redirected to s while recording)
+void capture_operator(PcgSystem& S, hipStream_t s) {
+  H& h = *S.h;
+  ensure_work(h);
+  const hipStream_t keep = h.s;
+  const bool prof = h.prof_on;
+  const int vl = h.verbose_level;
+  auto restore = [&]() {
+    h.s = keep;
+    h.prof_on = prof;
+    h.verbose_level = vl;
+  };
+  h.s = s;
+  h.prof_on = false;
+  h.verbose_level = std::min(vl, 1);   // no host synchronisation while recording
+  hipGraph_t g = nullptr;
+  HIPCHECK(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+  try {
+    from_orth(h, S.set, (const double*)S.p.p, h.wx.p);
+    residual(h, S.L, (const double*)h.wx.p, h.wsg.p, false);
+    to_orth(h, S.set, (const double*)h.wsg.p, S.q.p);
+  } catch (...) {
+    (void)hipStreamEndCapture(s, &g);
+    if (g) (void)hipGraphDestroy(g);
+    restore();
+    throw;
+  }
+  const hipError_t e1 = hipStreamEndCapture(s, &g);
+  restore();
+  HIPCHECK(e1);
+  const hipError_t e2 = hipGraphInstantiate(&S.graph, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  HIPCHECK(e2);
+}
+
+struct PcgEngine {
+  hipStream_t s = nullptr;
+  int capacity = 0;
+  int check_every = 4;
+  std::vector<std::unique_ptr<PcgSystem>> sys;
+  std::vector<int> active;             // ids the host still launches
+  DevBuf<PcgScalars> sc;
+  DevBuf<PcgVecs<double>> vecs;
+  std::vector<PcgScalars> hsc;
+  DevBuf<int32_t> blk_sys, sys_id, b0, b1;
+  DevBuf<int64_t> blk_start, blk_end;
+  DBuf part_a, part_b;
+  PcgTable tab{};
+  PcgSysTable st{};
+
+  explicit PcgEngine(int cap) : capacity(cap) {
+    HIPCHECK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    sc.alloc(cap);
+    vecs.alloc(cap);
+    hsc.assign(cap, PcgScalars{});
+  }
+  ~PcgEngine() {
+    sys.clear();
+    if (s) (void)hipStreamDestroy(s);
+  }
+  PcgEngine(const PcgEngine&) = delete;
+  PcgEngine& operator=(const PcgEngine&) = delete;
+
+  // new system A x = -b (b in the orthonormal basis, device, on h.s)
+  PcgSystem& add(H& h, int L, int kind, const double* b, double tol, int maxiter) {
+    if ((int)sys.size() >= capacity) throw DevError(CASPT2_E_ARG, "pcg engine capacity");
+    auto S = std::make_unique<PcgSystem>();
+    S->h = &h;
+    S->L = L;
+    S->kind = kind;
+    S->set = set_of(h, L);
+    S->n = olen(h, S->set);
+    S->id = (int)sys.size();
+    caspt2_info& info = S->info;
+    double dmin = INFINITY;
+    build_denoms(h, L, S->D, &dmin);
+    info.min_denom = dmin;
+    info.e0 = h.e0[L];
+    info.emin_kept = INFINITY;
+    info.emax_dropped = -1.0;
+    for (auto& e : h.sets[S->set]) {
+      info.emin_kept = std::min(info.emin_kept, e.emin_kept);
+      info.emax_dropped = std::max(info.emax_dropped, e.emax_dropped);
+    }
+    S->t.alloc(S->n);
+    S->r.alloc(S->n);
+    S->p.alloc(S->n);
+    S->q.alloc(S->n);
+    HIPCHECK(vec_fill(S->n, 0.0, S->t.p, h.s));
+    HIPCHECK(vec_scale_copy(S->n, -1.0, b, S->r.p, h.s));
+    host_sync(h);
+    S->status = dmin > 0.0 ? PCG_IDLE : PCG_INDEFINITE;
+    PcgScalars c{};
+    c.tol2 = tol * tol;
+    c.maxiter = maxiter;
+    c.status = S->status;
+    c.active = 0;
+    PcgVecs<double> v{};
+    v.vec[PCG_T] = S->t.p;
+    v.vec[PCG_R] = S->r.p;
+    v.vec[PCG_P] = S->p.p;
+    v.vec[PCG_Q] = S->q.p;
+    v.vec[PCG_D] = S->D.p;
+    HIPCHECK(hipMemcpy(sc.p + S->id, &c, sizeof(c), hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(vecs.p + S->id, &v, sizeof(v), hipMemcpyHostToDevice));
+    hsc[S->id] = c;
+    if (S->status == PCG_IDLE && S->n > 0) capture_operator(*S, s);
+    if (S->n == 0 && S->status == PCG_IDLE) S->status = PCG_CONVERGED;
+    sys.push_back(std::move(S));
+    return *sys.back();
+  }
+
+  // block and system tables over the given ids (device upload, synchronous;
+  // waits for the stream first: queued kernels may still read the tables)
+  void build_tables(const std::vector<int>& ids) {
+    HIPCHECK(hipStreamSynchronize(s));
+    std::vector<int32_t> hb_sys, h_sys, h_b0, h_b1;
+    std::vector<int64_t> hb_start, hb_end;
+    for (int id : ids) {
+      const PcgSystem& S = *sys[id];
+      h_sys.push_back(id);
+      h_b0.push_back((int32_t)hb_sys.size());
+      for (int64_t a = 0; a < S.n; a += PCG_CHUNK) {
+        hb_sys.push_back(id);
+        hb_start.push_back(a);
+        hb_end.push_back(std::min(S.n, a + PCG_CHUNK));
+      }
+      h_b1.push_back((int32_t)hb_sys.size());
+    }
+    const int64_t nb = (int64_t)hb_sys.size(), ns = (int64_t)h_sys.size();
+    if (nb > INT32_MAX) throw DevError(CASPT2_E_ARG, "pcg block table too large");
+    auto up = [](auto& buf, const auto& hv) {
+      using E = typename std::decay_t<decltype(hv)>::value_type;
+      if (buf.n < (int64_t)hv.size()) buf.alloc(std::max<int64_t>((int64_t)hv.size(), 2 * buf.n));
+      if (!hv.empty()) HIPCHECK(hipMemcpy(buf.p, hv.data(), hv.size() * sizeof(E), hipMemcpyHostToDevice));
+    };
+    up(blk_sys, hb_sys);
+    up(blk_start, hb_start);
+    up(blk_end, hb_end);
+    up(sys_id, h_sys);
+    up(b0, h_b0);
+    up(b1, h_b1);
+    if (part_a.n < nb) {
+      part_a.alloc(std::max<int64_t>(nb, 2 * part_a.n));
+      part_b.alloc(part_a.n);
+    }
+    tab = PcgTable{(int)nb, blk_sys.p, blk_start.p, blk_end.p};
+    st = PcgSysTable{(int)ns, sys_id.p, b0.p, b1.p};
+  }
+
+  // initialise (z, p, rz, rr) and activate the given systems
+  void start(const std::vector<int>& ids) {
+    std::vector<int> go;
+    for (int id : ids)
+      if (sys[id]->status == PCG_IDLE) go.push_back(id);
+    if (go.empty()) return;
+    build_tables(go);
+    HIPCHECK(pcg_init<double>(tab, st, vecs.p, sc.p, part_a.p, part_b.p, s));
+    for (int id : go) {
+      sys[id]->status = PCG_RUNNING;
+      active.push_back(id);
+    }
+    build_tables(active);
+  }
+
+  // copy the scalars to the host; retire systems that stopped on the device
+  bool poll() {
+    HIPCHECK(hipMemcpyAsync(hsc.data(), sc.p, sys.size() * sizeof(PcgScalars), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    std::vector<int> still;
+    for (int id : active) {
+      if (hsc[id].status == PCG_RUNNING)
+        still.push_back(id);
+      else
+        sys[id]->status = hsc[id].status;
+    }
+    const bool changed = still.size() != active.size();
+    active.swap(still);
+    return changed;
+  }
+
+  // iterate until no system runs; on_poll (called after every poll, and
+  // once before the first iteration) may start new systems
+  template <typename F>
+  void run(F&& on_poll) {
+    on_poll(*this);
+    while (!active.empty()) {
+      for (int k = 0; k < check_every; ++k) {
+        for (int id : active) HIPCHECK(hipGraphLaunch(sys[id]->graph, s));
+        HIPCHECK(pcg_step<double>(tab, st, vecs.p, sc.p, part_a.p, part_b.p, s));
+      }
+      poll();
+      on_poll(*this);
+      if (!active.empty()) build_tables(active);
+    }
+  }
+
+  // free the work vectors and the graph of a system that has finished
+  void retire(PcgSystem& S) {
+    S.r.release();
+    S.p.release();
+    S.q.release();
+    S.D.release();
+    if (S.graph) (void)hipGraphExecDestroy(S.graph);
+    S.graph = nullptr;
+  }
+
+  // final scalars into the system's info; solution stays in S.t
+  void finish(PcgSystem& S) {
+    const PcgScalars& c = hsc[S.id];
+    S.info.iters = c.iters;
+    S.info.resnorm = std::sqrt(std::max(c.rr, 0.0));
+    S.info.flags = S.status == PCG_CONVERGED ? 1 : 0;
+    S.info.refinements = 0;
+  }
+};
+
+// first failure wins, E_INDEFINITE over E_NOCONV
+int merge_status(int a, int b) {
+  if (a == CASPT2_E_INDEFINITE || b == CASPT2_E_INDEFINITE) return CASPT2_E_INDEFINITE;
+  return a != CASPT2_OK ? a : b;
+}
+
+int status_code(int pcg_status) {
+  switch (pcg_status) {
+    case PCG_CONVERGED: return CASPT2_OK;
+    case PCG_INDEFINITE: return CASPT2_E_INDEFINITE;
+    default: return CASPT2_E_NOCONV;
+  }
+}
+
+// right-hand sides in the orthonormal basis (device, on h.s)
+void amplitude_rhs(H& h, int L, double* b) { to_orth(h, set_of(h, L), (const double*)h.src[set_of(h, L)][L].p, b); }
+
+// b = R_LP sum_N R_NP X^T V^(N) - 2 E_s R_LP^2 t_L   (Eq. 20; X^T S X = 1)
+void lambda_rhs(H& h, int L, int P, double* b) {
+  const int set = set_of(h, L);
+  const int nst = h.nst;
+  const int64_t n = olen(h, set);
+  DBuf tmp(n);
+  HIPCHECK(vec_fill(n, 0.0, b, h.s));
+  for (int N = 0; N < nst; ++N) {
+    to_orth(h, set, (const double*)h.src[set][N].p, tmp.p);
+    HIPCHECK(vec_axpy(n, h.R[L * nst + P] * h.R[N * nst + P], tmp.p, b, h.s));
+  }
+  HIPCHECK(vec_axpy(n, -2.0 * h.d.shift * h.R[L * nst + P] * h.R[L * nst + P], h.Tt[L].p, b, h.s));
+  host_sync(h);
+}
+
+// H_eff (Eq. 15) from the amplitudes and its eigenpairs (Eqs. 16-17)
+void compute_heff(H& h) {
+  const int nst = h.nst;
+  std::vector<double> Hm(h.href);
+  for (int L = 0; L < nst; ++L) {
+    for (int Lp = 0; Lp < nst; ++Lp) {
+      const double a = ddot(h, h.length, h.T[L].p, h.src[set_of(h, L)][Lp].p);
+      const double b = ddot(h, h.length, h.T[Lp].p, h.src[set_of(h, Lp)][L].p);
+      Hm[L * nst + Lp] += 0.5 * (a + b);
+    }
+    const int64_t n = olen(h, set_of(h, L));
+    Hm[L * nst + L] -= h.d.shift * ddot(h, n, h.Tt[L].p, h.Tt[L].p);
+  }
+  DBuf Hd(nst * nst), wv(nst), Rd(nst * nst);
+  HIPCHECK(hipMemcpyAsync(Hd.p, Hm.data(), nst * nst * sizeof(double), hipMemcpyHostToDevice, h.s));
+  HIPCHECK(small_eigh(nst, Hd.p, wv.p, Rd.p, h.s));
+  h.heff = Hm;
+  h.ems.resize(nst);
+  h.R.resize(nst * nst);
+  HIPCHECK(hipMemcpyAsync(h.ems.data(), wv.p, nst * sizeof(double), hipMemcpyDeviceToHost, h.s));
+  HIPCHECK(hipMemcpyAsync(h.R.data(), Rd.p, nst * nst * sizeof(double), hipMemcpyDeviceToHost, h.s));
+  host_sync(h);
+  h.have_heff = true;
+}
+
+// move a finished system's solution into the handle (packed and orthonormal)
+void store_solution(PcgSystem& S, std::vector<DBuf>& packed, std::vector<DBuf>& orth) {
+  H& h = *S.h;
+  DBuf T(h.length);
+  from_orth(h, S.set, (const double*)S.t.p, T.p);
+  host_sync(h);
+  packed[S.L] = std::move(T);
+  orth[S.L] = std::move(S.t);
+}
+
 int solve_pcg(H& h, int L, const double* b_orth, double tol, int maxiter, DBuf& t, caspt2_info& info) {
   info.refinements = 0;
-  if (h.d.precision == CASPT2_MIXED) return pcg_mixed(h, L, b_orth, tol, maxiter, t, info);
-  return pcg(h, L, b_orth, tol, maxiter, t, info);
+  return pcg_mixed(h, L, b_orth, tol, maxiter, t, info);
+}
+
+// all states of one handle in one grouped FP64 solve; kind 0 amplitudes,
+// 1 lambda for target P
+int grouped_solve(H& h, int kind, int P, double tol, int maxiter, std::vector<DBuf>& packed,
+                  std::vector<DBuf>& orth, std::vector<caspt2_info>& infos) {
+  const int nst = h.nst;
+  PcgEngine eng(nst);
+  for (int L = 0; L < nst; ++L) {
+    DBuf b(olen(h, set_of(h, L)));
+    if (kind == 0)
+      amplitude_rhs(h, L, b.p);
+    else
+      lambda_rhs(h, L, P, b.p);
+    host_sync(h);
+    eng.add(h, L, kind, b.p, tol, maxiter);
+  }
+  std::vector<int> ids(nst);
+  for (int L = 0; L < nst; ++L) ids[L] = L;
+  eng.start(ids);
+  eng.run([](PcgEngine&) {});
+  int status = CASPT2_OK;
+  packed.resize(nst);
+  orth.resize(nst);
+  infos.assign(nst, caspt2_info{});
+  for (auto& S : eng.sys) {
+    eng.finish(*S);
+    infos[S->L] = S->info;
+    const int rc = status_code(S->status);
+    if (rc == CASPT2_E_INDEFINITE) {
+      char msg[200];
+      const PcgScalars& c = eng.hsc[S->id];
+      std::snprintf(msg, sizeof msg, "state %d: %s (min denominator %.6g, p.Ap %.6g after %d iterations)",
+                    S->L, S->info.min_denom > 0.0 ? "operator not positive definite" : "non-positive denominator",
+                    S->info.min_denom, c.pap, c.iters);
+      g_last_error = msg;
+      return rc;
+    }
+    if (rc != CASPT2_OK) status = rc;
+  }
+  for (auto& S : eng.sys) {
+    store_solution(*S, packed, orth);
+    eng.retire(*S);
+  }
+  return status;
 }
 
 void validate(const caspt2_dims* d, const std::vector<double>& f, const std::vector<double>& hc,
@@ -1674,23 +2056,28 @@ int caspt2_solve_amplitudes(caspt2_handle* h, double tol, int32_t maxiter, caspt
     H& hh = *h;
     hh.T.clear();
     hh.Tt.clear();
-    hh.tinfo.assign(hh.nst, caspt2_info{});
+    hh.have_T = hh.have_heff = hh.have_lam = false;
     int status = CASPT2_OK;
-    for (int L = 0; L < hh.nst; ++L) {
-      const int set = set_of(hh, L);
-      DBuf b(olen(hh, set)), t;
-      to_orth(hh, set, hh.src[set][L].p, b.p);
-      const int rc = solve_pcg(hh, L, b.p, tol, maxiter, t, hh.tinfo[L]);
-      if (rc == CASPT2_E_INDEFINITE) return rc;
-      if (rc != CASPT2_OK) status = rc;
-      DBuf T(hh.length);
-      from_orth(hh, set, t.p, T.p);
-      hh.T.push_back(std::move(T));
-      hh.Tt.push_back(std::move(t));
+    if (hh.d.precision == CASPT2_FP64) {
+      status = grouped_solve(hh, 0, 0, tol, maxiter, hh.T, hh.Tt, hh.tinfo);
+      if (status == CASPT2_E_INDEFINITE) return status;
+    } else {
+      hh.tinfo.assign(hh.nst, caspt2_info{});
+      for (int L = 0; L < hh.nst; ++L) {
+        const int set = set_of(hh, L);
+        DBuf b(olen(hh, set)), t;
+        amplitude_rhs(hh, L, b.p);
+        const int rc = solve_pcg(hh, L, b.p, tol, maxiter, t, hh.tinfo[L]);
+        if (rc == CASPT2_E_INDEFINITE) return rc;
+        if (rc != CASPT2_OK) status = rc;
+        DBuf T(hh.length);
+        from_orth(hh, set, (const double*)t.p, T.p);
+        hh.T.push_back(std::move(T));
+        hh.Tt.push_back(std::move(t));
+      }
     }
     host_sync(hh);
     hh.have_T = true;
-    hh.have_heff = hh.have_lam = false;
     if (info)
       for (int L = 0; L < hh.nst; ++L) info[L] = hh.tinfo[L];
     return status;
@@ -1720,29 +2107,10 @@ int xms_heff(caspt2_handle* h, double* heff, double* e_ms, double* R) {
   ABI_GUARD({
     H& hh = *h;
     const int nst = hh.nst;
-    std::vector<double> Hm(hh.href);
-    for (int L = 0; L < nst; ++L) {
-      for (int Lp = 0; Lp < nst; ++Lp) {
-        const double a = ddot(hh, hh.length, hh.T[L].p, hh.src[set_of(hh, L)][Lp].p);
-        const double b = ddot(hh, hh.length, hh.T[Lp].p, hh.src[set_of(hh, Lp)][L].p);
-        Hm[L * nst + Lp] += 0.5 * (a + b);
-      }
-      const int64_t n = olen(hh, set_of(hh, L));
-      Hm[L * nst + L] -= hh.d.shift * ddot(hh, n, hh.Tt[L].p, hh.Tt[L].p);
-    }
-    DBuf Hd(nst * nst), wv(nst), Rd(nst * nst);
-    HIPCHECK(hipMemcpyAsync(Hd.p, Hm.data(), nst * nst * sizeof(double), hipMemcpyHostToDevice, hh.s));
-    HIPCHECK(small_eigh(nst, Hd.p, wv.p, Rd.p, hh.s));
-    hh.heff = Hm;
-    hh.ems.resize(nst);
-    hh.R.resize(nst * nst);
-    HIPCHECK(hipMemcpyAsync(hh.ems.data(), wv.p, nst * sizeof(double), hipMemcpyDeviceToHost, hh.s));
-    HIPCHECK(hipMemcpyAsync(hh.R.data(), Rd.p, nst * nst * sizeof(double), hipMemcpyDeviceToHost, hh.s));
-    host_sync(hh);
-    if (heff) std::memcpy(heff, Hm.data(), nst * nst * sizeof(double));
+    compute_heff(hh);
+    if (heff) std::memcpy(heff, hh.heff.data(), nst * nst * sizeof(double));
     if (e_ms) std::memcpy(e_ms, hh.ems.data(), nst * sizeof(double));
     if (R) std::memcpy(R, hh.R.data(), nst * nst * sizeof(double));
-    hh.have_heff = true;
     return CASPT2_OK;
   })
 }
@@ -1755,32 +2123,140 @@ int caspt2_solve_lambda(caspt2_handle* h, int32_t P, double tol, int32_t maxiter
     const int nst = hh.nst;
     hh.lam.clear();
     hh.lamt.clear();
-    hh.linfo.assign(nst, caspt2_info{});
+    hh.have_lam = false;
     int status = CASPT2_OK;
-    for (int L = 0; L < nst; ++L) {
-      const int set = set_of(hh, L);
-      const int64_t n = olen(hh, set);
-      // b = R_LP sum_N R_NP X^T V^(N) - 2 E_s R_LP^2 t_L   (Eq. 20; X^T S X = 1)
-      DBuf b(n), tmp(n), t;
-      b.zero(hh.s);
-      for (int N = 0; N < nst; ++N) {
-        to_orth(hh, set, hh.src[set][N].p, tmp.p);
-        HIPCHECK(vec_axpy(n, hh.R[L * nst + P] * hh.R[N * nst + P], tmp.p, b.p, hh.s));
+    if (hh.d.precision == CASPT2_FP64) {
+      status = grouped_solve(hh, 1, P, tol, maxiter, hh.lam, hh.lamt, hh.linfo);
+      if (status == CASPT2_E_INDEFINITE) return status;
+    } else {
+      hh.linfo.assign(nst, caspt2_info{});
+      for (int L = 0; L < nst; ++L) {
+        const int set = set_of(hh, L);
+        DBuf b(olen(hh, set)), t;
+        lambda_rhs(hh, L, P, b.p);
+        const int rc = solve_pcg(hh, L, b.p, tol, maxiter, t, hh.linfo[L]);
+        if (rc == CASPT2_E_INDEFINITE) return rc;
+        if (rc != CASPT2_OK) status = rc;
+        DBuf lam(hh.length);
+        from_orth(hh, set, (const double*)t.p, lam.p);
+        hh.lam.push_back(std::move(lam));
+        hh.lamt.push_back(std::move(t));
       }
-      HIPCHECK(vec_axpy(n, -2.0 * hh.d.shift * hh.R[L * nst + P] * hh.R[L * nst + P], hh.Tt[L].p,
-                        b.p, hh.s));
-      const int rc = solve_pcg(hh, L, b.p, tol, maxiter, t, hh.linfo[L]);
-      if (rc == CASPT2_E_INDEFINITE) return rc;
-      if (rc != CASPT2_OK) status = rc;
-      DBuf lam(hh.length);
-      from_orth(hh, set, t.p, lam.p);
-      hh.lam.push_back(std::move(lam));
-      hh.lamt.push_back(std::move(t));
     }
     host_sync(hh);
     hh.have_lam = true;
     if (info)
       for (int L = 0; L < nst; ++L) info[L] = hh.linfo[L];
+    return status;
+  })
+}
+
+int caspt2_batch_solve(caspt2_handle* const* handles, int32_t n, const int32_t* targets, double tol,
+                       int32_t maxiter, caspt2_info* amp_info, caspt2_info* lambda_info) {
+  if (!handles || n <= 0 || !targets || !(tol > 0.0) || maxiter < 0) return CASPT2_E_ARG;
+  for (int i = 0; i < n; ++i) {
+    if (!handles[i] || targets[i] < 0 || targets[i] >= handles[i]->nst) return CASPT2_E_ARG;
+    if (handles[i]->d.precision != CASPT2_FP64) return CASPT2_E_NOTIMPL;
+    for (int j = 0; j < i; ++j)
+      if (handles[j] == handles[i]) return CASPT2_E_ARG;
+  }
+  ABI_GUARD({
+    int cap = 0;
+    std::vector<int64_t> off(n + 1, 0);
+    for (int i = 0; i < n; ++i) {
+      cap += 2 * handles[i]->nst;
+      off[i + 1] = off[i] + handles[i]->nst;
+    }
+    PcgEngine eng(cap);
+    // phase per problem: 0 amplitudes running, 1 lambda running, 2 done, 3 failed
+    std::vector<int> phase(n, 0), result(n, CASPT2_OK);
+    std::vector<std::vector<int>> amp(n), lam(n);
+    for (int i = 0; i < n; ++i) {
+      H& h = *handles[i];
+      h.T.clear();
+      h.Tt.clear();
+      h.lam.clear();
+      h.lamt.clear();
+      h.tinfo.clear();
+      h.linfo.clear();
+      h.have_T = h.have_heff = h.have_lam = false;
+      for (int L = 0; L < h.nst; ++L) {
+        DBuf b(olen(h, set_of(h, L)));
+        amplitude_rhs(h, L, b.p);
+        host_sync(h);
+        amp[i].push_back(eng.add(h, L, 0, b.p, tol, maxiter).id);
+      }
+    }
+    std::vector<int> all;
+    for (auto& v : amp) all.insert(all.end(), v.begin(), v.end());
+    eng.start(all);
+    auto done = [&](const std::vector<int>& ids) {
+      for (int id : ids) {
+        const int st = eng.sys[id]->status;
+        if (st == PCG_RUNNING || st == PCG_IDLE) return false;
+      }
+      return true;
+    };
+    auto collect = [&](int i, const std::vector<int>& ids, std::vector<caspt2_info>& infos) {
+      int rc = CASPT2_OK;
+      infos.assign(handles[i]->nst, caspt2_info{});
+      for (int id : ids) {
+        PcgSystem& S = *eng.sys[id];
+        eng.finish(S);
+        infos[S.L] = S.info;
+        rc = merge_status(rc, status_code(S.status));
+      }
+      return rc;
+    };
+    // interleaving: a problem whose amplitude systems have all stopped gets
+    // H_eff and its lambda systems at once, while others still iterate
+    eng.run([&](PcgEngine& e) {
+      for (int i = 0; i < n; ++i) {
+        H& h = *handles[i];
+        if (phase[i] == 0 && done(amp[i])) {
+          result[i] = collect(i, amp[i], h.tinfo);
+          if (result[i] != CASPT2_OK) {
+            phase[i] = 3;
+            continue;
+          }
+          h.T.resize(h.nst);
+          h.Tt.resize(h.nst);
+          for (int id : amp[i]) {
+            store_solution(*e.sys[id], h.T, h.Tt);
+            e.retire(*e.sys[id]);
+          }
+          h.have_T = true;
+          compute_heff(h);
+          for (int L = 0; L < h.nst; ++L) {
+            DBuf b(olen(h, set_of(h, L)));
+            lambda_rhs(h, L, targets[i], b.p);
+            lam[i].push_back(e.add(h, L, 1, b.p, tol, maxiter).id);
+          }
+          e.start(lam[i]);
+          phase[i] = 1;
+        }
+        if (phase[i] == 1 && done(lam[i])) {
+          result[i] = collect(i, lam[i], h.linfo);
+          h.lam.resize(h.nst);
+          h.lamt.resize(h.nst);
+          for (int id : lam[i]) {
+            store_solution(*e.sys[id], h.lam, h.lamt);
+            e.retire(*e.sys[id]);
+          }
+          h.have_lam = result[i] == CASPT2_OK;
+          phase[i] = result[i] == CASPT2_OK ? 2 : 3;
+        }
+      }
+    });
+    int status = CASPT2_OK;
+    for (int i = 0; i < n; ++i) {
+      H& h = *handles[i];
+      if (amp_info && !h.tinfo.empty())
+        for (int L = 0; L < h.nst; ++L) amp_info[off[i] + L] = h.tinfo[L];
+      if (lambda_info && (int)h.linfo.size() == h.nst)
+        for (int L = 0; L < h.nst; ++L) lambda_info[off[i] + L] = h.linfo[L];
+      status = merge_status(status, result[i]);
+    }
     return status;
   })
 }

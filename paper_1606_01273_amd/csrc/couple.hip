@@ -7,16 +7,65 @@ namespace caspt2 {
 
 static inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
-template <typename T>
-__global__ void k_unpack_all(PackInfo p, AllDesc a, int64_t nrows, const T* __restrict__ packed,
-                             T* __restrict__ out) {
-  const int64_t total = nrows * p.rowlen;
+// calls fn(e, chi) for every distinct image e of the orbit of e0 under the
+// swaps of d (chi = product of the characters of the applied swaps) and
+// returns the packing weight 1 / sqrt(number of images)
+template <typename D, typename F>
+__device__ inline double orbit_images(const D& d, const int e0[4], F&& fn) {
+  int ndist = 0;
+  bool eq[2] = {false, false};
+#pragma unroll
+  for (int sw = 0; sw < 2; ++sw) {
+    if (sw >= d.nswap) continue;
+    int u, v;
+    pair_values(d, sw, e0, u, v);
+    eq[sw] = u == v;
+    ndist += u != v ? 1 : 0;
+  }
+#pragma unroll
+  for (int bits = 0; bits < 4; ++bits) {
+    if (bits >= (1 << d.nswap)) continue;
+    if (((bits & 1) && eq[0]) || ((bits & 2) && eq[1])) continue;
+    int e[4] = {e0[0], e0[1], e0[2], e0[3]};
+    double sg = 1.0;
+    if (bits & 1) {
+      swap_pair(d, 0, e);
+      sg *= d.chi[0];
+    }
+    if (bits & 2) {
+      swap_pair(d, 1, e);
+      sg *= d.chi[1];
+    }
+    fn(e, sg);
+  }
+  return ndist == 0 ? 1.0 : (ndist == 1 ? 0.70710678118654752440 : 0.5);
+}
+
+// Column groups: a thread handles NC consecutive alpha columns of one row
+// (NC = 4, 2 or 1 by the row length), so index work and Fock values are
+// shared by the group and the row data moves in wide loads.
+static inline int col_group(int64_t ncol) { return ncol >= 4 ? 4 : (ncol >= 2 ? 2 : 1); }
+
+#define CASPT2_NC_DISPATCH(NCV, KERNEL, GRID, ...)                                             \
+  switch (NCV) {                                                                               \
+    case 4: hipLaunchKernelGGL((KERNEL<T, 4>), GRID, dim3(256), 0, s, __VA_ARGS__); break;     \
+    case 2: hipLaunchKernelGGL((KERNEL<T, 2>), GRID, dim3(256), 0, s, __VA_ARGS__); break;     \
+    default: hipLaunchKernelGGL((KERNEL<T, 1>), GRID, dim3(256), 0, s, __VA_ARGS__); break;    \
+  }
+
+template <typename T, int NC>
+__global__ __launch_bounds__(256) void k_unpack_all(PackInfo p, AllDesc a, int64_t nrows,
+                                                    const T* __restrict__ packed, T* __restrict__ out) {
+  const int64_t ng = (p.rowlen + NC - 1) / NC;
+  const int64_t total = nrows * ng;
   for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
        g += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t row = g / p.rowlen, c = g % p.rowlen;
-    int e[4] = {0, 0, 0, 0};
+    const int64_t row = g / ng, c0 = (g - row * ng) * NC;
+    int e[4];
     decode_all(a, row, e);
-    out[g] = (T)gather_all(p, packed, e, c);
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+      if (c0 + c < p.rowlen) out[row * p.rowlen + c0 + c] = (T)gather_all(p, packed, e, c0 + c);
   }
 }
 
@@ -25,124 +74,203 @@ hipError_t unpack_all(const PackInfo& p, const AllDesc& a, const T* packed, T* o
                       hipStream_t s) {
   int64_t nrows = 1;
   for (int k = 0; k < a.nslot; ++k) nrows *= a.slot_dim[k];
-  const int64_t total = nrows * p.rowlen;
-  if (total == 0) return hipSuccess;
-  unsigned grid = cdiv(total, 256);
+  if (nrows * p.rowlen == 0) return hipSuccess;
+  if (nrows >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+  const int nc = col_group(p.rowlen);
+  unsigned grid = cdiv(nrows * ((p.rowlen + nc - 1) / nc), 256);
   if (grid > 65536) grid = 65536;
-  hipLaunchKernelGGL(k_unpack_all<T>, dim3(grid), dim3(256), 0, s, p, a, nrows, packed, out_all);
+  CASPT2_NC_DISPATCH(nc, k_unpack_all, dim3(grid), p, a, nrows, packed, out_all)
   return hipGetLastError();
 }
 
-template <typename T>
-__global__ void k_pack_acc(TermDesc d, AllDesc a, const T* __restrict__ in,
-                           T* __restrict__ out) {
-  const int64_t total = d.nrow * d.nalpha;
+template <typename T, int NC>
+__global__ __launch_bounds__(256) void k_pack_acc(TermDesc d, AllDesc a, const T* __restrict__ in,
+                                                  T* __restrict__ out) {
+  const int64_t ng = (d.nalpha + NC - 1) / NC;
+  const int64_t total = d.nrow * ng;
   for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
        g += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t row = g / d.nalpha, c = g % d.nalpha;
-    int e0[4] = {0, 0, 0, 0};
+    const int64_t row = g / ng, c0 = (g - row * ng) * NC;
+    int e0[4];
     decode_orbit(d, row, e0);
-    int ndistinct = 0;
-    for (int s = 0; s < d.nswap; ++s)
-      if (e0[d.swap_k[s]] != e0[d.swap_l[s]]) ++ndistinct;
-    const double w = 1.0 / sqrt((double)(1 << ndistinct));
-    double acc = 0.0;
-    for (int bits = 0; bits < (1 << d.nswap); ++bits) {
-      int e[4] = {e0[0], e0[1], e0[2], e0[3]};
-      double sg = 1.0;
-      bool dup = false;
-      for (int s = 0; s < d.nswap; ++s)
-        if ((bits >> s) & 1) {
-          if (e0[d.swap_k[s]] == e0[d.swap_l[s]]) dup = true;
-          const int t = e[d.swap_k[s]];
-          e[d.swap_k[s]] = e[d.swap_l[s]];
-          e[d.swap_l[s]] = t;
-          sg *= d.chi[s];
-        }
-      if (dup) continue;
-      acc += sg * (double)in[encode_all(a, e) * d.nalpha + c];
-    }
-    out[row * d.ldo + c] += (T)(w * acc);
+    double acc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+    const double w = orbit_images(d, e0, [&](const int e[4], double sg) {
+      const T* ip = in + encode_all(a, e) * d.nalpha + c0;
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+        if (c0 + c < d.nalpha) acc[c] += sg * (double)ip[c];
+    });
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+      if (c0 + c < d.nalpha) out[row * d.ldo + c0 + c] += (T)(w * acc[c]);
   }
 }
 
 template <typename T>
 hipError_t pack_acc(const TermDesc& d, const AllDesc& a, const T* in_all, T* packed,
                     hipStream_t s) {
-  const int64_t total = d.nrow * d.nalpha;
-  if (total == 0) return hipSuccess;
-  unsigned grid = cdiv(total, 256);
+  if (d.nrow * d.nalpha == 0) return hipSuccess;
+  if (d.nrow >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+  const int nc = col_group(d.nalpha);
+  unsigned grid = cdiv(d.nrow * ((d.nalpha + nc - 1) / nc), 256);
   if (grid > 65536) grid = 65536;
-  hipLaunchKernelGGL(k_pack_acc<T>, dim3(grid), dim3(256), 0, s, d, a, in_all, packed);
+  CASPT2_NC_DISPATCH(nc, k_pack_acc, dim3(grid), d, a, in_all, packed)
   return hipGetLastError();
 }
 
-// expand: one thread per (ket row, alpha column); the bra slots that are not
-// fed from the ket (the Fock index slots) are looped inside the thread, so
-// every W row is read once.
-template <typename T>
-__global__ void k_couple_expand(CoupleDesc d, const double* __restrict__ f,
-                                const T* __restrict__ W, T* __restrict__ out) {
-  int64_t nrows_k = 1;
-  for (int k = 0; k < d.ket.nslot; ++k) nrows_k *= d.ket.slot_dim[k];
-  const int64_t total = nrows_k * d.ncol;
-  const int64_t wlen = (int64_t)d.ny * d.ncol;
-  // bra slots not fed from the ket
-  int free_slot[2] = {-1, -1}, nfree = 0;
-  for (int k = 0; k < d.bra.nslot; ++k) {
-    bool fed = false;
-    for (int l = 0; l < d.ket.nslot; ++l)
-      if (d.ket_src[l] == k) fed = true;
-    if (!fed && nfree < 2) free_slot[nfree++] = k;
+// Linear index maps of an expand term, folded on the host: the bra
+// all-orderings row and the Fock offset as functions of the ket slot values,
+// the free bra slots (not fed from the ket; at most two, looped) and y.
+struct ExpandPlan {
+  uint32_t kdim[4];          // ket all-orderings dims (1 beyond the ket's slots)
+  int64_t ob_k[4], ob_f[2];  // bra row stride per ket slot / per free slot
+  int64_t fk[4], ff[2], fy;  // Fock offset coefficients
+  uint32_t nf0, nf1;         // free slot ranges (1 if absent)
+  uint32_t bdim[4];          // bra all-orderings dims (out-parallel form)
+  int64_t wk_b[4];           // ket row stride per bra slot (out-parallel form)
+  int64_t fb[4];             // Fock offset coefficient per bra slot (out-parallel form)
+  int ny;
+  int64_t ncol;
+};
+
+ExpandPlan make_expand_plan(const CoupleDesc& d) {
+  ExpandPlan r{};
+  int64_t bst[4] = {0, 0, 0, 0}, kst[4] = {0, 0, 0, 0}, st = 1;
+  for (int k = d.bra.nslot - 1; k >= 0; --k) {
+    bst[k] = st;
+    st *= d.bra.slot_dim[k];
   }
-  const int n0 = nfree > 0 ? d.bra.slot_dim[free_slot[0]] : 1;
-  const int n1 = nfree > 1 ? d.bra.slot_dim[free_slot[1]] : 1;
-  const int z[2] = {0, 0};
+  st = 1;
+  for (int l = d.ket.nslot - 1; l >= 0; --l) {
+    kst[l] = st;
+    st *= d.ket.slot_dim[l];
+  }
+  for (int l = 0; l < 4; ++l) r.kdim[l] = l < d.ket.nslot ? (uint32_t)d.ket.slot_dim[l] : 1u;
+  for (int k = 0; k < 4; ++k) r.bdim[k] = k < d.bra.nslot ? (uint32_t)d.bra.slot_dim[k] : 1u;
+  // bra slot k fed by ket slot feed[k] (or free)
+  int feed[4] = {-1, -1, -1, -1};
+  for (int l = 0; l < d.ket.nslot; ++l) {
+    feed[d.ket_src[l]] = l;
+    r.wk_b[d.ket_src[l]] += kst[l];
+  }
+  int free_of[4] = {-1, -1, -1, -1}, nfree = 0;
+  r.nf0 = r.nf1 = 1;
+  for (int k = 0; k < d.bra.nslot; ++k) {
+    if (feed[k] >= 0) {
+      r.ob_k[feed[k]] += bst[k];
+    } else {
+      free_of[k] = nfree;
+      r.ob_f[nfree] += bst[k];
+      if (nfree == 0) r.nf0 = (uint32_t)d.bra.slot_dim[k];
+      else r.nf1 = (uint32_t)d.bra.slot_dim[k];
+      ++nfree;
+    }
+  }
+  auto fcoef = [&](int src, int64_t c) {
+    if (src == -10) {
+      r.fy += c;
+      return;
+    }
+    r.fb[src] += c;
+    if (feed[src] >= 0) r.fk[feed[src]] += c;
+    else r.ff[free_of[src]] += c;
+  };
+  fcoef(d.fx_src, d.f_stride);
+  fcoef(d.fy_src, 1);
+  r.ny = d.ny;
+  r.ncol = d.ncol;
+  return r;
+}
+
+// expand, ket-parallel form: a thread holds the W values of one ket row and
+// column group (ny x NC, in registers) and loops over the free bra slots, so
+// every W row is read once; out is read-modify-written NC values at a time.
+template <typename T, int NC>
+__global__ __launch_bounds__(256) void k_couple_expand(ExpandPlan ep, const double* __restrict__ f,
+                                                       const T* __restrict__ W, T* __restrict__ out) {
+  const uint32_t nrows_k = ep.kdim[0] * ep.kdim[1] * ep.kdim[2] * ep.kdim[3];
+  const int64_t ng = (ep.ncol + NC - 1) / NC;
+  const int64_t total = (int64_t)nrows_k * ng;
+  const int64_t wlen = (int64_t)ep.ny * ep.ncol;
   for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
        g += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t rk = g / d.ncol, a = g % d.ncol;
-    int ek[4] = {0, 0, 0, 0}, e[4] = {0, 0, 0, 0};
-    decode_all(d.ket, rk, ek);
-    for (int l = 0; l < d.ket.nslot; ++l) e[d.ket_src[l]] = ek[l];
-    double wreg[8];
-    const T* w = W + rk * wlen + a;
-    for (int y = 0; y < d.ny; ++y) wreg[y] = (double)w[(int64_t)y * d.ncol];
-    for (int z0 = 0; z0 < n0; ++z0) {
-      if (nfree > 0) e[free_slot[0]] = z0;
-      for (int z1 = 0; z1 < n1; ++z1) {
-        if (nfree > 1) e[free_slot[1]] = z1;
-        double acc = 0.0;
-        for (int y = 0; y < d.ny; ++y)
-          acc += f[(int64_t)src_value(d.fx_src, e, z, y) * d.f_stride + src_value(d.fy_src, e, z, y)] *
-                 wreg[y];
-        out[encode_all(d.bra, e) * d.ncol + a] += (T)acc;
+    const int64_t rk = g / ng, c0 = (g - rk * ng) * NC;
+    uint32_t q = (uint32_t)rk;
+    const uint32_t k3 = q % ep.kdim[3];
+    q /= ep.kdim[3];
+    const uint32_t k2 = q % ep.kdim[2];
+    q /= ep.kdim[2];
+    const uint32_t k1 = q % ep.kdim[1];
+    const uint32_t k0 = q / ep.kdim[1];
+    const int64_t ob = k0 * ep.ob_k[0] + k1 * ep.ob_k[1] + k2 * ep.ob_k[2] + k3 * ep.ob_k[3];
+    const int64_t fo = k0 * ep.fk[0] + k1 * ep.fk[1] + k2 * ep.fk[2] + k3 * ep.fk[3];
+    double wreg[8][NC];
+    const T* w = W + rk * wlen + c0;
+#pragma unroll
+    for (int y = 0; y < 8; ++y)
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+        wreg[y][c] = (y < ep.ny && c0 + c < ep.ncol) ? (double)w[(int64_t)y * ep.ncol + c] : 0.0;
+    for (uint32_t z0 = 0; z0 < ep.nf0; ++z0)
+      for (uint32_t z1 = 0; z1 < ep.nf1; ++z1) {
+        const double* fr = f + fo + z0 * ep.ff[0] + z1 * ep.ff[1];
+        double acc[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+#pragma unroll
+        for (int y = 0; y < 8; ++y)
+          if (y < ep.ny) {
+            const double fv = fr[y * ep.fy];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) acc[c] += fv * wreg[y][c];
+          }
+        T* op = out + (ob + z0 * ep.ob_f[0] + z1 * ep.ob_f[1]) * ep.ncol + c0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+          if (c0 + c < ep.ncol) op[c] += (T)acc[c];
       }
-    }
   }
 }
 
-// expand, output-parallel form (for kets with few rows): one thread per
-// (bra row, alpha column); W rows are small and stay in cache.
-template <typename T>
-__global__ void k_couple_expand_out(CoupleDesc d, const double* __restrict__ f,
-                                    const T* __restrict__ W, T* __restrict__ out) {
-  int64_t nrows = 1;
-  for (int k = 0; k < d.bra.nslot; ++k) nrows *= d.bra.slot_dim[k];
-  const int64_t total = nrows * d.ncol;
-  const int64_t wlen = (int64_t)d.ny * d.ncol;
-  const int z[2] = {0, 0};
+// expand, output-parallel form (for kets with few rows): a thread per bra
+// row and column group; W rows are small and stay in cache.
+template <typename T, int NC>
+__global__ __launch_bounds__(256) void k_couple_expand_out(ExpandPlan ep, const double* __restrict__ f,
+                                                           const T* __restrict__ W, T* __restrict__ out) {
+  const uint32_t nrows = ep.bdim[0] * ep.bdim[1] * ep.bdim[2] * ep.bdim[3];
+  const int64_t ng = (ep.ncol + NC - 1) / NC;
+  const int64_t total = (int64_t)nrows * ng;
+  const int64_t wlen = (int64_t)ep.ny * ep.ncol;
   for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
        g += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t row = g / d.ncol, a = g % d.ncol;
-    int e[4] = {0, 0, 0, 0}, ek[4] = {0, 0, 0, 0};
-    decode_all(d.bra, row, e);
-    for (int l = 0; l < d.ket.nslot; ++l) ek[l] = e[d.ket_src[l]];
-    const T* w = W + encode_all(d.ket, ek) * wlen + a;
-    double acc = 0.0;
-    for (int y = 0; y < d.ny; ++y)
-      acc += f[(int64_t)src_value(d.fx_src, e, z, y) * d.f_stride + src_value(d.fy_src, e, z, y)] *
-             (double)w[(int64_t)y * d.ncol];
-    out[g] += (T)acc;
+    const int64_t row = g / ng, c0 = (g - row * ng) * NC;
+    uint32_t q = (uint32_t)row;
+    const uint32_t b3 = q % ep.bdim[3];
+    q /= ep.bdim[3];
+    const uint32_t b2 = q % ep.bdim[2];
+    q /= ep.bdim[2];
+    const uint32_t b1 = q % ep.bdim[1];
+    const uint32_t b0 = q / ep.bdim[1];
+    const int64_t rk = b0 * ep.wk_b[0] + b1 * ep.wk_b[1] + b2 * ep.wk_b[2] + b3 * ep.wk_b[3];
+    const double* fr = f + b0 * ep.fb[0] + b1 * ep.fb[1] + b2 * ep.fb[2] + b3 * ep.fb[3];
+    const T* w = W + rk * wlen + c0;
+    double acc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+#pragma unroll
+    for (int y = 0; y < 8; ++y)
+      if (y < ep.ny) {
+        const double fv = fr[y * ep.fy];
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+          if (c0 + c < ep.ncol) acc[c] += fv * (double)w[(int64_t)y * ep.ncol + c];
+      }
+    T* op = out + row * ep.ncol + c0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+      if (c0 + c < ep.ncol) op[c] += (T)acc[c];
   }
 }
 
@@ -154,99 +282,259 @@ hipError_t couple_expand(const CoupleDesc& d, const double* f, const T* W, T* ou
   for (int k = 0; k < d.ket.nslot; ++k) nrows_k *= d.ket.slot_dim[k];
   for (int k = 0; k < d.bra.nslot; ++k) nrows_b *= d.bra.slot_dim[k];
   if (nrows_b * d.ncol == 0) return hipSuccess;
-  if (nrows_k * d.ncol >= (int64_t)1 << 20) {
-    unsigned grid = cdiv(nrows_k * d.ncol, 256);
+  if (nrows_b >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+  // each ket slot feeds a distinct bra slot; at most two bra slots are free
+  {
+    int fed[4] = {0, 0, 0, 0};
+    for (int l = 0; l < d.ket.nslot; ++l) {
+      if (d.ket_src[l] < 0 || d.ket_src[l] >= d.bra.nslot || fed[d.ket_src[l]]) return hipErrorInvalidValue;
+      fed[d.ket_src[l]] = 1;
+    }
+    if (d.bra.nslot - d.ket.nslot > 2) return hipErrorInvalidValue;
+  }
+  const ExpandPlan ep = make_expand_plan(d);
+  const int nc = col_group(d.ncol);
+  const int64_t ng = (d.ncol + nc - 1) / nc;
+  if (nrows_k * ng >= (int64_t)1 << 18) {
+    unsigned grid = cdiv(nrows_k * ng, 256);
     if (grid > 65536) grid = 65536;
-    hipLaunchKernelGGL(k_couple_expand<T>, dim3(grid), dim3(256), 0, s, d, f, W, out_all);
+    CASPT2_NC_DISPATCH(nc, k_couple_expand, dim3(grid), ep, f, W, out_all)
   } else {
-    unsigned grid = cdiv(nrows_b * d.ncol, 256);
+    unsigned grid = cdiv(nrows_b * ng, 256);
     if (grid > 65536) grid = 65536;
-    hipLaunchKernelGGL(k_couple_expand_out<T>, dim3(grid), dim3(256), 0, s, d, f, W, out_all);
+    CASPT2_NC_DISPATCH(nc, k_couple_expand_out, dim3(grid), ep, f, W, out_all)
   }
   return hipGetLastError();
 }
 
-// reduce: a workgroup handles R bra rows; thread = (row, alpha column, z part);
-// partial sums over the summed external labels are combined through LDS.
-template <typename T>
-__global__ __launch_bounds__(256) void k_couple_reduce(CoupleDesc d, int P, int CT,
+// ---------------------------------------------------------------------------
+// reduce (down terms):  Y[e_b][y ncol + a] = sum_z f(e_b, z, y) X[e_k(e_b, z)][a]
+// The index maps are linear in the slot values, so the host folds them into
+// per-slot coefficients (ket row strides and f offsets); the kernel keeps the
+// slot values in registers (no per-thread arrays indexed at run time).
+// ---------------------------------------------------------------------------
+struct ReducePlan {
+  int nb;                 // bra slots
+  uint32_t bdim[4];       // bra all-orderings dims (1 beyond nb)
+  int64_t xs_b[4], xs_z[2];   // ket all-orderings row stride per bra slot / summed label
+  int64_t fs_b[4], fs_z[2], fs_y;
+  uint32_t nz1, nz;       // summed labels: z = z0 * nz1 + z1, nz = nz0 * nz1
+  int ksrc[4];            // ket slot sources (packed ket gather): bra slot k, or -1 - s
+  int ny;
+  int64_t ncol;
+};
+
+ReducePlan make_reduce_plan(const CoupleDesc& d) {
+  ReducePlan r{};
+  r.nb = d.bra.nslot;
+  for (int k = 0; k < 4; ++k) r.bdim[k] = k < d.bra.nslot ? (uint32_t)d.bra.slot_dim[k] : 1u;
+  int64_t kst[4] = {0, 0, 0, 0}, st = 1;
+  for (int l = d.ket.nslot - 1; l >= 0; --l) {
+    kst[l] = st;
+    st *= d.ket.slot_dim[l];
+  }
+  for (int l = 0; l < 4; ++l) r.ksrc[l] = 0;
+  for (int l = 0; l < d.ket.nslot; ++l) {
+    const int src = d.ket_src[l];
+    r.ksrc[l] = src;
+    if (src >= 0) r.xs_b[src] += kst[l];
+    else r.xs_z[-1 - src] += kst[l];
+  }
+  auto fcoef = [&](int src, int64_t c) {
+    if (src >= 0) r.fs_b[src] += c;
+    else if (src == -10) r.fs_y += c;
+    else r.fs_z[-1 - src] += c;
+  };
+  fcoef(d.fx_src, d.f_stride);
+  fcoef(d.fy_src, 1);
+  const uint32_t nz0 = d.nsum > 0 ? (uint32_t)d.sum_dim[0] : 1u;
+  r.nz1 = d.nsum > 1 ? (uint32_t)d.sum_dim[1] : 1u;
+  r.nz = nz0 * r.nz1;
+  r.ny = d.ny;
+  r.ncol = d.ncol;
+  return r;
+}
+
+__device__ inline int pick_src(int src, int e0, int e1, int e2, int e3, int z0, int z1) {
+  switch (src) {
+    case 0: return e0;
+    case 1: return e1;
+    case 2: return e2;
+    case 3: return e3;
+    case -1: return z0;
+    default: return z1;
+  }
+}
+
+// all-orderings values x[i, j, a, b][col .. col + VC) of the ccvv amplitude
+// (packed entries '+' (i >= j, a >= b) and '-' (i > j, a > b)), added with
+// weight fw into acc[y][.] for the nyv Fock values fv[y]
+template <typename T, int VC>
+__device__ inline void gather_ccvv(const PackInfo& p, const T* __restrict__ base, int i, int j, int a, int b,
+                                   int64_t col, int nvc, double v[VC]) {
+  const bool s0 = i < j, s1 = a < b;
+  const int hi0 = s0 ? j : i, lo0 = s0 ? i : j, hi1 = s1 ? b : a, lo1 = s1 ? a : b;
+  const int64_t nv = p.slot_dim[2];
+  const int64_t rp = ((int64_t)hi0 * (hi0 + 1) / 2 + lo0) * (nv * (nv + 1) / 2) + (int64_t)hi1 * (hi1 + 1) / 2 + lo1;
+  const T* xp = base + p.offset[0] + rp * p.rowlen + col;
+  const bool d0 = hi0 != lo0, d1 = hi1 != lo1;
+#pragma unroll
+  for (int c = 0; c < VC; ++c) v[c] = c < nvc ? (double)xp[c] : 0.0;
+  if (d0 && d1) {
+    const int64_t rm = ((int64_t)hi0 * (hi0 - 1) / 2 + lo0) * (nv * (nv - 1) / 2) + (int64_t)hi1 * (hi1 - 1) / 2 + lo1;
+    const double sg = (s0 != s1) ? -1.0 : 1.0;
+    const T* xm = base + p.offset[1] + rm * p.rowlen + col;
+#pragma unroll
+    for (int c = 0; c < VC; ++c) v[c] = 0.5 * (v[c] + (c < nvc ? sg * (double)xm[c] : 0.0));
+  } else if (d0 || d1) {
+#pragma unroll
+    for (int c = 0; c < VC; ++c) v[c] *= 0.70710678118654752440;
+  }
+}
+
+// a workgroup handles R bra rows; thread = (column group of VC columns, row,
+// z part); partial sums over the summed labels are combined through LDS
+template <typename T, bool PACKED, int VC>
+__global__ __launch_bounds__(256) void k_couple_reduce(ReducePlan rp, PackInfo pk, int P, int CG,
                                                        const double* __restrict__ f,
                                                        const T* __restrict__ X,
                                                        T* __restrict__ Y) {
   __shared__ double part[256 * 8];
-  int64_t nrows = 1;
-  for (int k = 0; k < d.bra.nslot; ++k) nrows *= d.bra.slot_dim[k];
-  const int per_row = CT * P;
-  const int R = 256 / per_row;
-  const int n0 = d.nsum > 0 ? d.sum_dim[0] : 1;
-  const int n1 = d.nsum > 1 ? d.sum_dim[1] : 1;
-  const int nz = n0 * n1;
+  const uint32_t nrows = rp.bdim[0] * rp.bdim[1] * rp.bdim[2] * rp.bdim[3];
+  const int R = 256 / (CG * P);
   const int t = threadIdx.x;
-  // lanes: column fastest, then row, then z part (coalesced row reads)
-  const int zp = t / (R * CT);
-  const int rr = t % (R * CT);
-  const int r = rr / CT;
-  const int64_t a = (int64_t)blockIdx.y * CT + rr % CT;
-  const bool acol = a < d.ncol;
-  const int64_t width = (int64_t)d.ny * d.ncol;
-  for (int64_t row0 = (int64_t)blockIdx.x * R; row0 < nrows; row0 += (int64_t)gridDim.x * R) {
+  const int zp = t / (R * CG);
+  const int rr = t % (R * CG);
+  const int r = rr / CG;
+  const int64_t a0 = ((int64_t)blockIdx.y * CG + rr % CG) * VC;
+  const int nvc = (int)(rp.ncol - a0 < VC ? rp.ncol - a0 : VC);
+  const bool acol = a0 < rp.ncol;
+  const int64_t width = (int64_t)rp.ny * rp.ncol;
+  for (int64_t row0 = (int64_t)blockIdx.x * R; row0 < (int64_t)nrows; row0 += (int64_t)gridDim.x * R) {
     const int64_t row = row0 + r;
-    const bool live = zp < P && row < nrows && acol;
-    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const bool live = zp < P && row < (int64_t)nrows && acol;
+    double acc[8][VC];
+#pragma unroll
+    for (int y = 0; y < 8; ++y)
+#pragma unroll
+      for (int c = 0; c < VC; ++c) acc[y][c] = 0.0;
     if (live) {
-      int e[4] = {0, 0, 0, 0};
-      decode_all(d.bra, row, e);
-      for (int zz = zp; zz < nz; zz += P) {
-        const int zv[2] = {zz / n1, zz % n1};
-        int ek[4] = {0, 0, 0, 0};
-        for (int l = 0; l < d.ket.nslot; ++l) ek[l] = src_value(d.ket_src[l], e, zv, 0);
-        const double xv = (double)X[encode_all(d.ket, ek) * d.ncol + a];
-        for (int y = 0; y < d.ny; ++y)
-          acc[y] += f[(int64_t)src_value(d.fx_src, e, zv, y) * d.f_stride + src_value(d.fy_src, e, zv, y)] * xv;
+      uint32_t q = (uint32_t)row;
+      const uint32_t b3 = q % rp.bdim[3];
+      q /= rp.bdim[3];
+      const uint32_t b2 = q % rp.bdim[2];
+      q /= rp.bdim[2];
+      const uint32_t b1 = q % rp.bdim[1];
+      const uint32_t b0 = q / rp.bdim[1];   // slots beyond nb have dim 1: value 0
+      const int64_t xb = b0 * rp.xs_b[0] + b1 * rp.xs_b[1] + b2 * rp.xs_b[2] + b3 * rp.xs_b[3];
+      const int64_t fb = b0 * rp.fs_b[0] + b1 * rp.fs_b[1] + b2 * rp.fs_b[2] + b3 * rp.fs_b[3];
+      for (uint32_t zz = zp; zz < rp.nz; zz += P) {
+        const uint32_t z0 = zz / rp.nz1, z1 = zz - z0 * rp.nz1;
+        double xv[VC];
+        if (PACKED) {
+          const int k0 = pick_src(rp.ksrc[0], b0, b1, b2, b3, z0, z1);
+          const int k1 = pick_src(rp.ksrc[1], b0, b1, b2, b3, z0, z1);
+          const int k2 = pick_src(rp.ksrc[2], b0, b1, b2, b3, z0, z1);
+          const int k3 = pick_src(rp.ksrc[3], b0, b1, b2, b3, z0, z1);
+          gather_ccvv<T, VC>(pk, X, k0, k1, k2, k3, a0, nvc, xv);
+        } else {
+          const T* xp = X + (xb + z0 * rp.xs_z[0] + z1 * rp.xs_z[1]) * rp.ncol + a0;
+#pragma unroll
+          for (int c = 0; c < VC; ++c) xv[c] = c < nvc ? (double)xp[c] : 0.0;
+        }
+        const double* fr = f + fb + z0 * rp.fs_z[0] + z1 * rp.fs_z[1];
+#pragma unroll
+        for (int y = 0; y < 8; ++y)
+          if (y < rp.ny) {
+            const double fv = fr[y * rp.fs_y];
+#pragma unroll
+            for (int c = 0; c < VC; ++c) acc[y][c] += fv * xv[c];
+          }
       }
     }
-    for (int y = 0; y < 8; ++y) part[y * 256 + t] = acc[y];
-    __syncthreads();
-    if (live && zp == 0) {
-      for (int y = 0; y < d.ny; ++y) {
-        double sum = 0.0;
-        for (int q = 0; q < P; ++q) sum += part[y * 256 + t + q * R * CT];
-        Y[row * width + (int64_t)y * d.ncol + a] = (T)sum;
+#pragma unroll
+    for (int c = 0; c < VC; ++c) {
+#pragma unroll
+      for (int y = 0; y < 8; ++y) part[y * 256 + t] = acc[y][c];
+      __syncthreads();
+      if (live && zp == 0 && c < nvc) {
+        for (int y = 0; y < rp.ny; ++y) {
+          double sum = 0.0;
+          for (int qq = 0; qq < P; ++qq) sum += part[y * 256 + t + qq * R * CG];
+          Y[row * width + (int64_t)y * rp.ncol + a0 + c] = (T)sum;
+        }
       }
+      __syncthreads();
     }
-    __syncthreads();
   }
 }
 
-template <typename T>
-hipError_t couple_reduce(const CoupleDesc& d, const double* f, const T* X, T* Y,
+template <typename T, bool PACKED, int VC>
+hipError_t launch_reduce_vc(const CoupleDesc& d, const PackInfo& pk, const double* f, const T* X, T* Y,
+                            hipStream_t s) {
+  int64_t nrows = 1;
+  for (int k = 0; k < d.bra.nslot; ++k) nrows *= d.bra.slot_dim[k];
+  const ReducePlan rp = make_reduce_plan(d);
+  const int nz = (int)rp.nz;
+  const int64_t ngroups = (d.ncol + VC - 1) / VC;
+  const int CG = (int)(ngroups < 64 ? ngroups : 64);
+  // rows per wave first (coalesced ket rows), then z parts; with few bra
+  // rows, spread the summed labels over more lanes
+  auto zparts = [&](int rw) {
+    int p = 1;
+    while (p * 2 <= nz && p * 2 * rw * CG <= 256) p *= 2;
+    return p;
+  };
+  int Rw = 1;
+  while (Rw * 2 * CG <= 64) Rw *= 2;
+  while (Rw > 1 && nrows * CG * zparts(Rw) < ((int64_t)1 << 20)) Rw /= 2;
+  const int P = zparts(Rw);
+  const int R = 256 / (CG * P);
+  unsigned gx = cdiv(nrows, R);
+  if (gx > 65536) gx = 65536;
+  const unsigned gy = cdiv(ngroups, CG);
+  hipLaunchKernelGGL((k_couple_reduce<T, PACKED, VC>), dim3(gx, gy), dim3(256), 0, s, rp, pk, P, CG, f, X, Y);
+  return hipGetLastError();
+}
+
+template <typename T, bool PACKED>
+hipError_t launch_reduce(const CoupleDesc& d, const PackInfo& pk, const double* f, const T* X, T* Y,
                          hipStream_t s) {
   if (d.ny > 8) return hipErrorInvalidValue;
   int64_t nrows = 1;
   for (int k = 0; k < d.bra.nslot; ++k) nrows *= d.bra.slot_dim[k];
   if (nrows * d.ncol == 0) return hipSuccess;
-  const int n0 = d.nsum > 0 ? d.sum_dim[0] : 1;
-  const int n1 = d.nsum > 1 ? d.sum_dim[1] : 1;
-  const int nz = n0 * n1;
-  const int CT = (int)(d.ncol < 256 ? d.ncol : 256);
-  // rows per block: fill a wave with (row, column) pairs first
-  int Rw = 1;
-  while (Rw * 2 * CT <= 64) Rw *= 2;
-  int P = 1;
-  while (P * 2 <= nz && P * 2 * Rw * CT <= 256) P *= 2;
-  const int R = 256 / (CT * P);
-  unsigned gx = cdiv(nrows, R);
-  if (gx > 65536) gx = 65536;
-  const unsigned gy = cdiv(d.ncol, CT);
-  hipLaunchKernelGGL(k_couple_reduce<T>, dim3(gx, gy), dim3(256), 0, s, d, P, CT, f, X, Y);
-  return hipGetLastError();
+  if (nrows >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+  if (d.ncol == 1) return launch_reduce_vc<T, PACKED, 1>(d, pk, f, X, Y, s);
+  if (d.ncol == 2) return launch_reduce_vc<T, PACKED, 2>(d, pk, f, X, Y, s);
+  return launch_reduce_vc<T, PACKED, 4>(d, pk, f, X, Y, s);
+}
+
+template <typename T>
+hipError_t couple_reduce(const CoupleDesc& d, const double* f, const T* X, T* Y,
+                         hipStream_t s) {
+  return launch_reduce<T, false>(d, PackInfo{}, f, X, Y, s);
+}
+
+// the packed ket must be ccvv-shaped: slots (c, c, v, v), swaps (0,1) and
+// (2,3), entries '+' (1, 1) and '-' (-1, -1), rows of ncol values
+template <typename T>
+hipError_t couple_reduce_packed(const CoupleDesc& d, const PackInfo& pk, const double* f, const T* x,
+                                T* Y, hipStream_t s) {
+  if (pk.rowlen != d.ncol || pk.nslot != 4 || pk.nswap != 2 || pk.nent != 2 || pk.swap_k[0] != 0 ||
+      pk.swap_l[0] != 1 || pk.swap_k[1] != 2 || pk.swap_l[1] != 3 || pk.chi[0][0] != 1 || pk.chi[0][1] != 1 ||
+      pk.chi[1][0] != -1 || pk.chi[1][1] != -1 || d.ket.nslot != 4)
+    return hipErrorInvalidValue;
+  return launch_reduce<T, true>(d, pk, f, x, Y, s);
 }
 
 #define CASPT2_COUPLE_INSTANCES(T)                                                                  \
   template hipError_t unpack_all<T>(const PackInfo&, const AllDesc&, const T*, T*, hipStream_t);   \
   template hipError_t pack_acc<T>(const TermDesc&, const AllDesc&, const T*, T*, hipStream_t);     \
   template hipError_t couple_expand<T>(const CoupleDesc&, const double*, const T*, T*, hipStream_t); \
-  template hipError_t couple_reduce<T>(const CoupleDesc&, const double*, const T*, T*, hipStream_t);
+  template hipError_t couple_reduce<T>(const CoupleDesc&, const double*, const T*, T*, hipStream_t);  \
+  template hipError_t couple_reduce_packed<T>(const CoupleDesc&, const PackInfo&, const double*,     \
+                                              const T*, T*, hipStream_t);
 CASPT2_COUPLE_INSTANCES(double)
 CASPT2_COUPLE_INSTANCES(float)
 #undef CASPT2_COUPLE_INSTANCES

@@ -1,5 +1,12 @@
 // Device helpers shared by the HIP kernels: decoding of packed orbit rows,
 // gathering all-orderings values from packed rows, all-orderings indexing.
+//
+// Every loop over the (at most four) external slots has a fixed trip count
+// and is unrolled, and slot positions are compile-time constants after
+// unrolling, so the slot values live in registers: a per-thread array indexed
+// with a run-time value would be placed in scratch memory.  Swap pairs are
+// always adjacent slots (k, k + 1).  Row indices fit in 32 bits (checked by
+// the host), which keeps the index divisions in 32-bit arithmetic.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -9,39 +16,77 @@
 
 namespace caspt2 {
 
+// value of slot `src` of (e0..e3), of a summed label (-1 - s) or of the
+// operator's active label y (-10), by selection (no indexed array)
+__device__ inline int src_pick(int src, const int e[4], const int z[2], int y) {
+  int v = y;
+  v = src == 0 ? e[0] : v;
+  v = src == 1 ? e[1] : v;
+  v = src == 2 ? e[2] : v;
+  v = src == 3 ? e[3] : v;
+  v = src == -1 ? z[0] : v;
+  v = src == -2 ? z[1] : v;
+  return v;
+}
+__device__ inline int src_value(int src, const int e[4], const int z[2], int y) {
+  return src_pick(src, e, z, y);
+}
+
+// is slot k the first slot of a swap pair of d (returns the swap or -1)
+template <typename D>
+__device__ inline int swap_at(const D& d, int k) {
+  int s = -1;
+  if (d.nswap > 0 && d.swap_k[0] == k) s = 0;
+  if (d.nswap > 1 && d.swap_k[1] == k) s = 1;
+  return s;
+}
+
+__device__ inline void pair_from_rank(uint32_t p, bool strict, int& hi, int& lo) {
+  int64_t h;
+  if (strict) {
+    h = (int64_t)floor((sqrt(8.0 * (double)p + 1.0) + 1.0) * 0.5);
+    while (h * (h - 1) / 2 > (int64_t)p) --h;
+    while ((h + 1) * h / 2 <= (int64_t)p) ++h;
+    hi = (int)h;
+    lo = (int)((int64_t)p - h * (h - 1) / 2);
+  } else {
+    h = (int64_t)floor((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
+    while (h * (h + 1) / 2 > (int64_t)p) --h;
+    while ((h + 1) * (h + 2) / 2 <= (int64_t)p) ++h;
+    hi = (int)h;
+    lo = (int)((int64_t)p - h * (h + 1) / 2);
+  }
+}
+
+// orbit representative of packed row `row` of entry d: units from the last
+// slot backwards; a swap pair (k, k + 1) is one unit of rank pair_rank
 __device__ inline void decode_orbit(const TermDesc& d, int64_t row, int e[4]) {
-  // units from the last slot backwards; a swap pair (k, k+1) is one unit
-  int k = d.nslot - 1;
-  int64_t rem = row;
-  while (k >= 0) {
-    int sw = -1;
-    for (int s = 0; s < d.nswap; ++s)
-      if (d.swap_l[s] == k && d.swap_k[s] == k - 1) sw = s;
+  uint32_t rem = (uint32_t)row;
+  e[0] = e[1] = e[2] = e[3] = 0;
+  bool second = false;   // slot k is the second slot of a pair (already set)
+#pragma unroll
+  for (int k = 3; k >= 0; --k) {
+    if (k >= d.nslot) continue;
+    if (second) {
+      second = false;
+      continue;
+    }
+    // slot k closes a pair when slot k - 1 opens one
+    const int sw = k >= 1 ? swap_at(d, k - 1) : -1;
+    const uint32_t dim = (uint32_t)d.slot_dim[k];
     if (sw >= 0) {
-      const int64_t dim = d.slot_dim[k];
-      const int64_t cnt = d.strict[sw] ? dim * (dim - 1) / 2 : dim * (dim + 1) / 2;
-      const int64_t p = rem % cnt;
+      const bool strict = d.strict[sw] != 0;
+      const uint32_t cnt = strict ? dim * (dim - 1) / 2 : dim * (dim + 1) / 2;
+      const uint32_t p = rem % cnt;
       rem /= cnt;
-      int64_t hi;
-      if (d.strict[sw]) {
-        hi = (int64_t)floor((sqrt(8.0 * (double)p + 1.0) + 1.0) * 0.5);
-        while (hi * (hi - 1) / 2 > p) --hi;
-        while ((hi + 1) * hi / 2 <= p) ++hi;
-        e[k - 1] = (int)hi;
-        e[k] = (int)(p - hi * (hi - 1) / 2);
-      } else {
-        hi = (int64_t)floor((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
-        while (hi * (hi + 1) / 2 > p) --hi;
-        while ((hi + 1) * (hi + 2) / 2 <= p) ++hi;
-        e[k - 1] = (int)hi;
-        e[k] = (int)(p - hi * (hi + 1) / 2);
-      }
-      k -= 2;
+      int hi, lo;
+      pair_from_rank(p, strict, hi, lo);
+      if (k >= 1) e[k - 1] = hi;
+      e[k] = lo;
+      second = true;   // skip slot k - 1
     } else {
-      const int64_t dim = d.slot_dim[k];
       e[k] = (int)(rem % dim);
       rem /= dim;
-      k -= 1;
     }
   }
 }
@@ -54,41 +99,59 @@ __device__ inline int64_t pair_rank(int hi, int lo, bool strict) {
 // x[e] = sum_chi chi(pi_e) t_chi[orbit(e)] / sqrt(|orbit|)
 template <typename T>
 __device__ inline double gather_all(const PackInfo& p, const T* __restrict__ base, const int e[4],
-                             int64_t col) {
+                                    int64_t col) {
+  // canonical order of each swap pair and its flags
   int c[4] = {e[0], e[1], e[2], e[3]};
   int swapped[2] = {0, 0}, equal[2] = {0, 0}, ndist = 0;
-  for (int s = 0; s < p.nswap; ++s) {
-    const int k = p.swap_k[s], l = p.swap_l[s];
-    if (c[k] < c[l]) {
-      const int t = c[k];
-      c[k] = c[l];
-      c[l] = t;
-      swapped[s] = 1;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int s = swap_at(p, k);
+    if (s >= 0) {
+      const bool sw = c[k] < c[k + 1];
+      const int hi = sw ? c[k + 1] : c[k], lo = sw ? c[k] : c[k + 1];
+      c[k] = hi;
+      c[k + 1] = lo;
+      const int eq = hi == lo ? 1 : 0;
+      if (s == 0) {
+        swapped[0] = sw;
+        equal[0] = eq;
+      } else {
+        swapped[1] = sw;
+        equal[1] = eq;
+      }
+      ndist += 1 - eq;
     }
-    if (c[k] == c[l]) equal[s] = 1;
-    else ++ndist;
   }
-  const double w = 1.0 / sqrt((double)(1 << ndist));
+  const double w = ndist == 0 ? 1.0 : (ndist == 1 ? 0.70710678118654752440 : 0.5);
   double acc = 0.0;
-  for (int ent = 0; ent < p.nent; ++ent) {
+#pragma unroll
+  for (int ent = 0; ent < 2; ++ent) {
+    if (ent >= p.nent) continue;
     bool ok = true;
     double sg = 1.0;
-    for (int s = 0; s < p.nswap; ++s) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      if (s >= p.nswap) continue;
       if (equal[s] && p.chi[ent][s] < 0) ok = false;
       if (swapped[s]) sg *= p.chi[ent][s];
     }
     if (!ok) continue;
     int64_t row = 0;
-    for (int k = 0; k < p.nslot; ++k) {
-      int sw = -1;
-      for (int s = 0; s < p.nswap; ++s)
-        if (p.swap_k[s] == k) sw = s;
+    bool second = false;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (k >= p.nslot) continue;
+      if (second) {
+        second = false;
+        continue;
+      }
+      const int s = k < 3 ? swap_at(p, k) : -1;
       const int64_t d = p.slot_dim[k];
-      if (sw >= 0) {
-        const bool strict = p.chi[ent][sw] < 0;
+      if (s >= 0) {
+        const bool strict = p.chi[ent][s] < 0;
         const int64_t cnt = strict ? d * (d - 1) / 2 : d * (d + 1) / 2;
         row = row * cnt + pair_rank(c[k], c[k + 1], strict);
-        ++k;
+        second = true;
       } else {
         row = row * d + c[k];
       }
@@ -98,22 +161,42 @@ __device__ inline double gather_all(const PackInfo& p, const T* __restrict__ bas
   return w * acc;
 }
 
-__device__ inline int src_value(int src, const int e[4], const int z[2], int y) {
-  return src >= 0 ? e[src] : (src == -10 ? y : z[-1 - src]);
-}
-
 __device__ inline void decode_all(const AllDesc& a, int64_t row, int e[4]) {
-  for (int k = a.nslot - 1; k >= 0; --k) {
-    e[k] = (int)(row % a.slot_dim[k]);
-    row /= a.slot_dim[k];
+  uint32_t q = (uint32_t)row;
+  e[0] = e[1] = e[2] = e[3] = 0;
+#pragma unroll
+  for (int k = 3; k >= 0; --k) {
+    if (k >= a.nslot) continue;
+    const uint32_t dim = (uint32_t)a.slot_dim[k];
+    e[k] = (int)(q % dim);
+    q /= dim;
   }
 }
 
 __device__ inline int64_t encode_all(const AllDesc& a, const int e[4]) {
   int64_t row = 0;
-  for (int k = 0; k < a.nslot; ++k) row = row * a.slot_dim[k] + e[k];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (k < a.nslot) row = row * a.slot_dim[k] + e[k];
   return row;
 }
 
+// e[swap pair of swap s] exchanged (the pair is adjacent: (swap_k, swap_k + 1))
+template <typename D>
+__device__ inline void swap_pair(const D& d, int s, int e[4]) {
+  const int k = d.swap_k[s];
+  int t;
+  if (k == 0) { t = e[0]; e[0] = e[1]; e[1] = t; }
+  if (k == 1) { t = e[1]; e[1] = e[2]; e[2] = t; }
+  if (k == 2) { t = e[2]; e[2] = e[3]; e[3] = t; }
+}
+
+// first and second slot value of swap s
+template <typename D>
+__device__ inline void pair_values(const D& d, int s, const int e[4], int& a, int& b) {
+  const int k = d.swap_k[s];
+  a = k == 0 ? e[0] : (k == 1 ? e[1] : e[2]);
+  b = k == 0 ? e[1] : (k == 1 ? e[2] : e[3]);
+}
 
 }  // namespace caspt2

@@ -152,6 +152,11 @@ hipError_t couple_expand(const CoupleDesc& d, const double* f, const T* W, T* ou
 template <typename T>
 hipError_t couple_reduce(const CoupleDesc& d, const double* f, const T* X, T* Y,
                          hipStream_t s);
+// reduce reading the ket from its packed rows (pk: packed layout of the ket
+// block, offsets relative to x) instead of an all-orderings copy
+template <typename T>
+hipError_t couple_reduce_packed(const CoupleDesc& d, const PackInfo& pk, const double* f, const T* x,
+                                T* Y, hipStream_t s);
 
 // X0[i][k] = Q[i][idx[k]] * scale[k]  (Q is n x ncq, X0 is n x nk)
 hipError_t select_scale_cols(int64_t n, int64_t ncq, const double* Q, const int32_t* idx,
@@ -177,6 +182,48 @@ hipError_t vec_scale_copy(int64_t n, double a, const X* x, Y* y, hipStream_t s);
 template <typename T>
 hipError_t vec_fill(int64_t n, double v, T* y, hipStream_t s);
 hipError_t vec_min(int64_t n, const double* x, double* partial, double* out, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// grouped PCG over many linear systems with device-resident scalars
+// ---------------------------------------------------------------------------
+constexpr int PCG_THREADS = 256;
+constexpr int64_t PCG_CHUNK = 16384;   // elements of one system per block
+enum { PCG_T = 0, PCG_R = 1, PCG_P = 2, PCG_Q = 3, PCG_D = 4, PCG_NVEC = 5 };
+enum { PCG_IDLE = 0, PCG_RUNNING = 1, PCG_CONVERGED = 2, PCG_INDEFINITE = 3, PCG_MAXITER = 4 };
+// per-system vectors (orthonormal basis, length n): solution t, residual r,
+// search direction p, q = A p, preconditioner denominators D
+template <typename T>
+struct PcgVecs {
+  T* vec[PCG_NVEC];
+};
+// per-system scalars (device); tol2 = tolerance on |r|^2
+struct PcgScalars {
+  double rz, rr, alpha, beta, tol2, pap;   // pap: last p.Ap
+  int32_t iters, maxiter, status, active;
+};
+// block table: block b works on elements [blk_start, blk_end) of system blk_sys
+struct PcgTable {
+  int nblk;
+  const int32_t* blk_sys;
+  const int64_t* blk_start;
+  const int64_t* blk_end;
+};
+// per-system view of the same table: system sys_id[k] owns blocks [b0[k], b1[k])
+struct PcgSysTable {
+  int nsys;
+  const int32_t* sys_id;
+  const int32_t* b0;
+  const int32_t* b1;
+};
+// z = r / D, p = z, rz = r.z, rr = r.r; running unless rr <= tol2
+template <typename T>
+hipError_t pcg_init(const PcgTable& tab, const PcgSysTable& st, const PcgVecs<T>* v, PcgScalars* sc,
+                    double* part_rr, double* part_rz, hipStream_t s);
+// one PCG step after q = A p: alpha, t += alpha p, r -= alpha q, z = r / D,
+// convergence test, beta, p = z + beta p (systems no longer active keep t)
+template <typename T>
+hipError_t pcg_step(const PcgTable& tab, const PcgSysTable& st, const PcgVecs<T>* v, PcgScalars* sc,
+                    double* part_a, double* part_b, hipStream_t s);
 
 // small dense symmetric eigenproblem on one thread (n <= 16): A -> values w
 // ascending, vectors R (columns, largest-magnitude entry positive)

@@ -199,7 +199,10 @@ def make_problem(nc: int, na: int, nv: int, naux: int, nst: int, seed: int,
     clo, vir = slice(0, nc), slice(nc + na, nmo)
     for (b1, b2) in ((clo, act), (act, vir), (clo, vir)):
         n1, n2 = b1.stop - b1.start, b2.stop - b2.start
-        blk = coupling_sigma * rng.standard_normal((n1, n2))
+        # entries scaled by 1/sqrt(max(n1, n2)): the spectral norm of each
+        # off-diagonal block stays about 2 coupling_sigma at any orbital-space
+        # size, so the couplings remain small next to the orbital-energy gaps
+        blk = coupling_sigma / math.sqrt(max(n1, n2, 1)) * rng.standard_normal((n1, n2))
         hcore[b1, b2] = blk
         hcore[b2, b1] = blk.T
 
