@@ -27,7 +27,7 @@ if ROOT not in sys.path:
 
 # (nc, na, nv, naux, nst, seed, shift) and a short name
 WORKLOADS = {
-    "full": ((30, 8, 400, 1500, 4, 2, 0.2), "XMS-CASPT2 MS-MR 30c/8a(8e)/400v naux 1500, 4 states, shift 0.2"),
+    "full": ((30, 8, 400, 1500, 4, 8, 0.2), "XMS-CASPT2 MS-MR 30c/8a(8e)/400v naux 1500, 4 states, shift 0.2"),
     "mid": ((10, 6, 120, 400, 3, 1, 0.2), "XMS-CASPT2 MS-MR 10c/6a(6e)/120v naux 400, 3 states, shift 0.2"),
     "small": ((4, 4, 20, 60, 1, 0, 0.0), "CASPT2 4c/4a(4e)/20v naux 60, 1 state, no shift"),
 }
@@ -36,22 +36,107 @@ HBM_PEAK_GBS = 8000.0
 
 def _pmc_traffic(entry, workload, reading):
     """HBM bytes per launch of the dominant kernel from the committed
-    rocprofv3 PMC summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of
-    known size), or None when no summary matches this kernel source."""
-    import hashlib
+    rocprofv3 PMC summary (FETCH_SIZE + WRITE_SIZE, scaled by calibration
+    kernels of known traffic), or None when no summary matches the current
+    source of that kernel."""
+    from paper_1606_01273_amd.rocprof_summary import rows_kernel_source_sha256
     path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    src = os.path.join(ROOT, "paper_1606_01273_amd", "csrc", "kernels.hip")
-    with open(src, "rb") as fh:
-        digest = hashlib.sha256(fh.read()).hexdigest()
-    key = f"{workload}/{reading}/{entry}"
-    r = rec.get(key)
-    if not r or r.get("kernels_sha256") != digest:
+    r = rec.get(f"{workload}/{reading}/{entry}")
+    if not r or r.get("kernel_source_sha256") != rows_kernel_source_sha256():
         return None
     return r.get("bytes_per_launch")
+
+
+def _solve_all(g, tol, maxiter=400):
+    """amplitudes, H_eff and lambda (target 0) of one handle; seconds and results"""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, info = g.solve_amplitudes(tol=tol, maxiter=maxiter)
+    H, w, R = g.heff()
+    rc2, linfo = g.solve_lambda(0, tol=tol, maxiter=maxiter)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, (rc, rc2), info, linfo, w
+
+
+def _precision_compare(workload, reading, tol):
+    """FP64 and mixed-precision (FP64 refinement around FP32 PCG) solves of
+    the same problem: time to solution and the differences of E_MS and lambda."""
+    import numpy as np
+    import torch
+    from synth.gen import make_problem
+    from paper_1606_01273_amd import FP64, MIXED, Caspt2
+    (nc, na, nv, naux, nst, seed, shift), wname = WORKLOADS[workload]
+    prob = make_problem(nc, na, nv, naux, nst, seed, reading=reading, shift=shift)
+    out = {"workload": wname, "reading": reading, "tol": tol}
+    ref = None
+    for name, prec in (("fp64", FP64), ("mixed", MIXED)):
+        g = Caspt2.from_problem(prob, precision=prec)
+        dt, rcs, info, linfo, w = _solve_all(g, tol)
+        lam = [g.lam(L) for L in range(nst)]
+        rec = {"seconds": round(dt, 3), "status": list(rcs), "amp_iters": [i["iters"] for i in info],
+               "lambda_iters": [i["iters"] for i in linfo], "e_ms": [float(v) for v in w]}
+        if name == "mixed":
+            rec["refinements"] = [i["refinements"] for i in info + linfo]
+            rec["max_abs_dE_ms_vs_fp64"] = float(np.abs(np.asarray(w) - ref[0]).max())
+            scale = max(float(torch.linalg.vector_norm(v)) for v in ref[1])
+            rec["max_rel_dlambda_vs_fp64"] = max(float(torch.linalg.vector_norm(a - b)) / scale
+                                                 for a, b in zip(lam, ref[1]))
+            rec["speedup_vs_fp64"] = round(out["fp64"]["seconds"] / dt, 3)
+        else:
+            ref = (np.asarray(w).copy(), lam)
+        out[name] = rec
+        del lam
+        g.close()
+        print(f"[bench] {workload}/{reading} {name} solves in {dt:.2f} s", file=sys.stderr, flush=True)
+    return out
+
+
+def _batch_compare(n, seed, reading, tol):
+    """n uneven problems: one batched solve (amplitudes, H_eff, lambda of all
+    problems interleaved) against the same solves one problem at a time."""
+    import numpy as np
+    import torch
+    from synth.gen import batch_sizes, make_problem
+    from paper_1606_01273_amd import E_INDEFINITE, Caspt2, Caspt2Error, batch_solve
+    sizes = batch_sizes(n, seed=seed)
+    t0 = time.perf_counter()
+    gs = [Caspt2.from_problem(make_problem(nc, na, nv, nx, ns, seed=sd, reading=reading, shift=0.2))
+          for nc, na, nv, nx, ns, sd in sizes]
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    print(f"[bench] batch of {n}: set-up {t_setup:.1f} s", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    rc, ainfo, linfo = batch_solve(gs, [0] * n, tol=tol, maxiter=400)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    ok = [all(a["flags"] & 1 for a in ai) and all(b["flags"] & 1 for b in li) for ai, li in zip(ainfo, linfo)]
+    e_b = [g.heff()[1].copy() if k else None for g, k in zip(gs, ok)]
+    print(f"[bench] batched solve {t_batch:.2f} s, {sum(ok)}/{n} solved", file=sys.stderr, flush=True)
+    t_seq, dmax, bad = 0.0, 0.0, []
+    for i, g in enumerate(gs):
+        try:
+            dt, rcs, info, li, w = _solve_all(g, tol)
+        except Caspt2Error as ex:
+            if ex.code != E_INDEFINITE:
+                raise
+            bad.append(i)
+            continue
+        t_seq += dt
+        if e_b[i] is not None:
+            dmax = max(dmax, float(np.abs(np.asarray(w) - e_b[i]).max()))
+    for g in gs:
+        g.close()
+    return {"instances": n, "sizes_seed": seed, "reading": reading, "shift": 0.2, "tol": tol,
+            "solved": int(sum(ok)), "indefinite_instances": bad, "setup_s": round(t_setup, 2),
+            "seconds_batched": round(t_batch, 3), "seconds_one_by_one": round(t_seq, 3),
+            "speedup": round(t_seq / t_batch, 3) if t_batch > 0 else None,
+            "max_abs_dE_ms_batched_vs_one_by_one": dmax,
+            "systems": int(sum(len(a) for a in ainfo) * 2)}
 
 
 def _cpu_worker(conn, dims, reading, sample_nv, min_seconds):
@@ -93,10 +178,15 @@ def main():
     ap.add_argument("--cpu-sample-nv", type=int, default=24)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--solve", action="store_true",
-                    help="also time the amplitude, H_eff and lambda solves in FP64 and in mixed precision")
+                    help="also time the amplitude, H_eff and lambda solves of the timed workload in FP64 "
+                         "and in mixed precision")
     ap.add_argument("--solve-tol", type=float, default=1e-10)
+    ap.add_argument("--precision-workload", default="mid",
+                    help="workload of the mixed-precision comparison (reading B); 'none' to skip")
+    ap.add_argument("--batch", type=int, default=64, help="problems in the batched-solve comparison (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="after the timed region, run a plain 1 GiB device copy (calibrates PMC byte counters)")
+                    help="after the timed region, run a 1 GiB fill and a 1 GiB element-wise multiply "
+                         "(known traffic for calibrating PMC byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: one GPU only; the per-state equations would shard by state and by batch "
@@ -149,9 +239,9 @@ def main():
     print(f"[bench] {args.steps} steps in {elapsed:.3f} s", file=sys.stderr, flush=True)
 
     if args.copy_calibration:
-        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
+        src = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+        src.fill_(1.0)                  # writes 1 GiB
+        dst = torch.mul(src, 2.0)       # reads 1 GiB, writes 1 GiB
         torch.cuda.synchronize()
         del src, dst
 
@@ -172,38 +262,25 @@ def main():
 
     solve = None
     if args.solve:
-        # amplitude + H_eff + lambda solves in FP64 and in mixed precision
-        # (FP64 refinement around FP32 PCG), same inputs, same tolerance
-        from paper_1606_01273_amd import MIXED
-        solve = {"tol": args.solve_tol}
-        ref = None
-        for name in ("fp64", "mixed"):
-            gg = g if name == "fp64" else Caspt2.from_problem(prob, precision=MIXED)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            rc, info = gg.solve_amplitudes(tol=args.solve_tol, maxiter=400)
-            H, w, R = gg.heff()
-            rc2, linfo = gg.solve_lambda(0, tol=args.solve_tol, maxiter=400)
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t0
-            lam = [gg.lam(L) for L in range(nst)]
-            rec = {"seconds": round(dt, 3), "status": [rc, rc2], "amp_iters": [i["iters"] for i in info],
-                   "lambda_iters": [i["iters"] for i in linfo], "e_ms": [float(v) for v in w],
-                   "lambda_norm": [float(torch.linalg.vector_norm(v)) for v in lam]}
-            if name == "mixed":
-                rec["refinements"] = [i["refinements"] for i in info] + [i["refinements"] for i in linfo]
-                rec["max_abs_dE_ms_vs_fp64"] = float(np.abs(np.asarray(w) - ref[0]).max())
-                scale = max(float(torch.linalg.vector_norm(v)) for v in ref[1])
-                rec["max_rel_dlambda_vs_fp64"] = max(float(torch.linalg.vector_norm(a - b)) / scale
-                                                     for a, b in zip(lam, ref[1]))
-                rec["speedup_vs_fp64"] = round(solve["fp64"]["seconds"] / dt, 3)
-                del lam
-                gg.close()
-            else:
-                ref = (np.asarray(w).copy(), lam)
-            solve[name] = rec
-            print(f"[bench] {name} solves in {dt:.2f} s", file=sys.stderr, flush=True)
-        ref = None
+        try:
+            solve = _precision_compare(args.workload, args.reading, args.solve_tol)
+        except Exception as ex:  # keep the headline line
+            solve = {"error": repr(ex)}
+    g.close()
+    del x, sig
+    torch.cuda.empty_cache()
+    precision = None
+    if args.precision_workload != "none":
+        try:
+            precision = _precision_compare(args.precision_workload, "B", args.solve_tol)
+        except Exception as ex:
+            precision = {"error": repr(ex)}
+    batch = None
+    if args.batch > 0:
+        try:
+            batch = _batch_compare(args.batch, 4, "B", args.solve_tol)
+        except Exception as ex:
+            batch = {"error": repr(ex)}
 
     cpu = None
     if child is not None:
@@ -233,8 +310,11 @@ def main():
            "roofline": roofline, "cpu_baseline": cpu, "per_entry": per_entry}
     if solve is not None:
         out["solve"] = solve
+    if precision is not None:
+        out["precision"] = precision
+    if batch is not None:
+        out["batch"] = batch
     print(json.dumps(out))
-    g.close()
 
 
 if __name__ == "__main__":

@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = ["engine.cpp", "kernels.hip", "couple.hip", "gemm_f32.hip", "pcg_kernels.hip", "caspt2.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-fvisibility=hidden", "-fvisibility-inlines-hidden",
-         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-Wl,--no-undefined"]   # every referenced symbol must be defined or in a linked library
 
 
 def build(verbose: bool = False) -> str:

@@ -99,6 +99,9 @@ struct Entry {
   int64_t nkeep = 0, ooff = 0;   // orthogonal-basis columns and offset
   DBuf S, F, X, mu, eps;          // S,F [nalpha^2]; X [nalpha][nkeep]; mu [nkeep]; eps [nrow]
   FBuf S32, F32, X32, eps32;      // FP32 copies for the inner solver (mixed precision)
+  DBuf epsA, epsB;                // separable row energies: eps(m) = A[m / nB] + B[m % nB]
+  FBuf epsA32, epsB32;
+  int64_t nB = 1;
   double emin_kept = INFINITY, emax_dropped = -1.0;
 };
 
@@ -120,6 +123,7 @@ struct Sel<double> {
   static const double* F(const Entry& e) { return e.F.p; }
   static const double* X(const Entry& e) { return e.X.p; }
   static const double* eps(const Entry& e) { return e.eps.p; }
+  static RowEnergy<double> rows(const Entry& e) { return RowEnergy<double>{e.epsA.p, e.epsB.p, (uint32_t)e.nB}; }
   static const double* G(const CoupleTerm& t) { return t.G.p; }
 };
 template <>
@@ -128,6 +132,7 @@ struct Sel<float> {
   static const float* F(const Entry& e) { return e.F32.p; }
   static const float* X(const Entry& e) { return e.X32.p; }
   static const float* eps(const Entry& e) { return e.eps32.p; }
+  static RowEnergy<float> rows(const Entry& e) { return RowEnergy<float>{e.epsA32.p, e.epsB32.p, (uint32_t)e.nB}; }
   static const float* G(const CoupleTerm& t) { return t.G32.p; }
 };
 
@@ -567,6 +572,19 @@ void row_energies(H& h, const Block& b, Entry& e) {
     d.scale = vir ? 1.0 : -1.0;
     HIPCHECK(term_source(d, epsd.p + (vir ? h.nc + h.na : 0), one.p, e.eps.p, h.s));
   }
+  // separable form: the first orbital unit (slot 0, or the swap pair (0, 1))
+  // indexes A, the remaining units B
+  int64_t nA = b.ext.empty() ? 1 : (b.ext[0].second == CLO ? h.nc : h.nv);
+  for (size_t sw = 0; sw < b.swaps.size(); ++sw)
+    if (b.swaps[sw].first == 0) {
+      const int64_t d = nA;
+      nA = e.chi[sw] < 0 ? d * (d - 1) / 2 : d * (d + 1) / 2;
+    }
+  if (nA <= 0 || e.nrow % nA != 0) throw DevError(CASPT2_E_DEVICE, "row energy split");
+  e.nB = e.nrow / nA;
+  e.epsA.alloc(nA);
+  e.epsB.alloc(e.nB);
+  HIPCHECK(split_energies(nA, e.nB, e.eps.p, e.epsA.p, e.epsB.p, h.s));
   host_sync(h);
 }
 
@@ -1214,8 +1232,8 @@ void residual(H& h, int L, const T* x, T* sig, bool with_source) {
       prof_begin(h, &ev);
       HIPCHECK(residual_rows<T>((int)e.nalpha, e.nrow, e2.nrow, x + e.offset, Sel<T>::S(e), Sel<T>::F(e),
                                 e2.nrow ? Sel<T>::S(e2) : nullptr, e2.nrow ? Sel<T>::F(e2) : nullptr,
-                                Sel<T>::eps(e), e2.nrow ? Sel<T>::eps(e2) : nullptr, (T)dshift, V,
-                                sig + e.offset, h.s));
+                                Sel<T>::rows(e), e2.nrow ? Sel<T>::rows(e2) : RowEnergy<T>{nullptr, nullptr, 1},
+                                (T)dshift, V, sig + e.offset, h.s));
       prof_end(h, (int)k, (with_source ? 3.0 : 2.0) * esz * (double)(e.nrow + e2.nrow) * e.nalpha, ev);
       ++k;
       continue;
@@ -1223,7 +1241,8 @@ void residual(H& h, int L, const T* x, T* sig, bool with_source) {
     prof_begin(h, &ev);
     if (e.nalpha <= 4)
       HIPCHECK(residual_rows<T>((int)e.nalpha, e.nrow, 0, x + e.offset, Sel<T>::S(e), Sel<T>::F(e), nullptr,
-                                nullptr, Sel<T>::eps(e), nullptr, (T)dshift, V, sig + e.offset, h.s));
+                                nullptr, Sel<T>::rows(e), RowEnergy<T>{nullptr, nullptr, 1}, (T)dshift, V,
+                                sig + e.offset, h.s));
     else if (e.nalpha <= 64)
       HIPCHECK(residual_small_t(e.nrow, e.nalpha, x + e.offset, Sel<T>::S(e), Sel<T>::F(e), Sel<T>::eps(e),
                                 dshift, V, sig + e.offset, h.s));
@@ -1409,6 +1428,8 @@ void setup_mixed(H& h) {
       cast(e.F, e.F32);
       cast(e.X, e.X32);
       cast(e.eps, e.eps32);
+      cast(e.epsA, e.epsA32);
+      cast(e.epsB, e.epsB32);
     }
   for (auto& cs : h.couple)
     for (auto& t : cs) {
@@ -1488,6 +1509,13 @@ void capture_operator(PcgSystem& S, hipStream_t s) {
 
 struct PcgEngine {
   hipStream_t s = nullptr;
+  // operator applications of different problems run concurrently on these
+  // streams (default priority; all systems of one problem share one stream,
+  // as they share its work vectors); the recurrence waits for all of them
+  std::vector<hipStream_t> lanes;
+  std::vector<hipEvent_t> lane_done;
+  hipEvent_t fork = nullptr;
+  std::map<const H*, int> lane_of;
   int capacity = 0;
   int check_every = 4;
   std::vector<std::unique_ptr<PcgSystem>> sys;
@@ -1501,15 +1529,36 @@ struct PcgEngine {
   PcgTable tab{};
   PcgSysTable st{};
 
-  explicit PcgEngine(int cap) : capacity(cap) {
+  explicit PcgEngine(int cap, int nlanes = 1) : capacity(cap) {
     HIPCHECK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    HIPCHECK(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+    for (int k = 0; k < std::max(1, nlanes); ++k) {
+      hipStream_t ls;
+      hipEvent_t ev;
+      HIPCHECK(hipStreamCreateWithFlags(&ls, hipStreamNonBlocking));
+      lanes.push_back(ls);
+      HIPCHECK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+      lane_done.push_back(ev);
+    }
     sc.alloc(cap);
     vecs.alloc(cap);
     hsc.assign(cap, PcgScalars{});
   }
   ~PcgEngine() {
+    if (s) (void)hipStreamSynchronize(s);
+    for (auto ls : lanes) (void)hipStreamSynchronize(ls);
     sys.clear();
+    for (auto ev : lane_done) (void)hipEventDestroy(ev);
+    for (auto ls : lanes) (void)hipStreamDestroy(ls);
+    if (fork) (void)hipEventDestroy(fork);
     if (s) (void)hipStreamDestroy(s);
+  }
+  int lane(const H* h) {
+    auto it = lane_of.find(h);
+    if (it != lane_of.end()) return it->second;
+    const int k = (int)(lane_of.size() % lanes.size());
+    lane_of.emplace(h, k);
+    return k;
   }
   PcgEngine(const PcgEngine&) = delete;
   PcgEngine& operator=(const PcgEngine&) = delete;
@@ -1638,8 +1687,20 @@ struct PcgEngine {
   void run(F&& on_poll) {
     on_poll(*this);
     while (!active.empty()) {
+      std::vector<int> used(lanes.size(), 0);
+      for (int id : active) used[lane(sys[id]->h)] = 1;
       for (int k = 0; k < check_every; ++k) {
-        for (int id : active) HIPCHECK(hipGraphLaunch(sys[id]->graph, s));
+        // fork: the lanes wait for the previous recurrence step
+        HIPCHECK(hipEventRecord(fork, s));
+        for (size_t l = 0; l < lanes.size(); ++l)
+          if (used[l]) HIPCHECK(hipStreamWaitEvent(lanes[l], fork, 0));
+        for (int id : active) HIPCHECK(hipGraphLaunch(sys[id]->graph, lanes[lane(sys[id]->h)]));
+        // join
+        for (size_t l = 0; l < lanes.size(); ++l)
+          if (used[l]) {
+            HIPCHECK(hipEventRecord(lane_done[l], lanes[l]));
+            HIPCHECK(hipStreamWaitEvent(s, lane_done[l], 0));
+          }
         HIPCHECK(pcg_step<double>(tab, st, vecs.p, sc.p, part_a.p, part_b.p, s));
       }
       poll();
@@ -2167,7 +2228,7 @@ int caspt2_batch_solve(caspt2_handle* const* handles, int32_t n, const int32_t* 
       cap += 2 * handles[i]->nst;
       off[i + 1] = off[i] + handles[i]->nst;
     }
-    PcgEngine eng(cap);
+    PcgEngine eng(cap, std::min(n, 4));   // four operator lanes (the hardware queues of a process)
     // phase per problem: 0 amplitudes running, 1 lambda running, 2 done, 3 failed
     std::vector<int> phase(n, 0), result(n, CASPT2_OK);
     std::vector<std::vector<int>> amp(n), lam(n);

@@ -324,8 +324,11 @@ hipError_t residual_small_f32(int64_t M, int64_t N, const float* X, const float*
 // ---------------------------------------------------------------------------
 // ccvv streaming residual: rows of NST doubles, two consecutive entries (the
 // '+' and '-' characters) in one launch.  Row m of entry c:
-//   C[m][n] = V[m][n] + (d[m] + dshift) sum_k X[m][k] S_c[k][n] + sum_k X[m][k] F_c[k][n]
-// S_c, F_c are NST x NST (kept in registers); one thread per row.
+//   C[m][n] = V[m][n] + (d_c(m) + dshift) sum_k X[m][k] S_c[k][n] + sum_k X[m][k] F_c[k][n]
+// S_c, F_c are NST x NST (kept in registers); one thread per row.  The row
+// energy is separable in the packed row index, d_c(m) = A_c[m / nB_c] +
+// B_c[m % nB_c] (first orbital unit / the rest; small tables that stay in
+// cache), so no per-row energy stream is read.
 // ---------------------------------------------------------------------------
 template <typename T, int NST>
 __global__ __launch_bounds__(256) void k_residual_rows(int64_t M0, int64_t M1,
@@ -334,8 +337,7 @@ __global__ __launch_bounds__(256) void k_residual_rows(int64_t M0, int64_t M1,
                                                        const T* __restrict__ F0,
                                                        const T* __restrict__ S1,
                                                        const T* __restrict__ F1,
-                                                       const T* __restrict__ d0,
-                                                       const T* __restrict__ d1, T dshift,
+                                                       RowEnergy<T> d0, RowEnergy<T> d1, T dshift,
                                                        const T* __restrict__ V,
                                                        T* __restrict__ C) {
   T s0[NST * NST], f0[NST * NST], s1[NST * NST], f1[NST * NST];
@@ -350,7 +352,10 @@ __global__ __launch_bounds__(256) void k_residual_rows(int64_t M0, int64_t M1,
   for (int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; m < total;
        m += (int64_t)gridDim.x * blockDim.x) {
     const bool second = m >= M0;
-    const T r = (second ? d1[m - M0] : d0[m]) + dshift;
+    const uint32_t mr = (uint32_t)(second ? m - M0 : m);
+    const RowEnergy<T>& de = second ? d1 : d0;
+    const uint32_t qa = mr / de.nB;
+    const T r = de.A[qa] + de.B[mr - qa * de.nB] + dshift;
     T x[NST], out[NST];
 #pragma unroll
     for (int k = 0; k < NST; ++k) x[k] = X[m * NST + k];
@@ -375,12 +380,14 @@ __global__ __launch_bounds__(256) void k_residual_rows(int64_t M0, int64_t M1,
 
 template <typename T>
 hipError_t residual_rows(int nst, int64_t M0, int64_t M1, const T* X, const T* S0, const T* F0,
-                         const T* S1, const T* F1, const T* d0, const T* d1, T dshift, const T* V,
-                         T* C, hipStream_t s) {
+                         const T* S1, const T* F1, RowEnergy<T> d0, RowEnergy<T> d1, T dshift,
+                         const T* V, T* C, hipStream_t s) {
   const int64_t total = M0 + M1;
   if (total <= 0) return hipSuccess;
+  if (M0 >= ((int64_t)1 << 31) || M1 >= ((int64_t)1 << 31) || d0.nB == 0 || (M1 > 0 && d1.nB == 0))
+    return hipErrorInvalidValue;
   unsigned grid = cdiv(total, 256);
-  if (grid > 8192) grid = 8192;
+  if (grid > 65536) grid = 65536;
   switch (nst) {
 #define CASPT2_ROWS(NS)                                                                        \
   case NS:                                                                                     \
@@ -397,17 +404,36 @@ hipError_t residual_rows(int nst, int64_t M0, int64_t M1, const T* X, const T* S
   }
   return hipGetLastError();
 }
-
-// ---------------------------------------------------------------------------
-// permuted accumulate and leading contraction
-// ---------------------------------------------------------------------------
 template hipError_t residual_rows<double>(int, int64_t, int64_t, const double*, const double*,
                                           const double*, const double*, const double*,
-                                          const double*, const double*, double, const double*,
+                                          RowEnergy<double>, RowEnergy<double>, double, const double*,
                                           double*, hipStream_t);
 template hipError_t residual_rows<float>(int, int64_t, int64_t, const float*, const float*,
-                                         const float*, const float*, const float*, const float*,
-                                         const float*, float, const float*, float*, hipStream_t);
+                                         const float*, const float*, const float*, RowEnergy<float>,
+                                         RowEnergy<float>, float, const float*, float*, hipStream_t);
+
+// separable row energies from the full table: A[a] = eps[a nB], B[b] =
+// eps[b] - eps[0] (eps(a nB + b) = A[a] + B[b] when eps is a sum of a
+// function of the first unit and a function of the rest)
+__global__ void k_split_energies(int64_t nA, int64_t nB, const double* __restrict__ eps,
+                                 double* __restrict__ A, double* __restrict__ B) {
+  const int64_t n = nA > nB ? nA : nB;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    if (g < nA) A[g] = eps[g * nB];
+    if (g < nB) B[g] = eps[g] - eps[0];
+  }
+}
+
+hipError_t split_energies(int64_t nA, int64_t nB, const double* eps, double* A, double* B,
+                          hipStream_t s) {
+  const int64_t n = nA > nB ? nA : nB;
+  if (n <= 0) return hipSuccess;
+  unsigned grid = cdiv(n, 256);
+  if (grid > 4096) grid = 4096;
+  hipLaunchKernelGGL(k_split_energies, dim3(grid), dim3(256), 0, s, nA, nB, eps, A, B);
+  return hipGetLastError();
+}
 
 // ---------------------------------------------------------------------------
 // row transform for narrow rows (nin, nout <= 8), one thread per row:
@@ -446,7 +472,7 @@ hipError_t transform_rows(int64_t M, int nin, int nout, const T* in, const T* W,
   if (M <= 0 || nout <= 0) return hipSuccess;
   if (nin < 0 || nin > 8 || nout > 8) return hipErrorInvalidValue;
   unsigned grid = cdiv(M, 256);
-  if (grid > 8192) grid = 8192;
+  if (grid > 65536) grid = 65536;
   hipLaunchKernelGGL(k_transform_rows<T>, dim3(grid), dim3(256), 0, s, M, nin, nout, in, W, ws_in,
                      ws_out, out);
   return hipGetLastError();

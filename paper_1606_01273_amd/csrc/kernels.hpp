@@ -35,13 +35,25 @@ hipError_t residual_small_f32(int64_t M, int64_t N, const float* X, const float*
                               const float* d, float dshift, const float* V, float* C,
                               hipStream_t s);
 
+// Row energies of a packed entry in separable form: eps(m) = A[m / nB] +
+// B[m % nB] (first orbital unit of the row / the remaining units).
+template <typename T>
+struct RowEnergy {
+  const T* A;
+  const T* B;
+  uint32_t nB;
+};
+// A[a] = eps[a nB], B[b] = eps[b] - eps[0]  (a < nA, b < nB)
+hipError_t split_energies(int64_t nA, int64_t nB, const double* eps, double* A, double* B,
+                          hipStream_t s);
+
 // Streaming residual of two consecutive packed entries with nalpha = nst
 // (<= 4), e.g. ccvv '+' and '-': rows [0, M0) use (S0, F0, d0), rows
 // [M0, M0+M1) use (S1, F1, d1).  X, V, C are [M0+M1][nst].  T: double, float.
 template <typename T>
 hipError_t residual_rows(int nst, int64_t M0, int64_t M1, const T* X, const T* S0, const T* F0,
-                         const T* S1, const T* F1, const T* d0, const T* d1, T dshift, const T* V,
-                         T* C, hipStream_t s);
+                         const T* S1, const T* F1, RowEnergy<T> d0, RowEnergy<T> d1, T dshift,
+                         const T* V, T* C, hipStream_t s);
 
 // C = alpha * A * op(B) + beta * C in FP32 (SIMT FMA, 64 x 64 tiles); same
 // operand conventions as gemm_f64.

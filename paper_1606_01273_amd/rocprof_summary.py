@@ -1,0 +1,139 @@
+"""Summaries of rocprofv3 output for the measurement record (text and JSON).
+
+  python -m paper_1606_01273_amd.rocprof_summary stats KERNEL_STATS_CSV OUT_TXT --command CMD
+  python -m paper_1606_01273_amd.rocprof_summary pmc FETCH_CSV WRITE_CSV OUT_JSON OUT_TXT \
+      --key WORKLOAD/READING/ENTRY --kernel REGEX --command-fetch CMD --command-write CMD
+
+The PMC form reads two counter-collection CSVs (one run with FETCH_SIZE, one
+with WRITE_SIZE, both in KiB per dispatch) and scales them with the same
+counters read for calibration kernels of known traffic run in the same
+process (a fill of 1 GiB: writes 1 GiB; an element-wise multiply of 1 GiB:
+reads 1 GiB and writes 1 GiB).  The HBM bytes per launch of the matched
+kernel are fetch * 1024 * fetch_scale + write * 1024 * write_scale.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import json
+import os
+import re
+import sys
+
+GIB = float(1 << 30)
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def rows_kernel_source_sha256() -> str:
+    """Hash of the source text of the streaming residual kernel (the region
+    from its template line to the separable-energy helper in kernels.hip): a
+    recorded traffic figure is valid only for this exact kernel source."""
+    path = os.path.join(HERE, "csrc", "kernels.hip")
+    with open(path) as fh:
+        src = fh.read()
+    a = src.index("template <typename T, int NST>\n__global__ __launch_bounds__(256) void k_residual_rows(")
+    b = src.index("// separable row energies from the full table")
+    return hashlib.sha256(src[a:b].encode()).hexdigest()
+
+
+def _per_dispatch(path: str, counter: str):
+    out = {}
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            if r.get("Counter_Name") != counter:
+                continue
+            out.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+    return out
+
+
+def cmd_stats(a):
+    with open(a.csv) as fh:
+        rows = list(csv.DictReader(fh))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    tot = sum(float(r["TotalDurationNs"]) for r in rows)
+    lines = [f"# rocprofv3 kernel-trace statistics", f"# command: {a.command}", "",
+             f"{'total ms':>10} {'calls':>7} {'avg us':>10} {'%':>6}  kernel"]
+    for r in rows[: a.top]:
+        name = re.sub(r"\s+", " ", r["Name"])[:110]
+        lines.append(f"{float(r['TotalDurationNs']) / 1e6:10.3f} {int(r['Calls']):7d} "
+                     f"{float(r['AverageNs']) / 1e3:10.2f} {100 * float(r['TotalDurationNs']) / tot:6.2f}  {name}")
+    with open(a.out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines[:12]))
+
+
+def cmd_pmc(a):
+    fetch = _per_dispatch(a.fetch_csv, "FETCH_SIZE")
+    write = _per_dispatch(a.write_csv, "WRITE_SIZE")
+    kre = re.compile(a.kernel)
+
+    def pick(d, pat):
+        vals = [v for k, vs in d.items() if re.search(pat, k) for v in vs]
+        return vals
+
+    kf, kw = pick(fetch, kre), pick(write, kre)
+    if not kf or not kw:
+        sys.exit(f"no dispatch of {a.kernel} in the counter files")
+    fill_w = pick(write, r"FillFunctor")
+    mul_f = pick(fetch, r"MulFunctor")
+    mul_w = pick(write, r"MulFunctor")
+    # calibration dispatches: the ones moving about 1 GiB
+    fill_w = [v for v in fill_w if v * 1024 > 0.5 * GIB]
+    mul_f = [v for v in mul_f if v * 1024 > 0.25 * GIB]
+    mul_w = [v for v in mul_w if v * 1024 > 0.5 * GIB]
+    if not fill_w or not mul_f:
+        sys.exit("calibration dispatches not found (run the bench with --copy-calibration)")
+    fetch_scale = GIB / (1024 * mul_f[-1])
+    write_scale = GIB / (1024 * fill_w[-1])
+    f_kib = sum(kf) / len(kf)
+    w_kib = sum(kw) / len(kw)
+    traffic = f_kib * 1024 * fetch_scale + w_kib * 1024 * write_scale
+    rec = {"bytes_per_launch": traffic, "fetch_kib_per_dispatch": f_kib, "write_kib_per_dispatch": w_kib,
+           "dispatches": [len(kf), len(kw)], "fetch_scale": fetch_scale, "write_scale": write_scale,
+           "calibration": {"fill_write_kib": fill_w[-1], "mul_fetch_kib": mul_f[-1],
+                           "mul_write_kib": mul_w[-1] if mul_w else None},
+           "kernel_regex": a.kernel, "kernel_source_sha256": rows_kernel_source_sha256(),
+           "command_fetch": a.command_fetch, "command_write": a.command_write}
+    db = {}
+    if os.path.exists(a.out_json):
+        with open(a.out_json) as fh:
+            db = json.load(fh)
+    db[a.key] = rec
+    with open(a.out_json, "w") as fh:
+        json.dump(db, fh, indent=1, sort_keys=True)
+    lines = [f"# rocprofv3 PMC traffic of {a.kernel} ({a.key})",
+             f"# FETCH_SIZE run: {a.command_fetch}", f"# WRITE_SIZE run: {a.command_write}", "",
+             f"dispatches (fetch, write): {len(kf)}, {len(kw)}",
+             f"FETCH_SIZE per dispatch: {f_kib:.1f} KiB   WRITE_SIZE per dispatch: {w_kib:.1f} KiB",
+             f"calibration: fill of 1 GiB -> WRITE_SIZE {fill_w[-1]:.1f} KiB (scale {write_scale:.4f}); "
+             f"multiply of 1 GiB -> FETCH_SIZE {mul_f[-1]:.1f} KiB (scale {fetch_scale:.4f})",
+             f"HBM bytes per launch: {traffic / 1e9:.4f} GB"]
+    with open(a.out_txt, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("csv")
+    s.add_argument("out")
+    s.add_argument("--command", required=True)
+    s.add_argument("--top", type=int, default=25)
+    p = sub.add_parser("pmc")
+    p.add_argument("fetch_csv")
+    p.add_argument("write_csv")
+    p.add_argument("out_json")
+    p.add_argument("out_txt")
+    p.add_argument("--key", required=True)
+    p.add_argument("--kernel", required=True)
+    p.add_argument("--command-fetch", required=True)
+    p.add_argument("--command-write", required=True)
+    a = ap.parse_args()
+    cmd_stats(a) if a.cmd == "stats" else cmd_pmc(a)
+
+
+if __name__ == "__main__":
+    main()
