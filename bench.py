@@ -79,7 +79,8 @@ def _precision_compare(workload, reading, tol):
         dt, rcs, info, linfo, w = _solve_all(g, tol)
         lam = [g.lam(L) for L in range(nst)]
         rec = {"seconds": round(dt, 3), "status": list(rcs), "amp_iters": [i["iters"] for i in info],
-               "lambda_iters": [i["iters"] for i in linfo], "e_ms": [float(v) for v in w]}
+               "lambda_iters": [i["iters"] for i in linfo], "e_ms": [float(v) for v in w],
+               "lambda_norm": [float(torch.linalg.vector_norm(v)) for v in lam]}
         if name == "mixed":
             rec["refinements"] = [i["refinements"] for i in info + linfo]
             rec["max_abs_dE_ms_vs_fp64"] = float(np.abs(np.asarray(w) - ref[0]).max())

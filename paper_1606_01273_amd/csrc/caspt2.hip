@@ -158,12 +158,12 @@ inline hipError_t residual_small_t(int64_t M, int64_t N, const float* X, const f
 }
 inline hipError_t residual_gemm_t(int64_t M, int64_t N, const double* X, const double* S,
                                   const double* F, const double* d, double dshift,
-                                  const double* V, double* C, hipStream_t s) {
-  return residual_gemm_f64(M, N, N, X, N, S, F, d, dshift, V, N, C, N, s);
+                                  const double* V, double* C, hipStream_t s, DBuf& ws) {
+  return residual_gemm_f64(M, N, N, X, N, S, F, d, dshift, V, N, C, N, s, ws.p, ws.n);
 }
 inline hipError_t residual_gemm_t(int64_t M, int64_t N, const float* X, const float* S,
                                   const float* F, const float* d, double dshift, const float* V,
-                                  float* C, hipStream_t s) {
+                                  float* C, hipStream_t s, DBuf&) {
   return residual_gemm_f32(M, N, N, X, N, S, F, d, (float)dshift, V, N, C, N, s);
 }
 
@@ -212,6 +212,7 @@ struct caspt2_handle {
   std::vector<std::vector<struct CoupleTerm>> couple;  // per function set
   DBuf cscratch;                                       // W / Y of the couplings
   DBuf wx, wsg;                                        // operator work vectors of the grouped solver
+  DBuf splitk_ws;                                      // partial products of the split-K residual GEMMs
   DBuf xall[NBLOCK], sall[NBLOCK];                      // all-orderings x and sigma per block
   bool direct[NBLOCK] = {};                            // ket read from packed rows (no all-orderings x)
   bool prof_on = false;
@@ -697,6 +698,15 @@ void setup_blocks(H& h) {
     host_sync(h);
     progress(h, "metrics and orthonormal bases of block " + b.name);
   }
+  // workspace of the split-K residual GEMMs (entries with few rows)
+  int64_t ws = 0;
+  for (auto& es : h.sets)
+    for (auto& e : es)
+      if (e.nrow > 0 && e.nalpha > 64) {
+        const int ns = residual_splitk(e.nrow, e.nalpha, e.nalpha);
+        if (ns > 1) ws = std::max(ws, (int64_t)ns * 2 * e.nrow * e.nalpha);
+      }
+  h.splitk_ws.alloc(ws);
   // offsets
   for (auto& set : h.sets) {
     int64_t off = 0, ooff = 0;
@@ -1248,7 +1258,7 @@ void residual(H& h, int L, const T* x, T* sig, bool with_source) {
                                 dshift, V, sig + e.offset, h.s));
     else
       HIPCHECK(residual_gemm_t(e.nrow, e.nalpha, x + e.offset, Sel<T>::S(e), Sel<T>::F(e), Sel<T>::eps(e),
-                               dshift, V, sig + e.offset, h.s));
+                               dshift, V, sig + e.offset, h.s, h.splitk_ws));
     prof_end(h, (int)k, (with_source ? 3.0 : 2.0) * esz * (double)e.nrow * e.nalpha, ev);
   }
   if (!h.couple.empty() && !h.couple[set].empty()) {

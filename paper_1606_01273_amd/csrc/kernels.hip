@@ -62,7 +62,9 @@ hipError_t launch_gather_apply(const double* X, int64_t nlead, int64_t dim_from,
 // ---------------------------------------------------------------------------
 constexpr int BM = 64, BN = 64, BK = 16, LDP = BK + 1;
 
-template <bool B_NK, bool DUAL>
+// SPLIT (dual only): blockIdx.z selects a K range of kchunk; the raw X S and
+// X F partial products go to C as [split][2][M][N] for a separate epilogue.
+template <bool B_NK, bool DUAL, bool SPLIT = false>
 __global__ __launch_bounds__(256) void k_gemm_f64(int64_t M, int64_t N, int64_t K, double alpha,
                                                   const double* __restrict__ A, int64_t lda,
                                                   int64_t sA, const double* __restrict__ B,
@@ -71,7 +73,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int64_t M, int64_t N, int64_t 
                                                   double* __restrict__ C, int64_t ldc, int64_t sC,
                                                   const double* __restrict__ dvec, double dshift,
                                                   const double* __restrict__ V, int64_t ldv,
-                                                  int m_on_x) {
+                                                  int m_on_x, int64_t kchunk) {
   __shared__ double As[BM][LDP];
   __shared__ double Bs[BN][LDP];
   __shared__ double B2s[DUAL ? BN : 1][LDP];
@@ -80,9 +82,15 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int64_t M, int64_t N, int64_t 
   const int wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int64_t bz = blockIdx.z;
-  A += bz * sA;
-  B += bz * sB;
-  C += bz * sC;
+  int64_t kb = 0, ke = K;
+  if (SPLIT) {
+    kb = bz * kchunk;
+    ke = kb + kchunk < K ? kb + kchunk : K;
+  } else {
+    A += bz * sA;
+    B += bz * sB;
+    C += bz * sC;
+  }
   // the longer tile dimension runs on grid x (y and z are limited to 65535)
   const int64_t m0 = (int64_t)(m_on_x ? blockIdx.x : blockIdx.y) * BM;
   const int64_t n0 = (int64_t)(m_on_x ? blockIdx.y : blockIdx.x) * BN;
@@ -92,14 +100,14 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int64_t M, int64_t N, int64_t 
       acc[i][j] = d4{0, 0, 0, 0};
       acc2[i][j] = d4{0, 0, 0, 0};
     }
-  for (int64_t k0 = 0; k0 < K; k0 += BK) {
+  for (int64_t k0 = kb; k0 < ke; k0 += BK) {
     // A tile: 64 rows x 16 k, 4 per thread
     {
       const int r = tid >> 2, c = (tid & 3) * 4;
       const int64_t gm = m0 + r;
       for (int u = 0; u < 4; ++u) {
         const int64_t gk = k0 + c + u;
-        As[r][c + u] = (gm < M && gk < K) ? A[gm * lda + gk] : 0.0;
+        As[r][c + u] = (gm < M && gk < ke) ? A[gm * lda + gk] : 0.0;
       }
     }
     if (B_NK) {
@@ -107,7 +115,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int64_t M, int64_t N, int64_t 
       const int64_t gn = n0 + r;
       for (int u = 0; u < 4; ++u) {
         const int64_t gk = k0 + c + u;
-        Bs[r][c + u] = (gn < N && gk < K) ? B[gn * ldb + gk] : 0.0;
+        Bs[r][c + u] = (gn < N && gk < ke) ? B[gn * ldb + gk] : 0.0;
       }
     } else {
       // B is [K][N]: thread loads k = tid/16, n = (tid%16)*4 .. +3
@@ -115,8 +123,8 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int64_t M, int64_t N, int64_t 
       const int64_t gk = k0 + kk;
       for (int u = 0; u < 4; ++u) {
         const int64_t gn = n0 + c + u;
-        Bs[c + u][kk] = (gn < N && gk < K) ? B[gk * ldb + gn] : 0.0;
-        if (DUAL) B2s[c + u][kk] = (gn < N && gk < K) ? B2[gk * ldb + gn] : 0.0;
+        Bs[c + u][kk] = (gn < N && gk < ke) ? B[gk * ldb + gn] : 0.0;
+        if (DUAL) B2s[c + u][kk] = (gn < N && gk < ke) ? B2[gk * ldb + gn] : 0.0;
       }
     }
     __syncthreads();
@@ -141,7 +149,11 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int64_t M, int64_t N, int64_t 
         const int64_t gm = m0 + wm * 32 + i * 16 + (lane >> 4) + 4 * v;
         const int64_t gn = n0 + wn * 32 + j * 16 + (lane & 15);
         if (gm < M && gn < N) {
-          if (DUAL) {
+          if (SPLIT) {
+            double* P = C + bz * 2 * M * N;
+            P[gm * N + gn] = acc[i][j][v];
+            P[M * N + gm * N + gn] = acc2[i][j][v];
+          } else if (DUAL) {
             double r = dvec[gm] + dshift;
             double val = r * acc[i][j][v] + acc2[i][j][v];
             if (V) val += V[gm * ldv + gn];
@@ -165,23 +177,71 @@ hipError_t gemm_f64(bool b_is_nk, int64_t M, int64_t N, int64_t K, double alpha,
   if (b_is_nk)
     hipLaunchKernelGGL((k_gemm_f64<true, false>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda,
                        sA, B, ldb, sB, (const double*)nullptr, beta, C, ldc, sC,
-                       (const double*)nullptr, 0.0, (const double*)nullptr, (int64_t)0, mx);
+                       (const double*)nullptr, 0.0, (const double*)nullptr, (int64_t)0, mx, (int64_t)0);
   else
     hipLaunchKernelGGL((k_gemm_f64<false, false>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda,
                        sA, B, ldb, sB, (const double*)nullptr, beta, C, ldc, sC,
-                       (const double*)nullptr, 0.0, (const double*)nullptr, (int64_t)0, mx);
+                       (const double*)nullptr, 0.0, (const double*)nullptr, (int64_t)0, mx, (int64_t)0);
   return hipGetLastError();
+}
+
+int residual_splitk(int64_t M, int64_t N, int64_t K) {
+  if (M <= 0 || N <= 0 || K < 8 * BK) return 1;
+  const int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+  if (tiles >= 512) return 1;
+  int64_t ns = 1024 / tiles;             // about 1024 workgroups in all
+  const int64_t maxs = K / (4 * BK);      // at least four K steps per split
+  if (ns > maxs) ns = maxs;
+  if (ns > 64) ns = 64;
+  return ns < 2 ? 1 : (int)ns;
+}
+
+// C[m][n] = V[m][n] + (d[m] + dshift) sum_z P[z][0][m][n] + sum_z P[z][1][m][n]
+__global__ void k_splitk_epilogue(int64_t M, int64_t N, int ns, const double* __restrict__ P,
+                                  const double* __restrict__ d, double dshift,
+                                  const double* __restrict__ V, int64_t ldv, double* __restrict__ C,
+                                  int64_t ldc) {
+  const int64_t total = M * N;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t m = g / N, n = g % N;
+    double xs = 0.0, xf = 0.0;
+    for (int z = 0; z < ns; ++z) {
+      xs += P[(int64_t)z * 2 * total + g];
+      xf += P[(int64_t)z * 2 * total + total + g];
+    }
+    double val = (d[m] + dshift) * xs + xf;
+    if (V) val += V[m * ldv + n];
+    C[m * ldc + n] = val;
+  }
 }
 
 hipError_t residual_gemm_f64(int64_t M, int64_t N, int64_t K, const double* X, int64_t ldx,
                              const double* S, const double* F, const double* d, double dshift,
-                             const double* V, int64_t ldv, double* C, int64_t ldc, hipStream_t s) {
+                             const double* V, int64_t ldv, double* C, int64_t ldc, hipStream_t s,
+                             double* ws, int64_t ws_len) {
   if (M <= 0 || N <= 0) return hipSuccess;
   dim3 grid;
   int mx;
   if (!tile_grid(M, N, 1, BM, BN, &grid, &mx)) return hipErrorInvalidValue;
+  const int ns = residual_splitk(M, N, K);
+  if (ns > 1 && ws && ws_len >= (int64_t)ns * 2 * M * N) {
+    // few output tiles: split K over ns workgroups per tile, then one epilogue
+    const int64_t kchunk = ((K + ns - 1) / ns + BK - 1) / BK * BK;
+    const int nsplit = (int)((K + kchunk - 1) / kchunk);
+    grid.z = nsplit;
+    hipLaunchKernelGGL((k_gemm_f64<false, true, true>), grid, dim3(256), 0, s, M, N, K, 1.0, X, ldx,
+                       (int64_t)0, S, N, (int64_t)0, F, 0.0, ws, N, (int64_t)0, d, dshift, V, ldv, mx,
+                       kchunk);
+    unsigned eg = (unsigned)((M * N + 255) / 256);
+    if (eg > 4096) eg = 4096;
+    hipLaunchKernelGGL(k_splitk_epilogue, dim3(eg), dim3(256), 0, s, M, N, nsplit, (const double*)ws, d,
+                       dshift, V, ldv, C, ldc);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL((k_gemm_f64<false, true>), grid, dim3(256), 0, s, M, N, K, 1.0, X, ldx,
-                     (int64_t)0, S, N, (int64_t)0, F, 0.0, C, ldc, (int64_t)0, d, dshift, V, ldv, mx);
+                     (int64_t)0, S, N, (int64_t)0, F, 0.0, C, ldc, (int64_t)0, d, dshift, V, ldv, mx,
+                     (int64_t)0);
   return hipGetLastError();
 }
 

@@ -22,9 +22,15 @@ hipError_t gemm_f64(bool b_is_nk, int64_t M, int64_t N, int64_t K, double alpha,
 // Residual of one packed entry on MFMA:
 //   C[m][n] = V[m][n] + d[m] * (X S)[m][n] + (X F)[m][n]   (V may be null)
 // X [M][K], S and F [K][N] row major (symmetric in use), d [M].
+// With few output tiles (small M) the K range is split over workgroups
+// (residual_splitk(M, N, K) splits, workspace ws of >= splits * 2 * M * N
+// doubles; without it the plain kernel runs).
 hipError_t residual_gemm_f64(int64_t M, int64_t N, int64_t K, const double* X, int64_t ldx,
                              const double* S, const double* F, const double* d, double dshift,
-                             const double* V, int64_t ldv, double* C, int64_t ldc, hipStream_t s);
+                             const double* V, int64_t ldv, double* C, int64_t ldc, hipStream_t s,
+                             double* ws = nullptr, int64_t ws_len = 0);
+// number of K splits residual_gemm_f64 uses for this shape (1: none)
+int residual_splitk(int64_t M, int64_t N, int64_t K);
 // Same for small K = N (<= 64): streaming kernel with S, F staged in LDS.
 hipError_t residual_small_f64(int64_t M, int64_t N, const double* X, const double* S,
                               const double* F, const double* d, double dshift, const double* V,
