@@ -61,6 +61,10 @@ hipError_t launch_gather_apply(const double* X, int64_t nlead, int64_t dim_from,
 //     D[i][j]: j = l % 16, i = l / 16 + 4 * v, v = 0..3 (checked on gfx950).
 // ---------------------------------------------------------------------------
 constexpr int BM = 64, BN = 64, BK = 16, LDP = BK + 1;
+// per-thread share of a K tile: A (and B as [N][K]) rows of UA consecutive k;
+// B as [K][N]: KT threads per k row, UB consecutive n each
+constexpr int UA = BM * BK / 256, KT = 256 / BK, UB = BN * BK / 256;
+static_assert(BM == 64 && BN == 64 && UA * 256 == BM * BK && KT * BK == 256, "tile shares");
 
 // SPLIT (dual only): blockIdx.z selects a K range of kchunk; the raw X S and
 // X F partial products go to C as [split][2][M][N] for a separate epilogue.
@@ -100,34 +104,65 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int64_t M, int64_t N, int64_t 
       acc[i][j] = d4{0, 0, 0, 0};
       acc2[i][j] = d4{0, 0, 0, 0};
     }
-  for (int64_t k0 = kb; k0 < ke; k0 += BK) {
-    // A tile: 64 rows x 16 k, 4 per thread
-    {
-      const int r = tid >> 2, c = (tid & 3) * 4;
+  // global -> registers -> LDS; the next K tile's loads are issued before
+  // the MFMAs of the current one (register prefetch), so their latency hides
+  // behind the matrix work
+  double ra[UA], rb[UA > UB ? UA : UB], rb2[UB];
+  auto load_tile = [&](int64_t k0) {
+    {  // A tile: 64 rows x BK k, UA per thread
+      const int r = tid >> 2, c = (tid & 3) * UA;
       const int64_t gm = m0 + r;
-      for (int u = 0; u < 4; ++u) {
+#pragma unroll
+      for (int u = 0; u < UA; ++u) {
         const int64_t gk = k0 + c + u;
-        As[r][c + u] = (gm < M && gk < ke) ? A[gm * lda + gk] : 0.0;
+        ra[u] = (gm < M && gk < ke) ? A[gm * lda + gk] : 0.0;
       }
     }
     if (B_NK) {
-      const int r = tid >> 2, c = (tid & 3) * 4;
+      const int r = tid >> 2, c = (tid & 3) * UA;
       const int64_t gn = n0 + r;
-      for (int u = 0; u < 4; ++u) {
+#pragma unroll
+      for (int u = 0; u < UA; ++u) {
         const int64_t gk = k0 + c + u;
-        Bs[r][c + u] = (gn < N && gk < ke) ? B[gn * ldb + gk] : 0.0;
+        rb[u] = (gn < N && gk < ke) ? B[gn * ldb + gk] : 0.0;
       }
     } else {
-      // B is [K][N]: thread loads k = tid/16, n = (tid%16)*4 .. +3
-      const int kk = tid >> 4, c = (tid & 15) * 4;
+      // B is [K][N]: thread loads k = tid / KT, n = (tid % KT) * UB .. + UB - 1
+      const int kk = tid / KT, c = (tid % KT) * UB;
       const int64_t gk = k0 + kk;
-      for (int u = 0; u < 4; ++u) {
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
         const int64_t gn = n0 + c + u;
-        Bs[c + u][kk] = (gn < N && gk < ke) ? B[gk * ldb + gn] : 0.0;
-        if (DUAL) B2s[c + u][kk] = (gn < N && gk < ke) ? B2[gk * ldb + gn] : 0.0;
+        const bool in = gn < N && gk < ke;
+        rb[u] = in ? B[gk * ldb + gn] : 0.0;
+        if (DUAL) rb2[u] = in ? B2[gk * ldb + gn] : 0.0;
       }
     }
+  };
+  auto store_tile = [&]() {
+    {
+      const int r = tid >> 2, c = (tid & 3) * UA;
+#pragma unroll
+      for (int u = 0; u < UA; ++u) As[r][c + u] = ra[u];
+    }
+    if (B_NK) {
+      const int r = tid >> 2, c = (tid & 3) * UA;
+#pragma unroll
+      for (int u = 0; u < UA; ++u) Bs[r][c + u] = rb[u];
+    } else {
+      const int kk = tid / KT, c = (tid % KT) * UB;
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
+        Bs[c + u][kk] = rb[u];
+        if (DUAL) B2s[c + u][kk] = rb2[u];
+      }
+    }
+  };
+  if (kb < ke) load_tile(kb);
+  for (int64_t k0 = kb; k0 < ke; k0 += BK) {
+    store_tile();
     __syncthreads();
+    if (k0 + BK < ke) load_tile(k0 + BK);
     for (int kk = 0; kk < BK; kk += 4) {
       double a[2], b[2], b2[2];
       for (int i = 0; i < 2; ++i) a[i] = As[wm * 32 + i * 16 + (lane & 15)][kk + (lane >> 4)];
@@ -190,7 +225,7 @@ int residual_splitk(int64_t M, int64_t N, int64_t K) {
   const int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
   if (tiles >= 512) return 1;
   int64_t ns = 1024 / tiles;             // about 1024 workgroups in all
-  const int64_t maxs = K / (4 * BK);      // at least four K steps per split
+  const int64_t maxs = K / (4 * BK);      // at least four K tiles per split
   if (ns > maxs) ns = maxs;
   if (ns > 64) ns = 64;
   return ns < 2 ? 1 : (int)ns;

@@ -214,8 +214,13 @@ def make_problem(nc: int, na: int, nv: int, naux: int, nst: int, seed: int,
             raise ValueError("more states than determinants")
         ci = v[:, :nst].T.copy()
         eref = w[:nst].copy()
+        # sign: the first determinant whose weight is within 1e-6 of the largest
+        # is positive (entries of equal magnitude by spin symmetry differ only
+        # by rounding, which varies between BLAS builds; a plain argmax would
+        # let that rounding pick the sign)
         for N in range(nst):
-            k = int(np.argmax(np.abs(ci[N])))
+            a = np.abs(ci[N])
+            k = int(np.flatnonzero(a >= (1.0 - 1e-6) * a.max())[0])
             if ci[N, k] < 0:
                 ci[N] = -ci[N]
         d_sa = np.zeros((na, na))
@@ -297,3 +302,13 @@ def batch_sizes(n: int = 64, seed: int = 4):
         child = int(kids[k].generate_state(1)[0])
         out.append((nc, na, nv, 3 * (nc + na + nv), nst, child))
     return out
+
+
+def random_vector(n: int, seed: int) -> np.ndarray:
+    """Seeded standard-normal vector (trial amplitudes for residual checks)."""
+    return np.random.default_rng(seed).standard_normal(n)
+
+
+def sample_positions(n: int, k: int, seed: int) -> np.ndarray:
+    """k distinct sorted positions in [0, n), seeded."""
+    return np.sort(np.random.default_rng(seed).choice(n, k, replace=False))

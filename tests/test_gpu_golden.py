@@ -1,0 +1,100 @@
+"""Parity beyond the oracle's interactive sizes.
+
+* Mid size (10 closed, 6 active, 120 virtual, 400 auxiliary, 3 states,
+  Fock couplings on): stored oracle values in tests/golden/mid_B.json, written
+  by tests/golden/make_golden.py (which calls the oracle only): the residual
+  of Eq. 10 at 64 sampled positions, E^MS, and the norms of T and lambda.
+  FP64 bars: 1e-12 relative on the residual, 1e-10 Eh, 1e-8 relative; the
+  mixed mode: 1e-8 Eh, 1e-6 relative.
+* Full size (30 closed, 8 active, 400 virtual, 1500 auxiliary, 4 states),
+  in the launch configuration the benchmark times: properties that hold at
+  any size -- the residual without source is linear in x and its operator is
+  symmetric (Eq. 10 with a symmetric f and metric), with the Fock couplings
+  between blocks on.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from synth.gen import make_problem, random_vector  # noqa: E402
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1606_01273_amd import lib
+    lib()
+    return torch.device("cuda")
+
+
+def _ok(err, tol, what):
+    err = float(err)
+    print(f"  {what}: {err:.3e} (bar {tol:.0e})", flush=True)
+    if not err < tol:
+        pytest.fail(f"{what}: error {err:.3e} >= {tol:.1e}")
+
+
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+def test_mid_matches_stored_oracle(dev, mode):
+    from paper_1606_01273_amd import FP64, MIXED, Caspt2
+    with open(os.path.join(HERE, "golden", "mid_B.json")) as fh:
+        rec = json.load(fh)
+    p = make_problem(*rec["dims"], seed=rec["seed"], reading=rec["reading"], shift=rec["shift"])
+    g = Caspt2.from_problem(p, precision=FP64 if mode == "fp64" else MIXED)
+    assert g.length == rec["length"]
+    e_tol, v_tol = (1e-10, 1e-8) if mode == "fp64" else (1e-8, 1e-6)
+    if mode == "fp64":
+        x = torch.tensor(random_vector(g.length, rec["residual_x_seed"]), device=dev)
+        s = torch.empty_like(x)
+        g.residual(0, x, s, with_source=True)
+        got = s.cpu().numpy()[np.asarray(rec["residual_index"])]
+        ref = np.asarray(rec["residual_value"])
+        _ok(np.abs(got - ref).max() / np.abs(ref).max(), 1e-12, "residual at sampled positions")
+    rc, info = g.solve_amplitudes(tol=1e-11, maxiter=400)
+    assert rc == 0
+    H, w, R = g.heff()
+    _ok(np.abs(w - np.asarray(rec["e_ms"])).max(), e_tol, f"E_MS ({mode}, Eh)")
+    for L in range(p.nst):
+        tn = float(torch.linalg.vector_norm(g.amplitudes(L)))
+        _ok(abs(tn - rec["t_norm"][L]) / rec["t_norm"][L], v_tol, f"|T| L {L}")
+    rc, info = g.solve_lambda(rec["target"], tol=1e-11, maxiter=400)
+    assert rc == 0
+    scale = max(rec["lambda_norm"])
+    for L in range(p.nst):
+        ln = float(torch.linalg.vector_norm(g.lam(L)))
+        _ok(abs(ln - rec["lambda_norm"][L]) / scale, v_tol, f"|lambda| L {L}")
+    g.close()
+
+
+def test_full_size_operator_linear_and_symmetric(dev):
+    from paper_1606_01273_amd import Caspt2
+    p = make_problem(30, 8, 400, 1500, 4, seed=8, reading="B", shift=0.2)
+    g = Caspt2.from_problem(p)
+    n = g.length
+    print("full size vector length", n, flush=True)
+    x = torch.tensor(random_vector(n, 21), device=dev)
+    y = torch.tensor(random_vector(n, 22), device=dev)
+    ax = torch.empty_like(x)
+    ay = torch.empty_like(x)
+    L = p.nst - 1
+    g.residual(L, x, ax, with_source=False)
+    g.residual(L, y, ay, with_source=False)
+    xay = float(torch.dot(x, ay))
+    yax = float(torch.dot(y, ax))
+    _ok(abs(xay - yax) / max(abs(xay), 1e-300), 1e-11, "x.(A y) - y.(A x), relative")
+    x.add_(y)                      # x + y
+    axy = torch.empty_like(x)
+    g.residual(L, x, axy, with_source=False)
+    axy.sub_(ax).sub_(ay)
+    _ok(float(torch.linalg.vector_norm(axy)) / float(torch.linalg.vector_norm(ax)), 1e-12,
+        "A(x + y) - A x - A y, relative")
+    g.close()

@@ -338,3 +338,24 @@ def test_threshold_insensitivity(mid):
     for th in (1e-12, 1e-7):
         e = Caspt2Oracle(p, "MSMR", thresh=th).run().e_ms
         assert np.abs(e - o.e_ms).max() < 1e-10
+
+
+def test_degenerate_xms_rotation_invariance():
+    """With every CAS state a reference, F^ref has a degenerate eigenvalue
+    here; any rotation inside that eigenspace is a valid XMS rotation
+    (Eqs. 3-5).  Without shift E^MS is the same for every such choice; with
+    a real shift it is not (the shift term of Eq. 15 is diagonal in the
+    rotated basis), which the library documents as a reading."""
+    import numpy as np
+    from oracle.ic import Caspt2Oracle
+    for shift, same in ((0.0, True), (0.3, False)):
+        p = make_problem(2, 2, 3, 12, 4, seed=5, reading="B", shift=shift)
+        o = Caspt2Oracle(p, "MSMR").run(P=0)
+        i = int(np.argmin(np.diff(o.e0)))
+        assert np.diff(o.e0)[i] < 1e-12
+        G = np.eye(4)
+        c, s_ = np.cos(0.5), np.sin(0.5)
+        G[i, i], G[i, i + 1], G[i + 1, i], G[i + 1, i + 1] = c, -s_, s_, c
+        o2 = Caspt2Oracle(p, "MSMR", xms=False, rotate_states=o.U @ G).run(P=0)
+        d = np.abs(np.sort(o2.e_ms) - np.sort(o.e_ms)).max()
+        assert (d < 1e-12) if same else (d > 1e-6), (shift, d)
