@@ -32,6 +32,7 @@ WORKLOADS = {
     "small": ((4, 4, 20, 60, 1, 0, 0.0), "CASPT2 4c/4a(4e)/20v naux 60, 1 state, no shift"),
 }
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFS = 78.6
 
 
 def _pmc_traffic(entry, workload, reading):
@@ -259,6 +260,15 @@ def main():
                 "bytes_per_launch": bytes_pl}
     per_entry = {k: {"avg_ms": round(v[0], 4), "launches": v[1], "GBs": round(v[2] / (v[0] * 1e-3) / 1e9, 1)
                      if v[0] > 0 else None} for k, v in prof.items()}
+    # dense contraction entries (nalpha > 64: MFMA GEMMs): algorithmic flops
+    # 2 * 2 * rows * nalpha^2 per launch (X S and X F), rate vs the FP64 peak
+    mfma = {}
+    for name, _, rows, na in g.layout():
+        v = prof.get(name)
+        if na > 64 and v and v[0] > 0 and rows > 0:
+            tf = 4.0 * rows * na * na / (v[0] * 1e-3) / 1e12
+            mfma[name] = {"TFs": round(tf, 2), "util": round(tf / FP64_PEAK_TFS, 3), "rows": rows, "nalpha": na}
+            per_entry[name]["TFs"] = round(tf, 2)
     per_entry["couplings"] = {"avg_ms": round(coupl[0], 4), "launches": coupl[1]}
 
     solve = None
@@ -308,7 +318,7 @@ def main():
            "data": "synthetic (seeded generator: DF factors, orbital energies, CAS-CI)",
            "config": {"workload": wname, "reading": args.reading, "scheme": "MS-MR", "vector_length": g.length,
                       "setup_s": round(t_setup, 2)},
-           "roofline": roofline, "cpu_baseline": cpu, "per_entry": per_entry}
+           "roofline": roofline, "cpu_baseline": cpu, "mfma": mfma, "per_entry": per_entry}
     if solve is not None:
         out["solve"] = solve
     if precision is not None:

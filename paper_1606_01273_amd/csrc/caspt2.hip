@@ -1169,7 +1169,9 @@ void apply_couplings(H& h, int set, const T* x, T* sig) {
       std::fprintf(stderr, "[caspt2] term %s %s <- %s ny %d nsum %d: ", t.up ? "up" : "down",
                    blocks()[t.bra].name.c_str(), blocks()[t.ket].name.c_str(), t.d.ny, t.d.nsum);
     }
-    if (t.up) {
+    if (t.up && couple_up_fusable<T>(t.d, nak)) {
+      HIPCHECK(couple_up_fused(t.d, f, (const T*)xall(t.ket), nak, Sel<T>::G(t), sall(t.bra), h.s));
+    } else if (t.up) {
       const int64_t width = (int64_t)t.d.ny * nab;
       HIPCHECK(gemm_t(true, all_rows(h, t.ket), width, nak, 1.0, xall(t.ket), nak, Sel<T>::G(t), nak, 0.0,
                       scratch, width, h.s));

@@ -234,6 +234,80 @@ __global__ __launch_bounds__(256) void k_couple_expand(ExpandPlan ep, const doub
   }
 }
 
+// Up term with the active contraction fused in: W[rk][y][c] = sum_k X[rk][k]
+// G[(y ncol + c)][k] is formed in registers from the ket row (G staged in
+// LDS), then expanded over the free bra slots as in k_couple_expand.  The
+// free range of the first free slot is split over nsplit threads when the
+// ket has few rows.  Thread order: ket row fastest (a wave shares its column
+// group and split, so LDS reads of G are broadcasts).
+constexpr int FUSED_G_MAX = 6144;   // G entries staged in LDS (48 KB of doubles)
+template <typename T, int NC>
+__global__ __launch_bounds__(256) void k_couple_up_fused(ExpandPlan ep, int64_t nak, int nsplit,
+                                                         const double* __restrict__ f,
+                                                         const T* __restrict__ X,
+                                                         const T* __restrict__ G, T* __restrict__ out) {
+  __shared__ T Gs[FUSED_G_MAX];
+  const int64_t glen = (int64_t)ep.ny * ep.ncol * nak;
+  for (int64_t i = threadIdx.x; i < glen; i += blockDim.x) Gs[i] = G[i];
+  __syncthreads();
+  const uint32_t nrows_k = ep.kdim[0] * ep.kdim[1] * ep.kdim[2] * ep.kdim[3];
+  const int64_t ng = (ep.ncol + NC - 1) / NC;
+  const int64_t total = (int64_t)nrows_k * ng * nsplit;
+  const uint32_t chunk = (ep.nf0 + nsplit - 1) / nsplit;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t rk = g % nrows_k;
+    const int64_t rest = g / nrows_k;
+    const int64_t cg = rest % ng;
+    const uint32_t zs = (uint32_t)(rest / ng);
+    const int64_t c0 = cg * NC;
+    uint32_t q = (uint32_t)rk;
+    const uint32_t k3 = q % ep.kdim[3];
+    q /= ep.kdim[3];
+    const uint32_t k2 = q % ep.kdim[2];
+    q /= ep.kdim[2];
+    const uint32_t k1 = q % ep.kdim[1];
+    const uint32_t k0 = q / ep.kdim[1];
+    const int64_t ob = k0 * ep.ob_k[0] + k1 * ep.ob_k[1] + k2 * ep.ob_k[2] + k3 * ep.ob_k[3];
+    const int64_t fo = k0 * ep.fk[0] + k1 * ep.fk[1] + k2 * ep.fk[2] + k3 * ep.fk[3];
+    double wreg[8][NC];
+#pragma unroll
+    for (int y = 0; y < 8; ++y)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) wreg[y][c] = 0.0;
+    const T* xr = X + rk * nak;
+    for (int64_t k = 0; k < nak; ++k) {
+      const double xv = (double)xr[k];
+#pragma unroll
+      for (int y = 0; y < 8; ++y)
+        if (y < ep.ny) {
+#pragma unroll
+          for (int c = 0; c < NC; ++c)
+            if (c0 + c < ep.ncol) wreg[y][c] += xv * (double)Gs[((int64_t)y * ep.ncol + c0 + c) * nak + k];
+        }
+    }
+    const uint32_t zb = zs * chunk, ze = zb + chunk < ep.nf0 ? zb + chunk : ep.nf0;
+    for (uint32_t z0 = zb; z0 < ze; ++z0)
+      for (uint32_t z1 = 0; z1 < ep.nf1; ++z1) {
+        const double* fr = f + fo + z0 * ep.ff[0] + z1 * ep.ff[1];
+        double acc[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+#pragma unroll
+        for (int y = 0; y < 8; ++y)
+          if (y < ep.ny) {
+            const double fv = fr[y * ep.fy];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) acc[c] += fv * wreg[y][c];
+          }
+        T* op = out + (ob + z0 * ep.ob_f[0] + z1 * ep.ob_f[1]) * ep.ncol + c0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+          if (c0 + c < ep.ncol) op[c] += (T)acc[c];
+      }
+  }
+}
+
 // expand, output-parallel form (for kets with few rows): a thread per bra
 // row and column group; W rows are small and stay in cache.
 template <typename T, int NC>
@@ -304,6 +378,48 @@ hipError_t couple_expand(const CoupleDesc& d, const double* f, const T* W, T* ou
     if (grid > 65536) grid = 65536;
     CASPT2_NC_DISPATCH(nc, k_couple_expand_out, dim3(grid), ep, f, W, out_all)
   }
+  return hipGetLastError();
+}
+
+// fused only in the ket-parallel regime (many ket rows): with few ket rows
+// and large free ranges the output-parallel expand of a precomputed W is
+// faster
+template <typename T>
+bool couple_up_fusable(const CoupleDesc& d, int64_t nak) {
+  int64_t nrows_k = 1;
+  for (int k = 0; k < d.ket.nslot; ++k) nrows_k *= d.ket.slot_dim[k];
+  const int64_t ng = (d.ncol + col_group(d.ncol) - 1) / col_group(d.ncol);
+  return d.ny <= 8 && (int64_t)d.ny * d.ncol * nak <= FUSED_G_MAX && nak > 0 &&
+         nrows_k * ng >= ((int64_t)1 << 18);
+}
+
+template <typename T>
+hipError_t couple_up_fused(const CoupleDesc& d, const double* f, const T* X_all, int64_t nak, const T* G,
+                           T* out_all, hipStream_t s) {
+  if (!couple_up_fusable<T>(d, nak)) return hipErrorInvalidValue;
+  int64_t nrows_k = 1, nrows_b = 1;
+  for (int k = 0; k < d.ket.nslot; ++k) nrows_k *= d.ket.slot_dim[k];
+  for (int k = 0; k < d.bra.nslot; ++k) nrows_b *= d.bra.slot_dim[k];
+  if (nrows_b * d.ncol == 0 || nrows_k == 0) return hipSuccess;
+  if (nrows_b >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+  {
+    int fed[4] = {0, 0, 0, 0};
+    for (int l = 0; l < d.ket.nslot; ++l) {
+      if (d.ket_src[l] < 0 || d.ket_src[l] >= d.bra.nslot || fed[d.ket_src[l]]) return hipErrorInvalidValue;
+      fed[d.ket_src[l]] = 1;
+    }
+    if (d.bra.nslot - d.ket.nslot > 2) return hipErrorInvalidValue;
+  }
+  const ExpandPlan ep = make_expand_plan(d);
+  const int nc = col_group(d.ncol);
+  const int64_t ng = (d.ncol + nc - 1) / nc;
+  // split the first free range until about 2M threads run, keeping >= 8
+  // free values per thread
+  int nsplit = 1;
+  while (nsplit * 2 <= (int)ep.nf0 / 8 && nrows_k * ng * nsplit < ((int64_t)1 << 21)) nsplit *= 2;
+  unsigned grid = cdiv(nrows_k * ng * nsplit, 256);
+  if (grid > 65536) grid = 65536;
+  CASPT2_NC_DISPATCH(nc, k_couple_up_fused, dim3(grid), ep, nak, nsplit, f, X_all, G, out_all)
   return hipGetLastError();
 }
 
@@ -534,7 +650,10 @@ hipError_t couple_reduce_packed(const CoupleDesc& d, const PackInfo& pk, const d
   template hipError_t couple_expand<T>(const CoupleDesc&, const double*, const T*, T*, hipStream_t); \
   template hipError_t couple_reduce<T>(const CoupleDesc&, const double*, const T*, T*, hipStream_t);  \
   template hipError_t couple_reduce_packed<T>(const CoupleDesc&, const PackInfo&, const double*,     \
-                                              const T*, T*, hipStream_t);
+                                              const T*, T*, hipStream_t);                           \
+  template bool couple_up_fusable<T>(const CoupleDesc&, int64_t);                                  \
+  template hipError_t couple_up_fused<T>(const CoupleDesc&, const double*, const T*, int64_t,        \
+                                         const T*, T*, hipStream_t);
 CASPT2_COUPLE_INSTANCES(double)
 CASPT2_COUPLE_INSTANCES(float)
 #undef CASPT2_COUPLE_INSTANCES

@@ -165,6 +165,15 @@ struct CoupleDesc {
 template <typename T>
 hipError_t couple_expand(const CoupleDesc& d, const double* f, const T* W, T* out_all,
                          hipStream_t s);
+// up term with the active contraction fused in (G [(y, alpha_b)][alpha_k]
+// staged in LDS; X_all the ket's all-orderings rows of nak values):
+//   out_all[e_b][a] += sum_y f(.) sum_k X_all[e_k(e_b)][k] G[y ncol + a][k]
+// usable when couple_up_fusable (G small enough for LDS)
+template <typename T>
+bool couple_up_fusable(const CoupleDesc& d, int64_t nak);
+template <typename T>
+hipError_t couple_up_fused(const CoupleDesc& d, const double* f, const T* X_all, int64_t nak, const T* G,
+                           T* out_all, hipStream_t s);
 // reduce (bra has fewer external slots):
 //   Y_all[e_b][y * ncol + a] = sum_z f(.) X_all[e_k(e_b, z)][a]
 template <typename T>

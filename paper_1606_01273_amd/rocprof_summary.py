@@ -3,6 +3,7 @@
   python -m paper_1606_01273_amd.rocprof_summary stats KERNEL_STATS_CSV OUT_TXT --command CMD
   python -m paper_1606_01273_amd.rocprof_summary pmc FETCH_CSV WRITE_CSV OUT_JSON OUT_TXT \
       --key WORKLOAD/READING/ENTRY --kernel REGEX --command-fetch CMD --command-write CMD
+  python -m paper_1606_01273_amd.rocprof_summary mfma COUNTER_CSV OUT_TXT --command CMD
 
 The PMC form reads two counter-collection CSVs (one run with FETCH_SIZE, one
 with WRITE_SIZE, both in KiB per dispatch) and scales them with the same
@@ -114,6 +115,43 @@ def cmd_pmc(a):
     print("\n".join(lines))
 
 
+def cmd_mfma(a):
+    """Per kernel: the F64 MFMA work (SQ_INSTS_VALU_MFMA_MOPS_F64, units of 512
+    flops), the MFMA busy cycles and the GPU-active cycles of the dispatch
+    (averages per dispatch).  Utilisation is taken from the work and the
+    kernel's measured duration (flops / duration / FP64 peak); the busy-cycle
+    counter is listed as read."""
+    per = {}
+    with open(a.csv) as fh:
+        for r in csv.DictReader(fh):
+            key = (r["Kernel_Name"], r.get("Dispatch_Id") or r.get("Correlation_Id") or "")
+            per.setdefault(key, {})[r["Counter_Name"]] = float(r["Counter_Value"])
+    agg = {}
+    for (name, _), c in per.items():
+        short = re.sub(r"\(.*", "", re.sub(r"\s+", " ", name))[:70]
+        g = agg.setdefault(short, {"n": 0, "busy": 0.0, "gui": 0.0, "mops": 0.0})
+        g["n"] += 1
+        g["busy"] += c.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0)
+        g["gui"] += c.get("GRBM_GUI_ACTIVE", 0.0)
+        g["mops"] += c.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0)
+    lines = [f"# rocprofv3 MFMA counters per kernel (averages per dispatch)", f"# command: {a.command}",
+             "# F64 MFMA GFLOP = 512 * SQ_INSTS_VALU_MFMA_MOPS_F64 / 1e9; GRBM_GUI_ACTIVE is summed over the",
+             f"# {a.xcds} XCDs, so the dispatch time is GUI_ACTIVE / ({a.xcds} * {a.clock_ghz} GHz); MFMA_BUSY counts per",
+             f"# SIMD: utilisation = MFMA_BUSY / (GUI_ACTIVE / {a.xcds} * {a.simds} SIMDs)", "",
+             f"{'dispatches':>10} {'F64 GFLOP':>10} {'MFMA_BUSY':>14} {'GUI_ACTIVE':>12} {'time us':>9} "
+             f"{'TF/s':>7} {'MFMA util':>9}  kernel"]
+    for k, g in sorted(agg.items(), key=lambda kv: -kv[1]["mops"]):
+        n = g["n"]
+        gf = 512 * g["mops"] / n / 1e9
+        t = g["gui"] / n / (a.xcds * a.clock_ghz * 1e9)
+        util = g["busy"] / (g["gui"] / a.xcds * a.simds) if g["gui"] > 0 else float("nan")
+        lines.append(f"{n:10d} {gf:10.3f} {g['busy'] / n:14.0f} {g['gui'] / n:12.0f} {t * 1e6:9.1f} "
+                     f"{gf / 1e3 / t if t > 0 else 0:7.2f} {100 * util:8.1f}%  {k}")
+    with open(a.out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -131,8 +169,15 @@ def main():
     p.add_argument("--kernel", required=True)
     p.add_argument("--command-fetch", required=True)
     p.add_argument("--command-write", required=True)
+    m = sub.add_parser("mfma")
+    m.add_argument("csv")
+    m.add_argument("out")
+    m.add_argument("--command", required=True)
+    m.add_argument("--xcds", type=int, default=8)
+    m.add_argument("--simds", type=int, default=1024)
+    m.add_argument("--clock-ghz", type=float, default=2.4)
     a = ap.parse_args()
-    cmd_stats(a) if a.cmd == "stats" else cmd_pmc(a)
+    {"stats": cmd_stats, "pmc": cmd_pmc, "mfma": cmd_mfma}[a.cmd](a)
 
 
 if __name__ == "__main__":
