@@ -118,9 +118,9 @@ def cmd_pmc(a):
 def cmd_mfma(a):
     """Per kernel: the F64 MFMA work (SQ_INSTS_VALU_MFMA_MOPS_F64, units of 512
     flops), the MFMA busy cycles and the GPU-active cycles of the dispatch
-    (averages per dispatch).  Utilisation is taken from the work and the
-    kernel's measured duration (flops / duration / FP64 peak); the busy-cycle
-    counter is listed as read."""
+    (averages per dispatch).  The dispatch time is the GPU-active count (summed
+    over the XCDs) over the XCD count and the clock; utilisation is the busy
+    count (per SIMD) over the GPU-active cycles of every SIMD."""
     per = {}
     with open(a.csv) as fh:
         for r in csv.DictReader(fh):
