@@ -98,13 +98,13 @@ def _precision_compare(workload, reading, tol):
     return out
 
 
-def _batch_compare(n, seed, reading, tol):
+def _batch_compare(n, seed, reading, tol, tune=True):
     """n uneven problems: one batched solve (amplitudes, H_eff, lambda of all
     problems interleaved) against the same solves one problem at a time."""
     import numpy as np
     import torch
     from synth.gen import batch_sizes, make_problem
-    from paper_1606_01273_amd import E_INDEFINITE, Caspt2, Caspt2Error, batch_solve
+    from paper_1606_01273_amd import E_INDEFINITE, MIXED, Caspt2, Caspt2Error, batch_solve
     sizes = batch_sizes(n, seed=seed)
     t0 = time.perf_counter()
     gs = [Caspt2.from_problem(make_problem(nc, na, nv, nx, ns, seed=sd, reading=reading, shift=0.2))
@@ -112,6 +112,11 @@ def _batch_compare(n, seed, reading, tol):
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     print(f"[bench] batch of {n}: set-up {t_setup:.1f} s", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    if tune:
+        for g in gs:
+            g.autotune()
+    t_tune = time.perf_counter() - t0
     t0 = time.perf_counter()
     rc, ainfo, linfo = batch_solve(gs, [0] * n, tol=tol, maxiter=400)
     torch.cuda.synchronize()
@@ -131,13 +136,30 @@ def _batch_compare(n, seed, reading, tol):
         t_seq += dt
         if e_b[i] is not None:
             dmax = max(dmax, float(np.abs(np.asarray(w) - e_b[i]).max()))
+    # the same batch in the mixed mode (FP32 grouped inner PCG, FP64 refinement)
+    for g in gs:
+        g.set_precision(MIXED)
+    t0 = time.perf_counter()
+    rc_m, ainfo_m, linfo_m = batch_solve(gs, [0] * n, tol=tol, maxiter=400)
+    torch.cuda.synchronize()
+    t_mixed = time.perf_counter() - t0
+    ok_m = [all(a["flags"] & 1 for a in ai) and all(b["flags"] & 1 for b in li)
+            for ai, li in zip(ainfo_m, linfo_m)]
+    dmix = 0.0
+    for g, e, k in zip(gs, e_b, ok_m):
+        if k and e is not None:
+            dmix = max(dmix, float(np.abs(g.heff()[1] - e).max()))
+    print(f"[bench] batched mixed solve {t_mixed:.2f} s, {sum(ok_m)}/{n} solved", file=sys.stderr, flush=True)
     for g in gs:
         g.close()
     return {"instances": n, "sizes_seed": seed, "reading": reading, "shift": 0.2, "tol": tol,
             "solved": int(sum(ok)), "indefinite_instances": bad, "setup_s": round(t_setup, 2),
+            "tune_s": round(t_tune, 2),
             "seconds_batched": round(t_batch, 3), "seconds_one_by_one": round(t_seq, 3),
             "speedup": round(t_seq / t_batch, 3) if t_batch > 0 else None,
             "max_abs_dE_ms_batched_vs_one_by_one": dmax,
+            "seconds_batched_mixed": round(t_mixed, 3), "solved_mixed": int(sum(ok_m)),
+            "max_abs_dE_ms_mixed_vs_fp64": dmix,
             "systems": int(sum(len(a) for a in ainfo) * 2)}
 
 
@@ -186,6 +208,8 @@ def main():
     ap.add_argument("--precision-workload", default="mid",
                     help="workload of the mixed-precision comparison (reading B); 'none' to skip")
     ap.add_argument("--batch", type=int, default=64, help="problems in the batched-solve comparison (0: skip)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the built-in launch rules (no autotuning of the residual launches)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed region, run a 1 GiB fill and a 1 GiB element-wise multiply "
                          "(known traffic for calibrating PMC byte counters)")
@@ -221,6 +245,14 @@ def main():
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     print(f"[bench] library set-up {t_setup:.1f} s, vector length {g.length}", file=sys.stderr, flush=True)
+    tune, t_tune = None, 0.0
+    if not args.no_tune:
+        t0 = time.perf_counter()
+        choices = g.autotune()
+        t_tune = time.perf_counter() - t0
+        tune = {k: {"splitk": c[0], "order": c[1], "grid": c[2], "rule_ms": round(c[3], 4),
+                    "tuned_ms": round(c[4], 4)} for k, c in choices.items() if c[3] > 0}
+        print(f"[bench] autotuned the residual launches in {t_tune:.1f} s", file=sys.stderr, flush=True)
     gen = torch.Generator(device="cuda")
     gen.manual_seed(0)
     x = torch.randn((nst, g.length), dtype=torch.float64, device="cuda", generator=gen)
@@ -289,7 +321,7 @@ def main():
     batch = None
     if args.batch > 0:
         try:
-            batch = _batch_compare(args.batch, 4, "B", args.solve_tol)
+            batch = _batch_compare(args.batch, 4, "B", args.solve_tol, tune=not args.no_tune)
         except Exception as ex:
             batch = {"error": repr(ex)}
 
@@ -317,8 +349,10 @@ def main():
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
            "data": "synthetic (seeded generator: DF factors, orbital energies, CAS-CI)",
            "config": {"workload": wname, "reading": args.reading, "scheme": "MS-MR", "vector_length": g.length,
-                      "setup_s": round(t_setup, 2)},
+                      "setup_s": round(t_setup, 2), "tune_s": round(t_tune, 2)},
            "roofline": roofline, "cpu_baseline": cpu, "mfma": mfma, "per_entry": per_entry}
+    if tune is not None:
+        out["tune"] = tune
     if solve is not None:
         out["solve"] = solve
     if precision is not None:

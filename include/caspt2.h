@@ -151,6 +151,31 @@ CASPT2_API int caspt2_create(const caspt2_dims* dims, const caspt2_inputs* input
                   void* stream, caspt2_handle** out);
 CASPT2_API int caspt2_destroy(caspt2_handle* h);
 
+/* Switch the arithmetic of later solves (CASPT2_FP64 or CASPT2_MIXED) on an
+ * existing handle; the first switch to MIXED makes the FP32 copies of the
+ * operands (device memory owned by the handle).  Solutions already stored
+ * stay valid.  E_ARG for an unknown precision. */
+CASPT2_API int caspt2_set_precision(caspt2_handle* h, int32_t precision);
+
+/* Autotune the launches of the FP64 residual (Eq. 10, within-block part) of
+ * this handle: for every packed entry, time each candidate -- the K split
+ * count and tile order (plain or XCD-grouped) of the MFMA residual GEMM, or
+ * the workgroup-count cap of the streaming kernels -- on the handle's own
+ * operands and keep the fastest (the built-in rule is one of the
+ * candidates).  Choices are cached per entry shape for the process and, if
+ * cache_path is not NULL, in that text file (read first, rewritten after;
+ * one line per shape), so handles of equal shapes are timed once; force = 1
+ * times again even for cached shapes.  Results change only by the order of
+ * the K summation.  Errors: E_ARG (cache file not writable), E_DEVICE. */
+CASPT2_API int caspt2_autotune(caspt2_handle* h, const char* cache_path, int32_t force);
+
+/* The launch choice of entry k (order of the packed layout) after
+ * caspt2_autotune: choice[3] = {K splits, tile order, grid cap} (-1, -1, 0:
+ * the rule); rule_ms and tuned_ms the timings of the rule and of the choice
+ * (-1 when the choice came from the cache).  host outputs, each may be NULL. */
+CASPT2_API int caspt2_tune_entry(const caspt2_handle* h, int32_t k, int32_t* choice, double* rule_ms,
+                                 double* tuned_ms);
+
 /* Packed vector length per state L (number of doubles). */
 CASPT2_API int64_t caspt2_vector_length(const caspt2_handle* h);
 /* Layout entry k (0..12, order above): offset (doubles), rows, nalpha.
@@ -192,8 +217,9 @@ CASPT2_API int caspt2_solve_lambda(caspt2_handle* h, int32_t target, double tol,
                         caspt2_info* info);
 CASPT2_API int caspt2_get_lambda(caspt2_handle* h, int32_t L, double* lambda);
 
-/* Batched solves over many independent problems (each a handle created with
- * CASPT2_FP64; the problems may differ in every dimension and state count).
+/* Batched solves over many independent problems (handles created with the
+ * same precision, CASPT2_FP64 or CASPT2_MIXED; the problems may differ in
+ * every dimension and state count).
  * All amplitude systems (every state of every problem) advance in one
  * grouped PCG with device-resident scalars and one captured HIP graph per
  * system for the operator application; as soon as the amplitudes of a
@@ -206,7 +232,9 @@ CASPT2_API int caspt2_get_lambda(caspt2_handle* h, int32_t L, double* lambda);
  * arrays of sum_i nstates_i entries (problem-major) or NULL.  Returns the
  * first failure over the problems (E_INDEFINITE takes precedence, then
  * E_NOCONV); a problem whose amplitude solve fails gets no lambda.
- * E_NOTIMPL if a handle is not FP64. */
+ * In CASPT2_MIXED the grouped recurrence is the FP32 inner solver and each
+ * system is refined in FP64 as in caspt2_solve_amplitudes.  E_ARG if the
+ * handles differ in precision. */
 CASPT2_API int caspt2_batch_solve(caspt2_handle* const* handles, int32_t n, const int32_t* targets, double tol,
                                   int32_t maxiter, caspt2_info* amp_info, caspt2_info* lambda_info);
 

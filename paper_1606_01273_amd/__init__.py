@@ -6,6 +6,7 @@ memory and streams only; every arithmetic step runs in the HIP library.
 from __future__ import annotations
 
 import ctypes
+import os
 
 import numpy as np
 
@@ -82,6 +83,22 @@ class Caspt2:
             _check(lib().caspt2_layout(self._h, k, ctypes.byref(o), ctypes.byref(r), ctypes.byref(a)),
                    "caspt2_layout")
             out.append((ENTRY_NAMES[k], o.value, r.value, a.value))
+        return out
+
+    def set_precision(self, precision):
+        _check(lib().caspt2_set_precision(self._h, int(precision)), "caspt2_set_precision")
+
+    def autotune(self, cache_path=None, force=False):
+        """Time the launch candidates of every residual entry and keep the
+        fastest; returns {entry name: (splitk, order, grid, rule_ms, tuned_ms)}."""
+        path = None if cache_path is None else os.fsencode(cache_path)
+        _check(lib().caspt2_autotune(self._h, path, 1 if force else 0), "caspt2_autotune")
+        out = {}
+        for k, name in enumerate(ENTRY_NAMES):
+            c = (ctypes.c_int32 * 3)()
+            r, t = ctypes.c_double(), ctypes.c_double()
+            _check(lib().caspt2_tune_entry(self._h, k, c, ctypes.byref(r), ctypes.byref(t)), "caspt2_tune_entry")
+            out[name] = (c[0], c[1], c[2], r.value, t.value)
         return out
 
     def profile(self, enable=True):

@@ -50,6 +50,10 @@ SIGNATURES = {
     "caspt2_create": (ctypes.c_int, [ctypes.POINTER(Dims), ctypes.POINTER(Inputs), ctypes.c_int, _P,
                                      ctypes.POINTER(_P)]),
     "caspt2_destroy": (ctypes.c_int, [_P]),
+    "caspt2_set_precision": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "caspt2_autotune": (ctypes.c_int, [_P, ctypes.c_char_p, ctypes.c_int32]),
+    "caspt2_tune_entry": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "caspt2_vector_length": (ctypes.c_int64, [_P]),
     "caspt2_layout": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
                                      ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
@@ -75,6 +79,8 @@ SIGNATURES = {
     "caspt2_debug_entry": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _D]),
     "caspt2_debug_source": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P]),
     "caspt2_debug_eigh": (ctypes.c_int, [ctypes.c_int32, _P, _D, _P]),
+    "caspt2_debug_eigh_method": (ctypes.c_int, [ctypes.c_int32, _P, _D, _P, ctypes.c_int32,
+                                                ctypes.POINTER(ctypes.c_int32)]),
     "caspt2_last_error": (ctypes.c_char_p, []),
 }
 

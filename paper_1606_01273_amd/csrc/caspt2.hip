@@ -12,6 +12,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -103,6 +104,8 @@ struct Entry {
   FBuf epsA32, epsB32;
   int64_t nB = 1;
   double emin_kept = INFINITY, emax_dropped = -1.0;
+  LaunchTune tune;                // FP64 launch choices (rule unless autotuned)
+  double tune_rule_ms = -1.0, tune_best_ms = -1.0;   // autotuner timings (-1: not timed)
 };
 
 struct CoupleTerm {
@@ -125,6 +128,7 @@ struct Sel<double> {
   static const double* eps(const Entry& e) { return e.eps.p; }
   static RowEnergy<double> rows(const Entry& e) { return RowEnergy<double>{e.epsA.p, e.epsB.p, (uint32_t)e.nB}; }
   static const double* G(const CoupleTerm& t) { return t.G.p; }
+  static LaunchTune tune(const Entry& e) { return e.tune; }
 };
 template <>
 struct Sel<float> {
@@ -134,6 +138,7 @@ struct Sel<float> {
   static const float* eps(const Entry& e) { return e.eps32.p; }
   static RowEnergy<float> rows(const Entry& e) { return RowEnergy<float>{e.epsA32.p, e.epsB32.p, (uint32_t)e.nB}; }
   static const float* G(const CoupleTerm& t) { return t.G32.p; }
+  static LaunchTune tune(const Entry&) { return LaunchTune{}; }
 };
 
 inline hipError_t gemm_t(bool nk, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
@@ -148,22 +153,22 @@ inline hipError_t gemm_t(bool nk, int64_t M, int64_t N, int64_t K, double alpha,
 }
 inline hipError_t residual_small_t(int64_t M, int64_t N, const double* X, const double* S,
                                    const double* F, const double* d, double dshift,
-                                   const double* V, double* C, hipStream_t s) {
-  return residual_small_f64(M, N, X, S, F, d, dshift, V, C, s);
+                                   const double* V, double* C, hipStream_t s, LaunchTune tu) {
+  return residual_small_f64(M, N, X, S, F, d, dshift, V, C, s, tu);
 }
 inline hipError_t residual_small_t(int64_t M, int64_t N, const float* X, const float* S,
                                    const float* F, const float* d, double dshift, const float* V,
-                                   float* C, hipStream_t s) {
+                                   float* C, hipStream_t s, LaunchTune) {
   return residual_small_f32(M, N, X, S, F, d, (float)dshift, V, C, s);
 }
 inline hipError_t residual_gemm_t(int64_t M, int64_t N, const double* X, const double* S,
                                   const double* F, const double* d, double dshift,
-                                  const double* V, double* C, hipStream_t s, DBuf& ws) {
-  return residual_gemm_f64(M, N, N, X, N, S, F, d, dshift, V, N, C, N, s, ws.p, ws.n);
+                                  const double* V, double* C, hipStream_t s, DBuf& ws, LaunchTune tu) {
+  return residual_gemm_f64(M, N, N, X, N, S, F, d, dshift, V, N, C, N, s, ws.p, ws.n, tu);
 }
 inline hipError_t residual_gemm_t(int64_t M, int64_t N, const float* X, const float* S,
                                   const float* F, const float* d, double dshift, const float* V,
-                                  float* C, hipStream_t s, DBuf&) {
+                                  float* C, hipStream_t s, DBuf&, LaunchTune) {
   return residual_gemm_f32(M, N, N, X, N, S, F, d, (float)dshift, V, N, C, N, s);
 }
 
@@ -215,6 +220,7 @@ struct caspt2_handle {
   DBuf splitk_ws;                                      // partial products of the split-K residual GEMMs
   DBuf xall[NBLOCK], sall[NBLOCK];                      // all-orderings x and sigma per block
   bool direct[NBLOCK] = {};                            // ket read from packed rows (no all-orderings x)
+  bool have_mixed = false;                             // FP32 operand copies made
   bool prof_on = false;
   bool verbose = false;
   int verbose_level = 0;
@@ -1220,6 +1226,38 @@ void prof_end(H& h, int entry, double bytes, hipEvent_t a) {
   h.prof_events.push_back({entry, bytes, a, b});
 }
 
+// true if entry k of the set shares one streaming launch with entry k + 1
+// (the '+' and '-' entries of a block with nalpha <= 4)
+bool paired_rows(const std::vector<Entry>& es, size_t k) {
+  const Entry& e = es[k];
+  return e.nalpha <= 4 && k + 1 < es.size() && es[k + 1].block == e.block && es[k + 1].nalpha == e.nalpha;
+}
+
+// within-block part of the residual for entry k (and k + 1 when paired):
+// sig = ((eps + dshift) S + F) x (+ V), with the launch choices tu
+template <typename T>
+void launch_entry(H& h, const std::vector<Entry>& es, size_t k, LaunchTune tu, const T* x, const T* V,
+                  T* sig, double dshift) {
+  const Entry& e = es[k];
+  if (paired_rows(es, k)) {
+    const Entry& e2 = es[k + 1];
+    HIPCHECK(residual_rows<T>((int)e.nalpha, e.nrow, e2.nrow, x + e.offset, Sel<T>::S(e), Sel<T>::F(e),
+                              e2.nrow ? Sel<T>::S(e2) : nullptr, e2.nrow ? Sel<T>::F(e2) : nullptr,
+                              Sel<T>::rows(e), e2.nrow ? Sel<T>::rows(e2) : RowEnergy<T>{nullptr, nullptr, 1},
+                              (T)dshift, V ? V + e.offset : nullptr, sig + e.offset, h.s, tu));
+  } else if (e.nalpha <= 4) {
+    HIPCHECK(residual_rows<T>((int)e.nalpha, e.nrow, 0, x + e.offset, Sel<T>::S(e), Sel<T>::F(e), nullptr,
+                              nullptr, Sel<T>::rows(e), RowEnergy<T>{nullptr, nullptr, 1}, (T)dshift,
+                              V ? V + e.offset : nullptr, sig + e.offset, h.s, tu));
+  } else if (e.nalpha <= 64) {
+    HIPCHECK(residual_small_t(e.nrow, e.nalpha, x + e.offset, Sel<T>::S(e), Sel<T>::F(e), Sel<T>::eps(e),
+                              dshift, V ? V + e.offset : nullptr, sig + e.offset, h.s, tu));
+  } else {
+    HIPCHECK(residual_gemm_t(e.nrow, e.nalpha, x + e.offset, Sel<T>::S(e), Sel<T>::F(e), Sel<T>::eps(e),
+                             dshift, V ? V + e.offset : nullptr, sig + e.offset, h.s, h.splitk_ws, tu));
+  }
+}
+
 // sigma_L = A_L x (+ V^(L)) in the packed layout (Eq. 10).  T = double is
 // the FP64 operator; T = float the FP32 operator of the mixed-precision
 // inner solver (FP32 copies of S, F, eps and of the coupling matrices).
@@ -1229,39 +1267,21 @@ void residual(H& h, int L, const T* x, T* sig, bool with_source) {
   const double dshift = h.d.shift - h.e0[L];
   const double esz = (double)sizeof(T);
   auto& es = h.sets[set];
+  const T* V = nullptr;
+  if (with_source) {
+    if (sizeof(T) != sizeof(double)) throw DevError(CASPT2_E_ARG, "source only in FP64");
+    V = reinterpret_cast<const T*>(h.src[set][L].p);
+  }
   for (size_t k = 0; k < es.size(); ++k) {
     auto& e = es[k];
     if (e.nrow == 0 || e.nalpha == 0) continue;
-    const T* V = nullptr;
-    if (with_source) {
-      if (sizeof(T) != sizeof(double)) throw DevError(CASPT2_E_ARG, "source only in FP64");
-      V = reinterpret_cast<const T*>(h.src[set][L].p) + e.offset;
-    }
+    const bool pair = paired_rows(es, k);
+    const double rows = (double)(e.nrow + (pair ? es[k + 1].nrow : 0));
     hipEvent_t ev = nullptr;
-    // '+' and '-' entries of a block with nalpha <= 4 share one streaming launch
-    if (e.nalpha <= 4 && k + 1 < es.size() && es[k + 1].block == e.block && es[k + 1].nalpha == e.nalpha) {
-      auto& e2 = es[k + 1];
-      prof_begin(h, &ev);
-      HIPCHECK(residual_rows<T>((int)e.nalpha, e.nrow, e2.nrow, x + e.offset, Sel<T>::S(e), Sel<T>::F(e),
-                                e2.nrow ? Sel<T>::S(e2) : nullptr, e2.nrow ? Sel<T>::F(e2) : nullptr,
-                                Sel<T>::rows(e), e2.nrow ? Sel<T>::rows(e2) : RowEnergy<T>{nullptr, nullptr, 1},
-                                (T)dshift, V, sig + e.offset, h.s));
-      prof_end(h, (int)k, (with_source ? 3.0 : 2.0) * esz * (double)(e.nrow + e2.nrow) * e.nalpha, ev);
-      ++k;
-      continue;
-    }
     prof_begin(h, &ev);
-    if (e.nalpha <= 4)
-      HIPCHECK(residual_rows<T>((int)e.nalpha, e.nrow, 0, x + e.offset, Sel<T>::S(e), Sel<T>::F(e), nullptr,
-                                nullptr, Sel<T>::rows(e), RowEnergy<T>{nullptr, nullptr, 1}, (T)dshift, V,
-                                sig + e.offset, h.s));
-    else if (e.nalpha <= 64)
-      HIPCHECK(residual_small_t(e.nrow, e.nalpha, x + e.offset, Sel<T>::S(e), Sel<T>::F(e), Sel<T>::eps(e),
-                                dshift, V, sig + e.offset, h.s));
-    else
-      HIPCHECK(residual_gemm_t(e.nrow, e.nalpha, x + e.offset, Sel<T>::S(e), Sel<T>::F(e), Sel<T>::eps(e),
-                               dshift, V, sig + e.offset, h.s, h.splitk_ws));
-    prof_end(h, (int)k, (with_source ? 3.0 : 2.0) * esz * (double)e.nrow * e.nalpha, ev);
+    launch_entry<T>(h, es, k, Sel<T>::tune(e), x, V, sig, dshift);
+    prof_end(h, (int)k, (with_source ? 3.0 : 2.0) * esz * rows * e.nalpha, ev);
+    if (pair) ++k;
   }
   if (!h.couple.empty() && !h.couple[set].empty()) {
     hipEvent_t ev = nullptr;
@@ -1343,93 +1363,9 @@ void build_denoms(H& h, int L, DBuf& D, double* dmin) {
   *dmin = mn;
 }
 
-// Mixed precision: FP64 iterative refinement around an FP32 PCG.  The outer
-// loop keeps t and the true residual r = -b - A t in FP64 (FP64 operator);
-// each inner solve runs PCG on A d = r / |r| entirely in FP32 (operator,
-// transforms, couplings, vectors; dot products accumulated in FP64) until
-// its residual drops by inner_tol, then t += |r| d.  The converged t meets
-// the same FP64 residual tolerance as pcg(); the inputs (sources, metrics,
-// bases, denominators) are the FP64 ones, rounded once for the inner solve.
-int pcg_mixed(H& h, int L, const double* b_orth, double tol, int maxiter, DBuf& t, caspt2_info& info) {
-  const int set = set_of(h, L);
-  const int64_t n = olen(h, set);
-  DBuf D;
-  double dmin;
-  build_denoms(h, L, D, &dmin);
-  info.min_denom = dmin;
-  info.e0 = h.e0[L];
-  info.emin_kept = INFINITY;
-  info.emax_dropped = -1.0;
-  for (auto& e : h.sets[set]) {
-    info.emin_kept = std::min(info.emin_kept, e.emin_kept);
-    info.emax_dropped = std::max(info.emax_dropped, e.emax_dropped);
-  }
-  if (!(dmin > 0.0)) return CASPT2_E_INDEFINITE;
-  const double inner_tol = 1e-5;   // relative reduction per inner solve
-  const int inner_cap = 200;       // FP32 iterations per inner solve
-  t.alloc(n);
-  t.zero(h.s);
-  FBuf D32(n), r32(n), z32(n), p32(n), q32(n), d32(n), x32(h.length), s32(h.length);
-  DBuf r(n), Ap(n), x(h.length), sg(h.length);
-  HIPCHECK(vec_scale_copy(n, 1.0, D.p, D32.p, h.s));
-  HIPCHECK(vec_scale_copy(n, -1.0, b_orth, r.p, h.s));
-  double rn = std::sqrt(ddot(h, n, r.p, r.p));
-  int inner = 0, outer = 0;
-  while (rn > tol && inner < maxiter) {
-    HIPCHECK(vec_scale_copy(n, 1.0 / rn, r.p, r32.p, h.s));
-    HIPCHECK(vec_fill(n, 0.0, d32.p, h.s));
-    HIPCHECK(vec_div(n, r32.p, D32.p, z32.p, h.s));
-    HIPCHECK(hipMemcpyAsync(p32.p, z32.p, n * sizeof(float), hipMemcpyDeviceToDevice, h.s));
-    double rz = ddot(h, n, r32.p, z32.p);
-    double rin = std::sqrt(ddot(h, n, r32.p, r32.p));
-    const double goal = std::max(inner_tol, 0.5 * tol / rn);
-    int k = 0;
-    while (rin > goal && inner < maxiter && k < inner_cap) {
-      from_orth(h, set, (const float*)p32.p, x32.p);
-      residual(h, L, (const float*)x32.p, s32.p, false);
-      to_orth(h, set, (const float*)s32.p, q32.p);
-      const double pAp = ddot(h, n, p32.p, q32.p);
-      if (!(pAp > 0.0)) {
-        info.iters = inner;
-        info.refinements = outer;
-        info.resnorm = rn;
-        return CASPT2_E_INDEFINITE;
-      }
-      const double alpha = rz / pAp;
-      HIPCHECK(vec_axpy(n, alpha, p32.p, d32.p, h.s));
-      HIPCHECK(vec_axpy(n, -alpha, q32.p, r32.p, h.s));
-      rin = std::sqrt(ddot(h, n, r32.p, r32.p));
-      HIPCHECK(vec_div(n, r32.p, D32.p, z32.p, h.s));
-      const double rz2 = ddot(h, n, r32.p, z32.p);
-      HIPCHECK(vec_xpay(n, z32.p, rz2 / rz, p32.p, h.s));
-      rz = rz2;
-      ++inner;
-      ++k;
-    }
-    HIPCHECK(vec_axpy(n, rn, d32.p, t.p, h.s));   // t += |r| d (FP32 d widened)
-    // true residual in FP64
-    from_orth(h, set, (const double*)t.p, x.p);
-    residual(h, L, (const double*)x.p, sg.p, false);
-    to_orth(h, set, (const double*)sg.p, Ap.p);
-    HIPCHECK(vec_scale_copy(n, -1.0, b_orth, r.p, h.s));
-    HIPCHECK(vec_axpy(n, -1.0, Ap.p, r.p, h.s));
-    const double rn_new = std::sqrt(ddot(h, n, r.p, r.p));
-    ++outer;
-    if (!(rn_new < rn)) {   // refinement no longer reduces the FP64 residual
-      rn = rn_new;
-      break;
-    }
-    rn = rn_new;
-  }
-  info.iters = inner;
-  info.refinements = outer;
-  info.resnorm = rn;
-  info.flags = rn <= tol ? 1 : 0;
-  return rn <= tol ? CASPT2_OK : CASPT2_E_NOCONV;
-}
-
 // FP32 copies of the operands of the inner solver (mixed precision)
 void setup_mixed(H& h) {
+  if (h.have_mixed) return;
   for (auto& es : h.sets)
     for (auto& e : es) {
       auto cast = [&](const DBuf& src, FBuf& dst) {
@@ -1448,31 +1384,52 @@ void setup_mixed(H& h) {
       t.G32.alloc(t.G.n);
       HIPCHECK(vec_scale_copy(t.G.n, 1.0, t.G.p, t.G32.p, h.s));
     }
+  h.have_mixed = true;
 }
 
 // ---------------------------------------------------------------------------
-// Grouped FP64 PCG.  Every linear system of a solve (all states of one
-// problem, or all amplitude and lambda systems of a batch of problems)
-// advances in lockstep.  Per system, the operator application q = A p
-// (from_orth, residual, to_orth) is one captured HIP graph; the recurrence
-// runs in the grouped kernels with device-resident scalars; the host reads
-// the scalars every few iterations only (then retires finished systems and
-// may add new ones).
+// Grouped PCG.  Every linear system of a solve (all states of one problem,
+// or all amplitude and lambda systems of a batch of problems) advances in
+// lockstep.  Per system, the operator application q = A p (from_orth,
+// residual, to_orth) is one captured HIP graph; the recurrence runs in the
+// grouped kernels with device-resident scalars; the host reads the scalars
+// every few iterations only (then retires finished systems and may add new
+// ones).
+//
+// Mixed precision: the same engine runs the recurrence in FP32 (operator,
+// transforms, couplings and vectors in FP32, dot products accumulated in
+// FP64) as the inner solver of an FP64 iterative refinement.  Per system
+// the FP64 solution t and the true residual r = -b - A t (FP64 operator, a
+// second captured graph) are kept; each inner solve runs on A d = r / |r|
+// until its residual drops by inner_tol (or by what the FP64 tolerance
+// still needs), then t += |r| d and r is recomputed.  A system ends when
+// |r| meets the FP64 tolerance, when a refinement no longer reduces |r|,
+// or when the inner iterations reach maxiter.  The inputs (sources,
+// metrics, bases, denominators) are the FP64 ones, rounded once.
 // ---------------------------------------------------------------------------
+constexpr double MIXED_INNER_TOL = 1e-5;   // relative reduction per inner solve
+constexpr int MIXED_INNER_CAP = 200;       // FP32 iterations per inner solve
+
 struct PcgSystem {
   H* h = nullptr;
   int L = 0, set = 0, kind = 0;   // kind 0: amplitudes, 1: lambda
   int64_t n = 0;
-  DBuf t, r, p, q, D;
-  hipGraphExec_t graph = nullptr;
+  DBuf t, r, p, q, D;             // FP64 mode: the recurrence vectors; mixed: t and true residual r
+  FBuf t32, r32, p32, q32, D32;   // mixed: inner correction d, its residual, p, q = A p, denominators
+  DBuf b;                         // mixed: right-hand side (for the true residual)
+  hipGraphExec_t graph = nullptr;     // q = A p in the recurrence's precision
+  hipGraphExec_t graph64 = nullptr;   // mixed: r = A t in FP64
   int id = -1;
   int status = PCG_IDLE;
+  double tol = 0.0, rn = 0.0;     // mixed: FP64 tolerance and current |r|
+  int maxiter = 0;
   caspt2_info info{};
   PcgSystem() = default;
   PcgSystem(const PcgSystem&) = delete;
   PcgSystem& operator=(const PcgSystem&) = delete;
   ~PcgSystem() {
     if (graph) (void)hipGraphExecDestroy(graph);
+    if (graph64) (void)hipGraphExecDestroy(graph64);
   }
 };
 
@@ -1483,11 +1440,16 @@ void ensure_work(H& h) {
   }
 }
 
-// capture q = A p of one system into a graph recorded on stream s (the
-// handle's own launches are redirected to s while recording)
-void capture_operator(PcgSystem& S, hipStream_t s) {
-  H& h = *S.h;
+// capture out = A in (orthonormal basis, precision T) of state L into a
+// graph recorded on stream s (the handle's own launches are redirected to s
+// while recording); the packed work vectors wx, wsg of the handle serve
+// both precisions (graphs of one handle never run concurrently)
+template <typename T>
+hipGraphExec_t capture_operator(H& h, int L, const T* in, T* out, hipStream_t s) {
   ensure_work(h);
+  const int set = set_of(h, L);
+  T* wx = reinterpret_cast<T*>(h.wx.p);
+  T* wsg = reinterpret_cast<T*>(h.wsg.p);
   const hipStream_t keep = h.s;
   const bool prof = h.prof_on;
   const int vl = h.verbose_level;
@@ -1502,9 +1464,9 @@ void capture_operator(PcgSystem& S, hipStream_t s) {
   hipGraph_t g = nullptr;
   HIPCHECK(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
   try {
-    from_orth(h, S.set, (const double*)S.p.p, h.wx.p);
-    residual(h, S.L, (const double*)h.wx.p, h.wsg.p, false);
-    to_orth(h, S.set, (const double*)h.wsg.p, S.q.p);
+    from_orth(h, set, in, wx);
+    residual(h, L, (const T*)wx, wsg, false);
+    to_orth(h, set, (const T*)wsg, out);
   } catch (...) {
     (void)hipStreamEndCapture(s, &g);
     if (g) (void)hipGraphDestroy(g);
@@ -1514,13 +1476,16 @@ void capture_operator(PcgSystem& S, hipStream_t s) {
   const hipError_t e1 = hipStreamEndCapture(s, &g);
   restore();
   HIPCHECK(e1);
-  const hipError_t e2 = hipGraphInstantiate(&S.graph, g, nullptr, nullptr, 0);
+  hipGraphExec_t ex = nullptr;
+  const hipError_t e2 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   HIPCHECK(e2);
+  return ex;
 }
 
 struct PcgEngine {
   hipStream_t s = nullptr;
+  bool mixed = false;
   // operator applications of different problems run concurrently on these
   // streams (default priority; all systems of one problem share one stream,
   // as they share its work vectors); the recurrence waits for all of them
@@ -1532,16 +1497,19 @@ struct PcgEngine {
   int check_every = 4;
   std::vector<std::unique_ptr<PcgSystem>> sys;
   std::vector<int> active;             // ids the host still launches
+  std::vector<int> stopped;            // ids retired by the last poll
   DevBuf<PcgScalars> sc;
   DevBuf<PcgVecs<double>> vecs;
+  DevBuf<PcgVecs<float>> vecs32;
   std::vector<PcgScalars> hsc;
   DevBuf<int32_t> blk_sys, sys_id, b0, b1;
   DevBuf<int64_t> blk_start, blk_end;
   DBuf part_a, part_b;
+  DBuf dot_part, dot_out;              // mixed: norms of the true residuals
   PcgTable tab{};
   PcgSysTable st{};
 
-  explicit PcgEngine(int cap, int nlanes = 1) : capacity(cap) {
+  PcgEngine(int cap, int nlanes, bool mixed_) : mixed(mixed_), capacity(cap) {
     HIPCHECK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
     HIPCHECK(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
     for (int k = 0; k < std::max(1, nlanes); ++k) {
@@ -1553,7 +1521,13 @@ struct PcgEngine {
       lane_done.push_back(ev);
     }
     sc.alloc(cap);
-    vecs.alloc(cap);
+    if (mixed) {
+      vecs32.alloc(cap);
+      dot_part.alloc(1024);
+      dot_out.alloc(cap);
+    } else {
+      vecs.alloc(cap);
+    }
     hsc.assign(cap, PcgScalars{});
   }
   ~PcgEngine() {
@@ -1575,9 +1549,29 @@ struct PcgEngine {
   PcgEngine(const PcgEngine&) = delete;
   PcgEngine& operator=(const PcgEngine&) = delete;
 
+  void upload_scalars(int id) {
+    HIPCHECK(hipMemcpy(sc.p + id, &hsc[id], sizeof(PcgScalars), hipMemcpyHostToDevice));
+  }
+
+  // inner solve of a mixed system from its current true residual (|r| = rn):
+  // r32 = r / rn, d = 0, stop at the relative reduction the refinement needs
+  void arm_inner(PcgSystem& S) {
+    HIPCHECK(vec_scale_copy(S.n, 1.0 / S.rn, S.r.p, S.r32.p, s));
+    HIPCHECK(vec_fill(S.n, 0.0, S.t32.p, s));
+    PcgScalars& c = hsc[S.id];
+    const double goal = std::max(MIXED_INNER_TOL, 0.5 * S.tol / S.rn);
+    c.tol2 = goal * goal;
+    c.maxiter = std::min(c.iters + MIXED_INNER_CAP, S.maxiter);
+    c.status = PCG_IDLE;
+    c.active = 0;
+    upload_scalars(S.id);
+    S.status = PCG_IDLE;
+  }
+
   // new system A x = -b (b in the orthonormal basis, device, on h.s)
   PcgSystem& add(H& h, int L, int kind, const double* b, double tol, int maxiter) {
     if ((int)sys.size() >= capacity) throw DevError(CASPT2_E_ARG, "pcg engine capacity");
+    if (mixed != (h.d.precision == CASPT2_MIXED)) throw DevError(CASPT2_E_ARG, "pcg engine precision");
     auto S = std::make_unique<PcgSystem>();
     S->h = &h;
     S->L = L;
@@ -1585,6 +1579,8 @@ struct PcgEngine {
     S->set = set_of(h, L);
     S->n = olen(h, S->set);
     S->id = (int)sys.size();
+    S->tol = tol;
+    S->maxiter = maxiter;
     caspt2_info& info = S->info;
     double dmin = INFINITY;
     build_denoms(h, L, S->D, &dmin);
@@ -1598,28 +1594,60 @@ struct PcgEngine {
     }
     S->t.alloc(S->n);
     S->r.alloc(S->n);
-    S->p.alloc(S->n);
-    S->q.alloc(S->n);
     HIPCHECK(vec_fill(S->n, 0.0, S->t.p, h.s));
     HIPCHECK(vec_scale_copy(S->n, -1.0, b, S->r.p, h.s));
-    host_sync(h);
-    S->status = dmin > 0.0 ? PCG_IDLE : PCG_INDEFINITE;
-    PcgScalars c{};
+    PcgScalars& c = hsc[S->id];
+    c = PcgScalars{};
     c.tol2 = tol * tol;
     c.maxiter = maxiter;
-    c.status = S->status;
-    c.active = 0;
-    PcgVecs<double> v{};
-    v.vec[PCG_T] = S->t.p;
-    v.vec[PCG_R] = S->r.p;
-    v.vec[PCG_P] = S->p.p;
-    v.vec[PCG_Q] = S->q.p;
-    v.vec[PCG_D] = S->D.p;
-    HIPCHECK(hipMemcpy(sc.p + S->id, &c, sizeof(c), hipMemcpyHostToDevice));
-    HIPCHECK(hipMemcpy(vecs.p + S->id, &v, sizeof(v), hipMemcpyHostToDevice));
-    hsc[S->id] = c;
-    if (S->status == PCG_IDLE && S->n > 0) capture_operator(*S, s);
-    if (S->n == 0 && S->status == PCG_IDLE) S->status = PCG_CONVERGED;
+    if (!mixed) {
+      S->p.alloc(S->n);
+      S->q.alloc(S->n);
+      host_sync(h);
+      S->status = dmin > 0.0 ? PCG_IDLE : PCG_INDEFINITE;
+      c.status = S->status;
+      PcgVecs<double> v{};
+      v.vec[PCG_T] = S->t.p;
+      v.vec[PCG_R] = S->r.p;
+      v.vec[PCG_P] = S->p.p;
+      v.vec[PCG_Q] = S->q.p;
+      v.vec[PCG_D] = S->D.p;
+      HIPCHECK(hipMemcpy(vecs.p + S->id, &v, sizeof(v), hipMemcpyHostToDevice));
+      upload_scalars(S->id);
+      if (S->status == PCG_IDLE && S->n > 0) S->graph = capture_operator<double>(h, L, S->p.p, S->q.p, s);
+      if (S->n == 0 && S->status == PCG_IDLE) S->status = PCG_CONVERGED;
+    } else {
+      S->b.alloc(S->n);
+      S->t32.alloc(S->n);
+      S->r32.alloc(S->n);
+      S->p32.alloc(S->n);
+      S->q32.alloc(S->n);
+      S->D32.alloc(S->n);
+      HIPCHECK(hipMemcpyAsync(S->b.p, b, S->n * sizeof(double), hipMemcpyDeviceToDevice, h.s));
+      HIPCHECK(vec_scale_copy(S->n, 1.0, S->D.p, S->D32.p, h.s));
+      S->rn = S->n > 0 ? std::sqrt(ddot(h, S->n, S->r.p, S->r.p)) : 0.0;
+      S->D.release();
+      PcgVecs<float> v{};
+      v.vec[PCG_T] = S->t32.p;
+      v.vec[PCG_R] = S->r32.p;
+      v.vec[PCG_P] = S->p32.p;
+      v.vec[PCG_Q] = S->q32.p;
+      v.vec[PCG_D] = S->D32.p;
+      HIPCHECK(hipMemcpy(vecs32.p + S->id, &v, sizeof(v), hipMemcpyHostToDevice));
+      c.rr = S->rn * S->rn;
+      if (!(dmin > 0.0)) {
+        S->status = c.status = PCG_INDEFINITE;
+        upload_scalars(S->id);
+      } else if (S->n == 0 || S->rn <= tol) {
+        S->status = c.status = PCG_CONVERGED;
+        upload_scalars(S->id);
+      } else {
+        S->graph = capture_operator<float>(h, L, S->p32.p, S->q32.p, s);
+        S->graph64 = capture_operator<double>(h, L, S->t.p, S->r.p, s);
+        arm_inner(*S);
+        HIPCHECK(hipStreamSynchronize(s));
+      }
+    }
     sys.push_back(std::move(S));
     return *sys.back();
   }
@@ -1669,7 +1697,10 @@ struct PcgEngine {
       if (sys[id]->status == PCG_IDLE) go.push_back(id);
     if (go.empty()) return;
     build_tables(go);
-    HIPCHECK(pcg_init<double>(tab, st, vecs.p, sc.p, part_a.p, part_b.p, s));
+    if (mixed)
+      HIPCHECK(pcg_init<float>(tab, st, vecs32.p, sc.p, part_a.p, part_b.p, s));
+    else
+      HIPCHECK(pcg_init<double>(tab, st, vecs.p, sc.p, part_a.p, part_b.p, s));
     for (int id : go) {
       sys[id]->status = PCG_RUNNING;
       active.push_back(id);
@@ -1682,23 +1713,86 @@ struct PcgEngine {
     HIPCHECK(hipMemcpyAsync(hsc.data(), sc.p, sys.size() * sizeof(PcgScalars), hipMemcpyDeviceToHost, s));
     HIPCHECK(hipStreamSynchronize(s));
     std::vector<int> still;
+    stopped.clear();
     for (int id : active) {
-      if (hsc[id].status == PCG_RUNNING)
+      if (hsc[id].status == PCG_RUNNING) {
         still.push_back(id);
-      else
+      } else {
         sys[id]->status = hsc[id].status;
+        stopped.push_back(id);
+      }
     }
     const bool changed = still.size() != active.size();
     active.swap(still);
     return changed;
   }
 
+  // mixed: fold the inner corrections of the stopped systems into their
+  // FP64 solutions, recompute the true residuals (FP64 operator graphs on
+  // the lanes) and restart the inner solve of every system not yet done
+  void refine() {
+    std::vector<int> ids;
+    for (int id : stopped)
+      if (sys[id]->status == PCG_CONVERGED || sys[id]->status == PCG_MAXITER) ids.push_back(id);
+    if (ids.empty()) return;
+    std::vector<int> used(lanes.size(), 0);
+    for (int id : ids) {
+      PcgSystem& S = *sys[id];
+      HIPCHECK(vec_axpy(S.n, S.rn, S.t32.p, S.t.p, s));   // t += |r| d
+      used[lane(S.h)] = 1;
+    }
+    HIPCHECK(hipEventRecord(fork, s));
+    for (size_t l = 0; l < lanes.size(); ++l)
+      if (used[l]) HIPCHECK(hipStreamWaitEvent(lanes[l], fork, 0));
+    for (int id : ids) HIPCHECK(hipGraphLaunch(sys[id]->graph64, lanes[lane(sys[id]->h)]));   // r = A t
+    for (size_t l = 0; l < lanes.size(); ++l)
+      if (used[l]) {
+        HIPCHECK(hipEventRecord(lane_done[l], lanes[l]));
+        HIPCHECK(hipStreamWaitEvent(s, lane_done[l], 0));
+      }
+    for (int id : ids) {
+      PcgSystem& S = *sys[id];
+      HIPCHECK(vec_negsum(S.n, S.b.p, S.r.p, s));   // r = -(b + A t)
+      HIPCHECK(vec_dot(S.n, S.r.p, S.r.p, dot_part.p, dot_out.p + id, s));
+    }
+    std::vector<double> rr(sys.size());
+    HIPCHECK(hipMemcpyAsync(rr.data(), dot_out.p, sys.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    std::vector<int> again;
+    for (int id : ids) {
+      PcgSystem& S = *sys[id];
+      PcgScalars& c = hsc[id];
+      const double rn_new = std::sqrt(std::max(rr[id], 0.0));
+      S.info.refinements += 1;
+      const bool reduced = rn_new < S.rn;
+      S.rn = rn_new;
+      if (rn_new <= S.tol) {
+        S.status = PCG_CONVERGED;
+      } else if (!reduced || c.iters >= S.maxiter) {
+        S.status = PCG_MAXITER;   // refinement stalled, or the iteration budget is spent
+      } else {
+        arm_inner(S);
+        again.push_back(id);
+      }
+      c.status = S.status;
+    }
+    start(again);
+  }
+
   // iterate until no system runs; on_poll (called after every poll, and
   // once before the first iteration) may start new systems
+  //
+  // Polling interval: a system that stops inside a block of check_every
+  // iterations still has its operator graph launched until the next poll
+  // (the graph cannot see the device-side status), so long iterations are
+  // polled every iteration and short ones (launch- and latency-bound, where
+  // a host synchronisation per iteration would dominate) every few.
   template <typename F>
   void run(F&& on_poll) {
     on_poll(*this);
+    check_every = 1;
     while (!active.empty()) {
+      const double t_block = wall();
       std::vector<int> used(lanes.size(), 0);
       for (int id : active) used[lane(sys[id]->h)] = 1;
       for (int k = 0; k < check_every; ++k) {
@@ -1713,31 +1807,44 @@ struct PcgEngine {
             HIPCHECK(hipEventRecord(lane_done[l], lanes[l]));
             HIPCHECK(hipStreamWaitEvent(s, lane_done[l], 0));
           }
-        HIPCHECK(pcg_step<double>(tab, st, vecs.p, sc.p, part_a.p, part_b.p, s));
+        if (mixed)
+          HIPCHECK(pcg_step<float>(tab, st, vecs32.p, sc.p, part_a.p, part_b.p, s));
+        else
+          HIPCHECK(pcg_step<double>(tab, st, vecs.p, sc.p, part_a.p, part_b.p, s));
       }
       poll();
+      const double per_iter = (wall() - t_block) / check_every;
+      check_every = per_iter > 1e-3 ? 1 : per_iter > 2.5e-4 ? 2 : 4;
+      if (mixed) refine();
       on_poll(*this);
       if (!active.empty()) build_tables(active);
     }
   }
 
-  // free the work vectors and the graph of a system that has finished
+  // free the work vectors and the graphs of a system that has finished
   void retire(PcgSystem& S) {
     S.r.release();
     S.p.release();
     S.q.release();
     S.D.release();
+    S.b.release();
+    S.t32.release();
+    S.r32.release();
+    S.p32.release();
+    S.q32.release();
+    S.D32.release();
     if (S.graph) (void)hipGraphExecDestroy(S.graph);
-    S.graph = nullptr;
+    if (S.graph64) (void)hipGraphExecDestroy(S.graph64);
+    S.graph = S.graph64 = nullptr;
   }
 
   // final scalars into the system's info; solution stays in S.t
   void finish(PcgSystem& S) {
     const PcgScalars& c = hsc[S.id];
     S.info.iters = c.iters;
-    S.info.resnorm = std::sqrt(std::max(c.rr, 0.0));
+    S.info.resnorm = mixed ? S.rn : std::sqrt(std::max(c.rr, 0.0));
     S.info.flags = S.status == PCG_CONVERGED ? 1 : 0;
-    S.info.refinements = 0;
+    if (!mixed) S.info.refinements = 0;
   }
 };
 
@@ -1808,17 +1915,13 @@ void store_solution(PcgSystem& S, std::vector<DBuf>& packed, std::vector<DBuf>& 
   orth[S.L] = std::move(S.t);
 }
 
-int solve_pcg(H& h, int L, const double* b_orth, double tol, int maxiter, DBuf& t, caspt2_info& info) {
-  info.refinements = 0;
-  return pcg_mixed(h, L, b_orth, tol, maxiter, t, info);
-}
-
-// all states of one handle in one grouped FP64 solve; kind 0 amplitudes,
-// 1 lambda for target P
+// all states of one handle in one grouped solve (FP64, or mixed with FP64
+// refinement, by the handle's precision); kind 0 amplitudes, 1 lambda for
+// target P
 int grouped_solve(H& h, int kind, int P, double tol, int maxiter, std::vector<DBuf>& packed,
                   std::vector<DBuf>& orth, std::vector<caspt2_info>& infos) {
   const int nst = h.nst;
-  PcgEngine eng(nst);
+  PcgEngine eng(nst, 1, h.d.precision == CASPT2_MIXED);
   for (int L = 0; L < nst; ++L) {
     DBuf b(olen(h, set_of(h, L)));
     if (kind == 0)
@@ -1856,6 +1959,185 @@ int grouped_solve(H& h, int kind, int P, double tol, int maxiter, std::vector<DB
     eng.retire(*S);
   }
   return status;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner of the FP64 residual launches.  Per entry, every candidate
+// launch choice -- the K split count and the tile order (plain or
+// XCD-grouped) of the residual GEMM, the workgroup-count cap of the
+// streaming kernels -- is timed on the entry's own operands and the fastest
+// kept; the rule's choice is always a candidate, so tuning never picks a
+// slower launch than the rule on the timing run.  Choices are cached per
+// shape in the process and, when a path is given, in a text file (one line
+// per shape: the key, then splitk order grid), so handles of equal shapes
+// time once.  Every candidate computes the same residual; split counts
+// differ from each other only in the order of the K summation.
+// ---------------------------------------------------------------------------
+std::mutex g_tune_mu;
+std::map<std::string, LaunchTune> g_tune_cache;
+
+std::string tune_key(const std::vector<Entry>& es, size_t k) {
+  const Entry& e = es[k];
+  char buf[160];
+  if (paired_rows(es, k))
+    std::snprintf(buf, sizeof buf, "rows2 %lld %lld %lld", (long long)e.nalpha, (long long)e.nrow,
+                  (long long)es[k + 1].nrow);
+  else if (e.nalpha <= 4)
+    std::snprintf(buf, sizeof buf, "rows %lld %lld", (long long)e.nalpha, (long long)e.nrow);
+  else if (e.nalpha <= 64)
+    std::snprintf(buf, sizeof buf, "small %lld %lld", (long long)e.nalpha, (long long)e.nrow);
+  else
+    std::snprintf(buf, sizeof buf, "gemm %lld %lld", (long long)e.nalpha, (long long)e.nrow);
+  return buf;
+}
+
+std::vector<LaunchTune> tune_candidates(const std::vector<Entry>& es, size_t k, int64_t ws_cap) {
+  const Entry& e = es[k];
+  std::vector<LaunchTune> c;
+  c.push_back(LaunchTune{});   // the rule
+  if (e.nalpha <= 64) {
+    const int64_t rows = e.nrow + (paired_rows(es, k) ? es[k + 1].nrow : 0);
+    const int64_t natural = e.nalpha <= 4 ? (rows + 255) / 256
+                            : e.nalpha <= 16 ? (rows * e.nalpha + 255) / 256
+                                             : ((rows + 15) / 16 + 3) / 4;
+    for (unsigned g : {512u, 1024u, 2048u, 4096u, 8192u, 16384u, 32768u})
+      if ((int64_t)g < natural) {
+        LaunchTune t;
+        t.grid = g;
+        c.push_back(t);
+      }
+    return c;
+  }
+  const int64_t M = e.nrow, N = e.nalpha, K = e.nalpha;
+  for (int order : {-1, 2})
+    for (int ns : {1, 2, 4, 8, 16, 32, 64}) {
+      if (ns > 1 && ((int64_t)ns * BK_RESIDUAL > K || (int64_t)ns * 2 * M * N > ws_cap)) continue;
+      LaunchTune t;
+      t.splitk = ns;
+      t.order = order;
+      c.push_back(t);
+    }
+  return c;
+}
+
+double time_entry(H& h, const std::vector<Entry>& es, size_t k, const LaunchTune& tu, const double* x,
+                  const double* V, double* out, double dshift, hipEvent_t a, hipEvent_t b) {
+  launch_entry<double>(h, es, k, tu, x, V, out, dshift);   // warm-up
+  HIPCHECK(hipEventRecord(a, h.s));
+  launch_entry<double>(h, es, k, tu, x, V, out, dshift);
+  HIPCHECK(hipEventRecord(b, h.s));
+  HIPCHECK(hipEventSynchronize(b));
+  float ms1 = 0.0f;
+  HIPCHECK(hipEventElapsedTime(&ms1, a, b));
+  const int reps = std::max(2, std::min(20, (int)(2.0 / std::max(ms1, 1e-3f))));
+  HIPCHECK(hipEventRecord(a, h.s));
+  for (int r = 0; r < reps; ++r) launch_entry<double>(h, es, k, tu, x, V, out, dshift);
+  HIPCHECK(hipEventRecord(b, h.s));
+  HIPCHECK(hipEventSynchronize(b));
+  float ms = 0.0f;
+  HIPCHECK(hipEventElapsedTime(&ms, a, b));
+  return ms / reps;
+}
+
+void load_tune_file(const char* path) {
+  if (!path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  char line[256];
+  while (std::fgets(line, sizeof line, f)) {
+    char* tab = std::strchr(line, '\t');
+    if (!tab) continue;
+    *tab = 0;
+    LaunchTune t;
+    if (std::sscanf(tab + 1, "%d %d %u", &t.splitk, &t.order, &t.grid) != 3) continue;
+    g_tune_cache[line] = t;
+  }
+  std::fclose(f);
+}
+
+void save_tune_file(const char* path) {
+  if (!path) return;
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) throw DevError(CASPT2_E_ARG, "cannot write the tuning cache file");
+  for (auto& kv : g_tune_cache)
+    std::fprintf(f, "%s\t%d %d %u\n", kv.first.c_str(), kv.second.splitk, kv.second.order, kv.second.grid);
+  std::fclose(f);
+  if (std::rename(tmp.c_str(), path) != 0) throw DevError(CASPT2_E_ARG, "cannot replace the tuning cache file");
+}
+
+void autotune(H& h, const char* cache_path, bool force) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  load_tune_file(cache_path);
+  ensure_work(h);
+  const int64_t ws_cap = std::max<int64_t>(h.splitk_ws.n, (int64_t)1 << 26);   // 512 MB of partials
+  hipEvent_t a, b;
+  HIPCHECK(hipEventCreate(&a));
+  HIPCHECK(hipEventCreate(&b));
+  try {
+    for (size_t set = 0; set < h.sets.size(); ++set) {
+      auto& es = h.sets[set];
+      const int L = h.d.scheme == CASPT2_SSSR ? (int)set : 0;
+      // x, the source V and the output in three distinct buffers, as in the
+      // solver (values do not matter for timing)
+      const double* V = h.src[set][L].p;
+      HIPCHECK(hipMemcpyAsync(h.wx.p, V, h.length * sizeof(double), hipMemcpyDeviceToDevice, h.s));
+      const double* x = h.wx.p;
+      const double dshift = h.d.shift - h.e0[L];
+      for (size_t k = 0; k < es.size(); ++k) {
+        Entry& e = es[k];
+        const bool pair = paired_rows(es, k);
+        if (e.nrow == 0 || e.nalpha == 0) continue;
+        const std::string key = tune_key(es, k);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end() && !force) {
+          e.tune = it->second;
+          e.tune_rule_ms = e.tune_best_ms = -1.0;
+        } else {
+          const auto cands = tune_candidates(es, k, ws_cap);
+          int64_t need = h.splitk_ws.n;
+          for (auto& c : cands)
+            if (c.splitk > 1) need = std::max(need, (int64_t)c.splitk * 2 * e.nrow * e.nalpha);
+          if (need > h.splitk_ws.n) h.splitk_ws.alloc(need);
+          double best = INFINITY, rule = INFINITY;
+          LaunchTune pick;
+          for (size_t c = 0; c < cands.size(); ++c) {
+            const double ms = time_entry(h, es, k, cands[c], x, V, h.wsg.p, dshift, a, b);
+            if (c == 0) rule = ms;
+            if (ms < best) {
+              best = ms;
+              pick = cands[c];
+            }
+          }
+          e.tune = pick;
+          e.tune_rule_ms = rule;
+          e.tune_best_ms = best;
+          g_tune_cache[key] = pick;
+          if (h.verbose)
+            std::fprintf(stderr, "[caspt2] tune %-28s splitk %d order %d grid %u: %.4f ms (rule %.4f ms)\n",
+                         key.c_str(), pick.splitk, pick.order, pick.grid, best, rule);
+        }
+        if (pair) es[k + 1].tune = e.tune;
+        if (pair) ++k;
+      }
+    }
+    // workspace for the chosen split counts
+    int64_t ws = 0;
+    for (auto& es : h.sets)
+      for (auto& e : es)
+        if (e.nrow > 0 && e.nalpha > 64) {
+          const int ns = e.tune.splitk >= 1 ? e.tune.splitk : residual_splitk(e.nrow, e.nalpha, e.nalpha);
+          if (ns > 1) ws = std::max(ws, (int64_t)ns * 2 * e.nrow * e.nalpha);
+        }
+    if (ws != h.splitk_ws.n) h.splitk_ws.alloc(ws);
+    save_tune_file(cache_path);
+  } catch (...) {
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    throw;
+  }
+  HIPCHECK(hipEventDestroy(a));
+  HIPCHECK(hipEventDestroy(b));
 }
 
 void validate(const caspt2_dims* d, const std::vector<double>& f, const std::vector<double>& hc,
@@ -2057,6 +2339,40 @@ int caspt2_destroy(caspt2_handle* h) {
   return CASPT2_OK;
 }
 
+int caspt2_set_precision(caspt2_handle* h, int32_t precision) {
+  if (!h || (precision != CASPT2_FP64 && precision != CASPT2_MIXED)) return CASPT2_E_ARG;
+  ABI_GUARD({
+    if (precision == CASPT2_MIXED) {
+      setup_mixed(*h);
+      host_sync(*h);
+    }
+    h->d.precision = precision;
+    return CASPT2_OK;
+  })
+}
+
+int caspt2_autotune(caspt2_handle* h, const char* cache_path, int32_t force) {
+  if (!h) return CASPT2_E_ARG;
+  ABI_GUARD({
+    autotune(*h, cache_path, force != 0);
+    host_sync(*h);
+    return CASPT2_OK;
+  })
+}
+
+int caspt2_tune_entry(const caspt2_handle* h, int32_t k, int32_t* choice, double* rule_ms, double* tuned_ms) {
+  if (!h || k < 0 || k >= (int32_t)h->sets[0].size()) return CASPT2_E_ARG;
+  const Entry& e = h->sets[0][k];
+  if (choice) {
+    choice[0] = e.tune.splitk;
+    choice[1] = e.tune.order;
+    choice[2] = (int32_t)e.tune.grid;
+  }
+  if (rule_ms) *rule_ms = e.tune_rule_ms;
+  if (tuned_ms) *tuned_ms = e.tune_best_ms;
+  return CASPT2_OK;
+}
+
 int caspt2_profile(caspt2_handle* h, int32_t enable) {
   if (!h) return CASPT2_E_ARG;
   ABI_GUARD({
@@ -2130,25 +2446,8 @@ int caspt2_solve_amplitudes(caspt2_handle* h, double tol, int32_t maxiter, caspt
     hh.T.clear();
     hh.Tt.clear();
     hh.have_T = hh.have_heff = hh.have_lam = false;
-    int status = CASPT2_OK;
-    if (hh.d.precision == CASPT2_FP64) {
-      status = grouped_solve(hh, 0, 0, tol, maxiter, hh.T, hh.Tt, hh.tinfo);
-      if (status == CASPT2_E_INDEFINITE) return status;
-    } else {
-      hh.tinfo.assign(hh.nst, caspt2_info{});
-      for (int L = 0; L < hh.nst; ++L) {
-        const int set = set_of(hh, L);
-        DBuf b(olen(hh, set)), t;
-        amplitude_rhs(hh, L, b.p);
-        const int rc = solve_pcg(hh, L, b.p, tol, maxiter, t, hh.tinfo[L]);
-        if (rc == CASPT2_E_INDEFINITE) return rc;
-        if (rc != CASPT2_OK) status = rc;
-        DBuf T(hh.length);
-        from_orth(hh, set, (const double*)t.p, T.p);
-        hh.T.push_back(std::move(T));
-        hh.Tt.push_back(std::move(t));
-      }
-    }
+    const int status = grouped_solve(hh, 0, 0, tol, maxiter, hh.T, hh.Tt, hh.tinfo);
+    if (status == CASPT2_E_INDEFINITE) return status;
     host_sync(hh);
     hh.have_T = true;
     if (info)
@@ -2197,25 +2496,8 @@ int caspt2_solve_lambda(caspt2_handle* h, int32_t P, double tol, int32_t maxiter
     hh.lam.clear();
     hh.lamt.clear();
     hh.have_lam = false;
-    int status = CASPT2_OK;
-    if (hh.d.precision == CASPT2_FP64) {
-      status = grouped_solve(hh, 1, P, tol, maxiter, hh.lam, hh.lamt, hh.linfo);
-      if (status == CASPT2_E_INDEFINITE) return status;
-    } else {
-      hh.linfo.assign(nst, caspt2_info{});
-      for (int L = 0; L < nst; ++L) {
-        const int set = set_of(hh, L);
-        DBuf b(olen(hh, set)), t;
-        lambda_rhs(hh, L, P, b.p);
-        const int rc = solve_pcg(hh, L, b.p, tol, maxiter, t, hh.linfo[L]);
-        if (rc == CASPT2_E_INDEFINITE) return rc;
-        if (rc != CASPT2_OK) status = rc;
-        DBuf lam(hh.length);
-        from_orth(hh, set, (const double*)t.p, lam.p);
-        hh.lam.push_back(std::move(lam));
-        hh.lamt.push_back(std::move(t));
-      }
-    }
+    const int status = grouped_solve(hh, 1, P, tol, maxiter, hh.lam, hh.lamt, hh.linfo);
+    if (status == CASPT2_E_INDEFINITE) return status;
     host_sync(hh);
     hh.have_lam = true;
     if (info)
@@ -2229,7 +2511,7 @@ int caspt2_batch_solve(caspt2_handle* const* handles, int32_t n, const int32_t* 
   if (!handles || n <= 0 || !targets || !(tol > 0.0) || maxiter < 0) return CASPT2_E_ARG;
   for (int i = 0; i < n; ++i) {
     if (!handles[i] || targets[i] < 0 || targets[i] >= handles[i]->nst) return CASPT2_E_ARG;
-    if (handles[i]->d.precision != CASPT2_FP64) return CASPT2_E_NOTIMPL;
+    if (handles[i]->d.precision != handles[0]->d.precision) return CASPT2_E_ARG;
     for (int j = 0; j < i; ++j)
       if (handles[j] == handles[i]) return CASPT2_E_ARG;
   }
@@ -2240,7 +2522,8 @@ int caspt2_batch_solve(caspt2_handle* const* handles, int32_t n, const int32_t* 
       cap += 2 * handles[i]->nst;
       off[i + 1] = off[i] + handles[i]->nst;
     }
-    PcgEngine eng(cap, std::min(n, 4));   // four operator lanes (the hardware queues of a process)
+    // four operator lanes (the hardware queues of a process)
+    PcgEngine eng(cap, std::min(n, 4), handles[0]->d.precision == CASPT2_MIXED);
     // phase per problem: 0 amplitudes running, 1 lambda running, 2 done, 3 failed
     std::vector<int> phase(n, 0), result(n, CASPT2_OK);
     std::vector<std::vector<int>> amp(n), lam(n);
@@ -2403,12 +2686,18 @@ int caspt2_debug_source(const caspt2_handle* h, int32_t set, int32_t N, double* 
 }
 
 int caspt2_debug_eigh(int32_t n, double* A, double* w, double* V) {
-  if (n <= 0 || !A || !w || !V) return CASPT2_E_ARG;
+  return caspt2_debug_eigh_method(n, A, w, V, 0, nullptr);
+}
+
+int caspt2_debug_eigh_method(int32_t n, double* A, double* w, double* V, int32_t method, int32_t* sweeps_out) {
+  if (n <= 0 || !A || !w || !V || method < 0 || method > 3) return CASPT2_E_ARG;
+  if ((method == 1 && n > 64) || (method == 2 && n > 512)) return CASPT2_E_ARG;
   ABI_GUARD({
     double* ws = nullptr;
     HIPCHECK(hipMalloc(&ws, (4 * (size_t)n + 16) * sizeof(double)));
     int sweeps = 0;
-    hipError_t e = jacobi_eigh(n, A, V, ws, 60, 1e-15, nullptr, &sweeps);
+    hipError_t e = jacobi_eigh(n, A, V, ws, 60, 1e-15, nullptr, &sweeps, method);
+    if (sweeps_out) *sweeps_out = sweeps;
     std::vector<double> full((size_t)n * n);
     if (e == hipSuccess) e = hipMemcpy(full.data(), A, full.size() * sizeof(double), hipMemcpyDeviceToHost);
     (void)hipFree(ws);

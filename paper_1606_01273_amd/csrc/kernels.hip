@@ -60,7 +60,7 @@ hipError_t launch_gather_apply(const double* X, int64_t nlead, int64_t dim_from,
 //     A[i][k]: i = l % 16, k = l / 16;  B[k][j]: j = l % 16, k = l / 16;
 //     D[i][j]: j = l % 16, i = l / 16 + 4 * v, v = 0..3 (checked on gfx950).
 // ---------------------------------------------------------------------------
-constexpr int BM = 64, BN = 64, BK = 16, LDP = BK + 1;
+constexpr int BM = 64, BN = 64, BK = BK_RESIDUAL, LDP = BK + 1;
 // per-thread share of a K tile: A (and B as [N][K]) rows of UA consecutive k;
 // B as [K][N]: KT threads per k row, UB consecutive n each
 constexpr int UA = BM * BK / 256, KT = 256 / BK, UB = BN * BK / 256;
@@ -77,7 +77,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int64_t M, int64_t N, int64_t 
                                                   double* __restrict__ C, int64_t ldc, int64_t sC,
                                                   const double* __restrict__ dvec, double dshift,
                                                   const double* __restrict__ V, int64_t ldv,
-                                                  int m_on_x, int64_t kchunk) {
+                                                  int order, int64_t kchunk) {
   __shared__ double As[BM][LDP];
   __shared__ double Bs[BN][LDP];
   __shared__ double B2s[DUAL ? BN : 1][LDP];
@@ -85,7 +85,29 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int64_t M, int64_t N, int64_t 
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int64_t bz = blockIdx.z;
+  // tile of this workgroup.  order 0/1: n or m tile index on grid x (the
+  // longer tile dimension runs on x; y and z are limited to 65535).  order 2:
+  // XCD-grouped -- workgroups are dispatched round-robin over the 8 XCDs, so
+  // linear id g runs on XCD g % 8; each XCD takes a contiguous range of the
+  // tiles (n fastest), and the tiles of one row band that share their A rows
+  // run on one XCD at about the same time (one L2)
+  int64_t bz, tmi, tni;
+  if (order == 2) {
+    const int64_t gx = gridDim.x, gy = gridDim.y;
+    const int64_t nwg = gx * gy * (int64_t)gridDim.z;
+    const int64_t g = ((int64_t)blockIdx.z * gy + blockIdx.y) * gx + blockIdx.x;
+    const int64_t x = g & 7, j = g >> 3, per = nwg >> 3, rem = nwg & 7;
+    const int64_t t = x * per + (x < rem ? x : rem) + j;
+    const int64_t tnn = (N + BN - 1) / BN, tmn = (M + BM - 1) / BM;
+    bz = t / (tmn * tnn);
+    const int64_t r = t - bz * tmn * tnn;
+    tmi = r / tnn;
+    tni = r - tmi * tnn;
+  } else {
+    bz = blockIdx.z;
+    tmi = order ? blockIdx.x : blockIdx.y;
+    tni = order ? blockIdx.y : blockIdx.x;
+  }
   int64_t kb = 0, ke = K;
   if (SPLIT) {
     kb = bz * kchunk;
@@ -95,9 +117,8 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int64_t M, int64_t N, int64_t 
     B += bz * sB;
     C += bz * sC;
   }
-  // the longer tile dimension runs on grid x (y and z are limited to 65535)
-  const int64_t m0 = (int64_t)(m_on_x ? blockIdx.x : blockIdx.y) * BM;
-  const int64_t n0 = (int64_t)(m_on_x ? blockIdx.y : blockIdx.x) * BN;
+  const int64_t m0 = tmi * BM;
+  const int64_t n0 = tni * BN;
   d4 acc[2][2], acc2[2][2];
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j) {
@@ -254,12 +275,24 @@ __global__ void k_splitk_epilogue(int64_t M, int64_t N, int ns, const double* __
 hipError_t residual_gemm_f64(int64_t M, int64_t N, int64_t K, const double* X, int64_t ldx,
                              const double* S, const double* F, const double* d, double dshift,
                              const double* V, int64_t ldv, double* C, int64_t ldc, hipStream_t s,
-                             double* ws, int64_t ws_len) {
+                             double* ws, int64_t ws_len, LaunchTune tune) {
   if (M <= 0 || N <= 0) return hipSuccess;
   dim3 grid;
   int mx;
   if (!tile_grid(M, N, 1, BM, BN, &grid, &mx)) return hipErrorInvalidValue;
-  const int ns = residual_splitk(M, N, K);
+  if (tune.order >= 0) {
+    // 0: n tiles on grid x, 1: m tiles on grid x, 2: XCD-grouped (the
+    // kernel linearises the grid, any shape with the right count works)
+    if (tune.order > 2) return hipErrorInvalidValue;
+    if (tune.order != mx && tune.order != 2) {
+      const unsigned gx = grid.x, gy = grid.y;
+      if (gx > 65535) return hipErrorInvalidValue;
+      grid.x = gy;
+      grid.y = gx;
+    }
+    mx = tune.order;
+  }
+  const int ns = tune.splitk >= 1 ? tune.splitk : residual_splitk(M, N, K);
   if (ns > 1 && ws && ws_len >= (int64_t)ns * 2 * M * N) {
     // few output tiles: split K over ns workgroups per tile, then one epilogue
     const int64_t kchunk = ((K + ns - 1) / ns + BK - 1) / BK * BK;
@@ -379,13 +412,14 @@ __global__ __launch_bounds__(256) void k_residual_mfma(int64_t M, int K, const d
 
 hipError_t residual_small_f64(int64_t M, int64_t N, const double* X, const double* S,
                               const double* F, const double* d, double dshift, const double* V,
-                              double* C, hipStream_t s) {
+                              double* C, hipStream_t s, LaunchTune tune) {
   if (M <= 0 || N <= 0) return hipSuccess;
   if (N > 64) return hipErrorInvalidValue;
+  const unsigned cap = tune.grid ? tune.grid : 0;
   if (N > 16) {
     const int64_t ntiles = (M + 15) / 16;
     unsigned grid = cdiv(ntiles, 4);
-    if (grid > 16384) grid = 16384;
+    if (grid > (cap ? cap : 16384u)) grid = cap ? cap : 16384u;
     if (N <= 32)
       hipLaunchKernelGGL(k_residual_mfma<32>, dim3(grid), dim3(256), 0, s, M, (int)N, X, S, F, d,
                          dshift, V, C);
@@ -398,7 +432,7 @@ hipError_t residual_small_f64(int64_t M, int64_t N, const double* X, const doubl
     return hipGetLastError();
   }
   unsigned grid = cdiv(M * N, 256);
-  if (grid > 65536) grid = 65536;
+  if (grid > (cap ? cap : 65536u)) grid = cap ? cap : 65536u;
   hipLaunchKernelGGL(k_residual_small<double>, dim3(grid), dim3(256), 0, s, M, (int)N, X, S, F, d,
                      dshift, V, C);
   return hipGetLastError();
@@ -476,13 +510,14 @@ __global__ __launch_bounds__(256) void k_residual_rows(int64_t M0, int64_t M1,
 template <typename T>
 hipError_t residual_rows(int nst, int64_t M0, int64_t M1, const T* X, const T* S0, const T* F0,
                          const T* S1, const T* F1, RowEnergy<T> d0, RowEnergy<T> d1, T dshift,
-                         const T* V, T* C, hipStream_t s) {
+                         const T* V, T* C, hipStream_t s, LaunchTune tune) {
   const int64_t total = M0 + M1;
   if (total <= 0) return hipSuccess;
   if (M0 >= ((int64_t)1 << 31) || M1 >= ((int64_t)1 << 31) || d0.nB == 0 || (M1 > 0 && d1.nB == 0))
     return hipErrorInvalidValue;
+  const unsigned cap = tune.grid ? tune.grid : 65536u;
   unsigned grid = cdiv(total, 256);
-  if (grid > 65536) grid = 65536;
+  if (grid > cap) grid = cap;
   switch (nst) {
 #define CASPT2_ROWS(NS)                                                                        \
   case NS:                                                                                     \
@@ -502,10 +537,11 @@ hipError_t residual_rows(int nst, int64_t M0, int64_t M1, const T* X, const T* S
 template hipError_t residual_rows<double>(int, int64_t, int64_t, const double*, const double*,
                                           const double*, const double*, const double*,
                                           RowEnergy<double>, RowEnergy<double>, double, const double*,
-                                          double*, hipStream_t);
+                                          double*, hipStream_t, LaunchTune);
 template hipError_t residual_rows<float>(int, int64_t, int64_t, const float*, const float*,
                                          const float*, const float*, const float*, RowEnergy<float>,
-                                         RowEnergy<float>, float, const float*, float*, hipStream_t);
+                                         RowEnergy<float>, float, const float*, float*, hipStream_t,
+                                         LaunchTune);
 
 // separable row energies from the full table: A[a] = eps[a nB], B[b] =
 // eps[b] - eps[0] (eps(a nB + b) = A[a] + B[b] when eps is a sum of a
@@ -845,20 +881,29 @@ __global__ void k_jac_norms(int n, const double* __restrict__ A, double* __restr
   }
 }
 
-// Whole cyclic-Jacobi solve in one workgroup (n <= 512): the same
+// Whole cyclic-Jacobi solve in one workgroup (n <= JACOBI_WG_MAX): the same
 // round-robin rotations as the multi-launch path, with barriers instead of
 // launches; stops when the off-diagonal norm falls below tol * |A|_F, stops
-// decreasing, or after max_sweeps.
-__global__ __launch_bounds__(1024) void k_jacobi_small(int n, double* __restrict__ A,
-                                                       double* __restrict__ V, double tol,
+// decreasing, or after max_sweeps.  LDS = true (n <= JACOBI_LDS_MAX): A and
+// V live in LDS for the whole solve (dynamic shared memory of 2 n^2
+// doubles) and are written back at the end.
+constexpr int JACOBI_WG_MAX = 512, JACOBI_LDS_MAX = 64;
+template <bool LDS>
+__global__ __launch_bounds__(1024) void k_jacobi_small(int n, double* __restrict__ Ag,
+                                                       double* __restrict__ Vg, double tol,
                                                        int max_sweeps, int* __restrict__ sweeps) {
-  __shared__ double cs[512];
-  __shared__ int pq[512];
+  __shared__ double cs[JACOBI_WG_MAX];
+  __shared__ int pq[JACOBI_WG_MAX];
   __shared__ double red[2][1024];
   __shared__ int stop;
+  extern __shared__ double dyn[];
   const int t = threadIdx.x, nt = blockDim.x;
   const int m = n + (n & 1);
   const int h = m / 2;
+  double* A = LDS ? dyn : Ag;
+  double* V = LDS ? dyn + (int64_t)n * n : Vg;
+  if (LDS)
+    for (int64_t g = t; g < (int64_t)n * n; g += nt) A[g] = Ag[g];
   for (int64_t g = t; g < (int64_t)n * n; g += nt) V[g] = (g / n == g % n) ? 1.0 : 0.0;
   double prev_off = INFINITY;
   int sw = 0;
@@ -945,17 +990,40 @@ __global__ __launch_bounds__(1024) void k_jacobi_small(int n, double* __restrict
       __syncthreads();
     }
   }
+  if (LDS) {
+    __syncthreads();
+    for (int64_t g = t; g < (int64_t)n * n; g += nt) {
+      Ag[g] = A[g];
+      Vg[g] = V[g];
+    }
+  }
   if (t == 0 && sweeps) *sweeps = sw;
 }
 
 hipError_t jacobi_eigh(int n, double* A, double* V, double* ws, int max_sweeps, double tol,
-                       hipStream_t s, int* sweeps_done) {
+                       hipStream_t s, int* sweeps_done, int method) {
   if (n <= 0) return hipSuccess;
   // the attainable off-diagonal norm grows with n (round-off of the rotations)
   tol = fmax(tol, 4e-16 * (double)n);
-  if (n <= 512) {
+  if (method == 0 || method == 1) {
+    // the LDS form needs 2 n^2 doubles of dynamic LDS beside its static arrays
+    int dev = 0, lds_max = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (e != hipSuccess) return e;
+    const size_t need = 2 * (size_t)n * n * sizeof(double) + 24 * 1024;
+    const bool lds_ok = n <= JACOBI_LDS_MAX && need <= (size_t)lds_max;
+    if (method == 1 && !lds_ok) return hipErrorInvalidValue;
+    if (method == 0) method = lds_ok ? 1 : n <= JACOBI_WG_AUTO ? 2 : 3;
+  }
+  if (method == 2 && n > JACOBI_WG_MAX) return hipErrorInvalidValue;
+  if (method == 1 || method == 2) {
     int* dsw = reinterpret_cast<int*>(ws + 2 * n + 8);
-    hipLaunchKernelGGL(k_jacobi_small, dim3(1), dim3(1024), 0, s, n, A, V, tol, max_sweeps, dsw);
+    if (method == 1)
+      hipLaunchKernelGGL(k_jacobi_small<true>, dim3(1), dim3(1024), 2 * (size_t)n * n * sizeof(double), s, n,
+                         A, V, tol, max_sweeps, dsw);
+    else
+      hipLaunchKernelGGL(k_jacobi_small<false>, dim3(1), dim3(1024), 0, s, n, A, V, tol, max_sweeps, dsw);
     if (sweeps_done) {
       hipError_t e = hipMemcpyAsync(sweeps_done, dsw, sizeof(int), hipMemcpyDeviceToHost, s);
       if (e != hipSuccess) return e;
@@ -1088,6 +1156,7 @@ CASPT2_ELEMENTWISE(xpay, y[g] = x[g] + (Y)a * y[g])
 CASPT2_ELEMENTWISE(div, y[g] = x[g] / d[g])
 CASPT2_ELEMENTWISE(scale_copy, y[g] = (Y)(a * x[g]))
 CASPT2_ELEMENTWISE(fill, y[g] = (Y)a)
+CASPT2_ELEMENTWISE(negsum, y[g] = -(x[g] + y[g]))
 
 static inline unsigned egrid(int64_t n) {
   unsigned g = cdiv(n, 256);
@@ -1104,6 +1173,12 @@ template <typename T>
 hipError_t vec_xpay(int64_t n, const T* x, double a, T* y, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL((k_xpay<T, T>), dim3(egrid(n)), dim3(256), 0, s, n, a, x, (const T*)nullptr, y);
+  return hipGetLastError();
+}
+hipError_t vec_negsum(int64_t n, const double* x, double* y, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_negsum<double, double>), dim3(egrid(n)), dim3(256), 0, s, n, 0.0, x,
+                     (const double*)nullptr, y);
   return hipGetLastError();
 }
 template <typename T>

@@ -19,6 +19,17 @@ hipError_t gemm_f64(bool b_is_nk, int64_t M, int64_t N, int64_t K, double alpha,
                     int64_t lda, int64_t sA, const double* B, int64_t ldb, int64_t sB, double beta,
                     double* C, int64_t ldc, int64_t sC, int batch, hipStream_t s);
 
+// Launch choices of a residual entry; a field left at its default means
+// "by rule" (the launcher's built-in choice for the shape).  The autotuner
+// sets them per entry from timings.
+constexpr int BK_RESIDUAL = 16;   // K tile of the residual GEMM (split ranges are multiples)
+struct LaunchTune {
+  int splitk = -1;     // residual GEMM: K splits (1 = none)
+  int order = -1;      // residual GEMM tile order: 0/1 plain (n or m tiles on
+                       // grid x), 2 XCD-grouped
+  unsigned grid = 0;   // streaming residual kernels: cap on the workgroup count
+};
+
 // Residual of one packed entry on MFMA:
 //   C[m][n] = V[m][n] + d[m] * (X S)[m][n] + (X F)[m][n]   (V may be null)
 // X [M][K], S and F [K][N] row major (symmetric in use), d [M].
@@ -28,13 +39,13 @@ hipError_t gemm_f64(bool b_is_nk, int64_t M, int64_t N, int64_t K, double alpha,
 hipError_t residual_gemm_f64(int64_t M, int64_t N, int64_t K, const double* X, int64_t ldx,
                              const double* S, const double* F, const double* d, double dshift,
                              const double* V, int64_t ldv, double* C, int64_t ldc, hipStream_t s,
-                             double* ws = nullptr, int64_t ws_len = 0);
-// number of K splits residual_gemm_f64 uses for this shape (1: none)
+                             double* ws = nullptr, int64_t ws_len = 0, LaunchTune tune = {});
+// number of K splits residual_gemm_f64 uses by rule for this shape (1: none)
 int residual_splitk(int64_t M, int64_t N, int64_t K);
 // Same for small K = N (<= 64): streaming kernel with S, F staged in LDS.
 hipError_t residual_small_f64(int64_t M, int64_t N, const double* X, const double* S,
                               const double* F, const double* d, double dshift, const double* V,
-                              double* C, hipStream_t s);
+                              double* C, hipStream_t s, LaunchTune tune = {});
 
 // FP32 form of residual_small_f64 for K = N <= 64 (SIMT, S and F in LDS).
 hipError_t residual_small_f32(int64_t M, int64_t N, const float* X, const float* S, const float* F,
@@ -59,7 +70,7 @@ hipError_t split_energies(int64_t nA, int64_t nB, const double* eps, double* A, 
 template <typename T>
 hipError_t residual_rows(int nst, int64_t M0, int64_t M1, const T* X, const T* S0, const T* F0,
                          const T* S1, const T* F1, RowEnergy<T> d0, RowEnergy<T> d1, T dshift,
-                         const T* V, T* C, hipStream_t s);
+                         const T* V, T* C, hipStream_t s, LaunchTune tune = {});
 
 // C = alpha * A * op(B) + beta * C in FP32 (SIMT FMA, 64 x 64 tiles); same
 // operand conventions as gemm_f64.
@@ -191,9 +202,13 @@ hipError_t select_scale_cols(int64_t n, int64_t ncq, const double* Q, const int3
 
 // Jacobi eigensolver of a symmetric n x n matrix A (destroyed; diagonal ->
 // eigenvalues, unsorted); V receives eigenvectors (columns).  ws: device
-// workspace of >= 4*n doubles + 2*n ints. sweeps: max sweeps.
+// workspace of >= 4*n doubles + 2*n ints. sweeps: max sweeps.  method: 0
+// by size (below), 1 one workgroup with A and V in LDS (n <= 64), 2 one
+// workgroup on global memory (n <= 512), 3 one launch pair per rotation
+// step over the whole chip.
+constexpr int JACOBI_WG_AUTO = 96;   // largest n solved by one workgroup by default
 hipError_t jacobi_eigh(int n, double* A, double* V, double* ws, int max_sweeps, double tol,
-                       hipStream_t s, int* sweeps_done);
+                       hipStream_t s, int* sweeps_done, int method = 0);
 
 // vector kernels (element types as instantiated in kernels.hip)
 template <typename T>  // FP64 accumulation; out on device (1 double); partial >= 1024 doubles
@@ -208,6 +223,8 @@ template <typename X, typename Y>  // y = a x (converting)
 hipError_t vec_scale_copy(int64_t n, double a, const X* x, Y* y, hipStream_t s);
 template <typename T>
 hipError_t vec_fill(int64_t n, double v, T* y, hipStream_t s);
+// y = -(x + y)
+hipError_t vec_negsum(int64_t n, const double* x, double* y, hipStream_t s);
 hipError_t vec_min(int64_t n, const double* x, double* partial, double* out, hipStream_t s);
 
 // ---------------------------------------------------------------------------

@@ -69,6 +69,40 @@ def test_batch_matches_oracle(dev):
         g.close()
 
 
+def test_batch_mixed_matches_oracle(dev):
+    """The same uneven batch in the mixed mode (FP32 grouped inner PCG, FP64
+    refinement per system): energies within 1e-8 Eh of the oracle, T and
+    lambda within 1e-6 relative, every system with a non-zero right-hand side
+    refined at least once."""
+    from oracle.ic import Caspt2Oracle
+    from paper_1606_01273_amd import MIXED, Caspt2, batch_solve
+    probs = [make_problem(*d, seed=s, reading=r, shift=sh) for d, s, r, sh, _ in SMALL]
+    targets = [c[4] for c in SMALL]
+    gs = [Caspt2.from_problem(p, precision=MIXED) for p in probs]
+    rc, ainfo, linfo = batch_solve(gs, targets, tol=1e-10, maxiter=400)
+    assert rc == 0, f"batch status {rc}"
+    for i, (p, g, P) in enumerate(zip(probs, gs, targets)):
+        print("problem", i, SMALL[i][:3], "amp iters/refinements",
+              [(a["iters"], a["refinements"]) for a in ainfo[i]],
+              "lambda", [(a["iters"], a["refinements"]) for a in linfo[i]], flush=True)
+        assert all(a["flags"] & 1 and a["resnorm"] <= 1e-10 for a in ainfo[i] + linfo[i])
+        # a system whose right-hand side vanishes (a lambda state with R_LP = 0)
+        # is solved at the start, without refinement
+        assert all(a["refinements"] >= 1 or a["iters"] == 0 for a in ainfo[i] + linfo[i])
+        o = Caspt2Oracle(p, "MSMR").run(P=P)
+        for L in range(p.nst):
+            T = g.amplitudes(L).cpu().numpy()
+            _ok(np.linalg.norm(T - o.T[L]) / max(np.linalg.norm(o.T[L]), 1e-300), 1e-6, f"T {i} L {L}")
+        H, w, R = g.heff()
+        _ok(np.abs(w - o.e_ms).max(), 1e-8, f"E_MS {i}")
+        scale = max(np.linalg.norm(v) for v in o.lam)
+        for L in range(p.nst):
+            lam = g.lam(L).cpu().numpy()
+            _ok(np.linalg.norm(lam - o.lam[L]) / scale, 1e-6, f"lambda {i} L {L}")
+    for g in gs:
+        g.close()
+
+
 def test_batch_matches_single_solves(dev):
     """First 12 problems of the 64-instance uneven workload (closed 4-16,
     active 4-6, virtual 20-150, 1-4 states, shift 0.2, Fock couplings on):
@@ -118,7 +152,7 @@ def test_batch_matches_single_solves(dev):
 
 
 def test_batch_argument_errors(dev):
-    from paper_1606_01273_amd import E_ARG, E_NOTIMPL, MIXED, Caspt2, Caspt2Error, batch_solve
+    from paper_1606_01273_amd import E_ARG, MIXED, Caspt2, Caspt2Error, batch_solve
     p = make_problem(2, 2, 3, 12, 2, seed=1, reading="A", shift=0.1)
     g = Caspt2.from_problem(p)
     with pytest.raises(Caspt2Error) as ex:
@@ -129,8 +163,8 @@ def test_batch_argument_errors(dev):
     assert ex.value.code == E_ARG
     gm = Caspt2.from_problem(p, precision=MIXED)
     with pytest.raises(Caspt2Error) as ex:
-        batch_solve([g, gm])
-    assert ex.value.code == E_NOTIMPL
+        batch_solve([g, gm])             # precisions differ
+    assert ex.value.code == E_ARG
     rc, a, l = batch_solve([g], [1])      # a batch of one
     assert rc == 0 and len(a) == 1 and len(a[0]) == 2
     g.close()

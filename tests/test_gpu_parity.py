@@ -72,6 +72,28 @@ def test_debug_eigh_matches_numpy(dev):
         _ok(np.abs(Vn.T @ Vn - np.eye(n)).max(), 1e-12, f"eigh orthonormality n={n}")
 
 
+@pytest.mark.parametrize("method,sizes", [(1, (1, 2, 7, 33, 64)), (2, (2, 7, 64, 101, 300)),
+                                          (3, (2, 7, 64, 101, 257))])
+def test_debug_eigh_methods_match_numpy(dev, method, sizes):
+    """every form of the Jacobi solver (LDS workgroup, global-memory workgroup,
+    whole-device launches) on the sizes it takes"""
+    from paper_1606_01273_amd import lib
+    rng = np.random.default_rng(2)
+    for n in sizes:
+        G = rng.standard_normal((n, n))
+        S = G @ G.T / n
+        ta = torch.tensor(S, device=dev)
+        V = torch.empty((n, n), dtype=torch.float64, device=dev)
+        w = np.zeros(n)
+        sw = ctypes.c_int32()
+        assert lib().caspt2_debug_eigh_method(n, ta.data_ptr(), w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                              V.data_ptr(), method, ctypes.byref(sw)) == 0
+        Vn = V.cpu().numpy()
+        _ok(np.abs(np.sort(w) - np.linalg.eigvalsh(S)).max(), 1e-12, f"eigh values n={n} method {method}")
+        _ok(np.abs(Vn @ np.diag(w) @ Vn.T - S).max(), 1e-12, f"eigh reconstruction n={n} method {method}")
+        _ok(np.abs(Vn.T @ Vn - np.eye(n)).max(), 1e-12, f"eigh orthonormality n={n} method {method}")
+
+
 CASES = [
     # (dims, seed, reading, scheme, xms, shift); seeds chosen free of intruders
     ((2, 3, 3, 16, 3), 7, "A", "MSMR", True, 0.15),
