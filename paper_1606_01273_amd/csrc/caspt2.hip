@@ -2012,10 +2012,14 @@ std::vector<LaunchTune> tune_candidates(const std::vector<Entry>& es, size_t k, 
   for (int order : {-1, 2})
     for (int ns : {1, 2, 4, 8, 16, 32, 64}) {
       if (ns > 1 && ((int64_t)ns * BK_RESIDUAL > K || (int64_t)ns * 2 * M * N > ws_cap)) continue;
-      LaunchTune t;
-      t.splitk = ns;
-      t.order = order;
-      c.push_back(t);
+      for (int tile : {64, 128}) {
+        if (tile == 128 && (ns > 1 || M < 4 * 128)) continue;
+        LaunchTune t;
+        t.splitk = ns;
+        t.order = order;
+        t.tile = tile;
+        c.push_back(t);
+      }
     }
   return c;
 }
@@ -2049,7 +2053,9 @@ void load_tune_file(const char* path) {
     if (!tab) continue;
     *tab = 0;
     LaunchTune t;
-    if (std::sscanf(tab + 1, "%d %d %u", &t.splitk, &t.order, &t.grid) != 3) continue;
+    const int got = std::sscanf(tab + 1, "%d %d %u %d", &t.splitk, &t.order, &t.grid, &t.tile);
+    if (got < 3) continue;
+    if (got == 3) t.tile = 0;
     g_tune_cache[line] = t;
   }
   std::fclose(f);
@@ -2061,7 +2067,8 @@ void save_tune_file(const char* path) {
   FILE* f = std::fopen(tmp.c_str(), "w");
   if (!f) throw DevError(CASPT2_E_ARG, "cannot write the tuning cache file");
   for (auto& kv : g_tune_cache)
-    std::fprintf(f, "%s\t%d %d %u\n", kv.first.c_str(), kv.second.splitk, kv.second.order, kv.second.grid);
+    std::fprintf(f, "%s\t%d %d %u %d\n", kv.first.c_str(), kv.second.splitk, kv.second.order, kv.second.grid,
+                 kv.second.tile);
   std::fclose(f);
   if (std::rename(tmp.c_str(), path) != 0) throw DevError(CASPT2_E_ARG, "cannot replace the tuning cache file");
 }
@@ -2114,8 +2121,8 @@ void autotune(H& h, const char* cache_path, bool force) {
           e.tune_best_ms = best;
           g_tune_cache[key] = pick;
           if (h.verbose)
-            std::fprintf(stderr, "[caspt2] tune %-28s splitk %d order %d grid %u: %.4f ms (rule %.4f ms)\n",
-                         key.c_str(), pick.splitk, pick.order, pick.grid, best, rule);
+            std::fprintf(stderr, "[caspt2] tune %-28s splitk %d order %d grid %u tile %d: %.4f ms (rule %.4f ms)\n",
+                         key.c_str(), pick.splitk, pick.order, pick.grid, pick.tile, best, rule);
         }
         if (pair) es[k + 1].tune = e.tune;
         if (pair) ++k;
@@ -2367,6 +2374,7 @@ int caspt2_tune_entry(const caspt2_handle* h, int32_t k, int32_t* choice, double
     choice[0] = e.tune.splitk;
     choice[1] = e.tune.order;
     choice[2] = (int32_t)e.tune.grid;
+    choice[3] = e.tune.tile;
   }
   if (rule_ms) *rule_ms = e.tune_rule_ms;
   if (tuned_ms) *tuned_ms = e.tune_best_ms;

@@ -61,14 +61,17 @@ hipError_t launch_gather_apply(const double* X, int64_t nlead, int64_t dim_from,
 //     D[i][j]: j = l % 16, i = l / 16 + 4 * v, v = 0..3 (checked on gfx950).
 // ---------------------------------------------------------------------------
 constexpr int BM = 64, BN = 64, BK = BK_RESIDUAL, LDP = BK + 1;
-// per-thread share of a K tile: A (and B as [N][K]) rows of UA consecutive k;
-// B as [K][N]: KT threads per k row, UB consecutive n each
-constexpr int UA = BM * BK / 256, KT = 256 / BK, UB = BN * BK / 256;
-static_assert(BM == 64 && BN == 64 && UA * 256 == BM * BK && KT * BK == 256, "tile shares");
+// B (as [K][N]): KT threads per k row, UB consecutive n each; B as [N][K]:
+// four threads per n row, UN consecutive k each
+constexpr int KT = 256 / BK, UB = BN * BK / 256, UN = BK / 4;
+static_assert(BN == 64 && KT * BK == 256 && UB * 256 == BN * BK, "tile shares");
 
+// MT: 16-row MFMA blocks per wave along M; the workgroup tile is (32 MT) x
+// 64 (MT = 2: 64 x 64, MT = 4: 128 x 64 -- more flops per byte staged, at
+// twice the accumulator registers).
 // SPLIT (dual only): blockIdx.z selects a K range of kchunk; the raw X S and
 // X F partial products go to C as [split][2][M][N] for a separate epilogue.
-template <bool B_NK, bool DUAL, bool SPLIT = false>
+template <bool B_NK, bool DUAL, bool SPLIT = false, int MT = 2>
 __global__ __launch_bounds__(256) void k_gemm_f64(int64_t M, int64_t N, int64_t K, double alpha,
                                                   const double* __restrict__ A, int64_t lda,
                                                   int64_t sA, const double* __restrict__ B,
@@ -78,7 +81,11 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int64_t M, int64_t N, int64_t 
                                                   const double* __restrict__ dvec, double dshift,
                                                   const double* __restrict__ V, int64_t ldv,
                                                   int order, int64_t kchunk) {
-  __shared__ double As[BM][LDP];
+  constexpr int TM = 32 * MT;          // tile rows
+  constexpr int TPR = 256 / TM;        // threads per A row of a K tile
+  constexpr int UA = BK / TPR;         // consecutive k per thread in the A tile
+  static_assert(TPR * TM == 256 && UA * TPR == BK, "A tile shares");
+  __shared__ double As[TM][LDP];
   __shared__ double Bs[BN][LDP];
   __shared__ double B2s[DUAL ? BN : 1][LDP];
   const int tid = threadIdx.x;
@@ -98,7 +105,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int64_t M, int64_t N, int64_t 
     const int64_t g = ((int64_t)blockIdx.z * gy + blockIdx.y) * gx + blockIdx.x;
     const int64_t x = g & 7, j = g >> 3, per = nwg >> 3, rem = nwg & 7;
     const int64_t t = x * per + (x < rem ? x : rem) + j;
-    const int64_t tnn = (N + BN - 1) / BN, tmn = (M + BM - 1) / BM;
+    const int64_t tnn = (N + BN - 1) / BN, tmn = (M + TM - 1) / TM;
     bz = t / (tmn * tnn);
     const int64_t r = t - bz * tmn * tnn;
     tmi = r / tnn;
@@ -117,10 +124,10 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int64_t M, int64_t N, int64_t 
     B += bz * sB;
     C += bz * sC;
   }
-  const int64_t m0 = tmi * BM;
+  const int64_t m0 = tmi * TM;
   const int64_t n0 = tni * BN;
-  d4 acc[2][2], acc2[2][2];
-  for (int i = 0; i < 2; ++i)
+  d4 acc[MT][2], acc2[MT][2];
+  for (int i = 0; i < MT; ++i)
     for (int j = 0; j < 2; ++j) {
       acc[i][j] = d4{0, 0, 0, 0};
       acc2[i][j] = d4{0, 0, 0, 0};
@@ -128,10 +135,10 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int64_t M, int64_t N, int64_t 
   // global -> registers -> LDS; the next K tile's loads are issued before
   // the MFMAs of the current one (register prefetch), so their latency hides
   // behind the matrix work
-  double ra[UA], rb[UA > UB ? UA : UB], rb2[UB];
+  double ra[UA], rb[UN > UB ? UN : UB], rb2[UB];
   auto load_tile = [&](int64_t k0) {
-    {  // A tile: 64 rows x BK k, UA per thread
-      const int r = tid >> 2, c = (tid & 3) * UA;
+    {  // A tile: TM rows x BK k, UA per thread
+      const int r = tid / TPR, c = (tid % TPR) * UA;
       const int64_t gm = m0 + r;
 #pragma unroll
       for (int u = 0; u < UA; ++u) {
@@ -140,10 +147,10 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int64_t M, int64_t N, int64_t 
       }
     }
     if (B_NK) {
-      const int r = tid >> 2, c = (tid & 3) * UA;
+      const int r = tid >> 2, c = (tid & 3) * UN;
       const int64_t gn = n0 + r;
 #pragma unroll
-      for (int u = 0; u < UA; ++u) {
+      for (int u = 0; u < UN; ++u) {
         const int64_t gk = k0 + c + u;
         rb[u] = (gn < N && gk < ke) ? B[gn * ldb + gk] : 0.0;
       }
@@ -162,14 +169,14 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int64_t M, int64_t N, int64_t 
   };
   auto store_tile = [&]() {
     {
-      const int r = tid >> 2, c = (tid & 3) * UA;
+      const int r = tid / TPR, c = (tid % TPR) * UA;
 #pragma unroll
       for (int u = 0; u < UA; ++u) As[r][c + u] = ra[u];
     }
     if (B_NK) {
-      const int r = tid >> 2, c = (tid & 3) * UA;
+      const int r = tid >> 2, c = (tid & 3) * UN;
 #pragma unroll
-      for (int u = 0; u < UA; ++u) Bs[r][c + u] = rb[u];
+      for (int u = 0; u < UN; ++u) Bs[r][c + u] = rb[u];
     } else {
       const int kk = tid / KT, c = (tid % KT) * UB;
 #pragma unroll
@@ -185,13 +192,13 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int64_t M, int64_t N, int64_t 
     __syncthreads();
     if (k0 + BK < ke) load_tile(k0 + BK);
     for (int kk = 0; kk < BK; kk += 4) {
-      double a[2], b[2], b2[2];
-      for (int i = 0; i < 2; ++i) a[i] = As[wm * 32 + i * 16 + (lane & 15)][kk + (lane >> 4)];
+      double a[MT], b[2], b2[2];
+      for (int i = 0; i < MT; ++i) a[i] = As[wm * (16 * MT) + i * 16 + (lane & 15)][kk + (lane >> 4)];
       for (int j = 0; j < 2; ++j) {
         b[j] = Bs[wn * 32 + j * 16 + (lane & 15)][kk + (lane >> 4)];
         if (DUAL) b2[j] = B2s[wn * 32 + j * 16 + (lane & 15)][kk + (lane >> 4)];
       }
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < MT; ++i)
         for (int j = 0; j < 2; ++j) {
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
           if (DUAL) acc2[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b2[j], acc2[i][j], 0, 0, 0);
@@ -199,10 +206,10 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int64_t M, int64_t N, int64_t 
     }
     __syncthreads();
   }
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < MT; ++i)
     for (int j = 0; j < 2; ++j)
       for (int v = 0; v < 4; ++v) {
-        const int64_t gm = m0 + wm * 32 + i * 16 + (lane >> 4) + 4 * v;
+        const int64_t gm = m0 + wm * (16 * MT) + i * 16 + (lane >> 4) + 4 * v;
         const int64_t gn = n0 + wn * 32 + j * 16 + (lane & 15);
         if (gm < M && gn < N) {
           if (SPLIT) {
@@ -277,9 +284,13 @@ hipError_t residual_gemm_f64(int64_t M, int64_t N, int64_t K, const double* X, i
                              const double* V, int64_t ldv, double* C, int64_t ldc, hipStream_t s,
                              double* ws, int64_t ws_len, LaunchTune tune) {
   if (M <= 0 || N <= 0) return hipSuccess;
+  if (tune.tile != 0 && tune.tile != 64 && tune.tile != 128) return hipErrorInvalidValue;
+  int ns = tune.splitk >= 1 ? tune.splitk : residual_splitk(M, N, K);
+  if (!(ns > 1 && ws && ws_len >= (int64_t)ns * 2 * M * N)) ns = 1;
+  const int tm = (ns == 1 && tune.tile == 128) ? 128 : 64;   // 128-row tiles without K splits only
   dim3 grid;
   int mx;
-  if (!tile_grid(M, N, 1, BM, BN, &grid, &mx)) return hipErrorInvalidValue;
+  if (!tile_grid(M, N, 1, tm, BN, &grid, &mx)) return hipErrorInvalidValue;
   if (tune.order >= 0) {
     // 0: n tiles on grid x, 1: m tiles on grid x, 2: XCD-grouped (the
     // kernel linearises the grid, any shape with the right count works)
@@ -292,8 +303,7 @@ hipError_t residual_gemm_f64(int64_t M, int64_t N, int64_t K, const double* X, i
     }
     mx = tune.order;
   }
-  const int ns = tune.splitk >= 1 ? tune.splitk : residual_splitk(M, N, K);
-  if (ns > 1 && ws && ws_len >= (int64_t)ns * 2 * M * N) {
+  if (ns > 1) {
     // few output tiles: split K over ns workgroups per tile, then one epilogue
     const int64_t kchunk = ((K + ns - 1) / ns + BK - 1) / BK * BK;
     const int nsplit = (int)((K + kchunk - 1) / kchunk);
@@ -307,9 +317,14 @@ hipError_t residual_gemm_f64(int64_t M, int64_t N, int64_t K, const double* X, i
                        dshift, V, ldv, C, ldc);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL((k_gemm_f64<false, true>), grid, dim3(256), 0, s, M, N, K, 1.0, X, ldx,
-                     (int64_t)0, S, N, (int64_t)0, F, 0.0, C, ldc, (int64_t)0, d, dshift, V, ldv, mx,
-                     (int64_t)0);
+  if (tm == 128)
+    hipLaunchKernelGGL((k_gemm_f64<false, true, false, 4>), grid, dim3(256), 0, s, M, N, K, 1.0, X, ldx,
+                       (int64_t)0, S, N, (int64_t)0, F, 0.0, C, ldc, (int64_t)0, d, dshift, V, ldv, mx,
+                       (int64_t)0);
+  else
+    hipLaunchKernelGGL((k_gemm_f64<false, true>), grid, dim3(256), 0, s, M, N, K, 1.0, X, ldx,
+                       (int64_t)0, S, N, (int64_t)0, F, 0.0, C, ldc, (int64_t)0, d, dshift, V, ldv, mx,
+                       (int64_t)0);
   return hipGetLastError();
 }
 

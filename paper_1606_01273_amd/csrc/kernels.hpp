@@ -28,6 +28,7 @@ struct LaunchTune {
   int order = -1;      // residual GEMM tile order: 0/1 plain (n or m tiles on
                        // grid x), 2 XCD-grouped
   unsigned grid = 0;   // streaming residual kernels: cap on the workgroup count
+  int tile = 0;        // residual GEMM tile rows: 64 or 128 (without K splits)
 };
 
 // Residual of one packed entry on MFMA:

@@ -1,6 +1,7 @@
 """Summaries of rocprofv3 output for the measurement record (text and JSON).
 
-  python -m paper_1606_01273_amd.rocprof_summary stats KERNEL_STATS_CSV OUT_TXT --command CMD
+  python -m paper_1606_01273_amd.rocprof_summary stats KERNEL_STATS_CSV OUT_TXT --command CMD \
+      [--trace KERNEL_TRACE_CSV --last-kernel REGEX --last N]
   python -m paper_1606_01273_amd.rocprof_summary pmc FETCH_CSV WRITE_CSV OUT_JSON OUT_TXT \
       --key WORKLOAD/READING/ENTRY --kernel REGEX --command-fetch CMD --command-write CMD
   python -m paper_1606_01273_amd.rocprof_summary mfma COUNTER_CSV OUT_TXT --command CMD
@@ -39,12 +40,17 @@ def rows_kernel_source_sha256() -> str:
 
 
 def _per_dispatch(path: str, counter: str):
-    out = {}
+    """counter value per dispatch, per kernel name, in dispatch order"""
+    rows = []
     with open(path) as fh:
         for r in csv.DictReader(fh):
             if r.get("Counter_Name") != counter:
                 continue
-            out.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+            rows.append((int(r.get("Dispatch_Id") or 0), r["Kernel_Name"], float(r["Counter_Value"])))
+    rows.sort(key=lambda t: t[0])
+    out = {}
+    for _, name, v in rows:
+        out.setdefault(name, []).append(v)
     return out
 
 
@@ -59,9 +65,26 @@ def cmd_stats(a):
         name = re.sub(r"\s+", " ", r["Name"])[:110]
         lines.append(f"{float(r['TotalDurationNs']) / 1e6:10.3f} {int(r['Calls']):7d} "
                      f"{float(r['AverageNs']) / 1e3:10.2f} {100 * float(r['TotalDurationNs']) / tot:6.2f}  {name}")
+    if a.trace and a.last_kernel and a.last > 0:
+        # per-dispatch durations of one kernel from the kernel trace: the last
+        # N dispatches are the timed ones (earlier ones include the
+        # autotuner's trial launches of other launch shapes)
+        kre = re.compile(a.last_kernel)
+        disp = []
+        with open(a.trace) as fh:
+            for r in csv.DictReader(fh):
+                if kre.search(r.get("Kernel_Name", "")):
+                    disp.append((int(r.get("Dispatch_Id") or 0),
+                                 int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+        disp.sort()
+        sel = [d for _, d in disp[-a.last:]]
+        if sel:
+            lines += ["", f"last {len(sel)} dispatches of {a.last_kernel} (of {len(disp)}): "
+                          f"average {sum(sel) / len(sel) / 1e3:.2f} us, min {min(sel) / 1e3:.2f} us, "
+                          f"max {max(sel) / 1e3:.2f} us"]
     with open(a.out, "w") as fh:
         fh.write("\n".join(lines) + "\n")
-    print("\n".join(lines[:12]))
+    print("\n".join(lines[:12] + lines[-1:]))
 
 
 def cmd_pmc(a):
@@ -76,6 +99,8 @@ def cmd_pmc(a):
     kf, kw = pick(fetch, kre), pick(write, kre)
     if not kf or not kw:
         sys.exit(f"no dispatch of {a.kernel} in the counter files")
+    if a.last > 0:   # the timed launches only (not the autotuner's trial launches before them)
+        kf, kw = kf[-a.last:], kw[-a.last:]
     fill_w = pick(write, r"FillFunctor")
     mul_f = pick(fetch, r"MulFunctor")
     mul_w = pick(write, r"MulFunctor")
@@ -94,7 +119,7 @@ def cmd_pmc(a):
            "dispatches": [len(kf), len(kw)], "fetch_scale": fetch_scale, "write_scale": write_scale,
            "calibration": {"fill_write_kib": fill_w[-1], "mul_fetch_kib": mul_f[-1],
                            "mul_write_kib": mul_w[-1] if mul_w else None},
-           "kernel_regex": a.kernel, "kernel_source_sha256": rows_kernel_source_sha256(),
+           "kernel_regex": a.kernel, "last_dispatches": a.last, "kernel_source_sha256": rows_kernel_source_sha256(),
            "command_fetch": a.command_fetch, "command_write": a.command_write}
     db = {}
     if os.path.exists(a.out_json):
@@ -124,10 +149,20 @@ def cmd_mfma(a):
     per = {}
     with open(a.csv) as fh:
         for r in csv.DictReader(fh):
-            key = (r["Kernel_Name"], r.get("Dispatch_Id") or r.get("Correlation_Id") or "")
+            key = (r["Kernel_Name"], int(r.get("Dispatch_Id") or r.get("Correlation_Id") or 0))
             per.setdefault(key, {})[r["Counter_Name"]] = float(r["Counter_Value"])
+    first = 0
+    if a.from_last:
+        # keep the dispatches from the N-th last dispatch of the marker kernel
+        # on (the timed region; earlier ones include the autotuner's trials)
+        mre, n = re.compile(a.from_last[0]), int(a.from_last[1])
+        ids = sorted(d for (name, d) in per if mre.search(name))
+        if len(ids) >= n:
+            first = ids[-n]
     agg = {}
-    for (name, _), c in per.items():
+    for (name, did), c in per.items():
+        if did < first:
+            continue
         short = re.sub(r"\(.*", "", re.sub(r"\s+", " ", name))[:70]
         g = agg.setdefault(short, {"n": 0, "busy": 0.0, "gui": 0.0, "mops": 0.0})
         g["n"] += 1
@@ -135,6 +170,7 @@ def cmd_mfma(a):
         g["gui"] += c.get("GRBM_GUI_ACTIVE", 0.0)
         g["mops"] += c.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0)
     lines = [f"# rocprofv3 MFMA counters per kernel (averages per dispatch)", f"# command: {a.command}",
+             f"# dispatches from the {a.from_last[1]}-th last of {a.from_last[0]} on" if a.from_last else "#",
              "# F64 MFMA GFLOP = 512 * SQ_INSTS_VALU_MFMA_MOPS_F64 / 1e9; GRBM_GUI_ACTIVE is summed over the",
              f"# {a.xcds} XCDs, so the dispatch time is GUI_ACTIVE / ({a.xcds} * {a.clock_ghz} GHz); MFMA_BUSY counts per",
              f"# SIMD: utilisation = MFMA_BUSY / (GUI_ACTIVE / {a.xcds} * {a.simds} SIMDs)", "",
@@ -160,6 +196,9 @@ def main():
     s.add_argument("out")
     s.add_argument("--command", required=True)
     s.add_argument("--top", type=int, default=25)
+    s.add_argument("--trace", help="kernel trace CSV (per-dispatch timestamps)")
+    s.add_argument("--last-kernel", help="kernel regex for the last-N average")
+    s.add_argument("--last", type=int, default=0)
     p = sub.add_parser("pmc")
     p.add_argument("fetch_csv")
     p.add_argument("write_csv")
@@ -169,6 +208,7 @@ def main():
     p.add_argument("--kernel", required=True)
     p.add_argument("--command-fetch", required=True)
     p.add_argument("--command-write", required=True)
+    p.add_argument("--last", type=int, default=0, help="average over the last N dispatches of the kernel only")
     m = sub.add_parser("mfma")
     m.add_argument("csv")
     m.add_argument("out")
@@ -176,6 +216,8 @@ def main():
     m.add_argument("--xcds", type=int, default=8)
     m.add_argument("--simds", type=int, default=1024)
     m.add_argument("--clock-ghz", type=float, default=2.4)
+    m.add_argument("--from-last", nargs=2, metavar=("KERNEL_REGEX", "N"),
+                   help="only dispatches from the N-th last dispatch of this kernel on")
     a = ap.parse_args()
     {"stats": cmd_stats, "pmc": cmd_pmc, "mfma": cmd_mfma}[a.cmd](a)
 
