@@ -250,8 +250,9 @@ def main():
         t0 = time.perf_counter()
         choices = g.autotune()
         t_tune = time.perf_counter() - t0
-        tune = {k: {"splitk": c[0], "order": c[1], "grid": c[2], "tile": c[3], "rule_ms": round(c[4], 4),
-                    "tuned_ms": round(c[5], 4)} for k, c in choices.items() if c[4] > 0}
+        tune = {k: {"splitk": c[0], "order": c[1], "grid": c[2], "tile": c[3], "kb": c[4], "occ": c[5],
+                    "plain": c[6], "rule_ms": round(c[7], 4), "tuned_ms": round(c[8], 4)}
+                for k, c in choices.items() if c[7] > 0}
         print(f"[bench] autotuned the residual launches in {t_tune:.1f} s", file=sys.stderr, flush=True)
     gen = torch.Generator(device="cuda")
     gen.manual_seed(0)

@@ -160,8 +160,9 @@ CASPT2_API int caspt2_set_precision(caspt2_handle* h, int32_t precision);
 /* Autotune the launches of the FP64 residual (Eq. 10, within-block part) of
  * this handle: for every packed entry, time each candidate -- the K split
  * count and tile order (plain or XCD-grouped) of the MFMA residual GEMM, or
- * the tile shape (64 x 64 or 128 x 64), or
- * the workgroup-count cap of the streaming kernels -- on the handle's own
+ * the tile shape (64 x 64 or 128 x 64), K tile (16 or 32) and occupancy, or
+ * the workgroup-count cap and prefetch form of the streaming kernels -- on
+ * the handle's own
  * operands and keep the fastest (the built-in rule is one of the
  * candidates).  Choices are cached per entry shape for the process and, if
  * cache_path is not NULL, in that text file (read first, rewritten after;
@@ -171,10 +172,11 @@ CASPT2_API int caspt2_set_precision(caspt2_handle* h, int32_t precision);
 CASPT2_API int caspt2_autotune(caspt2_handle* h, const char* cache_path, int32_t force);
 
 /* The launch choice of entry k (order of the packed layout) after
- * caspt2_autotune: choice[4] = {K splits, tile order, grid cap, tile rows}
- * (-1, -1, 0, 0: the rule); rule_ms and tuned_ms the timings of the rule and
- * of the choice (-1 when the choice came from the cache).  host outputs, each
- * may be NULL. */
+ * caspt2_autotune: choice[7] = {K splits, tile order, grid cap, tile rows,
+ * K tile, waves per SIMD asked of the compiler, streaming MFMA kernel
+ * without prefetch} (-1, -1, 0, 0, 0, 0, 0: the rule); rule_ms
+ * and tuned_ms the timings of the rule and of the choice (-1 when the choice
+ * came from the cache).  host outputs, each may be NULL. */
 CASPT2_API int caspt2_tune_entry(const caspt2_handle* h, int32_t k, int32_t* choice, double* rule_ms,
                                  double* tuned_ms);
 

@@ -2000,26 +2000,42 @@ std::vector<LaunchTune> tune_candidates(const std::vector<Entry>& es, size_t k, 
     const int64_t natural = e.nalpha <= 4 ? (rows + 255) / 256
                             : e.nalpha <= 16 ? (rows * e.nalpha + 255) / 256
                                              : ((rows + 15) / 16 + 3) / 4;
-    for (unsigned g : {512u, 1024u, 2048u, 4096u, 8192u, 16384u, 32768u})
-      if ((int64_t)g < natural) {
+    const bool mfma = e.nalpha > 16;   // the streaming MFMA kernel (with or without prefetch)
+    for (int plain : {0, 1}) {
+      if (plain && !mfma) continue;
+      if (plain) {
         LaunchTune t;
-        t.grid = g;
+        t.plain = 1;
         c.push_back(t);
       }
+      for (unsigned g : {512u, 1024u, 2048u, 4096u, 8192u, 16384u, 32768u})
+        if ((int64_t)g < natural) {
+          LaunchTune t;
+          t.grid = g;
+          t.plain = plain;
+          c.push_back(t);
+        }
+    }
     return c;
   }
   const int64_t M = e.nrow, N = e.nalpha, K = e.nalpha;
   for (int order : {-1, 2})
     for (int ns : {1, 2, 4, 8, 16, 32, 64}) {
       if (ns > 1 && ((int64_t)ns * BK_RESIDUAL > K || (int64_t)ns * 2 * M * N > ws_cap)) continue;
-      for (int tile : {64, 128}) {
-        if (tile == 128 && (ns > 1 || M < 4 * 128)) continue;
-        LaunchTune t;
-        t.splitk = ns;
-        t.order = order;
-        t.tile = tile;
-        c.push_back(t);
-      }
+      for (int tile : {64, 128})
+        for (int kb : {16, 32})
+          for (int occ : {0, 1}) {   // the rule's occupancy, or one wave per SIMD
+            if ((tile == 128 || kb == 32 || occ == 1) && ns > 1) continue;
+            if (tile == 128 && M < 4 * 128) continue;
+            if (occ == 1 && tile == 128 && kb == 32) continue;
+            LaunchTune t;
+            t.splitk = ns;
+            t.order = order;
+            t.tile = tile;
+            t.kb = kb;
+            t.occ = occ;
+            c.push_back(t);
+          }
     }
   return c;
 }
@@ -2053,9 +2069,13 @@ void load_tune_file(const char* path) {
     if (!tab) continue;
     *tab = 0;
     LaunchTune t;
-    const int got = std::sscanf(tab + 1, "%d %d %u %d", &t.splitk, &t.order, &t.grid, &t.tile);
+    const int got = std::sscanf(tab + 1, "%d %d %u %d %d %d %d", &t.splitk, &t.order, &t.grid, &t.tile, &t.kb,
+                                &t.occ, &t.plain);
     if (got < 3) continue;
-    if (got == 3) t.tile = 0;
+    if (got < 4) t.tile = 0;
+    if (got < 5) t.kb = 0;
+    if (got < 6) t.occ = 0;
+    if (got < 7) t.plain = 0;
     g_tune_cache[line] = t;
   }
   std::fclose(f);
@@ -2067,8 +2087,8 @@ void save_tune_file(const char* path) {
   FILE* f = std::fopen(tmp.c_str(), "w");
   if (!f) throw DevError(CASPT2_E_ARG, "cannot write the tuning cache file");
   for (auto& kv : g_tune_cache)
-    std::fprintf(f, "%s\t%d %d %u %d\n", kv.first.c_str(), kv.second.splitk, kv.second.order, kv.second.grid,
-                 kv.second.tile);
+    std::fprintf(f, "%s\t%d %d %u %d %d %d %d\n", kv.first.c_str(), kv.second.splitk, kv.second.order,
+                 kv.second.grid, kv.second.tile, kv.second.kb, kv.second.occ, kv.second.plain);
   std::fclose(f);
   if (std::rename(tmp.c_str(), path) != 0) throw DevError(CASPT2_E_ARG, "cannot replace the tuning cache file");
 }
@@ -2121,8 +2141,10 @@ void autotune(H& h, const char* cache_path, bool force) {
           e.tune_best_ms = best;
           g_tune_cache[key] = pick;
           if (h.verbose)
-            std::fprintf(stderr, "[caspt2] tune %-28s splitk %d order %d grid %u tile %d: %.4f ms (rule %.4f ms)\n",
-                         key.c_str(), pick.splitk, pick.order, pick.grid, pick.tile, best, rule);
+            std::fprintf(stderr,
+                         "[caspt2] tune %-28s splitk %d order %d grid %u tile %d kb %d occ %d plain %d: %.4f ms (rule %.4f ms)\n",
+                         key.c_str(), pick.splitk, pick.order, pick.grid, pick.tile, pick.kb, pick.occ, pick.plain, best,
+                         rule);
         }
         if (pair) es[k + 1].tune = e.tune;
         if (pair) ++k;
@@ -2375,6 +2397,9 @@ int caspt2_tune_entry(const caspt2_handle* h, int32_t k, int32_t* choice, double
     choice[1] = e.tune.order;
     choice[2] = (int32_t)e.tune.grid;
     choice[3] = e.tune.tile;
+    choice[4] = e.tune.kb;
+    choice[5] = e.tune.occ;
+    choice[6] = e.tune.plain;
   }
   if (rule_ms) *rule_ms = e.tune_rule_ms;
   if (tuned_ms) *tuned_ms = e.tune_best_ms;

@@ -60,19 +60,17 @@ hipError_t launch_gather_apply(const double* X, int64_t nlead, int64_t dim_from,
 //     A[i][k]: i = l % 16, k = l / 16;  B[k][j]: j = l % 16, k = l / 16;
 //     D[i][j]: j = l % 16, i = l / 16 + 4 * v, v = 0..3 (checked on gfx950).
 // ---------------------------------------------------------------------------
-constexpr int BM = 64, BN = 64, BK = BK_RESIDUAL, LDP = BK + 1;
-// B (as [K][N]): KT threads per k row, UB consecutive n each; B as [N][K]:
-// four threads per n row, UN consecutive k each
-constexpr int KT = 256 / BK, UB = BN * BK / 256, UN = BK / 4;
-static_assert(BN == 64 && KT * BK == 256 && UB * 256 == BN * BK, "tile shares");
+constexpr int BM = 64, BN = 64, BK = BK_RESIDUAL;
 
 // MT: 16-row MFMA blocks per wave along M; the workgroup tile is (32 MT) x
 // 64 (MT = 2: 64 x 64, MT = 4: 128 x 64 -- more flops per byte staged, at
-// twice the accumulator registers).
-// SPLIT (dual only): blockIdx.z selects a K range of kchunk; the raw X S and
-// X F partial products go to C as [split][2][M][N] for a separate epilogue.
-template <bool B_NK, bool DUAL, bool SPLIT = false, int MT = 2>
-__global__ __launch_bounds__(256) void k_gemm_f64(int64_t M, int64_t N, int64_t K, double alpha,
+// twice the accumulator registers).  KB: K tile (16 or 32; a longer tile
+// gives the register prefetch of the next tile more time to arrive).
+// SPLIT (dual only): blockIdx.z selects a K range of kchunk (a multiple of
+// KB); the raw X S and X F partial products go to C as [split][2][M][N] for
+// a separate epilogue.
+template <bool B_NK, bool DUAL, bool SPLIT = false, int MT = 2, int KB = BK, int WPE = 1>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void k_gemm_f64(int64_t M, int64_t N, int64_t K, double alpha,
                                                   const double* __restrict__ A, int64_t lda,
                                                   int64_t sA, const double* __restrict__ B,
                                                   int64_t ldb, int64_t sB,
@@ -83,8 +81,13 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int64_t M, int64_t N, int64_t 
                                                   int order, int64_t kchunk) {
   constexpr int TM = 32 * MT;          // tile rows
   constexpr int TPR = 256 / TM;        // threads per A row of a K tile
-  constexpr int UA = BK / TPR;         // consecutive k per thread in the A tile
-  static_assert(TPR * TM == 256 && UA * TPR == BK, "A tile shares");
+  constexpr int UA = KB / TPR;         // consecutive k per thread in the A tile
+  constexpr int LDP = KB + 1;          // LDS row pitch (odd: no bank conflicts on k)
+  // B as [K][N]: KT threads per k row, UB consecutive n each; B as [N][K]:
+  // four threads per n row, UN consecutive k each
+  constexpr int KT = 256 / KB, UB = BN * KB / 256, UN = KB / 4;
+  static_assert(TPR * TM == 256 && UA * TPR == KB, "A tile shares");
+  static_assert(BN == 64 && KT * KB == 256 && UB * 256 == BN * KB, "B tile shares");
   __shared__ double As[TM][LDP];
   __shared__ double Bs[BN][LDP];
   __shared__ double B2s[DUAL ? BN : 1][LDP];
@@ -134,64 +137,57 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int64_t M, int64_t N, int64_t 
     }
   // global -> registers -> LDS; the next K tile's loads are issued before
   // the MFMAs of the current one (register prefetch), so their latency hides
-  // behind the matrix work
+  // behind the matrix work.  Each thread's load coordinates are fixed over
+  // K: row validity and base pointers are resolved once, and the K bound is
+  // checked only on a partial last tile.
   double ra[UA], rb[UN > UB ? UN : UB], rb2[UB];
+  const int rA = tid / TPR, cA = (tid % TPR) * UA;
+  const bool a_ok = m0 + rA < M;
+  const double* pA = A + (a_ok ? m0 + rA : 0) * lda + cA;
+  const int rB = tid >> 2, cB = (tid & 3) * UN;            // B as [N][K]
+  const bool bn_ok = n0 + rB < N;
+  const double* pBn = B + (bn_ok ? n0 + rB : 0) * ldb + cB;
+  const int kB = tid / KT, cN = (tid % KT) * UB;           // B as [K][N]
+  const int64_t nB0 = n0 + cN;
   auto load_tile = [&](int64_t k0) {
-    {  // A tile: TM rows x BK k, UA per thread
-      const int r = tid / TPR, c = (tid % TPR) * UA;
-      const int64_t gm = m0 + r;
+    const bool kfull = k0 + KB <= ke;
 #pragma unroll
-      for (int u = 0; u < UA; ++u) {
-        const int64_t gk = k0 + c + u;
-        ra[u] = (gm < M && gk < ke) ? A[gm * lda + gk] : 0.0;
-      }
-    }
+    for (int u = 0; u < UA; ++u) ra[u] = (a_ok && (kfull || k0 + cA + u < ke)) ? pA[k0 + u] : 0.0;
     if (B_NK) {
-      const int r = tid >> 2, c = (tid & 3) * UN;
-      const int64_t gn = n0 + r;
 #pragma unroll
-      for (int u = 0; u < UN; ++u) {
-        const int64_t gk = k0 + c + u;
-        rb[u] = (gn < N && gk < ke) ? B[gn * ldb + gk] : 0.0;
-      }
+      for (int u = 0; u < UN; ++u) rb[u] = (bn_ok && (kfull || k0 + cB + u < ke)) ? pBn[k0 + u] : 0.0;
     } else {
-      // B is [K][N]: thread loads k = tid / KT, n = (tid % KT) * UB .. + UB - 1
-      const int kk = tid / KT, c = (tid % KT) * UB;
-      const int64_t gk = k0 + kk;
+      const bool krow = kfull || k0 + kB < ke;
+      const int64_t off = (k0 + kB) * ldb + nB0;
 #pragma unroll
       for (int u = 0; u < UB; ++u) {
-        const int64_t gn = n0 + c + u;
-        const bool in = gn < N && gk < ke;
-        rb[u] = in ? B[gk * ldb + gn] : 0.0;
-        if (DUAL) rb2[u] = in ? B2[gk * ldb + gn] : 0.0;
+        const bool in = krow && nB0 + u < N;
+        rb[u] = in ? B[off + u] : 0.0;
+        if (DUAL) rb2[u] = in ? B2[off + u] : 0.0;
       }
     }
   };
   auto store_tile = [&]() {
-    {
-      const int r = tid / TPR, c = (tid % TPR) * UA;
 #pragma unroll
-      for (int u = 0; u < UA; ++u) As[r][c + u] = ra[u];
-    }
+    for (int u = 0; u < UA; ++u) As[rA][cA + u] = ra[u];
     if (B_NK) {
-      const int r = tid >> 2, c = (tid & 3) * UN;
 #pragma unroll
-      for (int u = 0; u < UN; ++u) Bs[r][c + u] = rb[u];
+      for (int u = 0; u < UN; ++u) Bs[rB][cB + u] = rb[u];
     } else {
-      const int kk = tid / KT, c = (tid % KT) * UB;
 #pragma unroll
       for (int u = 0; u < UB; ++u) {
-        Bs[c + u][kk] = rb[u];
-        if (DUAL) B2s[c + u][kk] = rb2[u];
+        Bs[cN + u][kB] = rb[u];
+        if (DUAL) B2s[cN + u][kB] = rb2[u];
       }
     }
   };
   if (kb < ke) load_tile(kb);
-  for (int64_t k0 = kb; k0 < ke; k0 += BK) {
+  for (int64_t k0 = kb; k0 < ke; k0 += KB) {
     store_tile();
     __syncthreads();
-    if (k0 + BK < ke) load_tile(k0 + BK);
-    for (int kk = 0; kk < BK; kk += 4) {
+    if (k0 + KB < ke) load_tile(k0 + KB);
+#pragma unroll
+    for (int kk = 0; kk < KB; kk += 4) {
       double a[MT], b[2], b2[2];
       for (int i = 0; i < MT; ++i) a[i] = As[wm * (16 * MT) + i * 16 + (lane & 15)][kk + (lane >> 4)];
       for (int j = 0; j < 2; ++j) {
@@ -285,6 +281,8 @@ hipError_t residual_gemm_f64(int64_t M, int64_t N, int64_t K, const double* X, i
                              double* ws, int64_t ws_len, LaunchTune tune) {
   if (M <= 0 || N <= 0) return hipSuccess;
   if (tune.tile != 0 && tune.tile != 64 && tune.tile != 128) return hipErrorInvalidValue;
+  if (tune.kb != 0 && tune.kb != 16 && tune.kb != 32) return hipErrorInvalidValue;
+  if (tune.occ < 0 || tune.occ > 3) return hipErrorInvalidValue;
   int ns = tune.splitk >= 1 ? tune.splitk : residual_splitk(M, N, K);
   if (!(ns > 1 && ws && ws_len >= (int64_t)ns * 2 * M * N)) ns = 1;
   const int tm = (ns == 1 && tune.tile == 128) ? 128 : 64;   // 128-row tiles without K splits only
@@ -317,14 +315,38 @@ hipError_t residual_gemm_f64(int64_t M, int64_t N, int64_t K, const double* X, i
                        dshift, V, ldv, C, ldc);
     return hipGetLastError();
   }
-  if (tm == 128)
-    hipLaunchKernelGGL((k_gemm_f64<false, true, false, 4>), grid, dim3(256), 0, s, M, N, K, 1.0, X, ldx,
-                       (int64_t)0, S, N, (int64_t)0, F, 0.0, C, ldc, (int64_t)0, d, dshift, V, ldv, mx,
-                       (int64_t)0);
-  else
-    hipLaunchKernelGGL((k_gemm_f64<false, true>), grid, dim3(256), 0, s, M, N, K, 1.0, X, ldx,
-                       (int64_t)0, S, N, (int64_t)0, F, 0.0, C, ldc, (int64_t)0, d, dshift, V, ldv, mx,
-                       (int64_t)0);
+#define CASPT2_DUAL(MT_, KB_, WPE_)                                                                      \
+  hipLaunchKernelGGL((k_gemm_f64<false, true, false, MT_, KB_, WPE_>), grid, dim3(256), 0, s, M, N, K, 1.0, X, \
+                     ldx, (int64_t)0, S, N, (int64_t)0, F, 0.0, C, ldc, (int64_t)0, d, dshift, V, ldv, mx, (int64_t)0)
+  // waves per SIMD asked of the compiler (it then keeps the accumulators in
+  // VGPRs); by rule the most that compiles without spills: 3 for 64-row
+  // tiles, 2 for 128-row tiles with K tile 16, 1 for 128 x 32
+  const bool k32 = tune.kb == 32;
+  if (tm == 128) {
+    if (k32) {
+      if (tune.occ > 1) return hipErrorInvalidValue;
+      CASPT2_DUAL(4, 32, 1);
+    } else if (tune.occ == 1) {
+      CASPT2_DUAL(4, 16, 1);
+    } else {
+      if (tune.occ > 2) return hipErrorInvalidValue;
+      CASPT2_DUAL(4, 16, 2);
+    }
+  } else {
+    if (tune.occ == 2) return hipErrorInvalidValue;
+    if (k32) {
+      if (tune.occ == 1)
+        CASPT2_DUAL(2, 32, 1);
+      else
+        CASPT2_DUAL(2, 32, 3);
+    } else {
+      if (tune.occ == 1)
+        CASPT2_DUAL(2, 16, 1);
+      else
+        CASPT2_DUAL(2, 16, 3);
+    }
+  }
+#undef CASPT2_DUAL
   return hipGetLastError();
 }
 
@@ -368,13 +390,19 @@ __global__ __launch_bounds__(256) void k_residual_small(int64_t M, int N, const 
 // K16 = ceil16(K)) live in LDS for the whole launch; each wave stages 16 rows
 // of X in LDS with coalesced loads and accumulates X S and X F with
 // v_mfma_f64_16x16x4f64; epilogue (d[m] + dshift) XS + XF + V.
-template <int K16>
+// PIPE: the wave's next 16-row tile of X is loaded into registers while the
+// current one is multiplied, and the current tile's V and row energies are
+// requested before the MFMAs, so HBM latency overlaps the matrix work (the
+// plain form waits for its loads at every tile).
+template <int K16, bool PIPE>
 __global__ __launch_bounds__(256) void k_residual_mfma(int64_t M, int K, const double* __restrict__ X,
                                                        const double* __restrict__ S,
                                                        const double* __restrict__ F,
                                                        const double* __restrict__ d, double dshift,
                                                        const double* __restrict__ V,
                                                        double* __restrict__ C) {
+  constexpr int XPL = 16 * K16 / 64;   // staged X values per lane
+  constexpr int NCT = K16 / 16;        // 16-column output tiles
   __shared__ double Ss[K16][K16 + 1];
   __shared__ double Fs[K16][K16 + 1];
   __shared__ double Xs[4][16][K16 + 1];
@@ -387,20 +415,49 @@ __global__ __launch_bounds__(256) void k_residual_mfma(int64_t M, int K, const d
   }
   __syncthreads();
   const int64_t ntiles = (M + 15) / 16;
-  for (int64_t tile = (int64_t)blockIdx.x * 4 + w; tile < ntiles; tile += (int64_t)gridDim.x * 4) {
-    const int64_t m0 = tile * 16;
-    // stage 16 rows (contiguous 16*K doubles) of X
-    const int64_t base = m0 * K;
-    const int64_t limit = M * (int64_t)K;
-    for (int i = lane; i < 16 * K16; i += 64) {
+  const int64_t stride = (int64_t)gridDim.x * 4;
+  const int64_t limit = M * (int64_t)K;
+  double xr[XPL];
+  auto load_x = [&](int64_t tile) {   // 16 rows (contiguous 16*K doubles) of X
+    const int64_t base = tile * 16 * K;
+#pragma unroll
+    for (int j = 0; j < XPL; ++j) {
+      const int i = lane + 64 * j;
       const int r = i / K16, c = i % K16;
       const int64_t gi = base + (int64_t)r * K + c;
-      Xs[w][r][c] = (c < K && gi < limit) ? X[gi] : 0.0;
+      xr[j] = (c < K && gi < limit) ? X[gi] : 0.0;
     }
-    __builtin_amdgcn_s_waitcnt(0);
-    __builtin_amdgcn_wave_barrier();
+  };
+  int64_t tile = (int64_t)blockIdx.x * 4 + w;
+  if (PIPE && tile < ntiles) load_x(tile);
+  for (; tile < ntiles; tile += stride) {
+    const int64_t m0 = tile * 16;
+    if (!PIPE) load_x(tile);
 #pragma unroll
-    for (int ct = 0; ct < K16 / 16; ++ct) {
+    for (int j = 0; j < XPL; ++j) {
+      const int i = lane + 64 * j;
+      Xs[w][i / K16][i % K16] = xr[j];
+    }
+    // the staged tile is read by other lanes of this wave: wait for the LDS
+    // writes only (lgkmcnt 0; vmcnt and expcnt left at their maxima)
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    __builtin_amdgcn_wave_barrier();
+    // this tile's row energies and V, then the next tile's X, all in flight
+    // during the MFMAs (loads complete in order: V before the prefetch)
+    double rr[4], vr[NCT][4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t row = m0 + (lane >> 4) + 4 * v;
+      rr[v] = row < M ? d[row] + dshift : 0.0;
+#pragma unroll
+      for (int ct = 0; ct < NCT; ++ct) {
+        const int col = ct * 16 + (lane & 15);
+        vr[ct][v] = (V && row < M && col < K) ? V[row * K + col] : 0.0;
+      }
+    }
+    if (PIPE && tile + stride < ntiles) load_x(tile + stride);
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct) {
       d4 as = {0, 0, 0, 0}, af = {0, 0, 0, 0};
 #pragma unroll
       for (int k0 = 0; k0 < K16; k0 += 4) {
@@ -414,11 +471,7 @@ __global__ __launch_bounds__(256) void k_residual_mfma(int64_t M, int K, const d
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int64_t row = m0 + (lane >> 4) + 4 * v;
-        if (row < M && col < K) {
-          double val = (d[row] + dshift) * as[v] + af[v];
-          if (V) val += V[row * K + col];
-          C[row * K + col] = val;
-        }
+        if (row < M && col < K) C[row * K + col] = rr[v] * as[v] + af[v] + vr[ct][v];
       }
     }
     __builtin_amdgcn_wave_barrier();
@@ -435,15 +488,22 @@ hipError_t residual_small_f64(int64_t M, int64_t N, const double* X, const doubl
     const int64_t ntiles = (M + 15) / 16;
     unsigned grid = cdiv(ntiles, 4);
     if (grid > (cap ? cap : 16384u)) grid = cap ? cap : 16384u;
+#define CASPT2_RMFMA(K16_)                                                                              \
+  do {                                                                                                  \
+    if (tune.plain)                                                                                     \
+      hipLaunchKernelGGL((k_residual_mfma<K16_, false>), dim3(grid), dim3(256), 0, s, M, (int)N, X, S, F, d, \
+                         dshift, V, C);                                                                 \
+    else                                                                                                \
+      hipLaunchKernelGGL((k_residual_mfma<K16_, true>), dim3(grid), dim3(256), 0, s, M, (int)N, X, S, F, d, \
+                         dshift, V, C);                                                                 \
+  } while (0)
     if (N <= 32)
-      hipLaunchKernelGGL(k_residual_mfma<32>, dim3(grid), dim3(256), 0, s, M, (int)N, X, S, F, d,
-                         dshift, V, C);
+      CASPT2_RMFMA(32);
     else if (N <= 48)
-      hipLaunchKernelGGL(k_residual_mfma<48>, dim3(grid), dim3(256), 0, s, M, (int)N, X, S, F, d,
-                         dshift, V, C);
+      CASPT2_RMFMA(48);
     else
-      hipLaunchKernelGGL(k_residual_mfma<64>, dim3(grid), dim3(256), 0, s, M, (int)N, X, S, F, d,
-                         dshift, V, C);
+      CASPT2_RMFMA(64);
+#undef CASPT2_RMFMA
     return hipGetLastError();
   }
   unsigned grid = cdiv(M * N, 256);

@@ -29,6 +29,10 @@ struct LaunchTune {
                        // grid x), 2 XCD-grouped
   unsigned grid = 0;   // streaming residual kernels: cap on the workgroup count
   int tile = 0;        // residual GEMM tile rows: 64 or 128 (without K splits)
+  int kb = 0;          // residual GEMM K tile: 16 or 32 (without K splits)
+  int occ = 0;         // residual GEMM without K splits: waves per SIMD asked of
+                       // the compiler (1, 2 with 128-row tiles, 3 with 64-row tiles)
+  int plain = 0;       // streaming MFMA residual: 1 = without the X prefetch
 };
 
 // Residual of one packed entry on MFMA:
