@@ -15,6 +15,16 @@ extern "C" {
 CASPT2_API int caspt2_debug_gemm(int32_t b_is_nk, int64_t M, int64_t N, int64_t K, const double* A,
                                  const double* B, double* C);
 
+/* The FP32 operator of the mixed-precision inner solver: sigma = A_L x
+ * (Eq. 10 without the source) in FP32, packed layout, device x and sigma of
+ * caspt2_vector_length floats.  E_STATE unless the handle holds the FP32
+ * operands (created with, or switched to, CASPT2_MIXED). */
+CASPT2_API int caspt2_debug_residual_f32(caspt2_handle* h, int32_t L, const float* x, float* sigma);
+
+/* Diagnostics on stderr: 0 off, 1 set-up progress, 2 also per-stage timings
+ * of the coupling terms in every residual. */
+CASPT2_API int caspt2_set_verbose(caspt2_handle* h, int32_t level);
+
 /* C = A * op(B) with the library's FP32 GEMM (same layout, float data). */
 CASPT2_API int caspt2_debug_gemm_f32(int32_t b_is_nk, int64_t M, int64_t N, int64_t K, const float* A,
                                      const float* B, float* C);

@@ -79,6 +79,8 @@ SIGNATURES = {
     "caspt2_debug_entry": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _D]),
     "caspt2_debug_source": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P]),
     "caspt2_debug_eigh": (ctypes.c_int, [ctypes.c_int32, _P, _D, _P]),
+    "caspt2_debug_residual_f32": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P]),
+    "caspt2_set_verbose": (ctypes.c_int, [_P, ctypes.c_int32]),
     "caspt2_debug_eigh_method": (ctypes.c_int, [ctypes.c_int32, _P, _D, _P, ctypes.c_int32,
                                                 ctypes.POINTER(ctypes.c_int32)]),
     "caspt2_last_error": (ctypes.c_char_p, []),

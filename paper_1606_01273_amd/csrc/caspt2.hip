@@ -2687,6 +2687,23 @@ int caspt2_debug_gemm_f32(int32_t b_is_nk, int64_t M, int64_t N, int64_t K, cons
   })
 }
 
+int caspt2_debug_residual_f32(caspt2_handle* h, int32_t L, const float* x, float* sigma) {
+  if (!h || L < 0 || L >= h->nst || !x || !sigma) return CASPT2_E_ARG;
+  if (!h->have_mixed) return CASPT2_E_STATE;
+  ABI_GUARD({
+    residual<float>(*h, L, x, sigma, false);
+    host_sync(*h);
+    return CASPT2_OK;
+  })
+}
+
+int caspt2_set_verbose(caspt2_handle* h, int32_t level) {
+  if (!h || level < 0) return CASPT2_E_ARG;
+  h->verbose_level = level;
+  h->verbose = level > 0;
+  return CASPT2_OK;
+}
+
 int caspt2_debug_entry(const caspt2_handle* h, int32_t set, int32_t k, int32_t which, double* out) {
   if (!h || set < 0 || set >= (int32_t)h->sets.size() || k < 0 ||
       k >= (int32_t)h->sets[set].size() || !out)
