@@ -184,6 +184,50 @@ ExpandPlan make_expand_plan(const CoupleDesc& d) {
   return r;
 }
 
+// out[bra row(z0, z1)][c0 .. c0 + NC) += sum_y f(z0, z1, y) wreg[y][.] for the
+// free values z0 in [zb, ze) and every z1.  The targets of ZB consecutive
+// free values are loaded together before any is written back (they are
+// distinct rows), so the read latency of the read-modify-write overlaps
+// instead of being paid once per free value.
+template <typename T, int NC>
+__device__ inline void expand_free_range(const ExpandPlan& ep, const double* __restrict__ f, int64_t fo,
+                                         int64_t ob, int64_t c0, const double (&wreg)[8][NC], uint32_t zb,
+                                         uint32_t ze, T* __restrict__ out) {
+  constexpr int ZB = 8;
+  const uint32_t nz = (ze - zb) * ep.nf1;
+  for (uint32_t zz = 0; zz < nz; zz += ZB) {
+    T old[ZB][NC];
+    int64_t orow[ZB], frow[ZB];
+#pragma unroll
+    for (int u = 0; u < ZB; ++u) {
+      const uint32_t z = zz + u;
+      const uint32_t z0 = zb + z / ep.nf1, z1 = z % ep.nf1;
+      orow[u] = (ob + z0 * ep.ob_f[0] + z1 * ep.ob_f[1]) * ep.ncol + c0;
+      frow[u] = fo + z0 * ep.ff[0] + z1 * ep.ff[1];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) old[u][c] = (z < nz && c0 + c < ep.ncol) ? out[orow[u] + c] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < ZB; ++u) {
+      if (zz + u >= nz) break;
+      const double* fr = f + frow[u];
+      double acc[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+#pragma unroll
+      for (int y = 0; y < 8; ++y)
+        if (y < ep.ny) {
+          const double fv = fr[y * ep.fy];
+#pragma unroll
+          for (int c = 0; c < NC; ++c) acc[c] += fv * wreg[y][c];
+        }
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+        if (c0 + c < ep.ncol) out[orow[u] + c] = old[u][c] + (T)acc[c];
+    }
+  }
+}
+
 // expand, ket-parallel form: a thread holds the W values of one ket row and
 // column group (ny x NC, in registers) and loops over the free bra slots, so
 // every W row is read once; out is read-modify-written NC values at a time.
@@ -213,24 +257,7 @@ __global__ __launch_bounds__(256) void k_couple_expand(ExpandPlan ep, const doub
 #pragma unroll
       for (int c = 0; c < NC; ++c)
         wreg[y][c] = (y < ep.ny && c0 + c < ep.ncol) ? (double)w[(int64_t)y * ep.ncol + c] : 0.0;
-    for (uint32_t z0 = 0; z0 < ep.nf0; ++z0)
-      for (uint32_t z1 = 0; z1 < ep.nf1; ++z1) {
-        const double* fr = f + fo + z0 * ep.ff[0] + z1 * ep.ff[1];
-        double acc[NC];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) acc[c] = 0.0;
-#pragma unroll
-        for (int y = 0; y < 8; ++y)
-          if (y < ep.ny) {
-            const double fv = fr[y * ep.fy];
-#pragma unroll
-            for (int c = 0; c < NC; ++c) acc[c] += fv * wreg[y][c];
-          }
-        T* op = out + (ob + z0 * ep.ob_f[0] + z1 * ep.ob_f[1]) * ep.ncol + c0;
-#pragma unroll
-        for (int c = 0; c < NC; ++c)
-          if (c0 + c < ep.ncol) op[c] += (T)acc[c];
-      }
+    expand_free_range<T, NC>(ep, f, fo, ob, c0, wreg, 0, ep.nf0, out);
   }
 }
 
@@ -287,24 +314,7 @@ __global__ __launch_bounds__(256) void k_couple_up_fused(ExpandPlan ep, int64_t 
         }
     }
     const uint32_t zb = zs * chunk, ze = zb + chunk < ep.nf0 ? zb + chunk : ep.nf0;
-    for (uint32_t z0 = zb; z0 < ze; ++z0)
-      for (uint32_t z1 = 0; z1 < ep.nf1; ++z1) {
-        const double* fr = f + fo + z0 * ep.ff[0] + z1 * ep.ff[1];
-        double acc[NC];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) acc[c] = 0.0;
-#pragma unroll
-        for (int y = 0; y < 8; ++y)
-          if (y < ep.ny) {
-            const double fv = fr[y * ep.fy];
-#pragma unroll
-            for (int c = 0; c < NC; ++c) acc[c] += fv * wreg[y][c];
-          }
-        T* op = out + (ob + z0 * ep.ob_f[0] + z1 * ep.ob_f[1]) * ep.ncol + c0;
-#pragma unroll
-        for (int c = 0; c < NC; ++c)
-          if (c0 + c < ep.ncol) op[c] += (T)acc[c];
-      }
+    expand_free_range<T, NC>(ep, f, fo, ob, c0, wreg, zb, ze, out);
   }
 }
 
