@@ -6,11 +6,14 @@ blocks (Eq. 10), on device-resident synthetic inputs.  Prints one JSON line.
 
   python bench.py [--steps K] [--warmup W] [--workload full|mid|small]
 
-The roofline object reports the dominant residual kernel (HIP events inside
-the library, on the stream it launches on); the cpu_baseline object times
-the CPU oracle on a bounded sample of the same workload in a child process
-(its set-up overlaps the GPU set-up; its timed part runs after the GPU timed
-region).
+The residual launches are autotuned after set-up (outside the timed region).
+In the timed region caspt2_residual_all spreads the states over two streams;
+a short second pass with one stream times every kernel alone.  The roofline
+object reports the dominant residual kernel (HIP events inside the library,
+on the stream it launches on) in the timed region and alone; the mfma object
+the dense-contraction rates alone.  The cpu_baseline object times the CPU
+oracle on a bounded sample of the same workload in a child process (its
+set-up overlaps the GPU set-up only; its timed part runs after all GPU work).
 """
 from __future__ import annotations
 
@@ -254,6 +257,12 @@ def main():
                     "plain": c[6], "rule_ms": round(c[7], 4), "tuned_ms": round(c[8], 4)}
                 for k, c in choices.items() if c[7] > 0}
         print(f"[bench] autotuned the residual launches in {t_tune:.1f} s", file=sys.stderr, flush=True)
+    # the CPU oracle's set-up (in the child) overlaps the GPU set-up only:
+    # wait for it, so that no host work competes with the GPU measurements
+    child_msg = None
+    if child is not None:
+        child_msg = parent_conn.recv()
+        print(f"[bench] CPU baseline set up ({child_msg[0]})", file=sys.stderr, flush=True)
     gen = torch.Generator(device="cuda")
     gen.manual_seed(0)
     x = torch.randn((nst, g.length), dtype=torch.float64, device="cuda", generator=gen)
@@ -272,6 +281,21 @@ def main():
     coupl = g.profile_entry(len(ENTRY_NAMES))
     g.profile(False)
     print(f"[bench] {args.steps} steps in {elapsed:.3f} s", file=sys.stderr, flush=True)
+    # the same steps with every launch on one stream: each kernel alone on
+    # the GPU (in the timed region above, kernels of different states overlap
+    # on two streams and share the memory system)
+    g.set_streams(1)
+    g.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n_alone = max(2, args.steps // 4)
+    for _ in range(n_alone):
+        g.residual_all(x, sig)
+    torch.cuda.synchronize()
+    elapsed_alone = time.perf_counter() - t0
+    prof_alone = {ENTRY_NAMES[k]: g.profile_entry(k) for k in range(len(ENTRY_NAMES))}
+    g.profile(False)
+    g.set_streams(2)
 
     if args.copy_calibration:
         src = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
@@ -286,22 +310,29 @@ def main():
     avg_ms, launches, bytes_pl = prof[dom]
     achieved = bytes_pl / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
     traffic = _pmc_traffic(dom, args.workload, args.reading)
+    a_ms, a_n, _ = prof_alone[dom]
+    achieved_alone = bytes_pl / (a_ms * 1e-3) / 1e9 if a_ms > 0 else 0.0
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "k_residual_rows (ccvv +/-)" if dom.startswith("ccvv") else dom,
                 "entry": dom, "avg_ms": round(avg_ms, 4), "launches": launches,
-                "bytes_per_launch": bytes_pl}
+                "bytes_per_launch": bytes_pl,
+                "alone": {"avg_ms": round(a_ms, 4), "launches": a_n, "achieved": round(achieved_alone, 1),
+                          "frac": round(achieved_alone / HBM_PEAK_GBS, 4),
+                          "evals_per_s_one_stream": round(n_alone / elapsed_alone, 3)}}
     per_entry = {k: {"avg_ms": round(v[0], 4), "launches": v[1], "GBs": round(v[2] / (v[0] * 1e-3) / 1e9, 1)
                      if v[0] > 0 else None} for k, v in prof.items()}
     # dense contraction entries (nalpha > 64: MFMA GEMMs): algorithmic flops
     # 2 * 2 * rows * nalpha^2 per launch (X S and X F), rate vs the FP64 peak
+    # (rates of each kernel alone on the GPU, from the one-stream pass; in the
+    # timed region the GEMMs share the GPU with other states' streaming kernels)
     mfma = {}
     for name, _, rows, na in g.layout():
-        v = prof.get(name)
+        v = prof_alone.get(name)
         if na > 64 and v and v[0] > 0 and rows > 0:
             tf = 4.0 * rows * na * na / (v[0] * 1e-3) / 1e12
-            mfma[name] = {"TFs": round(tf, 2), "util": round(tf / FP64_PEAK_TFS, 3), "rows": rows, "nalpha": na}
-            per_entry[name]["TFs"] = round(tf, 2)
+            mfma[name] = {"TFs": round(tf, 2), "util": round(tf / FP64_PEAK_TFS, 3), "rows": rows, "nalpha": na,
+                          "avg_ms_alone": round(v[0], 4)}
     per_entry["couplings"] = {"avg_ms": round(coupl[0], 4), "launches": coupl[1]}
 
     solve = None
@@ -328,7 +359,7 @@ def main():
 
     cpu = None
     if child is not None:
-        msg = parent_conn.recv()
+        msg = child_msg
         if msg[0] == "ready":
             parent_conn.send("go")
             msg = parent_conn.recv()

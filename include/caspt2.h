@@ -193,8 +193,17 @@ CASPT2_API int caspt2_layout(const caspt2_handle* h, int32_t k, int64_t* offset,
  * caspt2_vector_length; they must not overlap. */
 CASPT2_API int caspt2_residual(caspt2_handle* h, int32_t L, int32_t with_source, const double* x,
                     double* sigma);
-/* Residuals for every state at once: x and sigma are [nst][length] device. */
+/* Residuals for every state at once: x and sigma are [nst][length] device.
+ * Without couplings between blocks the states alternate between two
+ * streams of the handle (the second launching its entries in reverse
+ * order), so that HBM-bound and MFMA-bound kernels of different states
+ * overlap; results equal the one-state calls bit for bit.  The call returns
+ * when all of them are done. */
 CASPT2_API int caspt2_residual_all(caspt2_handle* h, int32_t with_source, const double* x, double* sigma);
+
+/* Streams caspt2_residual_all spreads the states over: 2 (default) or 1 (all
+ * on the handle's stream, e.g. to time each kernel alone).  E_ARG otherwise. */
+CASPT2_API int caspt2_set_streams(caspt2_handle* h, int32_t n);
 
 /* Solve Eq. 10 for every state by preconditioned conjugate gradients in the
  * orthonormal kept basis (preconditioner: external orbital energies +

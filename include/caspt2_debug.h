@@ -46,9 +46,10 @@ CASPT2_API int caspt2_debug_eigh(int32_t n, double* A, double* w, double* V);
 
 /* The same with the solver form chosen: method 0 by size, 1 one workgroup
  * with the matrices in LDS (n <= 64), 2 one workgroup on global memory
- * (n <= 512), 3 one launch pair per rotation step over the whole device;
- * sweeps (host, may be NULL) receives the number of sweeps.  E_ARG for a
- * form that does not take this n. */
+ * (n <= 512), 3 one launch pair per rotation step over the whole device, 4
+ * one launch per rotation step (alternating matrix buffers); sweeps (host,
+ * may be NULL) receives the number of sweeps.  E_ARG for a form that does
+ * not take this n. */
 CASPT2_API int caspt2_debug_eigh_method(int32_t n, double* A, double* w, double* V, int32_t method,
                                         int32_t* sweeps);
 

@@ -85,6 +85,9 @@ class Caspt2:
             out.append((ENTRY_NAMES[k], o.value, r.value, a.value))
         return out
 
+    def set_streams(self, n):
+        _check(lib().caspt2_set_streams(self._h, int(n)), "caspt2_set_streams")
+
     def set_precision(self, precision):
         _check(lib().caspt2_set_precision(self._h, int(precision)), "caspt2_set_precision")
 

@@ -51,6 +51,7 @@ SIGNATURES = {
                                      ctypes.POINTER(_P)]),
     "caspt2_destroy": (ctypes.c_int, [_P]),
     "caspt2_set_precision": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "caspt2_set_streams": (ctypes.c_int, [_P, ctypes.c_int32]),
     "caspt2_autotune": (ctypes.c_int, [_P, ctypes.c_char_p, ctypes.c_int32]),
     "caspt2_tune_entry": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),

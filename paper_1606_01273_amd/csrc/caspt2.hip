@@ -218,6 +218,14 @@ struct caspt2_handle {
   DBuf cscratch;                                       // W / Y of the couplings
   DBuf wx, wsg;                                        // operator work vectors of the grouped solver
   DBuf splitk_ws;                                      // partial products of the split-K residual GEMMs
+  DBuf* ws_cur = nullptr;                              // split-K workspace of the current stream (null: splitk_ws)
+  // caspt2_residual_all without couplings: states on two streams of default
+  // priority, their join events and the second stream's split-K workspace
+  hipStream_t slane[2] = {nullptr, nullptr};
+  hipEvent_t slane_done[2] = {nullptr, nullptr};
+  hipEvent_t sfork = nullptr;
+  DBuf splitk_ws2;
+  int residual_streams = 2;                            // 1: caspt2_residual_all on the handle's stream only
   DBuf xall[NBLOCK], sall[NBLOCK];                      // all-orderings x and sigma per block
   bool direct[NBLOCK] = {};                            // ket read from packed rows (no all-orderings x)
   bool have_mixed = false;                             // FP32 operand copies made
@@ -467,7 +475,10 @@ void eigh_dev(H& h, const double* A, int64_t n, std::vector<double>& w, DBuf& Ve
   Vec.alloc(n * n);
   if (h.jws.n < 4 * n + 16) h.jws.alloc(4 * n + 16);
   int sweeps = 0;
-  HIPCHECK(jacobi_eigh((int)n, Aw.p, Vec.p, h.jws.p, 60, 1e-15, h.s, &sweeps));
+  // second buffer of the one-launch-per-step form (faster than the launch
+  // pairs up to JACOBI_STEP1_MAX; above, its redundant rotation reads cost more)
+  DBuf A2(n > JACOBI_WG_AUTO && n <= JACOBI_STEP1_MAX ? n * n : 0);
+  HIPCHECK(jacobi_eigh((int)n, Aw.p, Vec.p, h.jws.p, 60, 1e-15, h.s, &sweeps, 0, A2.p));
   std::vector<double> full(n * n);
   HIPCHECK(hipMemcpyAsync(full.data(), Aw.p, (size_t)(n * n) * sizeof(double),
                           hipMemcpyDeviceToHost, h.s));
@@ -1254,15 +1265,18 @@ void launch_entry(H& h, const std::vector<Entry>& es, size_t k, LaunchTune tu, c
                               dshift, V ? V + e.offset : nullptr, sig + e.offset, h.s, tu));
   } else {
     HIPCHECK(residual_gemm_t(e.nrow, e.nalpha, x + e.offset, Sel<T>::S(e), Sel<T>::F(e), Sel<T>::eps(e),
-                             dshift, V ? V + e.offset : nullptr, sig + e.offset, h.s, h.splitk_ws, tu));
+                             dshift, V ? V + e.offset : nullptr, sig + e.offset, h.s,
+                             h.ws_cur ? *h.ws_cur : h.splitk_ws, tu));
   }
 }
 
 // sigma_L = A_L x (+ V^(L)) in the packed layout (Eq. 10).  T = double is
 // the FP64 operator; T = float the FP32 operator of the mixed-precision
 // inner solver (FP32 copies of S, F, eps and of the coupling matrices).
+// reverse: launch the entries last to first (a second stream then starts
+// with the MFMA-bound entries while the first streams the HBM-bound ones)
 template <typename T>
-void residual(H& h, int L, const T* x, T* sig, bool with_source) {
+void residual(H& h, int L, const T* x, T* sig, bool with_source, bool reverse = false) {
   const int set = set_of(h, L);
   const double dshift = h.d.shift - h.e0[L];
   const double esz = (double)sizeof(T);
@@ -1272,16 +1286,21 @@ void residual(H& h, int L, const T* x, T* sig, bool with_source) {
     if (sizeof(T) != sizeof(double)) throw DevError(CASPT2_E_ARG, "source only in FP64");
     V = reinterpret_cast<const T*>(h.src[set][L].p);
   }
+  std::vector<size_t> units;   // first entry of each launch
   for (size_t k = 0; k < es.size(); ++k) {
+    if (es[k].nrow == 0 || es[k].nalpha == 0) continue;
+    units.push_back(k);
+    if (paired_rows(es, k)) ++k;
+  }
+  if (reverse) std::reverse(units.begin(), units.end());
+  for (size_t k : units) {
     auto& e = es[k];
-    if (e.nrow == 0 || e.nalpha == 0) continue;
     const bool pair = paired_rows(es, k);
     const double rows = (double)(e.nrow + (pair ? es[k + 1].nrow : 0));
     hipEvent_t ev = nullptr;
     prof_begin(h, &ev);
     launch_entry<T>(h, es, k, Sel<T>::tune(e), x, V, sig, dshift);
     prof_end(h, (int)k, (with_source ? 3.0 : 2.0) * esz * rows * e.nalpha, ev);
-    if (pair) ++k;
   }
   if (!h.couple.empty() && !h.couple[set].empty()) {
     hipEvent_t ev = nullptr;
@@ -2359,11 +2378,20 @@ int caspt2_create(const caspt2_dims* dims, const caspt2_inputs* in, int on_devic
 }
 
 int caspt2_destroy(caspt2_handle* h) {
-  if (h)
+  if (h) {
     for (auto& r : h->prof_events) {
       (void)hipEventDestroy(r.a);
       (void)hipEventDestroy(r.b);
     }
+    for (int l = 0; l < 2; ++l) {
+      if (h->slane[l]) {
+        (void)hipStreamSynchronize(h->slane[l]);
+        (void)hipStreamDestroy(h->slane[l]);
+      }
+      if (h->slane_done[l]) (void)hipEventDestroy(h->slane_done[l]);
+    }
+    if (h->sfork) (void)hipEventDestroy(h->sfork);
+  }
   delete h;
   return CASPT2_OK;
 }
@@ -2378,6 +2406,12 @@ int caspt2_set_precision(caspt2_handle* h, int32_t precision) {
     h->d.precision = precision;
     return CASPT2_OK;
   })
+}
+
+int caspt2_set_streams(caspt2_handle* h, int32_t n) {
+  if (!h || n < 1 || n > 2) return CASPT2_E_ARG;
+  h->residual_streams = n;
+  return CASPT2_OK;
 }
 
 int caspt2_autotune(caspt2_handle* h, const char* cache_path, int32_t force) {
@@ -2465,9 +2499,53 @@ int caspt2_residual(caspt2_handle* h, int32_t L, int32_t with_source, const doub
 int caspt2_residual_all(caspt2_handle* h, int32_t with_source, const double* x, double* sigma) {
   if (!h || !x || !sigma) return CASPT2_E_ARG;
   ABI_GUARD({
-    for (int L = 0; L < h->nst; ++L)
-      residual(*h, L, x + (int64_t)L * h->length, sigma + (int64_t)L * h->length, with_source != 0);
-    host_sync(*h);
+    H& hh = *h;
+    bool coupled = false;
+    for (auto& cs : hh.couple) coupled = coupled || !cs.empty();
+    if (coupled || hh.residual_streams < 2) {
+      // one stream (the coupling terms share the handle's work tensors)
+      for (int L = 0; L < hh.nst; ++L)
+        residual(hh, L, x + (int64_t)L * hh.length, sigma + (int64_t)L * hh.length, with_source != 0);
+      host_sync(hh);
+      return CASPT2_OK;
+    }
+    // states alternate between two streams; the second runs its entries in
+    // reverse order, so MFMA-bound GEMMs of one state overlap the HBM-bound
+    // streaming kernels of another.  Results are identical to the one-stream
+    // order (each state's launches and split-K workspace are its stream's
+    // own).  (Measured: splitting instead by kind -- all streaming entries on
+    // one stream, all GEMM entries on the other -- is no faster at the full
+    // size and slower at the mid size.)
+    if (!hh.sfork) {
+      HIPCHECK(hipEventCreateWithFlags(&hh.sfork, hipEventDisableTiming));
+      for (int l = 0; l < 2; ++l) {
+        HIPCHECK(hipStreamCreateWithFlags(&hh.slane[l], hipStreamNonBlocking));
+        HIPCHECK(hipEventCreateWithFlags(&hh.slane_done[l], hipEventDisableTiming));
+      }
+    }
+    if (hh.splitk_ws2.n != hh.splitk_ws.n) hh.splitk_ws2.alloc(hh.splitk_ws.n);
+    const hipStream_t keep = hh.s;
+    HIPCHECK(hipEventRecord(hh.sfork, keep));
+    for (int l = 0; l < 2; ++l) HIPCHECK(hipStreamWaitEvent(hh.slane[l], hh.sfork, 0));
+    try {
+      for (int L = 0; L < hh.nst; ++L) {
+        const int l = L & 1;
+        hh.s = hh.slane[l];
+        hh.ws_cur = l ? &hh.splitk_ws2 : &hh.splitk_ws;
+        residual(hh, L, x + (int64_t)L * hh.length, sigma + (int64_t)L * hh.length, with_source != 0, l == 1);
+      }
+    } catch (...) {
+      hh.s = keep;
+      hh.ws_cur = nullptr;
+      throw;
+    }
+    hh.s = keep;
+    hh.ws_cur = nullptr;
+    for (int l = 0; l < 2; ++l) {
+      HIPCHECK(hipEventRecord(hh.slane_done[l], hh.slane[l]));
+      HIPCHECK(hipStreamWaitEvent(keep, hh.slane_done[l], 0));
+    }
+    host_sync(hh);
     return CASPT2_OK;
   })
 }
@@ -2740,13 +2818,15 @@ int caspt2_debug_eigh(int32_t n, double* A, double* w, double* V) {
 }
 
 int caspt2_debug_eigh_method(int32_t n, double* A, double* w, double* V, int32_t method, int32_t* sweeps_out) {
-  if (n <= 0 || !A || !w || !V || method < 0 || method > 3) return CASPT2_E_ARG;
+  if (n <= 0 || !A || !w || !V || method < 0 || method > 4) return CASPT2_E_ARG;
   if ((method == 1 && n > 64) || (method == 2 && n > 512)) return CASPT2_E_ARG;
   ABI_GUARD({
     double* ws = nullptr;
-    HIPCHECK(hipMalloc(&ws, (4 * (size_t)n + 16) * sizeof(double)));
+    HIPCHECK(hipMalloc(&ws, (4 * (size_t)n + 16 + (size_t)n * n) * sizeof(double)));
     int sweeps = 0;
-    hipError_t e = jacobi_eigh(n, A, V, ws, 60, 1e-15, nullptr, &sweeps, method);
+    // method 4: the whole-device form with one launch per step (second buffer)
+    hipError_t e = jacobi_eigh(n, A, V, ws, 60, 1e-15, nullptr, &sweeps, method == 4 ? 3 : method,
+                               method == 4 ? ws + 4 * (size_t)n + 16 : nullptr);
     if (sweeps_out) *sweeps_out = sweeps;
     std::vector<double> full((size_t)n * n);
     if (e == hipSuccess) e = hipMemcpy(full.data(), A, full.size() * sizeof(double), hipMemcpyDeviceToHost);

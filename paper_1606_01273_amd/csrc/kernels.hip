@@ -926,6 +926,73 @@ __global__ void k_jac_apply(int n, int m, double* __restrict__ A, double* __rest
   }
 }
 
+// rotation (c, s) that annihilates A[p][q] (p < q) of the current matrix
+__device__ inline void jac_rotation(int n, const double* __restrict__ A, int p, int q, double& c, double& s) {
+  c = 1.0;
+  s = 0.0;
+  if (q >= n) return;
+  const double apq = A[(int64_t)p * n + q];
+  if (apq == 0.0) return;
+  const double app = A[(int64_t)p * n + p], aqq = A[(int64_t)q * n + q];
+  const double tau = (aqq - app) / (2.0 * apq);
+  const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+  c = 1.0 / sqrt(1.0 + t * t);
+  s = t * c;
+}
+
+__device__ inline void jac_pair(int k, int step, int m, int& p, int& q) {
+  p = rr_player(k, step, m);
+  q = rr_player(m - 1 - k, step, m);
+  if (p > q) {
+    const int t = p;
+    p = q;
+    q = t;
+  }
+}
+
+// One rotation step in one launch: every thread derives the rotations it
+// needs from the matrix of the previous step (Aold, read only), so no
+// separate parameter launch and no race on the diagonal blocks; the rotated
+// matrix goes to Anew (the two buffers alternate).  Threads [0, h^2) rotate
+// the 2 x 2 blocks, the rest the rows of V (in place: each V element has one
+// owner).
+__global__ void k_jac_step(int n, int m, int step, const double* __restrict__ Aold, double* __restrict__ Anew,
+                           double* __restrict__ V) {
+  const int64_t h = m / 2;
+  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g < h * h) {
+    const int a = (int)(g / h), b = (int)(g % h);
+    int pa, qa, pb, qb;
+    jac_pair(a, step, m, pa, qa);
+    jac_pair(b, step, m, pb, qb);
+    double ca, sa, cb, sb;
+    jac_rotation(n, Aold, pa, qa, ca, sa);
+    jac_rotation(n, Aold, pb, qb, cb, sb);
+    const bool ipa = pa < n, iqa = qa < n, ipb = pb < n, iqb = qb < n;
+    const double m00 = (ipa && ipb) ? Aold[(int64_t)pa * n + pb] : 0.0;
+    const double m01 = (ipa && iqb) ? Aold[(int64_t)pa * n + qb] : 0.0;
+    const double m10 = (iqa && ipb) ? Aold[(int64_t)qa * n + pb] : 0.0;
+    const double m11 = (iqa && iqb) ? Aold[(int64_t)qa * n + qb] : 0.0;
+    const double r00 = ca * m00 - sa * m10, r01 = ca * m01 - sa * m11;
+    const double r10 = sa * m00 + ca * m10, r11 = sa * m01 + ca * m11;
+    if (ipa && ipb) Anew[(int64_t)pa * n + pb] = cb * r00 - sb * r01;
+    if (ipa && iqb) Anew[(int64_t)pa * n + qb] = sb * r00 + cb * r01;
+    if (iqa && ipb) Anew[(int64_t)qa * n + pb] = cb * r10 - sb * r11;
+    if (iqa && iqb) Anew[(int64_t)qa * n + qb] = sb * r10 + cb * r11;
+  } else if (g < h * h + (int64_t)n * h) {
+    const int64_t gg = g - h * h;
+    const int i = (int)(gg / h), a = (int)(gg % h);
+    int pa, qa;
+    jac_pair(a, step, m, pa, qa);
+    if (qa >= n) return;
+    double ca, sa;
+    jac_rotation(n, Aold, pa, qa, ca, sa);
+    const double vp = V[(int64_t)i * n + pa], vq = V[(int64_t)i * n + qa];
+    V[(int64_t)i * n + pa] = ca * vp - sa * vq;
+    V[(int64_t)i * n + qa] = sa * vp + ca * vq;
+  }
+}
+
 __global__ void k_eye(int n, double* V) {
   const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (g < (int64_t)n * n) V[g] = (g / n == g % n) ? 1.0 : 0.0;
@@ -1076,7 +1143,7 @@ __global__ __launch_bounds__(1024) void k_jacobi_small(int n, double* __restrict
 }
 
 hipError_t jacobi_eigh(int n, double* A, double* V, double* ws, int max_sweeps, double tol,
-                       hipStream_t s, int* sweeps_done, int method) {
+                       hipStream_t s, int* sweeps_done, int method, double* A2) {
   if (n <= 0) return hipSuccess;
   // the attainable off-diagonal norm grows with n (round-off of the rotations)
   tol = fmax(tol, 4e-16 * (double)n);
@@ -1122,11 +1189,29 @@ hipError_t jacobi_eigh(int n, double* A, double* V, double* ws, int max_sweeps, 
     if (e != hipSuccess) return e;
     if (hn[0] <= tol * tol * hn[1] || hn[1] == 0.0 || m < 2 || (sw > 2 && !(hn[0] < prev))) break;
     prev = hn[0];
-    for (int step = 0; step < m - 1; ++step) {
-      hipLaunchKernelGGL(k_jac_params, dim3(cdiv(m / 2, 128)), dim3(128), 0, s, n, m, step, A, cs,
-                         pq);
-      const int64_t work = (int64_t)(m / 2) * (m / 2) + (int64_t)n * (m / 2);
-      hipLaunchKernelGGL(k_jac_apply, dim3(cdiv(work, 256)), dim3(256), 0, s, n, m, A, V, cs, pq);
+    const int64_t work = (int64_t)(m / 2) * (m / 2) + (int64_t)n * (m / 2);
+    if (A2) {
+      // one launch per step, alternating buffers; an odd step count leaves
+      // the sweep's result in A2, copied back below
+      double* cur = A;
+      double* nxt = A2;
+      for (int step = 0; step < m - 1; ++step) {
+        hipLaunchKernelGGL(k_jac_step, dim3(cdiv(work, 256)), dim3(256), 0, s, n, m, step, (const double*)cur,
+                           nxt, V);
+        double* t = cur;
+        cur = nxt;
+        nxt = t;
+      }
+      if (cur != A) {
+        e = hipMemcpyAsync(A, cur, (size_t)n * n * sizeof(double), hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return e;
+      }
+    } else {
+      for (int step = 0; step < m - 1; ++step) {
+        hipLaunchKernelGGL(k_jac_params, dim3(cdiv(m / 2, 128)), dim3(128), 0, s, n, m, step, A, cs,
+                           pq);
+        hipLaunchKernelGGL(k_jac_apply, dim3(cdiv(work, 256)), dim3(256), 0, s, n, m, A, V, cs, pq);
+      }
     }
   }
   if (sweeps_done) *sweeps_done = sw;

@@ -209,11 +209,13 @@ hipError_t select_scale_cols(int64_t n, int64_t ncq, const double* Q, const int3
 // eigenvalues, unsorted); V receives eigenvectors (columns).  ws: device
 // workspace of >= 4*n doubles + 2*n ints. sweeps: max sweeps.  method: 0
 // by size (below), 1 one workgroup with A and V in LDS (n <= 64), 2 one
-// workgroup on global memory (n <= 512), 3 one launch pair per rotation
-// step over the whole chip.
-constexpr int JACOBI_WG_AUTO = 96;   // largest n solved by one workgroup by default
+// workgroup on global memory (n <= 512), 3 launches over the whole chip per
+// rotation step: one per step when A2 (a second n x n device buffer) is
+// given, else a parameter launch and a rotation launch.
+constexpr int JACOBI_WG_AUTO = 64;   // largest n solved by one workgroup (LDS form) by default
+constexpr int JACOBI_STEP1_MAX = 512;   // largest n for which the one-launch-per-step form pays
 hipError_t jacobi_eigh(int n, double* A, double* V, double* ws, int max_sweeps, double tol,
-                       hipStream_t s, int* sweeps_done, int method = 0);
+                       hipStream_t s, int* sweeps_done, int method = 0, double* A2 = nullptr);
 
 // vector kernels (element types as instantiated in kernels.hip)
 template <typename T>  // FP64 accumulation; out on device (1 double); partial >= 1024 doubles

@@ -77,14 +77,21 @@ def cmd_stats(a):
                     disp.append((int(r.get("Dispatch_Id") or 0),
                                  int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
         disp.sort()
+        tail = [d for _, d in disp[-a.skip_last:]] if a.skip_last > 0 else []
+        if a.skip_last > 0:
+            disp = disp[:-a.skip_last]
         sel = [d for _, d in disp[-a.last:]]
         if sel:
-            lines += ["", f"last {len(sel)} dispatches of {a.last_kernel} (of {len(disp)}): "
+            skip = f", skipping the last {a.skip_last}" if a.skip_last > 0 else ""
+            lines += ["", f"last {len(sel)} dispatches of {a.last_kernel}{skip} (of {len(disp) + a.skip_last}): "
                           f"average {sum(sel) / len(sel) / 1e3:.2f} us, min {min(sel) / 1e3:.2f} us, "
                           f"max {max(sel) / 1e3:.2f} us"]
+        if tail:
+            lines += [f"the skipped last {len(tail)} dispatches (a later pass of the command): average "
+                      f"{sum(tail) / len(tail) / 1e3:.2f} us, min {min(tail) / 1e3:.2f} us, max {max(tail) / 1e3:.2f} us"]
     with open(a.out, "w") as fh:
         fh.write("\n".join(lines) + "\n")
-    print("\n".join(lines[:12] + lines[-1:]))
+    print("\n".join(lines[:12] + lines[-2:]))
 
 
 def cmd_pmc(a):
@@ -99,6 +106,8 @@ def cmd_pmc(a):
     kf, kw = pick(fetch, kre), pick(write, kre)
     if not kf or not kw:
         sys.exit(f"no dispatch of {a.kernel} in the counter files")
+    if a.skip_last > 0:   # launches after the ones wanted (a later pass of the same command)
+        kf, kw = kf[:-a.skip_last], kw[:-a.skip_last]
     if a.last > 0:   # the timed launches only (not the autotuner's trial launches before them)
         kf, kw = kf[-a.last:], kw[-a.last:]
     fill_w = pick(write, r"FillFunctor")
@@ -119,7 +128,8 @@ def cmd_pmc(a):
            "dispatches": [len(kf), len(kw)], "fetch_scale": fetch_scale, "write_scale": write_scale,
            "calibration": {"fill_write_kib": fill_w[-1], "mul_fetch_kib": mul_f[-1],
                            "mul_write_kib": mul_w[-1] if mul_w else None},
-           "kernel_regex": a.kernel, "last_dispatches": a.last, "kernel_source_sha256": rows_kernel_source_sha256(),
+           "kernel_regex": a.kernel, "last_dispatches": a.last, "skipped_last": a.skip_last,
+           "kernel_source_sha256": rows_kernel_source_sha256(),
            "command_fetch": a.command_fetch, "command_write": a.command_write}
     db = {}
     if os.path.exists(a.out_json):
@@ -199,6 +209,7 @@ def main():
     s.add_argument("--trace", help="kernel trace CSV (per-dispatch timestamps)")
     s.add_argument("--last-kernel", help="kernel regex for the last-N average")
     s.add_argument("--last", type=int, default=0)
+    s.add_argument("--skip-last", type=int, default=0, help="ignore the last M dispatches of that kernel")
     p = sub.add_parser("pmc")
     p.add_argument("fetch_csv")
     p.add_argument("write_csv")
@@ -209,6 +220,7 @@ def main():
     p.add_argument("--command-fetch", required=True)
     p.add_argument("--command-write", required=True)
     p.add_argument("--last", type=int, default=0, help="average over the last N dispatches of the kernel only")
+    p.add_argument("--skip-last", type=int, default=0, help="ignore the last M dispatches of the kernel")
     m = sub.add_parser("mfma")
     m.add_argument("csv")
     m.add_argument("out")

@@ -73,10 +73,11 @@ def test_debug_eigh_matches_numpy(dev):
 
 
 @pytest.mark.parametrize("method,sizes", [(1, (1, 2, 7, 33, 64)), (2, (2, 7, 64, 101, 300)),
-                                          (3, (2, 7, 64, 101, 257))])
+                                          (3, (2, 7, 64, 101, 257)), (4, (1, 2, 3, 7, 64, 101, 257))])
 def test_debug_eigh_methods_match_numpy(dev, method, sizes):
     """every form of the Jacobi solver (LDS workgroup, global-memory workgroup,
-    whole-device launches) on the sizes it takes"""
+    whole-device launch pairs, one whole-device launch per step) on the sizes
+    it takes, odd and even"""
     from paper_1606_01273_amd import lib
     rng = np.random.default_rng(2)
     for n in sizes:
