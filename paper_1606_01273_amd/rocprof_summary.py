@@ -161,17 +161,20 @@ def cmd_mfma(a):
         for r in csv.DictReader(fh):
             key = (r["Kernel_Name"], int(r.get("Dispatch_Id") or r.get("Correlation_Id") or 0))
             per.setdefault(key, {})[r["Counter_Name"]] = float(r["Counter_Value"])
-    first = 0
+    first, stop = 0, None
     if a.from_last:
         # keep the dispatches from the N-th last dispatch of the marker kernel
-        # on (the timed region; earlier ones include the autotuner's trials)
+        # on (the timed region; earlier ones include the autotuner's trials),
+        # and, with --before-last M, before its M-th last (a later pass)
         mre, n = re.compile(a.from_last[0]), int(a.from_last[1])
         ids = sorted(d for (name, d) in per if mre.search(name))
         if len(ids) >= n:
             first = ids[-n]
+        if a.before_last and len(ids) >= a.before_last:
+            stop = ids[-a.before_last]
     agg = {}
     for (name, did), c in per.items():
-        if did < first:
+        if did < first or (stop is not None and did >= stop):
             continue
         short = re.sub(r"\(.*", "", re.sub(r"\s+", " ", name))[:70]
         g = agg.setdefault(short, {"n": 0, "busy": 0.0, "gui": 0.0, "mops": 0.0})
@@ -180,7 +183,8 @@ def cmd_mfma(a):
         g["gui"] += c.get("GRBM_GUI_ACTIVE", 0.0)
         g["mops"] += c.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0)
     lines = [f"# rocprofv3 MFMA counters per kernel (averages per dispatch)", f"# command: {a.command}",
-             f"# dispatches from the {a.from_last[1]}-th last of {a.from_last[0]} on" if a.from_last else "#",
+             (f"# dispatches from the {a.from_last[1]}-th last of {a.from_last[0]} on"
+              + (f", before its {a.before_last}-th last" if a.before_last else "")) if a.from_last else "#",
              "# F64 MFMA GFLOP = 512 * SQ_INSTS_VALU_MFMA_MOPS_F64 / 1e9; GRBM_GUI_ACTIVE is summed over the",
              f"# {a.xcds} XCDs, so the dispatch time is GUI_ACTIVE / ({a.xcds} * {a.clock_ghz} GHz); MFMA_BUSY counts per",
              f"# SIMD: utilisation = MFMA_BUSY / (GUI_ACTIVE / {a.xcds} * {a.simds} SIMDs)", "",
@@ -230,6 +234,8 @@ def main():
     m.add_argument("--clock-ghz", type=float, default=2.4)
     m.add_argument("--from-last", nargs=2, metavar=("KERNEL_REGEX", "N"),
                    help="only dispatches from the N-th last dispatch of this kernel on")
+    m.add_argument("--before-last", type=int, default=0,
+                   help="with --from-last: only dispatches before the M-th last dispatch of that kernel")
     a = ap.parse_args()
     {"stats": cmd_stats, "pmc": cmd_pmc, "mfma": cmd_mfma}[a.cmd](a)
 
