@@ -115,6 +115,8 @@ struct CoupleTerm {
   int64_t f_off;         // offset of the Fock block origin in f
   DBuf G;                // up: [ny * nalpha_b][nalpha_k]; down: [nalpha_b][ny * nalpha_k]
   FBuf G32;              // FP32 copy (mixed precision)
+  int fuse = -1;         // up terms (autotuned): -1 rule (fused where possible), 0 GEMM + ket-parallel
+                         // expand, 1 fused, 2 GEMM + output-parallel expand
 };
 
 // element-type selection of the per-entry and per-term operands
@@ -1150,16 +1152,45 @@ void setup_couplings(H& h) {
 // an index-mapped expand or reduce with the Fock block), pack once per block.
 // (T = float in the inner solver of the mixed-precision mode: the
 // all-orderings buffers, sized for doubles, then hold floats.)
+int64_t nalpha_of_block(const H& h, int set, int block) {
+  for (auto& e : h.sets[set])
+    if (e.block == block) return e.nalpha;
+  return 0;
+}
+
+// one coupling term into the all-orderings sigma of its bra (x: the packed
+// vector, read directly for a packed ket; the other kets' all-orderings
+// copies are current).  fuse: the term's own choice, or -1/0/1 to override.
+template <typename T>
+void couple_term(H& h, int set, const CoupleTerm& t, const T* x, int fuse) {
+  T* scratch = reinterpret_cast<T*>(h.cscratch.p);
+  T* xk = reinterpret_cast<T*>(h.xall[t.ket].p);
+  T* sb = reinterpret_cast<T*>(h.sall[t.bra].p);
+  const double* f = h.fock.p + t.f_off;
+  const int64_t nab = nalpha_of_block(h, set, t.bra), nak = nalpha_of_block(h, set, t.ket);
+  if (t.up && couple_up_fusable<T>(t.d, nak) && (fuse == -1 || fuse == 1)) {
+    HIPCHECK(couple_up_fused(t.d, f, (const T*)xk, nak, Sel<T>::G(t), sb, h.s));
+  } else if (t.up) {
+    const int64_t width = (int64_t)t.d.ny * nab;
+    HIPCHECK(gemm_t(true, all_rows(h, t.ket), width, nak, 1.0, xk, nak, Sel<T>::G(t), nak, 0.0, scratch, width,
+                    h.s));
+    HIPCHECK(couple_expand(t.d, f, (const T*)scratch, sb, h.s, fuse == 0 ? 1 : fuse == 2 ? 2 : 0));
+  } else {
+    const int64_t width = (int64_t)t.d.ny * nak;
+    if (h.direct[t.ket])
+      HIPCHECK(couple_reduce_packed(t.d, pack_info(h, set, t.ket, nullptr, nullptr, nak), f, x, scratch, h.s));
+    else
+      HIPCHECK(couple_reduce(t.d, f, (const T*)xk, scratch, h.s));
+    HIPCHECK(gemm_t(true, all_rows(h, t.bra), nab, width, 1.0, scratch, width, Sel<T>::G(t), width, 1.0, sb,
+                    nab, h.s));
+  }
+}
+
 template <typename T>
 void apply_couplings(H& h, int set, const T* x, T* sig) {
-  auto nalpha_of = [&](int block) {
-    for (auto& e : h.sets[set])
-      if (e.block == block) return e.nalpha;
-    return (int64_t)0;
-  };
+  auto nalpha_of = [&](int block) { return nalpha_of_block(h, set, block); };
   auto xall = [&](int b) { return reinterpret_cast<T*>(h.xall[b].p); };
   auto sall = [&](int b) { return reinterpret_cast<T*>(h.sall[b].p); };
-  T* scratch = reinterpret_cast<T*>(h.cscratch.p);
   const bool diag = h.verbose_level >= 2;   // per-stage timing on stderr
   double t_prev = diag ? (host_sync(h), wall()) : 0.0;
   auto stage = [&](const char* what) {
@@ -1179,33 +1210,26 @@ void apply_couplings(H& h, int set, const T* x, T* sig) {
   }
   stage("unpack");
   for (auto& t : h.couple[set]) {
-    const double* f = h.fock.p + t.f_off;
-    const int64_t nab = nalpha_of(t.bra), nak = nalpha_of(t.ket);
     if (diag) {
       stage("stage");
       std::fprintf(stderr, "[caspt2] term %s %s <- %s ny %d nsum %d: ", t.up ? "up" : "down",
                    blocks()[t.bra].name.c_str(), blocks()[t.ket].name.c_str(), t.d.ny, t.d.nsum);
     }
-    if (t.up && couple_up_fusable<T>(t.d, nak)) {
-      HIPCHECK(couple_up_fused(t.d, f, (const T*)xall(t.ket), nak, Sel<T>::G(t), sall(t.bra), h.s));
-    } else if (t.up) {
-      const int64_t width = (int64_t)t.d.ny * nab;
-      HIPCHECK(gemm_t(true, all_rows(h, t.ket), width, nak, 1.0, xall(t.ket), nak, Sel<T>::G(t), nak, 0.0,
-                      scratch, width, h.s));
-      HIPCHECK(couple_expand(t.d, f, (const T*)scratch, sall(t.bra), h.s));
-    } else {
-      const int64_t width = (int64_t)t.d.ny * nak;
-      if (h.direct[t.ket])
-        HIPCHECK(couple_reduce_packed(t.d, pack_info(h, set, t.ket, nullptr, nullptr, nak), f, x, scratch, h.s));
-      else
-        HIPCHECK(couple_reduce(t.d, f, (const T*)xall(t.ket), scratch, h.s));
-      HIPCHECK(gemm_t(true, all_rows(h, t.bra), nab, width, 1.0, scratch, width, Sel<T>::G(t), width, 1.0,
-                      sall(t.bra), nab, h.s));
-    }
+    couple_term<T>(h, set, t, x, t.fuse);
   }
   stage("last term");
   for (int b = 0; b < NBLOCK; ++b) {
     if (!h.sall[b].p) continue;
+    if (b == CCVV && nalpha_of(b) <= 4) {
+      // both characters in one tiled pass
+      T* plus = nullptr;
+      T* minus = nullptr;
+      for (auto& e : h.sets[set])
+        if (e.block == b && e.nrow > 0) (e.chi.empty() || e.chi[0] > 0 ? plus : minus) = sig + e.offset;
+      if (plus)
+        HIPCHECK(pack_ccvv(h.nc, h.nv, (int)nalpha_of(b), (const T*)sall(b), plus, minus, h.s));
+      continue;
+    }
     for (auto& e : h.sets[set]) {
       if (e.block != b || e.nrow == 0) continue;
       TermDesc d = base_desc(h, blocks()[b], e);
@@ -2169,6 +2193,49 @@ void autotune(H& h, const char* cache_path, bool force) {
         if (pair) ++k;
       }
     }
+    // up coupling terms that can run fused: fused against GEMM + expand
+    for (size_t set = 0; set < h.couple.size(); ++set)
+      for (auto& t : h.couple[set]) {
+        const int64_t nak = nalpha_of_block(h, (int)set, t.ket);
+        if (!t.up || t.d.ny > 8) continue;
+        const bool fusable = couple_up_fusable<double>(t.d, nak);
+        int64_t rows_k = 1;
+        for (int k = 0; k < t.d.ket.nslot; ++k) rows_k *= t.d.ket.slot_dim[k];
+        char kb[200];
+        std::snprintf(kb, sizeof kb, "term %d %d %d %lld %lld %lld %d %d %d %d %d %d", t.bra, t.ket, t.d.ny,
+                      (long long)t.d.ncol, (long long)nak, (long long)rows_k, t.d.ket_src[0], t.d.ket_src[1],
+                      t.d.ket_src[2], t.d.ket_src[3], t.d.fx_src, t.d.fy_src);
+        const std::string key = kb;
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end() && !force) {
+          t.fuse = it->second.splitk;   // the first field holds the fused flag for term keys
+          continue;
+        }
+        double best = INFINITY;
+        int pick = -1;
+        for (int fz : {1, 0, 2}) {
+          if (fz == 1 && !fusable) continue;
+          couple_term<double>(h, (int)set, t, h.wx.p, fz);   // warm-up
+          HIPCHECK(hipEventRecord(a, h.s));
+          for (int r = 0; r < 2; ++r) couple_term<double>(h, (int)set, t, h.wx.p, fz);
+          HIPCHECK(hipEventRecord(b, h.s));
+          HIPCHECK(hipEventSynchronize(b));
+          float ms = 0.0f;
+          HIPCHECK(hipEventElapsedTime(&ms, a, b));
+          if (ms / 2 < best) {
+            best = ms / 2;
+            pick = fz;
+          }
+        }
+        t.fuse = pick;
+        LaunchTune lt;
+        lt.splitk = pick;
+        g_tune_cache[key] = lt;
+        if (h.verbose)
+          std::fprintf(stderr, "[caspt2] tune %s: %s %.4f ms\n", key.c_str(),
+                       pick == 1 ? "fused" : pick == 2 ? "GEMM + output-parallel expand" : "GEMM + ket-parallel expand",
+                       best);
+      }
     // workspace for the chosen split counts
     int64_t ws = 0;
     for (auto& es : h.sets)

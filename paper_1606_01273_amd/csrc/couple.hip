@@ -1,5 +1,7 @@
 // Coupling kernels (Fock couplings between excitation blocks) and the
 // packed <-> all-orderings conversions, for FP64 and FP32 data.
+#include <algorithm>
+
 #include "device_common.hpp"
 #include "kernels.hpp"
 
@@ -39,6 +41,54 @@ __device__ inline double orbit_images(const D& d, const int e0[4], F&& fn) {
     fn(e, sg);
   }
   return ndist == 0 ? 1.0 : (ndist == 1 ? 0.70710678118654752440 : 0.5);
+}
+
+// NC consecutive values at p as doubles.  vec: the group is whole and p is
+// aligned to the group (row length a multiple of NC), so the values move in
+// 16-byte loads (two doubles or four floats per load) instead of one request
+// per value -- a thread's row segment is contiguous, so element-wise loads
+// would issue one memory request per lane per value.
+template <typename T, int NC>
+__device__ inline void load_group(const T* __restrict__ p, bool vec, double (&v)[NC]) {
+  if (vec && NC >= 2) {
+    if constexpr (sizeof(T) == 8) {
+#pragma unroll
+      for (int c = 0; c < NC; c += 2) {
+        const double2 q = *reinterpret_cast<const double2*>(p + c);
+        v[c] = q.x;
+        v[c + 1] = q.y;
+      }
+    } else if constexpr (NC == 4) {
+      const float4 q = *reinterpret_cast<const float4*>(p);
+      v[0] = q.x;
+      v[1] = q.y;
+      v[2] = q.z;
+      v[3] = q.w;
+    } else {
+      const float2 q = *reinterpret_cast<const float2*>(p);
+      v[0] = q.x;
+      v[1] = q.y;
+    }
+    return;
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c) v[c] = (double)p[c];
+}
+template <typename T, int NC>
+__device__ inline void store_group(T* __restrict__ p, bool vec, const double (&v)[NC]) {
+  if (vec && NC >= 2) {
+    if constexpr (sizeof(T) == 8) {
+#pragma unroll
+      for (int c = 0; c < NC; c += 2) *reinterpret_cast<double2*>(p + c) = double2{v[c], v[c + 1]};
+    } else if constexpr (NC == 4) {
+      *reinterpret_cast<float4*>(p) = float4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
+    } else {
+      *reinterpret_cast<float2*>(p) = float2{(float)v[0], (float)v[1]};
+    }
+    return;
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c) p[c] = (T)v[c];
 }
 
 // Column groups: a thread handles NC consecutive alpha columns of one row
@@ -120,6 +170,93 @@ hipError_t pack_acc(const TermDesc& d, const AllDesc& a, const T* in_all, T* pac
   return hipGetLastError();
 }
 
+// ccvv (slots i, j | a, b, swaps (i,j) and (a,b)) all-orderings sigma into
+// its two packed entries: + (i >= j, a >= b) and - (i > j, a > b), added to
+// packed + and - (rows of ncol <= 4 values).  A workgroup takes one closed
+// pair (i >= j) and a 16 x 16 tile (A, B) of virtual pairs with A >= B: the
+// four images (i,j,a,b), (j,i,a,b), (i,j,b,a), (j,i,b,a) of the tile are
+// staged through LDS -- the two (a,b)-swapped ones loaded from the mirrored
+// tile (B, A) row by row and read back transposed -- so every global access
+// runs along contiguous rows instead of gathering 32-byte rows 400 apart.
+constexpr int PCC_T = 16;
+template <typename T>
+__global__ __launch_bounds__(256) void k_pack_ccvv(int nc, int nv, int ncol, const T* __restrict__ in,
+                                                   T* __restrict__ plus, T* __restrict__ minus, int ntile) {
+  __shared__ double img[4][PCC_T * PCC_T][4];
+  const int t = threadIdx.x;
+  // tile pair (A >= B) from blockIdx.x, closed pair (i >= j) from blockIdx.y
+  int A = 0, rem = blockIdx.x;
+  while (rem > A) {   // blockIdx.x = A (A + 1) / 2 + B
+    rem -= A + 1;
+    ++A;
+  }
+  const int B = rem;
+  int i = 0;
+  {
+    int r = blockIdx.y;
+    while (r > i) {
+      r -= i + 1;
+      ++i;
+    }
+    rem = r;
+  }
+  const int j = rem;
+  const int a0 = A * PCC_T, b0 = B * PCC_T;
+  const int tl = t / PCC_T, tf = t % PCC_T;   // slow / fast index within the tile
+  const int64_t nv2 = (int64_t)nv * nv;
+  const int64_t pij = ((int64_t)i * nc + j) * nv2, pji = ((int64_t)j * nc + i) * nv2;
+  // identity and (i,j)-swapped images: row (a0 + tl, b0 + tf); the
+  // (a,b)-swapped ones: row (b0 + tl, a0 + tf) of the mirrored tile, stored
+  // at the transposed position (tf, tl)
+  {
+    const int a = a0 + tl, b = b0 + tf;
+    const bool ok = a < nv && b < nv;
+    const int64_t r = (int64_t)a * nv + b;
+    const int ba = b0 + tl, bb = a0 + tf;
+    const bool ok2 = ba < nv && bb < nv;
+    const int64_t r2 = (int64_t)ba * nv + bb;
+    for (int c = 0; c < 4; ++c) {
+      const bool in_c = c < ncol;
+      img[0][t][c] = (ok && in_c) ? (double)in[(pij + r) * ncol + c] : 0.0;
+      img[1][t][c] = (ok && in_c) ? (double)in[(pji + r) * ncol + c] : 0.0;
+      img[2][tf * PCC_T + tl][c] = (ok2 && in_c) ? (double)in[(pij + r2) * ncol + c] : 0.0;
+      img[3][tf * PCC_T + tl][c] = (ok2 && in_c) ? (double)in[(pji + r2) * ncol + c] : 0.0;
+    }
+  }
+  __syncthreads();
+  const int a = a0 + tl, b = b0 + tf;
+  if (a >= nv || b >= nv || a < b) return;
+  const bool dij = i != j, dab = a != b;
+  const int64_t npv = (int64_t)nv * (nv + 1) / 2, nmv = (int64_t)nv * (nv - 1) / 2;
+  const int64_t rp = ((int64_t)i * (i + 1) / 2 + j) * npv + (int64_t)a * (a + 1) / 2 + b;
+  const double w = (dij && dab) ? 0.5 : ((dij || dab) ? 0.70710678118654752440 : 1.0);
+  for (int c = 0; c < ncol; ++c) {
+    const double r1 = img[0][t][c], r2 = img[1][t][c], r3 = img[2][t][c], r4 = img[3][t][c];
+    // distinct images only: (i,j)-swap when i != j, (a,b)-swap when a != b
+    const double sp = r1 + (dij ? r2 : 0.0) + (dab ? r3 : 0.0) + ((dij && dab) ? r4 : 0.0);
+    plus[rp * ncol + c] += (T)(w * sp);
+  }
+  if (dij && dab && minus) {
+    const int64_t rm = ((int64_t)i * (i - 1) / 2 + j) * nmv + (int64_t)a * (a - 1) / 2 + b;
+    for (int c = 0; c < ncol; ++c) {
+      const double r1 = img[0][t][c], r2 = img[1][t][c], r3 = img[2][t][c], r4 = img[3][t][c];
+      minus[rm * ncol + c] += (T)(0.5 * (r1 - r2 - r3 + r4));
+    }
+  }
+}
+
+template <typename T>
+hipError_t pack_ccvv(int nc, int nv, int ncol, const T* in_all, T* plus, T* minus, hipStream_t s) {
+  if (nc <= 0 || nv <= 0 || ncol <= 0) return hipSuccess;
+  if (ncol > 4) return hipErrorInvalidValue;
+  const int ntile = (nv + PCC_T - 1) / PCC_T;
+  const int64_t ntp = (int64_t)ntile * (ntile + 1) / 2, npc = (int64_t)nc * (nc + 1) / 2;
+  if (ntp > 0x7fffffff || npc > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_pack_ccvv<T>, dim3((unsigned)ntp, (unsigned)npc), dim3(PCC_T * PCC_T), 0, s, nc, nv, ncol,
+                     in_all, plus, minus, ntile);
+  return hipGetLastError();
+}
+
 // Linear index maps of an expand term, folded on the host: the bra
 // all-orderings row and the Fock offset as functions of the ket slot values,
 // the free bra slots (not fed from the ket; at most two, looped) and y.
@@ -128,6 +265,12 @@ struct ExpandPlan {
   int64_t ob_k[4], ob_f[2];  // bra row stride per ket slot / per free slot
   int64_t fk[4], ff[2], fy;  // Fock offset coefficients
   uint32_t nf0, nf1;         // free slot ranges (1 if absent)
+  // thread order over the ket rows: the ket slots in decode order (fastest
+  // first: the slot feeding the highest bra slot, so neighbouring threads
+  // write neighbouring bra rows); per position its range, ket row stride,
+  // bra row stride and Fock offset coefficient
+  uint32_t ddim[4];
+  int64_t drk[4], dob[4], dfk[4];
   uint32_t bdim[4];          // bra all-orderings dims (out-parallel form)
   int64_t wk_b[4];           // ket row stride per bra slot (out-parallel form)
   int64_t fb[4];             // Fock offset coefficient per bra slot (out-parallel form)
@@ -181,7 +324,36 @@ ExpandPlan make_expand_plan(const CoupleDesc& d) {
   fcoef(d.fy_src, 1);
   r.ny = d.ny;
   r.ncol = d.ncol;
+  // decode order: ket slots by the bra slot they feed, highest first
+  int order[4] = {0, 1, 2, 3};
+  const int nk = d.ket.nslot;
+  std::sort(order, order + nk, [&](int x, int y) { return d.ket_src[x] > d.ket_src[y]; });
+  for (int p = 0; p < 4; ++p) {
+    if (p < nk) {
+      const int l = order[p];
+      r.ddim[p] = r.kdim[l];
+      r.drk[p] = kst[l];
+      r.dob[p] = r.ob_k[l];
+      r.dfk[p] = r.fk[l];
+    } else {
+      r.ddim[p] = 1u;
+      r.drk[p] = r.dob[p] = r.dfk[p] = 0;
+    }
+  }
   return r;
+}
+
+// ket row, bra row base and Fock offset of thread row q (decode order)
+__device__ inline void expand_decode(const ExpandPlan& ep, uint32_t q, int64_t& rk, int64_t& ob, int64_t& fo) {
+  rk = ob = fo = 0;
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    const uint32_t v = q % ep.ddim[p];
+    q /= ep.ddim[p];
+    rk += (int64_t)v * ep.drk[p];
+    ob += (int64_t)v * ep.dob[p];
+    fo += (int64_t)v * ep.dfk[p];
+  }
 }
 
 // out[bra row(z0, z1)][c0 .. c0 + NC) += sum_y f(z0, z1, y) wreg[y][.] for the
@@ -195,8 +367,9 @@ __device__ inline void expand_free_range(const ExpandPlan& ep, const double* __r
                                          uint32_t ze, T* __restrict__ out) {
   constexpr int ZB = 8;
   const uint32_t nz = (ze - zb) * ep.nf1;
+  const bool vec = ep.ncol % NC == 0;
   for (uint32_t zz = 0; zz < nz; zz += ZB) {
-    T old[ZB][NC];
+    double old[ZB][NC];
     int64_t orow[ZB], frow[ZB];
 #pragma unroll
     for (int u = 0; u < ZB; ++u) {
@@ -204,8 +377,12 @@ __device__ inline void expand_free_range(const ExpandPlan& ep, const double* __r
       const uint32_t z0 = zb + z / ep.nf1, z1 = z % ep.nf1;
       orow[u] = (ob + z0 * ep.ob_f[0] + z1 * ep.ob_f[1]) * ep.ncol + c0;
       frow[u] = fo + z0 * ep.ff[0] + z1 * ep.ff[1];
+      if (z < nz && vec) {
+        load_group<T, NC>(out + orow[u], true, old[u]);
+      } else {
 #pragma unroll
-      for (int c = 0; c < NC; ++c) old[u][c] = (z < nz && c0 + c < ep.ncol) ? out[orow[u] + c] : T(0);
+        for (int c = 0; c < NC; ++c) old[u][c] = (z < nz && c0 + c < ep.ncol) ? (double)out[orow[u] + c] : 0.0;
+      }
     }
 #pragma unroll
     for (int u = 0; u < ZB; ++u) {
@@ -213,7 +390,7 @@ __device__ inline void expand_free_range(const ExpandPlan& ep, const double* __r
       const double* fr = f + frow[u];
       double acc[NC];
 #pragma unroll
-      for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+      for (int c = 0; c < NC; ++c) acc[c] = old[u][c];
 #pragma unroll
       for (int y = 0; y < 8; ++y)
         if (y < ep.ny) {
@@ -221,9 +398,13 @@ __device__ inline void expand_free_range(const ExpandPlan& ep, const double* __r
 #pragma unroll
           for (int c = 0; c < NC; ++c) acc[c] += fv * wreg[y][c];
         }
+      if (vec) {
+        store_group<T, NC>(out + orow[u], true, acc);
+      } else {
 #pragma unroll
-      for (int c = 0; c < NC; ++c)
-        if (c0 + c < ep.ncol) out[orow[u] + c] = old[u][c] + (T)acc[c];
+        for (int c = 0; c < NC; ++c)
+          if (c0 + c < ep.ncol) out[orow[u] + c] = (T)acc[c];
+      }
     }
   }
 }
@@ -240,23 +421,22 @@ __global__ __launch_bounds__(256) void k_couple_expand(ExpandPlan ep, const doub
   const int64_t wlen = (int64_t)ep.ny * ep.ncol;
   for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
        g += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t rk = g / ng, c0 = (g - rk * ng) * NC;
-    uint32_t q = (uint32_t)rk;
-    const uint32_t k3 = q % ep.kdim[3];
-    q /= ep.kdim[3];
-    const uint32_t k2 = q % ep.kdim[2];
-    q /= ep.kdim[2];
-    const uint32_t k1 = q % ep.kdim[1];
-    const uint32_t k0 = q / ep.kdim[1];
-    const int64_t ob = k0 * ep.ob_k[0] + k1 * ep.ob_k[1] + k2 * ep.ob_k[2] + k3 * ep.ob_k[3];
-    const int64_t fo = k0 * ep.fk[0] + k1 * ep.fk[1] + k2 * ep.fk[2] + k3 * ep.fk[3];
+    const int64_t tr = g / ng, c0 = (g - tr * ng) * NC;
+    int64_t rk, ob, fo;
+    expand_decode(ep, (uint32_t)tr, rk, ob, fo);
     double wreg[8][NC];
     const T* w = W + rk * wlen + c0;
+    const bool vec = ep.ncol % NC == 0;
 #pragma unroll
-    for (int y = 0; y < 8; ++y)
+    for (int y = 0; y < 8; ++y) {
+      if (y < ep.ny && vec) {
+        load_group<T, NC>(w + (int64_t)y * ep.ncol, true, wreg[y]);
+      } else {
 #pragma unroll
-      for (int c = 0; c < NC; ++c)
-        wreg[y][c] = (y < ep.ny && c0 + c < ep.ncol) ? (double)w[(int64_t)y * ep.ncol + c] : 0.0;
+        for (int c = 0; c < NC; ++c)
+          wreg[y][c] = (y < ep.ny && c0 + c < ep.ncol) ? (double)w[(int64_t)y * ep.ncol + c] : 0.0;
+      }
+    }
     expand_free_range<T, NC>(ep, f, fo, ob, c0, wreg, 0, ep.nf0, out);
   }
 }
@@ -283,27 +463,37 @@ __global__ __launch_bounds__(256) void k_couple_up_fused(ExpandPlan ep, int64_t 
   const uint32_t chunk = (ep.nf0 + nsplit - 1) / nsplit;
   for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
        g += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t rk = g % nrows_k;
+    const int64_t tr = g % nrows_k;
     const int64_t rest = g / nrows_k;
     const int64_t cg = rest % ng;
     const uint32_t zs = (uint32_t)(rest / ng);
     const int64_t c0 = cg * NC;
-    uint32_t q = (uint32_t)rk;
-    const uint32_t k3 = q % ep.kdim[3];
-    q /= ep.kdim[3];
-    const uint32_t k2 = q % ep.kdim[2];
-    q /= ep.kdim[2];
-    const uint32_t k1 = q % ep.kdim[1];
-    const uint32_t k0 = q / ep.kdim[1];
-    const int64_t ob = k0 * ep.ob_k[0] + k1 * ep.ob_k[1] + k2 * ep.ob_k[2] + k3 * ep.ob_k[3];
-    const int64_t fo = k0 * ep.fk[0] + k1 * ep.fk[1] + k2 * ep.fk[2] + k3 * ep.fk[3];
+    int64_t rk, ob, fo;
+    expand_decode(ep, (uint32_t)tr, rk, ob, fo);
     double wreg[8][NC];
 #pragma unroll
     for (int y = 0; y < 8; ++y)
 #pragma unroll
       for (int c = 0; c < NC; ++c) wreg[y][c] = 0.0;
     const T* xr = X + rk * nak;
-    for (int64_t k = 0; k < nak; ++k) {
+    // the ket row in 16-byte loads when its length allows (four values per step)
+    const int64_t nak4 = (nak % 4 == 0) ? nak : 0;
+    for (int64_t k = 0; k < nak4; k += 4) {
+      double xv[4];
+      load_group<T, 4>(xr + k, true, xv);
+#pragma unroll
+      for (int y = 0; y < 8; ++y)
+        if (y < ep.ny) {
+#pragma unroll
+          for (int c = 0; c < NC; ++c)
+            if (c0 + c < ep.ncol) {
+              const T* g = Gs + ((int64_t)y * ep.ncol + c0 + c) * nak + k;
+              wreg[y][c] += xv[0] * (double)g[0] + xv[1] * (double)g[1] + xv[2] * (double)g[2] +
+                            xv[3] * (double)g[3];
+            }
+        }
+    }
+    for (int64_t k = nak4; k < nak; ++k) {
       const double xv = (double)xr[k];
 #pragma unroll
       for (int y = 0; y < 8; ++y)
@@ -340,27 +530,42 @@ __global__ __launch_bounds__(256) void k_couple_expand_out(ExpandPlan ep, const 
     const int64_t rk = b0 * ep.wk_b[0] + b1 * ep.wk_b[1] + b2 * ep.wk_b[2] + b3 * ep.wk_b[3];
     const double* fr = f + b0 * ep.fb[0] + b1 * ep.fb[1] + b2 * ep.fb[2] + b3 * ep.fb[3];
     const T* w = W + rk * wlen + c0;
+    T* op = out + row * ep.ncol + c0;
+    const bool vec = ep.ncol % NC == 0;
     double acc[NC];
+    if (vec) {
+      load_group<T, NC>(op, true, acc);
+    } else {
 #pragma unroll
-    for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+      for (int c = 0; c < NC; ++c) acc[c] = c0 + c < ep.ncol ? (double)op[c] : 0.0;
+    }
 #pragma unroll
     for (int y = 0; y < 8; ++y)
       if (y < ep.ny) {
         const double fv = fr[y * ep.fy];
+        double wv[NC];
+        if (vec) {
+          load_group<T, NC>(w + (int64_t)y * ep.ncol, true, wv);
+        } else {
 #pragma unroll
-        for (int c = 0; c < NC; ++c)
-          if (c0 + c < ep.ncol) acc[c] += fv * (double)w[(int64_t)y * ep.ncol + c];
+          for (int c = 0; c < NC; ++c) wv[c] = c0 + c < ep.ncol ? (double)w[(int64_t)y * ep.ncol + c] : 0.0;
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[c] += fv * wv[c];
       }
-    T* op = out + row * ep.ncol + c0;
+    if (vec) {
+      store_group<T, NC>(op, true, acc);
+    } else {
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
-      if (c0 + c < ep.ncol) op[c] += (T)acc[c];
+      for (int c = 0; c < NC; ++c)
+        if (c0 + c < ep.ncol) op[c] = (T)acc[c];
+    }
   }
 }
 
 template <typename T>
 hipError_t couple_expand(const CoupleDesc& d, const double* f, const T* W, T* out_all,
-                         hipStream_t s) {
+                         hipStream_t s, int mode) {
   if (d.ny > 8) return hipErrorInvalidValue;
   int64_t nrows_k = 1, nrows_b = 1;
   for (int k = 0; k < d.ket.nslot; ++k) nrows_k *= d.ket.slot_dim[k];
@@ -379,7 +584,8 @@ hipError_t couple_expand(const CoupleDesc& d, const double* f, const T* W, T* ou
   const ExpandPlan ep = make_expand_plan(d);
   const int nc = col_group(d.ncol);
   const int64_t ng = (d.ncol + nc - 1) / nc;
-  if (nrows_k * ng >= (int64_t)1 << 18) {
+  const bool ket_par = mode == 1 || (mode == 0 && nrows_k * ng >= (int64_t)1 << 18);
+  if (ket_par) {
     unsigned grid = cdiv(nrows_k * ng, 256);
     if (grid > 65536) grid = 65536;
     CASPT2_NC_DISPATCH(nc, k_couple_expand, dim3(grid), ep, f, W, out_all)
@@ -657,7 +863,8 @@ hipError_t couple_reduce_packed(const CoupleDesc& d, const PackInfo& pk, const d
 #define CASPT2_COUPLE_INSTANCES(T)                                                                  \
   template hipError_t unpack_all<T>(const PackInfo&, const AllDesc&, const T*, T*, hipStream_t);   \
   template hipError_t pack_acc<T>(const TermDesc&, const AllDesc&, const T*, T*, hipStream_t);     \
-  template hipError_t couple_expand<T>(const CoupleDesc&, const double*, const T*, T*, hipStream_t); \
+  template hipError_t pack_ccvv<T>(int, int, int, const T*, T*, T*, hipStream_t);                   \
+  template hipError_t couple_expand<T>(const CoupleDesc&, const double*, const T*, T*, hipStream_t, int); \
   template hipError_t couple_reduce<T>(const CoupleDesc&, const double*, const T*, T*, hipStream_t);  \
   template hipError_t couple_reduce_packed<T>(const CoupleDesc&, const PackInfo&, const double*,     \
                                               const T*, T*, hipStream_t);                           \

@@ -163,6 +163,11 @@ hipError_t unpack_all(const PackInfo& p, const AllDesc& a, const T* packed, T* o
 template <typename T>
 hipError_t pack_acc(const TermDesc& d, const AllDesc& a, const T* in_all, T* packed,
                     hipStream_t s);
+// the same for the two ccvv entries at once (all-orderings [nc][nc][nv][nv]
+// rows of ncol <= 4; plus: entry (+,+), minus: entry (-,-) or null),
+// LDS-tiled so that the (a,b)-swapped images are read along rows
+template <typename T>
+hipError_t pack_ccvv(int nc, int nv, int ncol, const T* in_all, T* plus, T* minus, hipStream_t s);
 
 // Index sources of the coupling kernels: a value >= 0 is a bra slot, -1 - s
 // is summed external label s, -10 is the operator's active label y.
@@ -179,8 +184,10 @@ struct CoupleDesc {
 // expand (bra has more external slots):
 //   out_all[e_b][a] += sum_y f(.) W_all[e_k(e_b)][y * ncol + a]
 template <typename T>
+// mode: 0 by size, 1 ket-parallel (a thread per ket row loops over the free
+// bra slots), 2 output-parallel (a thread per bra row)
 hipError_t couple_expand(const CoupleDesc& d, const double* f, const T* W, T* out_all,
-                         hipStream_t s);
+                         hipStream_t s, int mode = 0);
 // up term with the active contraction fused in (G [(y, alpha_b)][alpha_k]
 // staged in LDS; X_all the ket's all-orderings rows of nak values):
 //   out_all[e_b][a] += sum_y f(.) sum_k X_all[e_k(e_b)][k] G[y ncol + a][k]
