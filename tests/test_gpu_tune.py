@@ -110,3 +110,32 @@ def test_forced_launch_choices(dev, tmp_path):
         print("forced vs rule", variant, r, flush=True)
         assert r < 1e-12
     g.close()
+
+
+def test_forced_coupling_term_forms(dev, tmp_path):
+    """Mid size with Fock couplings (Reading B): every up coupling term forced
+    to each form through the cache file -- GEMM + ket-parallel expand (0),
+    fused where the term allows it (1), GEMM + output-parallel expand (2) --
+    gives the rule-based residual within 1e-12 relative."""
+    from paper_1606_01273_amd import Caspt2
+    p = make_problem(10, 6, 120, 400, 3, seed=1, reading="B", shift=0.2)
+    g = Caspt2.from_problem(p)
+    x = torch.tensor(random_vector(g.length, 7), device=dev)
+    ref = torch.empty_like(x)
+    g.residual(0, x, ref, with_source=True)
+    cache = str(tmp_path / "tune.txt")
+    g.autotune(cache, force=True)
+    with open(cache) as fh:
+        lines = [ln.rstrip("\n").split("\t") for ln in fh if ln.strip()]
+    assert any(k.startswith("term") for k, _ in lines), "no coupling term was tuned"
+    for mode in (0, 1, 2):
+        with open(cache, "w") as fh:
+            for k, v in lines:
+                fh.write(f"{k}\t{str(mode) + ' -1 0 0 0 0 0' if k.startswith('term') else v}\n")
+        g.autotune(cache)
+        got = torch.empty_like(x)
+        g.residual(0, x, got, with_source=True)
+        r = _rel(got, ref)
+        print("forced term form", mode, r, flush=True)
+        assert r < 1e-12
+    g.close()
