@@ -32,7 +32,7 @@ import math
 import numpy as np
 import scipy.sparse as sp
 
-__all__ = ["Problem", "make_problem", "config_problem", "batch_sizes", "strings"]
+__all__ = ["Problem", "make_problem", "workload_problem", "batch_sizes", "strings"]
 
 
 def strings(norb: int, nel: int) -> np.ndarray:
@@ -275,15 +275,15 @@ def make_problem(nc: int, na: int, nv: int, naux: int, nst: int, seed: int,
 # sizes of the named workloads: (nc, na, nv, naux, nst, seed, shift); the
 # seed of the large one is the first whose denominators are all positive at
 # shift 0.2 for every state (no intruder state)
-CONFIGS = {
-    0: (4, 4, 20, 60, 1, 0, 0.0),
-    1: (10, 6, 120, 400, 3, 1, 0.2),
-    2: (30, 8, 400, 1500, 4, 8, 0.2),
+WORKLOAD_SIZES = {
+    "small": (4, 4, 20, 60, 1, 0, 0.0),
+    "mid": (10, 6, 120, 400, 3, 1, 0.2),
+    "full": (30, 8, 400, 1500, 4, 8, 0.2),
 }
 
 
-def config_problem(k: int, reading: str = "B") -> Problem:
-    nc, na, nv, naux, nst, seed, shift = CONFIGS[k]
+def workload_problem(name: str, reading: str = "B") -> Problem:
+    nc, na, nv, naux, nst, seed, shift = WORKLOAD_SIZES[name]
     return make_problem(nc, na, nv, naux, nst, seed, reading=reading, shift=shift)
 
 
