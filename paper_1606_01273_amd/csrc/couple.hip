@@ -113,9 +113,35 @@ __global__ __launch_bounds__(256) void k_unpack_all(PackInfo p, AllDesc a, int64
     const int64_t row = g / ng, c0 = (g - row * ng) * NC;
     int e[4];
     decode_all(a, row, e);
+    int64_t off[2];
+    double sg[2];
+    gather_rows(p, e, off, sg);   // once per row and column group
+    const bool full = c0 + NC <= p.rowlen;
+    double v[NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
-      if (c0 + c < p.rowlen) out[row * p.rowlen + c0 + c] = (T)gather_all(p, packed, e, c0 + c);
+    for (int c = 0; c < NC; ++c) v[c] = 0.0;
+#pragma unroll
+    for (int ent = 0; ent < 2; ++ent) {
+      if (sg[ent] == 0.0) continue;
+      const T* src = packed + off[ent] + c0;
+      double q[NC];
+      if (full && (reinterpret_cast<uintptr_t>(src) & 15) == 0) {
+        load_group<T, NC>(src, true, q);
+      } else {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) q[c] = c0 + c < p.rowlen ? (double)src[c] : 0.0;
+      }
+#pragma unroll
+      for (int c = 0; c < NC; ++c) v[c] += sg[ent] * q[c];
+    }
+    T* dst = out + row * p.rowlen + c0;
+    if (full && (reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
+      store_group<T, NC>(dst, true, v);
+    } else {
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+        if (c0 + c < p.rowlen) dst[c] = (T)v[c];
+    }
   }
 }
 
@@ -143,18 +169,34 @@ __global__ __launch_bounds__(256) void k_pack_acc(TermDesc d, AllDesc a, const T
     const int64_t row = g / ng, c0 = (g - row * ng) * NC;
     int e0[4];
     decode_orbit(d, row, e0);
+    const bool full = c0 + NC <= d.nalpha;
     double acc[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc[c] = 0.0;
     const double w = orbit_images(d, e0, [&](const int e[4], double sg) {
       const T* ip = in + encode_all(a, e) * d.nalpha + c0;
+      double q[NC];
+      if (full && (reinterpret_cast<uintptr_t>(ip) & 15) == 0) {
+        load_group<T, NC>(ip, true, q);
+      } else {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) q[c] = c0 + c < d.nalpha ? (double)ip[c] : 0.0;
+      }
+#pragma unroll
+      for (int c = 0; c < NC; ++c) acc[c] += sg * q[c];
+    });
+    T* op = out + row * d.ldo + c0;
+    if (full && (reinterpret_cast<uintptr_t>(op) & 15) == 0) {
+      double cur[NC];
+      load_group<T, NC>(op, true, cur);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) cur[c] = (double)(T)(cur[c] + (double)(T)(w * acc[c]));
+      store_group<T, NC>(op, true, cur);
+    } else {
 #pragma unroll
       for (int c = 0; c < NC; ++c)
-        if (c0 + c < d.nalpha) acc[c] += sg * (double)ip[c];
-    });
-#pragma unroll
-    for (int c = 0; c < NC; ++c)
-      if (c0 + c < d.nalpha) out[row * d.ldo + c0 + c] += (T)(w * acc[c]);
+        if (c0 + c < d.nalpha) op[c] += (T)(w * acc[c]);
+    }
   }
 }
 

@@ -95,6 +95,72 @@ __device__ inline int64_t pair_rank(int hi, int lo, bool strict) {
   return strict ? (int64_t)hi * (hi - 1) / 2 + lo : (int64_t)hi * (hi + 1) / 2 + lo;
 }
 
+// packed rows holding the all-orderings row e: for each character entry
+// present, the offset of its row (from base, in elements) and the sign
+// chi(pi_e) times the packing weight 1 / sqrt(|orbit|); sg = 0 marks an
+// entry that has no row for e (a strict character on equal slot values)
+__device__ inline void gather_rows(const PackInfo& p, const int e[4], int64_t off[2], double sg[2]) {
+  int c[4] = {e[0], e[1], e[2], e[3]};
+  int swapped[2] = {0, 0}, equal[2] = {0, 0}, ndist = 0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int s = swap_at(p, k);
+    if (s >= 0) {
+      const bool sw = c[k] < c[k + 1];
+      const int hi = sw ? c[k + 1] : c[k], lo = sw ? c[k] : c[k + 1];
+      c[k] = hi;
+      c[k + 1] = lo;
+      const int eq = hi == lo ? 1 : 0;
+      if (s == 0) {
+        swapped[0] = sw;
+        equal[0] = eq;
+      } else {
+        swapped[1] = sw;
+        equal[1] = eq;
+      }
+      ndist += 1 - eq;
+    }
+  }
+  const double w = ndist == 0 ? 1.0 : (ndist == 1 ? 0.70710678118654752440 : 0.5);
+#pragma unroll
+  for (int ent = 0; ent < 2; ++ent) {
+    off[ent] = 0;
+    sg[ent] = 0.0;
+    if (ent >= p.nent) continue;
+    bool ok = true;
+    double sgn = w;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      if (s >= p.nswap) continue;
+      if (equal[s] && p.chi[ent][s] < 0) ok = false;
+      if (swapped[s]) sgn *= p.chi[ent][s];
+    }
+    if (!ok) continue;
+    int64_t row = 0;
+    bool second = false;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (k >= p.nslot) continue;
+      if (second) {
+        second = false;
+        continue;
+      }
+      const int s = k < 3 ? swap_at(p, k) : -1;
+      const int64_t d = p.slot_dim[k];
+      if (s >= 0) {
+        const bool strict = p.chi[ent][s] < 0;
+        const int64_t cnt = strict ? d * (d - 1) / 2 : d * (d + 1) / 2;
+        row = row * cnt + pair_rank(c[k], c[k + 1], strict);
+        second = true;
+      } else {
+        row = row * d + c[k];
+      }
+    }
+    off[ent] = p.offset[ent] + row * p.rowlen;
+    sg[ent] = sgn;
+  }
+}
+
 // value of the all-orderings amplitude x[e][col] from the packed rows:
 // x[e] = sum_chi chi(pi_e) t_chi[orbit(e)] / sqrt(|orbit|)
 template <typename T>
