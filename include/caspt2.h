@@ -194,11 +194,12 @@ CASPT2_API int caspt2_layout(const caspt2_handle* h, int32_t k, int64_t* offset,
 CASPT2_API int caspt2_residual(caspt2_handle* h, int32_t L, int32_t with_source, const double* x,
                     double* sigma);
 /* Residuals for every state at once: x and sigma are [nst][length] device.
- * Without couplings between blocks the states alternate between two
- * streams of the handle (the second launching its entries in reverse
- * order), so that HBM-bound and MFMA-bound kernels of different states
- * overlap; results equal the one-state calls bit for bit.  The call returns
- * when all of them are done. */
+ * The states alternate between two streams of the handle (the second
+ * launching its entries in reverse order; with couplings between blocks the
+ * second stream uses a second set of the handle's work tensors, allocated
+ * on first use), so that kernels of different states overlap; results equal
+ * the one-state calls bit for bit.  The call returns when all of them are
+ * done. */
 CASPT2_API int caspt2_residual_all(caspt2_handle* h, int32_t with_source, const double* x, double* sigma);
 
 /* Streams caspt2_residual_all spreads the states over: 2 (default) or 1 (all

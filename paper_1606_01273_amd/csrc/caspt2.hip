@@ -221,6 +221,11 @@ struct caspt2_handle {
   DBuf wx, wsg;                                        // operator work vectors of the grouped solver
   DBuf splitk_ws;                                      // partial products of the split-K residual GEMMs
   DBuf* ws_cur = nullptr;                              // split-K workspace of the current stream (null: splitk_ws)
+  // second work set (all-orderings tensors, coupling scratch, operator work
+  // vectors), so that two streams can apply the operator with couplings of
+  // two states at once; wset selects the set the launches use
+  DBuf xall2[NBLOCK], sall2[NBLOCK], cscratch2, wx2, wsg2;
+  int wset = 0;
   // caspt2_residual_all without couplings: states on two streams of default
   // priority, their join events and the second stream's split-K workspace
   hipStream_t slane[2] = {nullptr, nullptr};
@@ -1152,6 +1157,21 @@ void setup_couplings(H& h) {
 // an index-mapped expand or reduce with the Fock block), pack once per block.
 // (T = float in the inner solver of the mixed-precision mode: the
 // all-orderings buffers, sized for doubles, then hold floats.)
+// the current work set's buffers
+DBuf& xall_of(H& h, int b) { return h.wset ? h.xall2[b] : h.xall[b]; }
+DBuf& sall_of(H& h, int b) { return h.wset ? h.sall2[b] : h.sall[b]; }
+DBuf& cscratch_of(H& h) { return h.wset ? h.cscratch2 : h.cscratch; }
+
+// allocate the second work set like the first (once)
+void ensure_work_set2(H& h) {
+  for (int b = 0; b < NBLOCK; ++b) {
+    if (h.xall[b].n && h.xall2[b].n != h.xall[b].n) h.xall2[b].alloc(h.xall[b].n);
+    if (h.sall[b].n && h.sall2[b].n != h.sall[b].n) h.sall2[b].alloc(h.sall[b].n);
+  }
+  if (h.cscratch.n && h.cscratch2.n != h.cscratch.n) h.cscratch2.alloc(h.cscratch.n);
+  if (h.splitk_ws2.n != h.splitk_ws.n) h.splitk_ws2.alloc(h.splitk_ws.n);
+}
+
 int64_t nalpha_of_block(const H& h, int set, int block) {
   for (auto& e : h.sets[set])
     if (e.block == block) return e.nalpha;
@@ -1163,9 +1183,9 @@ int64_t nalpha_of_block(const H& h, int set, int block) {
 // copies are current).  fuse: the term's own choice, or -1/0/1 to override.
 template <typename T>
 void couple_term(H& h, int set, const CoupleTerm& t, const T* x, int fuse) {
-  T* scratch = reinterpret_cast<T*>(h.cscratch.p);
-  T* xk = reinterpret_cast<T*>(h.xall[t.ket].p);
-  T* sb = reinterpret_cast<T*>(h.sall[t.bra].p);
+  T* scratch = reinterpret_cast<T*>(cscratch_of(h).p);
+  T* xk = reinterpret_cast<T*>(xall_of(h, t.ket).p);
+  T* sb = reinterpret_cast<T*>(sall_of(h, t.bra).p);
   const double* f = h.fock.p + t.f_off;
   const int64_t nab = nalpha_of_block(h, set, t.bra), nak = nalpha_of_block(h, set, t.ket);
   if (t.up && couple_up_fusable<T>(t.d, nak) && (fuse == -1 || fuse == 1)) {
@@ -1189,8 +1209,8 @@ void couple_term(H& h, int set, const CoupleTerm& t, const T* x, int fuse) {
 template <typename T>
 void apply_couplings(H& h, int set, const T* x, T* sig) {
   auto nalpha_of = [&](int block) { return nalpha_of_block(h, set, block); };
-  auto xall = [&](int b) { return reinterpret_cast<T*>(h.xall[b].p); };
-  auto sall = [&](int b) { return reinterpret_cast<T*>(h.sall[b].p); };
+  auto xall = [&](int b) { return reinterpret_cast<T*>(xall_of(h, b).p); };
+  auto sall = [&](int b) { return reinterpret_cast<T*>(sall_of(h, b).p); };
   const bool diag = h.verbose_level >= 2;   // per-stage timing on stderr
   double t_prev = diag ? (host_sync(h), wall()) : 0.0;
   auto stage = [&](const char* what) {
@@ -1201,12 +1221,12 @@ void apply_couplings(H& h, int set, const T* x, T* sig) {
     t_prev = now;
   };
   for (int b = 0; b < NBLOCK; ++b) {
-    if (!h.sall[b].p) continue;
+    if (!sall_of(h, b).p) continue;
     const int64_t na_b = nalpha_of(b);
-    if (h.xall[b].p)
+    if (xall_of(h, b).p)
       HIPCHECK(unpack_all(pack_info(h, set, b, nullptr, nullptr, na_b), all_desc(h, b), x, xall(b), h.s));
     // fill kernel, not a memset: this sequence is recorded into HIP graphs
-    HIPCHECK(vec_fill(h.sall[b].n, 0.0, h.sall[b].p, h.s));
+    HIPCHECK(vec_fill(sall_of(h, b).n, 0.0, sall_of(h, b).p, h.s));
   }
   stage("unpack");
   for (auto& t : h.couple[set]) {
@@ -1219,7 +1239,7 @@ void apply_couplings(H& h, int set, const T* x, T* sig) {
   }
   stage("last term");
   for (int b = 0; b < NBLOCK; ++b) {
-    if (!h.sall[b].p) continue;
+    if (!sall_of(h, b).p) continue;
     if (b == CCVV && nalpha_of(b) <= 4) {
       // both characters in one tiled pass
       T* plus = nullptr;
@@ -1463,6 +1483,7 @@ struct PcgSystem {
   hipGraphExec_t graph = nullptr;     // q = A p in the recurrence's precision
   hipGraphExec_t graph64 = nullptr;   // mixed: r = A t in FP64
   int id = -1;
+  int lane = 0, wset = 0;         // stream of the operator graphs and the handle's work set they use
   int status = PCG_IDLE;
   double tol = 0.0, rn = 0.0;     // mixed: FP64 tolerance and current |r|
   int maxiter = 0;
@@ -1481,26 +1502,39 @@ void ensure_work(H& h) {
     h.wx.alloc(h.length);
     h.wsg.alloc(h.length);
   }
+  if (h.wset && h.wx2.n != h.length) {
+    h.wx2.alloc(h.length);
+    h.wsg2.alloc(h.length);
+  }
 }
 
 // capture out = A in (orthonormal basis, precision T) of state L into a
 // graph recorded on stream s (the handle's own launches are redirected to s
-// while recording); the packed work vectors wx, wsg of the handle serve
-// both precisions (graphs of one handle never run concurrently)
+// while recording), using work set wset (its packed work vectors,
+// all-orderings tensors, coupling scratch and split-K workspace): the work
+// vectors serve both precisions, and graphs of one work set never run
+// concurrently (they share a stream)
 template <typename T>
-hipGraphExec_t capture_operator(H& h, int L, const T* in, T* out, hipStream_t s) {
+hipGraphExec_t capture_operator(H& h, int L, const T* in, T* out, hipStream_t s, int wset = 0) {
+  const int keep_wset = h.wset;
+  h.wset = wset;
+  if (wset) ensure_work_set2(h);
   ensure_work(h);
   const int set = set_of(h, L);
-  T* wx = reinterpret_cast<T*>(h.wx.p);
-  T* wsg = reinterpret_cast<T*>(h.wsg.p);
+  T* wx = reinterpret_cast<T*>((wset ? h.wx2 : h.wx).p);
+  T* wsg = reinterpret_cast<T*>((wset ? h.wsg2 : h.wsg).p);
   const hipStream_t keep = h.s;
   const bool prof = h.prof_on;
   const int vl = h.verbose_level;
+  DBuf* keep_ws = h.ws_cur;
   auto restore = [&]() {
     h.s = keep;
     h.prof_on = prof;
     h.verbose_level = vl;
+    h.wset = keep_wset;
+    h.ws_cur = keep_ws;
   };
+  h.ws_cur = wset ? &h.splitk_ws2 : &h.splitk_ws;
   h.s = s;
   h.prof_on = false;
   h.verbose_level = std::min(vl, 1);   // no host synchronisation while recording
@@ -1530,12 +1564,15 @@ struct PcgEngine {
   hipStream_t s = nullptr;
   bool mixed = false;
   // operator applications of different problems run concurrently on these
-  // streams (default priority; all systems of one problem share one stream,
-  // as they share its work vectors); the recurrence waits for all of them
+  // streams (default priority); all systems of one problem share one stream,
+  // as they share its work set (measured: spreading one problem's systems
+  // over its two work sets and two streams costs more in set-up than the
+  // overlap of its coupling kernels returns); the recurrence waits for all
+  // of them
   std::vector<hipStream_t> lanes;
   std::vector<hipEvent_t> lane_done;
   hipEvent_t fork = nullptr;
-  std::map<const H*, int> lane_of;
+  std::map<std::pair<const H*, int>, int> lane_of;
   int capacity = 0;
   int check_every = 4;
   std::vector<std::unique_ptr<PcgSystem>> sys;
@@ -1582,11 +1619,12 @@ struct PcgEngine {
     if (fork) (void)hipEventDestroy(fork);
     if (s) (void)hipStreamDestroy(s);
   }
-  int lane(const H* h) {
-    auto it = lane_of.find(h);
+  int lane(const H* h, int wset) {
+    const auto key = std::make_pair(h, wset);
+    auto it = lane_of.find(key);
     if (it != lane_of.end()) return it->second;
     const int k = (int)(lane_of.size() % lanes.size());
-    lane_of.emplace(h, k);
+    lane_of.emplace(key, k);
     return k;
   }
   PcgEngine(const PcgEngine&) = delete;
@@ -1624,6 +1662,8 @@ struct PcgEngine {
     S->id = (int)sys.size();
     S->tol = tol;
     S->maxiter = maxiter;
+    S->wset = 0;
+    S->lane = lane(&h, S->wset);
     caspt2_info& info = S->info;
     double dmin = INFINITY;
     build_denoms(h, L, S->D, &dmin);
@@ -1657,7 +1697,8 @@ struct PcgEngine {
       v.vec[PCG_D] = S->D.p;
       HIPCHECK(hipMemcpy(vecs.p + S->id, &v, sizeof(v), hipMemcpyHostToDevice));
       upload_scalars(S->id);
-      if (S->status == PCG_IDLE && S->n > 0) S->graph = capture_operator<double>(h, L, S->p.p, S->q.p, s);
+      if (S->status == PCG_IDLE && S->n > 0)
+        S->graph = capture_operator<double>(h, L, S->p.p, S->q.p, s, S->wset);
       if (S->n == 0 && S->status == PCG_IDLE) S->status = PCG_CONVERGED;
     } else {
       S->b.alloc(S->n);
@@ -1685,8 +1726,8 @@ struct PcgEngine {
         S->status = c.status = PCG_CONVERGED;
         upload_scalars(S->id);
       } else {
-        S->graph = capture_operator<float>(h, L, S->p32.p, S->q32.p, s);
-        S->graph64 = capture_operator<double>(h, L, S->t.p, S->r.p, s);
+        S->graph = capture_operator<float>(h, L, S->p32.p, S->q32.p, s, S->wset);
+        S->graph64 = capture_operator<double>(h, L, S->t.p, S->r.p, s, S->wset);
         arm_inner(*S);
         HIPCHECK(hipStreamSynchronize(s));
       }
@@ -1782,12 +1823,12 @@ struct PcgEngine {
     for (int id : ids) {
       PcgSystem& S = *sys[id];
       HIPCHECK(vec_axpy(S.n, S.rn, S.t32.p, S.t.p, s));   // t += |r| d
-      used[lane(S.h)] = 1;
+      used[S.lane] = 1;
     }
     HIPCHECK(hipEventRecord(fork, s));
     for (size_t l = 0; l < lanes.size(); ++l)
       if (used[l]) HIPCHECK(hipStreamWaitEvent(lanes[l], fork, 0));
-    for (int id : ids) HIPCHECK(hipGraphLaunch(sys[id]->graph64, lanes[lane(sys[id]->h)]));   // r = A t
+    for (int id : ids) HIPCHECK(hipGraphLaunch(sys[id]->graph64, lanes[sys[id]->lane]));   // r = A t
     for (size_t l = 0; l < lanes.size(); ++l)
       if (used[l]) {
         HIPCHECK(hipEventRecord(lane_done[l], lanes[l]));
@@ -1837,13 +1878,13 @@ struct PcgEngine {
     while (!active.empty()) {
       const double t_block = wall();
       std::vector<int> used(lanes.size(), 0);
-      for (int id : active) used[lane(sys[id]->h)] = 1;
+      for (int id : active) used[sys[id]->lane] = 1;
       for (int k = 0; k < check_every; ++k) {
         // fork: the lanes wait for the previous recurrence step
         HIPCHECK(hipEventRecord(fork, s));
         for (size_t l = 0; l < lanes.size(); ++l)
           if (used[l]) HIPCHECK(hipStreamWaitEvent(lanes[l], fork, 0));
-        for (int id : active) HIPCHECK(hipGraphLaunch(sys[id]->graph, lanes[lane(sys[id]->h)]));
+        for (int id : active) HIPCHECK(hipGraphLaunch(sys[id]->graph, lanes[sys[id]->lane]));
         // join
         for (size_t l = 0; l < lanes.size(); ++l)
           if (used[l]) {
@@ -2569,8 +2610,7 @@ int caspt2_residual_all(caspt2_handle* h, int32_t with_source, const double* x, 
     H& hh = *h;
     bool coupled = false;
     for (auto& cs : hh.couple) coupled = coupled || !cs.empty();
-    if (coupled || hh.residual_streams < 2) {
-      // one stream (the coupling terms share the handle's work tensors)
+    if (hh.residual_streams < 2) {
       for (int L = 0; L < hh.nst; ++L)
         residual(hh, L, x + (int64_t)L * hh.length, sigma + (int64_t)L * hh.length, with_source != 0);
       host_sync(hh);
@@ -2578,9 +2618,10 @@ int caspt2_residual_all(caspt2_handle* h, int32_t with_source, const double* x, 
     }
     // states alternate between two streams; the second runs its entries in
     // reverse order, so MFMA-bound GEMMs of one state overlap the HBM-bound
-    // streaming kernels of another.  Results are identical to the one-stream
-    // order (each state's launches and split-K workspace are its stream's
-    // own).  (Measured: splitting instead by kind -- all streaming entries on
+    // streaming kernels of another, and with couplings the latency-bound
+    // coupling kernels of two states overlap (each stream with its own work
+    // set).  Results are identical to the one-stream order (each state's
+    // launches and workspaces are its stream's own).  (Measured: splitting instead by kind -- all streaming entries on
     // one stream, all GEMM entries on the other -- is no faster at the full
     // size and slower at the mid size.)
     if (!hh.sfork) {
@@ -2591,6 +2632,7 @@ int caspt2_residual_all(caspt2_handle* h, int32_t with_source, const double* x, 
       }
     }
     if (hh.splitk_ws2.n != hh.splitk_ws.n) hh.splitk_ws2.alloc(hh.splitk_ws.n);
+    if (coupled && hh.nst > 1) ensure_work_set2(hh);   // the second stream's coupling tensors
     const hipStream_t keep = hh.s;
     HIPCHECK(hipEventRecord(hh.sfork, keep));
     for (int l = 0; l < 2; ++l) HIPCHECK(hipStreamWaitEvent(hh.slane[l], hh.sfork, 0));
@@ -2599,15 +2641,18 @@ int caspt2_residual_all(caspt2_handle* h, int32_t with_source, const double* x, 
         const int l = L & 1;
         hh.s = hh.slane[l];
         hh.ws_cur = l ? &hh.splitk_ws2 : &hh.splitk_ws;
+        hh.wset = l;
         residual(hh, L, x + (int64_t)L * hh.length, sigma + (int64_t)L * hh.length, with_source != 0, l == 1);
       }
     } catch (...) {
       hh.s = keep;
       hh.ws_cur = nullptr;
+      hh.wset = 0;
       throw;
     }
     hh.s = keep;
     hh.ws_cur = nullptr;
+    hh.wset = 0;
     for (int l = 0; l < 2; ++l) {
       HIPCHECK(hipEventRecord(hh.slane_done[l], hh.slane[l]));
       HIPCHECK(hipStreamWaitEvent(keep, hh.slane_done[l], 0));

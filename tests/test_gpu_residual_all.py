@@ -1,11 +1,11 @@
 """caspt2_residual_all (the benchmark's step): every state's residual
-(Eq. 10, with the source) of one problem in one call.  Without couplings the
-states alternate between two streams, the second in reverse entry order; the
-results must equal the one-state calls bit for bit (the same launches on the
-same data).  Checked at the mid size with and without autotuned launches, at
-the full size in the benchmark's launch configuration, and with couplings
-(one stream).  The one-state residual itself is checked against the oracle
-in the parity and stored-value tests.
+(Eq. 10, with the source) of one problem in one call.  The states alternate
+between two streams, the second in reverse entry order and, with couplings,
+on the handle's second work set; the results must equal the one-state calls
+bit for bit (the same launches on the same data).  Checked at the mid size
+with and without couplings and autotuned launches, and at the full size in
+the benchmark's launch configuration.  The one-state residual itself is
+checked against the oracle in the parity and stored-value tests.
 """
 import pytest
 
