@@ -260,8 +260,8 @@ def main():
         choices = g.autotune()
         t_tune = time.perf_counter() - t0
         tune = {k: {"splitk": c[0], "order": c[1], "grid": c[2], "tile": c[3], "kb": c[4], "occ": c[5],
-                    "plain": c[6], "rule_ms": round(c[7], 4), "tuned_ms": round(c[8], 4)}
-                for k, c in choices.items() if c[7] > 0}
+                    "plain": c[6], "breg": c[7], "rule_ms": round(c[8], 4), "tuned_ms": round(c[9], 4)}
+                for k, c in choices.items() if c[8] > 0}
         print(f"[bench] autotuned the residual launches in {t_tune:.1f} s", file=sys.stderr, flush=True)
     # the CPU oracle's set-up (in the child) overlaps the GPU set-up only:
     # wait for it, so that no host work competes with the GPU measurements

@@ -172,9 +172,10 @@ CASPT2_API int caspt2_set_precision(caspt2_handle* h, int32_t precision);
 CASPT2_API int caspt2_autotune(caspt2_handle* h, const char* cache_path, int32_t force);
 
 /* The launch choice of entry k (order of the packed layout) after
- * caspt2_autotune: choice[7] = {K splits, tile order, grid cap, tile rows,
+ * caspt2_autotune: choice[8] = {K splits, tile order, grid cap, tile rows,
  * K tile, waves per SIMD asked of the compiler, streaming MFMA kernel
- * without prefetch} (-1, -1, 0, 0, 0, 0, 0: the rule); rule_ms
+ * without prefetch, streaming MFMA kernel with its S and F operands in
+ * registers} (-1, -1, 0, 0, 0, 0, 0, 0: the rule); rule_ms
  * and tuned_ms the timings of the rule and of the choice (-1 when the choice
  * came from the cache).  host outputs, each may be NULL. */
 CASPT2_API int caspt2_tune_entry(const caspt2_handle* h, int32_t k, int32_t* choice, double* rule_ms,

@@ -93,15 +93,15 @@ class Caspt2:
 
     def autotune(self, cache_path=None, force=False):
         """Time the launch candidates of every residual entry and keep the
-        fastest; returns {entry name: (splitk, order, grid, tile, kb, occ, plain, rule_ms, tuned_ms)}."""
+        fastest; returns {entry name: (splitk, order, grid, tile, kb, occ, plain, breg, rule_ms, tuned_ms)}."""
         path = None if cache_path is None else os.fsencode(cache_path)
         _check(lib().caspt2_autotune(self._h, path, 1 if force else 0), "caspt2_autotune")
         out = {}
         for k, name in enumerate(ENTRY_NAMES):
-            c = (ctypes.c_int32 * 7)()
+            c = (ctypes.c_int32 * 8)()
             r, t = ctypes.c_double(), ctypes.c_double()
             _check(lib().caspt2_tune_entry(self._h, k, c, ctypes.byref(r), ctypes.byref(t)), "caspt2_tune_entry")
-            out[name] = (c[0], c[1], c[2], c[3], c[4], c[5], c[6], r.value, t.value)
+            out[name] = (c[0], c[1], c[2], c[3], c[4], c[5], c[6], c[7], r.value, t.value)
         return out
 
     def profile(self, enable=True):

@@ -2084,19 +2084,22 @@ std::vector<LaunchTune> tune_candidates(const std::vector<Entry>& es, size_t k, 
     const int64_t natural = e.nalpha <= 4 ? (rows + 255) / 256
                             : e.nalpha <= 16 ? (rows * e.nalpha + 255) / 256
                                              : ((rows + 15) / 16 + 3) / 4;
-    const bool mfma = e.nalpha > 16;   // the streaming MFMA kernel (with or without prefetch)
-    for (int plain : {0, 1}) {
-      if (plain && !mfma) continue;
-      if (plain) {
+    const bool mfma = e.nalpha > 16;   // the streaming MFMA kernel (plain, prefetch, prefetch + B in registers)
+    for (int form : {0, 1, 2}) {
+      if (form && !mfma) continue;
+      if (form == 2 && e.nalpha > 32) continue;
+      if (form) {
         LaunchTune t;
-        t.plain = 1;
+        t.plain = form == 1;
+        t.breg = form == 2;
         c.push_back(t);
       }
       for (unsigned g : {512u, 1024u, 2048u, 4096u, 8192u, 16384u, 32768u})
         if ((int64_t)g < natural) {
           LaunchTune t;
           t.grid = g;
-          t.plain = plain;
+          t.plain = form == 1;
+          t.breg = form == 2;
           c.push_back(t);
         }
     }
@@ -2153,13 +2156,14 @@ void load_tune_file(const char* path) {
     if (!tab) continue;
     *tab = 0;
     LaunchTune t;
-    const int got = std::sscanf(tab + 1, "%d %d %u %d %d %d %d", &t.splitk, &t.order, &t.grid, &t.tile, &t.kb,
-                                &t.occ, &t.plain);
+    const int got = std::sscanf(tab + 1, "%d %d %u %d %d %d %d %d", &t.splitk, &t.order, &t.grid, &t.tile, &t.kb,
+                                &t.occ, &t.plain, &t.breg);
     if (got < 3) continue;
     if (got < 4) t.tile = 0;
     if (got < 5) t.kb = 0;
     if (got < 6) t.occ = 0;
     if (got < 7) t.plain = 0;
+    if (got < 8) t.breg = 0;
     g_tune_cache[line] = t;
   }
   std::fclose(f);
@@ -2171,8 +2175,8 @@ void save_tune_file(const char* path) {
   FILE* f = std::fopen(tmp.c_str(), "w");
   if (!f) throw DevError(CASPT2_E_ARG, "cannot write the tuning cache file");
   for (auto& kv : g_tune_cache)
-    std::fprintf(f, "%s\t%d %d %u %d %d %d %d\n", kv.first.c_str(), kv.second.splitk, kv.second.order,
-                 kv.second.grid, kv.second.tile, kv.second.kb, kv.second.occ, kv.second.plain);
+    std::fprintf(f, "%s\t%d %d %u %d %d %d %d %d\n", kv.first.c_str(), kv.second.splitk, kv.second.order,
+                 kv.second.grid, kv.second.tile, kv.second.kb, kv.second.occ, kv.second.plain, kv.second.breg);
   std::fclose(f);
   if (std::rename(tmp.c_str(), path) != 0) throw DevError(CASPT2_E_ARG, "cannot replace the tuning cache file");
 }
@@ -2226,9 +2230,10 @@ void autotune(H& h, const char* cache_path, bool force) {
           g_tune_cache[key] = pick;
           if (h.verbose)
             std::fprintf(stderr,
-                         "[caspt2] tune %-28s splitk %d order %d grid %u tile %d kb %d occ %d plain %d: %.4f ms (rule %.4f ms)\n",
-                         key.c_str(), pick.splitk, pick.order, pick.grid, pick.tile, pick.kb, pick.occ, pick.plain, best,
-                         rule);
+                         "[caspt2] tune %-28s splitk %d order %d grid %u tile %d kb %d occ %d plain %d breg %d: "
+                         "%.4f ms (rule %.4f ms)\n",
+                         key.c_str(), pick.splitk, pick.order, pick.grid, pick.tile, pick.kb, pick.occ, pick.plain,
+                         pick.breg, best, rule);
         }
         if (pair) es[k + 1].tune = e.tune;
         if (pair) ++k;
@@ -2542,6 +2547,7 @@ int caspt2_tune_entry(const caspt2_handle* h, int32_t k, int32_t* choice, double
     choice[4] = e.tune.kb;
     choice[5] = e.tune.occ;
     choice[6] = e.tune.plain;
+    choice[7] = e.tune.breg;
   }
   if (rule_ms) *rule_ms = e.tune_rule_ms;
   if (tuned_ms) *tuned_ms = e.tune_best_ms;

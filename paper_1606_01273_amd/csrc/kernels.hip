@@ -393,8 +393,10 @@ __global__ __launch_bounds__(256) void k_residual_small(int64_t M, int N, const 
 // PIPE: the wave's next 16-row tile of X is loaded into registers while the
 // current one is multiplied, and the current tile's V and row energies are
 // requested before the MFMAs, so HBM latency overlaps the matrix work (the
-// plain form waits for its loads at every tile).
-template <int K16, bool PIPE>
+// plain form waits for its loads at every tile).  BREG: each lane keeps its
+// MFMA B operands of S and F (the same for every tile) in registers instead
+// of reading them from LDS per tile (fewer LDS reads, more registers).
+template <int K16, bool PIPE, bool BREG = false>
 __global__ __launch_bounds__(256) void k_residual_mfma(int64_t M, int K, const double* __restrict__ X,
                                                        const double* __restrict__ S,
                                                        const double* __restrict__ F,
@@ -417,6 +419,17 @@ __global__ __launch_bounds__(256) void k_residual_mfma(int64_t M, int K, const d
   const int64_t ntiles = (M + 15) / 16;
   const int64_t stride = (int64_t)gridDim.x * 4;
   const int64_t limit = M * (int64_t)K;
+  constexpr int NKS = K16 / 4;
+  double bsr[BREG ? NCT : 1][BREG ? NKS : 1], bfr[BREG ? NCT : 1][BREG ? NKS : 1];
+  if (BREG) {
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+      for (int ks = 0; ks < NKS; ++ks) {
+        bsr[ct][ks] = Ss[ks * 4 + (lane >> 4)][ct * 16 + (lane & 15)];
+        bfr[ct][ks] = Fs[ks * 4 + (lane >> 4)][ct * 16 + (lane & 15)];
+      }
+  }
   double xr[XPL];
   auto load_x = [&](int64_t tile) {   // 16 rows (contiguous 16*K doubles) of X
     const int64_t base = tile * 16 * K;
@@ -462,8 +475,8 @@ __global__ __launch_bounds__(256) void k_residual_mfma(int64_t M, int K, const d
 #pragma unroll
       for (int k0 = 0; k0 < K16; k0 += 4) {
         const double a = Xs[w][lane & 15][k0 + (lane >> 4)];
-        const double bs = Ss[k0 + (lane >> 4)][ct * 16 + (lane & 15)];
-        const double bf = Fs[k0 + (lane >> 4)][ct * 16 + (lane & 15)];
+        const double bs = BREG ? bsr[BREG ? ct : 0][BREG ? k0 / 4 : 0] : Ss[k0 + (lane >> 4)][ct * 16 + (lane & 15)];
+        const double bf = BREG ? bfr[BREG ? ct : 0][BREG ? k0 / 4 : 0] : Fs[k0 + (lane >> 4)][ct * 16 + (lane & 15)];
         as = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bs, as, 0, 0, 0);
         af = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bf, af, 0, 0, 0);
       }
@@ -497,7 +510,10 @@ hipError_t residual_small_f64(int64_t M, int64_t N, const double* X, const doubl
       hipLaunchKernelGGL((k_residual_mfma<K16_, true>), dim3(grid), dim3(256), 0, s, M, (int)N, X, S, F, d, \
                          dshift, V, C);                                                                 \
   } while (0)
-    if (N <= 32)
+    if (N <= 32 && tune.breg)   // B operands in registers (K16 = 32 only: 32 doubles per lane)
+      hipLaunchKernelGGL((k_residual_mfma<32, true, true>), dim3(grid), dim3(256), 0, s, M, (int)N, X, S, F, d,
+                         dshift, V, C);
+    else if (N <= 32)
       CASPT2_RMFMA(32);
     else if (N <= 48)
       CASPT2_RMFMA(48);

@@ -33,6 +33,7 @@ struct LaunchTune {
   int occ = 0;         // residual GEMM without K splits: waves per SIMD asked of
                        // the compiler (1, 2 with 128-row tiles, 3 with 64-row tiles)
   int plain = 0;       // streaming MFMA residual: 1 = without the X prefetch
+  int breg = 0;        // streaming MFMA residual (nalpha <= 32): 1 = S, F operands in registers
 };
 
 // Residual of one packed entry on MFMA:

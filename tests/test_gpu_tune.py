@@ -48,9 +48,9 @@ def test_tuned_residual_matches_oracle_and_rule(dev, tmp_path):
     cache = str(tmp_path / "tune.txt")
     choices = g.autotune(cache, force=True)   # time every entry even if this process cached the shape
     print("choices", choices, flush=True)
-    timed = [c for c in choices.values() if c[7] > 0]
+    timed = [c for c in choices.values() if c[8] > 0]
     assert timed, "no entry was timed"
-    for name, (ns, order, grid, tile, kb, occ, plain, rule_ms, tuned_ms) in choices.items():
+    for name, (ns, order, grid, tile, kb, occ, plain, breg, rule_ms, tuned_ms) in choices.items():
         if rule_ms > 0:
             assert tuned_ms <= rule_ms * (1 + 1e-9), name
     got = torch.empty_like(x)
@@ -68,12 +68,12 @@ def test_tuned_residual_matches_oracle_and_rule(dev, tmp_path):
     with open(cache) as fh:
         lines = [ln.rstrip("\n").split("\t") for ln in fh if ln.strip()]
     assert len(lines) >= len(timed)
-    assert all(len(ln) == 2 and len(ln[1].split()) == 7 for ln in lines)
+    assert all(len(ln) == 2 and len(ln[1].split()) == 8 for ln in lines)
     g2 = Caspt2.from_problem(p)
     c2 = g2.autotune(cache)
     for name in choices:
-        assert c2[name][:7] == choices[name][:7], name
-        assert c2[name][7] == -1.0 or choices[name][7] == -1.0, name
+        assert c2[name][:8] == choices[name][:8], name
+        assert c2[name][8] == -1.0 or choices[name][8] == -1.0, name
     g2.close()
     g.close()
 
@@ -84,8 +84,8 @@ def test_forced_launch_choices(dev, tmp_path):
     XCD-grouped order, K split 1 with the plain order and 128-row tiles,
     128-row tiles with K tile 32 and the XCD-grouped order, 64-row tiles with
     K tile 32, 64- and 128-row tiles at one wave per SIMD on the GEMM
-    entries; grid caps of 512 to 16384, with and without the X prefetch, on
-    the streaming entries."""
+    entries; grid caps of 512 to 16384, with and without the X prefetch and
+    with the S, F operands in registers, on the streaming entries."""
     from paper_1606_01273_amd import Caspt2
     p = make_problem(10, 6, 120, 400, 3, seed=1, reading="A", shift=0.2)
     g = Caspt2.from_problem(p)
@@ -96,9 +96,9 @@ def test_forced_launch_choices(dev, tmp_path):
     g.autotune(cache)
     with open(cache) as fh:
         keys = [ln.split("\t")[0] for ln in fh if ln.strip()]
-    for variant in (("4 2 0 64 16 0 0", "-1 -1 512 0 0 0 0"), ("1 1 0 128 16 0 0", "-1 -1 2048 0 0 0 1"),
-                    ("1 2 0 128 32 0 0", "-1 -1 1024 0 0 0 0"), ("1 -1 0 64 32 0 0", "-1 -1 4096 0 0 0 1"),
-                    ("1 2 0 64 16 1 0", "-1 -1 8192 0 0 0 0"), ("1 -1 0 128 16 1 0", "-1 -1 16384 0 0 0 1")):
+    for variant in (("4 2 0 64 16 0 0 0", "-1 -1 512 0 0 0 0 0"), ("1 1 0 128 16 0 0 0", "-1 -1 2048 0 0 0 1 0"),
+                    ("1 2 0 128 32 0 0 0", "-1 -1 1024 0 0 0 0 1"), ("1 -1 0 64 32 0 0 0", "-1 -1 4096 0 0 0 1 0"),
+                    ("1 2 0 64 16 1 0 0", "-1 -1 8192 0 0 0 0 1"), ("1 -1 0 128 16 1 0 0", "-1 -1 16384 0 0 0 1 0")):
         with open(cache, "w") as fh:
             for k in keys:
                 fh.write(f"{k}\t{variant[0] if k.startswith('gemm') else variant[1]}\n")
@@ -131,7 +131,7 @@ def test_forced_coupling_term_forms(dev, tmp_path):
     for mode in (0, 1, 2):
         with open(cache, "w") as fh:
             for k, v in lines:
-                fh.write(f"{k}\t{str(mode) + ' -1 0 0 0 0 0' if k.startswith('term') else v}\n")
+                fh.write(f"{k}\t{str(mode) + ' -1 0 0 0 0 0 0' if k.startswith('term') else v}\n")
         g.autotune(cache)
         got = torch.empty_like(x)
         g.residual(0, x, got, with_source=True)
