@@ -1,6 +1,7 @@
 // FP32 GEMMs for the inner solver of the mixed-precision mode: the basis
-// transforms, the dense residual of the blocks with a wide active index, and
-// the GEMMs of the Fock couplings.  SIMT FMA on 64 x 64 output tiles, K staged
+// transforms and the GEMMs of the Fock couplings (SIMT), and the dense
+// residual of the blocks with a wide active index (MFMA, below).  The SIMT
+// kernel works on 64 x 64 output tiles, K staged
 // through LDS in steps of 16; each of the 256 threads owns a 4 x 4 sub-tile
 // strided by 16 in both directions, so LDS reads are broadcasts or
 // conflict-free.
@@ -146,6 +147,105 @@ hipError_t gemm_f32(bool b_is_nk, int64_t M, int64_t N, int64_t K, float alpha, 
   return hipGetLastError();
 }
 
+// Dense residual of one entry in FP32 on MFMA (v_mfma_f32_16x16x4f32, FP32
+// accumulation): C = V + (d + dshift) X S + X F with X [M][K], S, F [K][N].
+// 64 x 64 output tiles, four waves of 32 x 32 (2 x 2 blocks of 16 x 16), K
+// in steps of 16 through LDS with the next step's loads in registers while
+// the current one is multiplied.  Operand layout of the instruction (lane l):
+// A[i][k]: i = l % 16, k = l / 16; B[k][j]: j = l % 16, k = l / 16; the four
+// results of a lane: D[4 (l / 16) + v][l % 16].
+namespace {
+typedef float f4 __attribute__((ext_vector_type(4)));
+constexpr int MK = 16, MLD = MK + 1;
+__global__ __launch_bounds__(256) void k_residual_mfma_f32(int64_t M, int64_t N, int64_t K,
+                                                           const float* __restrict__ X, int64_t ldx,
+                                                           const float* __restrict__ S,
+                                                           const float* __restrict__ F,
+                                                           const float* __restrict__ d, float dshift,
+                                                           const float* __restrict__ V, int64_t ldv,
+                                                           float* __restrict__ C, int64_t ldc, int m_on_x) {
+  __shared__ float As[64][MLD];
+  __shared__ float Bs[64][MLD];
+  __shared__ float B2s[64][MLD];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int64_t m0 = (int64_t)(m_on_x ? blockIdx.x : blockIdx.y) * 64;
+  const int64_t n0 = (int64_t)(m_on_x ? blockIdx.y : blockIdx.x) * 64;
+  f4 acc[2][2], acc2[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+      acc2[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+  // per thread: A row r = tid / 4, k = 4 (tid % 4) .. + 3; B row k = tid / 16,
+  // n = 4 (tid % 16) .. + 3
+  const int ra = tid >> 2, ca = (tid & 3) * 4;
+  const int kb = tid >> 4, cb = (tid & 15) * 4;
+  const bool a_ok = m0 + ra < M;
+  const float* pA = X + (a_ok ? m0 + ra : 0) * ldx + ca;
+  float xa[4], xs[4], xf[4];
+  auto load = [&](int64_t k0) {
+    const bool full = k0 + MK <= K;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) xa[u] = (a_ok && (full || k0 + ca + u < K)) ? pA[k0 + u] : 0.f;
+    const bool krow = full || k0 + kb < K;
+    const int64_t off = (k0 + kb) * N + n0 + cb;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const bool in = krow && n0 + cb + u < N;
+      xs[u] = in ? S[off + u] : 0.f;
+      xf[u] = in ? F[off + u] : 0.f;
+    }
+  };
+  if (K > 0) load(0);
+  for (int64_t k0 = 0; k0 < K; k0 += MK) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      As[ra][ca + u] = xa[u];
+      Bs[cb + u][kb] = xs[u];
+      B2s[cb + u][kb] = xf[u];
+    }
+    __syncthreads();
+    if (k0 + MK < K) load(k0 + MK);
+#pragma unroll
+    for (int kk = 0; kk < MK; kk += 4) {
+      float a[2], b[2], b2[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = As[wm * 32 + i * 16 + (lane & 15)][kk + (lane >> 4)];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        b[j] = Bs[wn * 32 + j * 16 + (lane & 15)][kk + (lane >> 4)];
+        b2[j] = B2s[wn * 32 + j * 16 + (lane & 15)][kk + (lane >> 4)];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+          acc2[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b2[j], acc2[i][j], 0, 0, 0);
+        }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t gm = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + v;
+        const int64_t gn = n0 + wn * 32 + j * 16 + (lane & 15);
+        if (gm < M && gn < N) {
+          float val = (d[gm] + dshift) * acc[i][j][v] + acc2[i][j][v];
+          if (V) val += V[gm * ldv + gn];
+          C[gm * ldc + gn] = val;
+        }
+      }
+}
+}  // namespace
+
 hipError_t residual_gemm_f32(int64_t M, int64_t N, int64_t K, const float* X, int64_t ldx,
                              const float* S, const float* F, const float* d, float dshift,
                              const float* V, int64_t ldv, float* C, int64_t ldc, hipStream_t s) {
@@ -153,8 +253,8 @@ hipError_t residual_gemm_f32(int64_t M, int64_t N, int64_t K, const float* X, in
   dim3 grid;
   int mx;
   if (!tile_grid(M, N, 1, TM, TN, &grid, &mx)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_gemm_f32<false, true>), grid, dim3(256), 0, s, M, N, K, 1.f, X, ldx,
-                     (int64_t)0, S, N, (int64_t)0, F, 0.f, C, ldc, (int64_t)0, d, dshift, V, ldv, mx);
+  hipLaunchKernelGGL(k_residual_mfma_f32, grid, dim3(256), 0, s, M, N, K, X, ldx, S, F, d, dshift, V, ldv, C,
+                     ldc, mx);
   return hipGetLastError();
 }
 

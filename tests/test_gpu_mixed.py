@@ -50,6 +50,37 @@ def test_debug_gemm_f32_matches_numpy(dev):
         assert excess.max() <= 0.0, f"gemm_f32 {(M, N, K, nk)} exceeds the rounding bound"
 
 
+@pytest.mark.parametrize("reading", ["A", "B"])
+def test_residual_f32_matches_oracle(dev, reading):
+    """The FP32 residual of the inner solver against the FP64 oracle, without
+    the source term.  Six active orbitals and two states: the entries with 72,
+    144 and 432 internal functions take the dense FP32 MFMA path, with 1 to
+    2485 rows (several tiles and ragged tails in both dimensions).
+
+    Bar: the FP32 path chains three products (basis transform, dense block,
+    back transform) of length at most 2 * 432; each adds at most n * 2^-24
+    relative to the magnitudes it sums, so ||sigma32 - sigma|| / ||sigma||
+    stays below 3 * 864 * 2^-24 = 1.6e-4 for the well-conditioned random x
+    used here; a wrong operand or output layout gives O(1)."""
+    from oracle.ic import Caspt2Oracle
+    from paper_1606_01273_amd import MIXED, Caspt2, lib
+    p = make_problem(2, 6, 70, 100, 2, seed=7, reading=reading, shift=0.1)
+    o = Caspt2Oracle(p, "MSMR", xms=True)
+    g = Caspt2.from_problem(p, precision=MIXED)
+    assert g.length == o.length
+    g.xms_rotate()
+    rng = np.random.default_rng(5)
+    for L in range(p.nst):
+        x = rng.standard_normal(g.length)
+        tx = torch.tensor(x, dtype=torch.float32, device=dev)
+        ts = torch.empty_like(tx)
+        assert lib().caspt2_debug_residual_f32(g._h, L, tx.data_ptr(), ts.data_ptr()) == 0
+        ref = o.residual(L, x, with_source=False)
+        got = ts.cpu().numpy().astype(np.float64)
+        _ok(np.linalg.norm(got - ref) / np.linalg.norm(ref), 1.6e-4, f"FP32 residual L {L}")
+    g.close()
+
+
 CASES = [
     ((2, 3, 3, 16, 3), 7, "A", "MSMR", True, 0.15),
     ((5, 4, 30, 70, 2), 8, "A", "MSMR", True, 0.2),
