@@ -20,11 +20,16 @@
  * vectors must be eigenvectors of the active Hamiltonian with energies eref
  * (only eref enters H^ref, Eq. 6).
  *
- * Fock operator (Eqs. 11-12): f is symmetric; its closed-closed and
- * virtual-virtual blocks must be diagonal (semicanonical orbitals); the
- * active block and the closed-active, active-virtual and closed-virtual
- * blocks are general.  Normal ordering with respect to the closed vacuum is
- * taken as {E_ij}_C = E_ij - 2 delta_ij.
+ * Fock operator (Eqs. 11-12): f is symmetric and otherwise general.  Its
+ * diagonal enters through the energies of the external orbital tuples (and
+ * the diagonal preconditioner); the closed-active, active-virtual and
+ * closed-virtual blocks couple different excitation blocks; off-diagonal
+ * closed-closed and virtual-virtual elements (orbitals that are not
+ * semicanonical) couple each block with itself.  Both kinds of coupling are
+ * applied by the same index-mapped kernels, so non-semicanonical orbitals
+ * cost extra operator time (a sum over one closed or virtual index per
+ * element).  Normal ordering with respect to the closed vacuum is taken as
+ * {E_ij}_C = E_ij - 2 delta_ij.
  *
  * Hamiltonian: hcore = h^c, the one-electron operator dressed by the closed
  * orbitals, h^c_xy = h_xy + sum_i [2 (xy|ii) - (xi|iy)]; dfB[Q][p][q] with
@@ -145,7 +150,7 @@ typedef struct caspt2_handle caspt2_handle;
  * inputs_on_device: 0 if the inputs are host pointers, 1 if device.
  * stream: a hipStream_t (NULL = default stream).
  * Errors: E_ARG (dims <= 0 where forbidden, nst > ndet, non-finite inputs,
- * |f - f^T| > 1e-12, non-diagonal closed or virtual Fock block), E_NOMEM,
+ * |f - f^T| > 1e-12), E_NOMEM,
  * E_DEVICE, E_INDEFINITE (a denominator <= 0 for some state). */
 CASPT2_API int caspt2_create(const caspt2_dims* dims, const caspt2_inputs* inputs, int inputs_on_device,
                   void* stream, caspt2_handle** out);

@@ -944,13 +944,25 @@ void setup_couplings(H& h) {
         }
     if (nz) comps.push_back(pr);
   }
+  // off-diagonal closed-closed and virtual-virtual Fock elements (orbitals not
+  // canonical in those spaces): terms of each block with itself; the
+  // diagonal stays in the row energies, so the device copy of f has it zeroed
+  for (char c : {CLO, VIR}) {
+    bool nz = false;
+    for (int x = 0; x < dim(c) && !nz; ++x)
+      for (int y = 0; y < dim(c); ++y)
+        if (x != y && h.h_fock[(off(c) + x) * h.nmo + off(c) + y] != 0.0) {
+          nz = true;
+          break;
+        }
+    if (nz) comps.push_back({c, c});
+  }
   if (comps.empty()) return;
   bool used[NBLOCK] = {false, false, false, false, false, false, false, false};
   const auto& BL = blocks();
   int64_t scratch = 0;
   for (int bb = 0; bb < NBLOCK; ++bb)
     for (int kb = 0; kb < NBLOCK; ++kb) {
-      if (bb == kb) continue;
       const Block& B1 = BL[bb];
       const Block& B2 = BL[kb];
       const int nty_b = (int)B1.types.size(), nty_k = (int)B2.types.size();
@@ -959,6 +971,9 @@ void setup_couplings(H& h) {
       const int64_t nset_b = (ss ? 1 : nst) * nty_b * ntup_b, nset_k = (ss ? 1 : nst) * nty_k * ntup_k;
       if (nset_b == 0 || nset_k == 0) continue;
       for (auto comp : comps) {
+        // a Fock element within one orbital space keeps every block in
+        // itself; one between spaces always changes the block
+        if ((comp.first == comp.second) != (bb == kb)) continue;
         const OpString op = E("x_o", comp.first, "y_o", comp.second, "so");
         const int ny = (comp.first == ACT || comp.second == ACT) ? h.na : 1;
         std::map<std::string, PairAcc> acc;
@@ -966,6 +981,13 @@ void setup_couplings(H& h) {
           for (int tk = 0; tk < nty_k; ++tk) {
             auto pairings = matrix_element(suffixed(B1.types[tb], "_b"), op, suffixed(B2.types[tk], "_k"));
             for (auto& P : pairings) {
+              // the operator contracted with itself (closed x = y) weighs
+              // the trace of the off-diagonal part of f_cc: zero
+              bool self = false;
+              for (const auto& pr : P.pairs)
+                if ((pr.first == "x_o" && pr.second == "y_o") || (pr.first == "y_o" && pr.second == "x_o"))
+                  self = true;
+              if (self) continue;
               const std::string key = pair_key(P);
               auto it = acc.find(key);
               if (it == acc.end()) {
@@ -1042,7 +1064,7 @@ void setup_couplings(H& h) {
               const char sp = which == 0 ? comp.first : comp.second;
               int src;
               if (sp == ACT) src = -10;
-              else if (up) src = bra_slot(partner(lab));
+              else if (up || bra_slot(partner(lab)) >= 0) src = bra_slot(partner(lab));
               else src = -1 - sum_of.at(partner(lab));
               (which == 0 ? t.d.fx_src : t.d.fy_src) = src;
             }
@@ -2392,20 +2414,13 @@ int caspt2_create(const caspt2_dims* dims, const caspt2_inputs* in, int on_devic
     validate(dims, h.h_fock, hc, h.nmo, h.nc, h.na);
     for (double v : h.eref)
       if (!std::isfinite(v)) throw DevError(CASPT2_E_ARG, "non-finite eref");
-    // closed-closed and virtual-virtual blocks must be diagonal
-    bool offblock = false;
-    for (int i = 0; i < h.nmo; ++i)
-      for (int j = 0; j < h.nmo; ++j) {
-        if (i == j) continue;
-        auto cls = [&](int p) { return p < h.nc ? 0 : p < h.nc + h.na ? 1 : 2; };
-        const double v = h.h_fock[i * h.nmo + j];
-        if (cls(i) == cls(j) && cls(i) != 1 && std::fabs(v) > 1e-12)
-          throw DevError(CASPT2_E_NOTIMPL, "non-diagonal closed or virtual Fock block");
-        if (cls(i) != cls(j) && v != 0.0) offblock = true;
-      }
-    (void)offblock;
+    // the diagonal of f enters through the row energies; the coupling terms
+    // read the device copy, whose closed and virtual diagonals are zero
     h.h_eps.resize(h.nmo);
     for (int i = 0; i < h.nmo; ++i) h.h_eps[i] = h.h_fock[i * h.nmo + i];
+    std::vector<double> fdev(h.h_fock);
+    for (int i = 0; i < h.nmo; ++i)
+      if (i < h.nc || i >= h.nc + h.na) fdev[(size_t)i * h.nmo + i] = 0.0;
     // device copies
     const hipMemcpyKind k2 = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     h.fock.alloc(n2);
@@ -2413,7 +2428,7 @@ int caspt2_create(const caspt2_dims* dims, const caspt2_inputs* in, int on_devic
     h.B.alloc((int64_t)h.naux * n2);
     h.ci_raw.alloc((int64_t)h.nst * h.ndet);
     h.ci.alloc((int64_t)h.nst * h.ndet);
-    HIPCHECK(hipMemcpyAsync(h.fock.p, h.h_fock.data(), n2 * sizeof(double), hipMemcpyHostToDevice, h.s));
+    HIPCHECK(hipMemcpyAsync(h.fock.p, fdev.data(), n2 * sizeof(double), hipMemcpyHostToDevice, h.s));
     HIPCHECK(hipMemcpyAsync(h.hcore.p, hc.data(), n2 * sizeof(double), hipMemcpyHostToDevice, h.s));
     HIPCHECK(hipMemcpyAsync(h.B.p, in->dfB, (size_t)h.naux * n2 * sizeof(double), k2, h.s));
     HIPCHECK(hipMemcpyAsync(h.ci_raw.p, in->ci, (size_t)h.nst * h.ndet * sizeof(double), k2, h.s));

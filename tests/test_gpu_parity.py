@@ -109,6 +109,12 @@ CASES = [
     ((5, 4, 30, 70, 2), 8, "B", "MSMR", True, 0.2),
     ((3, 4, 10, 40, 2), 7, "B", "SSSR", True, 0.2),
     ((3, 3, 9, 30, 3), 7, "B", "MSMR", False, 0.1),
+    # orbitals rotated inside the closed and the virtual space: off-diagonal
+    # f_cc and f_vv couple every block with itself
+    ((2, 2, 3, 14, 2), 5, "C", "MSMR", True, 0.15),
+    ((3, 3, 7, 26, 2), 9, "C", "MSMR", True, 0.2),
+    ((3, 4, 10, 40, 2), 7, "C", "SSSR", True, 0.2),
+    ((5, 4, 30, 70, 2), 8, "C", "MSMR", True, 0.2),
 ]
 
 
@@ -175,7 +181,7 @@ def test_full_path_matches_oracle(dev, dims, seed, reading, scheme, xms, shift):
 
 
 def test_error_paths(dev):
-    from paper_1606_01273_amd import Caspt2, Caspt2Error, E_ARG, E_NOTIMPL
+    from paper_1606_01273_amd import Caspt2, Caspt2Error, E_ARG
     p = make_problem(2, 2, 3, 12, 1, seed=1, reading="A", shift=0.0)
     bad = p.fock.copy()
     bad[0, 1] += 1e-6
@@ -187,3 +193,21 @@ def test_error_paths(dev):
     with pytest.raises(Caspt2Error) as ex:
         Caspt2.from_problem(p.replace(hcore=nan))
     assert ex.value.code == E_ARG
+
+
+def test_closed_virtual_rotation_invariance(dev):
+    """E^MS does not depend on the orbital basis chosen inside the closed and
+    inside the virtual space (the functions of Eq. 8 span the same space and
+    Eq. 10 is covariant): the library with rotated orbitals against the
+    library with semicanonical ones, same problem otherwise."""
+    from paper_1606_01273_amd import Caspt2
+    e = {}
+    for reading in ("B", "C"):
+        p = make_problem(5, 4, 30, 70, 2, seed=8, reading=reading, shift=0.2)
+        g = Caspt2.from_problem(p)
+        rc, info = g.solve_amplitudes(tol=1e-11, maxiter=400)
+        assert rc == 0, f"Reading {reading}: amplitude solve status {rc}"
+        e[reading] = g.heff()[1]
+        print(f"  Reading {reading}: iterations {[i['iters'] for i in info]}", flush=True)
+        g.close()
+    _ok(np.abs(e["B"] - e["C"]).max(), 1e-10, "E_MS rotated vs semicanonical")
