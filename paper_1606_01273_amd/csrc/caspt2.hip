@@ -117,6 +117,9 @@ struct CoupleTerm {
   FBuf G32;              // FP32 copy (mixed precision)
   int fuse = -1;         // up terms (autotuned): -1 rule (fused where possible), 0 GEMM + ket-parallel
                          // expand, 1 fused, 2 GEMM + output-parallel expand
+  int sg_slot = -1;      // down term of a block with itself that applies f along one bra slot of the
+                         // ket tensor: that slot (batched MFMA GEMM in FP64), else -1
+  bool sg_perm = false;  // ... read from the block's slot-permuted copy of x
 };
 
 // element-type selection of the per-entry and per-term operands
@@ -234,6 +237,8 @@ struct caspt2_handle {
   DBuf splitk_ws2;
   int residual_streams = 2;                            // 1: caspt2_residual_all on the handle's stream only
   DBuf xall[NBLOCK], sall[NBLOCK];                      // all-orderings x and sigma per block
+  DBuf xperm[NBLOCK], xperm2[NBLOCK];                   // slot-permuted all-orderings x (both work sets)
+  int xperm_p[NBLOCK][4] = {};                          // its slot map: copy[e] = x[e[p[0]], e[p[1]], ..]
   bool direct[NBLOCK] = {};                            // ket read from packed rows (no all-orderings x)
   bool have_mixed = false;                             // FP32 operand copies made
   bool prof_on = false;
@@ -923,6 +928,45 @@ PackInfo pack_info(const H& h, int set, int block, const double* base, const std
   return p;
 }
 
+// A down term of a block with itself whose one summed label takes the place
+// of bra slot sb, the other ket slots being fed one to one by the remaining
+// bra slots, and whose Fock element is f(bra slot sb, summed label): it
+// applies f along slot sb of the ket tensor read with its slots permuted,
+// perm[l] being the bra slot that feeds ket slot l (sb for the summed one).
+bool slot_form(const int* ks, int fx, int fy, int nslot, int* sb_out, int* perm) {
+  int sb;
+  if (fx >= 0 && fy == -1) sb = fx;
+  else if (fy >= 0 && fx == -1) sb = fy;
+  else return false;
+  if (sb >= nslot) return false;
+  bool fed[4] = {false, false, false, false};
+  int nsum = 0;
+  for (int l = 0; l < nslot; ++l) {
+    const int v = ks[l];
+    if (v == -1) {
+      ++nsum;
+      perm[l] = sb;
+    } else if (v >= 0 && v < nslot && v != sb && !fed[v]) {
+      fed[v] = true;
+      perm[l] = v;
+    } else {
+      return false;
+    }
+  }
+  for (int l = nslot; l < 4; ++l) perm[l] = l;
+  *sb_out = sb;
+  return nsum == 1;
+}
+
+// the slot-permuted tensor equals x itself: the identity, or for ccvv the
+// joint exchange (i, a) <-> (j, b)
+bool perm_trivial(int block, const int* perm, int nslot) {
+  bool id = true;
+  for (int l = 0; l < nslot; ++l) id = id && perm[l] == l;
+  if (id) return true;
+  return block == CCVV && nslot == 4 && perm[0] == 1 && perm[1] == 0 && perm[2] == 3 && perm[3] == 2;
+}
+
 void setup_couplings(H& h) {
   const bool ss = h.d.scheme == CASPT2_SSSR;
   const int nst = h.nst;
@@ -1113,25 +1157,46 @@ void setup_couplings(H& h) {
     std::map<std::vector<int64_t>, size_t> seen;
     for (auto& t : cs) {
       int* ks = t.d.ket_src;
-      if (!t.up && t.ket == CCVV && t.d.ket.nslot == 4) {
-        const int alt[4] = {ks[1], ks[0], ks[3], ks[2]};
-        if (std::lexicographical_compare(alt, alt + 4, ks, ks + 4)) std::copy(alt, alt + 4, ks);
-      }
-      // an up term into the ccvv bra and its image under the joint exchange
-      // of the bra slots give the same packed contribution (the exchange has
-      // character +1 in both ccvv entries): map bra slots k -> pi(k)
-      if (t.up && t.bra == CCVV && t.d.bra.nslot == 4) {
+      // images of the term that act identically: the ccvv ket read through
+      // the joint exchange of its slots (a symmetry of x), and the ccvv bra
+      // written through it (the packed result is the same: the exchange has
+      // character +1 in both ccvv entries).  Among them the form that a slot
+      // GEMM can run without a permuted copy of x and with f along an inner
+      // slot is preferred, then the lexicographically smallest.
+      {
         auto pi = [](int v) { return v >= 0 && v < 4 ? (v ^ 1) : v; };
-        int alt[6];
-        for (int l = 0; l < 4; ++l) alt[l] = l < t.d.ket.nslot ? pi(ks[l]) : ks[l];
-        alt[4] = pi(t.d.fx_src);
-        alt[5] = pi(t.d.fy_src);
-        const int cur[6] = {ks[0], ks[1], ks[2], ks[3], t.d.fx_src, t.d.fy_src};
-        if (std::lexicographical_compare(alt, alt + 6, cur, cur + 6)) {
-          std::copy(alt, alt + 4, ks);
-          t.d.fx_src = alt[4];
-          t.d.fy_src = alt[5];
+        const bool kswap = !t.up && t.ket == CCVV && t.d.ket.nslot == 4;
+        const bool bswap = t.bra == CCVV && t.d.bra.nslot == 4;
+        auto score = [&](const int* c) {
+          int sb, perm[4];
+          if (t.up || t.bra != t.ket || t.d.nsum != 1 || t.d.ny != 1 ||
+              !slot_form(c, c[4], c[5], t.d.ket.nslot, &sb, perm))
+            return 4;
+          return (perm_trivial(t.ket, perm, t.d.ket.nslot) ? 0 : 2) + (sb == t.d.bra.nslot - 1 ? 1 : 0);
+        };
+        int best[6] = {ks[0], ks[1], ks[2], ks[3], t.d.fx_src, t.d.fy_src};
+        int best_score = score(best);
+        for (int m = 1; m < 4; ++m) {
+          if (((m & 1) && !kswap) || ((m & 2) && !bswap)) continue;
+          int c[6] = {ks[0], ks[1], ks[2], ks[3], t.d.fx_src, t.d.fy_src};
+          if (m & 1) {
+            std::swap(c[0], c[1]);
+            std::swap(c[2], c[3]);
+          }
+          if (m & 2) {
+            for (int l = 0; l < t.d.ket.nslot; ++l) c[l] = pi(c[l]);
+            c[4] = pi(c[4]);
+            c[5] = pi(c[5]);
+          }
+          const int sc = score(c);
+          if (sc < best_score || (sc == best_score && std::lexicographical_compare(c, c + 6, best, best + 6))) {
+            std::copy(c, c + 6, best);
+            best_score = sc;
+          }
         }
+        std::copy(best, best + 4, ks);
+        t.d.fx_src = best[4];
+        t.d.fy_src = best[5];
       }
       const std::vector<int64_t> key = {t.up, t.bra, t.ket, ks[0], ks[1], ks[2], ks[3], t.d.fx_src, t.d.fy_src,
                                         t.f_off, t.d.nsum, t.d.sum_dim[0], t.d.sum_dim[1], t.d.ny, t.d.ncol,
@@ -1154,6 +1219,40 @@ void setup_couplings(H& h) {
   // the down terms (it is never the ket of an up term): no all-orderings copy
   // of x for it
   if (used[CCVV]) h.direct[CCVV] = true;
+  // slot GEMMs (within-block terms of non-semicanonical orbitals): the ket
+  // tensor, slot-permuted where the term needs it, in all-orderings form
+  for (auto& cs : h.couple)
+    for (auto& t : cs) {
+      t.sg_slot = -1;
+      t.sg_perm = false;
+      int sb, perm[4];
+      if (t.up || t.bra != t.ket || t.d.nsum != 1 || t.d.ny != 1 ||
+          !slot_form(t.d.ket_src, t.d.fx_src, t.d.fy_src, t.d.ket.nslot, &sb, perm))
+        continue;
+      int64_t P = 1;
+      for (int l = 0; l < sb; ++l) P *= t.d.ket.slot_dim[l];
+      if (P > 65535) continue;   // batch limit of the batched GEMM: the reduce runs it
+      const int b = t.ket;
+      if (b == CCVV && t.d.ket.nslot == 4) {
+        // x[e_p0, e_p1, e_p2, e_p3] = x[e_p1, e_p0, e_p3, e_p2]: the two slot
+        // maps read the same tensor; keep the smaller
+        const int alt[4] = {perm[1], perm[0], perm[3], perm[2]};
+        if (std::lexicographical_compare(alt, alt + 4, perm, perm + 4)) std::copy(alt, alt + 4, perm);
+      }
+      if (!perm_trivial(b, perm, t.d.ket.nslot)) {
+        bool have = false, same = true;
+        for (auto& cs2 : h.couple)
+          for (auto& t2 : cs2)
+            if (t2.sg_perm && t2.ket == b) have = true;
+        if (have)
+          for (int l = 0; l < t.d.ket.nslot; ++l) same = same && h.xperm_p[b][l] == perm[l];
+        if (have && !same) continue;   // one permuted copy per block
+        std::copy(perm, perm + 4, h.xperm_p[b]);
+        t.sg_perm = true;
+      }
+      t.sg_slot = sb;
+      h.direct[b] = false;
+    }
   scratch = 0;
   for (auto& cs : h.couple)
     for (auto& t : cs) {
@@ -1172,6 +1271,9 @@ void setup_couplings(H& h) {
     if (!h.direct[b]) h.xall[b].alloc(all_rows(h, b) * na_b);
     h.sall[b].alloc(all_rows(h, b) * na_b);
   }
+  for (auto& cs : h.couple)
+    for (auto& t : cs)
+      if (t.sg_perm && !h.xperm[t.ket].n) h.xperm[t.ket].alloc(h.xall[t.ket].n);
 }
 
 // sigma += (Fock couplings between blocks) x, through all-orderings tensors:
@@ -1181,6 +1283,7 @@ void setup_couplings(H& h) {
 // all-orderings buffers, sized for doubles, then hold floats.)
 // the current work set's buffers
 DBuf& xall_of(H& h, int b) { return h.wset ? h.xall2[b] : h.xall[b]; }
+DBuf& xperm_of(H& h, int b) { return h.wset ? h.xperm2[b] : h.xperm[b]; }
 DBuf& sall_of(H& h, int b) { return h.wset ? h.sall2[b] : h.sall[b]; }
 DBuf& cscratch_of(H& h) { return h.wset ? h.cscratch2 : h.cscratch; }
 
@@ -1189,6 +1292,7 @@ void ensure_work_set2(H& h) {
   for (int b = 0; b < NBLOCK; ++b) {
     if (h.xall[b].n && h.xall2[b].n != h.xall[b].n) h.xall2[b].alloc(h.xall[b].n);
     if (h.sall[b].n && h.sall2[b].n != h.sall[b].n) h.sall2[b].alloc(h.sall[b].n);
+    if (h.xperm[b].n && h.xperm2[b].n != h.xperm[b].n) h.xperm2[b].alloc(h.xperm[b].n);
   }
   if (h.cscratch.n && h.cscratch2.n != h.cscratch.n) h.cscratch2.alloc(h.cscratch.n);
   if (h.splitk_ws2.n != h.splitk_ws.n) h.splitk_ws2.alloc(h.splitk_ws.n);
@@ -1199,6 +1303,23 @@ int64_t nalpha_of_block(const H& h, int set, int block) {
     if (e.block == block) return e.nalpha;
   return 0;
 }
+
+// Y[p][e][q] = sum_z f(e, z) X[p][z][q] along slot sg_slot of the ket's
+// all-orderings tensor (p: the slots before it, q: the slots after it and the
+// alpha columns): a batched FP64 GEMM on MFMA.  The FP32 operator of the
+// mixed mode keeps the index-mapped reduce (returns false).
+bool slot_gemm(H& h, const CoupleTerm& t, int64_t nak, const double* X, double* Y) {
+  const int s = t.sg_slot;
+  int64_t P = 1, Q = nak;
+  for (int l = 0; l < s; ++l) P *= t.d.ket.slot_dim[l];
+  for (int l = s + 1; l < t.d.ket.nslot; ++l) Q *= t.d.ket.slot_dim[l];
+  const int64_t D = t.d.ket.slot_dim[s];
+  // f is symmetric: f(e, z) = f(z, e) whichever of the two labels is summed
+  HIPCHECK(gemm_f64(false, D, Q, D, 1.0, h.fock.p + t.f_off, t.d.f_stride, 0, X, Q, D * Q, 0.0, Y, Q, D * Q,
+                    (int)P, h.s));
+  return true;
+}
+bool slot_gemm(H&, const CoupleTerm&, int64_t, const float*, float*) { return false; }
 
 // one coupling term into the all-orderings sigma of its bra (x: the packed
 // vector, read directly for a packed ket; the other kets' all-orderings
@@ -1219,7 +1340,11 @@ void couple_term(H& h, int set, const CoupleTerm& t, const T* x, int fuse) {
     HIPCHECK(couple_expand(t.d, f, (const T*)scratch, sb, h.s, fuse == 0 ? 1 : fuse == 2 ? 2 : 0));
   } else {
     const int64_t width = (int64_t)t.d.ny * nak;
-    if (h.direct[t.ket])
+    if (t.sg_slot >= 0 &&
+        slot_gemm(h, t, nak, reinterpret_cast<const T*>(t.sg_perm ? xperm_of(h, t.ket).p : xall_of(h, t.ket).p),
+                  scratch)) {
+      // done: f applied along one slot by a batched GEMM
+    } else if (h.direct[t.ket])
       HIPCHECK(couple_reduce_packed(t.d, pack_info(h, set, t.ket, nullptr, nullptr, nak), f, x, scratch, h.s));
     else
       HIPCHECK(couple_reduce(t.d, f, (const T*)xk, scratch, h.s));
@@ -1247,6 +1372,23 @@ void apply_couplings(H& h, int set, const T* x, T* sig) {
     const int64_t na_b = nalpha_of(b);
     if (xall_of(h, b).p)
       HIPCHECK(unpack_all(pack_info(h, set, b, nullptr, nullptr, na_b), all_desc(h, b), x, xall(b), h.s));
+    if (xperm_of(h, b).p && std::is_same<T, double>::value) {
+      // copy[e] = x[e[p[0]], e[p[1]], ...]: scatter x's element at k to the
+      // position e with e[p[l]] = k[l] (fill kernel first, not a memset:
+      // this sequence is recorded into HIP graphs)
+      const AllDesc ad = all_desc(h, b);
+      int64_t dims[5], dst[5], st[5];
+      st[ad.nslot] = 1;
+      for (int k = ad.nslot - 1; k >= 0; --k) st[k] = st[k + 1] * (k + 1 < ad.nslot ? ad.slot_dim[k + 1] : na_b);
+      for (int l = 0; l < ad.nslot; ++l) {
+        dims[l] = ad.slot_dim[l];
+        dst[l] = st[h.xperm_p[b][l]];
+      }
+      dims[ad.nslot] = na_b;
+      dst[ad.nslot] = 1;
+      HIPCHECK(vec_fill(xperm_of(h, b).n, 0.0, xperm_of(h, b).p, h.s));
+      HIPCHECK(permute_axpy(ad.nslot + 1, dims, dst, 1.0, xall_of(h, b).p, xperm_of(h, b).p, h.s));
+    }
     // fill kernel, not a memset: this sequence is recorded into HIP graphs
     HIPCHECK(vec_fill(sall_of(h, b).n, 0.0, sall_of(h, b).p, h.s));
   }
@@ -1254,8 +1396,9 @@ void apply_couplings(H& h, int set, const T* x, T* sig) {
   for (auto& t : h.couple[set]) {
     if (diag) {
       stage("stage");
-      std::fprintf(stderr, "[caspt2] term %s %s <- %s ny %d nsum %d: ", t.up ? "up" : "down",
-                   blocks()[t.bra].name.c_str(), blocks()[t.ket].name.c_str(), t.d.ny, t.d.nsum);
+      std::fprintf(stderr, "[caspt2] term %s %s <- %s ny %d nsum %d slot %d%s: ", t.up ? "up" : "down",
+                   blocks()[t.bra].name.c_str(), blocks()[t.ket].name.c_str(), t.d.ny, t.d.nsum, t.sg_slot,
+                   t.sg_perm ? " permuted" : "");
     }
     couple_term<T>(h, set, t, x, t.fuse);
   }
