@@ -289,6 +289,7 @@ def main():
     elapsed = time.perf_counter() - t0
     prof = {ENTRY_NAMES[k]: g.profile_entry(k) for k in range(len(ENTRY_NAMES))}
     coupl = g.profile_entry(len(ENTRY_NAMES))
+    slot = g.profile_entry(len(ENTRY_NAMES) + 1)
     g.profile(False)
     print(f"[bench] {args.steps} steps in {elapsed:.3f} s", file=sys.stderr, flush=True)
     # the library's default for caspt2_residual_all: states on two streams,
@@ -333,6 +334,14 @@ def main():
             tf = 4.0 * rows * na * na / (v[0] * 1e-3) / 1e12
             mfma[name] = {"TFs": round(tf, 2), "util": round(tf / FP64_PEAK_TFS, 3), "rows": rows, "nalpha": na}
     per_entry["couplings"] = {"avg_ms": round(coupl[0], 4), "launches": coupl[1]}
+    # non-semicanonical orbitals: the batched GEMMs applying off-diagonal f_cc
+    # and f_vv along one slot of ccvv, cavv and ccav (flops per launch from
+    # the library), rate vs the FP64 MFMA peak
+    if slot[1] > 0 and slot[0] > 0:
+        tf = slot[2] / (slot[0] * 1e-3) / 1e12
+        mfma["slot_gemm_ccvv_cavv_ccav"] = {"TFs": round(tf, 2), "util": round(tf / FP64_PEAK_TFS, 3),
+                                            "launches_per_step": slot[1] // max(args.steps, 1),
+                                            "avg_ms": round(slot[0], 4), "flops_per_launch": slot[2]}
 
     solve = None
     if args.solve:

@@ -1308,18 +1308,24 @@ int64_t nalpha_of_block(const H& h, int set, int block) {
 // all-orderings tensor (p: the slots before it, q: the slots after it and the
 // alpha columns): a batched FP64 GEMM on MFMA.  The FP32 operator of the
 // mixed mode keeps the index-mapped reduce (returns false).
-bool slot_gemm(H& h, const CoupleTerm& t, int64_t nak, const double* X, double* Y) {
+void prof_begin(H& h, hipEvent_t* a);
+void prof_end(H& h, int entry, double bytes, hipEvent_t a);
+bool slot_gemm(H& h, const CoupleTerm& t, int64_t nak, const double* X, double* Y, int prof_entry) {
   const int s = t.sg_slot;
   int64_t P = 1, Q = nak;
   for (int l = 0; l < s; ++l) P *= t.d.ket.slot_dim[l];
   for (int l = s + 1; l < t.d.ket.nslot; ++l) Q *= t.d.ket.slot_dim[l];
   const int64_t D = t.d.ket.slot_dim[s];
+  const bool timed = t.ket == CCVV || t.ket == CAVV || t.ket == CCAV;
+  hipEvent_t ev = nullptr;
+  if (timed) prof_begin(h, &ev);
   // f is symmetric: f(e, z) = f(z, e) whichever of the two labels is summed
   HIPCHECK(gemm_f64(false, D, Q, D, 1.0, h.fock.p + t.f_off, t.d.f_stride, 0, X, Q, D * Q, 0.0, Y, Q, D * Q,
                     (int)P, h.s));
+  if (timed) prof_end(h, prof_entry, 2.0 * (double)D * D * P * Q, ev);
   return true;
 }
-bool slot_gemm(H&, const CoupleTerm&, int64_t, const float*, float*) { return false; }
+bool slot_gemm(H&, const CoupleTerm&, int64_t, const float*, float*, int) { return false; }
 
 // one coupling term into the all-orderings sigma of its bra (x: the packed
 // vector, read directly for a packed ket; the other kets' all-orderings
@@ -1342,14 +1348,17 @@ void couple_term(H& h, int set, const CoupleTerm& t, const T* x, int fuse) {
     const int64_t width = (int64_t)t.d.ny * nak;
     if (t.sg_slot >= 0 &&
         slot_gemm(h, t, nak, reinterpret_cast<const T*>(t.sg_perm ? xperm_of(h, t.ket).p : xall_of(h, t.ket).p),
-                  scratch)) {
+                  scratch, (int)h.sets[set].size() + 1)) {
       // done: f applied along one slot by a batched GEMM
     } else if (h.direct[t.ket])
       HIPCHECK(couple_reduce_packed(t.d, pack_info(h, set, t.ket, nullptr, nullptr, nak), f, x, scratch, h.s));
     else
       HIPCHECK(couple_reduce(t.d, f, (const T*)xk, scratch, h.s));
-    HIPCHECK(gemm_t(true, all_rows(h, t.bra), nab, width, 1.0, scratch, width, Sel<T>::G(t), width, 1.0, sb,
-                    nab, h.s));
+    if (nab <= 8 && width <= 8)
+      HIPCHECK(rows_small_gemm(all_rows(h, t.bra), (int)nab, (int)width, (const T*)scratch, Sel<T>::G(t), sb, h.s));
+    else
+      HIPCHECK(gemm_t(true, all_rows(h, t.bra), nab, width, 1.0, scratch, width, Sel<T>::G(t), width, 1.0, sb,
+                      nab, h.s));
   }
 }
 
@@ -2728,7 +2737,7 @@ int caspt2_profile(caspt2_handle* h, int32_t enable) {
 
 int caspt2_profile_entry(caspt2_handle* h, int32_t k, double* avg_ms, int64_t* launches,
                          double* bytes_per_launch) {
-  if (!h || k < 0 || k > (int32_t)h->sets[0].size()) return CASPT2_E_ARG;
+  if (!h || k < 0 || k > (int32_t)h->sets[0].size() + 1) return CASPT2_E_ARG;
   ABI_GUARD({
     HIPCHECK(hipStreamSynchronize(h->s));
     double tot = 0.0, bytes = 0.0;

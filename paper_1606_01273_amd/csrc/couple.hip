@@ -902,7 +902,42 @@ hipError_t couple_reduce_packed(const CoupleDesc& d, const PackInfo& pk, const d
   return launch_reduce<T, true>(d, pk, f, x, Y, s);
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_rows_small_gemm(int64_t nrows, int nab, int width,
+                                                         const T* __restrict__ Y, const T* __restrict__ G,
+                                                         T* __restrict__ out) {
+  __shared__ double gs[64];
+  for (int k = threadIdx.x; k < nab * width; k += blockDim.x) gs[k] = (double)G[k];
+  __syncthreads();
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < nrows;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    double y[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) y[c] = c < width ? (double)Y[r * width + c] : 0.0;
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      if (a >= nab) break;
+      double acc = 0.0;
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        if (c < width) acc += y[c] * gs[a * width + c];
+      out[r * nab + a] += (T)acc;
+    }
+  }
+}
+
+template <typename T>
+hipError_t rows_small_gemm(int64_t nrows, int nab, int width, const T* Y, const T* G, T* out, hipStream_t s) {
+  if (nab < 1 || nab > 8 || width < 1 || width > 8) return hipErrorInvalidValue;
+  if (nrows <= 0) return hipSuccess;
+  unsigned grid = cdiv(nrows, 256);
+  if (grid > 65536) grid = 65536;
+  hipLaunchKernelGGL(k_rows_small_gemm<T>, dim3(grid), dim3(256), 0, s, nrows, nab, width, Y, G, out);
+  return hipGetLastError();
+}
+
 #define CASPT2_COUPLE_INSTANCES(T)                                                                  \
+  template hipError_t rows_small_gemm<T>(int64_t, int, int, const T*, const T*, T*, hipStream_t);  \
   template hipError_t unpack_all<T>(const PackInfo&, const AllDesc&, const T*, T*, hipStream_t);   \
   template hipError_t pack_acc<T>(const TermDesc&, const AllDesc&, const T*, T*, hipStream_t);     \
   template hipError_t pack_ccvv<T>(int, int, int, const T*, T*, T*, hipStream_t);                   \

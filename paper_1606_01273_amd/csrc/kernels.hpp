@@ -208,6 +208,11 @@ hipError_t couple_reduce(const CoupleDesc& d, const double* f, const T* X, T* Y,
 template <typename T>
 hipError_t couple_reduce_packed(const CoupleDesc& d, const PackInfo& pk, const double* f, const T* x,
                                 T* Y, hipStream_t s);
+// out[r][a] += sum_c Y[r][c] G[a][c] for rows r < nrows, a < nab, c < width
+// (G [nab][width]); one thread per row, for nab, width <= 8 (the contraction
+// of a down term's reduce with its active tensor when both are narrow)
+template <typename T>
+hipError_t rows_small_gemm(int64_t nrows, int nab, int width, const T* Y, const T* G, T* out, hipStream_t s);
 
 // X0[i][k] = Q[i][idx[k]] * scale[k]  (Q is n x ncq, X0 is n x nk)
 hipError_t select_scale_cols(int64_t n, int64_t ncq, const double* Q, const int32_t* idx,
