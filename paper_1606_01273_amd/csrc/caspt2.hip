@@ -1320,8 +1320,7 @@ bool slot_gemm(H& h, const CoupleTerm& t, int64_t nak, const double* X, double* 
   hipEvent_t ev = nullptr;
   if (timed) prof_begin(h, &ev);
   // f is symmetric: f(e, z) = f(z, e) whichever of the two labels is summed
-  HIPCHECK(gemm_f64(false, D, Q, D, 1.0, h.fock.p + t.f_off, t.d.f_stride, 0, X, Q, D * Q, 0.0, Y, Q, D * Q,
-                    (int)P, h.s));
+  HIPCHECK(gemm_f64_batched(D, Q, D, h.fock.p + t.f_off, t.d.f_stride, 0, X, Q, D * Q, Y, Q, D * Q, (int)P, h.s));
   if (timed) prof_end(h, prof_entry, 2.0 * (double)D * D * P * Q, ev);
   return true;
 }

@@ -101,8 +101,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
   // linear id g runs on XCD g % 8; each XCD takes a contiguous range of the
   // tiles (n fastest), and the tiles of one row band that share their A rows
   // run on one XCD at about the same time (one L2)
+  // order 3: the same with m fastest (the m tiles that share one B tile run
+  // back to back on one XCD: for batched products with few m tiles)
   int64_t bz, tmi, tni;
-  if (order == 2) {
+  if (order >= 2) {
     const int64_t gx = gridDim.x, gy = gridDim.y;
     const int64_t nwg = gx * gy * (int64_t)gridDim.z;
     const int64_t g = ((int64_t)blockIdx.z * gy + blockIdx.y) * gx + blockIdx.x;
@@ -111,8 +113,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     const int64_t tnn = (N + BN - 1) / BN, tmn = (M + TM - 1) / TM;
     bz = t / (tmn * tnn);
     const int64_t r = t - bz * tmn * tnn;
-    tmi = r / tnn;
-    tni = r - tmi * tnn;
+    if (order == 2) {
+      tmi = r / tnn;
+      tni = r - tmi * tnn;
+    } else {
+      tni = r / tmn;
+      tmi = r - tni * tmn;
+    }
   } else {
     bz = blockIdx.z;
     tmi = order ? blockIdx.x : blockIdx.y;
@@ -241,6 +248,22 @@ hipError_t gemm_f64(bool b_is_nk, int64_t M, int64_t N, int64_t K, double alpha,
     hipLaunchKernelGGL((k_gemm_f64<false, false>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda,
                        sA, B, ldb, sB, (const double*)nullptr, beta, C, ldc, sC,
                        (const double*)nullptr, 0.0, (const double*)nullptr, (int64_t)0, mx, (int64_t)0);
+  return hipGetLastError();
+}
+
+// batched C_p = A B_p (B_p [K][N], A shared or strided): 64 x 64 tiles with
+// the accumulators in VGPRs (3 waves per SIMD asked of the compiler) and the
+// XCD-grouped tile order with m fastest, so that the few m tiles reading one
+// B tile run back to back on one XCD and B comes from HBM about once
+hipError_t gemm_f64_batched(int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, int64_t sA,
+                            const double* B, int64_t ldb, int64_t sB, double* C, int64_t ldc, int64_t sC,
+                            int batch, hipStream_t s) {
+  if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+  const int64_t tmn = (M + BM - 1) / BM, tnn = (N + BN - 1) / BN;
+  if (tmn > 65535 || batch > 65535 || tnn > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_gemm_f64<false, false, false, 2, 16, 3>), dim3((unsigned)tnn, (unsigned)tmn, (unsigned)batch),
+                     dim3(256), 0, s, M, N, K, 1.0, A, lda, sA, B, ldb, sB, (const double*)nullptr, 0.0, C, ldc, sC,
+                     (const double*)nullptr, 0.0, (const double*)nullptr, (int64_t)0, 3, (int64_t)0);
   return hipGetLastError();
 }
 

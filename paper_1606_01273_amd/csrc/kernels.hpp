@@ -18,6 +18,10 @@ hipError_t launch_gather_apply(const double* X, int64_t nlead, int64_t dim_from,
 hipError_t gemm_f64(bool b_is_nk, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
                     int64_t lda, int64_t sA, const double* B, int64_t ldb, int64_t sB, double beta,
                     double* C, int64_t ldc, int64_t sC, int batch, hipStream_t s);
+// batched C_p = A_p B_p (B_p [K][N], beta 0), tile order for few m tiles
+hipError_t gemm_f64_batched(int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, int64_t sA,
+                            const double* B, int64_t ldb, int64_t sB, double* C, int64_t ldc, int64_t sC,
+                            int batch, hipStream_t s);
 
 // Launch choices of a residual entry; a field left at its default means
 // "by rule" (the launcher's built-in choice for the shape).  The autotuner
