@@ -289,7 +289,7 @@ def main():
     elapsed = time.perf_counter() - t0
     prof = {ENTRY_NAMES[k]: g.profile_entry(k) for k in range(len(ENTRY_NAMES))}
     coupl = g.profile_entry(len(ENTRY_NAMES))
-    slot = g.profile_entry(len(ENTRY_NAMES) + 1)
+    slot = {b: g.profile_entry(len(ENTRY_NAMES) + 1 + i) for i, b in enumerate(("ccvv", "cavv", "ccav"))}
     g.profile(False)
     print(f"[bench] {args.steps} steps in {elapsed:.3f} s", file=sys.stderr, flush=True)
     # the library's default for caspt2_residual_all: states on two streams,
@@ -337,11 +337,18 @@ def main():
     # non-semicanonical orbitals: the batched GEMMs applying off-diagonal f_cc
     # and f_vv along one slot of ccvv, cavv and ccav (flops per launch from
     # the library), rate vs the FP64 MFMA peak
-    if slot[1] > 0 and slot[0] > 0:
-        tf = slot[2] / (slot[0] * 1e-3) / 1e12
-        mfma["slot_gemm_ccvv_cavv_ccav"] = {"TFs": round(tf, 2), "util": round(tf / FP64_PEAK_TFS, 3),
-                                            "launches_per_step": slot[1] // max(args.steps, 1),
-                                            "avg_ms": round(slot[0], 4), "flops_per_launch": slot[2]}
+    tot_ms = tot_fl = 0.0
+    for b, (ms, n, fl) in slot.items():
+        if n > 0 and ms > 0:
+            tf = fl / (ms * 1e-3) / 1e12
+            mfma[f"slot_gemm_{b}"] = {"TFs": round(tf, 2), "util": round(tf / FP64_PEAK_TFS, 3),
+                                      "launches_per_step": n // max(args.steps, 1), "avg_ms": round(ms, 4),
+                                      "flops_per_launch": fl}
+            tot_ms += ms * n
+            tot_fl += fl * n
+    if tot_ms > 0:
+        tf = tot_fl / (tot_ms * 1e-3) / 1e12
+        mfma["slot_gemm_all"] = {"TFs": round(tf, 2), "util": round(tf / FP64_PEAK_TFS, 3)}
 
     solve = None
     if args.solve:

@@ -265,10 +265,11 @@ CASPT2_API int caspt2_batch_solve(caspt2_handle* const* handles, int32_t n, cons
  * launches and the algorithmic bytes per launch (read x, read the source when
  * it is added, write sigma; 8 bytes per double).  k = 13 reports the Fock
  * couplings between blocks of one residual, timed together (bytes 0).
- * k = 14 reports the batched GEMMs that apply off-diagonal closed-closed and
- * virtual-virtual Fock elements inside the ccvv, cavv and ccav blocks
- * (orbitals that are not semicanonical): per launch 2 D^2 P Q flops in place
- * of bytes (f of D x D along one slot, P Q the other elements). */
+ * k = 14, 15, 16 report the batched GEMMs that apply off-diagonal
+ * closed-closed and virtual-virtual Fock elements inside the ccvv, cavv and
+ * ccav blocks respectively (orbitals that are not semicanonical): per launch
+ * 2 D^2 P Q flops in place of bytes (f of D x D along one slot, P Q the other
+ * elements). */
 CASPT2_API int caspt2_profile(caspt2_handle* h, int32_t enable);
 CASPT2_API int caspt2_profile_entry(caspt2_handle* h, int32_t k, double* avg_ms, int64_t* launches,
                                     double* bytes_per_launch);

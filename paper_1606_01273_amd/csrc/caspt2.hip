@@ -1316,12 +1316,13 @@ bool slot_gemm(H& h, const CoupleTerm& t, int64_t nak, const double* X, double* 
   for (int l = 0; l < s; ++l) P *= t.d.ket.slot_dim[l];
   for (int l = s + 1; l < t.d.ket.nslot; ++l) Q *= t.d.ket.slot_dim[l];
   const int64_t D = t.d.ket.slot_dim[s];
-  const bool timed = t.ket == CCVV || t.ket == CAVV || t.ket == CCAV;
+  const int which = t.ket == CCVV ? 0 : t.ket == CAVV ? 1 : t.ket == CCAV ? 2 : -1;
+  const bool timed = which >= 0;
   hipEvent_t ev = nullptr;
   if (timed) prof_begin(h, &ev);
   // f is symmetric: f(e, z) = f(z, e) whichever of the two labels is summed
   HIPCHECK(gemm_f64_batched(D, Q, D, h.fock.p + t.f_off, t.d.f_stride, 0, X, Q, D * Q, Y, Q, D * Q, (int)P, h.s));
-  if (timed) prof_end(h, prof_entry, 2.0 * (double)D * D * P * Q, ev);
+  if (timed) prof_end(h, prof_entry + which, 2.0 * (double)D * D * P * Q, ev);
   return true;
 }
 bool slot_gemm(H&, const CoupleTerm&, int64_t, const float*, float*, int) { return false; }
@@ -2736,7 +2737,7 @@ int caspt2_profile(caspt2_handle* h, int32_t enable) {
 
 int caspt2_profile_entry(caspt2_handle* h, int32_t k, double* avg_ms, int64_t* launches,
                          double* bytes_per_launch) {
-  if (!h || k < 0 || k > (int32_t)h->sets[0].size() + 1) return CASPT2_E_ARG;
+  if (!h || k < 0 || k > (int32_t)h->sets[0].size() + 3) return CASPT2_E_ARG;
   ABI_GUARD({
     HIPCHECK(hipStreamSynchronize(h->s));
     double tot = 0.0, bytes = 0.0;
