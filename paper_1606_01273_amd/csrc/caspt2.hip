@@ -200,6 +200,7 @@ struct caspt2_handle {
   std::unique_ptr<ActiveSpace> as;
   int64_t ndet = 0;
   DBuf fock, hcore, B, ci_raw, ci;   // ci: rotated [nst][dim]
+  FBuf fock32;                       // FP32 copy of fock (mixed precision)
   std::vector<double> h_fock, h_eps, U, e0, fref, href, eref;
   // layout per function set (one for MS-MR, nst for SS-SR)
   std::vector<std::vector<Entry>> sets;
@@ -1306,8 +1307,8 @@ int64_t nalpha_of_block(const H& h, int set, int block) {
 
 // Y[p][e][q] = sum_z f(e, z) X[p][z][q] along slot sg_slot of the ket's
 // all-orderings tensor (p: the slots before it, q: the slots after it and the
-// alpha columns): a batched FP64 GEMM on MFMA.  The FP32 operator of the
-// mixed mode keeps the index-mapped reduce (returns false).
+// alpha columns): a batched FP64 GEMM on MFMA (the FP32 operator of the
+// mixed mode: the FP32 GEMM with the FP32 copy of f).
 void prof_begin(H& h, hipEvent_t* a);
 void prof_end(H& h, int entry, double bytes, hipEvent_t a);
 bool slot_gemm(H& h, const CoupleTerm& t, int64_t nak, const double* X, double* Y, int prof_entry) {
@@ -1325,7 +1326,17 @@ bool slot_gemm(H& h, const CoupleTerm& t, int64_t nak, const double* X, double* 
   if (timed) prof_end(h, prof_entry + which, 2.0 * (double)D * D * P * Q, ev);
   return true;
 }
-bool slot_gemm(H&, const CoupleTerm&, int64_t, const float*, float*, int) { return false; }
+bool slot_gemm(H& h, const CoupleTerm& t, int64_t nak, const float* X, float* Y, int) {
+  if (!h.fock32.p) return false;
+  const int s = t.sg_slot;
+  int64_t P = 1, Q = nak;
+  for (int l = 0; l < s; ++l) P *= t.d.ket.slot_dim[l];
+  for (int l = s + 1; l < t.d.ket.nslot; ++l) Q *= t.d.ket.slot_dim[l];
+  const int64_t D = t.d.ket.slot_dim[s];
+  HIPCHECK(gemm_f32(false, D, Q, D, 1.f, h.fock32.p + t.f_off, t.d.f_stride, 0, X, Q, D * Q, 0.f, Y, Q, D * Q,
+                    (int)P, h.s));
+  return true;
+}
 
 // one coupling term into the all-orderings sigma of its bra (x: the packed
 // vector, read directly for a packed ket; the other kets' all-orderings
@@ -1381,10 +1392,9 @@ void apply_couplings(H& h, int set, const T* x, T* sig) {
     const int64_t na_b = nalpha_of(b);
     if (xall_of(h, b).p)
       HIPCHECK(unpack_all(pack_info(h, set, b, nullptr, nullptr, na_b), all_desc(h, b), x, xall(b), h.s));
-    if (xperm_of(h, b).p && std::is_same<T, double>::value) {
+    if (xperm_of(h, b).p) {
       // copy[e] = x[e[p[0]], e[p[1]], ...]: scatter x's element at k to the
-      // position e with e[p[l]] = k[l] (fill kernel first, not a memset:
-      // this sequence is recorded into HIP graphs)
+      // position e with e[p[l]] = k[l]
       const AllDesc ad = all_desc(h, b);
       int64_t dims[5], dst[5], st[5];
       st[ad.nslot] = 1;
@@ -1395,8 +1405,8 @@ void apply_couplings(H& h, int set, const T* x, T* sig) {
       }
       dims[ad.nslot] = na_b;
       dst[ad.nslot] = 1;
-      HIPCHECK(vec_fill(xperm_of(h, b).n, 0.0, xperm_of(h, b).p, h.s));
-      HIPCHECK(permute_axpy(ad.nslot + 1, dims, dst, 1.0, xall_of(h, b).p, xperm_of(h, b).p, h.s));
+      HIPCHECK(permute_copy(ad.nslot + 1, dims, dst, (const T*)xall(b), reinterpret_cast<T*>(xperm_of(h, b).p),
+                            h.s));
     }
     // fill kernel, not a memset: this sequence is recorded into HIP graphs
     HIPCHECK(vec_fill(sall_of(h, b).n, 0.0, sall_of(h, b).p, h.s));
@@ -1621,6 +1631,8 @@ void setup_mixed(H& h) {
       t.G32.alloc(t.G.n);
       HIPCHECK(vec_scale_copy(t.G.n, 1.0, t.G.p, t.G32.p, h.s));
     }
+  h.fock32.alloc(h.fock.n);
+  HIPCHECK(vec_scale_copy(h.fock.n, 1.0, h.fock.p, h.fock32.p, h.s));
   h.have_mixed = true;
 }
 

@@ -764,6 +764,43 @@ hipError_t permute_axpy(int nd, const int64_t* dims, const int64_t* dstride, dou
   return hipGetLastError();
 }
 
+// dst[sum_k i_k dstride[k]] = src[g] for the element g = (i_0, .., i_{nd-1})
+// of src (row-major dims): a permutation of all elements, so dst needs no
+// clearing
+template <typename T>
+__global__ void k_permute_copy(PermArgs p, int64_t total, const T* __restrict__ src, T* __restrict__ dst) {
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    int64_t rem = g, off = 0;
+    for (int k = p.nd - 1; k >= 0; --k) {
+      const int64_t ik = rem % p.dims[k];
+      rem /= p.dims[k];
+      off += ik * p.dstride[k];
+    }
+    dst[off] = src[g];
+  }
+}
+
+template <typename T>
+hipError_t permute_copy(int nd, const int64_t* dims, const int64_t* dstride, const T* src, T* dst, hipStream_t s) {
+  if (nd < 1 || nd > 10) return hipErrorInvalidValue;
+  PermArgs p;
+  p.nd = nd;
+  int64_t total = 1;
+  for (int k = 0; k < nd; ++k) {
+    p.dims[k] = dims[k];
+    p.dstride[k] = dstride[k];
+    total *= dims[k];
+  }
+  if (total == 0) return hipSuccess;
+  unsigned grid = cdiv(total, 256);
+  if (grid > 65536) grid = 65536;
+  hipLaunchKernelGGL(k_permute_copy<T>, dim3(grid), dim3(256), 0, s, p, total, src, dst);
+  return hipGetLastError();
+}
+template hipError_t permute_copy<double>(int, const int64_t*, const int64_t*, const double*, double*, hipStream_t);
+template hipError_t permute_copy<float>(int, const int64_t*, const int64_t*, const float*, float*, hipStream_t);
+
 __global__ void k_contract_lead(int64_t ni, int64_t nj, const double* __restrict__ c,
                                 const double* __restrict__ G, double* __restrict__ y) {
   for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < nj;

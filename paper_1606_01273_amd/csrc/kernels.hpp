@@ -101,6 +101,10 @@ hipError_t transform_rows(int64_t M, int nin, int nout, const T* in, const T* W,
 // dst[sum_k idx_k * dstride_k] += c * src[flat], src dims dims[0..nd)
 hipError_t permute_axpy(int nd, const int64_t* dims, const int64_t* dstride, double c,
                         const double* src, double* dst, hipStream_t s);
+// dst[sum_k i_k dstride[k]] = src[(i_0, .., i_{nd-1})]: a permuted copy of
+// all elements (nd <= 10)
+template <typename T>
+hipError_t permute_copy(int nd, const int64_t* dims, const int64_t* dstride, const T* src, T* dst, hipStream_t s);
 
 // y[j] += sum_i c[i] * G[i][j], i < ni, j < nj   (c on device)
 hipError_t contract_lead(int64_t ni, int64_t nj, const double* c, const double* G, double* y,

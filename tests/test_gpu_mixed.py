@@ -87,6 +87,7 @@ CASES = [
     ((3, 4, 10, 40, 2), 7, "B", "SSSR", True, 0.2),
     ((5, 4, 30, 70, 2), 8, "B", "MSMR", True, 0.2),
     ((3, 3, 9, 30, 3), 7, "B", "MSMR", False, 0.1),
+    ((3, 3, 7, 26, 2), 9, "C", "MSMR", True, 0.2),
 ]
 
 
