@@ -926,13 +926,44 @@ __global__ __launch_bounds__(256) void k_rows_small_gemm(int64_t nrows, int nab,
   }
 }
 
+// the same for nab = width = 4 in FP64: rows move as two 16-byte loads
+__global__ __launch_bounds__(256) void k_rows_small_gemm4(int64_t nrows, const double* __restrict__ Y,
+                                                          const double* __restrict__ G, double* __restrict__ out) {
+  __shared__ double gs[16];
+  if (threadIdx.x < 16) gs[threadIdx.x] = G[threadIdx.x];
+  __syncthreads();
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < nrows;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    const double2* yp = reinterpret_cast<const double2*>(Y + r * 4);
+    double2* op = reinterpret_cast<double2*>(out + r * 4);
+    const double2 y01 = yp[0], y23 = yp[1];
+    double2 o01 = op[0], o23 = op[1];
+    const double y[4] = {y01.x, y01.y, y23.x, y23.y};
+    double acc[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+      acc[a] = y[0] * gs[4 * a] + y[1] * gs[4 * a + 1] + y[2] * gs[4 * a + 2] + y[3] * gs[4 * a + 3];
+    o01.x += acc[0];
+    o01.y += acc[1];
+    o23.x += acc[2];
+    o23.y += acc[3];
+    op[0] = o01;
+    op[1] = o23;
+  }
+}
+
 template <typename T>
 hipError_t rows_small_gemm(int64_t nrows, int nab, int width, const T* Y, const T* G, T* out, hipStream_t s) {
   if (nab < 1 || nab > 8 || width < 1 || width > 8) return hipErrorInvalidValue;
   if (nrows <= 0) return hipSuccess;
   unsigned grid = cdiv(nrows, 256);
   if (grid > 65536) grid = 65536;
-  hipLaunchKernelGGL(k_rows_small_gemm<T>, dim3(grid), dim3(256), 0, s, nrows, nab, width, Y, G, out);
+  const bool al16 = ((uintptr_t)Y % 16 == 0) && ((uintptr_t)out % 16 == 0);
+  if (std::is_same<T, double>::value && nab == 4 && width == 4 && al16)
+    hipLaunchKernelGGL(k_rows_small_gemm4, dim3(grid), dim3(256), 0, s, nrows, (const double*)Y, (const double*)G,
+                       (double*)out);
+  else
+    hipLaunchKernelGGL(k_rows_small_gemm<T>, dim3(grid), dim3(256), 0, s, nrows, nab, width, Y, G, out);
   return hipGetLastError();
 }
 

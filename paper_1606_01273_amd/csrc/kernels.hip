@@ -767,15 +767,19 @@ hipError_t permute_axpy(int nd, const int64_t* dims, const int64_t* dstride, dou
 // dst[sum_k i_k dstride[k]] = src[g] for the element g = (i_0, .., i_{nd-1})
 // of src (row-major dims): a permutation of all elements, so dst needs no
 // clearing
-template <typename T>
+template <typename T, typename I>
 __global__ void k_permute_copy(PermArgs p, int64_t total, const T* __restrict__ src, T* __restrict__ dst) {
+  // I: 32-bit index arithmetic when every element index fits (the
+  // division chain is the kernel's ALU cost)
   for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
        g += (int64_t)gridDim.x * blockDim.x) {
-    int64_t rem = g, off = 0;
+    I rem = (I)g;
+    int64_t off = 0;
     for (int k = p.nd - 1; k >= 0; --k) {
-      const int64_t ik = rem % p.dims[k];
-      rem /= p.dims[k];
-      off += ik * p.dstride[k];
+      const I dk = (I)p.dims[k];
+      const I q = rem / dk;
+      off += (int64_t)(rem - q * dk) * p.dstride[k];
+      rem = q;
     }
     dst[off] = src[g];
   }
@@ -795,7 +799,10 @@ hipError_t permute_copy(int nd, const int64_t* dims, const int64_t* dstride, con
   if (total == 0) return hipSuccess;
   unsigned grid = cdiv(total, 256);
   if (grid > 65536) grid = 65536;
-  hipLaunchKernelGGL(k_permute_copy<T>, dim3(grid), dim3(256), 0, s, p, total, src, dst);
+  if (total <= (int64_t)0xffffffffu)
+    hipLaunchKernelGGL((k_permute_copy<T, uint32_t>), dim3(grid), dim3(256), 0, s, p, total, src, dst);
+  else
+    hipLaunchKernelGGL((k_permute_copy<T, int64_t>), dim3(grid), dim3(256), 0, s, p, total, src, dst);
   return hipGetLastError();
 }
 template hipError_t permute_copy<double>(int, const int64_t*, const int64_t*, const double*, double*, hipStream_t);
