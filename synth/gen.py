@@ -272,6 +272,36 @@ def make_problem(nc: int, na: int, nv: int, naux: int, nst: int, seed: int,
                    rot_c=rot_c, rot_v=rot_v)
 
 
+def rotate_active(prob: Problem, seed: int) -> Problem:
+    """The same problem in active orbitals rotated by a seeded orthogonal
+    matrix: f, h^c and the DF factors transformed together, the reference
+    states recomputed as the lowest roots of the rotated active Hamiltonian
+    (same energies; sign fixed as in make_problem)."""
+    na, nc = prob.na, prob.nc
+    rng = np.random.Generator(np.random.PCG64(seed))
+    A = rng.standard_normal((na, na))
+    q, r = np.linalg.qr(A)
+    Ua = q * np.sign(np.diag(r))[None, :]
+    U = np.eye(prob.nmo)
+    act = slice(nc, nc + na)
+    U[act, act] = Ua
+    fock = _sym(U.T @ prob.fock @ U)
+    hcore = _sym(U.T @ prob.hcore @ U)
+    B = np.einsum("xp,Qxy,yq->Qpq", U, prob.B, U, optimize=True)
+    Ba = np.ascontiguousarray(B[:, act, act]).reshape(prob.naux, na * na)
+    g_act = (Ba.T @ Ba).reshape(na, na, na, na)
+    H, _ = _cas_hamiltonian(hcore[act, act], g_act, prob.nalpha, prob.nbeta)
+    w, v = np.linalg.eigh(H)
+    ci = v[:, :prob.nst].T.copy()
+    for N in range(prob.nst):
+        a = np.abs(ci[N])
+        k = int(np.flatnonzero(a >= (1.0 - 1e-6) * a.max())[0])
+        if ci[N, k] < 0:
+            ci[N] = -ci[N]
+    return prob.replace(fock=fock, hcore=hcore, B=B, ci=ci, eref=w[:prob.nst].copy(),
+                        eps=np.diag(fock).copy())
+
+
 # sizes of the named workloads: (nc, na, nv, naux, nst, seed, shift); the
 # seed of the large one is the first whose denominators are all positive at
 # shift 0.2 for every state (no intruder state)

@@ -211,3 +211,21 @@ def test_closed_virtual_rotation_invariance(dev):
         print(f"  Reading {reading}: iterations {[i['iters'] for i in info]}", flush=True)
         g.close()
     _ok(np.abs(e["B"] - e["C"]).max(), 1e-10, "E_MS rotated vs semicanonical")
+
+
+def test_active_rotation_invariance(dev):
+    """E^MS does not depend on the basis of the active orbitals (f, h^c, the
+    DF factors and the reference states transformed together): the library
+    on rotated active orbitals against the library on the original ones."""
+    from paper_1606_01273_amd import Caspt2
+    from synth.gen import rotate_active
+    p = make_problem(5, 4, 30, 70, 2, seed=8, reading="B", shift=0.2)
+    e = []
+    for q in (p, rotate_active(p, seed=11)):
+        g = Caspt2.from_problem(q)
+        rc, info = g.solve_amplitudes(tol=1e-11, maxiter=400)
+        assert rc == 0, f"amplitude solve status {rc}"
+        e.append(g.heff()[1])
+        g.close()
+    _ok(np.abs(e[0] - e[1]).max(), 1e-10, "E_MS rotated active orbitals vs original")
+

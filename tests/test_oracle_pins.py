@@ -333,6 +333,24 @@ def test_closed_virtual_rotation_invariance():
     assert np.abs(eb - ec).max() < 1e-10
 
 
+def test_active_rotation_invariance():
+    """E^MS does not depend on the basis of the active orbitals when f, h^c,
+    the DF factors and the reference states are transformed together: the
+    functions of Eq. 8 span the same space, the truncation of Sec. II.B acts
+    on metric eigenvalues that an orthogonal change of the active index
+    leaves alone, and the XMS Fock matrix of Eq. 3 is a scalar over the
+    reference space.  Catches an active index contracted in the wrong slot
+    of a Gamma tensor or of the active Fock block."""
+    from synth.gen import rotate_active
+    for reading in ("A", "B"):
+        p = make_problem(2, 3, 4, 20, 2, seed=5, reading=reading, shift=0.15)
+        pr = rotate_active(p, seed=11)
+        assert np.abs(pr.eref - p.eref).max() < 1e-12
+        e = Caspt2Oracle(p).run().e_ms
+        er = Caspt2Oracle(pr).run().e_ms
+        assert np.abs(e - er).max() < 1e-10, (reading, e, er)
+
+
 def test_threshold_insensitivity(mid):
     p, o = mid
     for th in (1e-12, 1e-7):
