@@ -351,6 +351,43 @@ def test_active_rotation_invariance():
         assert np.abs(e - er).max() < 1e-10, (reading, e, er)
 
 
+@pytest.mark.parametrize("reading", ["A", "B", "C"])
+def test_operator_vanishes_on_metric_null_space(reading):
+    """A coefficient vector in the null space of a block's metric S describes
+    the zero function (Eq. 8 functions are linearly dependent), so the
+    operator of Eq. 10 maps it to zero in every block, couplings included.
+    The metric and the Fock metric are evaluated separately (the Fock one
+    through the Fock-contracted fourth-order density), so this catches a
+    dropped or misplaced pairing in one of them."""
+    p = make_problem(2, 3, 4, 20, 2, seed=5, reading=reading, shift=0.15)
+    o = Caspt2Oracle(p)
+    ort = o.ortho(0)
+    rng = np.random.default_rng(3)
+    checked = 0
+    for k, ent in enumerate(o.layout):
+        S = ort[k]["S"]
+        if ent["nrow"] == 0 or S.size == 0:
+            continue
+        w, V = np.linalg.eigh(S)
+        null = V[:, np.abs(w) < 1e-10 * np.abs(w).max()]
+        if null.shape[1] == 0:
+            continue
+        na_, off = ent["nalpha"], ent["offset"]
+        for r in rng.choice(ent["nrow"], size=min(2, ent["nrow"]), replace=False):
+            sl = slice(off + r * na_, off + (r + 1) * na_)
+            x = np.zeros(o.length)
+            v = null @ rng.standard_normal(null.shape[1])
+            x[sl] = v / np.linalg.norm(v)
+            y = np.zeros(o.length)
+            y[sl] = V[:, -1]          # a unit vector of the same row off the null space
+            for L in range(p.nst):
+                ref = np.linalg.norm(o.residual(L, y, with_source=False))
+                got = np.linalg.norm(o.residual(L, x, with_source=False))
+                assert got < 1e-10 * ref, (reading, k, int(r), L, got, ref)
+                checked += 1
+    assert checked >= 8
+
+
 def test_threshold_insensitivity(mid):
     p, o = mid
     for th in (1e-12, 1e-7):
