@@ -388,6 +388,32 @@ def test_operator_vanishes_on_metric_null_space(reading):
     assert checked >= 8
 
 
+def test_amplitudes_transform_covariantly():
+    """With the closed and virtual orbitals rotated (Reading C), T and lambda
+    are the Reading B ones with every closed and virtual slot transformed by
+    the same rotation: the functions of Eq. 8 transform as their external
+    orbitals, and the solution of Eq. 10 in the kept space of Sec. II.B (and
+    of Eq. 20) is unique.  Element by element, relative to each block's
+    largest amplitude."""
+    from oracle.ic import CLO, VIR
+    pb = make_problem(3, 3, 7, 26, 2, seed=9, reading="B", shift=0.2)
+    pc = make_problem(3, 3, 7, 26, 2, seed=9, reading="C", shift=0.2)
+    ob = Caspt2Oracle(pb).run()
+    oc = Caspt2Oracle(pc).run()
+    U = {CLO: pc.rot_c, VIR: pc.rot_v}
+    for L in range(pb.nst):
+        for vb, vc in ((ob.T[L], oc.T[L]), (ob.lam[L], oc.lam[L])):
+            tb, tc = ob.unpack(vb), oc.unpack(vc)
+            for b in BLOCKS:
+                t = tb[b.name]
+                if t.size == 0:
+                    continue
+                for ax, (_, sp) in enumerate(b.ext):
+                    t = np.moveaxis(np.tensordot(U[sp], t, axes=([0], [ax])), 0, ax)
+                scale = max(np.abs(tc[b.name]).max(), 1e-300)
+                assert np.abs(t - tc[b.name]).max() < 1e-9 * scale, (L, b.name)
+
+
 def test_threshold_insensitivity(mid):
     p, o = mid
     for th in (1e-12, 1e-7):
