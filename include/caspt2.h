@@ -25,10 +25,12 @@
  * the diagonal preconditioner); the closed-active, active-virtual and
  * closed-virtual blocks couple different excitation blocks; off-diagonal
  * closed-closed and virtual-virtual elements (orbitals that are not
- * semicanonical) couple each block with itself.  Both kinds of coupling are
- * applied by the same index-mapped kernels, so non-semicanonical orbitals
- * cost extra operator time (a sum over one closed or virtual index per
- * element).  Normal ordering with respect to the closed vacuum is taken as
+ * semicanonical) couple each block with itself; these run as batched GEMMs
+ * along one closed or virtual slot of the block, so non-semicanonical
+ * orbitals cost extra operator time, extra device memory (copies of the
+ * amplitudes with all orderings of their external indices) and extra PCG
+ * iterations (the diagonal preconditioner does not hold them).  Normal
+ * ordering with respect to the closed vacuum is taken as
  * {E_ij}_C = E_ij - 2 delta_ij.
  *
  * Hamiltonian: hcore = h^c, the one-electron operator dressed by the closed
