@@ -929,45 +929,6 @@ PackInfo pack_info(const H& h, int set, int block, const double* base, const std
   return p;
 }
 
-// A down term of a block with itself whose one summed label takes the place
-// of bra slot sb, the other ket slots being fed one to one by the remaining
-// bra slots, and whose Fock element is f(bra slot sb, summed label): it
-// applies f along slot sb of the ket tensor read with its slots permuted,
-// perm[l] being the bra slot that feeds ket slot l (sb for the summed one).
-bool slot_form(const int* ks, int fx, int fy, int nslot, int* sb_out, int* perm) {
-  int sb;
-  if (fx >= 0 && fy == -1) sb = fx;
-  else if (fy >= 0 && fx == -1) sb = fy;
-  else return false;
-  if (sb >= nslot) return false;
-  bool fed[4] = {false, false, false, false};
-  int nsum = 0;
-  for (int l = 0; l < nslot; ++l) {
-    const int v = ks[l];
-    if (v == -1) {
-      ++nsum;
-      perm[l] = sb;
-    } else if (v >= 0 && v < nslot && v != sb && !fed[v]) {
-      fed[v] = true;
-      perm[l] = v;
-    } else {
-      return false;
-    }
-  }
-  for (int l = nslot; l < 4; ++l) perm[l] = l;
-  *sb_out = sb;
-  return nsum == 1;
-}
-
-// the slot-permuted tensor equals x itself: the identity, or for ccvv the
-// joint exchange (i, a) <-> (j, b)
-bool perm_trivial(int block, const int* perm, int nslot) {
-  bool id = true;
-  for (int l = 0; l < nslot; ++l) id = id && perm[l] == l;
-  if (id) return true;
-  return block == CCVV && nslot == 4 && perm[0] == 1 && perm[1] == 0 && perm[2] == 3 && perm[3] == 2;
-}
-
 void setup_couplings(H& h) {
   const bool ss = h.d.scheme == CASPT2_SSSR;
   const int nst = h.nst;

@@ -66,6 +66,18 @@ struct Pairing {
 // of the closed and virtual operators.
 std::vector<Pairing> matrix_element(const OpString& bra, const OpString& op, const OpString& ket);
 
+// A down coupling term of a block with itself (ket slot sources ks: a bra
+// slot >= 0 or summed label -1 - s; Fock indices fx, fy likewise) whose one
+// summed label takes the place of one bra slot sb, the other ket slots being
+// fed one to one by the remaining bra slots, and whose Fock element is
+// f(bra slot sb, summed label): f applied along slot sb of the ket tensor
+// read with its slots permuted, perm[l] the bra slot feeding ket slot l (sb
+// for the summed one).  False for any other term.
+bool slot_form(const int* ks, int fx, int fy, int nslot, int* sb_out, int* perm);
+// the slot-permuted tensor equals x itself: the identity map, or for ccvv
+// the joint exchange (i, a) <-> (j, b)
+bool perm_trivial(int block, const int* perm, int nslot);
+
 // ---------------------------------------------------------------------------
 // determinant sectors of the active space
 // ---------------------------------------------------------------------------

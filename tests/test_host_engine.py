@@ -59,3 +59,20 @@ def test_engine_pairings_match_oracle(tmp_path):
     missing = sorted(set(ora) - set(eng))[:5]
     extra = sorted(set(eng) - set(ora))[:5]
     assert eng == ora, f"oracle-only: {missing}; engine-only: {extra}"
+
+
+def test_within_block_term_forms(tmp_path):
+    """Classification of the coupling terms of a block with itself (Fock
+    elements inside the closed or the virtual space): which run as a GEMM
+    along one slot, with which permutation of the ket slots, and which
+    permutations leave the amplitude tensor unchanged."""
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not available")
+    exe = tmp_path / "slot_forms"
+    subprocess.run([gxx, "-std=c++17", "-O1", f"-I{CSRC}", str(CSRC / "engine.cpp"),
+                    str(ROOT / "tests" / "host" / "slot_forms.cpp"), "-o", str(exe)], check=True)
+    r = subprocess.run([str(exe)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.strip() == "ok"
+
