@@ -1119,47 +1119,8 @@ void setup_couplings(H& h) {
     std::map<std::vector<int64_t>, size_t> seen;
     for (auto& t : cs) {
       int* ks = t.d.ket_src;
-      // images of the term that act identically: the ccvv ket read through
-      // the joint exchange of its slots (a symmetry of x), and the ccvv bra
-      // written through it (the packed result is the same: the exchange has
-      // character +1 in both ccvv entries).  Among them the form that a slot
-      // GEMM can run without a permuted copy of x and with f along an inner
-      // slot is preferred, then the lexicographically smallest.
-      {
-        auto pi = [](int v) { return v >= 0 && v < 4 ? (v ^ 1) : v; };
-        const bool kswap = !t.up && t.ket == CCVV && t.d.ket.nslot == 4;
-        const bool bswap = t.bra == CCVV && t.d.bra.nslot == 4;
-        auto score = [&](const int* c) {
-          int sb, perm[4];
-          if (t.up || t.bra != t.ket || t.d.nsum != 1 || t.d.ny != 1 ||
-              !slot_form(c, c[4], c[5], t.d.ket.nslot, &sb, perm))
-            return 4;
-          return (perm_trivial(t.ket, perm, t.d.ket.nslot) ? 0 : 2) + (sb == t.d.bra.nslot - 1 ? 1 : 0);
-        };
-        int best[6] = {ks[0], ks[1], ks[2], ks[3], t.d.fx_src, t.d.fy_src};
-        int best_score = score(best);
-        for (int m = 1; m < 4; ++m) {
-          if (((m & 1) && !kswap) || ((m & 2) && !bswap)) continue;
-          int c[6] = {ks[0], ks[1], ks[2], ks[3], t.d.fx_src, t.d.fy_src};
-          if (m & 1) {
-            std::swap(c[0], c[1]);
-            std::swap(c[2], c[3]);
-          }
-          if (m & 2) {
-            for (int l = 0; l < t.d.ket.nslot; ++l) c[l] = pi(c[l]);
-            c[4] = pi(c[4]);
-            c[5] = pi(c[5]);
-          }
-          const int sc = score(c);
-          if (sc < best_score || (sc == best_score && std::lexicographical_compare(c, c + 6, best, best + 6))) {
-            std::copy(c, c + 6, best);
-            best_score = sc;
-          }
-        }
-        std::copy(best, best + 4, ks);
-        t.d.fx_src = best[4];
-        t.d.fy_src = best[5];
-      }
+      canonical_term(t.up, t.bra, t.ket, t.d.bra.nslot, t.d.ket.nslot, t.d.nsum, t.d.ny, ks, &t.d.fx_src,
+                     &t.d.fy_src);
       const std::vector<int64_t> key = {t.up, t.bra, t.ket, ks[0], ks[1], ks[2], ks[3], t.d.fx_src, t.d.fy_src,
                                         t.f_off, t.d.nsum, t.d.sum_dim[0], t.d.sum_dim[1], t.d.ny, t.d.ncol,
                                         t.G.n};

@@ -264,4 +264,45 @@ bool perm_trivial(int block, const int* perm, int nslot) {
   return block == CCVV && nslot == 4 && perm[0] == 1 && perm[1] == 0 && perm[2] == 3 && perm[3] == 2;
 }
 
+// Images of a coupling term that act identically: the ccvv ket read through
+// the joint exchange (i, a) <-> (j, b) of its slots (a symmetry of x), and
+// the ccvv bra written through it (the packed result is the same: the
+// exchange has character +1 in both ccvv entries).  Among them the form that
+// a slot GEMM can run without a permuted copy of x and with f along an inner
+// slot is preferred, then the lexicographically smallest (ks, fx, fy).
+void canonical_term(bool up, int bra, int ket, int nslot_b, int nslot_k, int nsum, int ny, int* ks, int* fx,
+                    int* fy) {
+  auto pi = [](int v) { return v >= 0 && v < 4 ? (v ^ 1) : v; };
+  const bool kswap = !up && ket == CCVV && nslot_k == 4;
+  const bool bswap = bra == CCVV && nslot_b == 4;
+  auto score = [&](const int* c) {
+    int sb, perm[4];
+    if (up || bra != ket || nsum != 1 || ny != 1 || !slot_form(c, c[4], c[5], nslot_k, &sb, perm)) return 4;
+    return (perm_trivial(ket, perm, nslot_k) ? 0 : 2) + (sb == nslot_b - 1 ? 1 : 0);
+  };
+  int best[6] = {ks[0], ks[1], ks[2], ks[3], *fx, *fy};
+  int best_score = score(best);
+  for (int m = 1; m < 4; ++m) {
+    if (((m & 1) && !kswap) || ((m & 2) && !bswap)) continue;
+    int c[6] = {ks[0], ks[1], ks[2], ks[3], *fx, *fy};
+    if (m & 1) {
+      std::swap(c[0], c[1]);
+      std::swap(c[2], c[3]);
+    }
+    if (m & 2) {
+      for (int l = 0; l < nslot_k; ++l) c[l] = pi(c[l]);
+      c[4] = pi(c[4]);
+      c[5] = pi(c[5]);
+    }
+    const int sc = score(c);
+    if (sc < best_score || (sc == best_score && std::lexicographical_compare(c, c + 6, best, best + 6))) {
+      std::copy(c, c + 6, best);
+      best_score = sc;
+    }
+  }
+  std::copy(best, best + 4, ks);
+  *fx = best[4];
+  *fy = best[5];
+}
+
 }  // namespace caspt2

@@ -77,6 +77,13 @@ bool slot_form(const int* ks, int fx, int fy, int nslot, int* sb_out, int* perm)
 // the slot-permuted tensor equals x itself: the identity map, or for ccvv
 // the joint exchange (i, a) <-> (j, b)
 bool perm_trivial(int block, const int* perm, int nslot);
+// Canonical form of a coupling term (ket slot sources ks[4], Fock indices
+// fx, fy; rewritten in place) among the images that give the same packed
+// contribution: the ccvv ket read through its joint slot exchange, the ccvv
+// bra written through it.  Prefers the form a slot GEMM runs without a
+// permuted copy and with f along an inner slot, then the smallest.
+void canonical_term(bool up, int bra, int ket, int nslot_b, int nslot_k, int nsum, int ny, int* ks, int* fx,
+                    int* fy);
 
 // ---------------------------------------------------------------------------
 // determinant sectors of the active space

@@ -73,6 +73,36 @@ int main() {
     const int ks[4] = {-1, 0, 0, 0};
     expect(slot_form(ks, 0, -1, 1, &sb, perm) && sb == 0 && perm[0] == 0, "one-slot block");
   }
+  // canonical forms of the eight Wick pairings of <ccvv| f_vv E |ccvv> (closed
+  // labels paired straight or crossed; x paired with the bra's a or b, y with
+  // the ket's a or b): they act as two distinct terms, f along the bra's
+  // first virtual slot with the ket read in place or with its virtual pair
+  // exchanged
+  {
+    const int in[8][5] = {{0, 1, 3, -1, 2}, {0, 1, -1, 3, 2}, {0, 1, 2, -1, 3}, {0, 1, -1, 2, 3},
+                          {1, 0, 3, -1, 2}, {1, 0, -1, 3, 2}, {1, 0, 2, -1, 3}, {1, 0, -1, 2, 3}};
+    const int want_in_place[6] = {0, 1, -1, 3, 2, -1}, want_exchanged[6] = {0, 1, 3, -1, 2, -1};
+    int n_in_place = 0, n_exchanged = 0;
+    for (const auto& t : in) {
+      int ks[4] = {t[0], t[1], t[2], t[3]}, fx = t[4], fy = -1;
+      canonical_term(false, CCVV, CCVV, 4, 4, 1, 1, ks, &fx, &fy);
+      const int got[6] = {ks[0], ks[1], ks[2], ks[3], fx, fy};
+      if (same(got, want_in_place, 6)) ++n_in_place;
+      else if (same(got, want_exchanged, 6)) ++n_exchanged;
+      else expect(false, "ccvv virtual pairing canonicalises to one of the two forms");
+    }
+    expect(n_in_place == 4 && n_exchanged == 4, "four pairings per ccvv form");
+    // the in-place form runs as a slot GEMM without a copy, on inner slot 2
+    int ks[4] = {0, 1, -1, 3};
+    expect(slot_form(ks, 2, -1, 4, &sb, perm) && sb == 2 && perm_trivial(CCVV, perm, 4), "in-place form");
+  }
+  // a term between different blocks keeps its form when nothing applies
+  {
+    int ks[4] = {2, 0, 1, 0}, fx = -1, fy = -10;
+    canonical_term(false, CAVV, CCAV, 3, 3, 1, 8, ks, &fx, &fy);
+    const int got[6] = {ks[0], ks[1], ks[2], ks[3], fx, fy}, want[6] = {2, 0, 1, 0, -1, -10};
+    expect(same(got, want, 6), "no symmetry: unchanged");
+  }
   if (fails) return EXIT_FAILURE;
   std::printf("ok\n");
   return 0;
