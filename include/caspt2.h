@@ -217,16 +217,37 @@ CASPT2_API int caspt2_set_streams(caspt2_handle* h, int32_t n);
 /* Solve Eq. 10 for every state by preconditioned conjugate gradients in the
  * orthonormal kept basis (preconditioner: external orbital energies +
  * E_s - E_L + eigenvalues of the block Fock metric).  Stops when the
- * residual 2-norm <= tol.  info: host array [nst] or NULL.
- * Returns E_NOCONV if any state hit maxiter, E_INDEFINITE as documented. */
-CASPT2_API int caspt2_solve_amplitudes(caspt2_handle* h, double tol, int32_t maxiter, caspt2_info* info);
+ * residual 2-norm <= tol.  T0: device [nst][length] packed starting
+ * amplitudes (warm start, e.g. the result of an earlier call that stopped
+ * at maxiter, read with caspt2_get_amplitudes), or NULL to start from zero;
+ * only its S-orthogonal projection on the kept space enters (components
+ * along dropped overlap eigenvectors are zero functions).  info: host array
+ * [nst] or NULL.  Returns E_NOCONV if any state hit maxiter (the last
+ * iterate is stored and can be read and resumed from), E_INDEFINITE as
+ * documented. */
+CASPT2_API int caspt2_solve_amplitudes(caspt2_handle* h, double tol, int32_t maxiter, const double* T0,
+                                       caspt2_info* info);
 /* Copy T_L (packed, device) after caspt2_solve_amplitudes; E_STATE before. */
 CASPT2_API int caspt2_get_amplitudes(caspt2_handle* h, int32_t L, double* T);
 
-/* XMS rotation computed at create (Eqs. 3-5): U [nst][nst] (column M is the
- * rotated state |M~>, ascending E~, largest-magnitude entry of each column
- * positive; identity when dims.xms = 0) and E_L^(0) [nst] (Eq. 14). host. */
-CASPT2_API int xms_rotate(const caspt2_handle* h, double* U, double* e0);
+/* XMS rotation (Eqs. 3-5) on its own: the Fock operator in the reference
+ * space, F_MN = sum_rs f_rs <M|E_rs|N> (active part; the closed part only
+ * adds a constant to the diagonal, Eq. 12), symmetrised and diagonalised:
+ * F U = U diag(E~).  f_act [nact][nact] and rdm1 [nst][nst][nact][nact]
+ * (rdm1[M][N][r][s] = <M|E_rs|N> of the states before rotation) host,
+ * read only; U [nst][nst] (column M is |M~> = sum_N |N> U[N][M]) and
+ * e0 [nst] = E~ ascending (= E_M^(0) of Eq. 14 for the rotated states)
+ * host outputs; each column of U has its largest-magnitude entry positive.
+ * Rotated transition densities follow as G~^{MN} = sum_KL U[K][M] U[L][N]
+ * G^{KL}.  Runs on the current HIP device.  Errors: E_ARG (nact < 0,
+ * nst < 1 or > 16, NULL or non-finite input), E_DEVICE. */
+CASPT2_API int xms_rotate(int32_t nact, int32_t nst, const double* f_act, const double* rdm1, double* U,
+                          double* e0);
+
+/* The XMS rotation a handle applied at create (dims.xms = 1; identity when
+ * 0): U [nst][nst] and E_L^(0) [nst] (Eq. 14), as xms_rotate returns them
+ * for the handle's f and reference states.  host outputs, each may be NULL. */
+CASPT2_API int caspt2_get_xms(const caspt2_handle* h, double* U, double* e0);
 
 /* Effective Hamiltonian (Eq. 15), its eigenvalues E^MS ascending (Eq. 17)
  * and eigenvectors R (Eq. 16, columns, largest-magnitude entry positive).
@@ -234,10 +255,39 @@ CASPT2_API int xms_rotate(const caspt2_handle* h, double* U, double* e0);
 CASPT2_API int xms_heff(caspt2_handle* h, double* heff, double* e_ms, double* R);
 
 /* Solve the lambda equation (Eq. 20) for target state P with the same
- * operator and solver as the amplitudes.  E_STATE before xms_heff. */
+ * operator and solver as the amplitudes.  lam0: device [nst][length] packed
+ * starting multipliers (warm start) or NULL, as T0 of
+ * caspt2_solve_amplitudes.  E_STATE before xms_heff. */
 CASPT2_API int caspt2_solve_lambda(caspt2_handle* h, int32_t target, double tol, int32_t maxiter,
-                        caspt2_info* info);
+                                   const double* lam0, caspt2_info* info);
 CASPT2_API int caspt2_get_lambda(caspt2_handle* h, int32_t L, double* lambda);
+
+/* Correlated density matrices of Sec. II.D (Eqs. 24-30) for the target
+ * state P of the last lambda solve (caspt2_solve_lambda or the batch), with
+ * the mixed states |P> = sum_M |M~> R_MP and T_PN = sum_M T_MN R_MP:
+ *   d1[x][y]  = sum_M <M~|T_PM^+ E_xy|P> + sum_MN <M~|lambda_NM^+ E_xy|N~>
+ *   D1        = the same with E_xy,zw = E_xy E_zw - delta_yz E_xw
+ *   dbar2[x][y] = sum_LMN <M~|lambda_LM^+ E_xy T_LN|N~>
+ *   NL[L]     = sum_MN <M~|lambda_LM^+ T_LN|N~>
+ *   d2        = dbar2 - sum_L NL[L] <L~|E_xy|L~> for active x, y; dbar2 else.
+ * E_xy is the plain spin-summed excitation (E_ii on a closed orbital counts
+ * its electrons).  d1 is non-zero only where x is active or virtual and y
+ * active or closed, not both active.  D1 covers the classes of the
+ * two-body part of H that act on the references (x, z active or virtual; y,
+ * w active or closed; not all four active): caspt2_density2_length doubles,
+ * class k (0..14) at the offset and with the orbital spaces (0 closed,
+ * 1 active, 2 virtual, for x, y, z, w) caspt2_density2_layout returns,
+ * stored [x][y][z][w] row major over the class's orbitals.  With these,
+ * dE^MS_P/dh^c_xy = <P|E_xy|P> + d1_xy and dE^MS_P/d(xy|zw) =
+ * (<P|E_xy,zw|P> + D1_xyzw)/2 at fixed reference states and f, and
+ * dE^MS_P/df_xy = d2_xy (minus 2 sum_L NL[L] on the closed diagonal,
+ * Eq. 12) at fixed references and XMS rotation.
+ * d1, dbar2, d2: host [nmo][nmo]; D1: device [caspt2_density2_length];
+ * NL: host [nst]; each may be NULL.  E_STATE before caspt2_solve_lambda. */
+CASPT2_API int caspt2_densities(caspt2_handle* h, double* d1, double* D1, double* dbar2, double* d2,
+                                double* NL);
+CASPT2_API int64_t caspt2_density2_length(const caspt2_handle* h);
+CASPT2_API int caspt2_density2_layout(const caspt2_handle* h, int32_t k, int64_t* offset, int32_t* spaces);
 
 /* Batched solves over many independent problems (handles created with the
  * same precision, CASPT2_FP64 or CASPT2_MIXED; the problems may differ in

@@ -53,6 +53,15 @@ CASPT2_API int caspt2_debug_eigh(int32_t n, double* A, double* w, double* V);
 CASPT2_API int caspt2_debug_eigh_method(int32_t n, double* A, double* w, double* V, int32_t method,
                                         int32_t* sweeps);
 
+/* The same with an absolute stopping bound for the whole-device forms:
+ * sweeps continue until the off-diagonal norm is also <= abs_tol (or stops
+ * decreasing).  The set-up solves each block metric this way with abs_tol =
+ * 0.1 times the overlap threshold (Sec. II.B), so that no eigenvalue outside
+ * 0.9..1.1 times the threshold is misjudged.  method 0 picks the form by size exactly as
+ * the set-up does.  E_ARG for a negative or non-finite abs_tol. */
+CASPT2_API int caspt2_debug_eigh_abs(int32_t n, double* A, double* w, double* V, int32_t method,
+                                     double abs_tol, int32_t* sweeps);
+
 #ifdef __cplusplus
 }
 #endif

@@ -206,21 +206,28 @@ def ic_labels(sysm: BruteSystem):
 
 
 def solve_brute(prob, scheme: str = "MSMR", xms: bool = True, thresh: float = 1e-9,
-                target: int = 0, want_lambda: bool = True):
+                target: int = 0, want_lambda: bool = True, sysm: BruteSystem | None = None,
+                fixed_U: np.ndarray | None = None):
     """Galerkin solution of Eq. 10 in the explicit IC space; Eq. 15-17; Eq. 20.
 
     Returns a dict with U, e0 (E_L^(0)), heff, e_ms, R, and per state L the
     overlap S, operator A_L, source b_L (non-orthogonal, over the IC labels x
     states in the function basis of that L), T_L and lambda_L.
+    sysm: operators to use instead of BruteSystem(prob) (e.g. with changed
+    integrals); fixed_U: XMS rotation to use instead of diagonalising F^ref
+    (derivatives at fixed reference states).
     """
-    sysm = BruteSystem(prob)
+    if sysm is None:
+        sysm = BruteSystem(prob)
     n = sysm.nmo
     nst = prob.nst
     refs = sysm.reference_states()
     # XMS rotation, Eq. 3-5
     fref = np.array([[dot(refs[L], sysm.apply_fock(refs[M])) for M in range(nst)]
                      for L in range(nst)])
-    if xms:
+    if fixed_U is not None:
+        U = np.array(fixed_U, dtype=float)
+    elif xms:
         w, U = np.linalg.eigh(0.5 * (fref + fref.T))
         for k in range(nst):
             if U[np.argmax(np.abs(U[:, k])), k] < 0:
@@ -251,7 +258,8 @@ def solve_brute(prob, scheme: str = "MSMR", xms: bool = True, thresh: float = 1e
                 keys.append((t, (p, q, r, s), N))
         return cols, keys
 
-    out = {"U": U, "e0": e0, "href": href, "fref": fref, "L": {}}
+    out = {"U": U, "e0": e0, "href": href, "fref": fref, "L": {}, "rot": rot, "sysm": sysm,
+           "scheme": scheme}
     Ts, Vs, Ss, keys_all, As = [], [], [], [], []
     for L in range(nst):
         states = list(range(nst)) if scheme == "MSMR" else [L]
@@ -319,4 +327,82 @@ def solve_brute(prob, scheme: str = "MSMR", xms: bool = True, thresh: float = 1e
             At = X.T @ dL["A"] @ X
             lt = np.linalg.solve(At, -(X.T @ src))
             dL["lam"] = X @ lt
+        out["target"] = P
     return out
+
+
+# ---------------------------------------------------------------------------
+# correlated density matrices, Sec. II.D
+# ---------------------------------------------------------------------------
+
+def _first_order_vector(out, L, coef) -> dict:
+    """sum_k coef[k] E_Omega(k)|N~> over the function set of state L, as an
+    explicit determinant expansion."""
+    Vm, dets = out["Vm"][0] if out["scheme"] == "MSMR" else out["Vm"][L]
+    v = Vm @ coef
+    return {d: c for d, c in zip(dets, v) if c != 0.0}
+
+
+def _apply_E2(vec: dict, x: int, y: int, z: int, w: int, n: int) -> dict:
+    """E_xy,zw = E_xy E_zw - delta_yz E_xw (the two-particle excitation)."""
+    r = apply_E(apply_E(vec, z, w, n), x, y, n)
+    if y == z:
+        axpy(r, -1.0, apply_E(vec, x, w, n))
+    return r
+
+
+def densities_brute(prob, out) -> dict:
+    """The correlated densities of Sec. II.D written out on explicit
+    determinants, from a solve_brute result with lambda (target P):
+
+      |P> = sum_M |M~> R_MP,   T_PN = sum_M T_MN R_MP (mixed states),
+      d1_xy   = sum_M <M~|T_PM^+ E_xy|P> + sum_MN <M~|lambda_NM^+ E_xy|N~>,
+      D1_xyzw = the same with E_xy,zw = E_xy E_zw - delta_yz E_xw,
+      dbar2_xy = sum_LMN <M~|lambda_LM^+ E_xy T_LN|N~>,
+      N_L = sum_MN <M~|lambda_LM^+ T_LN|N~>  (the dagger the printed N_L lacks),
+      d2_xy = dbar2_xy - sum_L N_L <L~|E_xy|L~> for active x, y; dbar2_xy otherwise.
+
+    Orbital indices are absolute (closed | active | virtual).  Also returned:
+    gamma_P = <P|E_xy|P> and Gamma_P = <P|E_xy,zw|P> (the reference part,
+    needed by the finite-difference checks)."""
+    sysm, rot = out["sysm"], out["rot"]
+    n = sysm.nmo
+    nst = prob.nst
+    P = out["target"]
+    R = out["R"]
+    Pv: dict = {}
+    for M in range(nst):
+        axpy(Pv, R[M, P], rot[M])
+    psi = [_first_order_vector(out, L, out["L"][L]["T"]) for L in range(nst)]
+    lam = [_first_order_vector(out, L, out["L"][L]["lam"]) for L in range(nst)]
+    # T_P = sum_L R_LP Psi1_L  (the bra of the first term of d1 and D1)
+    tp: dict = {}
+    for L in range(nst):
+        axpy(tp, R[L, P], psi[L])
+    d1 = np.zeros((n, n))
+    D1 = np.zeros((n, n, n, n))
+    gam = np.zeros((n, n))
+    Gam = np.zeros((n, n, n, n))
+    for x in range(n):
+        for y in range(n):
+            eP = apply_E(Pv, x, y, n)
+            gam[x, y] = dot(Pv, eP)
+            d1[x, y] = dot(tp, eP) + sum(dot(lam[N], apply_E(rot[N], x, y, n)) for N in range(nst))
+            for z in range(n):
+                for w in range(n):
+                    e2 = _apply_E2(Pv, x, y, z, w, n)
+                    Gam[x, y, z, w] = dot(Pv, e2)
+                    D1[x, y, z, w] = dot(tp, e2) + sum(dot(lam[N], _apply_E2(rot[N], x, y, z, w, n))
+                                                       for N in range(nst))
+    dbar2 = np.zeros((n, n))
+    for x in range(n):
+        for y in range(n):
+            dbar2[x, y] = sum(dot(lam[L], apply_E(psi[L], x, y, n)) for L in range(nst))
+    NL = np.array([dot(lam[L], psi[L]) for L in range(nst)])
+    d2 = dbar2.copy()
+    act = range(prob.nc, prob.nc + prob.na)
+    for L in range(nst):
+        for r in act:
+            for t in act:
+                d2[r, t] -= NL[L] * dot(rot[L], apply_E(rot[L], r, t, n))
+    return dict(d1=d1, D1=D1, dbar2=dbar2, NL=NL, d2=d2, gamma_P=gam, Gamma_P=Gam)

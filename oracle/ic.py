@@ -968,4 +968,103 @@ class Caspt2Oracle:
         self.solve_amplitudes(tol=tol)
         self.heff()
         self.solve_lambda(P, tol=tol)
+        self.target = P
         return self
+
+    # -- correlated densities, Sec. II.D ------------------------------------
+    @staticmethod
+    def _einsum_to(spec_in: str, out: str, shape, *ops):
+        """einsum into the output subscripts `out` (array of the given shape).
+        `out` may repeat a letter (a pairing that sets two operator indices
+        equal: the result goes on that diagonal) and may hold letters absent
+        from the inputs (an operator index contracted with the other one of
+        the same operator: the result does not depend on it)."""
+        uniq = "".join(dict.fromkeys(out))
+        ins = set(spec_in.replace(",", ""))
+        present = "".join(c for c in uniq if c in ins)
+        r = np.einsum(f"{spec_in}->{present}", *ops, optimize=True)
+        if present == out:
+            return r
+        dims = [shape[out.index(c)] for c in uniq]
+        idx = np.indices(dims)
+        val = r[tuple(idx[uniq.index(c)] for c in present)] if present else np.full(dims, float(r))
+        full = np.zeros(shape)
+        np.add.at(full, tuple(idx[uniq.index(c)] for c in out), val)
+        return full
+
+    def _space_of_label(self, ops, lab):
+        return next(o.space for o in ops if o.label == lab)
+
+    def densities(self):
+        """d^(1), D^(1), d-bar^(2), N_L and d^(2) of Sec. II.D for the target
+        state P of run(P), in factorised form: every density element is the
+        derivative of a matrix element already used by the amplitude
+        equation with respect to its operator coefficient, i.e. the same Wick
+        terms and active Gram tensors contracted with T, lambda and R instead
+        of with the integrals or f.
+
+        Returns d1 [nmo][nmo], D1 {spaces (p, q, r, s): [p][q][r][s]} over the
+        classes of the two-body part of H that act on the references
+        (creators p, r active or virtual; annihilators q, s active or closed;
+        not all active), dbar2 and d2 [nmo][nmo], NL [nst]."""
+        P = self.target
+        nst, R = self.nst, self.R
+        nmo = self.nc + self.na + self.nv
+        T_all = [self.unpack(v) for v in self.T]
+        l_all = [self.unpack(v) for v in self.lam]
+        # weights W[e..., alpha over every state's functions, ket N]
+        W = {}
+        for b in BLOCKS:
+            shape = tuple(self.dimsp[sp] for (_, sp) in b.ext) + (self.nst * len(b.types) * self.ntup[b.name], nst)
+            W[b.name] = np.zeros(shape)
+        for L in range(nst):
+            for b in BLOCKS:
+                sl = slice(None) if self.scheme == "MSMR" else self._alpha_slice(b, L)
+                for N in range(nst):
+                    W[b.name][..., sl, N] += R[L, P] * R[N, P] * T_all[L][b.name]
+                W[b.name][..., sl, L] += l_all[L][b.name]
+        d1 = np.zeros((nmo, nmo))
+        D1 = {}
+        for hi, (ops, C, clabels) in enumerate(self.ham_components()):
+            spaces = tuple(self._space_of_label(ops, lab) for lab in clabels)
+            acc = np.zeros(C.shape)
+            for bb in BLOCKS:
+                for spec, _, G, _ in self._plan(("H", hi, bb.name), bb, None, ops, C, clabels):
+                    cstr, rest = spec.split(",", 1)
+                    gstr, outz = rest.split("->")
+                    acc += self._einsum_to(f"{outz},{gstr}", cstr, acc.shape, W[bb.name], G)
+            if len(clabels) == 2:
+                d1[self.sl[spaces[0]], self.sl[spaces[1]]] += acc
+            else:
+                D1[spaces] = acc
+        # d-bar^(2): every block of f, whatever its values
+        dbar2 = np.zeros((nmo, nmo))
+        for sx in (CLO, ACT, VIR):
+            for sy in (CLO, ACT, VIR):
+                if self.dimsp[sx] == 0 or self.dimsp[sy] == 0:
+                    continue
+                ops = E("x_o", sx, "y_o", sy, "so")
+                dummy = np.zeros((self.dimsp[sx], self.dimsp[sy]))
+                acc = np.zeros_like(dummy)
+                for bb in BLOCKS:
+                    for kb in BLOCKS:
+                        plans = self._plan(("D2", sx, sy, bb.name, kb.name), bb, kb, ops, dummy,
+                                           ["x_o", "y_o"])
+                        for spec, _, G, _ in plans:
+                            cstr, gstr, rest = spec.split(",")
+                            xstr, outs = rest.split("->")
+                            for L in range(nst):
+                                Gr = self._restrict(G, bb, kb, L)
+                                acc += self._einsum_to(f"{outs},{gstr},{xstr}", cstr, acc.shape,
+                                                       l_all[L][bb.name], Gr, T_all[L][kb.name])
+                dbar2[self.sl[sx], self.sl[sy]] += acc
+        NL = np.array([self.lam[L] @ self.apply_S(L, self.T[L]) for L in range(nst)])
+        d2 = dbar2.copy()
+        sa = self.sl[ACT]
+        for r in range(self.na):
+            for t in range(self.na):
+                unit = np.zeros((self.na, self.na))
+                unit[r, t] = 1.0
+                g = self._one_body(unit, self.ci)
+                d2[sa.start + r, sa.start + t] -= sum(NL[L] * g[L, L] for L in range(nst))
+        return dict(d1=d1, D1=D1, dbar2=dbar2, NL=NL, d2=d2)

@@ -14,7 +14,7 @@ from . import _lib
 from ._lib import (E_ARG, E_DEVICE, E_INDEFINITE, E_NOCONV, E_NOMEM, E_NOTIMPL, E_STATE, ENTRY_NAMES,
                    FP64, MIXED, MSMR, OK, SSSR, Caspt2Error)
 
-__all__ = ["Caspt2", "Caspt2Error", "batch_solve", "lib", "MSMR", "SSSR", "FP64", "MIXED", "ENTRY_NAMES"]
+__all__ = ["Caspt2", "Caspt2Error", "batch_solve", "xms_rotate", "lib", "MSMR", "SSSR", "FP64", "MIXED", "ENTRY_NAMES"]
 
 _LIB = None
 
@@ -46,6 +46,8 @@ class Caspt2:
         import torch
         L = lib()
         self.nst = nstates
+        self.nc, self.na, self.nv = nclosed, nact, nvirt
+        self.nmo = nclosed + nact + nvirt
         d = _lib.Dims(nclosed, nact, nvirt, naux, nstates, nelec, scheme, 1 if xms else 0, int(precision), 0,
                       float(shift), float(thresh))
         arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (fock, hcore, dfB, ci, eref)]
@@ -121,9 +123,11 @@ class Caspt2:
         _check(lib().caspt2_residual_all(self._h, 1 if with_source else 0, _ptr(x), _ptr(sigma)),
                "caspt2_residual_all")
 
-    def solve_amplitudes(self, tol=1e-10, maxiter=200):
+    def solve_amplitudes(self, tol=1e-10, maxiter=200, T0=None):
+        """T0: optional device tensor [nst][length] of starting amplitudes."""
         info = (_lib.Info * self.nst)()
-        rc = _check(lib().caspt2_solve_amplitudes(self._h, tol, maxiter, info),
+        p0 = None if T0 is None else _ptr(T0)
+        rc = _check(lib().caspt2_solve_amplitudes(self._h, tol, maxiter, p0, info),
                     "caspt2_solve_amplitudes", allow=(OK, E_NOCONV))
         return rc, [i.as_dict() for i in info]
 
@@ -134,9 +138,11 @@ class Caspt2:
         return t
 
     def xms_rotate(self):
+        """The XMS rotation U and E^(0) the handle applied at creation."""
         U = np.zeros((self.nst, self.nst))
         e0 = np.zeros(self.nst)
-        _check(lib().xms_rotate(self._h, U.ctypes.data_as(_lib._D), e0.ctypes.data_as(_lib._D)), "xms_rotate")
+        _check(lib().caspt2_get_xms(self._h, U.ctypes.data_as(_lib._D), e0.ctypes.data_as(_lib._D)),
+               "caspt2_get_xms")
         return U, e0
 
     def heff(self):
@@ -146,17 +152,58 @@ class Caspt2:
                               R.ctypes.data_as(_lib._D)), "xms_heff")
         return H, w, R
 
-    def solve_lambda(self, target=0, tol=1e-10, maxiter=200):
+    def solve_lambda(self, target=0, tol=1e-10, maxiter=200, lam0=None):
+        """lam0: optional device tensor [nst][length] of starting multipliers."""
         info = (_lib.Info * self.nst)()
-        rc = _check(lib().caspt2_solve_lambda(self._h, target, tol, maxiter, info),
+        p0 = None if lam0 is None else _ptr(lam0)
+        rc = _check(lib().caspt2_solve_lambda(self._h, target, tol, maxiter, p0, info),
                     "caspt2_solve_lambda", allow=(OK, E_NOCONV))
         return rc, [i.as_dict() for i in info]
+
+    def densities(self):
+        """Correlated densities of the target state of the last lambda solve:
+        dict with d1, dbar2, d2 ([nmo][nmo] numpy), NL ([nst]) and D1
+        ({(spaces of x, y, z, w): device tensor [x][y][z][w]}, spaces 'c',
+        'a', 'v')."""
+        import torch
+        L = lib()
+        nmo = self.nmo
+        d1, db, d2 = np.zeros((nmo, nmo)), np.zeros((nmo, nmo)), np.zeros((nmo, nmo))
+        NL = np.zeros(self.nst)
+        n2 = int(L.caspt2_density2_length(self._h))
+        D1 = torch.empty(max(n2, 1), dtype=torch.float64, device="cuda")
+        _check(L.caspt2_densities(self._h, d1.ctypes.data_as(_lib._D), _ptr(D1), db.ctypes.data_as(_lib._D),
+                                  d2.ctypes.data_as(_lib._D), NL.ctypes.data_as(_lib._D)), "caspt2_densities")
+        dims = {"c": self.nc, "a": self.na, "v": self.nv}
+        out = {}
+        for k in range(15):
+            o = ctypes.c_int64()
+            sp = (ctypes.c_int32 * 4)()
+            _check(L.caspt2_density2_layout(self._h, k, ctypes.byref(o), sp), "caspt2_density2_layout")
+            key = tuple("cav"[sp[a]] for a in range(4))
+            shape = tuple(dims[c] for c in key)
+            n = int(np.prod(shape))
+            out[key] = D1[o.value:o.value + n].view(shape)
+        return dict(d1=d1, D1=out, dbar2=db, d2=d2, NL=NL)
 
     def lam(self, L):
         import torch
         t = torch.empty(self.length, dtype=torch.float64, device="cuda")
         _check(lib().caspt2_get_lambda(self._h, L, _ptr(t)), "caspt2_get_lambda")
         return t
+
+
+def xms_rotate(f_act, rdm1):
+    """Standalone XMS rotation (Eqs. 3-5) on the current device: f_act
+    [na][na], rdm1 [nst][nst][na][na] = <M|E_rs|N>; returns (U, E~)."""
+    f = np.ascontiguousarray(f_act, dtype=np.float64)
+    g = np.ascontiguousarray(rdm1, dtype=np.float64)
+    nst, na = g.shape[0], f.shape[0]
+    U = np.zeros((nst, nst))
+    e0 = np.zeros(nst)
+    _check(lib().xms_rotate(na, nst, f.ctypes.data_as(_lib._D), g.ctypes.data_as(_lib._D),
+                            U.ctypes.data_as(_lib._D), e0.ctypes.data_as(_lib._D)), "xms_rotate")
+    return U, e0
 
 
 def batch_solve(problems, targets=None, tol=1e-10, maxiter=200):

@@ -60,11 +60,12 @@ SIGNATURES = {
                                      ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
     "caspt2_residual": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P, _P]),
     "caspt2_residual_all": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P]),
-    "caspt2_solve_amplitudes": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(Info)]),
+    "caspt2_solve_amplitudes": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int32, _P, ctypes.POINTER(Info)]),
     "caspt2_get_amplitudes": (ctypes.c_int, [_P, ctypes.c_int32, _P]),
-    "xms_rotate": (ctypes.c_int, [_P, _D, _D]),
+    "xms_rotate": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _D, _D, _D, _D]),
+    "caspt2_get_xms": (ctypes.c_int, [_P, _D, _D]),
     "xms_heff": (ctypes.c_int, [_P, _D, _D, _D]),
-    "caspt2_solve_lambda": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+    "caspt2_solve_lambda": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, _P,
                                            ctypes.POINTER(Info)]),
     "caspt2_get_lambda": (ctypes.c_int, [_P, ctypes.c_int32, _P]),
     "caspt2_batch_solve": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
@@ -84,6 +85,12 @@ SIGNATURES = {
     "caspt2_set_verbose": (ctypes.c_int, [_P, ctypes.c_int32]),
     "caspt2_debug_eigh_method": (ctypes.c_int, [ctypes.c_int32, _P, _D, _P, ctypes.c_int32,
                                                 ctypes.POINTER(ctypes.c_int32)]),
+    "caspt2_debug_eigh_abs": (ctypes.c_int, [ctypes.c_int32, _P, _D, _P, ctypes.c_int32, ctypes.c_double,
+                                             ctypes.POINTER(ctypes.c_int32)]),
+    "caspt2_densities": (ctypes.c_int, [_P, _D, _P, _D, _D, _D]),
+    "caspt2_density2_length": (ctypes.c_int64, [_P]),
+    "caspt2_density2_layout": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
+                                              ctypes.POINTER(ctypes.c_int32)]),
     "caspt2_last_error": (ctypes.c_char_p, []),
 }
 

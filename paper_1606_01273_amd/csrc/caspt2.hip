@@ -76,6 +76,32 @@ struct DevBuf {
 using DBuf = DevBuf<double>;
 using FBuf = DevBuf<float>;
 
+// page-locked host buffer (hipHostMalloc): every device-to-host copy of
+// scalars and small arrays lands here, so no asynchronous copy targets
+// pageable memory
+template <typename T>
+struct PinBuf {
+  T* p = nullptr;
+  int64_t n = 0;
+  void ensure(int64_t n_) {
+    if (n_ <= n) return;
+    release();
+    HIPCHECK(hipHostMalloc((void**)&p, (size_t)n_ * sizeof(T), hipHostMallocDefault));
+    n = n_;
+  }
+  void release() {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  T& operator[](int64_t i) { return p[i]; }
+  const T& operator[](int64_t i) const { return p[i]; }
+  PinBuf() = default;
+  ~PinBuf() { release(); }
+  PinBuf(const PinBuf&) = delete;
+  PinBuf& operator=(const PinBuf&) = delete;
+};
+
 struct IBuf {
   int32_t* p = nullptr;
   void alloc(int64_t n) {
@@ -99,6 +125,7 @@ struct Entry {
   int64_t nrow = 0, nalpha = 0, offset = 0;
   int64_t nkeep = 0, ooff = 0;   // orthogonal-basis columns and offset
   DBuf S, F, X, mu, eps;          // S,F [nalpha^2]; X [nalpha][nkeep]; mu [nkeep]; eps [nrow]
+  DBuf SX;                        // S X [nalpha][nkeep], made on the first warm start
   FBuf S32, F32, X32, eps32;      // FP32 copies for the inner solver (mixed precision)
   DBuf epsA, epsB;                // separable row energies: eps(m) = A[m / nB] + B[m % nB]
   FBuf epsA32, epsB32;
@@ -218,8 +245,10 @@ struct caspt2_handle {
   std::vector<DBuf> T, Tt, lam, lamt;  // packed and orthogonal
   std::vector<caspt2_info> tinfo, linfo;
   bool have_T = false, have_heff = false, have_lam = false;
+  int lam_target = -1;                                 // target state P of the stored lambda
   std::vector<double> heff, ems, R;
   DBuf jws;
+  PinBuf<double> hpin;   // staging of device-to-host copies (d2h)
   std::vector<std::vector<struct CoupleTerm>> couple;  // per function set
   DBuf cscratch;                                       // W / Y of the couplings
   DBuf wx, wsg;                                        // operator work vectors of the grouped solver
@@ -473,31 +502,40 @@ void progress(H& h, const std::string& what) {
   std::fflush(stderr);
 }
 
+// device-to-host copy of a small array in stream order, through the
+// handle's page-locked staging buffer; returns when the data is on the host
+void d2h(H& h, void* dst, const void* src, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return;
+  h.hpin.ensure((int64_t)((bytes + sizeof(double) - 1) / sizeof(double)));
+  HIPCHECK(hipMemcpyAsync(h.hpin.p, src, bytes, hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  std::memcpy(dst, h.hpin.p, bytes);
+}
+
 double dev_scalar(H& h, const double* p) {
   double v;
-  HIPCHECK(hipMemcpyAsync(&v, p, sizeof(double), hipMemcpyDeviceToHost, h.s));
-  host_sync(h);
+  d2h(h, &v, p, sizeof(double), h.s);
   return v;
 }
 
 // symmetric eigendecomposition of an n x n device matrix: values (host,
 // unsorted as on the diagonal) and vectors (device, columns)
-void eigh_dev(H& h, const double* A, int64_t n, std::vector<double>& w, DBuf& Vec) {
+void eigh_dev(H& h, const double* A, int64_t n, std::vector<double>& w, DBuf& Vec, double abs_tol = 0.0) {
   DBuf Aw(n * n);
   HIPCHECK(hipMemcpyAsync(Aw.p, A, (size_t)(n * n) * sizeof(double), hipMemcpyDeviceToDevice, h.s));
   Vec.alloc(n * n);
-  if (h.jws.n < 4 * n + 16) h.jws.alloc(4 * n + 16);
+  if (h.jws.n < jacobi_ws_doubles(n)) h.jws.alloc(jacobi_ws_doubles(n));
+  h.hpin.ensure(std::max<int64_t>(n, 8));
   int sweeps = 0;
   // second buffer of the one-launch-per-step form (faster than the launch
   // pairs up to JACOBI_STEP1_MAX; above, its redundant rotation reads cost more)
   DBuf A2(n > JACOBI_WG_AUTO && n <= JACOBI_STEP1_MAX ? n * n : 0);
-  HIPCHECK(jacobi_eigh((int)n, Aw.p, Vec.p, h.jws.p, 60, 1e-15, h.s, &sweeps, 0, A2.p));
-  std::vector<double> full(n * n);
-  HIPCHECK(hipMemcpyAsync(full.data(), Aw.p, (size_t)(n * n) * sizeof(double),
-                          hipMemcpyDeviceToHost, h.s));
+  HIPCHECK(jacobi_eigh((int)n, Aw.p, Vec.p, h.jws.p, 60, 1e-15, h.s, &sweeps, 0, A2.p, h.hpin.p, abs_tol));
+  // the eigenvalues are the diagonal: a strided copy of n doubles
+  HIPCHECK(hipMemcpy2DAsync(h.hpin.p, sizeof(double), Aw.p, (size_t)(n + 1) * sizeof(double), sizeof(double),
+                            (size_t)n, hipMemcpyDeviceToHost, h.s));
   host_sync(h);
-  w.resize(n);
-  for (int64_t i = 0; i < n; ++i) w[i] = full[i * n + i];
+  w.assign(h.hpin.p, h.hpin.p + n);
 }
 
 // X = Q[:, keep] / sqrt(w); then rotate to diagonalise X^T F X (Sec. II.B)
@@ -505,7 +543,10 @@ void orthonormal_basis(H& h, Entry& e) {
   const int64_t n = e.nalpha;
   std::vector<double> w;
   DBuf Q;
-  eigh_dev(h, e.S.p, n, w, Q);
+  // the kept set is decided against an absolute threshold: converge until
+  // no diagonal element can be more than 0.1 thresh from its eigenvalue (the
+  // off-diagonal norm bounds that distance), where FP64 rotations attain it
+  eigh_dev(h, e.S.p, n, w, Q, 0.1 * h.d.ovl_thresh);
   std::vector<int64_t> keep;
   for (int64_t i = 0; i < n; ++i) {
     if (w[i] >= h.d.ovl_thresh) {
@@ -751,25 +792,20 @@ void setup_blocks(H& h) {
   }
 }
 
-// sources <M~| E_Omega^+ H |N~> for every N, packed, per function set
-void setup_sources(H& h) {
-  const bool ss = h.d.scheme == CASPT2_SSSR;
-  const int nst = h.nst;
-  const int nsets = ss ? nst : 1;
-  h.src.clear();
-  h.src.resize(nsets);
-  for (int set = 0; set < nsets; ++set)
-    for (int N = 0; N < nst; ++N) {
-      h.src[set].emplace_back(h.length);
-      h.src[set].back().zero(h.s);
-    }
-  struct Comp {
-    OpString ops;
-    std::vector<std::string> labels;
-    std::vector<char> spaces;
-    double scale;
-  };
-  std::vector<Comp> comps;
+// the parts of H that act on the references with something left (closed
+// creators and virtual annihilators removed): one-body h^c_pq E_pq and
+// two-body 1/2 (pq|rs) a+_p a+_r a_s a_q with p, r active or virtual and
+// q, s active or closed, not all active; fixed order (the one-body classes,
+// then the two-body classes with p slowest)
+struct SrcComp {
+  OpString ops;
+  std::vector<std::string> labels;
+  std::vector<char> spaces;
+  double scale;
+};
+
+std::vector<SrcComp> source_comps() {
+  std::vector<SrcComp> comps;
   for (char sp : {ACT, VIR})
     for (char sq : {ACT, CLO}) {
       if (sp == ACT && sq == ACT) continue;
@@ -784,6 +820,19 @@ void setup_sources(H& h) {
                           Op{'a', "s_o", ss2, "to"}, Op{'a', "q_o", sq, "so"}};
           comps.push_back({ops, {"p_o", "q_o", "r_o", "s_o"}, {sp, sq, sr, ss2}, 0.5});
         }
+  return comps;
+}
+
+// Every source term: for each block, component of H, Wick pairing and
+// packed entry, fn(comp index, component, term descriptor, coefficient
+// tensor, active tensor G [opact][alpha_all][N], set, entry).  The active
+// tensors are built per (block, component) and released afterwards.
+template <typename Fn>
+void for_source_terms(H& h, Fn&& fn) {
+  const bool ss = h.d.scheme == CASPT2_SSSR;
+  const int nst = h.nst;
+  const int nsets = ss ? nst : 1;
+  const std::vector<SrcComp> comps = source_comps();
   auto dim = [&](char c) { return c == CLO ? h.nc : c == ACT ? h.na : h.nv; };
   auto off = [&](char c) { return c == CLO ? 0 : c == ACT ? h.nc : h.nc + h.na; };
   const auto& BL = blocks();
@@ -794,7 +843,8 @@ void setup_sources(H& h) {
     const int64_t nall = (int64_t)nst * ntypes * ntup;
     const int64_t nset = (ss ? 1 : nst) * ntypes * ntup;
     if (nset == 0) continue;
-    for (const auto& c : comps) {
+    for (size_t ci = 0; ci < comps.size(); ++ci) {
+      const SrcComp& c = comps[ci];
       bool empty = false;
       for (char sp : c.spaces)
         if (dim(sp) == 0) empty = true;
@@ -871,18 +921,36 @@ void setup_sources(H& h) {
             d.goff = ss ? (int64_t)set * nset : 0;
             d.mode_avg = 0;
             d.scale = c.scale;
-            for (int N = 0; N < nst; ++N) {
-              d.gcol = N;
-              HIPCHECK(term_source(d, C, kv.second.G.p, h.src[set][N].p + e.offset, h.s));
-            }
+            fn((int)ci, c, d, C, (const double*)kv.second.G.p, set, e);
           }
       }
       host_sync(h);
     }
     h.vcache.clear();
-    progress(h, "sources of block " + b.name);
+    progress(h, "source terms of block " + b.name);
   }
   host_sync(h);
+}
+
+// sources <M~| E_Omega^+ H |N~> for every N, packed, per function set
+void setup_sources(H& h) {
+  const bool ss = h.d.scheme == CASPT2_SSSR;
+  const int nst = h.nst;
+  const int nsets = ss ? nst : 1;
+  h.src.clear();
+  h.src.resize(nsets);
+  for (int set = 0; set < nsets; ++set)
+    for (int N = 0; N < nst; ++N) {
+      h.src[set].emplace_back(h.length);
+      h.src[set].back().zero(h.s);
+    }
+  for_source_terms(h, [&](int, const SrcComp&, TermDesc d, const double* C, const double* G, int set,
+                          const Entry& e) {
+    for (int N = 0; N < nst; ++N) {
+      d.gcol = N;
+      HIPCHECK(term_source(d, C, G, h.src[set][N].p + e.offset, h.s));
+    }
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -929,44 +997,20 @@ PackInfo pack_info(const H& h, int set, int block, const double* base, const std
   return p;
 }
 
-void setup_couplings(H& h) {
+// Coupling terms of the blocks of f named in comps: between excitation
+// blocks for a block of f between two orbital spaces, inside each
+// excitation block for one within an orbital space (the operator's
+// contraction with itself, the trace of that block, dropped).  One term per
+// Wick pairing and function set, appended to terms[set]; used[b] marks the
+// excitation blocks taking part.
+void make_coupling_terms(H& h, const std::vector<std::pair<char, char>>& comps,
+                         std::vector<std::vector<CoupleTerm>>& terms, bool* used) {
   const bool ss = h.d.scheme == CASPT2_SSSR;
   const int nst = h.nst;
   const int nsets = ss ? nst : 1;
-  h.couple.clear();
-  h.couple.resize(nsets);
+  terms.resize(nsets);
   auto off = [&](char c) { return c == CLO ? 0 : c == ACT ? h.nc : h.nc + h.na; };
-  auto dim = [&](char c) { return c == CLO ? h.nc : c == ACT ? h.na : h.nv; };
-  // Fock blocks between orbital classes that are present
-  std::vector<std::pair<char, char>> comps;
-  for (auto pr : std::vector<std::pair<char, char>>{{ACT, CLO}, {CLO, ACT}, {VIR, ACT}, {ACT, VIR},
-                                                    {VIR, CLO}, {CLO, VIR}}) {
-    bool nz = false;
-    for (int x = 0; x < dim(pr.first) && !nz; ++x)
-      for (int y = 0; y < dim(pr.second); ++y)
-        if (h.h_fock[(off(pr.first) + x) * h.nmo + off(pr.second) + y] != 0.0) {
-          nz = true;
-          break;
-        }
-    if (nz) comps.push_back(pr);
-  }
-  // off-diagonal closed-closed and virtual-virtual Fock elements (orbitals not
-  // canonical in those spaces): terms of each block with itself; the
-  // diagonal stays in the row energies, so the device copy of f has it zeroed
-  for (char c : {CLO, VIR}) {
-    bool nz = false;
-    for (int x = 0; x < dim(c) && !nz; ++x)
-      for (int y = 0; y < dim(c); ++y)
-        if (x != y && h.h_fock[(off(c) + x) * h.nmo + off(c) + y] != 0.0) {
-          nz = true;
-          break;
-        }
-    if (nz) comps.push_back({c, c});
-  }
-  if (comps.empty()) return;
-  bool used[NBLOCK] = {false, false, false, false, false, false, false, false};
   const auto& BL = blocks();
-  int64_t scratch = 0;
   for (int bb = 0; bb < NBLOCK; ++bb)
     for (int kb = 0; kb < NBLOCK; ++kb) {
       const Block& B1 = BL[bb];
@@ -1090,7 +1134,6 @@ void setup_couplings(H& h) {
             t.d.ket = all_desc(h, kb);
             if (up) {
               t.G = std::move(Gs);                     // [(y, alpha_b)][alpha_k]
-              scratch = std::max(scratch, all_rows(h, kb) * ny * nset_b);
               t.d.ncol = nset_b;
             } else {
               t.G.alloc((int64_t)nset_b * ny * nset_k);   // [alpha_b][(y, alpha_k)]
@@ -1098,17 +1141,56 @@ void setup_couplings(H& h) {
               const int64_t dims3[3] = {ny, nset_b, nset_k};
               const int64_t str3[3] = {nset_k, (int64_t)ny * nset_k, 1};
               HIPCHECK(permute_axpy(3, dims3, str3, 1.0, Gs.p, t.G.p, h.s));
-              scratch = std::max(scratch, all_rows(h, bb) * ny * nset_k);
               t.d.ncol = nset_k;
             }
             used[bb] = used[kb] = true;
-            h.couple[set].push_back(std::move(t));
+            terms[set].push_back(std::move(t));
           }
         }
         host_sync(h);
       }
       progress(h, "couplings " + B1.name + " <- " + B2.name);
     }
+}
+
+void setup_couplings(H& h) {
+  const bool ss = h.d.scheme == CASPT2_SSSR;
+  const int nst = h.nst;
+  const int nsets = ss ? nst : 1;
+  h.couple.clear();
+  h.couple.resize(nsets);
+  auto off = [&](char c) { return c == CLO ? 0 : c == ACT ? h.nc : h.nc + h.na; };
+  auto dim = [&](char c) { return c == CLO ? h.nc : c == ACT ? h.na : h.nv; };
+  // Fock blocks between orbital classes that are present
+  std::vector<std::pair<char, char>> comps;
+  for (auto pr : std::vector<std::pair<char, char>>{{ACT, CLO}, {CLO, ACT}, {VIR, ACT}, {ACT, VIR},
+                                                    {VIR, CLO}, {CLO, VIR}}) {
+    bool nz = false;
+    for (int x = 0; x < dim(pr.first) && !nz; ++x)
+      for (int y = 0; y < dim(pr.second); ++y)
+        if (h.h_fock[(off(pr.first) + x) * h.nmo + off(pr.second) + y] != 0.0) {
+          nz = true;
+          break;
+        }
+    if (nz) comps.push_back(pr);
+  }
+  // off-diagonal closed-closed and virtual-virtual Fock elements (orbitals not
+  // canonical in those spaces): terms of each block with itself; the
+  // diagonal stays in the row energies, so the device copy of f has it zeroed
+  for (char c : {CLO, VIR}) {
+    bool nz = false;
+    for (int x = 0; x < dim(c) && !nz; ++x)
+      for (int y = 0; y < dim(c); ++y)
+        if (x != y && h.h_fock[(off(c) + x) * h.nmo + off(c) + y] != 0.0) {
+          nz = true;
+          break;
+        }
+    if (nz) comps.push_back({c, c});
+  }
+  if (comps.empty()) return;
+  bool used[NBLOCK] = {false, false, false, false, false, false, false, false};
+  const auto& BL = blocks();
+  make_coupling_terms(h, comps, h.couple, used);
   // merge terms that act identically (same blocks, index maps, Fock block
   // and shapes): their active tensors add.  A ccvv ket is symmetric under the
   // joint exchange (i, a) <-> (j, b) of its slots, so its slot map is first
@@ -1176,7 +1258,7 @@ void setup_couplings(H& h) {
       t.sg_slot = sb;
       h.direct[b] = false;
     }
-  scratch = 0;
+  int64_t scratch = 0;
   for (auto& cs : h.couple)
     for (auto& t : cs) {
       if (t.up && h.direct[t.ket]) throw DevError(CASPT2_E_NOTIMPL, "up coupling from a packed ket");
@@ -1492,6 +1574,27 @@ void from_orth(H& h, int set, const T* o, T* v) {
   }
 }
 
+// coefficients in the orthonormal kept basis of a packed amplitude-like
+// vector (T or lambda): t~ = X^T S v per entry, so that X t~ is the
+// S-orthogonal projection of v on the kept space (X^T S X = 1); used for
+// warm starts
+void amp_to_orth(H& h, int set, const double* v, double* o) {
+  for (auto& e : h.sets[set]) {
+    if (e.nrow == 0 || e.nkeep == 0) continue;
+    if (e.SX.n != e.nalpha * e.nkeep) {
+      e.SX.alloc(e.nalpha * e.nkeep);
+      HIPCHECK(gemm_f64(false, e.nalpha, e.nkeep, e.nalpha, 1.0, e.S.p, e.nalpha, 0, e.X.p, e.nkeep, 0, 0.0,
+                        e.SX.p, e.nkeep, 0, 1, h.s));
+    }
+    if (e.nalpha <= 8)
+      HIPCHECK(transform_rows<double>(e.nrow, (int)e.nalpha, (int)e.nkeep, v + e.offset, e.SX.p, (int)e.nkeep,
+                                      1, o + e.ooff, h.s));
+    else
+      HIPCHECK(gemm_t(false, e.nrow, e.nkeep, e.nalpha, 1.0, v + e.offset, e.nalpha, e.SX.p, e.nkeep, 0.0,
+                      o + e.ooff, e.nkeep, h.s));
+  }
+}
+
 int64_t olen(const H& h, int set) {
   int64_t n = 0;
   for (auto& e : h.sets[set]) n += e.nrow * e.nkeep;
@@ -1689,7 +1792,8 @@ struct PcgEngine {
   DevBuf<PcgScalars> sc;
   DevBuf<PcgVecs<double>> vecs;
   DevBuf<PcgVecs<float>> vecs32;
-  std::vector<PcgScalars> hsc;
+  PinBuf<PcgScalars> hsc;              // host copy of sc (page-locked)
+  PinBuf<double> hrr;                  // mixed: squared true-residual norms
   DevBuf<int32_t> blk_sys, sys_id, b0, b1;
   DevBuf<int64_t> blk_start, blk_end;
   DBuf part_a, part_b;
@@ -1716,7 +1820,8 @@ struct PcgEngine {
     } else {
       vecs.alloc(cap);
     }
-    hsc.assign(cap, PcgScalars{});
+    hsc.ensure(cap);
+    for (int k = 0; k < cap; ++k) hsc[k] = PcgScalars{};
   }
   ~PcgEngine() {
     if (s) (void)hipStreamSynchronize(s);
@@ -1738,8 +1843,11 @@ struct PcgEngine {
   PcgEngine(const PcgEngine&) = delete;
   PcgEngine& operator=(const PcgEngine&) = delete;
 
+  // in stream order on s (the recurrence kernels read sc on s); waits for
+  // the copy so the host may change hsc[id] afterwards
   void upload_scalars(int id) {
-    HIPCHECK(hipMemcpy(sc.p + id, &hsc[id], sizeof(PcgScalars), hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpyAsync(sc.p + id, hsc.p + id, sizeof(PcgScalars), hipMemcpyHostToDevice, s));
+    HIPCHECK(hipStreamSynchronize(s));
   }
 
   // inner solve of a mixed system from its current true residual (|r| = rn):
@@ -1757,8 +1865,9 @@ struct PcgEngine {
     S.status = PCG_IDLE;
   }
 
-  // new system A x = -b (b in the orthonormal basis, device, on h.s)
-  PcgSystem& add(H& h, int L, int kind, const double* b, double tol, int maxiter) {
+  // new system A x = -b (b in the orthonormal basis, device, on h.s); t0
+  // (orthonormal basis, device, nullable): starting solution instead of 0
+  PcgSystem& add(H& h, int L, int kind, const double* b, double tol, int maxiter, const double* t0 = nullptr) {
     if ((int)sys.size() >= capacity) throw DevError(CASPT2_E_ARG, "pcg engine capacity");
     if (mixed != (h.d.precision == CASPT2_MIXED)) throw DevError(CASPT2_E_ARG, "pcg engine precision");
     auto S = std::make_unique<PcgSystem>();
@@ -1785,8 +1894,12 @@ struct PcgEngine {
     }
     S->t.alloc(S->n);
     S->r.alloc(S->n);
-    HIPCHECK(vec_fill(S->n, 0.0, S->t.p, h.s));
+    if (t0 && S->n > 0)
+      HIPCHECK(hipMemcpyAsync(S->t.p, t0, S->n * sizeof(double), hipMemcpyDeviceToDevice, h.s));
+    else
+      HIPCHECK(vec_fill(S->n, 0.0, S->t.p, h.s));
     HIPCHECK(vec_scale_copy(S->n, -1.0, b, S->r.p, h.s));
+    const bool warm = t0 && S->n > 0 && dmin > 0.0;
     PcgScalars& c = hsc[S->id];
     c = PcgScalars{};
     c.tol2 = tol * tol;
@@ -1807,6 +1920,14 @@ struct PcgEngine {
       upload_scalars(S->id);
       if (S->status == PCG_IDLE && S->n > 0)
         S->graph = capture_operator<double>(h, L, S->p.p, S->q.p, s, S->wset);
+      if (warm) {
+        // r = -(b + A t0): the operator graph maps p to q
+        HIPCHECK(hipMemcpyAsync(S->p.p, S->t.p, S->n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        HIPCHECK(hipGraphLaunch(S->graph, s));
+        HIPCHECK(hipMemcpyAsync(S->r.p, S->q.p, S->n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        HIPCHECK(vec_negsum(S->n, b, S->r.p, s));
+        HIPCHECK(hipStreamSynchronize(s));
+      }
       if (S->n == 0 && S->status == PCG_IDLE) S->status = PCG_CONVERGED;
     } else {
       S->b.alloc(S->n);
@@ -1817,6 +1938,14 @@ struct PcgEngine {
       S->D32.alloc(S->n);
       HIPCHECK(hipMemcpyAsync(S->b.p, b, S->n * sizeof(double), hipMemcpyDeviceToDevice, h.s));
       HIPCHECK(vec_scale_copy(S->n, 1.0, S->D.p, S->D32.p, h.s));
+      if (warm) {
+        // r = -(b + A t0) with the FP64 operator graph (t -> r)
+        host_sync(h);
+        S->graph64 = capture_operator<double>(h, L, S->t.p, S->r.p, s, S->wset);
+        HIPCHECK(hipGraphLaunch(S->graph64, s));
+        HIPCHECK(vec_negsum(S->n, S->b.p, S->r.p, s));
+        HIPCHECK(hipStreamSynchronize(s));
+      }
       S->rn = S->n > 0 ? std::sqrt(ddot(h, S->n, S->r.p, S->r.p)) : 0.0;
       S->D.release();
       PcgVecs<float> v{};
@@ -1835,7 +1964,7 @@ struct PcgEngine {
         upload_scalars(S->id);
       } else {
         S->graph = capture_operator<float>(h, L, S->p32.p, S->q32.p, s, S->wset);
-        S->graph64 = capture_operator<double>(h, L, S->t.p, S->r.p, s, S->wset);
+        if (!S->graph64) S->graph64 = capture_operator<double>(h, L, S->t.p, S->r.p, s, S->wset);
         arm_inner(*S);
         HIPCHECK(hipStreamSynchronize(s));
       }
@@ -1902,7 +2031,7 @@ struct PcgEngine {
 
   // copy the scalars to the host; retire systems that stopped on the device
   bool poll() {
-    HIPCHECK(hipMemcpyAsync(hsc.data(), sc.p, sys.size() * sizeof(PcgScalars), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipMemcpyAsync(hsc.p, sc.p, sys.size() * sizeof(PcgScalars), hipMemcpyDeviceToHost, s));
     HIPCHECK(hipStreamSynchronize(s));
     std::vector<int> still;
     stopped.clear();
@@ -1947,8 +2076,9 @@ struct PcgEngine {
       HIPCHECK(vec_negsum(S.n, S.b.p, S.r.p, s));   // r = -(b + A t)
       HIPCHECK(vec_dot(S.n, S.r.p, S.r.p, dot_part.p, dot_out.p + id, s));
     }
-    std::vector<double> rr(sys.size());
-    HIPCHECK(hipMemcpyAsync(rr.data(), dot_out.p, sys.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    PinBuf<double>& rr = hrr;
+    rr.ensure((int64_t)sys.size());
+    HIPCHECK(hipMemcpyAsync(rr.p, dot_out.p, sys.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHECK(hipStreamSynchronize(s));
     std::vector<int> again;
     for (int id : ids) {
@@ -2091,9 +2221,8 @@ void compute_heff(H& h) {
   h.heff = Hm;
   h.ems.resize(nst);
   h.R.resize(nst * nst);
-  HIPCHECK(hipMemcpyAsync(h.ems.data(), wv.p, nst * sizeof(double), hipMemcpyDeviceToHost, h.s));
-  HIPCHECK(hipMemcpyAsync(h.R.data(), Rd.p, nst * nst * sizeof(double), hipMemcpyDeviceToHost, h.s));
-  host_sync(h);
+  d2h(h, h.ems.data(), wv.p, nst * sizeof(double), h.s);
+  d2h(h, h.R.data(), Rd.p, nst * nst * sizeof(double), h.s);
   h.have_heff = true;
 }
 
@@ -2111,7 +2240,7 @@ void store_solution(PcgSystem& S, std::vector<DBuf>& packed, std::vector<DBuf>& 
 // refinement, by the handle's precision); kind 0 amplitudes, 1 lambda for
 // target P
 int grouped_solve(H& h, int kind, int P, double tol, int maxiter, std::vector<DBuf>& packed,
-                  std::vector<DBuf>& orth, std::vector<caspt2_info>& infos) {
+                  std::vector<DBuf>& orth, std::vector<caspt2_info>& infos, const double* x0 = nullptr) {
   const int nst = h.nst;
   PcgEngine eng(nst, 1, h.d.precision == CASPT2_MIXED);
   for (int L = 0; L < nst; ++L) {
@@ -2120,8 +2249,10 @@ int grouped_solve(H& h, int kind, int P, double tol, int maxiter, std::vector<DB
       amplitude_rhs(h, L, b.p);
     else
       lambda_rhs(h, L, P, b.p);
+    DBuf t0(x0 ? b.n : 0);
+    if (x0) amp_to_orth(h, set_of(h, L), x0 + (int64_t)L * h.length, t0.p);
     host_sync(h);
-    eng.add(h, L, kind, b.p, tol, maxiter);
+    eng.add(h, L, kind, b.p, tol, maxiter, x0 ? t0.p : nullptr);
   }
   std::vector<int> ids(nst);
   for (int L = 0; L < nst; ++L) ids[L] = L;
@@ -2442,6 +2573,261 @@ void validate(const caspt2_dims* d, const std::vector<double>& f, const std::vec
     return CASPT2_E_DEVICE;                                                  \
   }
 
+
+// ---------------------------------------------------------------------------
+// Correlated density matrices (Sec. II.D) for the target state P of the
+// stored lambda.  With the mixed states |P> = sum_M |M~> R_MP and
+// T_PN = sum_M T_MN R_MP:
+//   d1_xy   = sum_M <M~|T_PM^+ E_xy|P> + sum_MN <M~|lambda_NM^+ E_xy|N~>
+//   D1_xyzw = the same with E_xy,zw = E_xy E_zw - delta_yz E_xw
+//   dbar2_xy = sum_LMN <M~|lambda_LM^+ E_xy T_LN|N~>,  N_L = <lambda_L|T_L>
+//   d2 = dbar2 - sum_L N_L <L~|E|L~> on the active block, dbar2 elsewhere.
+// Each is the derivative of a matrix element the amplitude equation already
+// evaluates with respect to its coefficient: d1 and D1 run the source terms
+// transposed (weights W_N = sum_L R_LP R_NP T_L + lambda_N in place of the
+// integrals); dbar2 runs the operator's f-dependence transposed: the row
+// energies (diagonal of the closed and virtual blocks of f, with N_L), the
+// active Fock metric (Gram tensors with the active E_xy explicit, contracted
+// with sum_rows lambda^T T) and the coupling terms of every other block of f
+// (also those whose f values vanish).
+// D1 holds the classes of the two-body part of H that acts on the
+// references (creators active or virtual, annihilators active or closed, not
+// all active), [p][q][r][s] per class, classes in a fixed order.
+// ---------------------------------------------------------------------------
+struct D2Class {
+  char sp[4];
+  int64_t offset, size;
+};
+
+std::vector<D2Class> d2_classes(const H& h) {
+  auto dim = [&](char c) -> int64_t { return c == CLO ? h.nc : c == ACT ? h.na : h.nv; };
+  std::vector<D2Class> out;
+  int64_t off = 0;
+  for (const auto& c : source_comps()) {
+    if (c.labels.size() != 4) continue;
+    D2Class k{};
+    int64_t n = 1;
+    for (int a = 0; a < 4; ++a) {
+      k.sp[a] = c.spaces[a];
+      n *= dim(c.spaces[a]);
+    }
+    k.offset = off;
+    k.size = n;
+    off += n;
+    out.push_back(k);
+  }
+  return out;
+}
+
+void compute_densities(H& h, DBuf& d1, DBuf& D1, DBuf& gf, DBuf& d2, DBuf& NLd) {
+  const bool ss = h.d.scheme == CASPT2_SSSR;
+  const int nst = h.nst, nmo = h.nmo;
+  const int nsets = ss ? nst : 1;
+  const int P = h.lam_target;
+  auto off = [&](char c) { return c == CLO ? 0 : c == ACT ? h.nc : h.nc + h.na; };
+  auto dim = [&](char c) { return c == CLO ? h.nc : c == ACT ? h.na : h.nv; };
+  auto Rm = [&](int a, int b) { return h.R[(size_t)a * nst + b]; };
+  // ---- weights of the source terms: W[set] = [N][length] ----------------
+  std::vector<DBuf> W(nsets);
+  for (int set = 0; set < nsets; ++set) {
+    W[set].alloc((int64_t)nst * h.length);
+    W[set].zero(h.s);
+  }
+  for (int L = 0; L < nst; ++L) {
+    const int set = set_of(h, L);
+    for (int N = 0; N < nst; ++N)
+      HIPCHECK(vec_axpy(h.length, Rm(L, P) * Rm(N, P), h.T[L].p, W[set].p + (int64_t)N * h.length, h.s));
+    HIPCHECK(vec_axpy(h.length, 1.0, h.lam[L].p, W[set].p + (int64_t)L * h.length, h.s));
+  }
+  // ---- d1, D1: source terms transposed ------------------------------------
+  const auto classes = d2_classes(h);
+  int64_t d2len = 0;
+  for (const auto& k : classes) d2len += k.size;
+  d1.alloc((int64_t)nmo * nmo);
+  d1.zero(h.s);
+  D1.alloc(d2len);
+  D1.zero(h.s);
+  int nonebody = 0;
+  for (const auto& c : source_comps())
+    if (c.labels.size() == 2) ++nonebody;
+  for_source_terms(h, [&](int ci, const SrcComp& c, TermDesc d, const double*, const double* G, int set,
+                          const Entry& e) {
+    double* out = c.labels.size() == 2 ? d1.p + (int64_t)off(c.spaces[0]) * nmo + off(c.spaces[1])
+                                       : D1.p + classes[ci - nonebody].offset;
+    d.scale = 1.0;
+    HIPCHECK(term_density(d, out, G, W[set].p + e.offset, h.length, nst, h.s));
+  });
+  W.clear();
+  // ---- dbar2: row energies (closed and virtual diagonal) and N_L ----------
+  gf.alloc((int64_t)nmo * nmo);
+  gf.zero(h.s);
+  NLd.alloc(nst);
+  NLd.zero(h.s);
+  {
+    int64_t ymax = 0;
+    for (auto& es : h.sets)
+      for (auto& e : es) ymax = std::max(ymax, e.nrow * e.nalpha);
+    DBuf Y(ymax);
+    for (int L = 0; L < nst; ++L)
+      for (auto& e : h.sets[set_of(h, L)]) {
+        if (e.nrow == 0 || e.nalpha == 0) continue;
+        const Block& b = blocks()[e.block];
+        HIPCHECK(gemm_f64(false, e.nrow, e.nalpha, e.nalpha, 1.0, h.lam[L].p + e.offset, e.nalpha, 0, e.S.p,
+                          e.nalpha, 0, 0.0, Y.p, e.nalpha, 0, 1, h.s));
+        int mask = 0;
+        for (size_t k = 0; k < b.ext.size(); ++k)
+          if (b.ext[k].second == VIR) mask |= 1 << k;
+        HIPCHECK(row_metric(base_desc(h, b, e), Y.p, h.T[L].p + e.offset, mask, h.nc + h.na, nmo, gf.p, nmo,
+                            NLd.p + L, h.s));
+      }
+    host_sync(h);
+  }
+  // ---- dbar2: active block through the Gram tensors with E_xy explicit ----
+  if (h.na > 0) {
+    const OpString fop = E("x_o", ACT, "y_o", ACT, "so");
+    const int64_t na2 = (int64_t)h.na * h.na;
+    DBuf part(1024), dxy(na2);
+    for (int bi = 0; bi < NBLOCK; ++bi) {
+      const Block& b = blocks()[bi];
+      const int ntypes = (int)b.types.size();
+      const int64_t ntup = ipow(h.na, (int)b.act.size());
+      const int64_t nall = (int64_t)nst * ntypes * ntup;
+      const int64_t nset = (ss ? 1 : nst) * ntypes * ntup;
+      bool any = false;
+      for (auto& e : h.sets[0])
+        if (e.block == bi && e.nrow > 0) any = true;
+      if (nset == 0 || !any) continue;
+      std::map<std::string, PairAcc> fk;
+      for (int tb = 0; tb < ntypes; ++tb)
+        for (int tk = 0; tk < ntypes; ++tk) {
+          auto pairings = matrix_element(suffixed(b.types[tb], "_b"), fop, suffixed(b.types[tk], "_k"));
+          for (auto& Pr : pairings) {
+            const std::string key = pair_key(Pr);
+            auto it = fk.find(key);
+            if (it == fk.end()) {
+              PairAcc pa;
+              pa.P.pairs = Pr.pairs;
+              pa.G.alloc(na2 * nall * nall);
+              pa.G.zero(h.s);
+              it = fk.emplace(key, std::move(pa)).first;
+            }
+            for (const auto& w : Pr.entries)
+              accumulate_gram(h, w, tb, ntypes, ntup, tk, ntypes, ntup, false, nullptr, it->second.G, 0);
+          }
+        }
+      h.vcache.clear();
+      // Q_chi = sum_L lambda_L^T T_L over the rows of each entry
+      std::vector<DBuf> Q;
+      std::vector<const Entry*> ents;
+      std::vector<int> eset;
+      for (int set = 0; set < nsets; ++set)
+        for (auto& e : h.sets[set]) {
+          if (e.block != bi || e.nrow == 0) continue;
+          Q.emplace_back(nset * nset);
+          Q.back().zero(h.s);
+          ents.push_back(&e);
+          eset.push_back(set);
+          for (int L = 0; L < nst; ++L)
+            if (set_of(h, L) == set)
+              HIPCHECK(outer_rows(e.nrow, nset, nset, h.lam[L].p + e.offset, h.T[L].p + e.offset,
+                                  Q.back().p, h.s));
+        }
+      DBuf Qsum(nall * nall);
+      for (auto& kv : fk) {
+        Qsum.zero(h.s);
+        for (size_t k = 0; k < ents.size(); ++k) {
+          const double sg = perm_sign(b, kv.second.P, ents[k]->chi);
+          if (ss) {
+            const int64_t dims2[2] = {nset, nset};
+            const int64_t str2[2] = {nall, 1};
+            HIPCHECK(permute_axpy(2, dims2, str2, sg, Q[k].p,
+                                  Qsum.p + (int64_t)eset[k] * nset * nall + (int64_t)eset[k] * nset, h.s));
+          } else {
+            HIPCHECK(vec_axpy(nall * nall, sg, Q[k].p, Qsum.p, h.s));
+          }
+        }
+        // d[x][y] = sum_{alpha beta} G[x][y][alpha][beta] Qsum[alpha][beta]
+        for (int64_t xy = 0; xy < na2; ++xy)
+          HIPCHECK(vec_dot(nall * nall, kv.second.G.p + xy * nall * nall, (const double*)Qsum.p, part.p,
+                           dxy.p + xy, h.s));
+        const int64_t dims2[2] = {h.na, h.na};
+        const int64_t str2[2] = {nmo, 1};
+        HIPCHECK(permute_axpy(2, dims2, str2, 1.0, dxy.p, gf.p + (int64_t)h.nc * nmo + h.nc, h.s));
+        host_sync(h);
+      }
+    }
+  }
+  // ---- dbar2: every other block of f through the coupling terms -----------
+  {
+    std::vector<std::pair<char, char>> comps;
+    for (auto pr : std::vector<std::pair<char, char>>{{ACT, CLO}, {CLO, ACT}, {VIR, ACT}, {ACT, VIR},
+                                                      {VIR, CLO}, {CLO, VIR}, {CLO, CLO}, {VIR, VIR}})
+      if (dim(pr.first) > 0 && dim(pr.second) > 0 && !(pr.first == pr.second && dim(pr.first) < 2))
+        comps.push_back(pr);
+    std::vector<std::vector<CoupleTerm>> terms;
+    bool used[NBLOCK] = {false, false, false, false, false, false, false, false};
+    make_coupling_terms(h, comps, terms, used);
+    std::vector<DBuf> lall(NBLOCK), tall(NBLOCK);
+    int64_t scr = 0;
+    for (int b = 0; b < NBLOCK; ++b)
+      if (used[b]) {
+        const int64_t na_b = nalpha_of_block(h, 0, b);
+        lall[b].alloc(all_rows(h, b) * na_b);
+        tall[b].alloc(all_rows(h, b) * na_b);
+      }
+    for (auto& ts : terms)
+      for (auto& t : ts)
+        scr = std::max(scr, (t.up ? all_rows(h, t.ket) : all_rows(h, t.bra)) * t.d.ny * t.d.ncol);
+    DBuf scratch(scr);
+    for (int L = 0; L < nst; ++L) {
+      const int set = set_of(h, L);
+      for (int b = 0; b < NBLOCK; ++b)
+        if (used[b]) {
+          const int64_t na_b = nalpha_of_block(h, set, b);
+          HIPCHECK(unpack_all(pack_info(h, set, b, nullptr, nullptr, na_b), all_desc(h, b),
+                              (const double*)h.lam[L].p, lall[b].p, h.s));
+          HIPCHECK(unpack_all(pack_info(h, set, b, nullptr, nullptr, na_b), all_desc(h, b),
+                              (const double*)h.T[L].p, tall[b].p, h.s));
+        }
+      for (auto& t : terms[set]) {
+        const int64_t nab = nalpha_of_block(h, set, t.bra), nak = nalpha_of_block(h, set, t.ket);
+        const int skip = t.bra == t.ket ? 1 : 0;   // f within one orbital space: diagonal from the row energies
+        if (t.up) {
+          const int64_t width = (int64_t)t.d.ny * nab;
+          HIPCHECK(gemm_f64(true, all_rows(h, t.ket), width, nak, 1.0, tall[t.ket].p, nak, 0, t.G.p, nak, 0, 0.0,
+                            scratch.p, width, 0, 1, h.s));
+          HIPCHECK(fock_grad(t.d, lall[t.bra].p, nab, 0, scratch.p, width, nab, nab, gf.p + t.f_off, nmo, skip,
+                             h.s));
+        } else {
+          const int64_t width = (int64_t)t.d.ny * nak;
+          HIPCHECK(gemm_f64(false, all_rows(h, t.bra), width, nab, 1.0, lall[t.bra].p, nab, 0, t.G.p, width, 0,
+                            0.0, scratch.p, width, 0, 1, h.s));
+          HIPCHECK(fock_grad(t.d, scratch.p, width, nak, tall[t.ket].p, nak, 0, nak, gf.p + t.f_off, nmo, skip,
+                             h.s));
+        }
+      }
+      host_sync(h);
+    }
+  }
+  // ---- <L~|E_rs|L~> and the finished dbar2, d2 ----------------------------
+  DBuf gam((int64_t)nst * h.na * h.na);
+  gam.zero(h.s);
+  if (h.na > 0)
+    for (int spin = 0; spin < 2; ++spin) {
+      const auto* v = apply_string(h, ActString{ActOp{'a', "r", spin}});
+      if (!v) continue;
+      const int64_t dimv = h.as->dim(v->second);
+      for (int L = 0; L < nst; ++L)
+        HIPCHECK(gemm_f64(true, h.na, h.na, dimv, 1.0, v->first.p + (int64_t)L * dimv, (int64_t)nst * dimv, 0,
+                          v->first.p + (int64_t)L * dimv, (int64_t)nst * dimv, 0, 1.0,
+                          gam.p + (int64_t)L * h.na * h.na, h.na, 0, 1, h.s));
+    }
+  h.vcache.clear();
+  d2.alloc((int64_t)nmo * nmo);
+  HIPCHECK(density_finish(nmo, h.nc, h.na, nst, NLd.p, gam.p, gf.p, d2.p, h.s));
+  host_sync(h);
+}
+
 extern "C" {
 
 const char* caspt2_last_error(void) { return g_last_error.c_str(); }
@@ -2540,16 +2926,14 @@ int caspt2_create(const caspt2_dims* dims, const caspt2_inputs* in, int on_devic
       Fr.zero(h.s);
     }
     h.fref.resize(nst * nst);
-    HIPCHECK(hipMemcpyAsync(h.fref.data(), Fr.p, nst * nst * sizeof(double), hipMemcpyDeviceToHost, h.s));
-    host_sync(h);
+    d2h(h, h.fref.data(), Fr.p, nst * nst * sizeof(double), h.s);
     DBuf wv(nst), Ud(nst * nst);
     h.U.assign(nst * nst, 0.0);
     h.e0.assign(nst, 0.0);
     if (dims->xms) {
       HIPCHECK(small_eigh(nst, Fr.p, wv.p, Ud.p, h.s));
-      HIPCHECK(hipMemcpyAsync(h.U.data(), Ud.p, nst * nst * sizeof(double), hipMemcpyDeviceToHost, h.s));
-      HIPCHECK(hipMemcpyAsync(h.e0.data(), wv.p, nst * sizeof(double), hipMemcpyDeviceToHost, h.s));
-      host_sync(h);
+      d2h(h, h.U.data(), Ud.p, nst * nst * sizeof(double), h.s);
+      d2h(h, h.e0.data(), wv.p, nst * sizeof(double), h.s);
     } else {
       for (int k = 0; k < nst; ++k) {
         h.U[k * nst + k] = 1.0;
@@ -2574,8 +2958,7 @@ int caspt2_create(const caspt2_dims* dims, const caspt2_inputs* in, int on_devic
       HIPCHECK(gemm_f64(false, nst, nst, nst, 1.0, Er.p, nst, 0, Ud.p, nst, 0, 0.0, T1.p, nst, 0, 1, h.s));
       HIPCHECK(gemm_f64(false, nst, nst, nst, 1.0, Ut.p, nst, 0, T1.p, nst, 0, 0.0, Hr.p, nst, 0, 1, h.s));
       h.href.resize(nst * nst);
-      HIPCHECK(hipMemcpyAsync(h.href.data(), Hr.p, nst * nst * sizeof(double), hipMemcpyDeviceToHost, h.s));
-      host_sync(h);
+      d2h(h, h.href.data(), Hr.p, nst * nst * sizeof(double), h.s);
     }
     h.vcache.clear();
     progress(h, "XMS rotation");
@@ -2769,14 +3152,15 @@ int caspt2_residual_all(caspt2_handle* h, int32_t with_source, const double* x, 
   })
 }
 
-int caspt2_solve_amplitudes(caspt2_handle* h, double tol, int32_t maxiter, caspt2_info* info) {
+int caspt2_solve_amplitudes(caspt2_handle* h, double tol, int32_t maxiter, const double* T0,
+                            caspt2_info* info) {
   if (!h || !(tol > 0.0) || maxiter < 0) return CASPT2_E_ARG;
   ABI_GUARD({
     H& hh = *h;
     hh.T.clear();
     hh.Tt.clear();
     hh.have_T = hh.have_heff = hh.have_lam = false;
-    const int status = grouped_solve(hh, 0, 0, tol, maxiter, hh.T, hh.Tt, hh.tinfo);
+    const int status = grouped_solve(hh, 0, 0, tol, maxiter, hh.T, hh.Tt, hh.tinfo, T0);
     if (status == CASPT2_E_INDEFINITE) return status;
     host_sync(hh);
     hh.have_T = true;
@@ -2796,11 +3180,72 @@ int caspt2_get_amplitudes(caspt2_handle* h, int32_t L, double* T) {
   })
 }
 
-int xms_rotate(const caspt2_handle* h, double* U, double* e0) {
+int caspt2_get_xms(const caspt2_handle* h, double* U, double* e0) {
   if (!h) return CASPT2_E_ARG;
   if (U) std::memcpy(U, h->U.data(), h->nst * h->nst * sizeof(double));
   if (e0) std::memcpy(e0, h->e0.data(), h->nst * sizeof(double));
   return CASPT2_OK;
+}
+
+int xms_rotate(int32_t nact, int32_t nst, const double* f_act, const double* rdm1, double* U, double* e0) {
+  if (nact < 0 || nst <= 0 || nst > 16 || (nact > 0 && (!f_act || !rdm1)) || !U || !e0) return CASPT2_E_ARG;
+  const int64_t nf = (int64_t)nact * nact, ng = (int64_t)nst * nst * nf;
+  for (int64_t k = 0; k < nf; ++k)
+    if (!std::isfinite(f_act[k])) return CASPT2_E_ARG;
+  for (int64_t k = 0; k < ng; ++k)
+    if (!std::isfinite(rdm1[k])) return CASPT2_E_ARG;
+  ABI_GUARD({
+    DBuf fd(nf), gd(ng), Fr((int64_t)nst * nst), wv(nst), Ud((int64_t)nst * nst);
+    PinBuf<double> hp;
+    hp.ensure((int64_t)nst * nst + nst);
+    if (nf > 0) {
+      HIPCHECK(hipMemcpy(fd.p, f_act, nf * sizeof(double), hipMemcpyHostToDevice));
+      HIPCHECK(hipMemcpy(gd.p, rdm1, ng * sizeof(double), hipMemcpyHostToDevice));
+    }
+    HIPCHECK(xms_fref(nact, nst, fd.p, gd.p, Fr.p, nullptr));
+    HIPCHECK(small_eigh(nst, Fr.p, wv.p, Ud.p, nullptr));
+    HIPCHECK(hipMemcpy(hp.p, Ud.p, (size_t)nst * nst * sizeof(double), hipMemcpyDeviceToHost));
+    HIPCHECK(hipMemcpy(hp.p + (int64_t)nst * nst, wv.p, nst * sizeof(double), hipMemcpyDeviceToHost));
+    std::memcpy(U, hp.p, (size_t)nst * nst * sizeof(double));
+    std::memcpy(e0, hp.p + (int64_t)nst * nst, nst * sizeof(double));
+    return CASPT2_OK;
+  })
+}
+
+int64_t caspt2_density2_length(const caspt2_handle* h) {
+  if (!h) return -1;
+  int64_t n = 0;
+  for (const auto& k : d2_classes(*h)) n += k.size;
+  return n;
+}
+
+int caspt2_density2_layout(const caspt2_handle* h, int32_t k, int64_t* offset, int32_t* spaces) {
+  if (!h) return CASPT2_E_ARG;
+  const auto cl = d2_classes(*h);
+  if (k < 0 || k >= (int32_t)cl.size()) return CASPT2_E_ARG;
+  if (offset) *offset = cl[k].offset;
+  if (spaces)
+    for (int a = 0; a < 4; ++a) spaces[a] = cl[k].sp[a] == CLO ? 0 : cl[k].sp[a] == ACT ? 1 : 2;
+  return CASPT2_OK;
+}
+
+int caspt2_densities(caspt2_handle* h, double* d1, double* D1, double* dbar2, double* d2, double* NL) {
+  if (!h) return CASPT2_E_ARG;
+  if (!h->have_lam || !h->have_heff || h->lam_target < 0) return CASPT2_E_STATE;
+  ABI_GUARD({
+    H& hh = *h;
+    DBuf dd1, dD1, dgf, dd2, dNL;
+    compute_densities(hh, dd1, dD1, dgf, dd2, dNL);
+    const size_t nn = (size_t)hh.nmo * hh.nmo;
+    if (d1) d2h(hh, d1, dd1.p, nn * sizeof(double), hh.s);
+    if (dbar2) d2h(hh, dbar2, dgf.p, nn * sizeof(double), hh.s);
+    if (d2) d2h(hh, d2, dd2.p, nn * sizeof(double), hh.s);
+    if (NL) d2h(hh, NL, dNL.p, hh.nst * sizeof(double), hh.s);
+    if (D1 && dD1.n > 0)
+      HIPCHECK(hipMemcpyAsync(D1, dD1.p, dD1.n * sizeof(double), hipMemcpyDeviceToDevice, hh.s));
+    host_sync(hh);
+    return CASPT2_OK;
+  })
 }
 
 int xms_heff(caspt2_handle* h, double* heff, double* e_ms, double* R) {
@@ -2817,7 +3262,8 @@ int xms_heff(caspt2_handle* h, double* heff, double* e_ms, double* R) {
   })
 }
 
-int caspt2_solve_lambda(caspt2_handle* h, int32_t P, double tol, int32_t maxiter, caspt2_info* info) {
+int caspt2_solve_lambda(caspt2_handle* h, int32_t P, double tol, int32_t maxiter, const double* lam0,
+                        caspt2_info* info) {
   if (!h || P < 0 || P >= h->nst || !(tol > 0.0) || maxiter < 0) return CASPT2_E_ARG;
   if (!h->have_heff) return CASPT2_E_STATE;
   ABI_GUARD({
@@ -2826,7 +3272,8 @@ int caspt2_solve_lambda(caspt2_handle* h, int32_t P, double tol, int32_t maxiter
     hh.lam.clear();
     hh.lamt.clear();
     hh.have_lam = false;
-    const int status = grouped_solve(hh, 1, P, tol, maxiter, hh.lam, hh.lamt, hh.linfo);
+    const int status = grouped_solve(hh, 1, P, tol, maxiter, hh.lam, hh.lamt, hh.linfo, lam0);
+    hh.lam_target = P;
     if (status == CASPT2_E_INDEFINITE) return status;
     host_sync(hh);
     hh.have_lam = true;
@@ -2930,6 +3377,7 @@ int caspt2_batch_solve(caspt2_handle* const* handles, int32_t n, const int32_t* 
             e.retire(*e.sys[id]);
           }
           h.have_lam = result[i] == CASPT2_OK;
+          h.lam_target = targets[i];
           phase[i] = result[i] == CASPT2_OK ? 2 : 3;
         }
       }
@@ -3037,21 +3485,33 @@ int caspt2_debug_eigh(int32_t n, double* A, double* w, double* V) {
 }
 
 int caspt2_debug_eigh_method(int32_t n, double* A, double* w, double* V, int32_t method, int32_t* sweeps_out) {
-  if (n <= 0 || !A || !w || !V || method < 0 || method > 4) return CASPT2_E_ARG;
+  return caspt2_debug_eigh_abs(n, A, w, V, method, 0.0, sweeps_out);
+}
+
+int caspt2_debug_eigh_abs(int32_t n, double* A, double* w, double* V, int32_t method, double abs_tol,
+                          int32_t* sweeps_out) {
+  if (n <= 0 || !A || !w || !V || method < 0 || method > 4 || !(abs_tol >= 0.0)) return CASPT2_E_ARG;
   if ((method == 1 && n > 64) || (method == 2 && n > 512)) return CASPT2_E_ARG;
   ABI_GUARD({
     double* ws = nullptr;
-    HIPCHECK(hipMalloc(&ws, (4 * (size_t)n + 16 + (size_t)n * n) * sizeof(double)));
+    const size_t nws = (size_t)jacobi_ws_doubles(n);
+    HIPCHECK(hipMalloc(&ws, (nws + (size_t)n * n) * sizeof(double)));
+    PinBuf<double> hp;
+    hp.ensure(std::max(n, 8));
     int sweeps = 0;
-    // method 4: the whole-device form with one launch per step (second buffer)
+    // method 4: the whole-device form with one launch per step (second
+    // buffer); method 0 picks the form by size as the library's set-up does
+    const bool second = method == 4 || (method == 0 && n > JACOBI_WG_AUTO && n <= JACOBI_STEP1_MAX);
     hipError_t e = jacobi_eigh(n, A, V, ws, 60, 1e-15, nullptr, &sweeps, method == 4 ? 3 : method,
-                               method == 4 ? ws + 4 * (size_t)n + 16 : nullptr);
+                               second ? ws + nws : nullptr, hp.p, abs_tol);
     if (sweeps_out) *sweeps_out = sweeps;
-    std::vector<double> full((size_t)n * n);
-    if (e == hipSuccess) e = hipMemcpy(full.data(), A, full.size() * sizeof(double), hipMemcpyDeviceToHost);
+    // eigenvalues: the diagonal, one strided copy
+    if (e == hipSuccess)
+      e = hipMemcpy2D(hp.p, sizeof(double), A, (size_t)(n + 1) * sizeof(double), sizeof(double), (size_t)n,
+                      hipMemcpyDeviceToHost);
     (void)hipFree(ws);
     HIPCHECK(e);
-    for (int i = 0; i < n; ++i) w[i] = full[(size_t)i * n + i];
+    std::memcpy(w, hp.p, (size_t)n * sizeof(double));
     return CASPT2_OK;
   })
 }

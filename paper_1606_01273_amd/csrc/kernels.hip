@@ -3,7 +3,9 @@
 #include "kernels.hpp"
 #include "device_common.hpp"
 
+#include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 namespace caspt2 {
@@ -1081,11 +1083,15 @@ __global__ void k_eye(int n, double* V) {
   if (g < (int64_t)n * n) V[g] = (g / n == g % n) ? 1.0 : 0.0;
 }
 
-// off-diagonal and total squared norms, one block
-__global__ void k_jac_norms(int n, const double* __restrict__ A, double* __restrict__ out) {
+// off-diagonal and total squared norms: per-workgroup partial sums over a
+// grid-stride range (part[2 b], part[2 b + 1]), then one workgroup adds the
+// partials in a fixed order (out[0] = off-diagonal, out[1] = total)
+constexpr int JAC_NORM_WG = 256;   // workgroups of the partial pass (<= 256)
+__global__ void k_jac_norms_part(int n, const double* __restrict__ A, double* __restrict__ part) {
   __shared__ double so[256], st[256];
   double off = 0.0, tot = 0.0;
-  for (int64_t g = threadIdx.x; g < (int64_t)n * n; g += blockDim.x) {
+  const int64_t nn = (int64_t)n * n;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < nn; g += (int64_t)gridDim.x * blockDim.x) {
     const double v = A[g];
     tot += v * v;
     if (g / n != g % n) off += v * v;
@@ -1101,6 +1107,25 @@ __global__ void k_jac_norms(int n, const double* __restrict__ A, double* __restr
     __syncthreads();
   }
   if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = so[0];
+    part[2 * blockIdx.x + 1] = st[0];
+  }
+}
+
+__global__ void k_jac_norms_fin(int nb, const double* __restrict__ part, double* __restrict__ out) {
+  __shared__ double so[256], st[256];
+  const int t = threadIdx.x;
+  so[t] = t < nb ? part[2 * t] : 0.0;
+  st[t] = t < nb ? part[2 * t + 1] : 0.0;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) {
+      so[t] += so[t + w];
+      st[t] += st[t + w];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
     out[0] = so[0];
     out[1] = st[0];
   }
@@ -1225,9 +1250,33 @@ __global__ __launch_bounds__(1024) void k_jacobi_small(int n, double* __restrict
   if (t == 0 && sweeps) *sweeps = sw;
 }
 
+// F^ref_MN = sum_rs f_rs (G[M][N][r][s] + G[N][M][r][s]) / 2: the Fock
+// operator in the reference space (Eq. 3) from the transition one-particle
+// densities, symmetrised; one thread per (M, N)
+__global__ void k_xms_fref(int na, int nst, const double* __restrict__ f, const double* __restrict__ G,
+                           double* __restrict__ F) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nst * nst) return;
+  const int M = t / nst, N = t % nst;
+  const int64_t nf = (int64_t)na * na;
+  const double* gmn = G + ((int64_t)M * nst + N) * nf;
+  const double* gnm = G + ((int64_t)N * nst + M) * nf;
+  double acc = 0.0;
+  for (int64_t k = 0; k < nf; ++k) acc += f[k] * (gmn[k] + gnm[k]);
+  F[t] = 0.5 * acc;
+}
+
+hipError_t xms_fref(int na, int nst, const double* f, const double* G, double* F, hipStream_t s) {
+  if (nst <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_xms_fref, dim3(cdiv((int64_t)nst * nst, 64)), dim3(64), 0, s, na, nst, f, G, F);
+  return hipGetLastError();
+}
+
 hipError_t jacobi_eigh(int n, double* A, double* V, double* ws, int max_sweeps, double tol,
-                       hipStream_t s, int* sweeps_done, int method, double* A2) {
+                       hipStream_t s, int* sweeps_done, int method, double* A2, double* hpin,
+                       double abs_tol) {
   if (n <= 0) return hipSuccess;
+  if (!hpin) return hipErrorInvalidValue;
   // the attainable off-diagonal norm grows with n (round-off of the rotations)
   tol = fmax(tol, 4e-16 * (double)n);
   if (method == 0 || method == 1) {
@@ -1249,29 +1298,42 @@ hipError_t jacobi_eigh(int n, double* A, double* V, double* ws, int max_sweeps, 
                          A, V, tol, max_sweeps, dsw);
     else
       hipLaunchKernelGGL(k_jacobi_small<false>, dim3(1), dim3(1024), 0, s, n, A, V, tol, max_sweeps, dsw);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     if (sweeps_done) {
-      hipError_t e = hipMemcpyAsync(sweeps_done, dsw, sizeof(int), hipMemcpyDeviceToHost, s);
+      e = hipMemcpyAsync(hpin, dsw, sizeof(int), hipMemcpyDeviceToHost, s);
       if (e != hipSuccess) return e;
       e = hipStreamSynchronize(s);
       if (e != hipSuccess) return e;
+      std::memcpy(sweeps_done, hpin, sizeof(int));
     }
-    return hipGetLastError();
+    return hipSuccess;
   }
   const int m = n + (n & 1);
+  // workspace (doubles): cs [2m] | norms [2] + pad [2] | pq [m ints] | partials [2 JAC_NORM_WG]
   double* cs = ws;
   double* norms = ws + 2 * m;
   int* pq = reinterpret_cast<int*>(ws + 2 * m + 4);
+  double* npart = ws + 2 * m + 4 + (m + 1) / 2 + 1;
+  const int nbn = (int)std::min<int64_t>(JAC_NORM_WG, std::max<int64_t>(1, cdiv((int64_t)n * n, 256 * 16)));
   hipLaunchKernelGGL(k_eye, dim3(cdiv((int64_t)n * n, 256)), dim3(256), 0, s, n, V);
   int sw = 0;
-  double hn[2], prev = INFINITY;
+  double prev = INFINITY;
   for (; sw < max_sweeps; ++sw) {
-    hipLaunchKernelGGL(k_jac_norms, dim3(1), dim3(256), 0, s, n, A, norms);
-    hipError_t e = hipMemcpyAsync(hn, norms, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
+    hipLaunchKernelGGL(k_jac_norms_part, dim3(nbn), dim3(256), 0, s, n, (const double*)A, npart);
+    hipLaunchKernelGGL(k_jac_norms_fin, dim3(1), dim3(256), 0, s, nbn, (const double*)npart, norms);
+    hipError_t e = hipMemcpyAsync(hpin, norms, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
     if (e != hipSuccess) return e;
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return e;
-    if (hn[0] <= tol * tol * hn[1] || hn[1] == 0.0 || m < 2 || (sw > 2 && !(hn[0] < prev))) break;
-    prev = hn[0];
+    const double off = hpin[0], tot = hpin[1];
+    // converged, or at the round-off floor (the off-diagonal norm no longer
+    // decreases); a sweep that decreases it only a little is not the floor:
+    // a large cluster of zero eigenvalues (rank-deficient metrics) keeps the
+    // couplings of the cluster to the rest converging slowly
+    const bool small = off <= tol * tol * tot && (abs_tol <= 0.0 || off <= abs_tol * abs_tol);
+    if (small || tot == 0.0 || m < 2 || (sw > 2 && !(off < prev))) break;
+    prev = off;
     const int64_t work = (int64_t)(m / 2) * (m / 2) + (int64_t)n * (m / 2);
     if (A2) {
       // one launch per step, alternating buffers; an odd step count leaves

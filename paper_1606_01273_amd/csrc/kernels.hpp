@@ -228,15 +228,23 @@ hipError_t select_scale_cols(int64_t n, int64_t ncq, const double* Q, const int3
 
 // Jacobi eigensolver of a symmetric n x n matrix A (destroyed; diagonal ->
 // eigenvalues, unsorted); V receives eigenvectors (columns).  ws: device
-// workspace of >= 4*n doubles + 2*n ints. sweeps: max sweeps.  method: 0
+// workspace of >= jacobi_ws_doubles(n) doubles. sweeps: max sweeps.  method: 0
 // by size (below), 1 one workgroup with A and V in LDS (n <= 64), 2 one
 // workgroup on global memory (n <= 512), 3 launches over the whole chip per
 // rotation step: one per step when A2 (a second n x n device buffer) is
-// given, else a parameter launch and a rotation launch.
+// given, else a parameter launch and a rotation launch.  hpin: page-locked
+// host memory (hipHostMalloc) of >= 2 doubles, the target of the per-sweep
+// convergence norms and of the sweep count (required).  The whole-device
+// forms stop when the off-diagonal Frobenius norm is <= tol |A|_F and, if
+// abs_tol > 0, also <= abs_tol (an absolute bound on how far a diagonal
+// element can be from an eigenvalue, for decisions against a fixed
+// threshold), or when it no longer decreases (the round-off floor).
 constexpr int JACOBI_WG_AUTO = 64;   // largest n solved by one workgroup (LDS form) by default
 constexpr int JACOBI_STEP1_MAX = 512;   // largest n for which the one-launch-per-step form pays
+inline int64_t jacobi_ws_doubles(int64_t n) { return 4 * n + 16 + 2 * 256; }
 hipError_t jacobi_eigh(int n, double* A, double* V, double* ws, int max_sweeps, double tol,
-                       hipStream_t s, int* sweeps_done, int method = 0, double* A2 = nullptr);
+                       hipStream_t s, int* sweeps_done, int method, double* A2, double* hpin,
+                       double abs_tol = 0.0);
 
 // vector kernels (element types as instantiated in kernels.hip)
 template <typename T>  // FP64 accumulation; out on device (1 double); partial >= 1024 doubles
@@ -300,5 +308,32 @@ hipError_t pcg_step(const PcgTable& tab, const PcgSysTable& st, const PcgVecs<T>
 // small dense symmetric eigenproblem on one thread (n <= 16): A -> values w
 // ascending, vectors R (columns, largest-magnitude entry positive)
 hipError_t small_eigh(int n, const double* A, double* w, double* R, hipStream_t s);
+// Correlated densities (Sec. II.D): the source contraction transposed,
+//   D[idx(e, y)] += scale w chi sum_N sum_alpha W[N wstride + row ldo + alpha]
+//                   G[(y galpha + goff + alpha) gcols + N]
+// over the images e of every packed row of entry d (D is the coefficient
+// tensor's layout, d.c_slot / d.c_stride index it; atomic adds)
+hipError_t term_density(const TermDesc& d, double* D, const double* G, const double* W, int64_t wstride,
+                        int nst, hipStream_t s);
+// u[row] = Y[row] . X[row] over the packed rows of entry d: sum into *nsum;
+// +u (virtual slot, bit k of virt_mask) or -u (closed slot) onto the
+// diagonal of gdiag at orbital (nvoff +) slot value; nmo <= 2048
+hipError_t row_metric(const TermDesc& d, const double* Y, const double* X, int virt_mask, int nvoff, int nmo,
+                      double* gdiag, int64_t ld, double* nsum, hipStream_t s);
+// transposed Fock coupling term: gf[fx][fy] += sum_{e_b, z, y} sum_a
+// A[e_b][y ay + a] B[e_k(e_b, z)][y by + a] with the term's index maps
+// (fx, fy from a bra slot, a summed label or y); skip_diag drops fx == fy
+hipError_t fock_grad(const CoupleDesc& d, const double* A, int64_t arow, int64_t ay, const double* B,
+                     int64_t brow, int64_t by, int64_t ncol, double* gf, int64_t fstride, int skip_diag,
+                     hipStream_t s);
+// Q[a][b] += sum_r X[r][a] Y[r][b] (row-major [nrow][n], row stride ld)
+hipError_t outer_rows(int64_t nrow, int64_t n, int64_t ld, const double* X, const double* Y, double* Q,
+                      hipStream_t s);
+// in place: gf[i][i] += 2 sum_L NL[L] (closed i); d2 = gf - sum_L NL[L]
+// gam[L] on the active block, gf elsewhere (n x n, device)
+hipError_t density_finish(int n, int nc, int na, int nst, const double* NL, const double* gam, double* gf,
+                          double* d2, hipStream_t s);
+// F [nst][nst] = sym(sum_rs f[r][s] G[M][N][r][s]) (Eq. 3 in the reference space)
+hipError_t xms_fref(int na, int nst, const double* f, const double* G, double* F, hipStream_t s);
 
 }  // namespace caspt2

@@ -95,6 +95,42 @@ def test_debug_eigh_methods_match_numpy(dev, method, sizes):
         _ok(np.abs(Vn.T @ Vn - np.eye(n)).max(), 1e-12, f"eigh orthonormality n={n} method {method}")
 
 
+@pytest.mark.parametrize("n", [300, 1000, 2048])
+def test_eigh_rank_deficient_near_threshold(dev, n):
+    """Block metrics are rank deficient (the functions of Eq. 8 are linearly
+    dependent) and their eigenvalues are cut at an absolute 1e-9 (Sec. II.B);
+    the largest metrics of the full workload are 2048 x 2048.  Half of the
+    spectrum is an exact null space, eight eigenvalues lie between 0.3e-9 and
+    3e-9, the rest spread over 1e-8..10.  The set-up's solver (form by size,
+    absolute stopping bound 0.1 of the threshold) keeps exactly the
+    eigenvalues numpy keeps, and matches numpy's eigenvalues near the cut."""
+    from paper_1606_01273_amd import lib
+    rng = np.random.default_rng(n)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    w0 = np.zeros(n)
+    nz = n // 2
+    w0[nz:nz + 8] = np.array([0.3, 0.5, 0.8, 0.9, 1.1, 1.25, 2.0, 3.0]) * 1e-9
+    w0[nz + 8:] = 10.0 ** rng.uniform(-8, 1, n - nz - 8)
+    S = (Q * w0) @ Q.T
+    S = 0.5 * (S + S.T)
+    ref = np.linalg.eigvalsh(S)
+    ta = torch.tensor(S, device=dev)
+    V = torch.empty((n, n), dtype=torch.float64, device=dev)
+    w = np.zeros(n)
+    sw = ctypes.c_int32()
+    thresh = 1e-9
+    assert lib().caspt2_debug_eigh_abs(n, ta.data_ptr(), w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                       V.data_ptr(), 0, 0.1 * thresh, ctypes.byref(sw)) == 0
+    ws = np.sort(w)
+    print(f"  n={n}: {sw.value} sweeps", flush=True)
+    assert int((ws >= thresh).sum()) == int((ref >= thresh).sum()) == n - nz - 4, "kept count"
+    near = (ref > 1e-10) & (ref < 1e-8)
+    assert int(near.sum()) == 8
+    _ok(np.abs(ws[near] - ref[near]).max(), 1e-12, f"eigenvalues near the cut n={n}")
+    Vn = V.cpu().numpy()
+    _ok(np.abs(Vn.T @ Vn - np.eye(n)).max(), 5e-15 * n, f"orthonormality n={n}")
+
+
 CASES = [
     # (dims, seed, reading, scheme, xms, shift); seeds chosen free of intruders
     ((2, 3, 3, 16, 3), 7, "A", "MSMR", True, 0.15),

@@ -440,3 +440,107 @@ def test_degenerate_xms_rotation_invariance():
         o2 = Caspt2Oracle(p, "MSMR", xms=False, rotate_states=o.U @ G).run(P=0)
         d = np.abs(np.sort(o2.e_ms) - np.sort(o.e_ms)).max()
         assert (d < 1e-12) if same else (d > 1e-6), (shift, d)
+
+
+# --------------------------------------------------------------------------
+# correlated densities (Sec. II.D): O1's written-out definitions against
+# finite differences of E^MS_P, which is stationary in T, lambda and R
+# (Eqs. 18-20), so its derivative with respect to a parameter of H or f at
+# fixed reference states is the parameter's explicit derivative of the
+# Lagrangian, i.e. a contraction with the densities
+# --------------------------------------------------------------------------
+
+def _richardson(fun, h=1e-4):
+    """Central difference with one Richardson step (error O(h^4))."""
+    d1 = (fun(h) - fun(-h)) / (2 * h)
+    d2 = (fun(h / 2) - fun(-h / 2)) / h
+    return (4 * d2 - d1) / 3
+
+
+@pytest.fixture(scope="module", params=["MSMR", "SSSR"])
+def dens_case(request):
+    from oracle.brute import densities_brute
+    scheme = request.param
+    p = make_problem(2, 2, 2, 12, 2, seed=5, reading="B", shift=0.15)
+    P = 1
+    o = solve_brute(p, scheme, xms=True, target=P)
+    return p, scheme, P, o, densities_brute(p, o)
+
+
+def test_density_d1_is_the_hcore_derivative(dens_case):
+    """dE^MS_P/dh^c along a symmetric direction = sum (gamma_P + d1) Dh:
+    <P|E_xy|P> from H^ref and d^(1) from the sources of Eqs. 10 and 15."""
+    p, scheme, P, o, d = dens_case
+    rng = np.random.default_rng(3)
+    Dh = rng.standard_normal((p.nmo, p.nmo))
+    Dh = Dh + Dh.T
+    fd = _richardson(lambda e: solve_brute(p.replace(hcore=p.hcore + e * Dh), scheme, xms=True, target=P,
+                                           want_lambda=False)["e_ms"][P])
+    ana = float(np.sum(Dh * (d["gamma_P"] + d["d1"])))
+    assert abs(fd - ana) < 1e-9 * max(1.0, abs(ana))
+
+
+def test_density_D1_is_the_eri_derivative(dens_case):
+    """dE^MS_P/d(xy|zw) along a random direction with the symmetry of real
+    integrals = 1/2 sum (Gamma_P + D1) D (bare h held fixed)."""
+    p, scheme, P, o, d = dens_case
+    rng = np.random.default_rng(4)
+    n = p.nmo
+    De = rng.standard_normal((n, n, n, n))
+    De = De + De.transpose(1, 0, 2, 3)
+    De = De + De.transpose(0, 1, 3, 2)
+    De = De + De.transpose(2, 3, 0, 1)
+
+    def e(eps):
+        s = BruteSystem(p)
+        s.eri = s.eri + eps * De
+        return solve_brute(p, scheme, xms=True, target=P, want_lambda=False, sysm=s)["e_ms"][P]
+    fd = _richardson(e)
+    ana = float(0.5 * np.sum(De * (d["Gamma_P"] + d["D1"])))
+    assert abs(fd - ana) < 1e-9 * max(1.0, abs(ana))
+
+
+def test_density_d2_is_the_fock_derivative(dens_case):
+    """dE^MS_P/df at fixed XMS rotation = sum d2 Df - 2 tr(Df_cc) sum_L N_L:
+    d-bar^(2) from the operator of Eq. 10, -N_L <L|E|L> from E_L^(0) (Eq. 14),
+    and the closed constant of the normal ordering (Eq. 12)."""
+    p, scheme, P, o, d = dens_case
+    rng = np.random.default_rng(5)
+    Df = rng.standard_normal((p.nmo, p.nmo))
+    Df = Df + Df.T
+    fd = _richardson(lambda e: solve_brute(p.replace(fock=p.fock + e * Df), scheme, xms=True, target=P,
+                                           want_lambda=False, fixed_U=o["U"])["e_ms"][P])
+    ana = float(np.sum(Df * d["d2"]) - 2.0 * np.trace(Df[:p.nc, :p.nc]) * d["NL"].sum())
+    assert abs(fd - ana) < 1e-9 * max(1.0, abs(ana))
+
+
+def test_density_norms_are_metric_products(dens_case):
+    """N_L = lambda_L . S . T_L in the function basis of state L."""
+    p, scheme, P, o, d = dens_case
+    for L in range(p.nst):
+        dL = o["L"][L]
+        assert abs(d["NL"][L] - dL["lam"] @ dL["S"] @ dL["T"]) < 1e-12 * max(1.0, abs(d["NL"][L]))
+
+
+@pytest.mark.parametrize("reading,scheme,dims,xms", [
+    ("B", "MSMR", (2, 2, 2, 12, 2), True), ("B", "SSSR", (2, 2, 2, 12, 2), True),
+    ("C", "MSMR", (2, 2, 3, 14, 2), True), ("A", "MSMR", (2, 3, 2, 14, 2), False)])
+def test_o2_densities_match_o1(reading, scheme, dims, xms):
+    """The factorised densities (Wick terms and active Gram tensors contracted
+    with T, lambda, R) equal O1's written-out ones element by element: d^(1),
+    D^(1) on the classes of the two-body part of H acting on the references,
+    d-bar^(2), N_L, d^(2)."""
+    from oracle.brute import densities_brute
+    p = make_problem(*dims, seed=5, reading=reading, shift=0.15)
+    P = 1
+    d = densities_brute(p, solve_brute(p, scheme, xms=xms, target=P))
+    e = Caspt2Oracle(p, scheme, xms=xms).run(P).densities()
+    sl = {"c": slice(0, p.nc), "a": slice(p.nc, p.nc + p.na), "v": slice(p.nc + p.na, p.nmo)}
+    tol = 1e-12
+    assert np.abs(d["d1"] - e["d1"]).max() < tol
+    assert len(e["D1"]) == 15
+    for k, v in e["D1"].items():
+        assert np.abs(d["D1"][sl[k[0]], sl[k[1]], sl[k[2]], sl[k[3]]] - v).max() < tol, k
+    assert np.abs(d["dbar2"] - e["dbar2"]).max() < tol
+    assert np.abs(d["d2"] - e["d2"]).max() < tol
+    assert np.abs(d["NL"] - e["NL"]).max() < tol
