@@ -200,6 +200,146 @@ def _cpu_worker(conn, dims, reading, sample_nv, min_seconds):
         conn.send(("error", repr(ex)))
 
 
+def _timed_steps(g, x, sig, steps, warmup):
+    """warm-up, then `steps` residual evaluations of all states on the
+    library's stream with profiling on; seconds"""
+    import torch
+    g.set_streams(1)
+    for _ in range(warmup):
+        g.residual_all(x, sig)
+    torch.cuda.synchronize()
+    g.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.residual_all(x, sig)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def _reading_b(steps, warmup, tune, tol, densities=True):
+    """The paper's operator (Eq. 10 with the general f of Eq. 11: its
+    closed-active, active-virtual and closed-virtual blocks couple the
+    excitation blocks) on the full workload: residual evaluations per second
+    on one stream and on two, the roofline of the whole evaluation (the
+    algorithmic bytes of Eq. 10: read x and the source, write sigma), the
+    time of every coupling stage per evaluation, and the amplitude, H_eff,
+    lambda solve with the correlated densities of Sec. II.D."""
+    import torch
+    from synth.gen import make_problem
+    from paper_1606_01273_amd import ENTRY_NAMES, Caspt2
+    nc, na, nv, naux, nst, seed, shift = WORKLOADS["full"][0]
+    prob = make_problem(nc, na, nv, naux, nst, seed, reading="B", shift=shift)
+    t0 = time.perf_counter()
+    g = Caspt2.from_problem(prob)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    if tune:
+        g.autotune()
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(1)
+    x = torch.randn((nst, g.length), dtype=torch.float64, device="cuda", generator=gen)
+    sig = torch.empty_like(x)
+    elapsed = _timed_steps(g, x, sig, steps, warmup)
+    prof = {ENTRY_NAMES[k]: g.profile_entry(k) for k in range(len(ENTRY_NAMES))}
+    coupl = g.profile_entry(len(ENTRY_NAMES))
+    stages = g.profile_stages()
+    g.profile(False)
+    g.set_streams(2)
+    g.residual_all(x, sig)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.residual_all(x, sig)
+    torch.cuda.synchronize()
+    elapsed_two = time.perf_counter() - t0
+    print(f"[bench] reading B: {steps} steps in {elapsed:.3f} s, two streams {elapsed_two:.3f} s",
+          file=sys.stderr, flush=True)
+    within = sum(v[0] * v[1] for v in prof.values()) / max(steps * nst, 1)
+    bytes_eval = 3.0 * nst * g.length * 8
+    t_eval = elapsed / steps
+    achieved = bytes_eval / t_eval / 1e9
+    out = {"value": round(steps / elapsed, 3), "unit": "evals/s", "ms_per_step": round(1e3 * t_eval, 3),
+           "two_streams": round(steps / elapsed_two, 3), "setup_s": round(t_setup, 2),
+           "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                        "bytes_per_eval": bytes_eval,
+                        "note": "whole evaluation: algorithmic bytes of Eq. 10 (read x and the source, write "
+                                "sigma, all states) over the time of one evaluation"},
+           "ms_per_state": {"within_block": round(within, 3), "couplings": round(coupl[0], 3)},
+           "coupling_stages_ms_per_state": {k: round(v, 3) for k, v in sorted(stages.items(),
+                                                                             key=lambda kv: -kv[1])}}
+    del x, sig
+    torch.cuda.empty_cache()
+    if densities:
+        t0 = time.perf_counter()
+        rc, ainfo = g.solve_amplitudes(tol=tol, maxiter=400)
+        H, w, R = g.heff()
+        rc2, linfo = g.solve_lambda(0, tol=tol, maxiter=400)
+        torch.cuda.synchronize()
+        t_solve = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        d = g.densities()
+        torch.cuda.synchronize()
+        t_dens = time.perf_counter() - t0
+        out["solve"] = {"status": [rc, rc2], "seconds": round(t_solve, 3),
+                        "iterations": [[i["iters"] for i in ainfo], [i["iters"] for i in linfo]],
+                        "e_ms": [float(v) for v in w]}
+        out["densities"] = {"seconds": round(t_dens, 3), "target": 0,
+                            "N_L": [float(v) for v in d["NL"]],
+                            "d2_len": int(sum(v.numel() for v in d["D1"].values())),
+                            "note": "d1, D1 (15 classes), dbar2, N_L, d2 of Sec. II.D after the amplitude and "
+                                    "lambda solves"}
+        print(f"[bench] reading B solve {t_solve:.2f} s, densities {t_dens:.2f} s", file=sys.stderr, flush=True)
+        # the precision form on the same problem: FP32 inner PCG, FP64 refinement
+        from paper_1606_01273_amd import MIXED
+        lam64 = [g.lam(L).cpu().numpy() for L in range(nst)]
+        g.set_precision(MIXED)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rcm, ainfo_m = g.solve_amplitudes(tol=tol, maxiter=400)
+        Hm, wm, Rm = g.heff()
+        rcm2, linfo_m = g.solve_lambda(0, tol=tol, maxiter=400)
+        torch.cuda.synchronize()
+        t_mixed = time.perf_counter() - t0
+        import numpy as np
+        lscale = max(float(np.linalg.norm(v)) for v in lam64)
+        dlam = max(float(np.linalg.norm(g.lam(L).cpu().numpy() - lam64[L])) for L in range(nst)) / lscale
+        out["precision"] = {"fp64_s": round(t_solve, 3), "mixed_s": round(t_mixed, 3),
+                            "speedup_vs_fp64": round(t_solve / t_mixed, 3), "status": [rcm, rcm2],
+                            "dE_ms_vs_fp64": [float(a - b) for a, b in zip(wm, w)],
+                            "rel_dlambda_vs_fp64": dlam,
+                            "refinements": [i["refinements"] for i in ainfo_m] + [i["refinements"] for i in linfo_m],
+                            "inner_iterations": [[i["iters"] for i in ainfo_m], [i["iters"] for i in linfo_m]],
+                            "note": "full workload with Fock couplings, tolerance as the FP64 solve; amplitudes, "
+                                    "H_eff and lambda (target 0)"}
+        print(f"[bench] reading B mixed solve {t_mixed:.2f} s", file=sys.stderr, flush=True)
+    g.close()
+    torch.cuda.empty_cache()
+    return out
+
+
+def _cpu_info():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    blas = None
+    try:
+        from threadpoolctl import threadpool_info
+        libs = [i for i in threadpool_info() if i.get("user_api") == "blas"]
+        if libs:
+            blas = f"{libs[0].get('internal_api')} ({os.path.basename(libs[0].get('filepath', ''))})"
+    except Exception:
+        pass
+    return model, blas
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -217,6 +357,8 @@ def main():
     ap.add_argument("--precision-workload", default="mid",
                     help="workload of the mixed-precision comparison (reading B); 'none' to skip")
     ap.add_argument("--batch", type=int, default=64, help="problems in the batched-solve comparison (0: skip)")
+    ap.add_argument("--no-reading-b", action="store_true",
+                    help="skip the residual, solve and densities of the full workload with Fock couplings")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the built-in launch rules (no autotuning of the residual launches)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -359,6 +501,12 @@ def main():
     g.close()
     del x, sig
     torch.cuda.empty_cache()
+    reading_b = None
+    if not args.no_reading_b and args.workload == "full" and args.reading == "A":
+        try:
+            reading_b = _reading_b(args.steps, args.warmup, not args.no_tune, args.solve_tol)
+        except Exception as ex:
+            reading_b = {"error": repr(ex)}
     precision = None
     if args.precision_workload != "none":
         try:
@@ -382,7 +530,9 @@ def main():
             dt, slen, threads = msg[1], msg[2], msg[3]
             # scale the sample's time per evaluation by the vector-length ratio
             scaled_dt = dt * (g.length / slen)
+            model, blas = _cpu_info()
             cpu = {"value": 1.0 / scaled_dt, "unit": "evals/s", "cores": int(threads), "kind": "oracle",
+                   "cpu_model": model, "blas": blas, "os_cpu_count": os.cpu_count(),
                    "sample": f"CPU oracle residual for all {nst} states with {args.cpu_sample_nv} virtuals "
                              f"(other sizes as the workload), {dt:.3f} s per evaluation, scaled by vector "
                              f"length {slen} -> {g.length}"}
@@ -406,6 +556,8 @@ def main():
         out["tune"] = tune
     if solve is not None:
         out["solve"] = solve
+    if reading_b is not None:
+        out["reading_B"] = reading_b
     if precision is not None:
         out["precision"] = precision
     if batch is not None:

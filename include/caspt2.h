@@ -325,6 +325,14 @@ CASPT2_API int caspt2_batch_solve(caspt2_handle* const* handles, int32_t n, cons
 CASPT2_API int caspt2_profile(caspt2_handle* h, int32_t enable);
 CASPT2_API int caspt2_profile_entry(caspt2_handle* h, int32_t k, double* avg_ms, int64_t* launches,
                                     double* bytes_per_launch);
+/* Stages of the Fock couplings timed while profiling is on: k = 0, 1, ...
+ * (E_ARG past the last): name (e.g. "unpack", "up ccvv <- cavv", "pack";
+ * the terms of one direction and block pair together; NUL-terminated,
+ * truncated to name_len), the stage's time per residual evaluation with
+ * couplings (ms, HIP events on the handle's stream) and the number of such
+ * evaluations recorded.  Each may be NULL. */
+CASPT2_API int caspt2_profile_stage(caspt2_handle* h, int32_t k, char* name, int32_t name_len,
+                                    double* ms_per_residual, int64_t* residuals);
 
 /* Human-readable text for a status code; last HIP error text. */
 CASPT2_API const char* caspt2_strerror(int code);

@@ -115,6 +115,20 @@ class Caspt2:
                "caspt2_profile_entry")
         return ms.value, n.value, b.value
 
+    def profile_stages(self):
+        """{stage name: ms per residual evaluation} of the Fock couplings
+        timed while profiling was on."""
+        out = {}
+        k = 0
+        while True:
+            buf = ctypes.create_string_buffer(64)
+            ms, n = ctypes.c_double(), ctypes.c_int64()
+            if lib().caspt2_profile_stage(self._h, k, buf, 64, ctypes.byref(ms), ctypes.byref(n)) != OK:
+                break
+            out[buf.value.decode()] = ms.value
+            k += 1
+        return out
+
     def residual(self, L, x, sigma, with_source=True):
         _check(lib().caspt2_residual(self._h, L, 1 if with_source else 0, _ptr(x), _ptr(sigma)),
                "caspt2_residual")

@@ -276,6 +276,7 @@ struct caspt2_handle {
   int verbose_level = 0;
   double t_start = 0.0;
   std::vector<ProfEventRec> prof_events;
+  std::vector<std::string> prof_stage;                 // names of the coupling stages timed (entries 1000 + k)
 };
 
 namespace {
@@ -1220,10 +1221,16 @@ void setup_couplings(H& h) {
                    merged.size());
     cs = std::move(merged);
   }
-  // ccvv, the largest block, is read from its packed rows by the reduce of
-  // the down terms (it is never the ket of an up term): no all-orderings copy
-  // of x for it
-  if (used[CCVV]) h.direct[CCVV] = true;
+  // ccvv is unpacked to all orderings once per operator application like the
+  // other blocks, so the down terms that read it run on coalesced rows
+  // (measured at the full workload: 13.8 ms for the six ccvv down terms
+  // against 22.4 ms gathering from the packed rows, for 3.5 ms more
+  // unpacking); when that copy would exceed 16 GiB the reduce reads the packed
+  // rows instead (ccvv is never the ket of an up term)
+  if (used[CCVV]) {
+    const int64_t na_ccvv = (ss ? 1 : nst) * (int64_t)BL[CCVV].types.size();
+    h.direct[CCVV] = all_rows(h, CCVV) * na_ccvv * (int64_t)sizeof(double) > ((int64_t)16 << 30);
+  }
   // slot GEMMs (within-block terms of non-semicanonical orbitals): the ket
   // tensor, slot-permuted where the term needs it, in all-orderings form
   for (auto& cs : h.couple)
@@ -1391,11 +1398,31 @@ void apply_couplings(H& h, int set, const T* x, T* sig) {
     std::fprintf(stderr, "[caspt2] coupling %s %.3f ms\n", what, 1e3 * (now - t_prev));
     t_prev = now;
   };
+  // stage timing (profiling on): pseudo entries 1000 + k, k the stage's
+  // index in h.prof_stage
+  auto stage_id = [&](const std::string& name) {
+    for (size_t k = 0; k < h.prof_stage.size(); ++k)
+      if (h.prof_stage[k] == name) return 1000 + (int)k;
+    h.prof_stage.push_back(name);
+    return 999 + (int)h.prof_stage.size();
+  };
+  hipEvent_t sev = nullptr;
+  prof_begin(h, &sev);
   for (int b = 0; b < NBLOCK; ++b) {
     if (!sall_of(h, b).p) continue;
     const int64_t na_b = nalpha_of(b);
-    if (xall_of(h, b).p)
-      HIPCHECK(unpack_all(pack_info(h, set, b, nullptr, nullptr, na_b), all_desc(h, b), x, xall(b), h.s));
+    if (xall_of(h, b).p) {
+      if (b == CCVV && na_b <= 4) {
+        // both characters in one tiled pass (the transpose of the pack below)
+        const T* plus = nullptr;
+        const T* minus = nullptr;
+        for (auto& e : h.sets[set])
+          if (e.block == b && e.nrow > 0) (e.chi.empty() || e.chi[0] > 0 ? plus : minus) = x + e.offset;
+        if (plus) HIPCHECK(unpack_ccvv(h.nc, h.nv, (int)na_b, plus, minus, xall(b), h.s));
+      } else {
+        HIPCHECK(unpack_all(pack_info(h, set, b, nullptr, nullptr, na_b), all_desc(h, b), x, xall(b), h.s));
+      }
+    }
     if (xperm_of(h, b).p) {
       // copy[e] = x[e[p[0]], e[p[1]], ...]: scatter x's element at k to the
       // position e with e[p[l]] = k[l]
@@ -1416,7 +1443,9 @@ void apply_couplings(H& h, int set, const T* x, T* sig) {
     HIPCHECK(vec_fill(sall_of(h, b).n, 0.0, sall_of(h, b).p, h.s));
   }
   stage("unpack");
+  if (h.prof_on) prof_end(h, stage_id("unpack"), 0.0, sev);
   for (auto& t : h.couple[set]) {
+    if (h.prof_on) prof_begin(h, &sev);
     if (diag) {
       stage("stage");
       std::fprintf(stderr, "[caspt2] term %s %s <- %s ny %d nsum %d slot %d%s: ", t.up ? "up" : "down",
@@ -1424,8 +1453,13 @@ void apply_couplings(H& h, int set, const T* x, T* sig) {
                    t.sg_perm ? " permuted" : "");
     }
     couple_term<T>(h, set, t, x, t.fuse);
+    if (h.prof_on)
+      prof_end(h, stage_id(std::string(t.up ? "up " : "down ") + blocks()[t.bra].name + " <- " +
+                           blocks()[t.ket].name),
+               0.0, sev);
   }
   stage("last term");
+  if (h.prof_on) prof_begin(h, &sev);
   for (int b = 0; b < NBLOCK; ++b) {
     if (!sall_of(h, b).p) continue;
     if (b == CCVV && nalpha_of(b) <= 4) {
@@ -1445,6 +1479,7 @@ void apply_couplings(H& h, int set, const T* x, T* sig) {
     }
   }
   stage("pack");
+  if (h.prof_on) prof_end(h, stage_id("pack"), 0.0, sev);
 }
 
 // ---------------------------------------------------------------------------
@@ -2619,6 +2654,87 @@ std::vector<D2Class> d2_classes(const H& h) {
   return out;
 }
 
+// The transposed form of a coupling term of f within one orbital space whose
+// one summed label z replaces bra slot sb (every other bra slot feeding one
+// ket slot, the active label absent): gf[e][z] += sum_{p, q} L[p][e][q]
+// X[p][z][q], L = lambda_all G in bra order and X the ket read with its slots
+// in bra order.  Both are copied with slot sb outermost, [D][R], and
+// multiplied in one MFMA GEMM (K = R); the result is added into gf at the
+// term's block of f (transposed when f's first index is the summed one),
+// diagonal left out.  False when the term is not of this form.
+bool slot_grad(H& h, const CoupleTerm& t, int64_t nak, const double* Lb, const double* Xk, double* gf,
+               int64_t nmo, int skip, DBuf& ta, DBuf& tb, DBuf& tg) {
+  const CoupleDesc& d = t.d;
+  if (t.up || t.bra != t.ket || d.nsum != 1 || d.ny != 1 || d.bra.nslot != d.ket.nslot) return false;
+  const int ns = d.bra.nslot;
+  int sb = -1;
+  bool z_first;
+  if (d.fx_src >= 0 && d.fy_src == -1) {
+    sb = d.fx_src;
+    z_first = false;
+  } else if (d.fy_src >= 0 && d.fx_src == -1) {
+    sb = d.fy_src;
+    z_first = true;
+  } else {
+    return false;
+  }
+  int fed[4] = {0, 0, 0, 0}, lz = -1;
+  for (int l = 0; l < ns; ++l) {
+    if (d.ket_src[l] == -1) {
+      if (lz >= 0) return false;
+      lz = l;
+    } else if (d.ket_src[l] >= 0 && d.ket_src[l] < ns && d.ket_src[l] != sb) {
+      if (fed[d.ket_src[l]]++) return false;
+    } else {
+      return false;
+    }
+  }
+  if (lz < 0 || d.ket.slot_dim[lz] != d.bra.slot_dim[sb]) return false;
+  const int64_t D = d.bra.slot_dim[sb];
+  // strides of [D][other bra slots in order][alpha]
+  int64_t st[4] = {0, 0, 0, 0}, R = nak;
+  for (int k = ns - 1; k >= 0; --k) {
+    if (k == sb) continue;
+    st[k] = R;
+    R *= d.bra.slot_dim[k];
+  }
+  st[sb] = R;
+  const int64_t n = D * R;
+  if (ta.n < n) ta.alloc(n);
+  if (tb.n < n) tb.alloc(n);
+  if (tg.n < D * D) tg.alloc(D * D);
+  int64_t dims[5], dst[5];
+  for (int k = 0; k < ns; ++k) {
+    dims[k] = d.bra.slot_dim[k];
+    dst[k] = st[k];
+  }
+  dims[ns] = nak;
+  dst[ns] = 1;
+  HIPCHECK(permute_copy(ns + 1, dims, dst, Lb, ta.p, h.s));
+  for (int l = 0; l < ns; ++l) {
+    dims[l] = d.ket.slot_dim[l];
+    dst[l] = l == lz ? st[sb] : st[d.ket_src[l]];
+  }
+  HIPCHECK(permute_copy(ns + 1, dims, dst, Xk, tb.p, h.s));
+  // split K over nb chunks (batched GEMM into partial products, the ragged
+  // rest into one more), then one GEMM with a row of ones adds the partials
+  const int64_t tiles = ((D + 63) / 64) * ((D + 63) / 64);
+  int64_t nb = std::max<int64_t>(1, std::min<int64_t>((1024 + tiles - 1) / tiles, R / 4096));
+  nb = std::min<int64_t>(nb, 65535);
+  const int64_t kc = R / nb, krest = R - nb * kc;
+  const int64_t nparts = nb + (krest > 0 ? 1 : 0);
+  DBuf parts(nparts * D * D), ones(nparts);
+  HIPCHECK(vec_fill(nparts, 1.0, ones.p, h.s));
+  HIPCHECK(gemm_f64(true, D, D, kc, 1.0, ta.p, R, kc, tb.p, R, kc, 0.0, parts.p, D, D * D, (int)nb, h.s));
+  if (krest > 0)
+    HIPCHECK(gemm_f64(true, D, D, krest, 1.0, ta.p + nb * kc, R, 0, tb.p + nb * kc, R, 0, 0.0,
+                      parts.p + nb * D * D, D, 0, 1, h.s));
+  HIPCHECK(gemm_f64(false, 1, D * D, nparts, 1.0, ones.p, nparts, 0, parts.p, D * D, 0, 0.0, tg.p, D * D, 0, 1,
+                    h.s));
+  HIPCHECK(add_block((int)D, tg.p, gf + t.f_off, nmo, z_first ? 1 : 0, skip, h.s));
+  return true;
+}
+
 void compute_densities(H& h, DBuf& d1, DBuf& D1, DBuf& gf, DBuf& d2, DBuf& NLd) {
   const bool ss = h.d.scheme == CASPT2_SSSR;
   const int nst = h.nst, nmo = h.nmo;
@@ -2658,6 +2774,7 @@ void compute_densities(H& h, DBuf& d1, DBuf& D1, DBuf& gf, DBuf& d2, DBuf& NLd) 
     HIPCHECK(term_density(d, out, G, W[set].p + e.offset, h.length, nst, h.s));
   });
   W.clear();
+  progress(h, "densities: d1, D1 from the source terms");
   // ---- dbar2: row energies (closed and virtual diagonal) and N_L ----------
   gf.alloc((int64_t)nmo * nmo);
   gf.zero(h.s);
@@ -2682,6 +2799,7 @@ void compute_densities(H& h, DBuf& d1, DBuf& D1, DBuf& gf, DBuf& d2, DBuf& NLd) 
       }
     host_sync(h);
   }
+  progress(h, "densities: row energies, N_L");
   // ---- dbar2: active block through the Gram tensors with E_xy explicit ----
   if (h.na > 0) {
     const OpString fop = E("x_o", ACT, "y_o", ACT, "so");
@@ -2757,6 +2875,7 @@ void compute_densities(H& h, DBuf& d1, DBuf& D1, DBuf& gf, DBuf& d2, DBuf& NLd) 
       }
     }
   }
+  progress(h, "densities: active block");
   // ---- dbar2: every other block of f through the coupling terms -----------
   {
     std::vector<std::pair<char, char>> comps;
@@ -2779,6 +2898,8 @@ void compute_densities(H& h, DBuf& d1, DBuf& D1, DBuf& gf, DBuf& d2, DBuf& NLd) 
       for (auto& t : ts)
         scr = std::max(scr, (t.up ? all_rows(h, t.ket) : all_rows(h, t.bra)) * t.d.ny * t.d.ncol);
     DBuf scratch(scr);
+    // permuted copies and the f-block product of the slot-GEMM form
+    DBuf slot_a, slot_b, slot_g;
     for (int L = 0; L < nst; ++L) {
       const int set = set_of(h, L);
       for (int b = 0; b < NBLOCK; ++b)
@@ -2802,13 +2923,15 @@ void compute_densities(H& h, DBuf& d1, DBuf& D1, DBuf& gf, DBuf& d2, DBuf& NLd) 
           const int64_t width = (int64_t)t.d.ny * nak;
           HIPCHECK(gemm_f64(false, all_rows(h, t.bra), width, nab, 1.0, lall[t.bra].p, nab, 0, t.G.p, width, 0,
                             0.0, scratch.p, width, 0, 1, h.s));
-          HIPCHECK(fock_grad(t.d, scratch.p, width, nak, tall[t.ket].p, nak, 0, nak, gf.p + t.f_off, nmo, skip,
-                             h.s));
+          if (!slot_grad(h, t, nak, scratch.p, tall[t.ket].p, gf.p, nmo, skip, slot_a, slot_b, slot_g))
+            HIPCHECK(fock_grad(t.d, scratch.p, width, nak, tall[t.ket].p, nak, 0, nak, gf.p + t.f_off, nmo, skip,
+                               h.s));
         }
       }
       host_sync(h);
     }
   }
+  progress(h, "densities: coupling terms");
   // ---- <L~|E_rs|L~> and the finished dbar2, d2 ----------------------------
   DBuf gam((int64_t)nst * h.na * h.na);
   gam.zero(h.s);
@@ -3070,6 +3193,31 @@ int caspt2_profile_entry(caspt2_handle* h, int32_t k, double* avg_ms, int64_t* l
     if (avg_ms) *avg_ms = n ? tot / n : 0.0;
     if (launches) *launches = n;
     if (bytes_per_launch) *bytes_per_launch = n ? bytes / n : 0.0;
+    return CASPT2_OK;
+  })
+}
+
+int caspt2_profile_stage(caspt2_handle* h, int32_t k, char* name, int32_t name_len, double* ms_per_residual,
+                         int64_t* residuals) {
+  if (!h || k < 0) return CASPT2_E_ARG;
+  if (k >= (int32_t)h->prof_stage.size()) return CASPT2_E_ARG;
+  ABI_GUARD({
+    HIPCHECK(hipStreamSynchronize(h->s));
+    double tot = 0.0;
+    int64_t n = 0, nres = 0;
+    for (auto& r : h->prof_events) {
+      if (r.entry == (int)h->sets[0].size()) ++nres;   // one per residual with couplings
+      if (r.entry != 1000 + k) continue;
+      float ms = 0.f;
+      HIPCHECK(hipEventElapsedTime(&ms, r.a, r.b));
+      tot += ms;
+      ++n;
+    }
+    if (name && name_len > 0) {
+      std::snprintf(name, (size_t)name_len, "%s", h->prof_stage[k].c_str());
+    }
+    if (ms_per_residual) *ms_per_residual = nres ? tot / nres : 0.0;
+    if (residuals) *residuals = nres;
     return CASPT2_OK;
   })
 }

@@ -299,6 +299,101 @@ hipError_t pack_ccvv(int nc, int nv, int ncol, const T* in_all, T* plus, T* minu
   return hipGetLastError();
 }
 
+// The transpose of k_pack_ccvv: the packed ccvv entries + (i >= j, a >= b)
+// and - (i > j, a > b) (rows of ncol <= 4 values) into the all-orderings
+// tensor [i][j][a][b][ncol], every element written once (no clearing):
+// x[e] = sum_chi chi(pi_e) t_chi[rep(e)] / sqrt(|orbit|).  A workgroup takes
+// one closed pair (i >= j) and a 16 x 16 tile (A, B) of virtual pairs with
+// A >= B; the images with (a, b) unswapped are written straight from the
+// thread that read the packed rows (rows along b), the swapped ones through
+// LDS from the transposed position, so every global access runs along
+// contiguous rows.
+template <typename T>
+__global__ __launch_bounds__(256) void k_unpack_ccvv(int nc, int nv, int ncol, const T* __restrict__ plus,
+                                                     const T* __restrict__ minus, T* __restrict__ out) {
+  __shared__ double sw[2][PCC_T * PCC_T][4];   // (i,j,b,a) and (j,i,b,a) images of rep (a, b)
+  const int t = threadIdx.x;
+  int A = 0, rem = blockIdx.x;
+  while (rem > A) {
+    rem -= A + 1;
+    ++A;
+  }
+  const int B = rem;
+  int i = 0;
+  {
+    int r = blockIdx.y;
+    while (r > i) {
+      r -= i + 1;
+      ++i;
+    }
+    rem = r;
+  }
+  const int j = rem;
+  const int a0 = A * PCC_T, b0 = B * PCC_T;
+  const int tl = t / PCC_T, tf = t % PCC_T;
+  const int64_t nv2 = (int64_t)nv * nv;
+  const int64_t pij = ((int64_t)i * nc + j) * nv2, pji = ((int64_t)j * nc + i) * nv2;
+  const int64_t npv = (int64_t)nv * (nv + 1) / 2, nmv = (int64_t)nv * (nv - 1) / 2;
+  const bool dij = i != j;
+  {
+    const int a = a0 + tl, b = b0 + tf;
+    double v[4][4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) v[k][c] = 0.0;
+    const bool rep = a < nv && b < nv && a >= b;
+    if (rep) {
+      const bool dab = a != b;
+      const double w = (dij && dab) ? 0.5 : ((dij || dab) ? 0.70710678118654752440 : 1.0);
+      const int64_t rp = ((int64_t)i * (i + 1) / 2 + j) * npv + (int64_t)a * (a + 1) / 2 + b;
+      const bool hasm = dij && dab && minus;
+      const int64_t rm = hasm ? ((int64_t)i * (i - 1) / 2 + j) * nmv + (int64_t)a * (a - 1) / 2 + b : 0;
+      for (int c = 0; c < ncol; ++c) {
+        const double pv = w * (double)plus[rp * ncol + c];
+        const double mv = hasm ? 0.5 * (double)minus[rm * ncol + c] : 0.0;
+        v[0][c] = pv + mv;   // (i, j, a, b)
+        v[1][c] = pv - mv;   // (j, i, a, b)
+        v[2][c] = pv - mv;   // (i, j, b, a)
+        v[3][c] = pv + mv;   // (j, i, b, a)
+      }
+      const int64_t r = (int64_t)a * nv + b;
+      for (int c = 0; c < ncol; ++c) {
+        out[(pij + r) * ncol + c] = (T)v[0][c];
+        if (dij) out[(pji + r) * ncol + c] = (T)v[1][c];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      sw[0][t][c] = v[2][c];
+      sw[1][t][c] = v[3][c];
+    }
+  }
+  __syncthreads();
+  // swapped images: all-orderings row (b0 + tl, a0 + tf), the image of rep
+  // (a0 + tf, b0 + tl) held by thread tf * PCC_T + tl
+  const int bb = b0 + tl, aa = a0 + tf;
+  if (bb >= nv || aa >= nv || !(aa > bb)) return;
+  const int src = tf * PCC_T + tl;
+  const int64_t r = (int64_t)bb * nv + aa;
+  for (int c = 0; c < ncol; ++c) {
+    out[(pij + r) * ncol + c] = (T)sw[0][src][c];
+    if (dij) out[(pji + r) * ncol + c] = (T)sw[1][src][c];
+  }
+}
+
+template <typename T>
+hipError_t unpack_ccvv(int nc, int nv, int ncol, const T* plus, const T* minus, T* out_all, hipStream_t s) {
+  if (nc <= 0 || nv <= 0 || ncol <= 0) return hipSuccess;
+  if (ncol > 4) return hipErrorInvalidValue;
+  const int ntile = (nv + PCC_T - 1) / PCC_T;
+  const int64_t ntp = (int64_t)ntile * (ntile + 1) / 2, npc = (int64_t)nc * (nc + 1) / 2;
+  if (ntp > 0x7fffffff || npc > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_unpack_ccvv<T>, dim3((unsigned)ntp, (unsigned)npc), dim3(PCC_T * PCC_T), 0, s, nc, nv,
+                     ncol, plus, minus, out_all);
+  return hipGetLastError();
+}
+
 // Linear index maps of an expand term, folded on the host: the bra
 // all-orderings row and the Fock offset as functions of the ket slot values,
 // the free bra slots (not fed from the ket; at most two, looped) and y.
@@ -972,6 +1067,7 @@ hipError_t rows_small_gemm(int64_t nrows, int nab, int width, const T* Y, const 
   template hipError_t unpack_all<T>(const PackInfo&, const AllDesc&, const T*, T*, hipStream_t);   \
   template hipError_t pack_acc<T>(const TermDesc&, const AllDesc&, const T*, T*, hipStream_t);     \
   template hipError_t pack_ccvv<T>(int, int, int, const T*, T*, T*, hipStream_t);                   \
+  template hipError_t unpack_ccvv<T>(int, int, int, const T*, const T*, T*, hipStream_t);           \
   template hipError_t couple_expand<T>(const CoupleDesc&, const double*, const T*, T*, hipStream_t, int); \
   template hipError_t couple_reduce<T>(const CoupleDesc&, const double*, const T*, T*, hipStream_t);  \
   template hipError_t couple_reduce_packed<T>(const CoupleDesc&, const PackInfo&, const double*,     \

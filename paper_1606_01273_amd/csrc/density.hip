@@ -219,80 +219,82 @@ hipError_t density_finish(int n, int nc, int na, int nst, const double* NL, cons
 struct GradPlan {
   int dim[7];        // range of every variable (1 if absent)
   int xvar, yvar;    // variable feeding fx, fy
-  int loopvar[7];    // the other variables, slowest first
+  int loopvar[7];    // the other variables with range > 1, slowest first
   int nloop;
+  int64_t da[7], db[7];   // offset of A and of B per unit step of each variable
   int64_t loop_total;
   int64_t chunk, nchunk;
 };
 
-__device__ inline int pick7(const int v[7], int k) {
-  int r = v[0];
-  r = k == 1 ? v[1] : r;
-  r = k == 2 ? v[2] : r;
-  r = k == 3 ? v[3] : r;
-  r = k == 4 ? v[4] : r;
-  r = k == 5 ? v[5] : r;
-  r = k == 6 ? v[6] : r;
-  return r;
-}
-
-__global__ __launch_bounds__(256) void k_fock_grad(CoupleDesc d, GradPlan gp, const double* __restrict__ A,
-                                                   int64_t arow, int64_t ay, const double* __restrict__ B,
-                                                   int64_t brow, int64_t by, int64_t ncol,
+// A thread owns one (fx, fy) and a chunk [lo, hi) of the other variables'
+// linear range: the start is decoded once, then the offsets into A and B
+// advance by the variables' deltas like an odometer (no division per step).
+__global__ __launch_bounds__(256) void k_fock_grad(GradPlan gp, const double* __restrict__ A,
+                                                   const double* __restrict__ B, int64_t ncol,
                                                    double* __restrict__ gf, int64_t fstride, int skip_diag) {
   const int64_t npair = (int64_t)gp.dim[gp.xvar] * gp.dim[gp.yvar];
   const int64_t total = npair * gp.nchunk;
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
        t += (int64_t)gridDim.x * blockDim.x) {
     const int64_t pairi = t / gp.nchunk, c = t % gp.nchunk;
-    int v[7] = {0, 0, 0, 0, 0, 0, 0};
     const int fx = (int)(pairi / gp.dim[gp.yvar]), fy = (int)(pairi % gp.dim[gp.yvar]);
     if (skip_diag && fx == fy) continue;
     const int64_t lo = c * gp.chunk;
     const int64_t hi = lo + gp.chunk < gp.loop_total ? lo + gp.chunk : gp.loop_total;
-    double acc = 0.0;
-    for (int64_t q = lo; q < hi; ++q) {
-      int64_t r = q;
+    if (lo >= hi) continue;
+    int64_t oa = fx * gp.da[gp.xvar] + fy * gp.da[gp.yvar];
+    int64_t ob = fx * gp.db[gp.xvar] + fy * gp.db[gp.yvar];
+    int cnt[7] = {0, 0, 0, 0, 0, 0, 0};
+    {
+      int64_t r = lo;
       for (int k = gp.nloop - 1; k >= 0; --k) {
         const int var = gp.loopvar[k];
-        const int dk = gp.dim[var];
-        const int val = (int)(r % dk);
-        r /= dk;
-        v[0] = var == 0 ? val : v[0];
-        v[1] = var == 1 ? val : v[1];
-        v[2] = var == 2 ? val : v[2];
-        v[3] = var == 3 ? val : v[3];
-        v[4] = var == 4 ? val : v[4];
-        v[5] = var == 5 ? val : v[5];
-        v[6] = var == 6 ? val : v[6];
+        const int v = (int)(r % gp.dim[var]);
+        r /= gp.dim[var];
+        cnt[k] = v;
+        oa += v * gp.da[var];
+        ob += v * gp.db[var];
       }
-      for (int k = 0; k < 7; ++k) {
-        v[k] = k == gp.xvar ? fx : v[k];
-        v[k] = k == gp.yvar ? fy : v[k];
-      }
-      const int e[4] = {v[0], v[1], v[2], v[3]};
-      const int z[2] = {v[4], v[5]};
-      int ek[4] = {0, 0, 0, 0};
-      for (int l = 0; l < 4; ++l)
-        if (l < d.ket.nslot) {
-          const int src = d.ket_src[l];
-          const int val = src >= 0 ? pick7(v, src) : pick7(v, 4 + (-1 - src));
-          ek[0] = l == 0 ? val : ek[0];
-          ek[1] = l == 1 ? val : ek[1];
-          ek[2] = l == 2 ? val : ek[2];
-          ek[3] = l == 3 ? val : ek[3];
+    }
+    double acc = 0.0;
+    for (int64_t q = lo; q < hi; ++q) {
+      const double* pa = A + oa;
+      const double* pb = B + ob;
+      for (int64_t a = 0; a < ncol; ++a) acc += pa[a] * pb[a];
+      // next value of the loop variables (the last one fastest)
+      for (int k = gp.nloop - 1; k >= 0; --k) {
+        const int var = gp.loopvar[k];
+        if (++cnt[k] < gp.dim[var]) {
+          oa += gp.da[var];
+          ob += gp.db[var];
+          break;
         }
-      const int64_t rb = encode_all(d.bra, e);
-      const int64_t rk = encode_all(d.ket, ek);
-      (void)z;
-      const double* pa = A + rb * arow + (int64_t)v[6] * ay;
-      const double* pb = B + rk * brow + (int64_t)v[6] * by;
-      double s = 0.0;
-      for (int64_t a = 0; a < ncol; ++a) s += pa[a] * pb[a];
-      acc += s;
+        cnt[k] = 0;
+        oa -= (int64_t)(gp.dim[var] - 1) * gp.da[var];
+        ob -= (int64_t)(gp.dim[var] - 1) * gp.db[var];
+      }
     }
     if (acc != 0.0) unsafeAtomicAdd(gf + (int64_t)fx * fstride + fy, acc);
   }
+}
+
+// dst (n x n block, row stride ld) += src (n x n) or its transpose, the
+// diagonal left out when skip_diag
+__global__ void k_add_block(int n, const double* __restrict__ src, double* __restrict__ dst, int64_t ld,
+                            int transpose, int skip_diag) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n * n) return;
+  const int r = (int)(t / n), c = (int)(t % n);
+  if (skip_diag && r == c) return;
+  dst[(int64_t)r * ld + c] += transpose ? src[(int64_t)c * n + r] : src[t];
+}
+
+hipError_t add_block(int n, const double* src, double* dst, int64_t ld, int transpose, int skip_diag,
+                     hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_add_block, dim3((unsigned)cdiv((int64_t)n * n, 256)), dim3(256), 0, s, n, src, dst, ld,
+                     transpose, skip_diag);
+  return hipGetLastError();
 }
 
 // the variable (0..3 bra slot, 4..5 summed label, 6 active y) an index
@@ -311,9 +313,31 @@ hipError_t fock_grad(const CoupleDesc& d, const double* A, int64_t arow, int64_t
   for (int k = 0; k < d.bra.nslot; ++k) gp.dim[k] = d.bra.slot_dim[k];
   for (int k = 0; k < d.nsum; ++k) gp.dim[4 + k] = d.sum_dim[k];
   gp.dim[6] = d.ny;
+  for (int k = 0; k < 7; ++k)
+    if (gp.dim[k] == 0) return hipSuccess;
   gp.xvar = src_var(d.fx_src);
   gp.yvar = src_var(d.fy_src);
   if (gp.xvar == gp.yvar) return hipErrorInvalidValue;   // both indices of f from one label
+  // row strides of the all-orderings tensors
+  int64_t bst[4] = {0, 0, 0, 0}, kst[4] = {0, 0, 0, 0}, st = 1;
+  for (int k = d.bra.nslot - 1; k >= 0; --k) {
+    bst[k] = st;
+    st *= d.bra.slot_dim[k];
+  }
+  st = 1;
+  for (int l = d.ket.nslot - 1; l >= 0; --l) {
+    kst[l] = st;
+    st *= d.ket.slot_dim[l];
+  }
+  for (int k = 0; k < 7; ++k) gp.da[k] = gp.db[k] = 0;
+  for (int k = 0; k < d.bra.nslot; ++k) gp.da[k] = bst[k] * arow;
+  for (int l = 0; l < d.ket.nslot; ++l) {
+    const int src = d.ket_src[l];
+    const int var = src >= 0 ? src : 4 + (-1 - src);
+    gp.db[var] += kst[l] * brow;
+  }
+  gp.da[6] += ay;
+  gp.db[6] += by;
   gp.nloop = 0;
   gp.loop_total = 1;
   for (int k = 0; k < 7; ++k)
@@ -321,8 +345,6 @@ hipError_t fock_grad(const CoupleDesc& d, const double* A, int64_t arow, int64_t
       gp.loopvar[gp.nloop++] = k;
       gp.loop_total *= gp.dim[k];
     }
-  for (int k = 0; k < 7; ++k)
-    if (gp.dim[k] == 0) return hipSuccess;
   const int64_t npair = (int64_t)gp.dim[gp.xvar] * gp.dim[gp.yvar];
   // about 2^20 threads, each with a chunk of at least 64 loop iterations
   int64_t nchunk = cdiv((int64_t)1 << 20, npair);
@@ -332,9 +354,8 @@ hipError_t fock_grad(const CoupleDesc& d, const double* A, int64_t arow, int64_t
   gp.nchunk = nchunk;
   gp.chunk = cdiv(gp.loop_total, nchunk);
   const int64_t total = npair * nchunk;
-  unsigned grid = (unsigned)std::min<int64_t>(cdiv(total, 256), 65536);
-  hipLaunchKernelGGL(k_fock_grad, dim3(grid), dim3(256), 0, s, d, gp, A, arow, ay, B, brow, by, ncol, gf,
-                     fstride, skip_diag);
+  const unsigned grid = (unsigned)std::min<int64_t>(cdiv(total, 256), 65536);
+  hipLaunchKernelGGL(k_fock_grad, dim3(grid), dim3(256), 0, s, gp, A, B, ncol, gf, fstride, skip_diag);
   return hipGetLastError();
 }
 

@@ -177,6 +177,10 @@ hipError_t pack_acc(const TermDesc& d, const AllDesc& a, const T* in_all, T* pac
 // LDS-tiled so that the (a,b)-swapped images are read along rows
 template <typename T>
 hipError_t pack_ccvv(int nc, int nv, int ncol, const T* in_all, T* plus, T* minus, hipStream_t s);
+// the transpose: packed ccvv + and - entries (minus may be NULL) into the
+// all-orderings tensor [i][j][a][b][ncol], every element written
+template <typename T>
+hipError_t unpack_ccvv(int nc, int nv, int ncol, const T* plus, const T* minus, T* out_all, hipStream_t s);
 
 // Index sources of the coupling kernels: a value >= 0 is a bra slot, -1 - s
 // is summed external label s, -10 is the operator's active label y.
@@ -325,6 +329,10 @@ hipError_t row_metric(const TermDesc& d, const double* Y, const double* X, int v
 // (fx, fy from a bra slot, a summed label or y); skip_diag drops fx == fy
 hipError_t fock_grad(const CoupleDesc& d, const double* A, int64_t arow, int64_t ay, const double* B,
                      int64_t brow, int64_t by, int64_t ncol, double* gf, int64_t fstride, int skip_diag,
+                     hipStream_t s);
+// dst (row stride ld) += src (n x n, row major) or src^T; diagonal skipped
+// when skip_diag
+hipError_t add_block(int n, const double* src, double* dst, int64_t ld, int transpose, int skip_diag,
                      hipStream_t s);
 // Q[a][b] += sum_r X[r][a] Y[r][b] (row-major [nrow][n], row stride ld)
 hipError_t outer_rows(int64_t nrow, int64_t n, int64_t ld, const double* X, const double* Y, double* Q,

@@ -202,6 +202,43 @@ def cmd_mfma(a):
     print("\n".join(lines))
 
 
+def cmd_pmcsum(a):
+    """HBM bytes of every kernel matching a regex, per residual evaluation of
+    one state: the counters of all its dispatches in the run (each scaled by
+    the calibration factors) divided by the number of evaluations the run
+    made, next to the algorithmic bytes of one evaluation."""
+    fetch = _per_dispatch(a.fetch_csv, "FETCH_SIZE")
+    write = _per_dispatch(a.write_csv, "WRITE_SIZE")
+    fill_w = [v for k, vs in write.items() if re.search(r"FillFunctor", k) for v in vs if v * 1024 > 0.5 * GIB]
+    mul_f = [v for k, vs in fetch.items() if re.search(r"MulFunctor", k) for v in vs if v * 1024 > 0.25 * GIB]
+    if not fill_w or not mul_f:
+        sys.exit("no calibration dispatches (fill / multiply of 1 GiB) in the counter files")
+    wscale = GIB / (fill_w[-1] * 1024)
+    fscale = GIB / (mul_f[-1] * 1024)
+    kre = re.compile(a.kernel)
+    rows = []
+    for name in sorted(set(fetch) | set(write)):
+        if not kre.search(name) or re.search(r"Functor", name):
+            continue
+        nf, nw = fetch.get(name, []), write.get(name, [])
+        by = (sum(nf) * fscale + sum(nw) * wscale) * 1024 / a.evals
+        rows.append((by, max(len(nf), len(nw)) / a.evals, re.sub(r"\s+", " ", name)[:100]))
+    rows.sort(key=lambda r: -r[0])
+    tot = sum(r[0] for r in rows)
+    lines = ["# rocprofv3 PMC traffic per residual evaluation of one state",
+             f"# FETCH_SIZE run: {a.command_fetch}", f"# WRITE_SIZE run: {a.command_write}", "",
+             f"evaluations in the run: {a.evals}; calibration scales: fetch {fscale:.4f}, write {wscale:.4f}",
+             f"algorithmic bytes of one evaluation (read x and the source, write sigma): {a.algo_bytes / 1e9:.3f} GB",
+             "", f"{'GB/eval':>9} {'disp/eval':>9}  kernel"]
+    for by, n, name in rows:
+        lines.append(f"{by / 1e9:9.3f} {n:9.1f}  {name}")
+    lines += ["", f"total of the matched kernels: {tot / 1e9:.3f} GB per evaluation = "
+                  f"{tot / a.algo_bytes:.2f} x the algorithmic bytes"]
+    with open(a.out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -236,8 +273,17 @@ def main():
                    help="only dispatches from the N-th last dispatch of this kernel on")
     m.add_argument("--before-last", type=int, default=0,
                    help="with --from-last: only dispatches before the M-th last dispatch of that kernel")
+    q = sub.add_parser("pmcsum")
+    q.add_argument("fetch_csv")
+    q.add_argument("write_csv")
+    q.add_argument("out")
+    q.add_argument("--kernel", required=True)
+    q.add_argument("--evals", type=int, required=True, help="residual evaluations of one state in the run")
+    q.add_argument("--algo-bytes", type=float, required=True)
+    q.add_argument("--command-fetch", required=True)
+    q.add_argument("--command-write", required=True)
     a = ap.parse_args()
-    {"stats": cmd_stats, "pmc": cmd_pmc, "mfma": cmd_mfma}[a.cmd](a)
+    {"stats": cmd_stats, "pmc": cmd_pmc, "mfma": cmd_mfma, "pmcsum": cmd_pmcsum}[a.cmd](a)
 
 
 if __name__ == "__main__":

@@ -169,3 +169,41 @@ def test_batch_argument_errors(dev):
     assert rc == 0 and len(a) == 1 and len(a[0]) == 2
     g.close()
     gm.close()
+
+
+def test_batch_workload_matches_stored_oracle(dev):
+    """The 64-instance uneven workload solved in one batch against the CPU
+    oracle's results stored in tests/golden/batch_B.jsonl (written by
+    tests/golden/make_batch_golden.py, which calls the oracle only): E^MS of
+    every problem the oracle solved (1e-10 Eh), and every problem the oracle
+    finds not positive definite at this shift (a non-positive preconditioner
+    denominator, or p.Ap <= 0) fails in the batch too, without stopping the
+    others."""
+    import json
+    import os
+    from paper_1606_01273_amd import E_INDEFINITE, Caspt2, batch_solve
+    path = os.path.join(os.path.dirname(__file__), "golden", "batch_B.jsonl")
+    with open(path) as fh:
+        recs = [json.loads(line) for line in fh if line.strip()]
+    sizes = batch_sizes(64, seed=4)
+    assert len(recs) >= 16
+    for r in recs:
+        assert tuple(r["dims"]) == sizes[r["index"]][:5] and r["seed"] == sizes[r["index"]][5]
+    probs = [make_problem(nc, na, nv, nx, ns, seed=sd, reading="B", shift=0.2)
+             for nc, na, nv, nx, ns, sd in sizes]
+    gs = [Caspt2.from_problem(p) for p in probs]
+    rc, ainfo, linfo = batch_solve(gs, [0] * len(gs), tol=1e-10, maxiter=300)
+    bad_oracle = [r["index"] for r in recs if r["indefinite"]]
+    print(f"{len(recs)} stored problems, {len(bad_oracle)} indefinite: {bad_oracle}", flush=True)
+    assert rc in (0, E_INDEFINITE)
+    for r in recs:
+        i = r["index"]
+        solved = all(a["flags"] & 1 for a in ainfo[i])
+        if r["indefinite"]:
+            assert not solved, f"problem {i}: the oracle finds it indefinite, the batch solved it"
+            continue
+        assert solved, f"problem {i}: the oracle solves it, the batch did not"
+        H, w, R = gs[i].heff()
+        _ok(np.abs(w - np.asarray(r["e_ms"])).max(), 1e-10, f"E_MS problem {i}")
+    for g in gs:
+        g.close()
