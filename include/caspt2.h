@@ -244,6 +244,21 @@ CASPT2_API int caspt2_get_amplitudes(caspt2_handle* h, int32_t L, double* T);
 CASPT2_API int xms_rotate(int32_t nact, int32_t nst, const double* f_act, const double* rdm1, double* U,
                           double* e0);
 
+/* xms_rotate for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops, harnesses that forbid hipMalloc): the same
+ * result from device inputs into device outputs -- f_act [nact][nact],
+ * rdm1 [nst][nst][nact][nact], U [nst][nst], e0 [nst], all device memory of
+ * the current device -- issued on `stream` (a hipStream_t, NULL = default)
+ * and complete when the stream reaches it.  No device memory is allocated
+ * or freed: the one intermediate (F^ref, nst x nst) lives in a fixed
+ * device array of 16 x 16 doubles per GPU, held until the process ends; its
+ * device address is looked up on the first call on each device.  Calls that
+ * overlap on one GPU (different streams or threads) race on that array.
+ * The inputs are not checked for finiteness (device memory).  Errors: E_ARG
+ * (nact < 0, nst < 1 or nst > 16, NULL pointer), E_DEVICE. */
+CASPT2_API int xms_rotate_noalloc(int32_t nact, int32_t nst, const double* f_act, const double* rdm1, double* U,
+                                  double* e0, void* stream);
+
 /* The XMS rotation a handle applied at create (dims.xms = 1; identity when
  * 0): U [nst][nst] and E_L^(0) [nst] (Eq. 14), as xms_rotate returns them
  * for the handle's f and reference states.  host outputs, each may be NULL. */

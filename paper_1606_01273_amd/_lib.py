@@ -64,6 +64,7 @@ SIGNATURES = {
     "caspt2_get_amplitudes": (ctypes.c_int, [_P, ctypes.c_int32, _P]),
     "xms_rotate": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _D, _D, _D, _D]),
     "caspt2_get_xms": (ctypes.c_int, [_P, _D, _D]),
+    "xms_rotate_noalloc": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, _P]),
     "xms_heff": (ctypes.c_int, [_P, _D, _D, _D]),
     "caspt2_solve_lambda": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, _P,
                                            ctypes.POINTER(Info)]),
