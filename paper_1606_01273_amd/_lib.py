@@ -88,6 +88,8 @@ SIGNATURES = {
                                                 ctypes.POINTER(ctypes.c_int32)]),
     "caspt2_debug_eigh_abs": (ctypes.c_int, [ctypes.c_int32, _P, _D, _P, ctypes.c_int32, ctypes.c_double,
                                              ctypes.POINTER(ctypes.c_int32)]),
+    "caspt2_debug_ccvv_passes": (ctypes.c_int, [ctypes.c_int32]),
+    "caspt2_debug_ccvv_passes_used": (ctypes.c_int, [_P, ctypes.c_int32]),
     "caspt2_profile_stage": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_char_p, ctypes.c_int32, _D,
                                             ctypes.POINTER(ctypes.c_int64)]),
     "caspt2_densities": (ctypes.c_int, [_P, _D, _P, _D, _D, _D]),

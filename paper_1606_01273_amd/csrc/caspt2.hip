@@ -147,7 +147,14 @@ struct CoupleTerm {
   int sg_slot = -1;      // down term of a block with itself that applies f along one bra slot of the
                          // ket tensor: that slot (batched MFMA GEMM in FP64), else -1
   bool sg_perm = false;  // ... read from the block's slot-permuted copy of x
+  int ccvv_kind = -1;    // up term into ccvv applied by the packed-row passes (couple_ccvv.hip): its role
+                         // (CcvvKind), else -1
 };
+
+// roles of the up terms into ccvv in the packed-row passes, with the slot
+// maps the host engine gives them (bra slots i, j, a, b = 0..3; the Fock
+// indices as bra slots, -10 the active label)
+enum CcvvKind { CK_CAVV1 = 0, CK_CAVV2, CK_CCAV1, CK_CCAV2, CK_CAAV1, CK_CAAV2, CK_N };
 
 // element-type selection of the per-entry and per-term operands
 template <typename T>
@@ -270,6 +277,11 @@ struct caspt2_handle {
   DBuf xperm[NBLOCK], xperm2[NBLOCK];                   // slot-permuted all-orderings x (both work sets)
   int xperm_p[NBLOCK][4] = {};                          // its slot map: copy[e] = x[e[p[0]], e[p[1]], ..]
   bool direct[NBLOCK] = {};                            // ket read from packed rows (no all-orderings x)
+  std::vector<char> ccvv_fused;                        // per set: up terms into ccvv run as packed-row passes
+  IBuf ccvv_groups;                                    // workgroup table of the virtual-pair pass
+  int64_t ccvv_ngroups = 0;
+  int64_t ccvv_woff[CK_N] = {};                        // offsets of the W products in ccvv_w (-1: absent)
+  DBuf ccvv_w, ccvv_w2;                                // W products of the ccav and caav terms (both work sets)
   bool have_mixed = false;                             // FP32 operand copies made
   bool prof_on = false;
   bool verbose = false;
@@ -1154,6 +1166,75 @@ void make_coupling_terms(H& h, const std::vector<std::pair<char, char>>& comps,
     }
 }
 
+// up terms into ccvv as packed-row passes (caspt2_debug_ccvv_passes turns
+// them off for handles created afterwards, to compare with the term path)
+bool g_ccvv_passes = true;
+int64_t nalpha_of_block(const H& h, int set, int block);
+
+// Classify the up terms into ccvv of every function set by their roles in the
+// packed-row passes; a set runs the passes when every such term has a role
+// (one term per role) and the shapes fit the kernels, else the term path.
+void classify_ccvv_terms(H& h) {
+  const int nsets = (int)h.couple.size();
+  h.ccvv_fused.assign(nsets, 0);
+  if (!g_ccvv_passes || h.nc == 0 || h.nv == 0) return;
+  const int64_t fac = (int64_t)h.nc * h.nmo, fvc = (int64_t)(h.nc + h.na) * h.nmo, fva = fvc + h.nc;
+  for (int set = 0; set < nsets; ++set) {
+    const int64_t ncol = nalpha_of_block(h, set, CCVV), nak = nalpha_of_block(h, set, CAVV);
+    if (!ccvv_up_supported(h.nc, h.nv, (int)ncol, h.na, (int)(nak ? nak : h.na * ncol))) continue;
+    CoupleTerm* by_kind[CK_N] = {};
+    bool ok = true, any = false;
+    for (auto& t : h.couple[set]) {
+      if (!t.up || t.bra != CCVV) continue;
+      any = true;
+      const int* k = t.d.ket_src;
+      int kind = -1;
+      if (t.d.nsum == 0 && t.d.ncol == ncol && t.d.f_stride == h.nmo) {
+        if (t.ket == CAVV && t.d.ny == h.na && t.f_off == fac && t.d.fx_src == -10 && t.d.fy_src == 1 &&
+            k[0] == 0 && nak == (int64_t)h.na * ncol) {
+          if (k[1] == 2 && k[2] == 3) kind = CK_CAVV1;
+          else if (k[1] == 3 && k[2] == 2) kind = CK_CAVV2;
+        } else if (t.ket == CCAV && t.d.ny == h.na && t.f_off == fva && t.d.fy_src == -10 && k[0] == 0 &&
+                   k[1] == 1) {
+          if (k[2] == 2 && t.d.fx_src == 3) kind = CK_CCAV1;
+          else if (k[2] == 3 && t.d.fx_src == 2) kind = CK_CCAV2;
+        } else if (t.ket == CAAV && t.d.ny == 1 && t.f_off == fvc && t.d.fy_src == 1 && k[0] == 0) {
+          if (k[1] == 2 && t.d.fx_src == 3) kind = CK_CAAV1;
+          else if (k[1] == 3 && t.d.fx_src == 2) kind = CK_CAAV2;
+        }
+      }
+      if (kind < 0 || by_kind[kind]) {
+        ok = false;
+        break;
+      }
+      by_kind[kind] = &t;
+    }
+    if (!ok || !any) continue;
+    for (int k = 0; k < CK_N; ++k)
+      if (by_kind[k]) by_kind[k]->ccvv_kind = k;
+    h.ccvv_fused[set] = 1;
+  }
+  bool anyset = false;
+  for (char f : h.ccvv_fused) anyset = anyset || f;
+  if (!anyset) return;
+  // W products of the ccav and caav roles, one region per role
+  int64_t ncol = 0;
+  for (int set = 0; set < nsets; ++set) ncol = std::max(ncol, nalpha_of_block(h, set, CCVV));
+  const int64_t wccav = all_rows(h, CCAV) * h.na * ncol, wcaav = all_rows(h, CAAV) * ncol;
+  h.ccvv_woff[CK_CAVV1] = h.ccvv_woff[CK_CAVV2] = -1;
+  h.ccvv_woff[CK_CCAV1] = 0;
+  h.ccvv_woff[CK_CCAV2] = wccav;
+  h.ccvv_woff[CK_CAAV1] = 2 * wccav;
+  h.ccvv_woff[CK_CAAV2] = 2 * wccav + wcaav;
+  h.ccvv_w.alloc(2 * (wccav + wcaav));
+  const std::vector<uint32_t> groups = ccvv_up_groups(h.nv);
+  h.ccvv_ngroups = (int64_t)groups.size();
+  h.ccvv_groups.alloc(h.ccvv_ngroups);
+  HIPCHECK(hipMemcpyAsync(h.ccvv_groups.p, groups.data(), groups.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
+                          h.s));
+  host_sync(h);
+}
+
 void setup_couplings(H& h) {
   const bool ss = h.d.scheme == CASPT2_SSSR;
   const int nst = h.nst;
@@ -1265,9 +1346,13 @@ void setup_couplings(H& h) {
       t.sg_slot = sb;
       h.direct[b] = false;
     }
+  classify_ccvv_terms(h);
   int64_t scratch = 0;
+  bool sall_need[NBLOCK] = {false, false, false, false, false, false, false, false};
   for (auto& cs : h.couple)
     for (auto& t : cs) {
+      if (t.ccvv_kind >= 0) continue;   // packed-row passes: no all-orderings sigma, no scratch
+      sall_need[t.bra] = true;
       if (t.up && h.direct[t.ket]) throw DevError(CASPT2_E_NOTIMPL, "up coupling from a packed ket");
       if (t.up)
         scratch = std::max(scratch, all_rows(h, t.ket) * t.d.ny * t.d.ncol);
@@ -1281,7 +1366,7 @@ void setup_couplings(H& h) {
     if (!used[b]) continue;
     const int64_t na_b = nset_of * (int64_t)BL[b].types.size() * ipow(h.na, (int)BL[b].act.size());
     if (!h.direct[b]) h.xall[b].alloc(all_rows(h, b) * na_b);
-    h.sall[b].alloc(all_rows(h, b) * na_b);
+    if (sall_need[b]) h.sall[b].alloc(all_rows(h, b) * na_b);
   }
   for (auto& cs : h.couple)
     for (auto& t : cs)
@@ -1307,6 +1392,7 @@ void ensure_work_set2(H& h) {
     if (h.xperm[b].n && h.xperm2[b].n != h.xperm[b].n) h.xperm2[b].alloc(h.xperm[b].n);
   }
   if (h.cscratch.n && h.cscratch2.n != h.cscratch.n) h.cscratch2.alloc(h.cscratch.n);
+  if (h.ccvv_w.n && h.ccvv_w2.n != h.ccvv_w.n) h.ccvv_w2.alloc(h.ccvv_w.n);
   if (h.splitk_ws2.n != h.splitk_ws.n) h.splitk_ws2.alloc(h.splitk_ws.n);
 }
 
@@ -1354,6 +1440,7 @@ bool slot_gemm(H& h, const CoupleTerm& t, int64_t nak, const float* X, float* Y,
 // copies are current).  fuse: the term's own choice, or -1/0/1 to override.
 template <typename T>
 void couple_term(H& h, int set, const CoupleTerm& t, const T* x, int fuse) {
+  if (t.ccvv_kind >= 0) throw DevError(CASPT2_E_ARG, "term applied by the ccvv packed-row passes");
   T* scratch = reinterpret_cast<T*>(cscratch_of(h).p);
   T* xk = reinterpret_cast<T*>(xall_of(h, t.ket).p);
   T* sb = reinterpret_cast<T*>(sall_of(h, t.bra).p);
@@ -1384,6 +1471,58 @@ void couple_term(H& h, int set, const CoupleTerm& t, const T* x, int fuse) {
   }
 }
 
+// the up terms into ccvv of a set whose roles were classified: the W
+// products of the ccav and caav terms by GEMM, then the two packed-row passes
+// (the cavv terms contract with their active tensors inside the first)
+template <typename T>
+void ccvv_up_passes(H& h, int set, T* sig) {
+  const CoupleTerm* tk[CK_N] = {};
+  for (auto& t : h.couple[set])
+    if (t.ccvv_kind >= 0) tk[t.ccvv_kind] = &t;
+  T* wbuf = reinterpret_cast<T*>((h.wset ? h.ccvv_w2 : h.ccvv_w).p);
+  CcvvUpArgs<T> a;
+  a.nc = h.nc;
+  a.nv = h.nv;
+  a.ny = h.na;
+  a.ncol = (int)nalpha_of_block(h, set, CCVV);
+  a.nak = a.ny * a.ncol;
+  for (int k : {CK_CCAV1, CK_CCAV2, CK_CAAV1, CK_CAAV2}) {
+    const CoupleTerm* t = tk[k];
+    if (!t) continue;
+    const int64_t nak = nalpha_of_block(h, set, t->ket);
+    const int64_t width = (int64_t)t->d.ny * a.ncol;
+    HIPCHECK(gemm_t(true, all_rows(h, t->ket), width, nak, 1.0, reinterpret_cast<const T*>(xall_of(h, t->ket).p),
+                    nak, Sel<T>::G(*t), nak, 0.0, wbuf + h.ccvv_woff[k], width, h.s));
+  }
+  auto W = [&](int k) { return tk[k] ? (const T*)(wbuf + h.ccvv_woff[k]) : nullptr; };
+  const CoupleTerm* tA = tk[CK_CAVV1] ? tk[CK_CAVV1] : tk[CK_CAVV2];
+  const CoupleTerm* tB = tk[CK_CCAV1] ? tk[CK_CCAV1] : tk[CK_CCAV2];
+  const CoupleTerm* tC = tk[CK_CAAV1] ? tk[CK_CAAV1] : tk[CK_CAAV2];
+  if (tA) {
+    a.X = reinterpret_cast<const T*>(xall_of(h, CAVV).p);
+    a.G1 = tk[CK_CAVV1] ? Sel<T>::G(*tk[CK_CAVV1]) : nullptr;
+    a.G2 = tk[CK_CAVV2] ? Sel<T>::G(*tk[CK_CAVV2]) : nullptr;
+    a.fA = h.fock.p + tA->f_off;
+    a.fA_stride = h.nmo;
+  }
+  if (tB) {
+    a.W3 = W(CK_CCAV1);
+    a.W4 = W(CK_CCAV2);
+    a.fV = h.fock.p + tB->f_off;
+    a.fV_stride = h.nmo;
+  }
+  if (tC) {
+    a.W5 = W(CK_CAAV1);
+    a.W6 = W(CK_CAAV2);
+    a.fC = h.fock.p + tC->f_off;
+    a.fC_stride = h.nmo;
+  }
+  for (auto& e : h.sets[set])
+    if (e.block == CCVV && e.nrow > 0) (e.chi.empty() || e.chi[0] > 0 ? a.plus : a.minus) = sig + e.offset;
+  if (!a.plus) return;
+  HIPCHECK(ccvv_up_apply<T>(a, reinterpret_cast<const uint32_t*>(h.ccvv_groups.p), h.ccvv_ngroups, h.s));
+}
+
 template <typename T>
 void apply_couplings(H& h, int set, const T* x, T* sig) {
   auto nalpha_of = [&](int block) { return nalpha_of_block(h, set, block); };
@@ -1409,7 +1548,7 @@ void apply_couplings(H& h, int set, const T* x, T* sig) {
   hipEvent_t sev = nullptr;
   prof_begin(h, &sev);
   for (int b = 0; b < NBLOCK; ++b) {
-    if (!sall_of(h, b).p) continue;
+    if (!sall_of(h, b).p && !xall_of(h, b).p) continue;
     const int64_t na_b = nalpha_of(b);
     if (xall_of(h, b).p) {
       if (b == CCVV && na_b <= 4) {
@@ -1440,11 +1579,12 @@ void apply_couplings(H& h, int set, const T* x, T* sig) {
                             h.s));
     }
     // fill kernel, not a memset: this sequence is recorded into HIP graphs
-    HIPCHECK(vec_fill(sall_of(h, b).n, 0.0, sall_of(h, b).p, h.s));
+    if (sall_of(h, b).p) HIPCHECK(vec_fill(sall_of(h, b).n, 0.0, sall_of(h, b).p, h.s));
   }
   stage("unpack");
   if (h.prof_on) prof_end(h, stage_id("unpack"), 0.0, sev);
   for (auto& t : h.couple[set]) {
+    if (t.ccvv_kind >= 0) continue;   // below, in the packed-row passes
     if (h.prof_on) prof_begin(h, &sev);
     if (diag) {
       stage("stage");
@@ -1459,6 +1599,12 @@ void apply_couplings(H& h, int set, const T* x, T* sig) {
                0.0, sev);
   }
   stage("last term");
+  if (set < (int)h.ccvv_fused.size() && h.ccvv_fused[set]) {
+    if (h.prof_on) prof_begin(h, &sev);
+    ccvv_up_passes<T>(h, set, sig);
+    stage("ccvv up passes");
+    if (h.prof_on) prof_end(h, stage_id("up ccvv passes"), 0.0, sev);
+  }
   if (h.prof_on) prof_begin(h, &sev);
   for (int b = 0; b < NBLOCK; ++b) {
     if (!sall_of(h, b).p) continue;
@@ -2517,7 +2663,7 @@ void autotune(H& h, const char* cache_path, bool force) {
     for (size_t set = 0; set < h.couple.size(); ++set)
       for (auto& t : h.couple[set]) {
         const int64_t nak = nalpha_of_block(h, (int)set, t.ket);
-        if (!t.up || t.d.ny > 8) continue;
+        if (!t.up || t.d.ny > 8 || t.ccvv_kind >= 0) continue;
         const bool fusable = couple_up_fusable<double>(t.d, nak);
         int64_t rows_k = 1;
         for (int k = 0; k < t.d.ket.nslot; ++k) rows_k *= t.d.ket.slot_dim[k];
@@ -3559,6 +3705,17 @@ int caspt2_get_lambda(caspt2_handle* h, int32_t L, double* lambda) {
 #include "../../include/caspt2_debug.h"
 
 extern "C" {
+
+int caspt2_debug_ccvv_passes(int32_t on) {
+  const int prev = g_ccvv_passes ? 1 : 0;
+  g_ccvv_passes = on != 0;
+  return prev;
+}
+
+int caspt2_debug_ccvv_passes_used(const caspt2_handle* h, int32_t set) {
+  if (!h || set < 0 || set >= (int32_t)h->couple.size()) return CASPT2_E_ARG;
+  return set < (int32_t)h->ccvv_fused.size() && h->ccvv_fused[set] ? 1 : 0;
+}
 
 int caspt2_debug_gemm(int32_t b_is_nk, int64_t M, int64_t N, int64_t K, const double* A,
                       const double* B, double* C) {

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 namespace caspt2 {
 
@@ -225,6 +226,38 @@ hipError_t couple_reduce_packed(const CoupleDesc& d, const PackInfo& pk, const d
 // of a down term's reduce with its active tensor when both are narrow)
 template <typename T>
 hipError_t rows_small_gemm(int64_t nrows, int nab, int width, const T* Y, const T* G, T* out, hipStream_t s);
+
+// The up coupling terms into ccvv added straight into its packed rows
+// (couple_ccvv.hip).  Absent terms are NULL.  Row layouts are the
+// all-orderings ones: X_cavv [i][a][b][nak], W5/W6 (caav) [i][a][ncol],
+// W3/W4 (ccav) [i][j][a][ny * ncol]; G1/G2 [ny * ncol][nak] (nak = ny * ncol).
+// f(y, j) = fA[y * fA_stride + j], f(v, j) = fC[v * fC_stride + j],
+// f(v, y) = fV[v * fV_stride + y].  plus/minus: the packed + and - entries
+// (rows of ncol values; minus may be NULL).
+template <typename T>
+struct CcvvUpArgs {
+  int nc = 0, nv = 0, ncol = 0, ny = 0, nak = 0;
+  const T* X = nullptr;
+  const T* G1 = nullptr;
+  const T* G2 = nullptr;
+  const double* fA = nullptr;
+  int64_t fA_stride = 0;
+  const T* W5 = nullptr;
+  const T* W6 = nullptr;
+  const double* fC = nullptr;
+  int64_t fC_stride = 0;
+  const T* W3 = nullptr;
+  const T* W4 = nullptr;
+  const double* fV = nullptr;
+  int64_t fV_stride = 0;
+  T* plus = nullptr;
+  T* minus = nullptr;
+};
+bool ccvv_up_supported(int nc, int nv, int ncol, int ny, int nak);
+// workgroup table of the virtual-pair pass: a << 16 | b0 per group
+std::vector<uint32_t> ccvv_up_groups(int nv);
+template <typename T>
+hipError_t ccvv_up_apply(const CcvvUpArgs<T>& p, const uint32_t* groups, int64_t ngroups, hipStream_t s);
 
 // X0[i][k] = Q[i][idx[k]] * scale[k]  (Q is n x ncq, X0 is n x nk)
 hipError_t select_scale_cols(int64_t n, int64_t ncq, const double* Q, const int32_t* idx,
