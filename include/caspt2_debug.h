@@ -62,15 +62,17 @@ CASPT2_API int caspt2_debug_eigh_method(int32_t n, double* A, double* w, double*
 CASPT2_API int caspt2_debug_eigh_abs(int32_t n, double* A, double* w, double* V, int32_t method,
                                      double abs_tol, int32_t* sweeps);
 
-/* Up coupling terms into ccvv (Eq. 10 with the f of Eq. 11): 1 (default)
- * applies them in the two packed-row passes for handles created from now
- * on, 0 through the all-orderings sigma of ccvv and its packing, term by
- * term, as every other coupling (for comparing the two).  Returns the
- * previous setting.  Not thread-safe against concurrent caspt2_create. */
+/* Coupling terms of ccvv (Eq. 10 with the f of Eq. 11): 1 (default) applies
+ * the up terms into ccvv in two packed-row passes and the down terms out of
+ * ccvv into cavv and caav in one, for handles created from now on; 0 runs
+ * them term by term through the all-orderings tensors, as every other
+ * coupling (for comparing the two).  Returns the previous setting.  Not
+ * thread-safe against concurrent caspt2_create. */
 CASPT2_API int caspt2_debug_ccvv_passes(int32_t on);
 
-/* 1 if function set `set` of the handle applies its up terms into ccvv in
- * the packed-row passes, 0 if term by term; E_ARG for a bad set. */
+/* For function set `set` of the handle: bit 0 set if its up terms into
+ * ccvv run in the packed-row passes, bit 1 if its down terms out of ccvv
+ * into cavv and caav do; 0 if all run term by term; E_ARG for a bad set. */
 CASPT2_API int caspt2_debug_ccvv_passes_used(const caspt2_handle* h, int32_t set);
 
 #ifdef __cplusplus

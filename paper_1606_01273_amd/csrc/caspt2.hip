@@ -149,12 +149,17 @@ struct CoupleTerm {
   bool sg_perm = false;  // ... read from the block's slot-permuted copy of x
   int ccvv_kind = -1;    // up term into ccvv applied by the packed-row passes (couple_ccvv.hip): its role
                          // (CcvvKind), else -1
+  int ccvv_down = -1;    // down term out of ccvv into cavv or caav applied by the packed-row pass: its
+                         // role (CcvvDownKind), else -1
 };
 
 // roles of the up terms into ccvv in the packed-row passes, with the slot
 // maps the host engine gives them (bra slots i, j, a, b = 0..3; the Fock
 // indices as bra slots, -10 the active label)
 enum CcvvKind { CK_CAVV1 = 0, CK_CAVV2, CK_CCAV1, CK_CCAV2, CK_CAAV1, CK_CAAV2, CK_N };
+// roles of the down terms out of ccvv in the packed-row pass (cavv bra slots
+// i, a, b; caav i, a; the ket ccvv slots from bra slots or summed labels -1, -2)
+enum CcvvDownKind { DK_CAVV1 = 0, DK_CAVV2, DK_CAAV1, DK_CAAV2, DK_CCAV1, DK_CCAV2, DK_N };
 
 // element-type selection of the per-entry and per-term operands
 template <typename T>
@@ -282,6 +287,8 @@ struct caspt2_handle {
   int64_t ccvv_ngroups = 0;
   int64_t ccvv_woff[CK_N] = {};                        // offsets of the W products in ccvv_w (-1: absent)
   DBuf ccvv_w, ccvv_w2;                                // W products of the ccav and caav terms (both work sets)
+  std::vector<char> ccvv_down_fused;                   // per set: down terms out of ccvv into cavv, caav as a pass
+  DBuf ccvv_t, ccvv_t2, ccvv_y, ccvv_y2;               // caav partial sums and reductions (both work sets)
   bool have_mixed = false;                             // FP32 operand copies made
   bool prof_on = false;
   bool verbose = false;
@@ -1214,19 +1221,72 @@ void classify_ccvv_terms(H& h) {
       if (by_kind[k]) by_kind[k]->ccvv_kind = k;
     h.ccvv_fused[set] = 1;
   }
+  // down terms out of ccvv into cavv and caav
+  h.ccvv_down_fused.assign(nsets, 0);
+  const int64_t fca = h.nc, fcv = h.nc + h.na, fav = (int64_t)h.nc * h.nmo + h.nc + h.na;
+  for (int set = 0; set < nsets; ++set) {
+    const int64_t ncol = nalpha_of_block(h, set, CCVV), nab = nalpha_of_block(h, set, CAVV);
+    if (!ccvv_down_supported(h.nc, h.nv, (int)ncol, h.na, (int)(nab ? nab : h.na * ncol))) continue;
+    CoupleTerm* by_kind[DK_N] = {};
+    bool ok = true, any = false;
+    for (auto& t : h.couple[set]) {
+      if (t.up || t.ket != CCVV || (t.bra != CAVV && t.bra != CAAV && t.bra != CCAV)) continue;
+      any = true;
+      const int* k = t.d.ket_src;
+      int kind = -1;
+      if (t.d.ncol == ncol && t.d.f_stride == h.nmo && t.sg_slot < 0 && k[0] == -1 && k[1] == 0 &&
+          t.d.fx_src == -1) {
+        if (t.bra == CAVV && t.d.nsum == 1 && t.d.sum_dim[0] == h.nc && t.d.ny == h.na && t.f_off == fca &&
+            t.d.fy_src == -10 && nab == (int64_t)h.na * ncol) {
+          if (k[2] == 1 && k[3] == 2) kind = DK_CAVV1;
+          else if (k[2] == 2 && k[3] == 1) kind = DK_CAVV2;
+        } else if (t.bra == CAAV && t.d.nsum == 2 && t.d.sum_dim[0] == h.nc && t.d.sum_dim[1] == h.nv &&
+                   t.d.ny == 1 && t.f_off == fcv && t.d.fy_src == -2) {
+          if (k[2] == -2 && k[3] == 1) kind = DK_CAAV1;
+          else if (k[2] == 1 && k[3] == -2) kind = DK_CAAV2;
+        }
+      }
+      if (t.bra == CCAV && t.d.ncol == ncol && t.d.f_stride == h.nmo && t.sg_slot < 0 && k[0] == 0 && k[1] == 1 &&
+          t.d.nsum == 1 && t.d.sum_dim[0] == h.nv && t.d.ny == h.na && t.f_off == fav && t.d.fx_src == -10 &&
+          t.d.fy_src == -1 && nalpha_of_block(h, set, CCAV) == (int64_t)h.na * ncol) {
+        if (k[2] == -1 && k[3] == 2) kind = DK_CCAV1;
+        else if (k[2] == 2 && k[3] == -1) kind = DK_CCAV2;
+      }
+      if (kind < 0 || by_kind[kind]) {
+        ok = false;
+        break;
+      }
+      by_kind[kind] = &t;
+    }
+    if (!ok || !any) continue;
+    for (int k = 0; k < DK_N; ++k)
+      if (by_kind[k]) by_kind[k]->ccvv_down = k;
+    h.ccvv_down_fused[set] = 1;
+  }
+  bool anydown = false;
+  for (char f : h.ccvv_down_fused) anydown = anydown || f;
+  if (anydown) {
+    int64_t ncol = 0;
+    for (int set = 0; set < nsets; ++set) ncol = std::max(ncol, nalpha_of_block(h, set, CCVV));
+    h.ccvv_t.alloc(2 * (int64_t)h.nc * h.nv * h.nv * ncol);
+    h.ccvv_y.alloc(2 * (int64_t)h.nc * h.nv * ncol);
+  }
   bool anyset = false;
   for (char f : h.ccvv_fused) anyset = anyset || f;
-  if (!anyset) return;
-  // W products of the ccav and caav roles, one region per role
-  int64_t ncol = 0;
-  for (int set = 0; set < nsets; ++set) ncol = std::max(ncol, nalpha_of_block(h, set, CCVV));
-  const int64_t wccav = all_rows(h, CCAV) * h.na * ncol, wcaav = all_rows(h, CAAV) * ncol;
-  h.ccvv_woff[CK_CAVV1] = h.ccvv_woff[CK_CAVV2] = -1;
-  h.ccvv_woff[CK_CCAV1] = 0;
-  h.ccvv_woff[CK_CCAV2] = wccav;
-  h.ccvv_woff[CK_CAAV1] = 2 * wccav;
-  h.ccvv_woff[CK_CAAV2] = 2 * wccav + wcaav;
-  h.ccvv_w.alloc(2 * (wccav + wcaav));
+  if (!anyset && !anydown) return;
+  if (anyset) {
+    // W products of the ccav and caav roles, one region per role
+    int64_t ncol = 0;
+    for (int set = 0; set < nsets; ++set) ncol = std::max(ncol, nalpha_of_block(h, set, CCVV));
+    const int64_t wccav = all_rows(h, CCAV) * h.na * ncol, wcaav = all_rows(h, CAAV) * ncol;
+    h.ccvv_woff[CK_CAVV1] = h.ccvv_woff[CK_CAVV2] = -1;
+    h.ccvv_woff[CK_CCAV1] = 0;
+    h.ccvv_woff[CK_CCAV2] = wccav;
+    h.ccvv_woff[CK_CAAV1] = 2 * wccav;
+    h.ccvv_woff[CK_CAAV2] = 2 * wccav + wcaav;
+    h.ccvv_w.alloc(2 * (wccav + wcaav));
+  }
+  // workgroup table of the virtual-pair passes (up and down)
   const std::vector<uint32_t> groups = ccvv_up_groups(h.nv);
   h.ccvv_ngroups = (int64_t)groups.size();
   h.ccvv_groups.alloc(h.ccvv_ngroups);
@@ -1349,9 +1409,16 @@ void setup_couplings(H& h) {
   classify_ccvv_terms(h);
   int64_t scratch = 0;
   bool sall_need[NBLOCK] = {false, false, false, false, false, false, false, false};
+  bool xall_need[NBLOCK] = {false, false, false, false, false, false, false, false};
   for (auto& cs : h.couple)
     for (auto& t : cs) {
+      if (t.ccvv_down < 0) xall_need[t.ket] = true;   // the ccvv down passes read the packed rows
       if (t.ccvv_kind >= 0) continue;   // packed-row passes: no all-orderings sigma, no scratch
+      if (t.ccvv_down >= 0) {
+        // into packed rows, except caav (its reduction, in a buffer of its own, then a GEMM)
+        if (t.ccvv_down == DK_CAAV1 || t.ccvv_down == DK_CAAV2) sall_need[t.bra] = true;
+        continue;
+      }
       sall_need[t.bra] = true;
       if (t.up && h.direct[t.ket]) throw DevError(CASPT2_E_NOTIMPL, "up coupling from a packed ket");
       if (t.up)
@@ -1365,7 +1432,7 @@ void setup_couplings(H& h) {
   for (int b = 0; b < NBLOCK; ++b) {
     if (!used[b]) continue;
     const int64_t na_b = nset_of * (int64_t)BL[b].types.size() * ipow(h.na, (int)BL[b].act.size());
-    if (!h.direct[b]) h.xall[b].alloc(all_rows(h, b) * na_b);
+    if (!h.direct[b] && xall_need[b]) h.xall[b].alloc(all_rows(h, b) * na_b);
     if (sall_need[b]) h.sall[b].alloc(all_rows(h, b) * na_b);
   }
   for (auto& cs : h.couple)
@@ -1393,6 +1460,8 @@ void ensure_work_set2(H& h) {
   }
   if (h.cscratch.n && h.cscratch2.n != h.cscratch.n) h.cscratch2.alloc(h.cscratch.n);
   if (h.ccvv_w.n && h.ccvv_w2.n != h.ccvv_w.n) h.ccvv_w2.alloc(h.ccvv_w.n);
+  if (h.ccvv_t.n && h.ccvv_t2.n != h.ccvv_t.n) h.ccvv_t2.alloc(h.ccvv_t.n);
+  if (h.ccvv_y.n && h.ccvv_y2.n != h.ccvv_y.n) h.ccvv_y2.alloc(h.ccvv_y.n);
   if (h.splitk_ws2.n != h.splitk_ws.n) h.splitk_ws2.alloc(h.splitk_ws.n);
 }
 
@@ -1440,7 +1509,7 @@ bool slot_gemm(H& h, const CoupleTerm& t, int64_t nak, const float* X, float* Y,
 // copies are current).  fuse: the term's own choice, or -1/0/1 to override.
 template <typename T>
 void couple_term(H& h, int set, const CoupleTerm& t, const T* x, int fuse) {
-  if (t.ccvv_kind >= 0) throw DevError(CASPT2_E_ARG, "term applied by the ccvv packed-row passes");
+  if (t.ccvv_kind >= 0 || t.ccvv_down >= 0) throw DevError(CASPT2_E_ARG, "term applied by the ccvv packed-row passes");
   T* scratch = reinterpret_cast<T*>(cscratch_of(h).p);
   T* xk = reinterpret_cast<T*>(xall_of(h, t.ket).p);
   T* sb = reinterpret_cast<T*>(sall_of(h, t.bra).p);
@@ -1523,6 +1592,69 @@ void ccvv_up_passes(H& h, int set, T* sig) {
   HIPCHECK(ccvv_up_apply<T>(a, reinterpret_cast<const uint32_t*>(h.ccvv_groups.p), h.ccvv_ngroups, h.s));
 }
 
+// the down terms out of ccvv into cavv and caav of a set whose roles were
+// classified: one packed-row pass (cavv straight into its packed rows, caav
+// through the reduction buffer Y), then Y times each caav term's G into the
+// all-orderings caav sigma
+template <typename T>
+void ccvv_down_pass(H& h, int set, const T* x, T* sig) {
+  const CoupleTerm* tk[DK_N] = {};
+  for (auto& t : h.couple[set])
+    if (t.ccvv_down >= 0) tk[t.ccvv_down] = &t;
+  CcvvDownArgs<T> d;
+  d.nc = h.nc;
+  d.nv = h.nv;
+  d.ny = h.na;
+  d.ncol = (int)nalpha_of_block(h, set, CCVV);
+  d.nab = d.ny * d.ncol;
+  for (auto& e : h.sets[set]) {
+    if (e.nrow == 0) continue;
+    const bool pl = e.chi.empty() || e.chi[0] > 0;
+    if (e.block == CCVV) (pl ? d.xp : d.xm) = x + e.offset;
+    if (e.block == CAVV) (pl ? d.sp : d.sm) = sig + e.offset;
+  }
+  if (!d.xp) return;
+  const CoupleTerm* tD = tk[DK_CAVV1] ? tk[DK_CAVV1] : tk[DK_CAVV2];
+  const CoupleTerm* tE = tk[DK_CAAV1] ? tk[DK_CAAV1] : tk[DK_CAAV2];
+  const CoupleTerm* tF = tk[DK_CCAV1] ? tk[DK_CCAV1] : tk[DK_CCAV2];
+  if (tF) {
+    for (auto& e : h.sets[set])
+      if (e.block == CCAV && e.nrow > 0) (e.chi.empty() || e.chi[0] > 0 ? d.cp : d.cm) = sig + e.offset;
+    d.nab3 = (int)nalpha_of_block(h, set, CCAV);
+    d.G3 = tk[DK_CCAV1] ? Sel<T>::G(*tk[DK_CCAV1]) : nullptr;
+    d.G4 = tk[DK_CCAV2] ? Sel<T>::G(*tk[DK_CCAV2]) : nullptr;
+    d.fV = h.fock.p + tF->f_off;
+    d.fV_stride = h.nmo;
+  }
+  if (tD && d.sp) {
+    d.G1 = tk[DK_CAVV1] ? Sel<T>::G(*tk[DK_CAVV1]) : nullptr;
+    d.G2 = tk[DK_CAVV2] ? Sel<T>::G(*tk[DK_CAVV2]) : nullptr;
+    d.fA = h.fock.p + tD->f_off;
+    d.fA_stride = h.nmo;
+  } else {
+    d.sp = d.sm = nullptr;
+  }
+  T* Y = reinterpret_cast<T*>((h.wset ? h.ccvv_y2 : h.ccvv_y).p);
+  if (tE) {
+    d.fC = h.fock.p + tE->f_off;
+    d.fC_stride = h.nmo;
+    d.Tw = reinterpret_cast<T*>((h.wset ? h.ccvv_t2 : h.ccvv_t).p);
+    d.Y = Y;
+  }
+  HIPCHECK(ccvv_down_apply<T>(d, reinterpret_cast<const uint32_t*>(h.ccvv_groups.p), h.ccvv_ngroups, h.s));
+  if (!tE) return;
+  const int64_t rows = (int64_t)h.nc * h.nv, nab = nalpha_of_block(h, set, CAAV);
+  T* sb = reinterpret_cast<T*>(sall_of(h, CAAV).p);
+  for (int k : {DK_CAAV1, DK_CAAV2}) {
+    if (!tk[k]) continue;
+    const T* Yk = Y + (k == DK_CAAV1 ? 0 : rows * d.ncol);
+    if (nab <= 8 && d.ncol <= 8)
+      HIPCHECK(rows_small_gemm(rows, (int)nab, d.ncol, Yk, Sel<T>::G(*tk[k]), sb, h.s));
+    else
+      HIPCHECK(gemm_t(true, rows, nab, d.ncol, 1.0, Yk, d.ncol, Sel<T>::G(*tk[k]), d.ncol, 1.0, sb, nab, h.s));
+  }
+}
+
 template <typename T>
 void apply_couplings(H& h, int set, const T* x, T* sig) {
   auto nalpha_of = [&](int block) { return nalpha_of_block(h, set, block); };
@@ -1584,7 +1716,7 @@ void apply_couplings(H& h, int set, const T* x, T* sig) {
   stage("unpack");
   if (h.prof_on) prof_end(h, stage_id("unpack"), 0.0, sev);
   for (auto& t : h.couple[set]) {
-    if (t.ccvv_kind >= 0) continue;   // below, in the packed-row passes
+    if (t.ccvv_kind >= 0 || t.ccvv_down >= 0) continue;   // below, in the packed-row passes
     if (h.prof_on) prof_begin(h, &sev);
     if (diag) {
       stage("stage");
@@ -1604,6 +1736,12 @@ void apply_couplings(H& h, int set, const T* x, T* sig) {
     ccvv_up_passes<T>(h, set, sig);
     stage("ccvv up passes");
     if (h.prof_on) prof_end(h, stage_id("up ccvv passes"), 0.0, sev);
+  }
+  if (set < (int)h.ccvv_down_fused.size() && h.ccvv_down_fused[set]) {
+    if (h.prof_on) prof_begin(h, &sev);
+    ccvv_down_pass<T>(h, set, x, sig);
+    stage("ccvv down pass");
+    if (h.prof_on) prof_end(h, stage_id("down ccvv pass"), 0.0, sev);
   }
   if (h.prof_on) prof_begin(h, &sev);
   for (int b = 0; b < NBLOCK; ++b) {
@@ -2663,7 +2801,7 @@ void autotune(H& h, const char* cache_path, bool force) {
     for (size_t set = 0; set < h.couple.size(); ++set)
       for (auto& t : h.couple[set]) {
         const int64_t nak = nalpha_of_block(h, (int)set, t.ket);
-        if (!t.up || t.d.ny > 8 || t.ccvv_kind >= 0) continue;
+        if (!t.up || t.d.ny > 8 || t.ccvv_kind >= 0 || t.ccvv_down >= 0) continue;
         const bool fusable = couple_up_fusable<double>(t.d, nak);
         int64_t rows_k = 1;
         for (int k = 0; k < t.d.ket.nslot; ++k) rows_k *= t.d.ket.slot_dim[k];
@@ -3714,7 +3852,10 @@ int caspt2_debug_ccvv_passes(int32_t on) {
 
 int caspt2_debug_ccvv_passes_used(const caspt2_handle* h, int32_t set) {
   if (!h || set < 0 || set >= (int32_t)h->couple.size()) return CASPT2_E_ARG;
-  return set < (int32_t)h->ccvv_fused.size() && h->ccvv_fused[set] ? 1 : 0;
+  int r = 0;
+  if (set < (int32_t)h->ccvv_fused.size() && h->ccvv_fused[set]) r |= 1;
+  if (set < (int32_t)h->ccvv_down_fused.size() && h->ccvv_down_fused[set]) r |= 2;
+  return r;
 }
 
 int caspt2_debug_gemm(int32_t b_is_nk, int64_t M, int64_t N, int64_t K, const double* A,

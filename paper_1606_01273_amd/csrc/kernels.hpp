@@ -259,6 +259,43 @@ std::vector<uint32_t> ccvv_up_groups(int nv);
 template <typename T>
 hipError_t ccvv_up_apply(const CcvvUpArgs<T>& p, const uint32_t* groups, int64_t ngroups, hipStream_t s);
 
+// The down terms out of ccvv into cavv, caav and ccav read straight from the
+// packed ccvv rows (couple_ccvv.hip).  xp/xm: packed ccvv + and - (xm may be
+// NULL); G1/G2 [nab][ny * ncol] of the two cavv terms (NULL if absent);
+// f(z, y) = fA[z * fA_stride + y] (closed, active); sp/sm: packed cavv + and
+// - sigma, added to; f(z, w) = fC[z * fC_stride + w] (closed, virtual);
+// Tw: work [2][nc][nv][nv][ncol]; Y [2][nc][nv][ncol] receives the two caav
+// reductions (caav rows (i, v)), to be contracted with the terms' G.
+template <typename T>
+struct CcvvDownArgs {
+  int nc = 0, nv = 0, ncol = 0, ny = 0, nab = 0;
+  const T* xp = nullptr;
+  const T* xm = nullptr;
+  const T* G1 = nullptr;
+  const T* G2 = nullptr;
+  const double* fA = nullptr;
+  int64_t fA_stride = 0;
+  T* sp = nullptr;
+  T* sm = nullptr;
+  const double* fC = nullptr;
+  int64_t fC_stride = 0;
+  T* Tw = nullptr;
+  T* Y = nullptr;
+  // into ccav: G3/G4 [nab3][ny * ncol]; f(y, w) = fV[y * fV_stride + w]
+  // (active, virtual); cp/cm: packed ccav + and - sigma, added to
+  int nab3 = 0;
+  const T* G3 = nullptr;
+  const T* G4 = nullptr;
+  const double* fV = nullptr;
+  int64_t fV_stride = 0;
+  T* cp = nullptr;
+  T* cm = nullptr;
+};
+bool ccvv_down_supported(int nc, int nv, int ncol, int ny, int nab);
+template <typename T>
+// groups: the workgroup table of ccvv_up_groups (device), ngroups its length
+hipError_t ccvv_down_apply(const CcvvDownArgs<T>& p, const uint32_t* groups, int64_t ngroups, hipStream_t s);
+
 // X0[i][k] = Q[i][idx[k]] * scale[k]  (Q is n x ncq, X0 is n x nk)
 hipError_t select_scale_cols(int64_t n, int64_t ncq, const double* Q, const int32_t* idx,
                              const double* scale, int64_t nk, double* X0, hipStream_t s);

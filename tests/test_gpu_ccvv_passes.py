@@ -1,9 +1,10 @@
-"""The up coupling terms into ccvv (Eq. 10 with the Fock operator of Eq. 11:
-ccvv <- cavv through f(active, closed), ccvv <- ccav through f(virtual,
-active), ccvv <- caav through f(virtual, closed)) applied in the two
-packed-row passes, against the same terms applied one at a time through the
-all-orderings sigma of ccvv and its packing (the form every other coupling
-takes, itself checked against both oracles in the parity tests).
+"""The coupling terms of ccvv (Eq. 10 with the Fock operator of Eq. 11)
+applied in packed-row passes -- the up terms into ccvv (from cavv through
+f(active, closed), from ccav through f(virtual, active), from caav through
+f(virtual, closed)) and the down terms out of ccvv into cavv and caav --
+against the same terms applied one at a time through the all-orderings
+tensors and their packing (the form every other coupling takes, itself
+checked against both oracles in the parity tests).
 
 Bars: FP64 residuals of every state within 1e-12 of the largest element (the
 two forms only sum the same products in another order); FP32 residuals of
@@ -12,8 +13,10 @@ product to FP32; the passes keep their partial sums in FP64).  Cases: several
 closed pairs and a single one (no '-' rows), virtual counts off the 16-wide
 tile (ragged tiles), 1-3 states (1-3 columns, and the 1-column function sets
 of SS-SR), rotated orbitals (Reading C: within-block terms into ccvv keep
-the all-orderings sigma beside the passes), and a Fock operator with only
-the closed-virtual block between orbital spaces (one pass alone)."""
+the all-orderings sigma beside the passes), forty closed orbitals (the
+in-pass active contraction in more than one round of matrix-core tiles), and
+a Fock operator with only the closed-virtual block between orbital spaces
+(one pass alone)."""
 import numpy as np
 import pytest
 
@@ -60,6 +63,7 @@ CASES = [
     ((1, 3, 5, 20, 2), 3, "B", "MSMR"),
     ((4, 4, 17, 50, 1), 4, "B", "MSMR"),
     ((5, 4, 30, 70, 2), 9, "C", "MSMR"),
+    ((40, 6, 5, 120, 3), 2, "B", "MSMR"),
 ]
 
 
@@ -73,7 +77,7 @@ def test_passes_match_term_path(dev, dims, seed, reading, scheme):
     nsets = p.nst if scheme == "SSSR" else 1
     for s in range(nsets):
         assert L.caspt2_debug_ccvv_passes_used(g0._h, s) == 0
-        assert L.caspt2_debug_ccvv_passes_used(g1._h, s) == 1
+        assert L.caspt2_debug_ccvv_passes_used(g1._h, s) == 3   # up passes and down pass
     x = torch.tensor(random_vector(g0.length, seed + 100), device=dev)
     for st in range(p.nst):
         ref = torch.empty_like(x)
@@ -89,7 +93,7 @@ def test_passes_match_term_path(dev, dims, seed, reading, scheme):
 
 def test_passes_closed_virtual_block_only(dev):
     """Only f(closed, virtual) couples orbital spaces: the caav terms alone
-    (the virtual-pair pass without the cavv contraction)."""
+    (the virtual-pair passes without the cavv contractions)."""
     import copy
     p = make_problem(4, 4, 20, 60, 2, seed=11, reading="B", shift=0.2)
     q = copy.deepcopy(p)
