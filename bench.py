@@ -269,6 +269,27 @@ def _reading_b(steps, warmup, tune, tol, densities=True):
            "ms_per_state": {"within_block": round(within, 3), "couplings": round(coupl[0], 3)},
            "coupling_stages_ms_per_state": {k: round(v, 3) for k, v in sorted(stages.items(),
                                                                              key=lambda kv: -kv[1])}}
+    # the packed-row passes of the ccvv couplings against their algorithmic
+    # bytes per state: read the ket amplitudes once, read and write the bra
+    # sigma once (all-orderings rows for the cavv, ccav, caav kets of the up
+    # terms; packed rows otherwise)
+    rows = {name: r for name, _, r, _ in g.layout()}
+    alpha = {name: a for name, _, _, a in g.layout()}
+    ccvv_packed = (rows["ccvv+"] + rows["ccvv-"]) * alpha["ccvv+"] * 8.0
+    cavv_all = nc * nv * nv * alpha["cavv+"] * 8.0
+    cavv_packed = (rows["cavv+"] + rows["cavv-"]) * alpha["cavv+"] * 8.0
+    ccav_packed = (rows["ccav+"] + rows["ccav-"]) * alpha["ccav+"] * 8.0
+    ccav_all = nc * nc * nv * alpha["ccav+"] * 8.0
+    caav_all = nc * nv * alpha["caav"] * 8.0
+    algo = {"up ccvv passes": cavv_all + ccav_all + caav_all + 2.0 * ccvv_packed,
+            "down ccvv pass": ccvv_packed + 2.0 * (cavv_packed + ccav_packed + caav_all)}
+    out["ccvv_passes"] = {}
+    for name, b in algo.items():
+        ms = stages.get(name)
+        if ms:
+            out["ccvv_passes"][name] = {"ms_per_state": round(ms, 3), "algorithmic_bytes": b,
+                                        "achieved_GBs": round(b / (ms * 1e-3) / 1e9, 1),
+                                        "frac_of_hbm_peak": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     del x, sig
     torch.cuda.empty_cache()
     if densities:

@@ -62,17 +62,19 @@ CASPT2_API int caspt2_debug_eigh_method(int32_t n, double* A, double* w, double*
 CASPT2_API int caspt2_debug_eigh_abs(int32_t n, double* A, double* w, double* V, int32_t method,
                                      double abs_tol, int32_t* sweeps);
 
-/* Coupling terms of ccvv (Eq. 10 with the f of Eq. 11): 1 (default) applies
- * the up terms into ccvv in two packed-row passes and the down terms out of
- * ccvv into cavv and caav in one, for handles created from now on; 0 runs
+/* Coupling terms applied in packed rows (Eq. 10 with the f of Eq. 11): 1
+ * (default) applies the up terms into ccvv in two packed-row passes, the
+ * down terms out of ccvv into cavv, caav and ccav in two, and the terms
+ * between cavv and aavv/aaav in one, for handles created from now on; 0 runs
  * them term by term through the all-orderings tensors, as every other
  * coupling (for comparing the two).  Returns the previous setting.  Not
  * thread-safe against concurrent caspt2_create. */
 CASPT2_API int caspt2_debug_ccvv_passes(int32_t on);
 
 /* For function set `set` of the handle: bit 0 set if its up terms into
- * ccvv run in the packed-row passes, bit 1 if its down terms out of ccvv
- * into cavv and caav do; 0 if all run term by term; E_ARG for a bad set. */
+ * ccvv run in the packed-row passes, bit 1 if its down terms out of ccvv do,
+ * bit 2 if its terms between cavv and aavv/aaav do; 0 if all run term by
+ * term; E_ARG for a bad set. */
 CASPT2_API int caspt2_debug_ccvv_passes_used(const caspt2_handle* h, int32_t set);
 
 #ifdef __cplusplus

@@ -6,7 +6,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = ["engine.cpp", "kernels.hip", "couple.hip", "couple_ccvv.hip", "gemm_f32.hip", "pcg_kernels.hip", "density.hip", "noalloc.hip", "caspt2.hip"]
+SRC = ["engine.cpp", "kernels.hip", "couple.hip", "couple_ccvv.hip", "couple_cavv.hip", "gemm_f32.hip", "pcg_kernels.hip", "density.hip", "noalloc.hip", "caspt2.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-fvisibility=hidden", "-fvisibility-inlines-hidden",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -151,6 +151,8 @@ struct CoupleTerm {
                          // (CcvvKind), else -1
   int ccvv_down = -1;    // down term out of ccvv into cavv or caav applied by the packed-row pass: its
                          // role (CcvvDownKind), else -1
+  int cavv_role = -1;    // term between cavv and aavv/aaav applied in packed rows (couple_cavv.hip): its
+                         // role (CavvRole), else -1
 };
 
 // roles of the up terms into ccvv in the packed-row passes, with the slot
@@ -160,6 +162,17 @@ enum CcvvKind { CK_CAVV1 = 0, CK_CAVV2, CK_CCAV1, CK_CCAV2, CK_CAAV1, CK_CAAV2, 
 // roles of the down terms out of ccvv in the packed-row pass (cavv bra slots
 // i, a, b; caav i, a; the ket ccvv slots from bra slots or summed labels -1, -2)
 enum CcvvDownKind { DK_CAVV1 = 0, DK_CAVV2, DK_CAAV1, DK_CAAV2, DK_CCAV1, DK_CCAV2, DK_N };
+// roles of the terms between cavv (slots i, a, b) and aavv (a, b) / aaav (a)
+// applied in packed rows: up from aavv, up from aaav, down into aavv; two
+// pairings each
+enum CavvRole { CV_UA1 = 0, CV_UA2, CV_UB1, CV_UB2, CV_DA1, CV_DA2, CV_N };
+
+// the G products of the cavv packed-row terms of one function set, summed
+// and differenced over the two pairings of each role (FP64 and FP32 copies)
+struct CavvG {
+  DBuf up[2], ub[2], da[2];   // [0]: G1 + G2, [1]: G1 - G2; empty when the role is absent
+  FBuf up32[2], ub32[2], da32[2];
+};
 
 // element-type selection of the per-entry and per-term operands
 template <typename T>
@@ -288,6 +301,10 @@ struct caspt2_handle {
   int64_t ccvv_woff[CK_N] = {};                        // offsets of the W products in ccvv_w (-1: absent)
   DBuf ccvv_w, ccvv_w2;                                // W products of the ccav and caav terms (both work sets)
   std::vector<char> ccvv_down_fused;                   // per set: down terms out of ccvv into cavv, caav as a pass
+  std::vector<char> cavv_fused;                        // per set: cavv - aavv/aaav terms in packed rows
+  std::vector<CavvG> cavv_g;                           // per set: their summed and differenced G
+  DBuf cavv_w, cavv_w2;                                // Q+-, B+-, Z+- of the cavv pass (both work sets)
+  int64_t cavv_off[6] = {};                            // offsets in cavv_w: Q+, Q-, B+, B-, Z+, Z-
   DBuf ccvv_t, ccvv_t2, ccvv_y, ccvv_y2;               // caav partial sums and reductions (both work sets)
   bool have_mixed = false;                             // FP32 operand copies made
   bool prof_on = false;
@@ -1178,6 +1195,84 @@ void make_coupling_terms(H& h, const std::vector<std::pair<char, char>>& comps,
 bool g_ccvv_passes = true;
 int64_t nalpha_of_block(const H& h, int set, int block);
 
+// Classify the terms between cavv and aavv/aaav of every function set by
+// their roles in the packed-row pass (couple_cavv.hip), and form the sums
+// and differences of the two pairings' G of each role.
+void classify_cavv_terms(H& h) {
+  const int nsets = (int)h.couple.size();
+  h.cavv_fused.assign(nsets, 0);
+  h.cavv_g.clear();
+  h.cavv_g.resize(nsets);
+  const int64_t fac = (int64_t)h.nc * h.nmo, fvc = (int64_t)(h.nc + h.na) * h.nmo, fca = h.nc;
+  for (int set = 0; set < nsets; ++set) {
+    const int64_t nak = nalpha_of_block(h, set, CAVV);
+    if (!cavv_pass_supported(h.nc, h.nv, (int)nak, h.na)) continue;
+    CoupleTerm* by[CV_N] = {};
+    bool ok = true, any = false;
+    for (auto& t : h.couple[set]) {
+      const bool cand = (t.up && t.bra == CAVV && (t.ket == AAVV || t.ket == AAAV)) ||
+                        (!t.up && t.bra == AAVV && t.ket == CAVV);
+      if (!cand) continue;
+      any = true;
+      const int* k = t.d.ket_src;
+      int role = -1;
+      if (t.d.f_stride == h.nmo && t.sg_slot < 0) {
+        if (t.up && t.ket == AAVV && t.d.nsum == 0 && t.d.ny == h.na && t.f_off == fac && t.d.fx_src == -10 &&
+            t.d.fy_src == 0 && t.d.ncol == nak) {
+          if (k[0] == 1 && k[1] == 2) role = CV_UA1;
+          else if (k[0] == 2 && k[1] == 1) role = CV_UA2;
+        } else if (t.up && t.ket == AAAV && t.d.nsum == 0 && t.d.ny == 1 && t.f_off == fvc && t.d.fy_src == 0 &&
+                   t.d.ncol == nak) {
+          if (k[0] == 1 && t.d.fx_src == 2) role = CV_UB1;
+          else if (k[0] == 2 && t.d.fx_src == 1) role = CV_UB2;
+        } else if (!t.up && t.d.nsum == 1 && t.d.sum_dim[0] == h.nc && t.d.ny == h.na && t.f_off == fca &&
+                   t.d.fx_src == -1 && t.d.fy_src == -10 && t.d.ncol == nak && k[0] == -1) {
+          if (k[1] == 0 && k[2] == 1) role = CV_DA1;
+          else if (k[1] == 1 && k[2] == 0) role = CV_DA2;
+        }
+      }
+      if (role < 0 || by[role]) {
+        ok = false;
+        break;
+      }
+      by[role] = &t;
+    }
+    if (!ok || !any) continue;
+    CavvG& cg = h.cavv_g[set];
+    auto combine = [&](CoupleTerm* t1, CoupleTerm* t2, DBuf (&out)[2]) {
+      if (!t1 && !t2) return;
+      const int64_t n = (t1 ? t1 : t2)->G.n;
+      for (int s2 = 0; s2 < 2; ++s2) {
+        out[s2].alloc(n);
+        if (t1) HIPCHECK(vec_scale_copy(n, 1.0, t1->G.p, out[s2].p, h.s));
+        else HIPCHECK(vec_fill(n, 0.0, out[s2].p, h.s));
+        if (t2) HIPCHECK(vec_axpy(n, s2 == 0 ? 1.0 : -1.0, t2->G.p, out[s2].p, h.s));
+      }
+    };
+    combine(by[CV_UA1], by[CV_UA2], cg.up);
+    combine(by[CV_UB1], by[CV_UB2], cg.ub);
+    combine(by[CV_DA1], by[CV_DA2], cg.da);
+    for (int r = 0; r < CV_N; ++r)
+      if (by[r]) by[r]->cavv_role = r;
+    h.cavv_fused[set] = 1;
+  }
+  bool anyset = false;
+  for (char f : h.cavv_fused) anyset = anyset || f;
+  if (!anyset) return;
+  int64_t nak = 0;
+  for (int set = 0; set < nsets; ++set) nak = std::max(nak, nalpha_of_block(h, set, CAVV));
+  const int64_t nq = (int64_t)h.na * nak;
+  const int64_t npv = (int64_t)h.nv * (h.nv + 1) / 2, nmv = (int64_t)h.nv * (h.nv - 1) / 2;
+  h.cavv_off[0] = 0;                          // Q+
+  h.cavv_off[1] = npv * nq;                   // Q-
+  h.cavv_off[2] = (npv + nmv) * nq;           // B+
+  h.cavv_off[3] = h.cavv_off[2] + h.nv * nak; // B-
+  h.cavv_off[4] = h.cavv_off[3] + h.nv * nak; // Z+
+  h.cavv_off[5] = h.cavv_off[4] + npv * nq;   // Z-
+  h.cavv_w.alloc(h.cavv_off[5] + nmv * nq);
+  host_sync(h);
+}
+
 // Classify the up terms into ccvv of every function set by their roles in the
 // packed-row passes; a set runs the passes when every such term has a role
 // (one term per role) and the shapes fit the kernels, else the term path.
@@ -1271,9 +1366,12 @@ void classify_ccvv_terms(H& h) {
     h.ccvv_t.alloc(2 * (int64_t)h.nc * h.nv * h.nv * ncol);
     h.ccvv_y.alloc(2 * (int64_t)h.nc * h.nv * ncol);
   }
+  classify_cavv_terms(h);
   bool anyset = false;
   for (char f : h.ccvv_fused) anyset = anyset || f;
-  if (!anyset && !anydown) return;
+  bool anycavv = false;
+  for (char f : h.cavv_fused) anycavv = anycavv || f;
+  if (!anyset && !anydown && !anycavv) return;
   if (anyset) {
     // W products of the ccav and caav roles, one region per role
     int64_t ncol = 0;
@@ -1412,6 +1510,7 @@ void setup_couplings(H& h) {
   bool xall_need[NBLOCK] = {false, false, false, false, false, false, false, false};
   for (auto& cs : h.couple)
     for (auto& t : cs) {
+      if (t.cavv_role >= 0) continue;   // the cavv pass reads and writes packed rows only
       if (t.ccvv_down < 0) xall_need[t.ket] = true;   // the ccvv down passes read the packed rows
       if (t.ccvv_kind >= 0) continue;   // packed-row passes: no all-orderings sigma, no scratch
       if (t.ccvv_down >= 0) {
@@ -1462,6 +1561,7 @@ void ensure_work_set2(H& h) {
   if (h.ccvv_w.n && h.ccvv_w2.n != h.ccvv_w.n) h.ccvv_w2.alloc(h.ccvv_w.n);
   if (h.ccvv_t.n && h.ccvv_t2.n != h.ccvv_t.n) h.ccvv_t2.alloc(h.ccvv_t.n);
   if (h.ccvv_y.n && h.ccvv_y2.n != h.ccvv_y.n) h.ccvv_y2.alloc(h.ccvv_y.n);
+  if (h.cavv_w.n && h.cavv_w2.n != h.cavv_w.n) h.cavv_w2.alloc(h.cavv_w.n);
   if (h.splitk_ws2.n != h.splitk_ws.n) h.splitk_ws2.alloc(h.splitk_ws.n);
 }
 
@@ -1509,7 +1609,8 @@ bool slot_gemm(H& h, const CoupleTerm& t, int64_t nak, const float* X, float* Y,
 // copies are current).  fuse: the term's own choice, or -1/0/1 to override.
 template <typename T>
 void couple_term(H& h, int set, const CoupleTerm& t, const T* x, int fuse) {
-  if (t.ccvv_kind >= 0 || t.ccvv_down >= 0) throw DevError(CASPT2_E_ARG, "term applied by the ccvv packed-row passes");
+  if (t.ccvv_kind >= 0 || t.ccvv_down >= 0 || t.cavv_role >= 0)
+    throw DevError(CASPT2_E_ARG, "term applied by a packed-row pass");
   T* scratch = reinterpret_cast<T*>(cscratch_of(h).p);
   T* xk = reinterpret_cast<T*>(xall_of(h, t.ket).p);
   T* sb = reinterpret_cast<T*>(sall_of(h, t.bra).p);
@@ -1655,6 +1756,93 @@ void ccvv_down_pass(H& h, int set, const T* x, T* sig) {
   }
 }
 
+// the terms between cavv and aavv/aaav of a set whose roles were classified:
+// GEMMs of the packed aavv and aaav rows with the summed and differenced G
+// of the up terms, the packed-row pass over virtual pairs, and the GEMM of
+// its Z rows with the down terms' G into the packed aavv rows
+const double* cavv_gp(const CavvG& g, int which, int s, const double*) {
+  const DBuf* b = which == 0 ? g.up : which == 1 ? g.ub : g.da;
+  return b[s].p;
+}
+const float* cavv_gp(const CavvG& g, int which, int s, const float*) {
+  const FBuf* b = which == 0 ? g.up32 : which == 1 ? g.ub32 : g.da32;
+  return b[s].p;
+}
+template <typename T>
+void cavv_pass(H& h, int set, const T* x, T* sig) {
+  const CoupleTerm* tr[CV_N] = {};
+  for (auto& t : h.couple[set])
+    if (t.cavv_role >= 0) tr[t.cavv_role] = &t;
+  const CavvG& cg = h.cavv_g[set];
+  const T* tag = nullptr;
+  T* w = reinterpret_cast<T*>((h.wset ? h.cavv_w2 : h.cavv_w).p);
+  CavvArgs<T> c;
+  c.nc = h.nc;
+  c.nv = h.nv;
+  c.ny = h.na;
+  c.nak = (int)nalpha_of_block(h, set, CAVV);
+  const int64_t nq = (int64_t)c.ny * c.nak;
+  const T *xa[2] = {nullptr, nullptr}, *xaaav = nullptr;
+  T* sa[2] = {nullptr, nullptr};
+  int64_t ra[2] = {0, 0}, naa = 0, naaav = 0;
+  for (auto& e : h.sets[set]) {
+    if (e.nrow == 0) continue;
+    const int k = e.chi.empty() || e.chi[0] > 0 ? 0 : 1;
+    if (e.block == CAVV) (k == 0 ? c.sp : c.sm) = sig + e.offset;
+    if (e.block == CAVV) (k == 0 ? c.xp : c.xm) = x + e.offset;
+    if (e.block == AAVV) {
+      xa[k] = x + e.offset;
+      sa[k] = sig + e.offset;
+      ra[k] = e.nrow;
+      naa = e.nalpha;
+    }
+    if (e.block == AAAV) {
+      xaaav = x + e.offset;
+      naaav = e.nalpha;
+    }
+  }
+  if (!c.sp) return;
+  if ((tr[CV_UA1] || tr[CV_UA2]) && xa[0]) {
+    const CoupleTerm* t = tr[CV_UA1] ? tr[CV_UA1] : tr[CV_UA2];
+    for (int k = 0; k < 2; ++k) {
+      if (!xa[k]) continue;
+      T* Q = w + h.cavv_off[k];
+      HIPCHECK(gemm_t(true, ra[k], nq, naa, 1.0, xa[k], naa, cavv_gp(cg, 0, k, tag), naa, 0.0, Q, nq, h.s));
+      (k == 0 ? c.Qp : c.Qm) = Q;
+    }
+    c.fAC = h.fock.p + t->f_off;
+    c.fAC_stride = h.nmo;
+  }
+  if ((tr[CV_UB1] || tr[CV_UB2]) && xaaav) {
+    const CoupleTerm* t = tr[CV_UB1] ? tr[CV_UB1] : tr[CV_UB2];
+    for (int k = 0; k < 2; ++k) {
+      T* B = w + h.cavv_off[2 + k];
+      HIPCHECK(gemm_t(true, h.nv, c.nak, naaav, 1.0, xaaav, naaav, cavv_gp(cg, 1, k, tag), naaav, 0.0, B, c.nak,
+                      h.s));
+      (k == 0 ? c.Bp : c.Bm) = B;
+    }
+    c.fVC = h.fock.p + t->f_off;
+    c.fVC_stride = h.nmo;
+  }
+  const bool down = (tr[CV_DA1] || tr[CV_DA2]) && sa[0];
+  if (down) {
+    const CoupleTerm* t = tr[CV_DA1] ? tr[CV_DA1] : tr[CV_DA2];
+    c.Zp = w + h.cavv_off[4];
+    if (sa[1]) c.Zm = w + h.cavv_off[5];
+    c.fCA = h.fock.p + t->f_off;
+    c.fCA_stride = h.nmo;
+  } else {
+    c.xp = c.xm = nullptr;
+  }
+  HIPCHECK(cavv_pass_apply<T>(c, reinterpret_cast<const uint32_t*>(h.ccvv_groups.p), h.ccvv_ngroups, h.s));
+  if (down)
+    for (int k = 0; k < 2; ++k) {
+      if (!sa[k]) continue;
+      const T* Z = k == 0 ? c.Zp : c.Zm;
+      HIPCHECK(gemm_t(true, ra[k], naa, nq, 1.0, Z, nq, cavv_gp(cg, 2, k, tag), nq, 1.0, sa[k], naa, h.s));
+    }
+}
+
 template <typename T>
 void apply_couplings(H& h, int set, const T* x, T* sig) {
   auto nalpha_of = [&](int block) { return nalpha_of_block(h, set, block); };
@@ -1716,7 +1904,7 @@ void apply_couplings(H& h, int set, const T* x, T* sig) {
   stage("unpack");
   if (h.prof_on) prof_end(h, stage_id("unpack"), 0.0, sev);
   for (auto& t : h.couple[set]) {
-    if (t.ccvv_kind >= 0 || t.ccvv_down >= 0) continue;   // below, in the packed-row passes
+    if (t.ccvv_kind >= 0 || t.ccvv_down >= 0 || t.cavv_role >= 0) continue;   // below, in the packed-row passes
     if (h.prof_on) prof_begin(h, &sev);
     if (diag) {
       stage("stage");
@@ -1742,6 +1930,12 @@ void apply_couplings(H& h, int set, const T* x, T* sig) {
     ccvv_down_pass<T>(h, set, x, sig);
     stage("ccvv down pass");
     if (h.prof_on) prof_end(h, stage_id("down ccvv pass"), 0.0, sev);
+  }
+  if (set < (int)h.cavv_fused.size() && h.cavv_fused[set]) {
+    if (h.prof_on) prof_begin(h, &sev);
+    cavv_pass<T>(h, set, x, sig);
+    stage("cavv pass");
+    if (h.prof_on) prof_end(h, stage_id("cavv pass"), 0.0, sev);
   }
   if (h.prof_on) prof_begin(h, &sev);
   for (int b = 0; b < NBLOCK; ++b) {
@@ -1975,6 +2169,14 @@ void setup_mixed(H& h) {
       t.G32.alloc(t.G.n);
       HIPCHECK(vec_scale_copy(t.G.n, 1.0, t.G.p, t.G32.p, h.s));
     }
+  for (auto& cg : h.cavv_g)
+    for (int k = 0; k < 2; ++k)
+      for (auto pr : {std::make_pair(&cg.up[k], &cg.up32[k]), std::make_pair(&cg.ub[k], &cg.ub32[k]),
+                      std::make_pair(&cg.da[k], &cg.da32[k])})
+        if (pr.first->n) {
+          pr.second->alloc(pr.first->n);
+          HIPCHECK(vec_scale_copy(pr.first->n, 1.0, pr.first->p, pr.second->p, h.s));
+        }
   h.fock32.alloc(h.fock.n);
   HIPCHECK(vec_scale_copy(h.fock.n, 1.0, h.fock.p, h.fock32.p, h.s));
   h.have_mixed = true;
@@ -2801,7 +3003,7 @@ void autotune(H& h, const char* cache_path, bool force) {
     for (size_t set = 0; set < h.couple.size(); ++set)
       for (auto& t : h.couple[set]) {
         const int64_t nak = nalpha_of_block(h, (int)set, t.ket);
-        if (!t.up || t.d.ny > 8 || t.ccvv_kind >= 0 || t.ccvv_down >= 0) continue;
+        if (!t.up || t.d.ny > 8 || t.ccvv_kind >= 0 || t.ccvv_down >= 0 || t.cavv_role >= 0) continue;
         const bool fusable = couple_up_fusable<double>(t.d, nak);
         int64_t rows_k = 1;
         for (int k = 0; k < t.d.ket.nslot; ++k) rows_k *= t.d.ket.slot_dim[k];
@@ -3855,6 +4057,7 @@ int caspt2_debug_ccvv_passes_used(const caspt2_handle* h, int32_t set) {
   int r = 0;
   if (set < (int32_t)h->ccvv_fused.size() && h->ccvv_fused[set]) r |= 1;
   if (set < (int32_t)h->ccvv_down_fused.size() && h->ccvv_down_fused[set]) r |= 2;
+  if (set < (int32_t)h->cavv_fused.size() && h->cavv_fused[set]) r |= 4;
   return r;
 }
 

@@ -1,0 +1,182 @@
+// Coupling terms of cavv with aavv and aaav (Fock couplings of Eq. 10 with
+// the f of Eq. 11), in the packed rows of cavv (+: i, a >= b; -: i, a > b)
+// and aavv (+: a >= b; -: a > b) instead of the all-orderings tensors:
+//   up   cavv <- aavv through f(active, closed):  sigma(i,a,b) += sum_y f(y,i)
+//        [W1(a,b) + W2(b,a)](y, .),  W = X_aavv G^T (two pairings)
+//   up   cavv <- aaav through f(virtual, closed): sigma(i,a,b) += f(b,i) W3(a)
+//        + f(a,i) W4(b)
+//   down aavv <- cavv through f(closed, active):  Y(a,b)(y,c) = sum_z f(z,y)
+//        X(z,a,b)(c), sigma_aavv(a,b) += G1 Y(a,b) + G2 Y(b,a)
+// With x(i,a,b) +- x(i,b,a) = sqrt 2 x+-(i,ab) (a != b) the packed entries
+// take sums and differences of the two pairings:
+//   cavv +(i,ab) += f(.,i).Q+(ab) + kv [f(b,i) B+(a) + f(a,i) B+(b)]
+//   cavv -(i,ab) += f(.,i).Q-(ab) + [f(b,i) B-(a) - f(a,i) B-(b)] / sqrt 2
+//   aavv +-(ab)  += (G1 +- G2) Z+-(ab),  Z+-(ab)(y,c) = sum_z f(z,y) x+-(z,ab)(c)
+// (Q+- = (G1 +- G2) x_aavv+-, B+- = (G3 +- G4) x_aaav; kv = 1/sqrt 2, or 1/2
+// for a = b).  The products with G run as GEMMs in the packed spaces; one
+// pass over virtual pairs adds the cavv rows and forms Z.
+#include <algorithm>
+#include <cmath>
+
+#include "device_common.hpp"
+#include "kernels.hpp"
+
+namespace caspt2 {
+
+namespace {
+
+constexpr int CV_NB = VPAIR_GROUP;   // virtual pairs (a, b0 .. b0 + 2) per workgroup
+constexpr int CV_THREADS = 512;
+constexpr int CV_IPT = 12;         // cavv outputs per thread whose old values are loaded first
+
+}  // namespace
+
+// Workgroup g: virtual index a and b_u = b0 + u (u < nb, b_u <= a) from
+// groups[g] = a << 16 | b0 (the table of the ccvv passes).  Shared memory
+// (doubles): Qs [nb][2][nq] (Q+ and Q- of each pair, nq = ny * nak), Xs
+// [nb][2][nc][nak] (x+ and x- of cavv for every closed z), Bs [1 + nb][2][nak]
+// (B+ and B- of v = a, b_0 ..), fac [ny][nc] (f(y, i)), fvc [1 + nb][nc]
+// (f(v, i)), fca [nc][ny] (f(z, y)).
+template <typename T>
+__global__ __launch_bounds__(CV_THREADS, 4) void k_cavv_vpair(CavvArgs<T> p, const uint32_t* __restrict__ groups) {
+  extern __shared__ double sm[];
+  const int nc = p.nc, nv = p.nv, nak = p.nak, ny = p.ny, nq = p.ny * p.nak;
+  const int t = threadIdx.x;
+  const uint32_t gv = groups[blockIdx.x];
+  const int a = (int)(gv >> 16), b0 = (int)(gv & 0xffffu);
+  const int nb = min(CV_NB, a + 1 - b0);
+  const int64_t npv = (int64_t)nv * (nv + 1) / 2, nmv = (int64_t)nv * (nv - 1) / 2;
+  const bool haveq = p.Qp != nullptr, haveb = p.Bp != nullptr, havez = p.Zp != nullptr;
+  const bool up = haveq || haveb;
+  double* Qs = sm;                                          // [nb][2][nq]
+  double* Xs = Qs + (haveq ? CV_NB * 2 * nq : 0);           // [nb][2][nc][nak]
+  double* Bs = Xs + (havez ? CV_NB * 2 * nc * nak : 0);     // [1 + nb][2][nak]
+  double* fac = Bs + (haveb ? (1 + CV_NB) * 2 * nak : 0);   // [ny][nc]
+  double* fvc = fac + (haveq ? ny * nc : 0);                // [1 + nb][nc]
+  double* fca = fvc + (haveb ? (1 + CV_NB) * nc : 0);       // [nc][ny]
+  auto vidx = [&](int v) { return v == 0 ? a : b0 + v - 1; };
+  auto pab = [&](int u) { return (int64_t)a * (a + 1) / 2 + b0 + u; };
+  auto mab = [&](int u) { return (int64_t)a * (a - 1) / 2 + b0 + u; };
+  // cavv outputs (u, kind, i, alpha), kind 0: +, 1: -
+  const int nout = up ? nb * 2 * nc * nak : 0;
+  auto out_ptr = [&](int e) -> T* {
+    const int al = e % nak, i = (e / nak) % nc, kind = (e / (nak * nc)) & 1, u = e / (2 * nak * nc);
+    if (kind == 1 && (a == b0 + u || !p.sm)) return nullptr;
+    return kind == 0 ? p.sp + ((int64_t)i * npv + pab(u)) * nak + al : p.sm + ((int64_t)i * nmv + mab(u)) * nak + al;
+  };
+  double old[CV_IPT];
+#pragma unroll
+  for (int m = 0; m < CV_IPT; ++m) {
+    const int e = t + m * (int)blockDim.x;
+    old[m] = 0.0;
+    if (e < nout) {
+      const T* q = out_ptr(e);
+      if (q) old[m] = (double)*q;
+    }
+  }
+  if (haveq) {
+    for (int e = t; e < nb * 2 * nq; e += blockDim.x) {
+      const int k = e % nq, kind = (e / nq) & 1, u = e / (2 * nq);
+      double v = 0.0;
+      if (kind == 0) v = (double)p.Qp[pab(u) * nq + k];
+      else if (a != b0 + u && p.Qm) v = (double)p.Qm[mab(u) * nq + k];
+      Qs[e] = v;
+    }
+    for (int e = t; e < ny * nc; e += blockDim.x) fac[e] = p.fAC[(int64_t)(e / nc) * p.fAC_stride + e % nc];
+  }
+  if (havez) {
+    for (int e = t; e < nb * 2 * nc * nak; e += blockDim.x) {
+      const int c = e % nak, z = (e / nak) % nc, kind = (e / (nak * nc)) & 1, u = e / (2 * nak * nc);
+      double v = 0.0;
+      if (kind == 0) v = (double)p.xp[((int64_t)z * npv + pab(u)) * nak + c];
+      else if (a != b0 + u && p.xm) v = (double)p.xm[((int64_t)z * nmv + mab(u)) * nak + c];
+      Xs[e] = v;
+    }
+    for (int e = t; e < nc * ny; e += blockDim.x) fca[e] = p.fCA[(int64_t)(e / ny) * p.fCA_stride + e % ny];
+  }
+  if (haveb) {
+    for (int e = t; e < (1 + nb) * 2 * nak; e += blockDim.x) {
+      const int c = e % nak, kind = (e / nak) & 1, v = e / (2 * nak);
+      const T* B = kind == 0 ? p.Bp : p.Bm;
+      Bs[e] = B ? (double)B[(int64_t)vidx(v) * nak + c] : 0.0;
+    }
+    for (int e = t; e < (1 + nb) * nc; e += blockDim.x)
+      fvc[e] = p.fVC[(int64_t)vidx(e / nc) * p.fVC_stride + e % nc];
+  }
+  __syncthreads();
+  // cavv rows
+  auto value = [&](int e) {
+    const int al = e % nak, i = (e / nak) % nc, kind = (e / (nak * nc)) & 1, u = e / (2 * nak * nc);
+    double s = 0.0;
+    if (haveq) {
+      const double* q = Qs + (u * 2 + kind) * nq + al;
+      for (int y = 0; y < ny; ++y) s += fac[y * nc + i] * q[y * nak];
+    }
+    if (haveb) {
+      const double fbi = fvc[(1 + u) * nc + i], fai = fvc[i];
+      const double ba = Bs[(0 * 2 + kind) * nak + al], bb = Bs[((1 + u) * 2 + kind) * nak + al];
+      if (kind == 0) s += (a != b0 + u ? 0.70710678118654752440 : 0.5) * (fbi * ba + fai * bb);
+      else s += 0.70710678118654752440 * (fbi * ba - fai * bb);
+    }
+    return s;
+  };
+#pragma unroll
+  for (int m = 0; m < CV_IPT; ++m) {
+    const int e = t + m * (int)blockDim.x;
+    if (e >= nout) continue;
+    T* q = out_ptr(e);
+    if (q) *q = (T)(old[m] + value(e));
+  }
+  for (int e = t + CV_IPT * (int)blockDim.x; e < nout; e += blockDim.x) {
+    T* q = out_ptr(e);
+    if (q) *q = (T)((double)*q + value(e));
+  }
+  // Z+- rows of the pairs: (u, kind, y, c)
+  if (havez)
+    for (int e = t; e < nb * 2 * nq; e += blockDim.x) {
+      const int c = e % nak, y = (e / nak) % ny, kind = (e / nq) & 1, u = e / (2 * nq);
+      if (kind == 1 && (a == b0 + u || !p.Zm)) continue;
+      const double* xz = Xs + (int64_t)(u * 2 + kind) * nc * nak + c;
+      double s = 0.0;
+      for (int z = 0; z < nc; ++z) s += fca[z * ny + y] * xz[z * nak];
+      if (kind == 0) p.Zp[pab(u) * nq + y * nak + c] = (T)s;
+      else p.Zm[mab(u) * nq + y * nak + c] = (T)s;
+    }
+}
+
+int64_t cavv_vpair_shared(int nc, int nak, int ny, bool haveq, bool haveb, bool havez) {
+  int64_t n = 0;
+  if (haveq) n += (int64_t)CV_NB * 2 * ny * nak + (int64_t)ny * nc;
+  if (havez) n += (int64_t)CV_NB * 2 * nc * nak + (int64_t)nc * ny;
+  if (haveb) n += (int64_t)(1 + CV_NB) * 2 * nak + (int64_t)(1 + CV_NB) * nc;
+  return n * (int64_t)sizeof(double);
+}
+
+bool cavv_pass_supported(int nc, int nv, int nak, int ny) {
+  if (nc <= 0 || nv <= 0 || nv > 65535 || nak <= 0 || ny < 1 || ny > 8) return false;
+  int dev = 0, lds_max = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+    return false;
+  return cavv_vpair_shared(nc, nak, ny, true, true, true) <= lds_max;
+}
+
+template <typename T>
+hipError_t cavv_pass_apply(const CavvArgs<T>& p, const uint32_t* groups, int64_t ngroups, hipStream_t s) {
+  if (p.nc <= 0 || p.nv <= 0) return hipSuccess;
+  if (!cavv_pass_supported(p.nc, p.nv, p.nak, p.ny)) return hipErrorInvalidValue;
+  CavvArgs<T> q = p;
+  const bool haveq = q.Qp && q.fAC, haveb = q.Bp && q.fVC, havez = q.Zp && q.xp && q.fCA;
+  if (!haveq) q.Qp = q.Qm = nullptr;
+  if (!haveb) q.Bp = q.Bm = nullptr;
+  if (!havez) q.Zp = q.Zm = nullptr;
+  if (!haveq && !haveb && !havez) return hipSuccess;
+  const size_t shm = (size_t)cavv_vpair_shared(q.nc, q.nak, q.ny, haveq, haveb, havez);
+  hipLaunchKernelGGL(k_cavv_vpair<T>, dim3((unsigned)ngroups), dim3(CV_THREADS), shm, s, q, groups);
+  return hipGetLastError();
+}
+
+template hipError_t cavv_pass_apply<double>(const CavvArgs<double>&, const uint32_t*, int64_t, hipStream_t);
+template hipError_t cavv_pass_apply<float>(const CavvArgs<float>&, const uint32_t*, int64_t, hipStream_t);
+
+}  // namespace caspt2

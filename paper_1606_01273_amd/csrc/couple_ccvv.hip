@@ -25,12 +25,18 @@ namespace caspt2 {
 
 namespace {
 
-constexpr int CUA_NB = 3;        // virtual pairs (a, b0 .. b0 + 2) per pass-A workgroup
+constexpr int CUA_NB = VPAIR_GROUP;   // virtual pairs (a, b0 .. b0 + 2) per pass-A workgroup
 constexpr int CUA_THREADS = 512;
 constexpr int CUB_T = 16;        // pass-B virtual tile edge
 constexpr int CUA_MAXT = 4;      // MFMA output tiles per wave and round of the pass-A contraction
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+
+// row stride (doubles) of the staged rows of the virtual-pair up pass: even
+// (16-byte aligned rows) and 2 mod 4 (consecutive rows start 8 banks apart)
+__host__ __device__ constexpr int vpair_ld(int nak) {
+  return ((nak + 1) & ~1) % 4 == 0 ? ((nak + 1) & ~1) + 2 : ((nak + 1) & ~1);
+}
 
 __device__ inline void closed_pair(int q, int& i, int& j) {
   int ii = (int)((sqrt(8.0 * q + 1.0) - 1.0) * 0.5);
@@ -74,8 +80,9 @@ __device__ inline void pack_load(int64_t rp, int64_t rm, int ncol, const T* __re
 // (f(.,j).Q = sum_y f(y, j) Q(y, c); kappa as in pass B).  Shared memory
 // (doubles):
 //   XU  [nb][2][nc][ldu]   X(i,a,b_u) + X(i,b_u,a) and their difference,
-//                          then Q and D in place; ldu = nak | 1 (odd: rows
-//                          start on different banks)
+//                          then Q and D in place; ldu = vpair_ld(nak) (rows
+//                          16-byte aligned for vector reads, starting on
+//                          different banks)
 //   Gt  [2][nak][nak]      (G1 + G2)^T, (G1 - G2)^T
 //   fA  [ny][nc]           f(y, j)
 //   fC  [1 + nb][nc]       f(v, j) for v = a, b_0 ..
@@ -84,7 +91,7 @@ template <typename T>
 // (two workgroups per CU: at most 80 KB of LDS and 128 VGPRs each)
 __global__ __launch_bounds__(CUA_THREADS, 4) void k_ccvv_up_vpair(CcvvUpArgs<T> p, const uint32_t* __restrict__ groups) {
   extern __shared__ double sm[];
-  const int nc = p.nc, nv = p.nv, ncol = p.ncol, ny = p.ny, nak = p.nak, ldu = nak | 1;
+  const int nc = p.nc, nv = p.nv, ncol = p.ncol, ny = p.ny, nak = p.nak, ldu = vpair_ld(nak);
   const uint32_t gv = groups[blockIdx.x];
   const int a = (int)(gv >> 16), b0 = (int)(gv & 0xffffu);
   const int nb = min(CUA_NB, a + 1 - b0);
@@ -532,9 +539,9 @@ __global__ __launch_bounds__(256) void k_sum_middle(int64_t n_outer, int64_t n_m
 // term (the second term's are Ys and -Yd), so
 //   + entry (ij, a) += kc (G3 + G4) Ys(a),  - entry += (G3 - G4) Yd(a) / sqrt 2
 // (kc = 1/sqrt 2, or 1/2 for i = j; G3/G4 [ccav columns][ny x ncol]).  A
-// thread owns (a, c) and runs the w sum from its own loads, eight w at a time
-// (f staged in LDS in chunks of CDB_FW); the G contraction runs on MFMA.
-constexpr int CDB_A = 64, CDB_FW = 128;
+// thread owns (a, c) and runs the w sum from its own loads, eight w at a
+// time; the G contraction runs on MFMA.
+constexpr int CDB_A = 64;
 template <typename T>
 __global__ __launch_bounds__(256) void k_ccvv_down_cpair(CcvvDownArgs<T> p) {
   extern __shared__ double sm[];
@@ -548,8 +555,7 @@ __global__ __launch_bounds__(256) void k_ccvv_down_cpair(CcvvDownArgs<T> p) {
   const int64_t pij = (int64_t)i * (i + 1) / 2 + j, mij = (int64_t)i * (i - 1) / 2 + j;
   const bool dij = i != j;
   const int ldy = nout | 1;
-  double* fw = sm;                               // [CDB_FW][ny]
-  double* Gs = fw + CDB_FW * ny;                 // [2][nab][nout]
+  double* Gs = sm;                               // [2][nab][nout]
   double* Ysd = Gs + 2 * nab * nout;             // [2][CDB_A][ldy]
   // the ccav rows this lane updates (MFMA output layout), loaded first
   const int ntr = CDB_A / 16, ntc = (nab + 15) / 16, ntile = 2 * ntr * ntc;
@@ -582,12 +588,12 @@ __global__ __launch_bounds__(256) void k_ccvv_down_cpair(CcvvDownArgs<T> p) {
   const bool act = al < na && c < ncol;
   const int a = a0 + min(al, na - 1);
   double ys[8] = {0, 0, 0, 0, 0, 0, 0, 0}, yd[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (int f0 = 0; f0 < nv; f0 += CDB_FW) {
-    const int nf = min(CDB_FW, nv - f0);
-    __syncthreads();   // the previous chunk of f is consumed
-    for (int e = t; e < nf * ny; e += blockDim.x) fw[e] = p.fV[(int64_t)(e % ny) * p.fV_stride + f0 + e / ny];
-    __syncthreads();
-    if (!act) continue;
+  // f(y, w) is read at addresses uniform over the workgroup (w runs in step
+  // on every thread): scalar loads, no LDS
+  const double* __restrict__ fV = p.fV;
+  const int64_t fs = p.fV_stride;
+  if (act) {
+    const int f0 = 0, nf = nv;
     for (int w0 = 0; w0 < nf; w0 += 8) {
       double pv[8], mv[8];
 #pragma unroll
@@ -610,7 +616,7 @@ __global__ __launch_bounds__(256) void k_ccvv_down_cpair(CcvvDownArgs<T> p) {
 #pragma unroll
         for (int y = 0; y < 8; ++y) {
           if (y >= ny) break;
-          const double f = fw[(w0 + u) * ny + y];
+          const double f = fV[(int64_t)y * fs + f0 + w0 + u];
           ys[y] += f * pv[u];
           yd[y] += f * mv[u];
         }
@@ -663,8 +669,7 @@ int64_t ccvv_down_shared(int nc, int ncol, int ny, int nab, bool havey, bool hav
 }
 
 int64_t ccvv_down_cpair_shared(int ncol, int ny, int nab3) {
-  return (int64_t)(CDB_FW * ny + 2 * (int64_t)nab3 * ny * ncol + 2 * CDB_A * ((ny * ncol) | 1)) *
-         (int64_t)sizeof(double);
+  return (int64_t)(2 * (int64_t)nab3 * ny * ncol + 2 * CDB_A * ((ny * ncol) | 1)) * (int64_t)sizeof(double);
 }
 
 bool ccvv_down_supported(int nc, int nv, int ncol, int ny, int nab) {
@@ -712,7 +717,7 @@ template hipError_t ccvv_down_apply<float>(const CcvvDownArgs<float>&, const uin
 
 int64_t ccvv_up_vpair_shared(int nc, int nak, int ncol, int ny, bool havex, bool havec) {
   int64_t n = 0;
-  if (havex) n += (int64_t)CUA_NB * 2 * nc * (nak | 1) + 2 * (int64_t)nak * nak + (int64_t)ny * nc;
+  if (havex) n += (int64_t)CUA_NB * 2 * nc * vpair_ld(nak) + 2 * (int64_t)nak * nak + (int64_t)ny * nc;
   if (havec) n += (int64_t)(1 + CUA_NB) * nc + 2 * (int64_t)(1 + CUA_NB) * nc * ncol;
   return n * (int64_t)sizeof(double);
 }

@@ -254,7 +254,10 @@ struct CcvvUpArgs {
   T* minus = nullptr;
 };
 bool ccvv_up_supported(int nc, int nv, int ncol, int ny, int nak);
-// workgroup table of the virtual-pair pass: a << 16 | b0 per group
+// virtual pairs per workgroup of the virtual-pair passes (ccvv and cavv)
+constexpr int VPAIR_GROUP = 3;
+// workgroup table of the virtual-pair passes: a << 16 | b0 per group of
+// VPAIR_GROUP pairs (a, b0 ..)
 std::vector<uint32_t> ccvv_up_groups(int nv);
 template <typename T>
 hipError_t ccvv_up_apply(const CcvvUpArgs<T>& p, const uint32_t* groups, int64_t ngroups, hipStream_t s);
@@ -295,6 +298,39 @@ bool ccvv_down_supported(int nc, int nv, int ncol, int ny, int nab);
 template <typename T>
 // groups: the workgroup table of ccvv_up_groups (device), ngroups its length
 hipError_t ccvv_down_apply(const CcvvDownArgs<T>& p, const uint32_t* groups, int64_t ngroups, hipStream_t s);
+
+// Coupling terms of cavv with aavv and aaav in the packed rows
+// (couple_cavv.hip).  nak: cavv columns; ny: active orbitals.  Absent parts
+// are NULL.  Q+-: [aavv +/- rows][ny * nak] (packed aavv rows times the
+// summed and differenced G of the two up terms); f(y, i) = fAC[y * stride + i];
+// B+-: [nv][nak] (aaav rows times the G sum and difference); f(v, i) =
+// fVC[v * stride + i]; sp/sm: packed cavv sigma (added to); xp/xm: packed
+// cavv x; f(z, y) = fCA[z * stride + y]; Zp/Zm: [aavv +/- rows][ny * nak]
+// (written) for the down terms into aavv.
+template <typename T>
+struct CavvArgs {
+  int nc = 0, nv = 0, nak = 0, ny = 0;
+  const T* Qp = nullptr;
+  const T* Qm = nullptr;
+  const double* fAC = nullptr;
+  int64_t fAC_stride = 0;
+  const T* Bp = nullptr;
+  const T* Bm = nullptr;
+  const double* fVC = nullptr;
+  int64_t fVC_stride = 0;
+  T* sp = nullptr;
+  T* sm = nullptr;
+  const T* xp = nullptr;
+  const T* xm = nullptr;
+  const double* fCA = nullptr;
+  int64_t fCA_stride = 0;
+  T* Zp = nullptr;
+  T* Zm = nullptr;
+};
+bool cavv_pass_supported(int nc, int nv, int nak, int ny);
+// groups: the table of ccvv_up_groups
+template <typename T>
+hipError_t cavv_pass_apply(const CavvArgs<T>& p, const uint32_t* groups, int64_t ngroups, hipStream_t s);
 
 // X0[i][k] = Q[i][idx[k]] * scale[k]  (Q is n x ncq, X0 is n x nk)
 hipError_t select_scale_cols(int64_t n, int64_t ncq, const double* Q, const int32_t* idx,

@@ -1,10 +1,10 @@
-"""The coupling terms of ccvv (Eq. 10 with the Fock operator of Eq. 11)
-applied in packed-row passes -- the up terms into ccvv (from cavv through
-f(active, closed), from ccav through f(virtual, active), from caav through
-f(virtual, closed)) and the down terms out of ccvv into cavv and caav --
-against the same terms applied one at a time through the all-orderings
-tensors and their packing (the form every other coupling takes, itself
-checked against both oracles in the parity tests).
+"""Coupling terms (Eq. 10 with the Fock operator of Eq. 11) applied in
+packed-row passes -- the up terms into ccvv (from cavv through f(active,
+closed), from ccav through f(virtual, active), from caav through f(virtual,
+closed)), the down terms out of ccvv into cavv, caav and ccav, and the terms
+between cavv and aavv/aaav -- against the same terms applied one at a time
+through the all-orderings tensors and their packing (the form every other
+coupling takes, itself checked against both oracles in the parity tests).
 
 Bars: FP64 residuals of every state within 1e-12 of the largest element (the
 two forms only sum the same products in another order); FP32 residuals of
@@ -77,7 +77,7 @@ def test_passes_match_term_path(dev, dims, seed, reading, scheme):
     nsets = p.nst if scheme == "SSSR" else 1
     for s in range(nsets):
         assert L.caspt2_debug_ccvv_passes_used(g0._h, s) == 0
-        assert L.caspt2_debug_ccvv_passes_used(g1._h, s) == 3   # up passes and down pass
+        assert L.caspt2_debug_ccvv_passes_used(g1._h, s) == 7   # ccvv up, ccvv down, cavv
     x = torch.tensor(random_vector(g0.length, seed + 100), device=dev)
     for st in range(p.nst):
         ref = torch.empty_like(x)
