@@ -162,16 +162,17 @@ enum CcvvKind { CK_CAVV1 = 0, CK_CAVV2, CK_CCAV1, CK_CCAV2, CK_CAAV1, CK_CAAV2, 
 // roles of the down terms out of ccvv in the packed-row pass (cavv bra slots
 // i, a, b; caav i, a; the ket ccvv slots from bra slots or summed labels -1, -2)
 enum CcvvDownKind { DK_CAVV1 = 0, DK_CAVV2, DK_CAAV1, DK_CAAV2, DK_CCAV1, DK_CCAV2, DK_N };
-// roles of the terms between cavv (slots i, a, b) and aavv (a, b) / aaav (a)
-// applied in packed rows: up from aavv, up from aaav, down into aavv; two
-// pairings each
-enum CavvRole { CV_UA1 = 0, CV_UA2, CV_UB1, CV_UB2, CV_DA1, CV_DA2, CV_N };
+// roles of the terms between cavv (slots i, a, b) and aavv (a, b), aaav (a),
+// caav (i, a) applied in packed rows: up from aavv, up from aaav, down into
+// aavv, up from caav, down into caav, down into aaav; two pairings each
+enum CavvRole { CV_UA1 = 0, CV_UA2, CV_UB1, CV_UB2, CV_DA1, CV_DA2, CV_UC1, CV_UC2, CV_DB1, CV_DB2, CV_DC1, CV_DC2,
+                CV_N };
 
 // the G products of the cavv packed-row terms of one function set, summed
 // and differenced over the two pairings of each role (FP64 and FP32 copies)
 struct CavvG {
-  DBuf up[2], ub[2], da[2];   // [0]: G1 + G2, [1]: G1 - G2; empty when the role is absent
-  FBuf up32[2], ub32[2], da32[2];
+  DBuf g[6][2];     // per role pair (UA, UB, DA, UC, DB, DC): [0] G1 + G2, [1] G1 - G2; empty when absent
+  FBuf g32[6][2];
 };
 
 // element-type selection of the per-entry and per-term operands
@@ -304,7 +305,8 @@ struct caspt2_handle {
   std::vector<char> cavv_fused;                        // per set: cavv - aavv/aaav terms in packed rows
   std::vector<CavvG> cavv_g;                           // per set: their summed and differenced G
   DBuf cavv_w, cavv_w2;                                // Q+-, B+-, Z+- of the cavv pass (both work sets)
-  int64_t cavv_off[6] = {};                            // offsets in cavv_w: Q+, Q-, B+, B-, Z+, Z-
+  int64_t cavv_off[12] = {};                           // offsets in cavv_w: Q+, Q-, B+, B-, Z+, Z-, C+, C-, Sb, Db,
+                                                       // Scd, Sc
   DBuf ccvv_t, ccvv_t2, ccvv_y, ccvv_y2;               // caav partial sums and reductions (both work sets)
   bool have_mixed = false;                             // FP32 operand copies made
   bool prof_on = false;
@@ -1204,14 +1206,15 @@ void classify_cavv_terms(H& h) {
   h.cavv_g.clear();
   h.cavv_g.resize(nsets);
   const int64_t fac = (int64_t)h.nc * h.nmo, fvc = (int64_t)(h.nc + h.na) * h.nmo, fca = h.nc;
+  const int64_t fva = fvc + h.nc, fav = fac + h.nc + h.na, fcv2 = h.nc + h.na;
   for (int set = 0; set < nsets; ++set) {
     const int64_t nak = nalpha_of_block(h, set, CAVV);
     if (!cavv_pass_supported(h.nc, h.nv, (int)nak, h.na)) continue;
     CoupleTerm* by[CV_N] = {};
     bool ok = true, any = false;
     for (auto& t : h.couple[set]) {
-      const bool cand = (t.up && t.bra == CAVV && (t.ket == AAVV || t.ket == AAAV)) ||
-                        (!t.up && t.bra == AAVV && t.ket == CAVV);
+      const bool cand = (t.up && t.bra == CAVV && (t.ket == AAVV || t.ket == AAAV || t.ket == CAAV)) ||
+                        (!t.up && t.ket == CAVV && (t.bra == AAVV || t.bra == CAAV || t.bra == AAAV));
       if (!cand) continue;
       any = true;
       const int* k = t.d.ket_src;
@@ -1225,10 +1228,23 @@ void classify_cavv_terms(H& h) {
                    t.d.ncol == nak) {
           if (k[0] == 1 && t.d.fx_src == 2) role = CV_UB1;
           else if (k[0] == 2 && t.d.fx_src == 1) role = CV_UB2;
-        } else if (!t.up && t.d.nsum == 1 && t.d.sum_dim[0] == h.nc && t.d.ny == h.na && t.f_off == fca &&
-                   t.d.fx_src == -1 && t.d.fy_src == -10 && t.d.ncol == nak && k[0] == -1) {
+        } else if (!t.up && t.bra == AAVV && t.d.nsum == 1 && t.d.sum_dim[0] == h.nc && t.d.ny == h.na &&
+                   t.f_off == fca && t.d.fx_src == -1 && t.d.fy_src == -10 && t.d.ncol == nak && k[0] == -1) {
           if (k[1] == 0 && k[2] == 1) role = CV_DA1;
           else if (k[1] == 1 && k[2] == 0) role = CV_DA2;
+        } else if (t.up && t.ket == CAAV && t.d.nsum == 0 && t.d.ny == h.na && t.f_off == fva && t.d.fy_src == -10 &&
+                   t.d.ncol == nak && k[0] == 0) {
+          if (k[1] == 1 && t.d.fx_src == 2) role = CV_UC1;
+          else if (k[1] == 2 && t.d.fx_src == 1) role = CV_UC2;
+        } else if (!t.up && t.bra == CAAV && t.d.nsum == 1 && t.d.sum_dim[0] == h.nv && t.d.ny == h.na &&
+                   t.f_off == fav && t.d.fx_src == -10 && t.d.fy_src == -1 && t.d.ncol == nak && k[0] == 0) {
+          if (k[1] == -1 && k[2] == 1) role = CV_DB1;
+          else if (k[1] == 1 && k[2] == -1) role = CV_DB2;
+        } else if (!t.up && t.bra == AAAV && t.d.nsum == 2 && t.d.sum_dim[0] == h.nc && t.d.sum_dim[1] == h.nv &&
+                   t.d.ny == 1 && t.f_off == fcv2 && t.d.fx_src == -1 && t.d.fy_src == -2 && t.d.ncol == nak &&
+                   k[0] == -1) {
+          if (k[1] == -2 && k[2] == 0) role = CV_DC1;
+          else if (k[1] == 0 && k[2] == -2) role = CV_DC2;
         }
       }
       if (role < 0 || by[role]) {
@@ -1249,9 +1265,7 @@ void classify_cavv_terms(H& h) {
         if (t2) HIPCHECK(vec_axpy(n, s2 == 0 ? 1.0 : -1.0, t2->G.p, out[s2].p, h.s));
       }
     };
-    combine(by[CV_UA1], by[CV_UA2], cg.up);
-    combine(by[CV_UB1], by[CV_UB2], cg.ub);
-    combine(by[CV_DA1], by[CV_DA2], cg.da);
+    for (int r = 0; r < 6; ++r) combine(by[2 * r], by[2 * r + 1], cg.g[r]);
     for (int r = 0; r < CV_N; ++r)
       if (by[r]) by[r]->cavv_role = r;
     h.cavv_fused[set] = 1;
@@ -1263,13 +1277,15 @@ void classify_cavv_terms(H& h) {
   for (int set = 0; set < nsets; ++set) nak = std::max(nak, nalpha_of_block(h, set, CAVV));
   const int64_t nq = (int64_t)h.na * nak;
   const int64_t npv = (int64_t)h.nv * (h.nv + 1) / 2, nmv = (int64_t)h.nv * (h.nv - 1) / 2;
-  h.cavv_off[0] = 0;                          // Q+
-  h.cavv_off[1] = npv * nq;                   // Q-
-  h.cavv_off[2] = (npv + nmv) * nq;           // B+
-  h.cavv_off[3] = h.cavv_off[2] + h.nv * nak; // B-
-  h.cavv_off[4] = h.cavv_off[3] + h.nv * nak; // Z+
-  h.cavv_off[5] = h.cavv_off[4] + npv * nq;   // Z-
-  h.cavv_w.alloc(h.cavv_off[5] + nmv * nq);
+  const int64_t ncv = (int64_t)h.nc * h.nv;
+  const int64_t len[12] = {npv * nq, nmv * nq, h.nv * nak, h.nv * nak, npv * nq, nmv * nq,   // Q+- B+- Z+-
+                           ncv * nq, ncv * nq, ncv * nq, ncv * nq, 2 * ncv * nak, 2 * h.nv * nak};   // C+- Sb Db Scd Sc
+  int64_t off = 0;
+  for (int k = 0; k < 12; ++k) {
+    h.cavv_off[k] = off;
+    off += len[k];
+  }
+  h.cavv_w.alloc(off);
   host_sync(h);
 }
 
@@ -1760,14 +1776,8 @@ void ccvv_down_pass(H& h, int set, const T* x, T* sig) {
 // GEMMs of the packed aavv and aaav rows with the summed and differenced G
 // of the up terms, the packed-row pass over virtual pairs, and the GEMM of
 // its Z rows with the down terms' G into the packed aavv rows
-const double* cavv_gp(const CavvG& g, int which, int s, const double*) {
-  const DBuf* b = which == 0 ? g.up : which == 1 ? g.ub : g.da;
-  return b[s].p;
-}
-const float* cavv_gp(const CavvG& g, int which, int s, const float*) {
-  const FBuf* b = which == 0 ? g.up32 : which == 1 ? g.ub32 : g.da32;
-  return b[s].p;
-}
+const double* cavv_gp(const CavvG& g, int which, int s, const double*) { return g.g[which][s].p; }
+const float* cavv_gp(const CavvG& g, int which, int s, const float*) { return g.g32[which][s].p; }
 template <typename T>
 void cavv_pass(H& h, int set, const T* x, T* sig) {
   const CoupleTerm* tr[CV_N] = {};
@@ -1782,9 +1792,10 @@ void cavv_pass(H& h, int set, const T* x, T* sig) {
   c.ny = h.na;
   c.nak = (int)nalpha_of_block(h, set, CAVV);
   const int64_t nq = (int64_t)c.ny * c.nak;
-  const T *xa[2] = {nullptr, nullptr}, *xaaav = nullptr;
+  const T *xa[2] = {nullptr, nullptr}, *xaaav = nullptr, *xcaav = nullptr;
   T* sa[2] = {nullptr, nullptr};
-  int64_t ra[2] = {0, 0}, naa = 0, naaav = 0;
+  T *scaav = nullptr, *saaav = nullptr;
+  int64_t ra[2] = {0, 0}, naa = 0, naaav = 0, ncaav = 0;
   for (auto& e : h.sets[set]) {
     if (e.nrow == 0) continue;
     const int k = e.chi.empty() || e.chi[0] > 0 ? 0 : 1;
@@ -1798,7 +1809,13 @@ void cavv_pass(H& h, int set, const T* x, T* sig) {
     }
     if (e.block == AAAV) {
       xaaav = x + e.offset;
+      saaav = sig + e.offset;
       naaav = e.nalpha;
+    }
+    if (e.block == CAAV) {
+      xcaav = x + e.offset;
+      scaav = sig + e.offset;
+      ncaav = e.nalpha;
     }
   }
   if (!c.sp) return;
@@ -1824,6 +1841,17 @@ void cavv_pass(H& h, int set, const T* x, T* sig) {
     c.fVC = h.fock.p + t->f_off;
     c.fVC_stride = h.nmo;
   }
+  const int64_t ncv = (int64_t)h.nc * h.nv;
+  if ((tr[CV_UC1] || tr[CV_UC2]) && xcaav) {
+    const CoupleTerm* t = tr[CV_UC1] ? tr[CV_UC1] : tr[CV_UC2];
+    for (int k = 0; k < 2; ++k) {
+      T* C = w + h.cavv_off[6 + k];
+      HIPCHECK(gemm_t(true, ncv, nq, ncaav, 1.0, xcaav, ncaav, cavv_gp(cg, 3, k, tag), ncaav, 0.0, C, nq, h.s));
+      (k == 0 ? c.Cp : c.Cm) = C;
+    }
+    c.fVA = h.fock.p + t->f_off;
+    c.fVA_stride = h.nmo;
+  }
   const bool down = (tr[CV_DA1] || tr[CV_DA2]) && sa[0];
   if (down) {
     const CoupleTerm* t = tr[CV_DA1] ? tr[CV_DA1] : tr[CV_DA2];
@@ -1831,9 +1859,24 @@ void cavv_pass(H& h, int set, const T* x, T* sig) {
     if (sa[1]) c.Zm = w + h.cavv_off[5];
     c.fCA = h.fock.p + t->f_off;
     c.fCA_stride = h.nmo;
-  } else {
-    c.xp = c.xm = nullptr;
   }
+  const bool downb = (tr[CV_DB1] || tr[CV_DB2]) && scaav;
+  if (downb) {
+    const CoupleTerm* t = tr[CV_DB1] ? tr[CV_DB1] : tr[CV_DB2];
+    c.Sb = w + h.cavv_off[8];
+    c.Db = w + h.cavv_off[9];
+    c.fAV = h.fock.p + t->f_off;
+    c.fAV_stride = h.nmo;
+  }
+  const bool downc = (tr[CV_DC1] || tr[CV_DC2]) && saaav;
+  if (downc) {
+    const CoupleTerm* t = tr[CV_DC1] ? tr[CV_DC1] : tr[CV_DC2];
+    c.Scd = w + h.cavv_off[10];
+    c.Sc = w + h.cavv_off[11];
+    c.fCV = h.fock.p + t->f_off;
+    c.fCV_stride = h.nmo;
+  }
+  if (!down && !downb && !downc) c.xp = c.xm = nullptr;
   HIPCHECK(cavv_pass_apply<T>(c, reinterpret_cast<const uint32_t*>(h.ccvv_groups.p), h.ccvv_ngroups, h.s));
   if (down)
     for (int k = 0; k < 2; ++k) {
@@ -1841,6 +1884,15 @@ void cavv_pass(H& h, int set, const T* x, T* sig) {
       const T* Z = k == 0 ? c.Zp : c.Zm;
       HIPCHECK(gemm_t(true, ra[k], naa, nq, 1.0, Z, nq, cavv_gp(cg, 2, k, tag), nq, 1.0, sa[k], naa, h.s));
     }
+  // caav += [(G1 + G2) Sb + (G1 - G2) Db] / 2, aaav likewise with Sc, Dc
+  if (downb)
+    for (int k = 0; k < 2; ++k)
+      HIPCHECK(gemm_t(true, ncv, ncaav, nq, 0.5, k == 0 ? c.Sb : c.Db, nq, cavv_gp(cg, 4, k, tag), nq, 1.0, scaav,
+                      ncaav, h.s));
+  if (downc)
+    for (int k = 0; k < 2; ++k)
+      HIPCHECK(gemm_t(true, h.nv, naaav, c.nak, 0.5, c.Sc + k * h.nv * c.nak, c.nak, cavv_gp(cg, 5, k, tag), c.nak,
+                      1.0, saaav, naaav, h.s));
 }
 
 template <typename T>
@@ -2170,12 +2222,11 @@ void setup_mixed(H& h) {
       HIPCHECK(vec_scale_copy(t.G.n, 1.0, t.G.p, t.G32.p, h.s));
     }
   for (auto& cg : h.cavv_g)
-    for (int k = 0; k < 2; ++k)
-      for (auto pr : {std::make_pair(&cg.up[k], &cg.up32[k]), std::make_pair(&cg.ub[k], &cg.ub32[k]),
-                      std::make_pair(&cg.da[k], &cg.da32[k])})
-        if (pr.first->n) {
-          pr.second->alloc(pr.first->n);
-          HIPCHECK(vec_scale_copy(pr.first->n, 1.0, pr.first->p, pr.second->p, h.s));
+    for (int r = 0; r < 6; ++r)
+      for (int k = 0; k < 2; ++k)
+        if (cg.g[r][k].n) {
+          cg.g32[r][k].alloc(cg.g[r][k].n);
+          HIPCHECK(vec_scale_copy(cg.g[r][k].n, 1.0, cg.g[r][k].p, cg.g32[r][k].p, h.s));
         }
   h.fock32.alloc(h.fock.n);
   HIPCHECK(vec_scale_copy(h.fock.n, 1.0, h.fock.p, h.fock32.p, h.s));

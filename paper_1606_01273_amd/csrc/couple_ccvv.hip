@@ -56,13 +56,57 @@ __device__ inline void pack_rows(int i, int j, int a, int b, int64_t npv, int64_
 
 // the current values of the two packed rows (issued early: the loads are in
 // flight while the workgroup stages and contracts its inputs)
-template <typename T>
+// NC columns of a packed row as doubles (NC = 4: the row is 32 bytes of
+// doubles or 16 bytes of floats, aligned: vector accesses; NC = 0: ncol
+// element accesses)
+template <typename T, int NC>
+__device__ inline void row_load(const T* __restrict__ p, int ncol, double (&v)[4]) {
+  if constexpr (NC == 4) {
+    if constexpr (sizeof(T) == 8) {
+      const double2 x = reinterpret_cast<const double2*>(p)[0], y = reinterpret_cast<const double2*>(p)[1];
+      v[0] = x.x;
+      v[1] = x.y;
+      v[2] = y.x;
+      v[3] = y.y;
+    } else {
+      const float4 x = *reinterpret_cast<const float4*>(p);
+      v[0] = x.x;
+      v[1] = x.y;
+      v[2] = x.z;
+      v[3] = x.w;
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) v[c] = c < ncol ? (double)p[c] : 0.0;
+  }
+}
+template <typename T, int NC>
+__device__ inline void row_store(T* __restrict__ p, int ncol, const double (&v)[4]) {
+  if constexpr (NC == 4) {
+    if constexpr (sizeof(T) == 8) {
+      reinterpret_cast<double2*>(p)[0] = double2{v[0], v[1]};
+      reinterpret_cast<double2*>(p)[1] = double2{v[2], v[3]};
+    } else {
+      *reinterpret_cast<float4*>(p) = float4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      if (c < ncol) p[c] = (T)v[c];
+  }
+}
+
+// the current values of the two packed rows (issued early: the loads are in
+// flight while the workgroup stages and contracts its inputs)
+template <typename T, int NC>
 __device__ inline void pack_load(int64_t rp, int64_t rm, int ncol, const T* __restrict__ plus,
                                  const T* __restrict__ minus, double (&op)[4], double (&om)[4]) {
+  row_load<T, NC>(plus + rp * ncol, ncol, op);
+  if (rm >= 0) {
+    row_load<T, NC>(minus + rm * ncol, ncol, om);
+  } else {
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    op[c] = c < ncol ? (double)plus[rp * ncol + c] : 0.0;
-    om[c] = (c < ncol && rm >= 0) ? (double)minus[rm * ncol + c] : 0.0;
+    for (int c = 0; c < 4; ++c) om[c] = 0.0;
   }
 }
 
@@ -87,7 +131,7 @@ __device__ inline void pack_load(int64_t rp, int64_t rm, int ncol, const T* __re
 //   fA  [ny][nc]           f(y, j)
 //   fC  [1 + nb][nc]       f(v, j) for v = a, b_0 ..
 //   Ss, Es [1 + nb][nc][ncol]  S(i, v), E(i, v)
-template <typename T>
+template <typename T, int NC>
 // (two workgroups per CU: at most 80 KB of LDS and 128 VGPRs each)
 __global__ __launch_bounds__(CUA_THREADS, 4) void k_ccvv_up_vpair(CcvvUpArgs<T> p, const uint32_t* __restrict__ groups) {
   extern __shared__ double sm[];
@@ -120,7 +164,7 @@ __global__ __launch_bounds__(CUA_THREADS, 4) void k_ccvv_up_vpair(CcvvUpArgs<T> 
       closed_pair(it / nb, i, j);
       int64_t rp, rm;
       pack_rows(i, j, a, b0 + it % nb, npv, nmv, p.minus != nullptr, rp, rm);
-      pack_load<T>(rp, rm, ncol, p.plus, p.minus, op[m], om[m]);
+      pack_load<T, NC>(rp, rm, ncol, p.plus, p.minus, op[m], om[m]);
     }
   }
   if (havex) {
@@ -237,13 +281,14 @@ __global__ __launch_bounds__(CUA_THREADS, 4) void k_ccvv_up_vpair(CcvvUpArgs<T> 
                    const double (&o1)[4], const double (&o2)[4]) {
     const bool dij = i != j, dab = a != b;
     const double wk = (dij && dab) ? 0.5 : ((dij || dab) ? 0.5 * 0.70710678118654752440 : 0.25);
+    double v[4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c)
-      if (c < ncol) p.plus[rp * ncol + c] = (T)(o1[c] + wk * sp[c]);
+    for (int c = 0; c < 4; ++c) v[c] = o1[c] + wk * sp[c];
+    row_store<T, NC>(p.plus + rp * ncol, ncol, v);
     if (rm >= 0) {
 #pragma unroll
-      for (int c = 0; c < 4; ++c)
-        if (c < ncol) p.minus[rm * ncol + c] = (T)(o2[c] + 0.5 * sd[c]);
+      for (int c = 0; c < 4; ++c) v[c] = o2[c] + 0.5 * sd[c];
+      row_store<T, NC>(p.minus + rm * ncol, ncol, v);
     }
   };
 #pragma unroll
@@ -264,7 +309,7 @@ __global__ __launch_bounds__(CUA_THREADS, 4) void k_ccvv_up_vpair(CcvvUpArgs<T> 
     sums(it, i, j, b, sp, sd);
     int64_t rp, rm;
     pack_rows(i, j, a, b, npv, nmv, p.minus != nullptr, rp, rm);
-    pack_load<T>(rp, rm, ncol, p.plus, p.minus, o1, o2);
+    pack_load<T, NC>(rp, rm, ncol, p.plus, p.minus, o1, o2);
     store(i, j, b, rp, rm, sp, sd, o1, o2);
   }
 }
@@ -277,7 +322,7 @@ __global__ __launch_bounds__(CUA_THREADS, 4) void k_ccvv_up_vpair(CcvvUpArgs<T> 
 // (f(v).P = sum_y f(v, y) P(y, c); kappa = 1, 1/2 or 1/4 as none, one or both
 // of i = j, a = b hold, where P counts coinciding images twice).  Shared:
 // P and M for tile A and tile B ([2][2][16][nout + 1], padded) and f(v, y).
-template <typename T>
+template <typename T, int NC>
 __global__ __launch_bounds__(CUB_T * CUB_T) void k_ccvv_up_cpair(CcvvUpArgs<T> p) {
   extern __shared__ double sm[];
   const int nc = p.nc, nv = p.nv, ncol = p.ncol, ny = p.ny;
@@ -301,7 +346,7 @@ __global__ __launch_bounds__(CUB_T * CUB_T) void k_ccvv_up_cpair(CcvvUpArgs<T> p
   double op[4] = {0, 0, 0, 0}, om[4] = {0, 0, 0, 0};
   if (valid) {
     pack_rows(i, j, a, b, npv, nmv, p.minus != nullptr, rp, rm);
-    pack_load<T>(rp, rm, ncol, p.plus, p.minus, op, om);
+    pack_load<T, NC>(rp, rm, ncol, p.plus, p.minus, op, om);
   }
   double* PM = sm;                         // [P, M][tile A, B][CUB_T][ld]
   double* fV = PM + 4 * CUB_T * ld;        // [tile][CUB_T][ny]
@@ -349,13 +394,14 @@ __global__ __launch_bounds__(CUB_T * CUB_T) void k_ccvv_up_cpair(CcvvUpArgs<T> p
   }
   const bool dij = i != j, dab = a != b;
   const double wk = (dij && dab) ? 0.5 : ((dij || dab) ? 0.5 * 0.70710678118654752440 : 0.25);
+  double v[4];
 #pragma unroll
-  for (int c = 0; c < 4; ++c)
-    if (c < ncol) p.plus[rp * ncol + c] = (T)(op[c] + wk * sp[c]);
+  for (int c = 0; c < 4; ++c) v[c] = op[c] + wk * sp[c];
+  row_store<T, NC>(p.plus + rp * ncol, ncol, v);
   if (rm >= 0) {
 #pragma unroll
-    for (int c = 0; c < 4; ++c)
-      if (c < ncol) p.minus[rm * ncol + c] = (T)(om[c] + 0.5 * sd[c]);
+    for (int c = 0; c < 4; ++c) v[c] = om[c] + 0.5 * sd[c];
+    row_store<T, NC>(p.minus + rm * ncol, ncol, v);
   }
 }
 
@@ -741,6 +787,15 @@ std::vector<uint32_t> ccvv_up_groups(int nv) {
   return g;
 }
 
+// the packed rows as whole vector accesses: four columns and both entries
+// aligned to a row
+template <typename T>
+bool rows_vectorised(const CcvvUpArgs<T>& p) {
+  const uintptr_t row = 4 * sizeof(T);
+  return p.ncol == 4 && reinterpret_cast<uintptr_t>(p.plus) % row == 0 &&
+         (!p.minus || reinterpret_cast<uintptr_t>(p.minus) % row == 0);
+}
+
 template <typename T>
 hipError_t ccvv_up_apply(const CcvvUpArgs<T>& p, const uint32_t* groups, int64_t ngroups, hipStream_t s) {
   if (p.nc <= 0 || p.nv <= 0) return hipSuccess;
@@ -752,7 +807,10 @@ hipError_t ccvv_up_apply(const CcvvUpArgs<T>& p, const uint32_t* groups, int64_t
     if (!havex) q.X = nullptr;
     if (!havec) q.fC = nullptr, q.W5 = q.W6 = nullptr;
     const int64_t shm = ccvv_up_vpair_shared(q.nc, q.nak, q.ncol, q.ny, havex, havec);
-    hipLaunchKernelGGL(k_ccvv_up_vpair<T>, dim3((unsigned)ngroups), dim3(CUA_THREADS), (size_t)shm, s, q, groups);
+    if (rows_vectorised(q))
+      hipLaunchKernelGGL((k_ccvv_up_vpair<T, 4>), dim3((unsigned)ngroups), dim3(CUA_THREADS), (size_t)shm, s, q, groups);
+    else
+      hipLaunchKernelGGL((k_ccvv_up_vpair<T, 0>), dim3((unsigned)ngroups), dim3(CUA_THREADS), (size_t)shm, s, q, groups);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -761,7 +819,10 @@ hipError_t ccvv_up_apply(const CcvvUpArgs<T>& p, const uint32_t* groups, int64_t
     const int64_t ntp = (int64_t)ntile * (ntile + 1) / 2, npc = (int64_t)p.nc * (p.nc + 1) / 2;
     const int ld = (p.ny * p.ncol) | 1;
     const size_t shm = (size_t)(4 * CUB_T * ld + 2 * CUB_T * p.ny) * sizeof(double);
-    hipLaunchKernelGGL(k_ccvv_up_cpair<T>, dim3((unsigned)ntp, (unsigned)npc), dim3(CUB_T * CUB_T), shm, s, p);
+    if (rows_vectorised(p))
+      hipLaunchKernelGGL((k_ccvv_up_cpair<T, 4>), dim3((unsigned)ntp, (unsigned)npc), dim3(CUB_T * CUB_T), shm, s, p);
+    else
+      hipLaunchKernelGGL((k_ccvv_up_cpair<T, 0>), dim3((unsigned)ntp, (unsigned)npc), dim3(CUB_T * CUB_T), shm, s, p);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

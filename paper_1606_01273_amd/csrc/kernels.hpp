@@ -326,6 +326,24 @@ struct CavvArgs {
   int64_t fCA_stride = 0;
   T* Zp = nullptr;
   T* Zm = nullptr;
+  // up from caav: C+- [nc * nv][ny * nak] (caav rows times the G sum and
+  // difference); f(v, y) = fVA[v * stride + y]
+  const T* Cp = nullptr;
+  const T* Cm = nullptr;
+  const double* fVA = nullptr;
+  int64_t fVA_stride = 0;
+  // down into caav and aaav (closed-index pass over the packed cavv x):
+  // Sb, Db [nc * nv][ny * nak] (written), f(y, w) = fAV[y * stride + w];
+  // Scd [2][nc][nv][nak] (written: per closed index, summed afterwards into
+  // Sc, Dc [2][nv][nak]), f(z, w) = fCV[z * stride + w]
+  T* Sb = nullptr;
+  T* Db = nullptr;
+  const double* fAV = nullptr;
+  int64_t fAV_stride = 0;
+  T* Scd = nullptr;
+  T* Sc = nullptr;
+  const double* fCV = nullptr;
+  int64_t fCV_stride = 0;
 };
 bool cavv_pass_supported(int nc, int nv, int nak, int ny);
 // groups: the table of ccvv_up_groups

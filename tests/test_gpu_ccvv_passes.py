@@ -11,8 +11,8 @@ two forms only sum the same products in another order); FP32 residuals of
 the inner solver within 1e-5 relative of each other (both round every
 product to FP32; the passes keep their partial sums in FP64).  Cases: several
 closed pairs and a single one (no '-' rows), virtual counts off the 16-wide
-tile (ragged tiles), 1-3 states (1-3 columns, and the 1-column function sets
-of SS-SR), rotated orbitals (Reading C: within-block terms into ccvv keep
+tile (ragged tiles), 1-4 states (1-4 columns -- four takes the vector row
+accesses --, and the 1-column function sets of SS-SR), rotated orbitals (Reading C: within-block terms into ccvv keep
 the all-orderings sigma beside the passes), forty closed orbitals (the
 in-pass active contraction in more than one round of matrix-core tiles), and
 a Fock operator with only the closed-virtual block between orbital spaces
@@ -64,6 +64,7 @@ CASES = [
     ((4, 4, 17, 50, 1), 4, "B", "MSMR"),
     ((5, 4, 30, 70, 2), 9, "C", "MSMR"),
     ((40, 6, 5, 120, 3), 2, "B", "MSMR"),
+    ((4, 4, 18, 50, 4), 6, "B", "MSMR"),
 ]
 
 
@@ -117,7 +118,7 @@ def test_passes_closed_virtual_block_only(dev):
     g1.close()
 
 
-@pytest.mark.parametrize("dims,seed", [((10, 6, 120, 400, 3), 1), ((3, 4, 17, 40, 2), 5)])
+@pytest.mark.parametrize("dims,seed", [((10, 6, 120, 400, 3), 1), ((3, 4, 17, 40, 2), 5), ((3, 4, 17, 40, 4), 5)])
 def test_passes_fp32(dev, dims, seed):
     from paper_1606_01273_amd import lib
     L = lib()
