@@ -41,7 +41,18 @@ namespace {
 
 constexpr int CV_NB = VPAIR_GROUP;   // virtual pairs (a, b0 .. b0 + 2) per workgroup
 constexpr int CV_THREADS = 512;
-constexpr int CV_IPT = 12;         // cavv outputs per thread whose old values are loaded first
+constexpr int CV_IPT = 4;
+
+// the packed cavv sigma element of item it = (kind, i, alpha) and pair u of
+// the group (a, b0 + u), or NULL (no such pair, or the - entry of a = b)
+template <typename T>
+__device__ inline T* cavv_out(T* sp, T* sm, int it, int u, int nb, int nc, int nak, int a, int b0, int64_t npv,
+                              int64_t nmv) {
+  const int al = it % nak, i = (it / nak) % nc, kind = it / (nak * nc);
+  if (u >= nb || (kind == 1 && (a == b0 + u || !sm))) return nullptr;
+  return kind == 0 ? sp + ((int64_t)i * npv + (int64_t)a * (a + 1) / 2 + b0 + u) * nak + al
+                   : sm + ((int64_t)i * nmv + (int64_t)a * (a - 1) / 2 + b0 + u) * nak + al;
+}          // (kind, i, alpha) items per thread whose old values are loaded first
 
 }  // namespace
 
@@ -72,21 +83,23 @@ __global__ __launch_bounds__(CV_THREADS, 4) void k_cavv_vpair(CavvArgs<T> p, con
   auto vidx = [&](int v) { return v == 0 ? a : b0 + v - 1; };
   auto pab = [&](int u) { return (int64_t)a * (a + 1) / 2 + b0 + u; };
   auto mab = [&](int u) { return (int64_t)a * (a - 1) / 2 + b0 + u; };
-  // cavv outputs (u, kind, i, alpha), kind 0: +, 1: -
-  const int nout = up ? nb * 2 * nc * nak : 0;
-  auto out_ptr = [&](int e) -> T* {
-    const int al = e % nak, i = (e / nak) % nc, kind = (e / (nak * nc)) & 1, u = e / (2 * nak * nc);
-    if (kind == 1 && (a == b0 + u || !p.sm)) return nullptr;
-    return kind == 0 ? p.sp + ((int64_t)i * npv + pab(u)) * nak + al : p.sm + ((int64_t)i * nmv + mab(u)) * nak + al;
-  };
-  double old[CV_IPT];
+  // cavv outputs: a thread takes (kind, i, alpha) (kind 0: +, 1: -) for the
+  // nb pairs of the group, so the caav product row of (i, a) is read once;
+  // at most CV_IPT items per thread (checked on the host)
+  const int nit = up ? 2 * nc * nak : 0;
+  T* const spl = p.sp;
+  T* const smi = p.sm;
+  double old[CV_IPT][CV_NB];
 #pragma unroll
   for (int m = 0; m < CV_IPT; ++m) {
-    const int e = t + m * (int)blockDim.x;
-    old[m] = 0.0;
-    if (e < nout) {
-      const T* q = out_ptr(e);
-      if (q) old[m] = (double)*q;
+    const int it = t + m * (int)blockDim.x;
+#pragma unroll
+    for (int u = 0; u < CV_NB; ++u) {
+      old[m][u] = 0.0;
+      if (it < nit) {
+        const T* q = cavv_out(spl, smi, it, u, nb, nc, nak, a, b0, npv, nmv);
+        if (q) old[m][u] = (double)*q;
+      }
     }
   }
   if (haveq) {
@@ -121,46 +134,49 @@ __global__ __launch_bounds__(CV_THREADS, 4) void k_cavv_vpair(CavvArgs<T> p, con
   if (havec)
     for (int e = t; e < (1 + nb) * ny; e += blockDim.x) fva[e] = p.fVA[(int64_t)vidx(e / ny) * p.fVA_stride + e % ny];
   __syncthreads();
-  // cavv rows
-  auto value = [&](int e) {
-    const int al = e % nak, i = (e / nak) % nc, kind = (e / (nak * nc)) & 1, u = e / (2 * nak * nc);
-    double s = 0.0;
-    if (haveq) {
-      const double* q = Qs + (u * 2 + kind) * nq + al;
-      for (int y = 0; y < ny; ++y) s += fac[y * nc + i] * q[y * nak];
-    }
-    if (haveb) {
-      const double fbi = fvc[(1 + u) * nc + i], fai = fvc[i];
-      const double ba = Bs[(0 * 2 + kind) * nak + al], bb = Bs[((1 + u) * 2 + kind) * nak + al];
-      if (kind == 0) s += (a != b0 + u ? 0.70710678118654752440 : 0.5) * (fbi * ba + fai * bb);
-      else s += 0.70710678118654752440 * (fbi * ba - fai * bb);
-    }
-    if (havec) {
-      const T* C = kind == 0 ? p.Cp : p.Cm;
-      const T* ca = C + ((int64_t)i * nv + a) * nq + al;
-      const T* cb = C + ((int64_t)i * nv + b0 + u) * nq + al;
-      const double* fa = fva;                   // f(a, y)
-      const double* fb = fva + (1 + u) * ny;    // f(b, y)
-      double sa = 0.0, sb = 0.0;
-      for (int y = 0; y < ny; ++y) {
-        sa += fb[y] * (double)ca[y * nak];
-        sb += fa[y] * (double)cb[y * nak];
-      }
-      if (kind == 0) s += (a != b0 + u ? 0.70710678118654752440 : 0.5) * (sa + sb);
-      else s += 0.70710678118654752440 * (sa - sb);
-    }
-    return s;
-  };
+  // cavv rows: the additions to the nb outputs of each (kind, i, alpha)
 #pragma unroll
   for (int m = 0; m < CV_IPT; ++m) {
-    const int e = t + m * (int)blockDim.x;
-    if (e >= nout) continue;
-    T* q = out_ptr(e);
-    if (q) *q = (T)(old[m] + value(e));
-  }
-  for (int e = t + CV_IPT * (int)blockDim.x; e < nout; e += blockDim.x) {
-    T* q = out_ptr(e);
-    if (q) *q = (T)((double)*q + value(e));
+    const int it = t + m * (int)blockDim.x;
+    if (it >= nit) continue;
+    const int al = it % nak, i = (it / nak) % nc, kind = it / (nak * nc);
+    double ca[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (havec) {
+      const T* C = (kind == 0 ? p.Cp : p.Cm) + ((int64_t)i * nv + a) * nq + al;
+#pragma unroll
+      for (int y = 0; y < 8; ++y)
+        if (y < ny) ca[y] = (double)C[y * nak];
+    }
+#pragma unroll
+    for (int u = 0; u < CV_NB; ++u) {
+      T* q = cavv_out(spl, smi, it, u, nb, nc, nak, a, b0, npv, nmv);
+      if (!q) continue;
+      const double kv = kind == 0 ? (a != b0 + u ? 0.70710678118654752440 : 0.5) : 0.70710678118654752440;
+      double s = 0.0;
+      if (haveq) {
+        const double* qs = Qs + (u * 2 + kind) * nq + al;
+        for (int y = 0; y < ny; ++y) s += fac[y * nc + i] * qs[y * nak];
+      }
+      if (haveb) {
+        const double fbi = fvc[(1 + u) * nc + i], fai = fvc[i];
+        const double ba = Bs[(0 * 2 + kind) * nak + al], bb = Bs[((1 + u) * 2 + kind) * nak + al];
+        s += kv * (kind == 0 ? fbi * ba + fai * bb : fbi * ba - fai * bb);
+      }
+      if (havec) {
+        const T* cb = (kind == 0 ? p.Cp : p.Cm) + ((int64_t)i * nv + b0 + u) * nq + al;
+        const double* fa = fva;                   // f(a, y)
+        const double* fb = fva + (1 + u) * ny;    // f(b, y)
+        double sa = 0.0, sb = 0.0;
+#pragma unroll
+        for (int y = 0; y < 8; ++y) {
+          if (y >= ny) break;
+          sa += fb[y] * ca[y];
+          sb += fa[y] * (double)cb[y * nak];
+        }
+        s += kv * (kind == 0 ? sa + sb : sa - sb);
+      }
+      *q = (T)(old[m][u] + s);
+    }
   }
   // Z+- rows of the pairs: (u, kind, y, c)
   if (havez)
@@ -254,6 +270,7 @@ int64_t cavv_vpair_shared(int nc, int nak, int ny, bool haveq, bool haveb, bool 
 bool cavv_pass_supported(int nc, int nv, int nak, int ny) {
   if (nc <= 0 || nv <= 0 || nv > 65535 || nak <= 0 || ny < 1 || ny > 8) return false;
   if (CVC_A * nak > 256) return false;   // closed-index pass: a thread per (a, column)
+  if (2 * nc * nak > CV_IPT * CV_THREADS) return false;   // virtual-pair pass: items per thread
   int dev = 0, lds_max = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)

@@ -421,6 +421,7 @@ __global__ __launch_bounds__(CUB_T * CUB_T) void k_ccvv_up_cpair(CcvvUpArgs<T> p
 // A thread owns (u, i, c) and runs the z sum from its own loads; the
 // contraction with G runs on FP64 MFMA (16 x 16 tiles of (i, column)).
 constexpr int CDV_THREADS = 512;
+constexpr int CDV_ZB = 8;   // closed indices whose packed values a thread loads at once
 // (two workgroups per CU: at most 80 KB of LDS and 128 VGPRs each)
 template <typename T>
 __global__ __launch_bounds__(CDV_THREADS, 4) void k_ccvv_down_vpair(CcvvDownArgs<T> p,
@@ -469,10 +470,10 @@ __global__ __launch_bounds__(CDV_THREADS, 4) void k_ccvv_down_vpair(CcvvDownArgs
     const int64_t pab = (int64_t)a * (a + 1) / 2 + b, mab = (int64_t)a * (a - 1) / 2 + b;
     double ys[8] = {0, 0, 0, 0, 0, 0, 0, 0}, yd[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     double t1ab = 0.0, t1ba = 0.0, t2ab = 0.0, t2ba = 0.0;
-    for (int z0 = 0; z0 < nc; z0 += 4) {
-      double psym[4], msk[4];
+    for (int z0 = 0; z0 < nc; z0 += CDV_ZB) {
+      double psym[CDV_ZB], msk[CDV_ZB];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
+      for (int k = 0; k < CDV_ZB; ++k) {
         psym[k] = msk[k] = 0.0;
         const int z = z0 + k;
         if (z >= nc) continue;
@@ -486,7 +487,7 @@ __global__ __launch_bounds__(CDV_THREADS, 4) void k_ccvv_down_vpair(CcvvDownArgs
         }
       }
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
+      for (int k = 0; k < CDV_ZB; ++k) {
         const int z = z0 + k;
         if (z >= nc) break;
         if (havey) {
@@ -585,9 +586,10 @@ __global__ __launch_bounds__(256) void k_sum_middle(int64_t n_outer, int64_t n_m
 // term (the second term's are Ys and -Yd), so
 //   + entry (ij, a) += kc (G3 + G4) Ys(a),  - entry += (G3 - G4) Yd(a) / sqrt 2
 // (kc = 1/sqrt 2, or 1/2 for i = j; G3/G4 [ccav columns][ny x ncol]).  A
-// thread owns (a, c) and runs the w sum from its own loads, eight w at a
+// thread owns (a, c) and runs the w sum from its own loads, CDB_WB w at a
 // time; the G contraction runs on MFMA.
 constexpr int CDB_A = 64;
+constexpr int CDB_WB = 8;    // virtual indices whose packed values a thread loads at once
 template <typename T>
 __global__ __launch_bounds__(256) void k_ccvv_down_cpair(CcvvDownArgs<T> p) {
   extern __shared__ double sm[];
@@ -640,10 +642,10 @@ __global__ __launch_bounds__(256) void k_ccvv_down_cpair(CcvvDownArgs<T> p) {
   const int64_t fs = p.fV_stride;
   if (act) {
     const int f0 = 0, nf = nv;
-    for (int w0 = 0; w0 < nf; w0 += 8) {
-      double pv[8], mv[8];
+    for (int w0 = 0; w0 < nf; w0 += CDB_WB) {
+      double pv[CDB_WB], mv[CDB_WB];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < CDB_WB; ++u) {
         pv[u] = mv[u] = 0.0;
         if (w0 + u >= nf) continue;
         const int w = f0 + w0 + u;
@@ -657,7 +659,7 @@ __global__ __launch_bounds__(256) void k_ccvv_down_cpair(CcvvDownArgs<T> p) {
         }
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < CDB_WB; ++u) {
         if (w0 + u >= nf) break;
 #pragma unroll
         for (int y = 0; y < 8; ++y) {

@@ -90,9 +90,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
   constexpr int KT = 256 / KB, UB = BN * KB / 256, UN = KB / 4;
   static_assert(TPR * TM == 256 && UA * TPR == KB, "A tile shares");
   static_assert(BN == 64 && KT * KB == 256 && UB * 256 == BN * KB, "B tile shares");
-  __shared__ double As[TM][LDP];
-  __shared__ double Bs[BN][LDP];
-  __shared__ double B2s[DUAL ? BN : 1][LDP];
+  // two LDS buffers where they fit in 64 KB: the next K tile is stored into
+  // the other buffer while this one feeds the MFMAs, one barrier per tile
+  constexpr bool DBUF = 2 * (TM + BN * (DUAL ? 2 : 1)) * LDP * 8 <= 64 * 1024;
+  constexpr int NBUF = DBUF ? 2 : 1;
+  __shared__ double As[NBUF][TM][LDP];
+  __shared__ double Bs[NBUF][BN][LDP];
+  __shared__ double B2s[NBUF][DUAL ? BN : 1][LDP];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -176,32 +180,40 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
       }
     }
   };
-  auto store_tile = [&]() {
+  auto store_tile = [&](int bf) {
 #pragma unroll
-    for (int u = 0; u < UA; ++u) As[rA][cA + u] = ra[u];
+    for (int u = 0; u < UA; ++u) As[bf][rA][cA + u] = ra[u];
     if (B_NK) {
 #pragma unroll
-      for (int u = 0; u < UN; ++u) Bs[rB][cB + u] = rb[u];
+      for (int u = 0; u < UN; ++u) Bs[bf][rB][cB + u] = rb[u];
     } else {
 #pragma unroll
       for (int u = 0; u < UB; ++u) {
-        Bs[cN + u][kB] = rb[u];
-        if (DUAL) B2s[cN + u][kB] = rb2[u];
+        Bs[bf][cN + u][kB] = rb[u];
+        if (DUAL) B2s[bf][cN + u][kB] = rb2[u];
       }
     }
   };
+  int buf = 0;
   if (kb < ke) load_tile(kb);
-  for (int64_t k0 = kb; k0 < ke; k0 += KB) {
-    store_tile();
+  if (DBUF) {
+    if (kb < ke) store_tile(0);
     __syncthreads();
-    if (k0 + KB < ke) load_tile(k0 + KB);
+  }
+  for (int64_t k0 = kb; k0 < ke; k0 += KB) {
+    if (!DBUF) {
+      store_tile(0);
+      __syncthreads();
+    }
+    const bool more = k0 + KB < ke;
+    if (more) load_tile(k0 + KB);
 #pragma unroll
     for (int kk = 0; kk < KB; kk += 4) {
       double a[MT], b[2], b2[2];
-      for (int i = 0; i < MT; ++i) a[i] = As[wm * (16 * MT) + i * 16 + (lane & 15)][kk + (lane >> 4)];
+      for (int i = 0; i < MT; ++i) a[i] = As[buf][wm * (16 * MT) + i * 16 + (lane & 15)][kk + (lane >> 4)];
       for (int j = 0; j < 2; ++j) {
-        b[j] = Bs[wn * 32 + j * 16 + (lane & 15)][kk + (lane >> 4)];
-        if (DUAL) b2[j] = B2s[wn * 32 + j * 16 + (lane & 15)][kk + (lane >> 4)];
+        b[j] = Bs[buf][wn * 32 + j * 16 + (lane & 15)][kk + (lane >> 4)];
+        if (DUAL) b2[j] = B2s[buf][wn * 32 + j * 16 + (lane & 15)][kk + (lane >> 4)];
       }
       for (int i = 0; i < MT; ++i)
         for (int j = 0; j < 2; ++j) {
@@ -209,7 +221,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
           if (DUAL) acc2[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b2[j], acc2[i][j], 0, 0, 0);
         }
     }
-    __syncthreads();
+    if (DBUF) {
+      // the other buffer was last read before the previous barrier
+      if (more) store_tile(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    } else {
+      __syncthreads();
+    }
   }
   for (int i = 0; i < MT; ++i)
     for (int j = 0; j < 2; ++j)

@@ -92,6 +92,31 @@ def test_passes_match_term_path(dev, dims, seed, reading, scheme):
     g1.close()
 
 
+def test_passes_match_term_path_full_workload(dev):
+    """The benchmark's workload (30 closed, 8 active, 400 virtual orbitals,
+    1500 auxiliary functions, 4 states, Reading B): the residual of one state
+    with the packed-row passes (four columns: whole-row vector accesses)
+    against the term-by-term path, 1e-12 of the largest element."""
+    from synth.gen import workload_problem
+    from paper_1606_01273_amd import lib
+    L = lib()
+    p = workload_problem("full", "B")
+    g0, g1 = _pair(p, "MSMR")
+    assert L.caspt2_debug_ccvv_passes_used(g1._h, 0) == 7
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(3)
+    x = torch.randn(g0.length, dtype=torch.float64, device=dev, generator=gen)
+    ref = torch.empty_like(x)
+    got = torch.empty_like(x)
+    g0.residual(1, x, ref, with_source=True)
+    g0.close()
+    g1.residual(1, x, got, with_source=True)
+    g1.close()
+    r = _rel(got, ref)
+    print(f"  full workload, state 1: {r:.3e}", flush=True)
+    assert r < 1e-12
+
+
 def test_passes_closed_virtual_block_only(dev):
     """Only f(closed, virtual) couples orbital spaces: the caav terms alone
     (the virtual-pair passes without the cavv contractions)."""
