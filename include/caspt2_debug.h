@@ -47,7 +47,9 @@ CASPT2_API int caspt2_debug_eigh(int32_t n, double* A, double* w, double* V);
 /* The same with the solver form chosen: method 0 by size, 1 one workgroup
  * with the matrices in LDS (n <= 64), 2 one workgroup on global memory
  * (n <= 512), 3 one launch pair per rotation step over the whole device, 4
- * one launch per rotation step (alternating matrix buffers); sweeps (host,
+ * one launch per rotation step (alternating matrix buffers), 5 block Jacobi
+ * (pairs of 16-index blocks diagonalised in LDS, their rotations applied to
+ * the whole matrix by one launch per step of the block tournament); sweeps (host,
  * may be NULL) receives the number of sweeps.  E_ARG for a form that does
  * not take this n. */
 CASPT2_API int caspt2_debug_eigh_method(int32_t n, double* A, double* w, double* V, int32_t method,

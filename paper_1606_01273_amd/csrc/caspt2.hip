@@ -566,10 +566,9 @@ void eigh_dev(H& h, const double* A, int64_t n, std::vector<double>& w, DBuf& Ve
   if (h.jws.n < jacobi_ws_doubles(n)) h.jws.alloc(jacobi_ws_doubles(n));
   h.hpin.ensure(std::max<int64_t>(n, 8));
   int sweeps = 0;
-  // second buffer of the one-launch-per-step form (faster than the launch
-  // pairs up to JACOBI_STEP1_MAX; above, its redundant rotation reads cost more)
-  DBuf A2(n > JACOBI_WG_AUTO && n <= JACOBI_STEP1_MAX ? n * n : 0);
-  HIPCHECK(jacobi_eigh((int)n, Aw.p, Vec.p, h.jws.p, 60, 1e-15, h.s, &sweeps, 0, A2.p, h.hpin.p, abs_tol));
+  // form by size: the LDS workgroup up to 64, the block form above (the
+  // scalar whole-device forms remain for comparison, through the debug entry)
+  HIPCHECK(jacobi_eigh((int)n, Aw.p, Vec.p, h.jws.p, 60, 1e-15, h.s, &sweeps, 0, nullptr, h.hpin.p, abs_tol));
   // the eigenvalues are the diagonal: a strided copy of n doubles
   HIPCHECK(hipMemcpy2DAsync(h.hpin.p, sizeof(double), Aw.p, (size_t)(n + 1) * sizeof(double), sizeof(double),
                             (size_t)n, hipMemcpyDeviceToHost, h.s));
@@ -4190,7 +4189,7 @@ int caspt2_debug_eigh_method(int32_t n, double* A, double* w, double* V, int32_t
 
 int caspt2_debug_eigh_abs(int32_t n, double* A, double* w, double* V, int32_t method, double abs_tol,
                           int32_t* sweeps_out) {
-  if (n <= 0 || !A || !w || !V || method < 0 || method > 4 || !(abs_tol >= 0.0)) return CASPT2_E_ARG;
+  if (n <= 0 || !A || !w || !V || method < 0 || method > 5 || !(abs_tol >= 0.0)) return CASPT2_E_ARG;
   if ((method == 1 && n > 64) || (method == 2 && n > 512)) return CASPT2_E_ARG;
   ABI_GUARD({
     double* ws = nullptr;
@@ -4201,7 +4200,7 @@ int caspt2_debug_eigh_abs(int32_t n, double* A, double* w, double* V, int32_t me
     int sweeps = 0;
     // method 4: the whole-device form with one launch per step (second
     // buffer); method 0 picks the form by size as the library's set-up does
-    const bool second = method == 4 || (method == 0 && n > JACOBI_WG_AUTO && n <= JACOBI_STEP1_MAX);
+    const bool second = method == 4;
     hipError_t e = jacobi_eigh(n, A, V, ws, 60, 1e-15, nullptr, &sweeps, method == 4 ? 3 : method,
                                second ? ws + nws : nullptr, hp.p, abs_tol);
     if (sweeps_out) *sweeps_out = sweeps;

@@ -1269,6 +1269,221 @@ __global__ __launch_bounds__(1024) void k_jacobi_small(int n, double* __restrict
   if (t == 0 && sweeps) *sweeps = sw;
 }
 
+// Block Jacobi (large n): the indices are cut into blocks of BJ_B, and the
+// blocks play the round-robin tournament the scalar form plays with single
+// indices.  At each step every pair of blocks (I, J) diagonalises its own
+// 2 BJ_B x 2 BJ_B submatrix (k_bjac_solve: BJ_INNER cyclic sweeps in LDS,
+// the accumulated rotation then permuted so that the pair's diagonal is in
+// ascending order, smallest values into block I, as a full eigensolver of the
+// submatrix would order them), and one launch applies every pair's rotation
+// R to the whole matrix, A <- P^T A P and V <- V P with P the block-diagonal
+// (after the pairing permutation) of the R (k_bjac_apply).  A sweep is
+// mb - 1 steps instead of n - 1, each reading A and V once.  The ordering
+// matters for convergence: without it the couplings inside a cluster of
+// equal eigenvalues (the null space of a rank-deficient metric) decay
+// slowly, with it the clusters gather into blocks and the sweep count is
+// that of an exact inner solve.
+constexpr int BJ_B = 16, BJ_P = 2 * BJ_B, BJ_INNER = 2;
+
+// local index l (0 .. BJ_P - 1) of the pair (I, J) -> global index
+__device__ inline int bj_index(int l, int I, int J) { return l < BJ_B ? I * BJ_B + l : J * BJ_B + (l - BJ_B); }
+
+// one workgroup per pair of blocks: R[k] (BJ_P x BJ_P, row-major) rotates the
+// pair's local indices; indices >= n are left alone (zero rows and columns,
+// identity in R)
+constexpr int BJ_SOLVE_THREADS = 256;
+__global__ __launch_bounds__(BJ_SOLVE_THREADS) void k_bjac_solve(int n, int mb, int step, const double* __restrict__ A,
+                                                   double* __restrict__ R) {
+  __shared__ double S[BJ_P][BJ_P + 1], Q[BJ_P][BJ_P + 1];
+  __shared__ double cs[BJ_B][2];
+  __shared__ int pq[BJ_B][2];
+  __shared__ int perm[BJ_P];
+  __shared__ double dg[BJ_P];
+  const int t = threadIdx.x, k = blockIdx.x;
+  int I, J;
+  jac_pair(k, step, mb, I, J);
+  for (int e = t; e < BJ_P * BJ_P; e += blockDim.x) {
+    const int r = e / BJ_P, c = e % BJ_P;
+    const int gr = bj_index(r, I, J), gc = bj_index(c, I, J);
+    S[r][c] = (gr < n && gc < n) ? A[(int64_t)gr * n + gc] : 0.0;
+    Q[r][c] = r == c ? 1.0 : 0.0;
+  }
+  if (t < BJ_P) perm[t] = t;
+  __syncthreads();
+  for (int sw = 0; sw < BJ_INNER; ++sw) {
+    for (int st = 0; st < BJ_P - 1; ++st) {
+      if (t < BJ_B) {
+        int p, q;
+        jac_pair(t, st, BJ_P, p, q);
+        double c = 1.0, s = 0.0;
+        const double apq = S[p][q];
+        if (apq != 0.0) {
+          const double tau = (S[q][q] - S[p][p]) / (2.0 * apq);
+          const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+          c = 1.0 / sqrt(1.0 + tt * tt);
+          s = tt * c;
+        }
+        cs[t][0] = c;
+        cs[t][1] = s;
+        pq[t][0] = p;
+        pq[t][1] = q;
+      }
+      __syncthreads();
+      // the 2 x 2 blocks of S (each owned by one thread), then the rows of Q
+      for (int e = t; e < BJ_B * BJ_B; e += blockDim.x) {
+        const int a = e / BJ_B, b = e % BJ_B;
+        const int pa = pq[a][0], qa = pq[a][1], pb = pq[b][0], qb = pq[b][1];
+        const double ca = cs[a][0], sa = cs[a][1], cb = cs[b][0], sb = cs[b][1];
+        const double m00 = S[pa][pb], m01 = S[pa][qb], m10 = S[qa][pb], m11 = S[qa][qb];
+        const double r00 = ca * m00 - sa * m10, r01 = ca * m01 - sa * m11;
+        const double r10 = sa * m00 + ca * m10, r11 = sa * m01 + ca * m11;
+        S[pa][pb] = cb * r00 - sb * r01;
+        S[pa][qb] = sb * r00 + cb * r01;
+        S[qa][pb] = cb * r10 - sb * r11;
+        S[qa][qb] = sb * r10 + cb * r11;
+      }
+      for (int e = t; e < BJ_P * BJ_B; e += blockDim.x) {
+        const int i = e / BJ_B, a = e % BJ_B;
+        const int pa = pq[a][0], qa = pq[a][1];
+        const double ca = cs[a][0], sa = cs[a][1];
+        const double vp = Q[i][pa], vq = Q[i][qa];
+        Q[i][pa] = ca * vp - sa * vq;
+        Q[i][qa] = sa * vp + ca * vq;
+      }
+      __syncthreads();
+    }
+  }
+  // one Newton-Schulz step towards the nearest orthogonal matrix, Q <- Q (3 -
+  // Q^T Q) / 2: the accumulated rotations are orthogonal only to a few ulps,
+  // with a bias of one sign on the diagonal of Q^T Q, and A and V take one
+  // such Q per step (hundreds per solve), which would otherwise add up to
+  // a drift of the eigenvalues well above the stopping bound
+  if (t < BJ_P) dg[t] = S[t][t];
+  __syncthreads();
+  {
+    constexpr int RS = BJ_SOLVE_THREADS / BJ_P, OPT = BJ_P / RS;   // row stride, outputs per thread
+    const int j = t % BJ_P, i0 = t / BJ_P;
+    double acc[OPT];
+#pragma unroll
+    for (int m = 0; m < OPT; ++m) {
+      const int i = i0 + RS * m;
+      double g = 0.0;
+      for (int r = 0; r < BJ_P; ++r) g += Q[r][i] * Q[r][j];
+      acc[m] = g;
+    }
+#pragma unroll
+    for (int m = 0; m < OPT; ++m) S[i0 + RS * m][j] = acc[m];   // Q^T Q over S (its diagonal kept in dg)
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < OPT; ++m) {
+      const int i = i0 + RS * m;
+      double g = 0.0;
+      for (int c = 0; c < BJ_P; ++c) g += Q[i][c] * S[c][j];
+      acc[m] = 1.5 * Q[i][j] - 0.5 * g;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < OPT; ++m) Q[i0 + RS * m][j] = acc[m];
+    __syncthreads();
+  }
+  // ascending diagonal over the pair's valid positions ([0, vI) of block I,
+  // then [BJ_B, BJ_B + vJ) of block J); ties keep the local order
+  if (t < BJ_P && bj_index(t, I, J) < n) {
+    const int vI = min(max(n - I * BJ_B, 0), BJ_B);
+    const double d = dg[t];
+    int rank = 0;
+    for (int m = 0; m < BJ_P; ++m)
+      if (bj_index(m, I, J) < n && (dg[m] < d || (dg[m] == d && m < t))) ++rank;
+    perm[rank < vI ? rank : BJ_B + rank - vI] = t;
+  }
+  __syncthreads();
+  for (int e = t; e < BJ_P * BJ_P; e += blockDim.x) {
+    const int r = e / BJ_P, c = e % BJ_P;
+    R[(int64_t)k * BJ_P * BJ_P + e] = Q[r][perm[c]];
+  }
+}
+
+// A <- P^T A P and V <- V P for the rotations R of step `step`.  Workgroups
+// [0, nA): the tile of rows of pair k1 and columns of pair k2 (k1 <= k2),
+// R[k1]^T A R[k2], written to both mirrored positions (A stays exactly
+// symmetric; the mirror goes through LDS so that both writes are row
+// segments); the rest: 32 rows of V by the columns of one pair.  The tiles
+// of one step partition A and V, so every element has one owner.  The
+// 32 x 32 products run on FP64 MFMA, one 16 x 16 output tile per wave.
+__global__ __launch_bounds__(256) void k_bjac_apply(int n, int mb, int step, double* __restrict__ A,
+                                                    double* __restrict__ V, const double* __restrict__ R) {
+  __shared__ double X[BJ_P][BJ_P + 1], T[BJ_P][BJ_P + 1], R1[BJ_P][BJ_P + 1], R2[BJ_P][BJ_P + 1];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6, nh = mb / 2;
+  const int ti = (wv >> 1) * 16, tj = (wv & 1) * 16;   // this wave's output tile
+  const int li = lane & 15, lk = lane >> 4;
+  const int64_t nA = (int64_t)nh * (nh + 1) / 2;
+  const int64_t g = blockIdx.x;
+  if (g < nA) {
+    int k1 = 0;
+    int64_t rem = g;
+    while (rem >= nh - k1) {
+      rem -= nh - k1;
+      ++k1;
+    }
+    const int k2 = k1 + (int)rem;
+    int I1, J1, I2, J2;
+    jac_pair(k1, step, mb, I1, J1);
+    jac_pair(k2, step, mb, I2, J2);
+    for (int e = t; e < BJ_P * BJ_P; e += blockDim.x) {
+      const int r = e / BJ_P, c = e % BJ_P;
+      const int gr = bj_index(r, I1, J1), gc = bj_index(c, I2, J2);
+      X[r][c] = (gr < n && gc < n) ? A[(int64_t)gr * n + gc] : 0.0;
+      R1[r][c] = R[(int64_t)k1 * BJ_P * BJ_P + e];
+      R2[r][c] = R[(int64_t)k2 * BJ_P * BJ_P + e];
+    }
+    __syncthreads();
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < BJ_P; k0 += 4)   // T = R1^T X
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(R1[k0 + lk][ti + li], X[k0 + lk][tj + li], acc, 0, 0, 0);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) T[ti + lk + 4 * v][tj + li] = acc[v];
+    __syncthreads();
+    acc = d4{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < BJ_P; k0 += 4)   // Y = T R2
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(T[ti + li][k0 + lk], R2[k0 + lk][tj + li], acc, 0, 0, 0);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = ti + lk + 4 * v, j = tj + li;
+      X[i][j] = acc[v];   // X is free after the first product
+      const int gr = bj_index(i, I1, J1), gc = bj_index(j, I2, J2);
+      if (gr < n && gc < n) A[(int64_t)gr * n + gc] = acc[v];
+    }
+    if (k1 == k2) return;
+    __syncthreads();
+    // mirror: A[gc][gr] = Y[i][j], consecutive threads along i
+    for (int e = t; e < BJ_P * BJ_P; e += blockDim.x) {
+      const int i = e % BJ_P, j = e / BJ_P;
+      const int gr = bj_index(i, I1, J1), gc = bj_index(j, I2, J2);
+      if (gr < n && gc < n) A[(int64_t)gc * n + gr] = X[i][j];
+    }
+  } else {
+    const int64_t gv = g - nA;
+    const int rt = (int)(gv / nh), k = (int)(gv % nh);
+    int I, J;
+    jac_pair(k, step, mb, I, J);
+    for (int e = t; e < BJ_P * BJ_P; e += blockDim.x) {
+      const int r = e / BJ_P, c = e % BJ_P;
+      const int gr = rt * BJ_P + r, gc = bj_index(c, I, J);
+      X[r][c] = (gr < n && gc < n) ? V[(int64_t)gr * n + gc] : 0.0;
+      R1[r][c] = R[(int64_t)k * BJ_P * BJ_P + e];
+    }
+    __syncthreads();
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < BJ_P; k0 += 4)   // V X R
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(X[ti + li][k0 + lk], R1[k0 + lk][tj + li], acc, 0, 0, 0);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int gr = rt * BJ_P + ti + lk + 4 * v, gc = bj_index(tj + li, I, J);
+      if (gr < n && gc < n) V[(int64_t)gr * n + gc] = acc[v];
+    }
+  }
+}
+
 // F^ref_MN = sum_rs f_rs (G[M][N][r][s] + G[N][M][r][s]) / 2: the Fock
 // operator in the reference space (Eq. 3) from the transition one-particle
 // densities, symmetrised; one thread per (M, N)
@@ -1307,9 +1522,10 @@ hipError_t jacobi_eigh(int n, double* A, double* V, double* ws, int max_sweeps, 
     const size_t need = 2 * (size_t)n * n * sizeof(double) + 24 * 1024;
     const bool lds_ok = n <= JACOBI_LDS_MAX && need <= (size_t)lds_max;
     if (method == 1 && !lds_ok) return hipErrorInvalidValue;
-    if (method == 0) method = lds_ok ? 1 : n <= JACOBI_WG_AUTO ? 2 : 3;
+    if (method == 0) method = lds_ok ? 1 : n <= JACOBI_WG_AUTO ? 2 : n >= JACOBI_BLOCK_MIN ? 5 : 3;
   }
   if (method == 2 && n > JACOBI_WG_MAX) return hipErrorInvalidValue;
+  if (method < 0 || method > 5) return hipErrorInvalidValue;
   if (method == 1 || method == 2) {
     int* dsw = reinterpret_cast<int*>(ws + 2 * n + 8);
     if (method == 1)
@@ -1334,6 +1550,7 @@ hipError_t jacobi_eigh(int n, double* A, double* V, double* ws, int max_sweeps, 
   double* norms = ws + 2 * m;
   int* pq = reinterpret_cast<int*>(ws + 2 * m + 4);
   double* npart = ws + 2 * m + 4 + (m + 1) / 2 + 1;
+  double* Rb = npart + 2 * JAC_NORM_WG;   // block form: bjac_pairs(n) rotations of BJ_P x BJ_P
   const int nbn = (int)std::min<int64_t>(JAC_NORM_WG, std::max<int64_t>(1, cdiv((int64_t)n * n, 256 * 16)));
   hipLaunchKernelGGL(k_eye, dim3(cdiv((int64_t)n * n, 256)), dim3(256), 0, s, n, V);
   int sw = 0;
@@ -1353,6 +1570,15 @@ hipError_t jacobi_eigh(int n, double* A, double* V, double* ws, int max_sweeps, 
     const bool small = off <= tol * tol * tot && (abs_tol <= 0.0 || off <= abs_tol * abs_tol);
     if (small || tot == 0.0 || m < 2 || (sw > 2 && !(off < prev))) break;
     prev = off;
+    if (method == 5) {
+      const int nb = (n + BJ_B - 1) / BJ_B, mb = nb + (nb & 1), nh = mb / 2;
+      const int64_t nwg = (int64_t)nh * (nh + 1) / 2 + (int64_t)cdiv(n, BJ_P) * nh;
+      for (int step = 0; step < mb - 1; ++step) {
+        hipLaunchKernelGGL(k_bjac_solve, dim3(nh), dim3(BJ_SOLVE_THREADS), 0, s, n, mb, step, (const double*)A, Rb);
+        hipLaunchKernelGGL(k_bjac_apply, dim3((unsigned)nwg), dim3(256), 0, s, n, mb, step, A, V, (const double*)Rb);
+      }
+      continue;
+    }
     const int64_t work = (int64_t)(m / 2) * (m / 2) + (int64_t)n * (m / 2);
     if (A2) {
       // one launch per step, alternating buffers; an odd step count leaves

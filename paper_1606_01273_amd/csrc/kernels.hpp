@@ -357,10 +357,11 @@ hipError_t select_scale_cols(int64_t n, int64_t ncq, const double* Q, const int3
 // Jacobi eigensolver of a symmetric n x n matrix A (destroyed; diagonal ->
 // eigenvalues, unsorted); V receives eigenvectors (columns).  ws: device
 // workspace of >= jacobi_ws_doubles(n) doubles. sweeps: max sweeps.  method: 0
-// by size (below), 1 one workgroup with A and V in LDS (n <= 64), 2 one
+// by size (the LDS form up to 64, the block form above), 1 one workgroup with A and V in LDS (n <= 64), 2 one
 // workgroup on global memory (n <= 512), 3 launches over the whole chip per
 // rotation step: one per step when A2 (a second n x n device buffer) is
-// given, else a parameter launch and a rotation launch.  hpin: page-locked
+// given, else a parameter launch and a rotation launch; 5 block Jacobi over
+// pairs of 16-index blocks (two launches per step of the block tournament).  hpin: page-locked
 // host memory (hipHostMalloc) of >= 2 doubles, the target of the per-sweep
 // convergence norms and of the sweep count (required).  The whole-device
 // forms stop when the off-diagonal Frobenius norm is <= tol |A|_F and, if
@@ -368,8 +369,13 @@ hipError_t select_scale_cols(int64_t n, int64_t ncq, const double* Q, const int3
 // element can be from an eigenvalue, for decisions against a fixed
 // threshold), or when it no longer decreases (the round-off floor).
 constexpr int JACOBI_WG_AUTO = 64;   // largest n solved by one workgroup (LDS form) by default
-constexpr int JACOBI_STEP1_MAX = 512;   // largest n for which the one-launch-per-step form pays
-inline int64_t jacobi_ws_doubles(int64_t n) { return 4 * n + 16 + 2 * 256; }
+constexpr int JACOBI_BLOCK_MIN = 65;   // smallest n the block form takes by default
+// pairs of 16-index blocks of the block form (its rotations: 1024 doubles each)
+inline int64_t bjac_pairs(int64_t n) {
+  const int64_t nb = (n + 15) / 16;
+  return (nb + (nb & 1)) / 2;
+}
+inline int64_t jacobi_ws_doubles(int64_t n) { return 4 * n + 16 + 2 * 256 + 1024 * bjac_pairs(n); }
 hipError_t jacobi_eigh(int n, double* A, double* V, double* ws, int max_sweeps, double tol,
                        hipStream_t s, int* sweeps_done, int method, double* A2, double* hpin,
                        double abs_tol = 0.0);

@@ -73,11 +73,13 @@ def test_debug_eigh_matches_numpy(dev):
 
 
 @pytest.mark.parametrize("method,sizes", [(1, (1, 2, 7, 33, 64)), (2, (2, 7, 64, 101, 300)),
-                                          (3, (2, 7, 64, 101, 257)), (4, (1, 2, 3, 7, 64, 101, 257))])
+                                          (3, (2, 7, 64, 101, 257)), (4, (1, 2, 3, 7, 64, 101, 257)),
+                                          (5, (1, 2, 7, 16, 17, 64, 101, 257, 600))])
 def test_debug_eigh_methods_match_numpy(dev, method, sizes):
     """every form of the Jacobi solver (LDS workgroup, global-memory workgroup,
-    whole-device launch pairs, one whole-device launch per step) on the sizes
-    it takes, odd and even"""
+    whole-device launch pairs, one whole-device launch per step, block Jacobi
+    over 16-index blocks) on the sizes it takes, odd and even, one block and
+    a ragged last block"""
     from paper_1606_01273_amd import lib
     rng = np.random.default_rng(2)
     for n in sizes:
@@ -95,15 +97,17 @@ def test_debug_eigh_methods_match_numpy(dev, method, sizes):
         _ok(np.abs(Vn.T @ Vn - np.eye(n)).max(), 1e-12, f"eigh orthonormality n={n} method {method}")
 
 
-@pytest.mark.parametrize("n", [300, 1000, 2048])
-def test_eigh_rank_deficient_near_threshold(dev, n):
+@pytest.mark.parametrize("n,method", [(300, 0), (1000, 0), (2048, 0), (300, 5), (1000, 5), (2048, 3)])
+def test_eigh_rank_deficient_near_threshold(dev, n, method):
     """Block metrics are rank deficient (the functions of Eq. 8 are linearly
     dependent) and their eigenvalues are cut at an absolute 1e-9 (Sec. II.B);
     the largest metrics of the full workload are 2048 x 2048.  Half of the
     spectrum is an exact null space, eight eigenvalues lie between 0.3e-9 and
     3e-9, the rest spread over 1e-8..10.  The set-up's solver (form by size,
     absolute stopping bound 0.1 of the threshold) keeps exactly the
-    eigenvalues numpy keeps, and matches numpy's eigenvalues near the cut."""
+    eigenvalues numpy keeps, and matches numpy's eigenvalues near the cut;
+    so do the block form and the scalar launch-pair form where the rule picks
+    the other."""
     from paper_1606_01273_amd import lib
     rng = np.random.default_rng(n)
     Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
@@ -120,9 +124,9 @@ def test_eigh_rank_deficient_near_threshold(dev, n):
     sw = ctypes.c_int32()
     thresh = 1e-9
     assert lib().caspt2_debug_eigh_abs(n, ta.data_ptr(), w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                                       V.data_ptr(), 0, 0.1 * thresh, ctypes.byref(sw)) == 0
+                                       V.data_ptr(), method, 0.1 * thresh, ctypes.byref(sw)) == 0
     ws = np.sort(w)
-    print(f"  n={n}: {sw.value} sweeps", flush=True)
+    print(f"  n={n} method {method}: {sw.value} sweeps", flush=True)
     assert int((ws >= thresh).sum()) == int((ref >= thresh).sum()) == n - nz - 4, "kept count"
     near = (ref > 1e-10) & (ref < 1e-8)
     assert int(near.sum()) == 8
