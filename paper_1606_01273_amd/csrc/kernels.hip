@@ -1288,78 +1288,106 @@ constexpr int BJ_B = 16, BJ_P = 2 * BJ_B, BJ_INNER = 2;
 // local index l (0 .. BJ_P - 1) of the pair (I, J) -> global index
 __device__ inline int bj_index(int l, int I, int J) { return l < BJ_B ? I * BJ_B + l : J * BJ_B + (l - BJ_B); }
 
+// 1/x for a normal x: the hardware estimate and two Newton steps
+__device__ inline double bj_rcp(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-x, y, 1.0);
+  return fma(y, e, y);
+}
+
+// 1/sqrt(x) for x in [1, 2]: the hardware estimate and two Newton steps
+__device__ inline double bj_rsq(double x) {
+  const double h = 0.5 * x;
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * fma(-h * y, y, 1.5);
+  return y * fma(-h * y, y, 1.5);
+}
+
+// Jacobi rotation (c, s) that annihilates apq, t = tan(theta) the root of
+// t^2 + 2 tau t - 1 = 0 of smaller magnitude, tau = (aqq - app) / (2 apq),
+// written in |aqq - app| and 2 |apq| scaled by their maximum so that every
+// intermediate stays in [1, 2.5] (no overflow for a tiny apq, no IEEE
+// divide or square root: hardware estimates refined by Newton steps); an
+// |apq| below 1e-290 (or NaN) gives no rotation.  Straight-line code, so that
+// the two rotations a thread needs are computed side by side.
+__device__ inline void bj_rotation(double app, double aqq, double apq, double& c, double& s) {
+  const double d = aqq - app, b = 2.0 * apq;
+  const bool skip = !(fabs(b) >= 1e-290);
+  const double bs = skip ? 1.0 : b;
+  const double rm = bj_rcp(fmax(fabs(d), fabs(bs)));
+  const double d1 = fabs(d) * rm, b1 = fabs(bs) * rm;   // the larger is 1
+  const double q = fma(d1, d1, b1 * b1);                // [1, 2]
+  const double tt = b1 * bj_rcp(d1 + q * bj_rsq(q));   // |t| <= 1
+  const double t = ((d < 0.0) != (bs < 0.0) && d != 0.0) ? -tt : tt;   // sign of tau, + for tau = 0
+  const double cc = bj_rsq(fma(t, t, 1.0));
+  c = skip ? 1.0 : cc;
+  s = skip ? 0.0 : t * cc;
+}
+
 // one workgroup per pair of blocks: R[k] (BJ_P x BJ_P, row-major) rotates the
 // pair's local indices; indices >= n are left alone (zero rows and columns,
-// identity in R)
-constexpr int BJ_SOLVE_THREADS = 256;
-__global__ __launch_bounds__(BJ_SOLVE_THREADS) void k_bjac_solve(int n, int mb, int step, const double* __restrict__ A,
-                                                   double* __restrict__ R) {
-  __shared__ double S[BJ_P][BJ_P + 1], Q[BJ_P][BJ_P + 1];
-  __shared__ double cs[BJ_B][2];
-  __shared__ int pq[BJ_B][2];
+// identity in R).  Thread (a, b) owns the 2 x 2 block of S at the index pairs
+// a and b of the inner step and the entries (b, a), (b + BJ_B, a) of Q's
+// column pairs; it computes the two rotations itself (the 16 threads that
+// need a rotation compute the same one) from the previous S, and writes the
+// next S to the other buffer: one barrier per inner step.
+constexpr int BJ_SOLVE_THREADS = BJ_B * BJ_B;
+__global__ __launch_bounds__(BJ_SOLVE_THREADS) void k_bjac_solve(int n, int mb, int step,
+                                                                 const double* __restrict__ A,
+                                                                 double* __restrict__ R) {
+  __shared__ double S[2][BJ_P][BJ_P + 1], Q[BJ_P][BJ_P + 1];
   __shared__ int perm[BJ_P];
   __shared__ double dg[BJ_P];
   const int t = threadIdx.x, k = blockIdx.x;
+  const int a = t / BJ_B, b = t % BJ_B;
   int I, J;
   jac_pair(k, step, mb, I, J);
   for (int e = t; e < BJ_P * BJ_P; e += blockDim.x) {
     const int r = e / BJ_P, c = e % BJ_P;
     const int gr = bj_index(r, I, J), gc = bj_index(c, I, J);
-    S[r][c] = (gr < n && gc < n) ? A[(int64_t)gr * n + gc] : 0.0;
+    S[0][r][c] = (gr < n && gc < n) ? A[(int64_t)gr * n + gc] : 0.0;
     Q[r][c] = r == c ? 1.0 : 0.0;
   }
   if (t < BJ_P) perm[t] = t;
   __syncthreads();
+  int cur = 0;
   for (int sw = 0; sw < BJ_INNER; ++sw) {
     for (int st = 0; st < BJ_P - 1; ++st) {
-      if (t < BJ_B) {
-        int p, q;
-        jac_pair(t, st, BJ_P, p, q);
-        double c = 1.0, s = 0.0;
-        const double apq = S[p][q];
-        if (apq != 0.0) {
-          const double tau = (S[q][q] - S[p][p]) / (2.0 * apq);
-          const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-          c = 1.0 / sqrt(1.0 + tt * tt);
-          s = tt * c;
-        }
-        cs[t][0] = c;
-        cs[t][1] = s;
-        pq[t][0] = p;
-        pq[t][1] = q;
-      }
-      __syncthreads();
-      // the 2 x 2 blocks of S (each owned by one thread), then the rows of Q
-      for (int e = t; e < BJ_B * BJ_B; e += blockDim.x) {
-        const int a = e / BJ_B, b = e % BJ_B;
-        const int pa = pq[a][0], qa = pq[a][1], pb = pq[b][0], qb = pq[b][1];
-        const double ca = cs[a][0], sa = cs[a][1], cb = cs[b][0], sb = cs[b][1];
-        const double m00 = S[pa][pb], m01 = S[pa][qb], m10 = S[qa][pb], m11 = S[qa][qb];
-        const double r00 = ca * m00 - sa * m10, r01 = ca * m01 - sa * m11;
-        const double r10 = sa * m00 + ca * m10, r11 = sa * m01 + ca * m11;
-        S[pa][pb] = cb * r00 - sb * r01;
-        S[pa][qb] = sb * r00 + cb * r01;
-        S[qa][pb] = cb * r10 - sb * r11;
-        S[qa][qb] = sb * r10 + cb * r11;
-      }
-      for (int e = t; e < BJ_P * BJ_B; e += blockDim.x) {
-        const int i = e / BJ_B, a = e % BJ_B;
-        const int pa = pq[a][0], qa = pq[a][1];
-        const double ca = cs[a][0], sa = cs[a][1];
+      int pa, qa, pb, qb;
+      jac_pair(a, st, BJ_P, pa, qa);
+      jac_pair(b, st, BJ_P, pb, qb);
+      const double(*Sc)[BJ_P + 1] = S[cur];
+      double(*Sn)[BJ_P + 1] = S[cur ^ 1];
+      double ca, sa, cb, sb;
+      bj_rotation(Sc[pa][pa], Sc[qa][qa], Sc[pa][qa], ca, sa);
+      bj_rotation(Sc[pb][pb], Sc[qb][qb], Sc[pb][qb], cb, sb);
+      const double m00 = Sc[pa][pb], m01 = Sc[pa][qb], m10 = Sc[qa][pb], m11 = Sc[qa][qb];
+      const double r00 = ca * m00 - sa * m10, r01 = ca * m01 - sa * m11;
+      const double r10 = sa * m00 + ca * m10, r11 = sa * m01 + ca * m11;
+      Sn[pa][pb] = cb * r00 - sb * r01;
+      Sn[pa][qb] = sb * r00 + cb * r01;
+      Sn[qa][pb] = cb * r10 - sb * r11;
+      Sn[qa][qb] = sb * r10 + cb * r11;
+#pragma unroll
+      for (int i = b; i < BJ_P; i += BJ_B) {
         const double vp = Q[i][pa], vq = Q[i][qa];
         Q[i][pa] = ca * vp - sa * vq;
         Q[i][qa] = sa * vp + ca * vq;
       }
+      cur ^= 1;
       __syncthreads();
     }
   }
+  const double(*Sf)[BJ_P + 1] = S[cur];
+  double(*Sw)[BJ_P + 1] = S[cur ^ 1];   // free: the Q^T Q product below
   // one Newton-Schulz step towards the nearest orthogonal matrix, Q <- Q (3 -
   // Q^T Q) / 2: the accumulated rotations are orthogonal only to a few ulps,
   // with a bias of one sign on the diagonal of Q^T Q, and A and V take one
   // such Q per step (hundreds per solve), which would otherwise add up to
   // a drift of the eigenvalues well above the stopping bound
-  if (t < BJ_P) dg[t] = S[t][t];
-  __syncthreads();
+  if (t < BJ_P) dg[t] = Sf[t][t];
   {
     constexpr int RS = BJ_SOLVE_THREADS / BJ_P, OPT = BJ_P / RS;   // row stride, outputs per thread
     const int j = t % BJ_P, i0 = t / BJ_P;
@@ -1372,13 +1400,13 @@ __global__ __launch_bounds__(BJ_SOLVE_THREADS) void k_bjac_solve(int n, int mb, 
       acc[m] = g;
     }
 #pragma unroll
-    for (int m = 0; m < OPT; ++m) S[i0 + RS * m][j] = acc[m];   // Q^T Q over S (its diagonal kept in dg)
+    for (int m = 0; m < OPT; ++m) Sw[i0 + RS * m][j] = acc[m];
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < OPT; ++m) {
       const int i = i0 + RS * m;
       double g = 0.0;
-      for (int c = 0; c < BJ_P; ++c) g += Q[i][c] * S[c][j];
+      for (int c = 0; c < BJ_P; ++c) g += Q[i][c] * Sw[c][j];
       acc[m] = 1.5 * Q[i][j] - 0.5 * g;
     }
     __syncthreads();
