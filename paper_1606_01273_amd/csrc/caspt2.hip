@@ -298,6 +298,7 @@ struct caspt2_handle {
   bool direct[NBLOCK] = {};                            // ket read from packed rows (no all-orderings x)
   std::vector<char> ccvv_fused;                        // per set: up terms into ccvv run as packed-row passes
   IBuf ccvv_groups;                                    // workgroup table of the virtual-pair pass
+  IBuf cavv_groups;                                    // the same groups, b-major in per-XCD runs
   int64_t ccvv_ngroups = 0;
   int64_t ccvv_woff[CK_N] = {};                        // offsets of the W products in ccvv_w (-1: absent)
   DBuf ccvv_w, ccvv_w2;                                // W products of the ccav and caav terms (both work sets)
@@ -1405,6 +1406,10 @@ void classify_ccvv_terms(H& h) {
   h.ccvv_groups.alloc(h.ccvv_ngroups);
   HIPCHECK(hipMemcpyAsync(h.ccvv_groups.p, groups.data(), groups.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
                           h.s));
+  const std::vector<uint32_t> bgroups = ccvv_up_groups(h.nv, true);
+  h.cavv_groups.alloc(h.ccvv_ngroups);
+  HIPCHECK(hipMemcpyAsync(h.cavv_groups.p, bgroups.data(), bgroups.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
+                          h.s));
   host_sync(h);
 }
 
@@ -1876,7 +1881,7 @@ void cavv_pass(H& h, int set, const T* x, T* sig) {
     c.fCV_stride = h.nmo;
   }
   if (!down && !downb && !downc) c.xp = c.xm = nullptr;
-  HIPCHECK(cavv_pass_apply<T>(c, reinterpret_cast<const uint32_t*>(h.ccvv_groups.p), h.ccvv_ngroups, h.s));
+  HIPCHECK(cavv_pass_apply<T>(c, reinterpret_cast<const uint32_t*>(h.cavv_groups.p), h.ccvv_ngroups, h.s));
   if (down)
     for (int k = 0; k < 2; ++k) {
       if (!sa[k]) continue;

@@ -782,10 +782,25 @@ bool ccvv_up_supported(int nc, int nv, int ncol, int ny, int nak) {
   return true;
 }
 
-std::vector<uint32_t> ccvv_up_groups(int nv) {
+std::vector<uint32_t> ccvv_up_groups(int nv, bool b_major) {
   std::vector<uint32_t> g;
-  for (int a = 0; a < nv; ++a)
-    for (int b0 = 0; b0 <= a; b0 += CUA_NB) g.push_back((uint32_t)a << 16 | (uint32_t)b0);
+  if (!b_major) {
+    for (int a = 0; a < nv; ++a)
+      for (int b0 = 0; b0 <= a; b0 += CUA_NB) g.push_back((uint32_t)a << 16 | (uint32_t)b0);
+    return g;
+  }
+  // b0 outermost, and workgroup g (dispatched to XCD g % 8) takes entry
+  // start(g % 8) + g / 8 of that list: each XCD runs a contiguous run of
+  // groups sharing b0, so rows indexed by the b of a pair stay in its L2
+  std::vector<uint32_t> list;
+  for (int b0 = 0; b0 < nv; b0 += CUA_NB)
+    for (int a = b0; a < nv; ++a) list.push_back((uint32_t)a << 16 | (uint32_t)b0);
+  const int64_t n = (int64_t)list.size(), q = n / 8, r = n % 8;
+  g.resize(list.size());
+  for (int64_t k = 0; k < n; ++k) {
+    const int64_t x = k % 8;
+    g[k] = list[x * q + std::min<int64_t>(x, r) + k / 8];
+  }
   return g;
 }
 

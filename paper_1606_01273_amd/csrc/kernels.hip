@@ -879,8 +879,6 @@ hipError_t df_pack(const double* B, int naux, int nmo, int p0, int np, int q0, i
 __global__ void k_term_source(TermDesc d, const double* __restrict__ C, const double* __restrict__ G,
                               double* __restrict__ out) {
   const int64_t total = d.nrow * d.nalpha;
-  int64_t ny = 1;
-  for (int k = 0; k < d.nopact; ++k) ny *= d.na;
   for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
        g += (int64_t)gridDim.x * blockDim.x) {
     const int64_t row = g / d.nalpha;
@@ -906,21 +904,29 @@ __global__ void k_term_source(TermDesc d, const double* __restrict__ C, const do
           sg *= d.chi[s];
         }
       if (dup) continue;
+      // C offset: the slot part, and the stride of each summed active label
+      int64_t base = 0, ls[3] = {0, 0, 0};
+      for (int a = 0; a < d.ncax; ++a) {
+        const int src = d.c_slot[a];
+        if (src >= 0) base += (int64_t)e[src] * d.c_stride[a];
+        else ls[-1 - src] += d.c_stride[a];
+      }
+      // y = (y0 na + y1) na + y2 (labels past nopact fixed at 0) in
+      // ascending order, the offsets advanced by additions
+      const int n0 = d.nopact >= 1 ? d.na : 1, n1 = d.nopact >= 2 ? d.na : 1, n2 = d.nopact >= 3 ? d.na : 1;
+      const int64_t gstep = d.galpha * d.gcols;
+      const double* gp = G + (d.goff + al) * d.gcols + d.gcol;
       double val = 0.0;
-      for (int64_t y = 0; y < ny; ++y) {
-        int yi[3] = {0, 0, 0};
-        int64_t yr = y;
-        for (int k = d.nopact - 1; k >= 0; --k) {
-          yi[k] = (int)(yr % d.na);
-          yr /= d.na;
+      int64_t o0 = base;
+      for (int y0 = 0; y0 < n0; ++y0, o0 += ls[0]) {
+        int64_t o1 = o0;
+        for (int y1 = 0; y1 < n1; ++y1, o1 += ls[1]) {
+          int64_t o2 = o1;
+          for (int y2 = 0; y2 < n2; ++y2, o2 += ls[2]) {
+            val += C[o2] * *gp;
+            gp += gstep;
+          }
         }
-        int64_t off = 0;
-        for (int a = 0; a < d.ncax; ++a) {
-          const int src = d.c_slot[a];
-          const int v = src >= 0 ? e[src] : yi[-1 - src];
-          off += (int64_t)v * d.c_stride[a];
-        }
-        val += C[off] * G[(y * d.galpha + d.goff + al) * d.gcols + d.gcol];
       }
       acc += sg * val;
     }

@@ -258,7 +258,9 @@ bool ccvv_up_supported(int nc, int nv, int ncol, int ny, int nak);
 constexpr int VPAIR_GROUP = 3;
 // workgroup table of the virtual-pair passes: a << 16 | b0 per group of
 // VPAIR_GROUP pairs (a, b0 ..)
-std::vector<uint32_t> ccvv_up_groups(int nv);
+// b_major: b0 outermost, in per-XCD runs (the cavv pass reads rows of the
+// pair's second index); else a outermost
+std::vector<uint32_t> ccvv_up_groups(int nv, bool b_major = false);
 template <typename T>
 hipError_t ccvv_up_apply(const CcvvUpArgs<T>& p, const uint32_t* groups, int64_t ngroups, hipStream_t s);
 
