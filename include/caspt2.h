@@ -156,6 +156,21 @@ typedef struct caspt2_handle caspt2_handle;
  * E_DEVICE, E_INDEFINITE (a denominator <= 0 for some state). */
 CASPT2_API int caspt2_create(const caspt2_dims* dims, const caspt2_inputs* inputs, int inputs_on_device,
                   void* stream, caspt2_handle** out);
+
+/* Set up n problems as caspt2_create does, nthreads at a time on host
+ * threads of the library (each creation is latency-bound: small launches,
+ * host synchronisations, the term engine; several overlap on the device).
+ * dims, inputs, streams, out and status are arrays of n; problem k runs on
+ * streams[k] (a hipStream_t the caller keeps alive for the handle's life;
+ * distinct streams let the creations overlap, a shared stream serialises
+ * them) on the caller's current device.  status[k] receives caspt2_create's
+ * code for problem k and out[k] its handle (NULL on failure; the others are
+ * still created).  Returns the first failing status in k order, or OK; the
+ * message of that failure is then caspt2_last_error's on the calling
+ * thread.  E_ARG for n < 1, nthreads < 1 or a NULL array. */
+CASPT2_API int caspt2_create_many(int32_t n, const caspt2_dims* dims, const caspt2_inputs* inputs,
+                                  int inputs_on_device, void* const* streams, int32_t nthreads,
+                                  caspt2_handle** out, int32_t* status);
 CASPT2_API int caspt2_destroy(caspt2_handle* h);
 
 /* Switch the arithmetic of later solves (CASPT2_FP64 or CASPT2_MIXED) on an

@@ -30,6 +30,16 @@ def _ptr(t) -> int:
     return int(t.data_ptr())
 
 
+def _marshal(nclosed, nact, nvirt, naux, nstates, nelec, fock, hcore, dfB, ci, eref, shift, scheme, xms, thresh,
+             precision):
+    """caspt2_dims and caspt2_inputs of one problem, and the host arrays the
+    inputs point to (to be kept alive until the creation returns)."""
+    d = _lib.Dims(nclosed, nact, nvirt, naux, nstates, nelec, scheme, 1 if xms else 0, int(precision), 0,
+                  float(shift), float(thresh))
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (fock, hcore, dfB, ci, eref)]
+    return d, _lib.Inputs(*[a.ctypes.data for a in arrs]), arrs
+
+
 def _check(rc: int, where: str, allow=(OK,)):
     if rc not in allow:
         L = lib()
@@ -45,27 +55,69 @@ class Caspt2:
                  shift=0.0, scheme=MSMR, xms=True, thresh=1e-9, precision=FP64, stream=None):
         import torch
         L = lib()
-        self.nst = nstates
-        self.nc, self.na, self.nv = nclosed, nact, nvirt
-        self.nmo = nclosed + nact + nvirt
-        d = _lib.Dims(nclosed, nact, nvirt, naux, nstates, nelec, scheme, 1 if xms else 0, int(precision), 0,
-                      float(shift), float(thresh))
-        arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (fock, hcore, dfB, ci, eref)]
-        inp = _lib.Inputs(*[a.ctypes.data for a in arrs])
+        d, inp, keep = _marshal(nclosed, nact, nvirt, naux, nstates, nelec, fock, hcore, dfB, ci, eref,
+                                shift, scheme, xms, thresh, precision)
         if stream is None:
             stream = torch.cuda.current_stream()
-        self._stream = stream
         h = ctypes.c_void_p()
         _check(L.caspt2_create(ctypes.byref(d), ctypes.byref(inp), 0, ctypes.c_void_p(stream.cuda_stream),
                                ctypes.byref(h)), "caspt2_create")
+        del keep
+        self._attach(h, nstates, nclosed, nact, nvirt, stream)
+
+    def _attach(self, h, nstates, nclosed, nact, nvirt, stream):
+        self.nst = nstates
+        self.nc, self.na, self.nv = nclosed, nact, nvirt
+        self.nmo = nclosed + nact + nvirt
+        self._stream = stream
         self._h = h
-        self.length = int(L.caspt2_vector_length(h))
+        self.length = int(lib().caspt2_vector_length(h))
 
     @classmethod
     def from_problem(cls, prob, scheme=MSMR, xms=True, thresh=1e-9, **kw):
         return cls(prob.nc, prob.na, prob.nv, prob.naux, prob.nst, prob.nelec, prob.fock, prob.hcore,
                    prob.B, prob.ci, prob.eref, shift=prob.shift, scheme=scheme, xms=xms,
                    thresh=thresh, **kw)
+
+    @classmethod
+    def create_many(cls, probs, threads=8, streams=None, scheme=MSMR, xms=True, thresh=1e-9, precision=FP64):
+        """Set up every problem of probs (objects with the fields from_problem
+        reads) with caspt2_create_many, `threads` creations at a time on the
+        library's host threads; problem k runs on streams[k] (default: one new
+        stream per thread, assigned round-robin).  Returns the handles in
+        order; raises on the first failed problem (the others are released)."""
+        import torch
+        L = lib()
+        n = len(probs)
+        if n == 0:
+            return []
+        if streams is None:
+            pool = [torch.cuda.Stream() for _ in range(max(1, min(threads, n)))]
+            streams = [pool[k % len(pool)] for k in range(n)]
+        ds = (_lib.Dims * n)()
+        ins = (_lib.Inputs * n)()
+        keep = []
+        for k, p in enumerate(probs):
+            d, inp, kp = _marshal(p.nc, p.na, p.nv, p.naux, p.nst, p.nelec, p.fock, p.hcore, p.B, p.ci, p.eref,
+                                  p.shift, scheme, xms, thresh, precision)
+            ds[k], ins[k] = d, inp
+            keep.append(kp)
+        sp = (ctypes.c_void_p * n)(*[s.cuda_stream for s in streams])
+        hs = (ctypes.c_void_p * n)()
+        st = (ctypes.c_int32 * n)()
+        rc = L.caspt2_create_many(n, ds, ins, 0, sp, int(threads), hs, st)
+        del keep
+        if rc != OK:
+            for k in range(n):
+                if hs[k]:
+                    L.caspt2_destroy(ctypes.c_void_p(hs[k]))
+            _check(rc, "caspt2_create_many")
+        out = []
+        for k, p in enumerate(probs):
+            g = cls.__new__(cls)
+            g._attach(ctypes.c_void_p(hs[k]), p.nst, p.nc, p.na, p.nv, streams[k])
+            out.append(g)
+        return out
 
     def close(self):
         if getattr(self, "_h", None):

@@ -49,6 +49,9 @@ _D = ctypes.POINTER(ctypes.c_double)
 SIGNATURES = {
     "caspt2_create": (ctypes.c_int, [ctypes.POINTER(Dims), ctypes.POINTER(Inputs), ctypes.c_int, _P,
                                      ctypes.POINTER(_P)]),
+    "caspt2_create_many": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(Dims), ctypes.POINTER(Inputs), ctypes.c_int,
+                                          ctypes.POINTER(_P), ctypes.c_int32, ctypes.POINTER(_P),
+                                          ctypes.POINTER(ctypes.c_int32)]),
     "caspt2_destroy": (ctypes.c_int, [_P]),
     "caspt2_set_precision": (ctypes.c_int, [_P, ctypes.c_int32]),
     "caspt2_set_streams": (ctypes.c_int, [_P, ctypes.c_int32]),

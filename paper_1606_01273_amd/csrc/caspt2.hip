@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cstdlib>
 #include <cmath>
@@ -15,6 +16,7 @@
 #include <mutex>
 #include <stdexcept>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/caspt2.h"
@@ -40,6 +42,73 @@ struct DevError : std::runtime_error {
                      std::string(#expr) + ": " + hipGetErrorString(_e));                 \
   } while (0)
 
+// Device blocks freed while a handle is being created are kept for the
+// allocations that follow in the same creation instead of going back through
+// hipFree, which waits for the whole device (a creation allocates and frees
+// a few thousand temporaries: for the small problems of a batch that cost
+// more than their kernels).  Every launch of a creation is ordered on the
+// handle's one stream, so a block is reused only by work queued after the
+// work that used it.  Sizes up to 4 MB are rounded to powers of two so that
+// blocks of neighbouring sizes are shared, larger ones to 256 KB.  The cache
+// belongs to one creation on one thread; the creation returns its blocks at
+// its end (or when it throws), after its last synchronisation.
+struct BlockCache {
+  std::multimap<size_t, void*> blocks;
+  size_t held = 0;
+  static constexpr size_t CAP = size_t(8) << 30;   // beyond this, freed blocks go back at once
+  ~BlockCache() {
+    for (auto& kv : blocks) (void)hipFree(kv.second);
+  }
+};
+thread_local BlockCache* t_block_cache = nullptr;
+
+size_t block_class(size_t bytes) {
+  if (bytes <= (size_t(4) << 20)) {
+    size_t c = 256;
+    while (c < bytes) c <<= 1;
+    return c;
+  }
+  const size_t g = size_t(256) << 10;
+  return (bytes + g - 1) / g * g;
+}
+
+void* dev_alloc(size_t bytes) {
+  void* p = nullptr;
+  if (BlockCache* c = t_block_cache) {
+    bytes = block_class(bytes);
+    auto it = c->blocks.find(bytes);
+    if (it != c->blocks.end()) {
+      p = it->second;
+      c->blocks.erase(it);
+      c->held -= bytes;
+      return p;
+    }
+  }
+  HIPCHECK(hipMalloc(&p, bytes));
+  return p;
+}
+
+void dev_free(void* p, size_t bytes) {
+  if (!p) return;
+  BlockCache* c = t_block_cache;
+  if (c && c->held + block_class(bytes) <= BlockCache::CAP) {
+    c->blocks.emplace(block_class(bytes), p);
+    c->held += block_class(bytes);
+    return;
+  }
+  (void)hipFree(p);
+}
+
+// the block cache of one creation on this thread (restores the previous one)
+struct BlockCacheScope {
+  BlockCache cache;
+  BlockCache* prev;
+  BlockCacheScope() : prev(t_block_cache) { t_block_cache = &cache; }
+  ~BlockCacheScope() { t_block_cache = prev; }
+  BlockCacheScope(const BlockCacheScope&) = delete;
+  BlockCacheScope& operator=(const BlockCacheScope&) = delete;
+};
+
 // owning device buffer
 template <typename T>
 struct DevBuf {
@@ -49,14 +118,14 @@ struct DevBuf {
   explicit DevBuf(int64_t n_) { alloc(n_); }
   void alloc(int64_t n_) {
     release();
+    if (n_ > 0) p = static_cast<T*>(dev_alloc((size_t)n_ * sizeof(T)));
     n = n_;
-    if (n > 0) HIPCHECK(hipMalloc(&p, (size_t)n * sizeof(T)));
   }
   void zero(hipStream_t s) {
     if (n > 0) HIPCHECK(hipMemsetAsync(p, 0, (size_t)n * sizeof(T), s));
   }
   void release() {
-    if (p) (void)hipFree(p);
+    dev_free(p, (size_t)n * sizeof(T));
     p = nullptr;
     n = 0;
   }
@@ -104,12 +173,15 @@ struct PinBuf {
 
 struct IBuf {
   int32_t* p = nullptr;
-  void alloc(int64_t n) {
-    if (p) (void)hipFree(p);
+  int64_t n = 0;
+  void alloc(int64_t n_) {
+    dev_free(p, (size_t)n * sizeof(int32_t));
     p = nullptr;
-    if (n > 0) HIPCHECK(hipMalloc(&p, (size_t)n * sizeof(int32_t)));
+    n = 0;
+    if (n_ > 0) p = static_cast<int32_t*>(dev_alloc((size_t)n_ * sizeof(int32_t)));
+    n = n_;
   }
-  ~IBuf() { if (p) (void)hipFree(p); }
+  ~IBuf() { dev_free(p, (size_t)n * sizeof(int32_t)); }
 };
 
 int64_t ipow(int64_t b, int e) {
@@ -3517,6 +3589,7 @@ int caspt2_create(const caspt2_dims* dims, const caspt2_inputs* in, int on_devic
   std::unique_ptr<caspt2_handle> hp(new caspt2_handle());
   H& h = *hp;
   ABI_GUARD({
+    BlockCacheScope cache;   // temporaries of this creation reuse each other's blocks
     h.d = *dims;
     h.s = (hipStream_t)stream;
     h.verbose = std::getenv("CASPT2_VERBOSE") != nullptr;
@@ -3636,6 +3709,43 @@ int caspt2_create(const caspt2_dims* dims, const caspt2_inputs* in, int on_devic
     *out = hp.release();
     return CASPT2_OK;
   })
+}
+
+int caspt2_create_many(int32_t n, const caspt2_dims* dims, const caspt2_inputs* inputs, int inputs_on_device,
+                       void* const* streams, int32_t nthreads, caspt2_handle** out, int32_t* status) {
+  if (n < 1 || nthreads < 1 || !dims || !inputs || !streams || !out || !status) return CASPT2_E_ARG;
+  for (int k = 0; k < n; ++k) {
+    out[k] = nullptr;
+    status[k] = CASPT2_E_STATE;
+  }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return CASPT2_E_DEVICE;
+  std::atomic<int> next(0);
+  std::vector<std::string> msg(n);
+  auto worker = [&]() {
+    if (hipSetDevice(dev) != hipSuccess) return;   // a new thread starts on device 0
+    for (int k; (k = next.fetch_add(1)) < n;) {
+      status[k] = caspt2_create(&dims[k], &inputs[k], inputs_on_device, streams[k], &out[k]);
+      if (status[k] != CASPT2_OK) msg[k] = g_last_error;
+    }
+  };
+  std::vector<std::thread> pool;
+  const int nt = std::min(nthreads, n);
+  try {
+    for (int t = 0; t < nt; ++t) pool.emplace_back(worker);
+  } catch (const std::exception& ex) {   // fewer threads than asked: the started ones take every problem
+    if (pool.empty()) {
+      g_last_error = ex.what();
+      return CASPT2_E_DEVICE;
+    }
+  }
+  for (auto& t : pool) t.join();
+  for (int k = 0; k < n; ++k)
+    if (status[k] != CASPT2_OK) {
+      g_last_error = msg[k].empty() ? "problem " + std::to_string(k) + " not created" : msg[k];
+      return status[k];
+    }
+  return CASPT2_OK;
 }
 
 int caspt2_destroy(caspt2_handle* h) {

@@ -1,0 +1,93 @@
+"""Concurrent set-up (caspt2_create_many): problems created several at a time
+on the library's host threads give the handles one-at-a-time creation gives.
+
+The creations share nothing but the device (each has its own stream and its
+own cache of freed device blocks), so every handle must reproduce the one
+caspt2_create makes for the same problem: the residual of every state on the
+same trial vector is compared bit for bit, with and without the source, for
+an uneven set of problems (both readings, 1-4 states) created four at a time
+on four streams and all on one shared stream.  A problem the library rejects
+(more than 16 states) fails alone: its status is E_ARG, the other
+handles are created, and the call returns that status."""
+import ctypes
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from synth.gen import batch_sizes, make_problem, random_vector  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1606_01273_amd import lib
+    lib()
+    return torch.device("cuda")
+
+
+def _problems():
+    out = []
+    for k, (nc, na, nv, nx, ns, sd) in enumerate(batch_sizes(10, seed=11)):
+        nv = min(nv, 40)
+        out.append(make_problem(nc, na, nv, 3 * (nc + na + nv), ns, seed=sd, reading="AB"[k % 2], shift=0.2))
+    return out
+
+
+@pytest.mark.parametrize("shared", [False, True])
+def test_create_many_matches_create(dev, shared):
+    from paper_1606_01273_amd import Caspt2
+    probs = _problems()
+    print(f"{len(probs)} problems, shared stream {shared}", flush=True)
+    ref = [Caspt2.from_problem(p) for p in probs]
+    streams = [torch.cuda.current_stream()] * len(probs) if shared else None
+    got = Caspt2.create_many(probs, threads=4, streams=streams)
+    torch.cuda.synchronize()
+    for k, (g0, g1) in enumerate(zip(ref, got)):
+        assert g0.length == g1.length
+        x = torch.tensor(random_vector(g0.length, 100 + k), device=dev)
+        for st in range(g0.nst):
+            for src in (True, False):
+                s0 = torch.empty_like(x)
+                s1 = torch.empty_like(x)
+                g0.residual(st, x, s0, with_source=src)
+                g1.residual(st, x, s1, with_source=src)
+                torch.cuda.synchronize()
+                assert torch.equal(s0, s1), f"problem {k} state {st} source {src}"
+    for g in ref + got:
+        g.close()
+
+
+def test_create_many_reports_a_rejected_problem(dev):
+    from paper_1606_01273_amd import E_ARG, lib
+    from paper_1606_01273_amd import _lib as raw
+    from paper_1606_01273_amd import _marshal
+    L = lib()
+    probs = _problems()[:3]
+    n = len(probs)
+    ds = (raw.Dims * n)()
+    ins = (raw.Inputs * n)()
+    keep = []
+    for k, p in enumerate(probs):
+        nst = p.nst if k != 1 else 17   # rejected before any input is read
+        d, inp, kp = _marshal(p.nc, p.na, p.nv, p.naux, nst, p.nelec, p.fock, p.hcore, p.B, p.ci, p.eref,
+                              p.shift, 0, True, 1e-9, 0)
+        ds[k], ins[k] = d, inp
+        keep.append(kp)
+    s = torch.cuda.current_stream().cuda_stream
+    sp = (ctypes.c_void_p * n)(*([s] * n))
+    hs = (ctypes.c_void_p * n)()
+    st = (ctypes.c_int32 * n)()
+    rc = L.caspt2_create_many(n, ds, ins, 0, sp, 2, hs, st)
+    assert rc == E_ARG
+    assert list(st) == [0, E_ARG, 0]
+    assert hs[0] and hs[2] and not hs[1]
+    assert b"dimensions" in L.caspt2_last_error()
+    for k in (0, 2):
+        assert L.caspt2_destroy(ctypes.c_void_p(hs[k])) == 0
+    assert L.caspt2_create_many(0, ds, ins, 0, sp, 2, hs, st) == E_ARG
+    assert L.caspt2_create_many(n, ds, ins, 0, sp, 0, hs, st) == E_ARG
