@@ -1636,6 +1636,18 @@ void setup_couplings(H& h) {
 // an index-mapped expand or reduce with the Fock block), pack once per block.
 // (T = float in the inner solver of the mixed-precision mode: the
 // all-orderings buffers, sized for doubles, then hold floats.)
+// coupling GEMMs: FP64 products split over K (in the current work set's
+// split-K workspace) when they have few tiles; FP32 as gemm_t
+inline hipError_t gemm_c(H& h, bool nk, int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
+                         const double* B, int64_t ldb, double beta, double* C, int64_t ldc) {
+  DBuf& ws = h.ws_cur ? *h.ws_cur : h.splitk_ws;
+  return gemm_f64_ws(nk, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws.p, ws.n, h.s);
+}
+inline hipError_t gemm_c(H& h, bool nk, int64_t M, int64_t N, int64_t K, double alpha, const float* A, int64_t lda,
+                         const float* B, int64_t ldb, double beta, float* C, int64_t ldc) {
+  return gemm_t(nk, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, h.s);
+}
+
 // the current work set's buffers
 DBuf& xall_of(H& h, int b) { return h.wset ? h.xall2[b] : h.xall[b]; }
 DBuf& xperm_of(H& h, int b) { return h.wset ? h.xperm2[b] : h.xperm[b]; }
@@ -1712,8 +1724,7 @@ void couple_term(H& h, int set, const CoupleTerm& t, const T* x, int fuse) {
     HIPCHECK(couple_up_fused(t.d, f, (const T*)xk, nak, Sel<T>::G(t), sb, h.s));
   } else if (t.up) {
     const int64_t width = (int64_t)t.d.ny * nab;
-    HIPCHECK(gemm_t(true, all_rows(h, t.ket), width, nak, 1.0, xk, nak, Sel<T>::G(t), nak, 0.0, scratch, width,
-                    h.s));
+    HIPCHECK(gemm_c(h, true, all_rows(h, t.ket), width, nak, 1.0, xk, nak, Sel<T>::G(t), nak, 0.0, scratch, width));
     HIPCHECK(couple_expand(t.d, f, (const T*)scratch, sb, h.s, fuse == 0 ? 1 : fuse == 2 ? 2 : 0));
   } else {
     const int64_t width = (int64_t)t.d.ny * nak;
@@ -1728,8 +1739,8 @@ void couple_term(H& h, int set, const CoupleTerm& t, const T* x, int fuse) {
     if (nab <= 8 && width <= 8)
       HIPCHECK(rows_small_gemm(all_rows(h, t.bra), (int)nab, (int)width, (const T*)scratch, Sel<T>::G(t), sb, h.s));
     else
-      HIPCHECK(gemm_t(true, all_rows(h, t.bra), nab, width, 1.0, scratch, width, Sel<T>::G(t), width, 1.0, sb,
-                      nab, h.s));
+      HIPCHECK(gemm_c(h, true, all_rows(h, t.bra), nab, width, 1.0, scratch, width, Sel<T>::G(t), width, 1.0, sb,
+                      nab));
   }
 }
 
@@ -1753,8 +1764,8 @@ void ccvv_up_passes(H& h, int set, T* sig) {
     if (!t) continue;
     const int64_t nak = nalpha_of_block(h, set, t->ket);
     const int64_t width = (int64_t)t->d.ny * a.ncol;
-    HIPCHECK(gemm_t(true, all_rows(h, t->ket), width, nak, 1.0, reinterpret_cast<const T*>(xall_of(h, t->ket).p),
-                    nak, Sel<T>::G(*t), nak, 0.0, wbuf + h.ccvv_woff[k], width, h.s));
+    HIPCHECK(gemm_c(h, true, all_rows(h, t->ket), width, nak, 1.0, reinterpret_cast<const T*>(xall_of(h, t->ket).p),
+                    nak, Sel<T>::G(*t), nak, 0.0, wbuf + h.ccvv_woff[k], width));
   }
   auto W = [&](int k) { return tk[k] ? (const T*)(wbuf + h.ccvv_woff[k]) : nullptr; };
   const CoupleTerm* tA = tk[CK_CAVV1] ? tk[CK_CAVV1] : tk[CK_CAVV2];
@@ -1844,7 +1855,7 @@ void ccvv_down_pass(H& h, int set, const T* x, T* sig) {
     if (nab <= 8 && d.ncol <= 8)
       HIPCHECK(rows_small_gemm(rows, (int)nab, d.ncol, Yk, Sel<T>::G(*tk[k]), sb, h.s));
     else
-      HIPCHECK(gemm_t(true, rows, nab, d.ncol, 1.0, Yk, d.ncol, Sel<T>::G(*tk[k]), d.ncol, 1.0, sb, nab, h.s));
+      HIPCHECK(gemm_c(h, true, rows, nab, d.ncol, 1.0, Yk, d.ncol, Sel<T>::G(*tk[k]), d.ncol, 1.0, sb, nab));
   }
 }
 
@@ -1900,7 +1911,7 @@ void cavv_pass(H& h, int set, const T* x, T* sig) {
     for (int k = 0; k < 2; ++k) {
       if (!xa[k]) continue;
       T* Q = w + h.cavv_off[k];
-      HIPCHECK(gemm_t(true, ra[k], nq, naa, 1.0, xa[k], naa, cavv_gp(cg, 0, k, tag), naa, 0.0, Q, nq, h.s));
+      HIPCHECK(gemm_c(h, true, ra[k], nq, naa, 1.0, xa[k], naa, cavv_gp(cg, 0, k, tag), naa, 0.0, Q, nq));
       (k == 0 ? c.Qp : c.Qm) = Q;
     }
     c.fAC = h.fock.p + t->f_off;
@@ -1910,8 +1921,7 @@ void cavv_pass(H& h, int set, const T* x, T* sig) {
     const CoupleTerm* t = tr[CV_UB1] ? tr[CV_UB1] : tr[CV_UB2];
     for (int k = 0; k < 2; ++k) {
       T* B = w + h.cavv_off[2 + k];
-      HIPCHECK(gemm_t(true, h.nv, c.nak, naaav, 1.0, xaaav, naaav, cavv_gp(cg, 1, k, tag), naaav, 0.0, B, c.nak,
-                      h.s));
+      HIPCHECK(gemm_c(h, true, h.nv, c.nak, naaav, 1.0, xaaav, naaav, cavv_gp(cg, 1, k, tag), naaav, 0.0, B, c.nak));
       (k == 0 ? c.Bp : c.Bm) = B;
     }
     c.fVC = h.fock.p + t->f_off;
@@ -1922,7 +1932,7 @@ void cavv_pass(H& h, int set, const T* x, T* sig) {
     const CoupleTerm* t = tr[CV_UC1] ? tr[CV_UC1] : tr[CV_UC2];
     for (int k = 0; k < 2; ++k) {
       T* C = w + h.cavv_off[6 + k];
-      HIPCHECK(gemm_t(true, ncv, nq, ncaav, 1.0, xcaav, ncaav, cavv_gp(cg, 3, k, tag), ncaav, 0.0, C, nq, h.s));
+      HIPCHECK(gemm_c(h, true, ncv, nq, ncaav, 1.0, xcaav, ncaav, cavv_gp(cg, 3, k, tag), ncaav, 0.0, C, nq));
       (k == 0 ? c.Cp : c.Cm) = C;
     }
     c.fVA = h.fock.p + t->f_off;
@@ -1958,17 +1968,17 @@ void cavv_pass(H& h, int set, const T* x, T* sig) {
     for (int k = 0; k < 2; ++k) {
       if (!sa[k]) continue;
       const T* Z = k == 0 ? c.Zp : c.Zm;
-      HIPCHECK(gemm_t(true, ra[k], naa, nq, 1.0, Z, nq, cavv_gp(cg, 2, k, tag), nq, 1.0, sa[k], naa, h.s));
+      HIPCHECK(gemm_c(h, true, ra[k], naa, nq, 1.0, Z, nq, cavv_gp(cg, 2, k, tag), nq, 1.0, sa[k], naa));
     }
   // caav += [(G1 + G2) Sb + (G1 - G2) Db] / 2, aaav likewise with Sc, Dc
   if (downb)
     for (int k = 0; k < 2; ++k)
-      HIPCHECK(gemm_t(true, ncv, ncaav, nq, 0.5, k == 0 ? c.Sb : c.Db, nq, cavv_gp(cg, 4, k, tag), nq, 1.0, scaav,
-                      ncaav, h.s));
+      HIPCHECK(gemm_c(h, true, ncv, ncaav, nq, 0.5, k == 0 ? c.Sb : c.Db, nq, cavv_gp(cg, 4, k, tag), nq, 1.0, scaav,
+                      ncaav));
   if (downc)
     for (int k = 0; k < 2; ++k)
-      HIPCHECK(gemm_t(true, h.nv, naaav, c.nak, 0.5, c.Sc + k * h.nv * c.nak, c.nak, cavv_gp(cg, 5, k, tag), c.nak,
-                      1.0, saaav, naaav, h.s));
+      HIPCHECK(gemm_c(h, true, h.nv, naaav, c.nak, 0.5, c.Sc + k * h.nv * c.nak, c.nak, cavv_gp(cg, 5, k, tag), c.nak,
+                      1.0, saaav, naaav));
 }
 
 template <typename T>

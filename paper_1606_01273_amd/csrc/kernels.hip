@@ -68,9 +68,9 @@ constexpr int BM = 64, BN = 64, BK = BK_RESIDUAL;
 // 64 (MT = 2: 64 x 64, MT = 4: 128 x 64 -- more flops per byte staged, at
 // twice the accumulator registers).  KB: K tile (16 or 32; a longer tile
 // gives the register prefetch of the next tile more time to arrive).
-// SPLIT (dual only): blockIdx.z selects a K range of kchunk (a multiple of
-// KB); the raw X S and X F partial products go to C as [split][2][M][N] for
-// a separate epilogue.
+// SPLIT: blockIdx.z selects a K range of kchunk (a multiple of KB); the raw
+// partial products go to C as [split][M][N] (dual: the X S and X F products
+// as [split][2][M][N]) for a separate epilogue.
 template <bool B_NK, bool DUAL, bool SPLIT = false, int MT = 2, int KB = BK, int WPE = 1>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void k_gemm_f64(int64_t M, int64_t N, int64_t K, double alpha,
                                                   const double* __restrict__ A, int64_t lda,
@@ -237,9 +237,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
         const int64_t gn = n0 + wn * 32 + j * 16 + (lane & 15);
         if (gm < M && gn < N) {
           if (SPLIT) {
-            double* P = C + bz * 2 * M * N;
+            double* P = C + bz * (DUAL ? 2 : 1) * M * N;
             P[gm * N + gn] = acc[i][j][v];
-            P[M * N + gm * N + gn] = acc2[i][j][v];
+            if (DUAL) P[M * N + gm * N + gn] = acc2[i][j][v];
           } else if (DUAL) {
             double r = dvec[gm] + dshift;
             double val = r * acc[i][j][v] + acc2[i][j][v];
@@ -261,14 +261,75 @@ hipError_t gemm_f64(bool b_is_nk, int64_t M, int64_t N, int64_t K, double alpha,
   dim3 grid;
   int mx;
   if (!tile_grid(M, N, batch, BM, BN, &grid, &mx)) return hipErrorInvalidValue;
+  // three waves per SIMD asked of the compiler (accumulators in VGPRs, a
+  // third wave for the MFMA pipe while the others wait on LDS or loads) and
+  // the XCD-grouped tile order (the tiles sharing an A row band run on one
+  // XCD at about the same time); the grid only fixes the workgroup count
+  // Products with fewer than two 64 x 64 tiles per CU take 32 x 64 tiles
+  // (twice the workgroups; each output element sums its K terms in the same
+  // order either way).
+  (void)mx;
+  const bool narrow = (int64_t)grid.x * grid.y * grid.z < 512 && tile_grid(M, N, batch, BM / 2, BN, &grid, &mx);
+#define GEMM_F64_LAUNCH(NK, MT_)                                                                               \
+  hipLaunchKernelGGL((k_gemm_f64<NK, false, false, MT_, BK, 3>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, \
+                     sA, B, ldb, sB, (const double*)nullptr, beta, C, ldc, sC, (const double*)nullptr, 0.0,     \
+                     (const double*)nullptr, (int64_t)0, 2, (int64_t)0)
+  if (b_is_nk) {
+    if (narrow) GEMM_F64_LAUNCH(true, 1);
+    else GEMM_F64_LAUNCH(true, 2);
+  } else {
+    if (narrow) GEMM_F64_LAUNCH(false, 1);
+    else GEMM_F64_LAUNCH(false, 2);
+  }
+#undef GEMM_F64_LAUNCH
+  return hipGetLastError();
+}
+
+// C = alpha sum_s P[s] + beta C over ns partial products P [ns][M][N]
+// (summed in split order, so the result does not depend on the launch)
+__global__ void k_splitk_sum(int64_t M, int64_t N, int ns, const double* __restrict__ P, double alpha, double beta,
+                             double* __restrict__ C, int64_t ldc) {
+  const int64_t mn = M * N;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < mn; e += (int64_t)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int k = 0; k < ns; ++k) acc += P[k * mn + e];
+    const int64_t m = e / N, n = e % N;
+    double v = alpha * acc;
+    if (beta != 0.0) v += beta * C[m * ldc + n];
+    C[m * ldc + n] = v;
+  }
+}
+
+hipError_t gemm_f64_ws(bool b_is_nk, int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
+                       const double* B, int64_t ldb, double beta, double* C, int64_t ldc, double* ws, int64_t ws_n,
+                       hipStream_t s) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  const int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+  int64_t ns = 1;
+  if (tiles < 512 && K >= 8 * BK) {
+    ns = std::min<int64_t>((1024 + tiles - 1) / tiles, K / (4 * BK));
+    ns = std::min<int64_t>(ns, 16);
+    while (ns > 1 && ns * M * N > ws_n) --ns;
+  }
+  if (ns < 2 || !ws) return gemm_f64(b_is_nk, M, N, K, alpha, A, lda, 0, B, ldb, 0, beta, C, ldc, 0, 1, s);
+  int64_t kchunk = (K + ns - 1) / ns;
+  kchunk = (kchunk + BK - 1) / BK * BK;
+  ns = (K + kchunk - 1) / kchunk;
+  dim3 grid;
+  int mx;
+  if (!tile_grid(M, N, (int)ns, BM, BN, &grid, &mx)) return hipErrorInvalidValue;
   if (b_is_nk)
-    hipLaunchKernelGGL((k_gemm_f64<true, false>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda,
-                       sA, B, ldb, sB, (const double*)nullptr, beta, C, ldc, sC,
-                       (const double*)nullptr, 0.0, (const double*)nullptr, (int64_t)0, mx, (int64_t)0);
+    hipLaunchKernelGGL((k_gemm_f64<true, false, true, 2, BK, 3>), grid, dim3(256), 0, s, M, N, K, 1.0, A, lda,
+                       (int64_t)0, B, ldb, (int64_t)0, (const double*)nullptr, 0.0, ws, N, (int64_t)0,
+                       (const double*)nullptr, 0.0, (const double*)nullptr, (int64_t)0, mx, kchunk);
   else
-    hipLaunchKernelGGL((k_gemm_f64<false, false>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda,
-                       sA, B, ldb, sB, (const double*)nullptr, beta, C, ldc, sC,
-                       (const double*)nullptr, 0.0, (const double*)nullptr, (int64_t)0, mx, (int64_t)0);
+    hipLaunchKernelGGL((k_gemm_f64<false, false, true, 2, BK, 3>), grid, dim3(256), 0, s, M, N, K, 1.0, A, lda,
+                       (int64_t)0, B, ldb, (int64_t)0, (const double*)nullptr, 0.0, ws, N, (int64_t)0,
+                       (const double*)nullptr, 0.0, (const double*)nullptr, (int64_t)0, mx, kchunk);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const unsigned g2 = cdiv(M * N, 256) > 65536 ? 65536 : cdiv(M * N, 256);
+  hipLaunchKernelGGL(k_splitk_sum, dim3(g2), dim3(256), 0, s, M, N, (int)ns, (const double*)ws, alpha, beta, C, ldc);
   return hipGetLastError();
 }
 

@@ -19,6 +19,14 @@ hipError_t launch_gather_apply(const double* X, int64_t nlead, int64_t dim_from,
 hipError_t gemm_f64(bool b_is_nk, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
                     int64_t lda, int64_t sA, const double* B, int64_t ldb, int64_t sB, double beta,
                     double* C, int64_t ldc, int64_t sC, int batch, hipStream_t s);
+// the same product (batch 1, no strides) split over K when it has fewer than
+// 512 tiles of 64 x 64 and K >= 128: partial products in ws (ws_n doubles;
+// split count reduced to fit, plain product if none fits), then one summing
+// pass, C = alpha sum + beta C.  Deterministic: the split count depends on
+// the shape and ws_n only.
+hipError_t gemm_f64_ws(bool b_is_nk, int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
+                       const double* B, int64_t ldb, double beta, double* C, int64_t ldc, double* ws, int64_t ws_n,
+                       hipStream_t s);
 // batched C_p = A_p B_p (B_p [K][N], beta 0), tile order for few m tiles
 hipError_t gemm_f64_batched(int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, int64_t sA,
                             const double* B, int64_t ldb, int64_t sB, double* C, int64_t ldc, int64_t sC,
