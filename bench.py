@@ -147,6 +147,24 @@ def _batch_compare(n, seed, reading, tol, tune=True):
         t_seq += dt
         if e_b[i] is not None:
             dmax = max(dmax, float(np.abs(np.asarray(w) - e_b[i]).max()))
+    # batched residual evaluations (Eq. 10 for every state of every problem,
+    # FP64): caspt2_residual_all of every problem, eight calls at a time on
+    # the library's host threads, each on its handle's stream
+    from paper_1606_01273_amd import residual_all_many
+    xs = [torch.randn(g.nst * g.length, dtype=torch.float64, device="cuda") for g in gs]
+    ss = [torch.empty_like(x) for x in xs]
+    residual_all_many(gs, xs, ss, threads=SETUP_THREADS)
+    torch.cuda.synchronize()
+    nrep = 5
+    t0 = time.perf_counter()
+    for _ in range(nrep):
+        residual_all_many(gs, xs, ss, threads=SETUP_THREADS)
+    torch.cuda.synchronize()
+    t_res = (time.perf_counter() - t0) / nrep
+    res_bytes = sum(3 * 8 * g.nst * g.length for g in gs)   # read x and the source, write sigma
+    del xs, ss
+    print(f"[bench] batched residual evaluation {t_res * 1e3:.2f} ms ({res_bytes / 1e9:.2f} GB algorithmic)",
+          file=sys.stderr, flush=True)
     # the same batch in the mixed mode (FP32 grouped inner PCG, FP64 refinement)
     for g in gs:
         g.set_precision(MIXED)
@@ -167,6 +185,13 @@ def _batch_compare(n, seed, reading, tol, tune=True):
             "solved": int(sum(ok)), "indefinite_instances": bad, "inputs_s": round(t_inputs, 2),
             "setup_s": round(t_setup, 2), "setup_threads": SETUP_THREADS,
             "tune_s": round(t_tune, 2),
+            "residual_evals_per_s": round(1.0 / t_res, 2),
+            "residual_roofline": {"bound": "hbm", "achieved": round(res_bytes / t_res / 1e9, 1), "peak": 8000.0,
+                                  "unit": "GB/s", "frac": round(res_bytes / t_res / 8e12, 4),
+                                  "bytes_per_eval": res_bytes,
+                                  "note": "one batched evaluation: caspt2_residual_all of all 64 problems "
+                                          "(caspt2_residual_all_many, eight at a time, eight streams), algorithmic "
+                                          "bytes 3 x 8 B x length x states summed over the problems"},
             "seconds_batched": round(t_batch, 3), "seconds_one_by_one": round(t_seq, 3),
             "speedup": round(t_seq / t_batch, 3) if t_batch > 0 else None,
             "max_abs_dE_ms_batched_vs_one_by_one": dmax,

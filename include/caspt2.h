@@ -225,6 +225,18 @@ CASPT2_API int caspt2_residual(caspt2_handle* h, int32_t L, int32_t with_source,
  * done. */
 CASPT2_API int caspt2_residual_all(caspt2_handle* h, int32_t with_source, const double* x, double* sigma);
 
+/* caspt2_residual_all for n handles (distinct; x[k] and sigma[k] as that call
+ * takes them for handle k), nthreads calls at a time on host threads of the
+ * library, so that the launches of different problems overlap on the device
+ * (each handle works on its own stream; handles created on distinct streams
+ * overlap).  status[k] receives handle k's code.  Returns when every call is
+ * done: the first failing status in k order (its message is then
+ * caspt2_last_error's), or OK.  E_ARG for n < 1, nthreads < 1, a NULL array
+ * or a repeated handle. */
+CASPT2_API int caspt2_residual_all_many(int32_t n, caspt2_handle* const* handles, int32_t with_source,
+                                        const double* const* x, double* const* sigma, int32_t nthreads,
+                                        int32_t* status);
+
 /* Streams caspt2_residual_all spreads the states over: 2 (default) or 1 (all
  * on the handle's stream, e.g. to time each kernel alone).  E_ARG otherwise. */
 CASPT2_API int caspt2_set_streams(caspt2_handle* h, int32_t n);

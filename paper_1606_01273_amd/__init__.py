@@ -14,7 +14,8 @@ from . import _lib
 from ._lib import (E_ARG, E_DEVICE, E_INDEFINITE, E_NOCONV, E_NOMEM, E_NOTIMPL, E_STATE, ENTRY_NAMES,
                    FP64, MIXED, MSMR, OK, SSSR, Caspt2Error)
 
-__all__ = ["Caspt2", "Caspt2Error", "batch_solve", "xms_rotate", "lib", "MSMR", "SSSR", "FP64", "MIXED", "ENTRY_NAMES"]
+__all__ = ["Caspt2", "Caspt2Error", "batch_solve", "residual_all_many", "xms_rotate", "lib", "MSMR", "SSSR", "FP64",
+           "MIXED", "ENTRY_NAMES"]
 
 _LIB = None
 
@@ -291,3 +292,17 @@ def batch_solve(problems, targets=None, tol=1e-10, maxiter=200):
         out_l.append([li[k + L].as_dict() for L in range(p.nst)])
         k += p.nst
     return rc, out_a, out_l
+
+
+def residual_all_many(handles, xs, sigmas, with_source=True, threads=8):
+    """caspt2_residual_all of every handle (xs[k], sigmas[k]: device tensors
+    [nst][length]), `threads` calls at a time on the library's host threads."""
+    n = len(handles)
+    if n == 0:
+        return
+    hs = (ctypes.c_void_p * n)(*[g._h.value for g in handles])
+    xp = (ctypes.c_void_p * n)(*[_ptr(x) for x in xs])
+    sp = (ctypes.c_void_p * n)(*[_ptr(s) for s in sigmas])
+    st = (ctypes.c_int32 * n)()
+    _check(lib().caspt2_residual_all_many(n, hs, 1 if with_source else 0, xp, sp, int(threads), st),
+           "caspt2_residual_all_many")

@@ -63,6 +63,9 @@ SIGNATURES = {
                                      ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
     "caspt2_residual": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P, _P]),
     "caspt2_residual_all": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P]),
+    "caspt2_residual_all_many": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(_P), ctypes.c_int32,
+                                                ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.c_int32,
+                                                ctypes.POINTER(ctypes.c_int32)]),
     "caspt2_solve_amplitudes": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int32, _P, ctypes.POINTER(Info)]),
     "caspt2_get_amplitudes": (ctypes.c_int, [_P, ctypes.c_int32, _P]),
     "xms_rotate": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _D, _D, _D, _D]),

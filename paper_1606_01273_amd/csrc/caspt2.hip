@@ -3961,6 +3961,45 @@ int caspt2_residual_all(caspt2_handle* h, int32_t with_source, const double* x, 
   })
 }
 
+int caspt2_residual_all_many(int32_t n, caspt2_handle* const* handles, int32_t with_source, const double* const* x,
+                             double* const* sigma, int32_t nthreads, int32_t* status) {
+  if (n < 1 || nthreads < 1 || !handles || !x || !sigma || !status) return CASPT2_E_ARG;
+  for (int k = 0; k < n; ++k) {
+    if (!handles[k]) return CASPT2_E_ARG;
+    for (int j = 0; j < k; ++j)
+      if (handles[j] == handles[k]) return CASPT2_E_ARG;
+    status[k] = CASPT2_E_STATE;
+  }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return CASPT2_E_DEVICE;
+  std::atomic<int> next(0);
+  std::vector<std::string> msg(n);
+  auto worker = [&]() {
+    if (hipSetDevice(dev) != hipSuccess) return;
+    for (int k; (k = next.fetch_add(1)) < n;) {
+      status[k] = caspt2_residual_all(handles[k], with_source, x[k], sigma[k]);
+      if (status[k] != CASPT2_OK) msg[k] = g_last_error;
+    }
+  };
+  std::vector<std::thread> pool;
+  const int nt = std::min(nthreads, n);
+  try {
+    for (int t = 0; t < nt; ++t) pool.emplace_back(worker);
+  } catch (const std::exception& ex) {
+    if (pool.empty()) {
+      g_last_error = ex.what();
+      return CASPT2_E_DEVICE;
+    }
+  }
+  for (auto& t : pool) t.join();
+  for (int k = 0; k < n; ++k)
+    if (status[k] != CASPT2_OK) {
+      g_last_error = msg[k].empty() ? "problem " + std::to_string(k) + " not evaluated" : msg[k];
+      return status[k];
+    }
+  return CASPT2_OK;
+}
+
 int caspt2_solve_amplitudes(caspt2_handle* h, double tol, int32_t maxiter, const double* T0,
                             caspt2_info* info) {
   if (!h || !(tol > 0.0) || maxiter < 0) return CASPT2_E_ARG;

@@ -957,13 +957,13 @@ hipError_t launch_reduce_vc(const CoupleDesc& d, const PackInfo& pk, const doubl
   int Rw = 1;
   while (Rw * 2 * CG <= 64) Rw *= 2;
   while (Rw > 1 && nrows * CG * zparts(Rw) < ((int64_t)1 << 20)) Rw /= 2;
-  // still few threads in all (few bra rows, long sums: e.g. 30 rows summed
+  // few bra rows (under 64) and few threads in all (e.g. 30 rows summed
   // over 12 000 labels): fewer column groups per workgroup (the others go
   // to grid y) and more z parts, until about 2^20 threads -- while the
   // combination of the parts (P ny additions by one thread) stays within
   // 256 and a z part keeps at least two column groups
-  while (Rw == 1 && CG > 2 && nrows * ngroups * zparts(1) < ((int64_t)1 << 20) && zparts(1) * 2 <= nz &&
-         zparts(1) * 2 * rp.ny <= 256)
+  while (Rw == 1 && CG > 2 && nrows < 64 && nrows * ngroups * zparts(1) < ((int64_t)1 << 20) &&
+         zparts(1) * 2 <= nz && zparts(1) * 2 * rp.ny <= 256)
     CG /= 2;
   const int P = zparts(Rw);
   const int R = 256 / (CG * P);
