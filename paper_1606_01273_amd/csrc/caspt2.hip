@@ -3728,34 +3728,39 @@ int caspt2_create_many(int32_t n, const caspt2_dims* dims, const caspt2_inputs* 
     out[k] = nullptr;
     status[k] = CASPT2_E_STATE;
   }
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return CASPT2_E_DEVICE;
-  std::atomic<int> next(0);
-  std::vector<std::string> msg(n);
-  auto worker = [&]() {
-    if (hipSetDevice(dev) != hipSuccess) return;   // a new thread starts on device 0
-    for (int k; (k = next.fetch_add(1)) < n;) {
-      status[k] = caspt2_create(&dims[k], &inputs[k], inputs_on_device, streams[k], &out[k]);
-      if (status[k] != CASPT2_OK) msg[k] = g_last_error;
+  ABI_GUARD({
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return CASPT2_E_DEVICE;
+    std::atomic<int> next(0);
+    std::vector<std::string> msg(n);
+    auto worker = [&]() {
+      if (hipSetDevice(dev) != hipSuccess) return;   // a new thread starts on device 0
+      try {
+        for (int k; (k = next.fetch_add(1)) < n;) {
+          status[k] = caspt2_create(&dims[k], &inputs[k], inputs_on_device, streams[k], &out[k]);
+          if (status[k] != CASPT2_OK) msg[k] = g_last_error;
+        }
+      } catch (...) {   // a message that cannot be copied: the status stays
+      }
+    };
+    std::vector<std::thread> pool;
+    const int nt = std::min(nthreads, n);
+    try {
+      for (int t = 0; t < nt; ++t) pool.emplace_back(worker);
+    } catch (const std::exception& ex) {   // fewer threads than asked: the started ones take every problem
+      if (pool.empty()) {
+        g_last_error = ex.what();
+        return CASPT2_E_DEVICE;
+      }
     }
-  };
-  std::vector<std::thread> pool;
-  const int nt = std::min(nthreads, n);
-  try {
-    for (int t = 0; t < nt; ++t) pool.emplace_back(worker);
-  } catch (const std::exception& ex) {   // fewer threads than asked: the started ones take every problem
-    if (pool.empty()) {
-      g_last_error = ex.what();
-      return CASPT2_E_DEVICE;
-    }
-  }
-  for (auto& t : pool) t.join();
-  for (int k = 0; k < n; ++k)
-    if (status[k] != CASPT2_OK) {
-      g_last_error = msg[k].empty() ? "problem " + std::to_string(k) + " not created" : msg[k];
-      return status[k];
-    }
-  return CASPT2_OK;
+    for (auto& t : pool) t.join();
+    for (int k = 0; k < n; ++k)
+      if (status[k] != CASPT2_OK) {
+        g_last_error = msg[k].empty() ? "problem " + std::to_string(k) + " not created" : msg[k];
+        return status[k];
+      }
+    return CASPT2_OK;
+  })
 }
 
 int caspt2_destroy(caspt2_handle* h) {
@@ -3970,34 +3975,39 @@ int caspt2_residual_all_many(int32_t n, caspt2_handle* const* handles, int32_t w
       if (handles[j] == handles[k]) return CASPT2_E_ARG;
     status[k] = CASPT2_E_STATE;
   }
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return CASPT2_E_DEVICE;
-  std::atomic<int> next(0);
-  std::vector<std::string> msg(n);
-  auto worker = [&]() {
-    if (hipSetDevice(dev) != hipSuccess) return;
-    for (int k; (k = next.fetch_add(1)) < n;) {
-      status[k] = caspt2_residual_all(handles[k], with_source, x[k], sigma[k]);
-      if (status[k] != CASPT2_OK) msg[k] = g_last_error;
+  ABI_GUARD({
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return CASPT2_E_DEVICE;
+    std::atomic<int> next(0);
+    std::vector<std::string> msg(n);
+    auto worker = [&]() {
+      if (hipSetDevice(dev) != hipSuccess) return;
+      try {
+        for (int k; (k = next.fetch_add(1)) < n;) {
+          status[k] = caspt2_residual_all(handles[k], with_source, x[k], sigma[k]);
+          if (status[k] != CASPT2_OK) msg[k] = g_last_error;
+        }
+      } catch (...) {   // a message that cannot be copied: the status stays
+      }
+    };
+    std::vector<std::thread> pool;
+    const int nt = std::min(nthreads, n);
+    try {
+      for (int t = 0; t < nt; ++t) pool.emplace_back(worker);
+    } catch (const std::exception& ex) {
+      if (pool.empty()) {
+        g_last_error = ex.what();
+        return CASPT2_E_DEVICE;
+      }
     }
-  };
-  std::vector<std::thread> pool;
-  const int nt = std::min(nthreads, n);
-  try {
-    for (int t = 0; t < nt; ++t) pool.emplace_back(worker);
-  } catch (const std::exception& ex) {
-    if (pool.empty()) {
-      g_last_error = ex.what();
-      return CASPT2_E_DEVICE;
-    }
-  }
-  for (auto& t : pool) t.join();
-  for (int k = 0; k < n; ++k)
-    if (status[k] != CASPT2_OK) {
-      g_last_error = msg[k].empty() ? "problem " + std::to_string(k) + " not evaluated" : msg[k];
-      return status[k];
-    }
-  return CASPT2_OK;
+    for (auto& t : pool) t.join();
+    for (int k = 0; k < n; ++k)
+      if (status[k] != CASPT2_OK) {
+        g_last_error = msg[k].empty() ? "problem " + std::to_string(k) + " not evaluated" : msg[k];
+        return status[k];
+      }
+    return CASPT2_OK;
+  })
 }
 
 int caspt2_solve_amplitudes(caspt2_handle* h, double tol, int32_t maxiter, const double* T0,
