@@ -49,8 +49,9 @@ struct DevError : std::runtime_error {
 // more than their kernels).  Every launch of a creation is ordered on the
 // handle's one stream, so a block is reused only by work queued after the
 // work that used it.  Sizes up to 4 MB are rounded to powers of two so that
-// blocks of neighbouring sizes are shared, larger ones to 256 KB.  The cache
-// belongs to one creation on one thread; the creation returns its blocks at
+// blocks of neighbouring sizes are shared, larger ones to 256 KB; a block is
+// keyed by its own size, so one allocated before the creation is reused only
+// for requests it covers.  The cache belongs to one creation on one thread; the creation returns its blocks at
 // its end (or when it throws), after its last synchronisation.
 struct BlockCache {
   std::multimap<size_t, void*> blocks;
@@ -72,7 +73,9 @@ size_t block_class(size_t bytes) {
   return (bytes + g - 1) / g * g;
 }
 
-void* dev_alloc(size_t bytes) {
+// a block of at least `bytes`; cap receives its size (the cache's key when
+// it is freed: a block is reused only for requests of its exact class)
+void* dev_alloc(size_t bytes, size_t& cap) {
   void* p = nullptr;
   if (BlockCache* c = t_block_cache) {
     bytes = block_class(bytes);
@@ -81,19 +84,21 @@ void* dev_alloc(size_t bytes) {
       p = it->second;
       c->blocks.erase(it);
       c->held -= bytes;
+      cap = bytes;
       return p;
     }
   }
   HIPCHECK(hipMalloc(&p, bytes));
+  cap = bytes;
   return p;
 }
 
-void dev_free(void* p, size_t bytes) {
+void dev_free(void* p, size_t cap) {
   if (!p) return;
   BlockCache* c = t_block_cache;
-  if (c && c->held + block_class(bytes) <= BlockCache::CAP) {
-    c->blocks.emplace(block_class(bytes), p);
-    c->held += block_class(bytes);
+  if (c && c->held + cap <= BlockCache::CAP) {
+    c->blocks.emplace(cap, p);
+    c->held += cap;
     return;
   }
   (void)hipFree(p);
@@ -114,31 +119,39 @@ template <typename T>
 struct DevBuf {
   T* p = nullptr;
   int64_t n = 0;
+  size_t cap = 0;   // bytes of the block
   DevBuf() = default;
   explicit DevBuf(int64_t n_) { alloc(n_); }
   void alloc(int64_t n_) {
     release();
-    if (n_ > 0) p = static_cast<T*>(dev_alloc((size_t)n_ * sizeof(T)));
+    if (n_ > 0) p = static_cast<T*>(dev_alloc((size_t)n_ * sizeof(T), cap));
     n = n_;
   }
   void zero(hipStream_t s) {
     if (n > 0) HIPCHECK(hipMemsetAsync(p, 0, (size_t)n * sizeof(T), s));
   }
   void release() {
-    dev_free(p, (size_t)n * sizeof(T));
+    dev_free(p, cap);
     p = nullptr;
     n = 0;
+    cap = 0;
   }
   ~DevBuf() { release(); }
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n), cap(o.cap) {
+    o.p = nullptr;
+    o.n = 0;
+    o.cap = 0;
+  }
   DevBuf& operator=(DevBuf&& o) noexcept {
     release();
     p = o.p;
     n = o.n;
+    cap = o.cap;
     o.p = nullptr;
     o.n = 0;
+    o.cap = 0;
     return *this;
   }
 };
@@ -174,14 +187,16 @@ struct PinBuf {
 struct IBuf {
   int32_t* p = nullptr;
   int64_t n = 0;
+  size_t cap = 0;
   void alloc(int64_t n_) {
-    dev_free(p, (size_t)n * sizeof(int32_t));
+    dev_free(p, cap);
     p = nullptr;
     n = 0;
-    if (n_ > 0) p = static_cast<int32_t*>(dev_alloc((size_t)n_ * sizeof(int32_t)));
+    cap = 0;
+    if (n_ > 0) p = static_cast<int32_t*>(dev_alloc((size_t)n_ * sizeof(int32_t), cap));
     n = n_;
   }
-  ~IBuf() { dev_free(p, (size_t)n * sizeof(int32_t)); }
+  ~IBuf() { dev_free(p, cap); }
 };
 
 int64_t ipow(int64_t b, int e) {
