@@ -40,3 +40,32 @@ def test_binding_signatures_cover_the_abi():
     assert set(declared_symbols()) <= set(_lib.SIGNATURES)
     lib = _lib.load()
     assert lib.caspt2_strerror(-6) == b"not implemented"
+
+
+def test_many_entry_points_reject_bad_arguments_before_any_device_call():
+    """caspt2_create_many and caspt2_residual_all_many check their arguments
+    on the host (no device needed): n < 1, nthreads < 1, NULL arrays and a
+    repeated handle are E_ARG; the Python helpers accept empty lists."""
+    import ctypes
+    from paper_1606_01273_amd import _lib, Caspt2, residual_all_many
+    lib = _lib.load()
+    E_ARG = _lib.E_ARG
+    ds = (_lib.Dims * 1)()
+    ins = (_lib.Inputs * 1)()
+    sp = (ctypes.c_void_p * 1)()
+    hs = (ctypes.c_void_p * 1)()
+    st = (ctypes.c_int32 * 1)()
+    assert lib.caspt2_create_many(0, ds, ins, 0, sp, 1, hs, st) == E_ARG
+    assert lib.caspt2_create_many(1, ds, ins, 0, sp, 0, hs, st) == E_ARG
+    assert lib.caspt2_create_many(1, None, ins, 0, sp, 1, hs, st) == E_ARG
+    assert lib.caspt2_create_many(1, ds, ins, 0, sp, 1, hs, None) == E_ARG
+    fake = (ctypes.c_void_p * 2)(0x1000, 0x1000)   # never dereferenced: rejected as repeated
+    xp = (ctypes.c_void_p * 2)()
+    st2 = (ctypes.c_int32 * 2)()
+    assert lib.caspt2_residual_all_many(0, fake, 1, xp, xp, 1, st2) == E_ARG
+    assert lib.caspt2_residual_all_many(2, fake, 1, xp, xp, 1, st2) == E_ARG
+    assert lib.caspt2_residual_all_many(2, fake, 1, xp, xp, 0, st2) == E_ARG
+    nul = (ctypes.c_void_p * 1)()
+    assert lib.caspt2_residual_all_many(1, nul, 1, xp, xp, 1, st2) == E_ARG
+    assert Caspt2.create_many([]) == []
+    assert residual_all_many([], [], []) is None
