@@ -491,6 +491,7 @@ def main():
     prof = {ENTRY_NAMES[k]: g.profile_entry(k) for k in range(len(ENTRY_NAMES))}
     coupl = g.profile_entry(len(ENTRY_NAMES))
     slot = {b: g.profile_entry(len(ENTRY_NAMES) + 1 + i) for i, b in enumerate(("ccvv", "cavv", "ccav"))}
+    stages = g.profile_stages()      # empty without Fock couplings
     g.profile(False)
     print(f"[bench] {args.steps} steps in {elapsed:.3f} s", file=sys.stderr, flush=True)
     # the library's default for caspt2_residual_all: states on two streams,
@@ -611,6 +612,9 @@ def main():
                           "ms_per_step": round(1e3 * elapsed_two / args.steps, 4),
                           "note": "caspt2_residual_all default: states on two streams, kernels of different "
                                   "states overlap"}
+    if stages:
+        out["coupling_stages_ms_per_state"] = {k: round(v, 3) for k, v in sorted(stages.items(),
+                                                                                key=lambda kv: -kv[1])}
     if tune is not None:
         out["tune"] = tune
     if solve is not None:
