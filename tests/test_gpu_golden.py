@@ -13,7 +13,12 @@
   in the launch configuration the benchmark times: properties that hold at
   any size -- the residual without source is linear in x and its operator is
   symmetric (Eq. 10 with a symmetric f and metric), with the Fock couplings
-  between blocks on.
+  between blocks on; and, with the canonical Fock operator, the ccvv rows
+  (the benchmark's dominant kernel) at sampled representatives against
+  their closed form (oracle/ccvv_closed.py, itself checked against the
+  factorised oracle on every ccvv row of small problems): every state, both
+  characters, with the source on one stream and without it on two, at 1e-12
+  of the largest sampled value.
 """
 import json
 import os
@@ -114,4 +119,58 @@ def test_full_size_operator_linear_and_symmetric(dev):
     axy.sub_(ax).sub_(ay)
     _ok(float(torch.linalg.vector_norm(axy)) / float(torch.linalg.vector_norm(ax)), 1e-12,
         "A(x + y) - A x - A y, relative")
+    g.close()
+
+
+def test_full_A_ccvv_rows_closed_form(dev):
+    from oracle.ccvv_closed import ccvv_pair_index, ccvv_rows
+    from paper_1606_01273_amd import Caspt2
+    p = make_problem(30, 8, 400, 1500, 4, seed=8, reading="A", shift=0.2)
+    g = Caspt2.from_problem(p)
+    g.autotune()
+    nc, nv, nst = p.nc, p.nv, p.nst
+    npc_p, npv_p = nc * (nc + 1) // 2, nv * (nv + 1) // 2
+    npc_m, npv_m = nc * (nc - 1) // 2, nv * (nv - 1) // 2
+    lay = {name: (off, rows, na) for name, off, rows, na in g.layout()}
+    assert lay["ccvv+"] == (0, npc_p * npv_p, nst)
+    assert lay["ccvv-"] == (npc_p * npv_p * nst, npc_m * npv_m, nst)
+    off_m = lay["ccvv-"][0]
+    rng = np.random.default_rng(42)
+    reps = [(0, 0, 0, 0), (nc - 1, nc - 1, nv - 1, nv - 1), (nc - 1, 0, nv - 1, 0), (5, 5, 300, 17),
+            (17, 3, 250, 250)]
+    while len(reps) < 256:
+        i, j = sorted(int(v) for v in rng.integers(0, nc, 2))[::-1]
+        a, b = sorted(int(v) for v in rng.integers(0, nv, 2))[::-1]
+        reps.append((i, j, a, b))
+    xh = random_vector(g.length, 41)
+    pos_p, pos_m, t_p, t_m, sel = [], [], [], [], []
+    for k, (i, j, a, b) in enumerate(reps):
+        r = ccvv_pair_index(i, j, False) * npv_p + ccvv_pair_index(a, b, False)
+        pos_p.append(r * nst)
+        t_p.append(xh[r * nst: (r + 1) * nst])
+        if i > j and a > b:
+            r = ccvv_pair_index(i, j, True) * npv_m + ccvv_pair_index(a, b, True)
+            pos_m.append(off_m + r * nst)
+            t_m.append(xh[off_m + r * nst: off_m + (r + 1) * nst])
+            sel.append(k)
+        else:
+            t_m.append(None)
+    cols = np.arange(nst)
+    idx = torch.tensor(np.concatenate([(np.asarray(pos_p)[:, None] + cols).ravel(),
+                                       (np.asarray(pos_m)[:, None] + cols).ravel()]), device=dev)
+    x = torch.from_numpy(xh).to(dev).unsqueeze(0).expand(nst, -1).contiguous()
+    del xh
+    sig = torch.empty_like(x)
+    for streams, src in ((1, True), (2, False)):
+        print(f"full A ccvv rows: {streams} stream(s), source {src}", flush=True)
+        g.set_streams(streams)
+        sig.fill_(float("nan"))
+        g.residual_all(x, sig, with_source=src)
+        torch.cuda.synchronize()
+        for L in range(nst):
+            got = sig[L].index_select(0, idx).cpu().numpy()
+            rp, rm = ccvv_rows(p, L, reps, t_p, t_m, with_source=src)
+            ref = np.concatenate([rp.ravel(), rm[sel].ravel()])
+            _ok(np.abs(got - ref).max() / np.abs(ref).max(), 1e-12,
+                f"ccvv rows, state {L} ({len(reps)} '+', {len(sel)} '-' rows)")
     g.close()
