@@ -122,19 +122,23 @@ def test_full_size_operator_linear_and_symmetric(dev):
     g.close()
 
 
-def test_full_A_ccvv_rows_closed_form(dev):
+def test_full_A_ccvv_cavv_rows_closed_form(dev):
+    from oracle.cavv_closed import cavv_rows
     from oracle.ccvv_closed import ccvv_pair_index, ccvv_rows
     from paper_1606_01273_amd import Caspt2
     p = make_problem(30, 8, 400, 1500, 4, seed=8, reading="A", shift=0.2)
     g = Caspt2.from_problem(p)
     g.autotune()
-    nc, nv, nst = p.nc, p.nv, p.nst
+    nc, na, nv, nst = p.nc, p.na, p.nv, p.nst
     npc_p, npv_p = nc * (nc + 1) // 2, nv * (nv + 1) // 2
     npc_m, npv_m = nc * (nc - 1) // 2, nv * (nv - 1) // 2
-    lay = {name: (off, rows, na) for name, off, rows, na in g.layout()}
+    lay = {name: (off, rows, n) for name, off, rows, n in g.layout()}
     assert lay["ccvv+"] == (0, npc_p * npv_p, nst)
     assert lay["ccvv-"] == (npc_p * npv_p * nst, npc_m * npv_m, nst)
-    off_m = lay["ccvv-"][0]
+    off_cp = (npc_p * npv_p + npc_m * npv_m) * nst
+    assert lay["cavv+"] == (off_cp, nc * npv_p, nst * na)
+    off_cm = off_cp + nc * npv_p * nst * na
+    assert lay["cavv-"] == (off_cm, nc * npv_m, nst * na)
     rng = np.random.default_rng(42)
     reps = [(0, 0, 0, 0), (nc - 1, nc - 1, nv - 1, nv - 1), (nc - 1, 0, nv - 1, 0), (5, 5, 300, 17),
             (17, 3, 250, 250)]
@@ -142,35 +146,54 @@ def test_full_A_ccvv_rows_closed_form(dev):
         i, j = sorted(int(v) for v in rng.integers(0, nc, 2))[::-1]
         a, b = sorted(int(v) for v in rng.integers(0, nv, 2))[::-1]
         reps.append((i, j, a, b))
+    creps = [(0, 0, 0), (nc - 1, nv - 1, nv - 1), (nc - 1, nv - 1, 0), (7, 123, 123)]
+    while len(creps) < 256:
+        a, b = sorted(int(v) for v in rng.integers(0, nv, 2))[::-1]
+        creps.append((int(rng.integers(0, nc)), a, b))
     xh = random_vector(g.length, 41)
-    pos_p, pos_m, t_p, t_m, sel = [], [], [], [], []
-    for k, (i, j, a, b) in enumerate(reps):
-        r = ccvv_pair_index(i, j, False) * npv_p + ccvv_pair_index(a, b, False)
-        pos_p.append(r * nst)
-        t_p.append(xh[r * nst: (r + 1) * nst])
-        if i > j and a > b:
-            r = ccvv_pair_index(i, j, True) * npv_m + ccvv_pair_index(a, b, True)
-            pos_m.append(off_m + r * nst)
-            t_m.append(xh[off_m + r * nst: off_m + (r + 1) * nst])
-            sel.append(k)
-        else:
-            t_m.append(None)
-    cols = np.arange(nst)
-    idx = torch.tensor(np.concatenate([(np.asarray(pos_p)[:, None] + cols).ravel(),
-                                       (np.asarray(pos_m)[:, None] + cols).ravel()]), device=dev)
+
+    def gather(rows_p, rows_m, width, off_p, off_m):
+        """positions and packed rows of the sampled representatives"""
+        pos, tp, tm, sel = [], [], [], []
+        for k, (rp, rm) in enumerate(zip(rows_p, rows_m)):
+            tp.append(xh[off_p + rp * width: off_p + (rp + 1) * width])
+            pos.append(off_p + rp * width)
+            if rm is None:
+                tm.append(None)
+            else:
+                tm.append(xh[off_m + rm * width: off_m + (rm + 1) * width])
+                sel.append(k)
+        pos += [off_m + rm * width for rm in rows_m if rm is not None]
+        cols = np.arange(width)
+        return (np.asarray(pos)[:, None] + cols).ravel(), tp, tm, sel
+
+    ccvv_p = [ccvv_pair_index(i, j, False) * npv_p + ccvv_pair_index(a, b, False) for i, j, a, b in reps]
+    ccvv_m = [ccvv_pair_index(i, j, True) * npv_m + ccvv_pair_index(a, b, True) if i > j and a > b else None
+              for i, j, a, b in reps]
+    cavv_p = [i * npv_p + ccvv_pair_index(a, b, False) for i, a, b in creps]
+    cavv_m = [i * npv_m + ccvv_pair_index(a, b, True) if a > b else None for i, a, b in creps]
+    pos1, t1p, t1m, sel1 = gather(ccvv_p, ccvv_m, nst, 0, lay["ccvv-"][0])
+    pos2, t2p, t2m, sel2 = gather(cavv_p, cavv_m, nst * na, off_cp, off_cm)
+    idx1 = torch.tensor(pos1, device=dev)
+    idx2 = torch.tensor(pos2, device=dev)
     x = torch.from_numpy(xh).to(dev).unsqueeze(0).expand(nst, -1).contiguous()
-    del xh
     sig = torch.empty_like(x)
+    dens = None
     for streams, src in ((1, True), (2, False)):
-        print(f"full A ccvv rows: {streams} stream(s), source {src}", flush=True)
+        print(f"full A ccvv and cavv rows: {streams} stream(s), source {src}", flush=True)
         g.set_streams(streams)
         sig.fill_(float("nan"))
         g.residual_all(x, sig, with_source=src)
         torch.cuda.synchronize()
         for L in range(nst):
-            got = sig[L].index_select(0, idx).cpu().numpy()
-            rp, rm = ccvv_rows(p, L, reps, t_p, t_m, with_source=src)
-            ref = np.concatenate([rp.ravel(), rm[sel].ravel()])
+            got = sig[L].index_select(0, idx1).cpu().numpy()
+            rp, rm = ccvv_rows(p, L, reps, t1p, t1m, with_source=src)
+            ref = np.concatenate([rp.ravel(), rm[sel1].ravel()])
             _ok(np.abs(got - ref).max() / np.abs(ref).max(), 1e-12,
-                f"ccvv rows, state {L} ({len(reps)} '+', {len(sel)} '-' rows)")
+                f"ccvv rows, state {L} ({len(reps)} '+', {len(sel1)} '-' rows)")
+            got = sig[L].index_select(0, idx2).cpu().numpy()
+            rp, rm, dens = cavv_rows(p, L, creps, t2p, t2m, with_source=src, dens=dens)
+            ref = np.concatenate([rp.ravel(), rm[sel2].ravel()])
+            _ok(np.abs(got - ref).max() / np.abs(ref).max(), 1e-12,
+                f"cavv rows, state {L} ({len(creps)} '+', {len(sel2)} '-' rows)")
     g.close()
