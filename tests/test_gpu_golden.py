@@ -122,7 +122,8 @@ def test_full_size_operator_linear_and_symmetric(dev):
     g.close()
 
 
-def test_full_A_ccvv_cavv_rows_closed_form(dev):
+def test_full_A_ccvv_cavv_aavv_rows_closed_form(dev):
+    from oracle.aavv_closed import aavv_rows
     from oracle.cavv_closed import cavv_rows
     from oracle.ccvv_closed import ccvv_pair_index, ccvv_rows
     from paper_1606_01273_amd import Caspt2
@@ -139,6 +140,10 @@ def test_full_A_ccvv_cavv_rows_closed_form(dev):
     assert lay["cavv+"] == (off_cp, nc * npv_p, nst * na)
     off_cm = off_cp + nc * npv_p * nst * na
     assert lay["cavv-"] == (off_cm, nc * npv_m, nst * na)
+    off_ap = off_cm + nc * npv_m * nst * na
+    assert lay["aavv+"] == (off_ap, npv_p, nst * na * na)
+    off_am = off_ap + npv_p * nst * na * na
+    assert lay["aavv-"] == (off_am, npv_m, nst * na * na)
     rng = np.random.default_rng(42)
     reps = [(0, 0, 0, 0), (nc - 1, nc - 1, nv - 1, nv - 1), (nc - 1, 0, nv - 1, 0), (5, 5, 300, 17),
             (17, 3, 250, 250)]
@@ -150,6 +155,9 @@ def test_full_A_ccvv_cavv_rows_closed_form(dev):
     while len(creps) < 256:
         a, b = sorted(int(v) for v in rng.integers(0, nv, 2))[::-1]
         creps.append((int(rng.integers(0, nc)), a, b))
+    areps = [(0, 0), (nv - 1, nv - 1), (nv - 1, 0), (211, 211)]
+    while len(areps) < 128:
+        areps.append(tuple(sorted(int(v) for v in rng.integers(0, nv, 2))[::-1]))
     xh = random_vector(g.length, 41)
 
     def gather(rows_p, rows_m, width, off_p, off_m):
@@ -174,13 +182,17 @@ def test_full_A_ccvv_cavv_rows_closed_form(dev):
     cavv_m = [i * npv_m + ccvv_pair_index(a, b, True) if a > b else None for i, a, b in creps]
     pos1, t1p, t1m, sel1 = gather(ccvv_p, ccvv_m, nst, 0, lay["ccvv-"][0])
     pos2, t2p, t2m, sel2 = gather(cavv_p, cavv_m, nst * na, off_cp, off_cm)
+    aavv_p = [ccvv_pair_index(a, b, False) for a, b in areps]
+    aavv_m = [ccvv_pair_index(a, b, True) if a > b else None for a, b in areps]
+    pos3, t3p, t3m, sel3 = gather(aavv_p, aavv_m, nst * na * na, off_ap, off_am)
     idx1 = torch.tensor(pos1, device=dev)
     idx2 = torch.tensor(pos2, device=dev)
+    idx3 = torch.tensor(pos3, device=dev)
     x = torch.from_numpy(xh).to(dev).unsqueeze(0).expand(nst, -1).contiguous()
     sig = torch.empty_like(x)
-    dens = None
+    dens = prods = None
     for streams, src in ((1, True), (2, False)):
-        print(f"full A ccvv and cavv rows: {streams} stream(s), source {src}", flush=True)
+        print(f"full A ccvv, cavv and aavv rows: {streams} stream(s), source {src}", flush=True)
         g.set_streams(streams)
         sig.fill_(float("nan"))
         g.residual_all(x, sig, with_source=src)
@@ -196,4 +208,9 @@ def test_full_A_ccvv_cavv_rows_closed_form(dev):
             ref = np.concatenate([rp.ravel(), rm[sel2].ravel()])
             _ok(np.abs(got - ref).max() / np.abs(ref).max(), 1e-12,
                 f"cavv rows, state {L} ({len(creps)} '+', {len(sel2)} '-' rows)")
+            got = sig[L].index_select(0, idx3).cpu().numpy()
+            rp, rm, prods = aavv_rows(p, L, areps, t3p, t3m, with_source=src, prods=prods)
+            ref = np.concatenate([rp.ravel(), rm[sel3].ravel()])
+            _ok(np.abs(got - ref).max() / np.abs(ref).max(), 1e-12,
+                f"aavv rows, state {L} ({len(areps)} '+', {len(sel3)} '-' rows)")
     g.close()
