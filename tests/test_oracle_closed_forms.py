@@ -20,6 +20,7 @@ from synth.gen import make_problem
 from oracle.ic import Caspt2Oracle
 from oracle.aavv_closed import aavv_rows
 from oracle.cavv_closed import cavv_rows, xms_states_diagonal_f
+from oracle.ccav_closed import ccav_rows
 from oracle.ccvv_closed import ccvv_pair_index, ccvv_rows, xms_energies_diagonal_f
 
 CASES = [((3, 2, 5, 30, 2), 1), ((2, 3, 4, 30, 3), 2), ((4, 0, 6, 30, 1), 3), ((1, 2, 3, 20, 1), 4)]
@@ -172,6 +173,45 @@ def test_aavv_closed_form_matches_factorised_oracle(dims, seed):
             ref_p = sig[ep["offset"]: ep["offset"] + ep["nrow"] * n].reshape(-1, n)
             ref_m = sig[em["offset"]: em["offset"] + em["nrow"] * n].reshape(-1, n)
             got_p, got_m, prods = aavv_rows(p, L, reps_p, xp, tm, with_source=src, prods=prods)
+            scale = max(np.abs(ref_p).max(), np.abs(ref_m).max() if ref_m.size else 0.0)
+            assert scale > 0.0
+            assert np.abs(got_p - ref_p).max() <= 1e-12 * scale
+            if sel:
+                assert np.abs(got_m[sel] - ref_m).max() <= 1e-12 * scale
+            assert np.all(np.isnan(np.delete(got_m, sel, axis=0)))
+
+
+CCAV_CASES = [((3, 2, 5, 30, 2), 1), ((3, 3, 4, 30, 3), 2), ((2, 4, 3, 20, 2), 4), ((2, 1, 3, 20, 1), 7)]
+
+
+@pytest.mark.parametrize("dims,seed", CCAV_CASES)
+def test_ccav_closed_form_matches_factorised_oracle(dims, seed):
+    p = make_problem(*dims, seed=seed, reading="A", shift=0.2)
+    o = Caspt2Oracle(p, "MSMR")
+    ents = {(e["block"].name, e["chi"]): e for e in o.layout}
+    ep, em = ents[("ccav", (1,))], ents[("ccav", (-1,))]
+    n = ep["nalpha"]
+    assert n == p.nst * p.na
+    reps_p = [(i, j, a) for i in range(p.nc) for j in range(i + 1) for a in range(p.nv)]
+    reps_m = [(i, j, a) for i in range(p.nc) for j in range(i) for a in range(p.nv)]
+    assert [tuple(r) for r in ep["reps"]] == reps_p
+    assert [tuple(r) for r in em["reps"]] == reps_m
+    for r, (i, j, a) in enumerate(reps_p):
+        assert ccvv_pair_index(i, j, False) * p.nv + a == r
+    for r, (i, j, a) in enumerate(reps_m):
+        assert ccvv_pair_index(i, j, True) * p.nv + a == r
+    x = np.random.default_rng(seed + 40).standard_normal(o.length)
+    sel = [k for k, (i, j, a) in enumerate(reps_p) if i > j]
+    dens = None
+    for xv, src in ((x, True), (x, False), (np.zeros_like(x), True)):
+        xp = xv[ep["offset"]: ep["offset"] + ep["nrow"] * n].reshape(-1, n)
+        xm = xv[em["offset"]: em["offset"] + em["nrow"] * n].reshape(-1, n)
+        tm = [xm[ccvv_pair_index(i, j, True) * p.nv + a] if i > j else None for (i, j, a) in reps_p]
+        for L in range(p.nst):
+            sig = o.residual(L, xv, with_source=src)
+            ref_p = sig[ep["offset"]: ep["offset"] + ep["nrow"] * n].reshape(-1, n)
+            ref_m = sig[em["offset"]: em["offset"] + em["nrow"] * n].reshape(-1, n)
+            got_p, got_m, dens = ccav_rows(p, L, reps_p, xp, tm, with_source=src, dens=dens)
             scale = max(np.abs(ref_p).max(), np.abs(ref_m).max() if ref_m.size else 0.0)
             assert scale > 0.0
             assert np.abs(got_p - ref_p).max() <= 1e-12 * scale
