@@ -122,9 +122,10 @@ def test_full_size_operator_linear_and_symmetric(dev):
     g.close()
 
 
-def test_full_A_ccvv_cavv_aavv_rows_closed_form(dev):
+def test_full_A_rows_closed_form(dev):
     from oracle.aavv_closed import aavv_rows
     from oracle.cavv_closed import cavv_rows
+    from oracle.ccav_closed import ccav_rows
     from oracle.ccvv_closed import ccvv_pair_index, ccvv_rows
     from paper_1606_01273_amd import Caspt2
     p = make_problem(30, 8, 400, 1500, 4, seed=8, reading="A", shift=0.2)
@@ -144,6 +145,10 @@ def test_full_A_ccvv_cavv_aavv_rows_closed_form(dev):
     assert lay["aavv+"] == (off_ap, npv_p, nst * na * na)
     off_am = off_ap + npv_p * nst * na * na
     assert lay["aavv-"] == (off_am, npv_m, nst * na * na)
+    off_vp = off_am + npv_m * nst * na * na
+    assert lay["ccav+"] == (off_vp, npc_p * nv, nst * na)
+    off_vm = off_vp + npc_p * nv * nst * na
+    assert lay["ccav-"] == (off_vm, npc_m * nv, nst * na)
     rng = np.random.default_rng(42)
     reps = [(0, 0, 0, 0), (nc - 1, nc - 1, nv - 1, nv - 1), (nc - 1, 0, nv - 1, 0), (5, 5, 300, 17),
             (17, 3, 250, 250)]
@@ -158,6 +163,10 @@ def test_full_A_ccvv_cavv_aavv_rows_closed_form(dev):
     areps = [(0, 0), (nv - 1, nv - 1), (nv - 1, 0), (211, 211)]
     while len(areps) < 128:
         areps.append(tuple(sorted(int(v) for v in rng.integers(0, nv, 2))[::-1]))
+    vreps = [(0, 0, 0), (nc - 1, nc - 1, nv - 1), (nc - 1, 0, nv - 1), (9, 9, 77)]
+    while len(vreps) < 128:
+        i, j = sorted(int(v) for v in rng.integers(0, nc, 2))[::-1]
+        vreps.append((i, j, int(rng.integers(0, nv))))
     xh = random_vector(g.length, 41)
 
     def gather(rows_p, rows_m, width, off_p, off_m):
@@ -185,6 +194,10 @@ def test_full_A_ccvv_cavv_aavv_rows_closed_form(dev):
     aavv_p = [ccvv_pair_index(a, b, False) for a, b in areps]
     aavv_m = [ccvv_pair_index(a, b, True) if a > b else None for a, b in areps]
     pos3, t3p, t3m, sel3 = gather(aavv_p, aavv_m, nst * na * na, off_ap, off_am)
+    ccav_p = [ccvv_pair_index(i, j, False) * nv + a for i, j, a in vreps]
+    ccav_m = [ccvv_pair_index(i, j, True) * nv + a if i > j else None for i, j, a in vreps]
+    pos4, t4p, t4m, sel4 = gather(ccav_p, ccav_m, nst * na, off_vp, off_vm)
+    idx4 = torch.tensor(pos4, device=dev)
     idx1 = torch.tensor(pos1, device=dev)
     idx2 = torch.tensor(pos2, device=dev)
     idx3 = torch.tensor(pos3, device=dev)
@@ -192,7 +205,7 @@ def test_full_A_ccvv_cavv_aavv_rows_closed_form(dev):
     sig = torch.empty_like(x)
     dens = prods = None
     for streams, src in ((1, True), (2, False)):
-        print(f"full A ccvv, cavv and aavv rows: {streams} stream(s), source {src}", flush=True)
+        print(f"full A ccvv, cavv, aavv and ccav rows: {streams} stream(s), source {src}", flush=True)
         g.set_streams(streams)
         sig.fill_(float("nan"))
         g.residual_all(x, sig, with_source=src)
@@ -213,4 +226,9 @@ def test_full_A_ccvv_cavv_aavv_rows_closed_form(dev):
             ref = np.concatenate([rp.ravel(), rm[sel3].ravel()])
             _ok(np.abs(got - ref).max() / np.abs(ref).max(), 1e-12,
                 f"aavv rows, state {L} ({len(areps)} '+', {len(sel3)} '-' rows)")
+            got = sig[L].index_select(0, idx4).cpu().numpy()
+            rp, rm, dens = ccav_rows(p, L, vreps, t4p, t4m, with_source=src, dens=dens)
+            ref = np.concatenate([rp.ravel(), rm[sel4].ravel()])
+            _ok(np.abs(got - ref).max() / np.abs(ref).max(), 1e-12,
+                f"ccav rows, state {L} ({len(vreps)} '+', {len(sel4)} '-' rows)")
     g.close()
