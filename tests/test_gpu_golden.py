@@ -13,12 +13,14 @@
   in the launch configuration the benchmark times: properties that hold at
   any size -- the residual without source is linear in x and its operator is
   symmetric (Eq. 10 with a symmetric f and metric), with the Fock couplings
-  between blocks on; and, with the canonical Fock operator, the ccvv rows
-  (the benchmark's dominant kernel) at sampled representatives against
-  their closed form (oracle/ccvv_closed.py, itself checked against the
-  factorised oracle on every ccvv row of small problems): every state, both
-  characters, with the source on one stream and without it on two, at 1e-12
-  of the largest sampled value.
+  between blocks on; and, with the canonical Fock operator, the ccvv, cavv,
+  aavv and ccav rows (98.6 % of the vector, the dominant kernel and the
+  dense matrix-core block among them) at sampled representatives against
+  their closed forms (oracle/*_closed.py, each checked against the
+  factorised oracle on every row of its block in small problems): every
+  state, both characters, with the source on one stream and without it on
+  two, at 1e-12 of the largest sampled value; then the FP32 operator of the
+  mixed mode on the same rows (FP32-rounded x) at 1e-5.
 """
 import json
 import os
@@ -231,4 +233,32 @@ def test_full_A_rows_closed_form(dev):
             ref = np.concatenate([rp.ravel(), rm[sel4].ravel()])
             _ok(np.abs(got - ref).max() / np.abs(ref).max(), 1e-12,
                 f"ccav rows, state {L} ({len(vreps)} '+', {len(sel4)} '-' rows)")
+    # the FP32 operator of the mixed mode (Eq. 10 without the source) on the
+    # FP32-rounded x, same rows: 1e-5 of the largest sampled value
+    from paper_1606_01273_amd import MIXED, lib
+    g.set_precision(MIXED)
+    x32 = x[0].float()
+    del x, sig
+    s32 = torch.empty_like(x32)
+
+    def r32(rows):
+        return [None if t is None else np.asarray(t, dtype=np.float32).astype(np.float64) for t in rows]
+
+    checks = [("ccvv", idx1, lambda L: ccvv_rows(p, L, reps, r32(t1p), r32(t1m), with_source=False), sel1),
+              ("cavv", idx2, lambda L: cavv_rows(p, L, creps, r32(t2p), r32(t2m), with_source=False,
+                                                 dens=dens)[:2], sel2),
+              ("aavv", idx3, lambda L: aavv_rows(p, L, areps, r32(t3p), r32(t3m), with_source=False,
+                                                 prods=prods)[:2], sel3),
+              ("ccav", idx4, lambda L: ccav_rows(p, L, vreps, r32(t4p), r32(t4m), with_source=False,
+                                                 dens=dens)[:2], sel4)]
+    for L in range(nst):
+        print(f"full A, FP32 operator, state {L}", flush=True)
+        s32.fill_(float("nan"))
+        assert lib().caspt2_debug_residual_f32(g._h, L, x32.data_ptr(), s32.data_ptr()) == 0
+        torch.cuda.synchronize()
+        for name, idx, fn, sel in checks:
+            got = s32.index_select(0, idx).double().cpu().numpy()
+            rp, rm = fn(L)
+            ref = np.concatenate([rp.ravel(), rm[sel].ravel()])
+            _ok(np.abs(got - ref).max() / np.abs(ref).max(), 1e-5, f"FP32 {name} rows, state {L}")
     g.close()
